@@ -1,0 +1,9 @@
+"""FP64 CPU oracle for the Image-GS renderer (test infrastructure only).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark may import this
+package.  It shares no code with the HIP implementation in ``paper_2407_01866_amd``:
+
+* ``cref``   - ctypes wrapper of ``oracle.c`` (brute-force FP64 render + adjoint, OpenMP);
+* ``dense``  - an independent NumPy FP64 evaluation of the same definition for tiny inputs;
+* ``fitref`` - NumPy FP64 L1 loss/gradient, PSNR and the Adam step of the fitter.
+"""
