@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Benchmark of the Image-GS renderer hot path on one MI355X.
+
+Workload: the texture-stack fit, 2048 x 2048 with n = 9 float32 channels (three synthetic
+3-channel maps), N = 100,000 Gaussians, top-K = 10, 16 x 16 tiles.  One step is one fitting
+iteration: binning (footprint bound, scan, pair emission, radix sort, tile ranges), forward
+raster, L1 loss gradient, adjoint raster and the fused Adam step, replayed as one HIP graph with
+all inputs resident in HBM.
+
+Printed JSON line: ``value`` is Gaussian-pixel evaluations per second over whole fitting
+iterations (E_fwd = sum over tiles of |S_j| times the tile's pixel count, per iteration); the
+``roofline`` object reports the dominant raster kernel's algorithmic VALU work divided by its
+average duration, timed live with HIP events on the stream it runs on; ``cpu_baseline`` is the
+FP64 oracle timed on the host's cores over a sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("fwd+bwd Gaussian-pixel evals/s and fit iters/s at 2048², 100k G; "
+          "×batched vs plain")
+# VALU issue peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one lane-op per lane per clock, packed
+# FP32 disabled); the algorithmic work below is counted in the same lane-ops.
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def tile_pixels(H, W, tile=16):
+    tx, ty = (W + tile - 1) // tile, (H + tile - 1) // tile
+    wx = np.full(tx, tile)
+    wx[-1] = W - tile * (tx - 1)
+    hy = np.full(ty, tile)
+    hy[-1] = H - tile * (ty - 1)
+    return (hy[:, None] * wx[None, :]).ravel()
+
+
+def fwd_valu_ops(e_fwd, hw, n):
+    # per (pixel, candidate): 2 sub + 4 (two 2-term dot products) + 2 (squared norm) + 1 compare;
+    # per pixel: K exps (4 each) and subs, K*n multiply-adds, n scalings, one reciprocal
+    return 9.0 * e_fwd + (60.0 + 10.0 * n) * hw
+
+
+def bwd_valu_ops(e_bwd, n):
+    # per retained (pixel, Gaussian): recompute e, q, w (~12 + exp), g.(c_i - c_r) (n+2),
+    # five geometry products and n colour products, 5+n accumulations
+    return (35.0 + 3.0 * n) * e_bwd
+
+
+def cpu_baseline(params, H, W, K, grad_img, budget_s=10.0):
+    from oracle import cref
+    p64 = params.astype(np.float64)
+    T = cref.num_tiles(H, W)
+    rng = np.random.default_rng(0)
+    order = rng.permutation(T).astype(np.int32)
+    tp = tile_pixels(H, W)
+    # calibrate on a few tiles, then size the sample to the time budget
+    probe = order[:32]
+    t0 = time.perf_counter()
+    cref.render_tiles(p64, H, W, K, tiles=probe, grad_img=grad_img, want=("img",))
+    per_tile = (time.perf_counter() - t0) / len(probe)
+    ntiles = int(min(T, max(64, budget_s / max(per_tile, 1e-6))))
+    tiles = order[:ntiles]
+    counts, _ = cref.tile_lists(p64, H, W, tiles=tiles)
+    t0 = time.perf_counter()
+    cref.render_tiles(p64, H, W, K, tiles=tiles, grad_img=grad_img, want=("img",))
+    dt = time.perf_counter() - t0
+    e = float((counts * tp[tiles]).sum())
+    return {"value": e / dt, "unit": "Gaussian-pixel evals/s", "cores": cref.max_threads(),
+            "kind": "oracle",
+            "sample": f"{ntiles} of {T} tiles (all pixels of each), forward + adjoint in FP64, "
+                      f"{dt:.1f} s"}
+
+
+def paper_context(torch, dev, K=10):
+    """Render and fit-iteration times at the paper's measured operating points (2048^2 RGB,
+    10K and 50K Gaussians), for comparison with its A6000 timings (context only)."""
+    from paper_2407_01866_amd import synth
+    from paper_2407_01866_amd.fit import PlainFitter
+    from paper_2407_01866_amd.render import Renderer
+    out = {}
+    tgt = torch.from_numpy(synth.gen_image(9000, 2048, 2048, 3, 200)).to(dev)
+    for N in (10000, 50000):
+        p = torch.from_numpy(synth.gen_gaussians(9500 + N, 2048, 2048, N, 3, 5.0, 5.0)).to(dev)
+        r = Renderer(N, 3, 2048, 2048, K, device=dev)
+        r.render(p, keep_state=False)
+        img = torch.empty((3, 2048, 2048), device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            r.render_into(p, img, None)
+        torch.cuda.synchronize()
+        render_ms = (time.perf_counter() - t0) / 20 * 1e3
+        f = PlainFitter(tgt, p, K, headroom=3.0)
+        init = f.snapshot()
+        f.advance_to(23, use_graph=False)          # sizes the pair buffer for this trajectory
+        f.restore(init)
+        f.capture()
+        for _ in range(3):
+            f.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            f.step()
+        torch.cuda.synchronize()
+        iter_ms = (time.perf_counter() - t0) / 20 * 1e3
+        ok = f.steps_done() == 23
+        out[f"N{N // 1000}k"] = {"render_ms": round(render_ms, 4),
+                                 "fit_iter_ms": round(iter_ms, 4) if ok else None}
+    out["paper_a6000"] = {"N10k": {"render_ms": 3.7, "fit_iter_ms": 18.74},
+                          "N50k": {"render_ms": 4.5, "fit_iter_ms": 26.32},
+                          "note": "Sec. 4.4, NVIDIA A6000, L1+0.1 SSIM loss, Gaussians at init "
+                                  "scale 5 px here"}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-context", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
+              "on a single MI355X; see the sharding notes in the design document)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_01866_amd import _native as nat
+    from paper_2407_01866_amd import synth
+    from paper_2407_01866_amd.fit import PlainFitter
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 1 GiB x3")
+        return
+
+    w = synth.workload(2)
+    log(f"[bench] workload {w.name}: generating inputs")
+    target = torch.from_numpy(w.target()).to(dev)
+    params = torch.from_numpy(w.gaussians()).to(dev)
+    fitter = PlainFitter(target, params, w.K)
+    init = fitter.snapshot()
+    # dry run of the same trajectory, one iteration at a time: sizes the pair buffer for every
+    # iteration and records each iteration's work counts (the timed run repeats the trajectory)
+    total = args.warmup + args.steps
+    log(f"[bench] dry run of {total} iterations")
+    evals = []
+    for it in range(1, total + 1):
+        fitter.advance_to(it, use_graph=False)
+        st = fitter.status().clone()
+        evals.append((int(st[nat.STAT_EVALS_FWD]), int(st[nat.STAT_EVALS_BWD]),
+                      int(st[nat.STAT_PAIRS])))
+    peak_pairs = max(e[2] for e in evals)
+    fitter.r.set_capacity(int(peak_pairs * 1.25) + 1024)
+    fitter.saved = fitter.r.new_saved()
+    fitter.graph = None
+    fitter.restore(init)
+    fitter.capture()
+    log(f"[bench] pair capacity {fitter.r.cap} (peak need {peak_pairs}); warmup {args.warmup}")
+    for _ in range(args.warmup):
+        fitter.step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} graph-replayed fit iterations")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fitter.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if fitter.steps_done() != total:
+        raise RuntimeError("an iteration overflowed the pair buffer during the timed run")
+    timed = evals[args.warmup:]
+    e_fwd = float(np.mean([e[0] for e in timed]))
+    e_bwd = float(np.mean([e[1] for e in timed]))
+    pairs = float(np.mean([e[2] for e in timed]))
+    ms_per_step = dt / args.steps * 1e3
+    value = e_fwd / (ms_per_step * 1e-3)
+
+    # live per-phase timing with HIP events on the launch stream (eager launches: events cannot
+    # be recorded inside the captured graph)
+    log("[bench] per-kernel HIP-event timing (same trajectory, eager launches)")
+    fitter.restore(init)
+    for _ in range(args.warmup):
+        fitter.step_async()
+    torch.cuda.synchronize()
+    nat.igs_timing_read(reset=True)
+    nat.igs_timing_enable(True)
+    for _ in range(args.steps):
+        fitter.step_async()
+    torch.cuda.synchronize()
+    ph = nat.igs_timing_read(reset=True)
+    nat.igs_timing_enable(False)
+    if fitter.steps_done() != total:
+        raise RuntimeError("an iteration overflowed the pair buffer during the timed kernels")
+    avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in ph.items()}
+    hw = w.H * w.W
+    ops = {"raster_fwd": fwd_valu_ops(e_fwd, hw, w.n), "raster_bwd": bwd_valu_ops(e_bwd, w.n)}
+    dom = max(ops, key=lambda k: avg[k])
+    achieved = ops[dom] / (avg[dom] * 1e-3)
+    fwdbwd_ms = avg["binning"] + avg["raster_fwd"] + avg["loss"] + avg["raster_bwd"]
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved / 1e12, 3),
+                "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
+                "avg_ms": round(avg[dom], 4),
+                "work_per_launch": f"{ops[dom]:.4g} VALU lane-ops"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        g = fitter.grad_image.double().cpu().numpy()
+        cpu = cpu_baseline(w.gaussians(), w.H, w.W, w.K, g, args.cpu_budget)
+    ctx = None if args.no_context else paper_context(torch, dev)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "Gaussian-pixel evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "H": w.H, "W": w.W, "n": w.n, "N": w.N, "K": w.K,
+                   "tile": 16, "step": "binning+render+L1 grad+adjoint+Adam (HIP graph)"},
+        "fit_iters_per_s": 1e3 / ms_per_step,
+        "fwd_bwd_evals_per_s": e_fwd / (fwdbwd_ms * 1e-3),
+        "phase_ms": {k: round(v, 4) for k, v in avg.items()},
+        "E_fwd": e_fwd, "E_bwd": e_bwd, "pairs": pairs,
+        "E_fwd_first_last": [evals[args.warmup][0], evals[-1][0]],
+        "roofline": roofline, "cpu_baseline": cpu, "paper_context": ctx,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

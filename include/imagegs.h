@@ -1,0 +1,206 @@
+/*
+ * imagegs.h - C ABI of libimagegs.so, the gfx950 (MI355X) implementation of the Image-GS
+ * differentiable renderer (anisotropic coloured 2D Gaussians, tile-based top-K normalized blend)
+ * and its adjoint.
+ *
+ * Paper: "Image-GS: Content-Adaptive Image Representation via 2D Gaussians", arXiv 2407.01866.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every buffer argument is a DEVICE pointer owned by the caller.  The library never allocates
+ *    or frees device memory and never synchronizes: all work is enqueued on `stream`
+ *    (a hipStream_t passed as void*; NULL = the default stream), so results are ready only once
+ *    the caller synchronizes that stream.
+ *  - Argument checks are synchronous and return an igs_status; nothing throws across the ABI.
+ *  - Data-dependent failures (too many tile/Gaussian pairs for `pair_capacity`, a tile list too
+ *    long for 16-bit slots) are detected on the device and reported in the status block, an
+ *    int64_t[8] array at byte offset 0 of `saved` (or of `workspace` when `saved` is NULL):
+ *        status[0]  P, the number of (tile, Gaussian) pairs the render required
+ *        status[1]  1 if P exceeded pair_capacity: nothing past the capacity was written, the
+ *                   image is NOT valid and the caller must retry with pair_capacity >= P
+ *        status[2]  the largest tile hit-set size |S_j|
+ *        status[3]  1 if some |S_j| exceeded 65535: the image is valid but the saved top-K slots
+ *                   are not, so igs_render_backward must not be called on this state
+ *        status[4]  E_fwd = sum over tiles of |S_j| times the tile's pixel count: the (pixel,
+ *                   candidate) evaluations the render performed
+ *        status[5]  E_bwd = sum over pixels of the number of retained Gaussians, min(K, |S_j|)
+ *    The caller reads it asynchronously (e.g. a copy to pinned memory) before trusting outputs.
+ *  - Parameters are float32 structure-of-arrays [5+n][N] (Eq. 3: p_i = (mu, theta, s, c)),
+ *    rows in this order:
+ *        0 mu_x, 1 mu_y   mean in pixel units; the image spans [0,W] x [0,H] and pixel (h, w)
+ *                         has its centre at (w + 1/2, h + 1/2)
+ *        2 theta          rotation angle in radians (any value; Sigma is pi-periodic)
+ *        3 s_1, 4 s_2     scales in pixels, > 0 (Eq. 2: Sigma = R(theta) S S^T R(theta)^T)
+ *        5 .. 4+n         colour c in R^n
+ *    Non-finite or non-positive scales give unspecified pixel values but never unsafe memory
+ *    access; a Gaussian whose mean or scale is not finite hits no tile.
+ *  - Images (render output, targets, image gradients) are float32 planar [n][H][W].
+ *  - Only 16 x 16 tiles (the paper's tile size, Sec. 4.1) are supported: tile_h = tile_w = 16.
+ */
+#ifndef IMAGEGS_H
+#define IMAGEGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t igs_status;
+
+#define IGS_OK 0
+#define IGS_ERR_INVALID_ARG (-1) /* a size, pointer or hyper-parameter is out of range          */
+#define IGS_ERR_WORKSPACE (-2)   /* workspace / saved buffer smaller than the size query said    */
+#define IGS_ERR_HIP (-3)         /* a HIP runtime call or kernel launch failed                   */
+#define IGS_ERR_UNSUPPORTED (-4) /* valid request this build does not implement (e.g. tile 8x8) */
+
+#define IGS_MAX_K 32          /* largest top-K                                                  */
+#define IGS_MAX_CHANNELS 32   /* largest colour dimension n                                     */
+#define IGS_TILE 16           /* tile side in pixels                                            */
+#define IGS_STATUS_WORDS 8    /* int64 words of the device status block                        */
+
+/* ABI revision; bumped on any incompatible change. */
+int32_t igs_abi_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char *igs_status_string(igs_status s);
+
+/*
+ * Buffer sizes for igs_render / igs_render_backward with these dimensions.
+ *   pair_capacity: how many (tile, Gaussian) pairs the binning may hold (>= 1, < 2^31).  P, the
+ *                  number needed, is data dependent (Sec. 3.2: one pair per tile a Gaussian's
+ *                  3-sigma circle meets); the status block reports it.
+ *   *saved_bytes:  state the forward leaves for the adjoint (status, tile ranges, sorted hit
+ *                  lists, per-Gaussian geometry, per-pixel top-K slots and blend normalizers).
+ *   *ws_bytes:     scratch needed by either call when `saved` is given; a forward without saved
+ *                  state needs ws_bytes + saved_bytes of workspace.
+ * Errors: IGS_ERR_INVALID_ARG (N < 0, n or K or H or W out of range, NULL out pointers),
+ *         IGS_ERR_UNSUPPORTED (tile size other than 16 x 16).
+ */
+igs_status igs_render_buffer_sizes(int32_t N, int32_t n, int32_t H, int32_t W, int32_t K,
+                                   int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                                   size_t *ws_bytes, size_t *saved_bytes);
+
+/*
+ * Byte offsets of the parts of the saved state, for inspection (e.g. to compare the tile hit sets
+ * and top-K selection with a reference).  out[0] status block; out[1] tile ranges, int32[T][2]
+ * (start, end) into the sorted list, tiles numbered row-major, T = ceil(H/16) * ceil(W/16);
+ * out[2] sorted Gaussian indices uint32[pair_capacity]: S_j is entries start..end-1 of tile j, in
+ * ascending index; out[3] top-K slots uint16[K][H][W], the rank-ordered positions of the retained
+ * Gaussians within their tile's S_j (0xFFFF = unused); out[4] per-pixel float32[H][W][2]
+ * (blend shift, 1/sum of weights); out[5] total bytes.
+ * Errors: as igs_render_buffer_sizes.
+ */
+igs_status igs_saved_offsets(int32_t N, int32_t n, int32_t H, int32_t W, int32_t K, int32_t tile_h,
+                             int32_t tile_w, int64_t pair_capacity, int64_t out[6]);
+
+/*
+ * Forward render, Sec. 3.2 / Eq. 5.  For each Gaussian: the radius r = 3 max(s_1, s_2) of the
+ * circle enclosing its 3-sigma ellipse; tile hit sets S_j = Gaussians whose circle meets the
+ * closed tile rectangle (clipped to the image), ordered by ascending Gaussian index; for every
+ * pixel x of tile j the K members of S_j with the largest G_i(x) (smallest Mahalanobis form q,
+ * equal q broken by the lower index); and c_r(x) = sum_K G_i c_i / sum_K G_i.  Pixels whose tile
+ * has an empty S_j are 0.
+ *   params   [5+n][N] float32 (see the conventions above), N >= 0 (N = 0 renders zeros)
+ *   image    [n][H][W] float32 output, fully overwritten
+ *   saved    NULL for inference only, else saved_bytes of state kept for igs_render_backward
+ *   workspace / ws_bytes: scratch of at least the queried ws_bytes (+ saved_bytes if saved is
+ *            NULL); 256-byte aligned pointers are required for saved and workspace.
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_UNSUPPORTED, IGS_ERR_WORKSPACE, IGS_ERR_HIP.
+ */
+igs_status igs_render(const float *params, int32_t N, int32_t n, int32_t H, int32_t W, int32_t K,
+                      int32_t tile_h, int32_t tile_w, int64_t pair_capacity, float *image,
+                      void *saved, size_t saved_bytes, void *workspace, size_t ws_bytes,
+                      void *stream);
+
+/*
+ * Adjoint of igs_render (Sec. 3.3): gradients flow through the K retained Gaussians of every
+ * pixel while the tile hit sets and the top-K selection saved by the forward are held fixed.
+ *   params, N, n, H, W, K, tile sizes, pair_capacity: exactly as passed to the forward
+ *   image       the forward's output [n][H][W]
+ *   grad_image  dL/dc_r, [n][H][W] float32
+ *   saved       the state written by the forward (its status block must show no overflow)
+ *   grad_params [5+n][N] float32 output, overwritten (not accumulated): dL/d(mu_x, mu_y, theta,
+ *               s_1, s_2, c) in the units of `params`
+ *   workspace   scratch of at least ws_bytes
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_UNSUPPORTED, IGS_ERR_WORKSPACE, IGS_ERR_HIP.
+ */
+igs_status igs_render_backward(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
+                               int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                               const float *image, const float *grad_image, const void *saved,
+                               size_t saved_bytes, float *grad_params, void *workspace,
+                               size_t ws_bytes, void *stream);
+
+/* Scratch bytes igs_l1_loss_grad needs for an image of count = n*H*W values. */
+igs_status igs_l1_workspace_size(int64_t count, size_t *ws_bytes);
+
+/*
+ * L1 term of the fitting loss (Sec. 3.3, Sec. 4.1), taken as the mean over all n*H*W values:
+ *   grad_image = sign(image - target) / (n*H*W)  (sign(0) = 0), [n][H][W] float32
+ *   loss_out   device double[2]: [0] mean |image - target|, [1] mean (image - target)^2 (for PSNR)
+ * Reductions are deterministic (fixed order).  Errors: IGS_ERR_INVALID_ARG, IGS_ERR_WORKSPACE,
+ * IGS_ERR_HIP.
+ */
+igs_status igs_l1_loss_grad(const float *image, const float *target, int32_t n, int32_t H,
+                            int32_t W, float *grad_image, double *loss_out, void *workspace,
+                            size_t ws_bytes, void *stream);
+
+/*
+ * One Adam step (Sec. 4.1: Adam with constant per-group learning rates) in the fitter's
+ * parameterization, fused with the chain rules from the renderer's units and the clipping of
+ * Sec. 3.1:
+ *   fit_params    [5+n][N] in/out: rows mu_x/W, mu_y/H (Sec. 4.1 maps the image to [0,1]^2),
+ *                 theta, 1/s_1, 1/s_2 (inverse scales, Sec. 3.3 footnote and Sec. 4.1), colour
+ *   render_params [5+n][N] out: the same parameters converted to igs_render's units
+ *   grad_render   [5+n][N] in: dL/d(render params), e.g. igs_render_backward's output
+ *   m, v          [5+n][N] in/out: Adam moments (zero before the first step)
+ *   step          device int32[1] in/out: steps taken so far; incremented on the device after
+ *                 the update
+ *   skip_flag     device int64 or NULL: when non-NULL and non-zero at execution time the whole
+ *                 step is a no-op (parameters, moments and step unchanged); pass the overflow
+ *                 word of the render's status block so that an iteration whose render overflowed
+ *                 the pair buffer changes nothing
+ *   lr_mu, lr_theta, lr_inv_scale, lr_color: learning rates of the four groups
+ *   beta1, beta2, eps: Adam constants; theta is clipped to [0, pi] and 1/s to
+ *   [inv_scale_lo, inv_scale_hi] after the update.
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_HIP.
+ */
+igs_status igs_adam_step(float *fit_params, float *render_params, const float *grad_render,
+                         float *m, float *v, int32_t *step, const int64_t *skip_flag, int32_t N,
+                         int32_t n, int32_t H,
+                         int32_t W, float lr_mu, float lr_theta, float lr_inv_scale,
+                         float lr_color, float beta1, float beta2, float eps, float inv_scale_lo,
+                         float inv_scale_hi, void *stream);
+
+/*
+ * Convert fitter parameters (see igs_adam_step) to render parameters without an update.
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_HIP.
+ */
+igs_status igs_fit_to_render(const float *fit_params, float *render_params, int32_t N, int32_t n,
+                             int32_t H, int32_t W, void *stream);
+
+/*
+ * Kernel timers (measurement aid, off by default).  While enabled, every entry point records a
+ * pair of HIP events on its stream around each of its phases; igs_timing_read waits for the
+ * recorded events, returns the accumulated milliseconds and call counts per phase and, if reset is
+ * non-zero, clears them.  Phases: IGS_PHASE_BINNING (footprint bound, scan, pair emission, sort
+ * and tile ranges), IGS_PHASE_RASTER_FWD, IGS_PHASE_RASTER_BWD (adjoint incl. its per-Gaussian
+ * finishing pass), IGS_PHASE_LOSS, IGS_PHASE_ADAM.  At most 65536 event pairs are kept between
+ * reads; further phases go untimed.  Not thread-safe; do not enable during graph capture.
+ */
+#define IGS_PHASE_BINNING 0
+#define IGS_PHASE_RASTER_FWD 1
+#define IGS_PHASE_RASTER_BWD 2
+#define IGS_PHASE_LOSS 3
+#define IGS_PHASE_ADAM 4
+#define IGS_NUM_PHASES 5
+igs_status igs_timing_enable(int32_t on);
+igs_status igs_timing_read(double ms_out[IGS_NUM_PHASES], int64_t calls_out[IGS_NUM_PHASES],
+                           int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMAGEGS_H */

@@ -31,7 +31,7 @@ def lib():
         L.orc_num_tiles.restype = ci
         L.orc_tile_lists.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, _i32p, ci, _i64p, vp, ctypes.c_int64]
         L.orc_tile_lists.restype = ci
-        L.orc_render_tiles.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, ci, _i32p, ci, vp, vp, vp, vp, vp, ci]
+        L.orc_render_tiles.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, ci, _i32p, ci, vp, vp, vp, vp, vp, vp, ci]
         L.orc_render_tiles.restype = ci
         L.orc_render_dense.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, ci, vp, ci]
         L.orc_render_dense.restype = ci
@@ -79,7 +79,8 @@ def tile_lists(params, H, W, tile=16, tiles: Optional[Sequence[int]] = None):
 def render_tiles(params, H, W, K, tile=16, tiles=None, grad_img=None, want=("img", "topk", "qsel"),
                  nthreads=0):
     """Render the listed tiles; returns dict with compact per-tile arrays and, when ``grad_img``
-    ([n][H][W]) is given, ``grad`` [5+n][N] holding the listed tiles' contributions."""
+    ([n][H][W]) is given, ``grad`` [5+n][N] holding the listed tiles' contributions and
+    ``grad_abs`` [5+n][N], the sums of the terms' magnitudes before cancellation."""
     p, N, n = _prep(params)
     T = num_tiles(H, W, tile)
     t = np.arange(T, dtype=np.int32) if tiles is None else np.ascontiguousarray(tiles, dtype=np.int32)
@@ -89,14 +90,15 @@ def render_tiles(params, H, W, K, tile=16, tiles=None, grad_img=None, want=("img
     topk = np.zeros((len(t), tp, K), dtype=np.int32) if "topk" in want else None
     qsel = np.zeros((len(t), tp, K + 1)) if "qsel" in want else None
     g = None
-    grad = None
+    grad = gabs = None
     if grad_img is not None:
         g = np.ascontiguousarray(grad_img, dtype=np.float64)
         if g.shape != (n, H, W):
             raise ValueError("grad_img must be [n][H][W]")
         grad = np.zeros((5 + n, N))
+        gabs = np.zeros((5 + n, N))
     rc = lib().orc_render_tiles(p, N, n, H, W, K, tile, tile, t, len(t), _ptr(img), _ptr(topk),
-                                _ptr(qsel), _ptr(g), _ptr(grad), nthreads)
+                                _ptr(qsel), _ptr(g), _ptr(grad), _ptr(gabs), nthreads)
     if rc != 0:
         raise RuntimeError(f"orc_render_tiles failed: {rc}")
     out["tiles"] = t
@@ -108,6 +110,7 @@ def render_tiles(params, H, W, K, tile=16, tiles=None, grad_img=None, want=("img
         out["qsel"] = qsel
     if grad is not None:
         out["grad"] = grad
+        out["grad_abs"] = gabs
     return out
 
 
@@ -137,6 +140,7 @@ def render(params, H, W, K, tile=16, grad_img=None, nthreads=0):
     }
     if "grad" in r:
         out["grad"] = r["grad"]
+        out["grad_abs"] = r["grad_abs"]
     return out
 
 
@@ -149,13 +153,17 @@ def render_dense(params, H, W, K, tile=16, nthreads=0) -> np.ndarray:
     return img
 
 
-def grad_for_gaussians(params, H, W, K, grad_img, gids: Sequence[int], tile=16, nthreads=0) -> np.ndarray:
+def grad_for_gaussians(params, H, W, K, grad_img, gids: Sequence[int], tile=16, nthreads=0,
+                       with_abs=False):
     """Exact gradient rows for the Gaussians ``gids`` ([5+n][len(gids)]): renders every tile whose
-    S_j contains one of them, which holds every pixel that can select them."""
+    S_j contains one of them, which holds every pixel that can select them.  With ``with_abs``
+    also returns the matching ``grad_abs`` rows."""
     p, N, n = _prep(params)
     gids = np.asarray(gids, dtype=np.int64)
     sub = p[:, gids]
     counts, _ = tile_lists(sub, H, W, tile)
     tiles = np.nonzero(counts > 0)[0].astype(np.int32)
     r = render_tiles(p, H, W, K, tile, tiles, grad_img, want=(), nthreads=nthreads)
+    if with_abs:
+        return r["grad"][:, gids], r["grad_abs"][:, gids]
     return r["grad"][:, gids]

@@ -152,11 +152,15 @@ int orc_tile_lists(const double *params, int N, int n, int H, int W, int th, int
  * Adjoint (Sec. 3.3): with g = grad_img[:, h, w] (full-size planar [n][H][W]) the contributions of
  * the listed tiles' pixels are added into grad_params [5+n][N] (caller zeroes it).  Gradients are
  * taken with S_j and S_j^K(x) held fixed.
+ * grad_abs [5+n][N] (optional, caller zeroes it) receives the conditioning of each gradient sum:
+ * the sum over pixels of the magnitudes of the terms before they cancel, i.e. |alpha g_c| for a
+ * colour and (1/2) alpha (|g.c_i| + |g.c_r|) |dq/dp| for a geometry parameter.  A float32
+ * evaluation of the same sums is accurate to a small multiple of eps32 times this value.
  * Any output pointer may be NULL.  nthreads <= 0 uses the OpenMP default.
  */
 int orc_render_tiles(const double *params, int N, int n, int H, int W, int K, int th, int tw,
                      const int32_t *tiles, int ntiles, double *img, int32_t *topk, double *qsel,
-                     const double *grad_img, double *grad_params, int nthreads) {
+                     const double *grad_img, double *grad_params, double *grad_abs, int nthreads) {
     if (N < 0 || n < 1 || H < 1 || W < 1 || K < 1 || th < 1 || tw < 1 || ntiles < 0) return ORC_EINVAL;
     int T = orc_num_tiles(H, W, th, tw);
     for (int t = 0; t < ntiles; ++t)
@@ -175,11 +179,12 @@ int orc_render_tiles(const double *params, int N, int n, int H, int W, int K, in
     {
         int32_t *members = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
         cand_t *cand = (cand_t *)malloc(sizeof(cand_t) * (size_t)(N > 0 ? N : 1));
-        double *gloc = NULL;
+        double *gloc = NULL, *aloc = NULL;
         if (do_grad) gloc = (double *)calloc((size_t)R * (size_t)(N > 0 ? N : 1), sizeof(double));
+        if (do_grad && grad_abs) aloc = (double *)calloc((size_t)R * (size_t)(N > 0 ? N : 1), sizeof(double));
         double *cr = (double *)malloc(sizeof(double) * (size_t)n);
         double *wts = (double *)malloc(sizeof(double) * (size_t)K);
-        int ok = members && cand && cr && wts && (!do_grad || gloc);
+        int ok = members && cand && cr && wts && (!do_grad || gloc) && (!(do_grad && grad_abs) || aloc);
         if (!ok) {
 #pragma omp atomic write
             status = ORC_ENOMEM;
@@ -237,13 +242,17 @@ int orc_render_tiles(const double *params, int N, int n, int H, int W, int K, in
                 for (int k = 0; k < keff; ++k) {
                     int i = cand[k].idx;
                     double alpha = wts[k] / Z;
-                    double dot = 0.0;
+                    double dot = 0.0, gci = 0.0, gcr = 0.0;
                     for (int ch = 0; ch < n; ++ch) {
                         double g = grad_img[((size_t)ch * H + h) * W + w];
                         gloc[(size_t)(5 + ch) * N + i] += alpha * g;
                         dot += g * (P(params, N, 5 + ch, i) - cr[ch]);
+                        gci += g * P(params, N, 5 + ch, i);
+                        gcr += g * cr[ch];
+                        if (aloc) aloc[(size_t)(5 + ch) * N + i] += fabs(alpha * g);
                     }
                     double dLdq = -0.5 * alpha * dot;
+                    double dmag = 0.5 * alpha * (fabs(gci) + fabs(gcr));
                     double mx = P(params, N, 0, i), my = P(params, N, 1, i), thv = P(params, N, 2, i);
                     double s1 = P(params, N, 3, i), s2 = P(params, N, 4, i);
                     double e1, e2;
@@ -260,6 +269,13 @@ int orc_render_tiles(const double *params, int N, int n, int H, int W, int K, in
                     gloc[(size_t)2 * N + i] += dLdq * dq_dth;
                     gloc[(size_t)3 * N + i] += dLdq * dq_ds1;
                     gloc[(size_t)4 * N + i] += dLdq * dq_ds2;
+                    if (aloc) {
+                        aloc[(size_t)0 * N + i] += dmag * fabs(dq_dmx);
+                        aloc[(size_t)1 * N + i] += dmag * fabs(dq_dmy);
+                        aloc[(size_t)2 * N + i] += dmag * fabs(dq_dth);
+                        aloc[(size_t)3 * N + i] += dmag * fabs(dq_ds1);
+                        aloc[(size_t)4 * N + i] += dmag * fabs(dq_ds2);
+                    }
                 }
             }
         }
@@ -267,11 +283,14 @@ int orc_render_tiles(const double *params, int N, int n, int H, int W, int K, in
 #pragma omp critical
             {
                 for (size_t e = 0; e < (size_t)R * (size_t)N; ++e) grad_params[e] += gloc[e];
+                if (aloc)
+                    for (size_t e = 0; e < (size_t)R * (size_t)N; ++e) grad_abs[e] += aloc[e];
             }
         }
         free(members);
         free(cand);
         free(gloc);
+        free(aloc);
         free(cr);
         free(wts);
     }

@@ -1,0 +1,213 @@
+"""ctypes binding of libimagegs.so (include/imagegs.h).  Argument marshalling only: every step of
+the renderer runs in the library's HIP kernels; torch tensors are used for device memory and the
+current HIP stream.  Importing works without a GPU; calling the compute entry points needs one.
+There is no fallback: a missing library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libimagegs.so")
+
+IGS_OK = 0
+IGS_ERR_INVALID_ARG = -1
+IGS_ERR_WORKSPACE = -2
+IGS_ERR_HIP = -3
+IGS_ERR_UNSUPPORTED = -4
+IGS_MAX_K = 32
+IGS_MAX_CHANNELS = 32
+IGS_TILE = 16
+IGS_STATUS_WORDS = 8
+
+# status block words (int64 at byte 0 of the saved state)
+STAT_PAIRS, STAT_OVERFLOW, STAT_MAX_LIST, STAT_SLOT_OVERFLOW, STAT_EVALS_FWD, STAT_EVALS_BWD = range(6)
+
+EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "igs_saved_offsets",
+            "igs_render",
+            "igs_render_backward", "igs_l1_workspace_size", "igs_l1_loss_grad", "igs_adam_step",
+            "igs_fit_to_render", "igs_timing_enable", "igs_timing_read")
+
+PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam")
+
+
+class IGSError(RuntimeError):
+    def __init__(self, func: str, status: int):
+        super().__init__(f"{func} failed: {status} ({_status_name(status)})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python paper_2407_01866_amd/build.py` "
+                          "(or __graft_entry__.build()) first")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, sz, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+    f32 = ctypes.c_float
+    L.igs_abi_version.argtypes = []
+    L.igs_abi_version.restype = i32
+    L.igs_status_string.argtypes = [i32]
+    L.igs_status_string.restype = ctypes.c_char_p
+    L.igs_render_buffer_sizes.argtypes = [i32, i32, i32, i32, i32, i32, i32, i64,
+                                          ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.igs_render_buffer_sizes.restype = i32
+    L.igs_saved_offsets.argtypes = [i32, i32, i32, i32, i32, i32, i32, i64, ctypes.POINTER(i64)]
+    L.igs_saved_offsets.restype = i32
+    L.igs_render.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, vp, sz, vp, sz, vp]
+    L.igs_render.restype = i32
+    L.igs_render_backward.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, vp, vp, sz,
+                                      vp, vp, sz, vp]
+    L.igs_render_backward.restype = i32
+    L.igs_l1_workspace_size.argtypes = [i64, ctypes.POINTER(sz)]
+    L.igs_l1_workspace_size.restype = i32
+    L.igs_l1_loss_grad.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.igs_l1_loss_grad.restype = i32
+    L.igs_adam_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, f32, f32, f32, f32,
+                                f32, f32, f32, f32, f32, vp]
+    L.igs_adam_step.restype = i32
+    L.igs_fit_to_render.argtypes = [vp, vp, i32, i32, i32, i32, vp]
+    L.igs_fit_to_render.restype = i32
+    L.igs_timing_enable.argtypes = [i32]
+    L.igs_timing_enable.restype = i32
+    L.igs_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
+    L.igs_timing_read.restype = i32
+    _lib = L
+    return L
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().igs_status_string(s).decode()
+    except Exception:  # pragma: no cover - only while reporting another failure
+        return "?"
+
+
+def _check(func: str, s: int) -> None:
+    if s != IGS_OK:
+        raise IGSError(func, s)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _f32(t: torch.Tensor, name: str) -> int:
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return _ptr(t)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+# ------------------------------------------------------------------------------- entry points
+
+
+def igs_abi_version() -> int:
+    return lib().igs_abi_version()
+
+
+def igs_status_string(s: int) -> str:
+    return lib().igs_status_string(s).decode()
+
+
+def igs_render_buffer_sizes(N: int, n: int, H: int, W: int, K: int, tile_h: int = IGS_TILE,
+                            tile_w: int = IGS_TILE, pair_capacity: int = 1) -> Tuple[int, int]:
+    ws, sv = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _check("igs_render_buffer_sizes",
+           lib().igs_render_buffer_sizes(N, n, H, W, K, tile_h, tile_w, pair_capacity,
+                                         ctypes.byref(ws), ctypes.byref(sv)))
+    return ws.value, sv.value
+
+
+def igs_saved_offsets(N: int, n: int, H: int, W: int, K: int, tile_h: int = IGS_TILE,
+                      tile_w: int = IGS_TILE, pair_capacity: int = 1) -> dict:
+    out = (ctypes.c_int64 * 6)()
+    _check("igs_saved_offsets",
+           lib().igs_saved_offsets(N, n, H, W, K, tile_h, tile_w, pair_capacity, out))
+    return dict(zip(("status", "ranges", "vals", "slots", "aux", "total"), list(out)))
+
+
+def igs_render(params, N, n, H, W, K, tile_h, tile_w, pair_capacity, image, saved, saved_bytes,
+               workspace, ws_bytes, stream=None) -> None:
+    _check("igs_render", lib().igs_render(
+        _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, pair_capacity,
+        _f32(image, "image"), _ptr(saved), saved_bytes, _ptr(workspace), ws_bytes,
+        _stream(stream)))
+
+
+def igs_render_backward(params, N, n, H, W, K, tile_h, tile_w, pair_capacity, image, grad_image,
+                        saved, saved_bytes, grad_params, workspace, ws_bytes, stream=None) -> None:
+    _check("igs_render_backward", lib().igs_render_backward(
+        _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, pair_capacity,
+        _f32(image, "image"), _f32(grad_image, "grad_image"), _ptr(saved), saved_bytes,
+        _f32(grad_params, "grad_params") if N > 0 else None, _ptr(workspace), ws_bytes,
+        _stream(stream)))
+
+
+def igs_l1_workspace_size(count: int) -> int:
+    ws = ctypes.c_size_t(0)
+    _check("igs_l1_workspace_size", lib().igs_l1_workspace_size(count, ctypes.byref(ws)))
+    return ws.value
+
+
+def igs_l1_loss_grad(image, target, n, H, W, grad_image, loss_out, workspace, ws_bytes,
+                     stream=None) -> None:
+    if loss_out.dtype != torch.float64:
+        raise TypeError("loss_out must be float64[2]")
+    _check("igs_l1_loss_grad", lib().igs_l1_loss_grad(
+        _f32(image, "image"), _f32(target, "target"), n, H, W, _f32(grad_image, "grad_image"),
+        _ptr(loss_out), _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_adam_step(fit_params, render_params, grad_render, m, v, step, N, n, H, W, lr_mu, lr_theta,
+                  lr_inv_scale, lr_color, beta1=0.9, beta2=0.999, eps=1e-8, inv_scale_lo=None,
+                  inv_scale_hi=4.0, skip_flag=None, stream=None) -> None:
+    """skip_flag: optional device int64 tensor (e.g. the render status's overflow word); when
+    non-zero at execution time the step changes nothing."""
+    if step.dtype != torch.int32:
+        raise TypeError("step must be int32[1]")
+    if inv_scale_lo is None:
+        inv_scale_lo = 1.0 / max(H, W)
+    _check("igs_adam_step", lib().igs_adam_step(
+        _f32(fit_params, "fit_params"), _f32(render_params, "render_params"),
+        _f32(grad_render, "grad_render"), _f32(m, "m"), _f32(v, "v"), _ptr(step),
+        _ptr(skip_flag), N, n, H, W,
+        lr_mu, lr_theta, lr_inv_scale, lr_color, beta1, beta2, eps, inv_scale_lo, inv_scale_hi,
+        _stream(stream)))
+
+
+def igs_fit_to_render(fit_params, render_params, N, n, H, W, stream=None) -> None:
+    _check("igs_fit_to_render", lib().igs_fit_to_render(
+        _f32(fit_params, "fit_params"), _f32(render_params, "render_params"), N, n, H, W,
+        _stream(stream)))
+
+
+def igs_timing_enable(on: bool) -> None:
+    _check("igs_timing_enable", lib().igs_timing_enable(1 if on else 0))
+
+
+def igs_timing_read(reset: bool = True) -> dict:
+    """{phase: (total_ms, calls)} accumulated since the last reset (waits for the events)."""
+    ms = (ctypes.c_double * len(PHASES))()
+    calls = (ctypes.c_int64 * len(PHASES))()
+    _check("igs_timing_read", lib().igs_timing_read(ms, calls, 1 if reset else 0))
+    return {p: (ms[i], calls[i]) for i, p in enumerate(PHASES)}

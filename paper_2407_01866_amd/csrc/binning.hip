@@ -1,0 +1,211 @@
+// Footprint bound and tile binning (Image-GS Sec. 3.2): per-Gaussian preprocessing, exact
+// circle/tile hit counting, pair emission and per-tile ranges over the sorted pair list.
+#include "common.hpp"
+
+namespace igs {
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void fill_u32_kernel(uint32_t *__restrict__ p, int64_t count, uint32_t value) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = value;
+}
+
+__global__ void fill_f32_kernel(float *__restrict__ p, int64_t count, float value) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = value;
+}
+
+__global__ void status_reset_kernel(int64_t *status) {
+  if (threadIdx.x < 8) status[threadIdx.x] = 0;
+}
+
+// Closed tile rectangle [x0, x1] x [y0, y1] (clipped to the image) against the circle of radius
+// r = 3 max(s1, s2) about mu, evaluated in double with every product and sum rounded on its own
+// so that the decision is reproducible bit for bit.  Tangency counts as a hit.
+__device__ __forceinline__ bool circle_meets_tile(double mx, double my, double r2, int tx, int ty,
+                                                  int H, int W) {
+#pragma clang fp contract(off)
+  double x0 = (double)(tx * kTile), y0 = (double)(ty * kTile);
+  double x1 = (double)min(tx * kTile + kTile, W), y1 = (double)min(ty * kTile + kTile, H);
+  double cx = mx < x0 ? x0 : (mx > x1 ? x1 : mx);
+  double cy = my < y0 ? y0 : (my > y1 ? y1 : my);
+  double dx = mx - cx;
+  double dy = my - cy;
+  double d2 = dx * dx + dy * dy;
+  return d2 <= r2;
+}
+
+struct TileBox {
+  int tx0, tx1, ty0, ty1;  // inclusive; empty when tx0 > tx1
+  double mx, my, r2;
+};
+
+// Candidate tile range of one Gaussian: every tile whose rectangle can meet the circle, widened
+// by one tile on each side so that rounding of mu +- r never drops a tangent tile.
+__device__ __forceinline__ TileBox tile_box(float fmx, float fmy, float fs1, float fs2,
+                                            int tiles_x, int tiles_y) {
+#pragma clang fp contract(off)
+  TileBox b;
+  b.mx = (double)fmx;
+  b.my = (double)fmy;
+  double r = 3.0 * (double)(fs1 > fs2 ? fs1 : fs2);
+  b.r2 = r * r;
+  if (!(isfinite(b.mx) && isfinite(b.my) && isfinite(r))) {
+    b.tx0 = b.ty0 = 1;
+    b.tx1 = b.ty1 = 0;
+    return b;
+  }
+  double lo_x = floor((b.mx - r) / kTile) - 1.0, hi_x = floor((b.mx + r) / kTile) + 1.0;
+  double lo_y = floor((b.my - r) / kTile) - 1.0, hi_y = floor((b.my + r) / kTile) + 1.0;
+  lo_x = fmax(lo_x, 0.0);
+  lo_y = fmax(lo_y, 0.0);
+  hi_x = fmin(hi_x, (double)(tiles_x - 1));
+  hi_y = fmin(hi_y, (double)(tiles_y - 1));
+  if (lo_x > hi_x || lo_y > hi_y) {
+    b.tx0 = b.ty0 = 1;
+    b.tx1 = b.ty1 = 0;
+    return b;
+  }
+  b.tx0 = (int)lo_x;
+  b.tx1 = (int)hi_x;
+  b.ty0 = (int)lo_y;
+  b.ty1 = (int)hi_y;
+  return b;
+}
+
+// Per Gaussian: rotation/inverse-scale coefficients (A, B; C, D) with e = (A dx + B dy,
+// C dx + D dy) = diag(1/s1, 1/s2) R(theta)^T (x - mu), so that q = |e|^2 (Eq. 1-2); kept in
+// float for ranking and in double for the blend weights; plus the exact tile-hit count.
+__global__ __launch_bounds__(kThreads) void preprocess_kernel(
+    const float *__restrict__ params, int N, int H, int W, int tiles_x, int tiles_y,
+    float4 *__restrict__ g32a, float2 *__restrict__ g32b, double4 *__restrict__ g64,
+    uint32_t *__restrict__ counts) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float mx = params[i], my = params[(size_t)N + i], th = params[2 * (size_t)N + i];
+  float s1 = params[3 * (size_t)N + i], s2 = params[4 * (size_t)N + i];
+  double sn, cs;
+  sincos((double)th, &sn, &cs);
+  double u1 = 1.0 / (double)s1, u2 = 1.0 / (double)s2;
+  double A = u1 * cs, B = u1 * sn, C = -u2 * sn, D = u2 * cs;
+  g64[i] = make_double4(A, B, C, D);
+  g32a[i] = make_float4(mx, my, (float)A, (float)B);
+  g32b[i] = make_float2((float)C, (float)D);
+  TileBox b = tile_box(mx, my, s1, s2, tiles_x, tiles_y);
+  uint32_t c = 0;
+  for (int ty = b.ty0; ty <= b.ty1; ++ty)
+    for (int tx = b.tx0; tx <= b.tx1; ++tx) c += circle_meets_tile(b.mx, b.my, b.r2, tx, ty, H, W);
+  counts[i] = c;
+}
+
+__global__ void pair_total_kernel(const uint32_t *__restrict__ counts,
+                                  const int64_t *__restrict__ offsets, int N, int64_t cap,
+                                  int64_t *__restrict__ status) {
+  if (threadIdx.x != 0) return;
+  int64_t P = N > 0 ? offsets[N - 1] + (int64_t)counts[N - 1] : 0;
+  status[kStatPairs] = P;
+  status[kStatOverflow] = P > cap ? 1 : 0;
+}
+
+// Writes (tile key, Gaussian index) for every tile the Gaussian hits, at the Gaussian's scanned
+// offset; the pair list is thereby in ascending Gaussian index, which the stable sort keeps
+// within each tile.  Nothing is written past the capacity.
+__global__ __launch_bounds__(kThreads) void emit_kernel(
+    const float *__restrict__ params, int N, int H, int W, int tiles_x, int tiles_y,
+    const uint32_t *__restrict__ counts, const int64_t *__restrict__ offsets, int64_t cap,
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  uint32_t c = counts[i];
+  int64_t o = offsets[i];
+  if (c == 0 || o + (int64_t)c > cap) return;
+  float mx = params[i], my = params[(size_t)N + i];
+  float s1 = params[3 * (size_t)N + i], s2 = params[4 * (size_t)N + i];
+  TileBox b = tile_box(mx, my, s1, s2, tiles_x, tiles_y);
+  uint32_t k = 0;
+  for (int ty = b.ty0; ty <= b.ty1; ++ty)
+    for (int tx = b.tx0; tx <= b.tx1; ++tx)
+      if (circle_meets_tile(b.mx, b.my, b.r2, tx, ty, H, W) && k < c) {
+        keys[o + k] = (uint32_t)(ty * tiles_x + tx);
+        vals[o + k] = (uint32_t)i;
+        ++k;
+      }
+}
+
+// [start, end) of every tile in the sorted pair list (ranges zeroed beforehand).
+__global__ __launch_bounds__(kThreads) void tile_ranges_kernel(const uint32_t *__restrict__ keys,
+                                                               const int64_t *__restrict__ status,
+                                                               int64_t cap,
+                                                               int2 *__restrict__ ranges) {
+  int64_t P = status[kStatOverflow] ? 0 : status[kStatPairs];
+  if (P > cap) P = 0;
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; p < P; p += stride) {
+    uint32_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
+    if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);
+  }
+}
+
+inline int grid_for(int64_t count, int threads, int max_blocks = 65536) {
+  int64_t b = (count + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  fill_u32_kernel<<<grid_for(count, kThreads, 4096), kThreads, 0, s>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  fill_f32_kernel<<<grid_for(count, kThreads, 4096), kThreads, 0, s>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_reset(int64_t *status, hipStream_t s) {
+  status_reset_kernel<<<1, 64, 0, s>>>(status);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const float *params, int N, int H, int W, int tiles_x, int tiles_y,
+                             float4 *g32a, float2 *g32b, double4 *g64, uint32_t *counts,
+                             hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  preprocess_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(
+      params, N, H, W, tiles_x, tiles_y, g32a, g32b, g64, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int N, int64_t cap,
+                             int64_t *status, hipStream_t s) {
+  pair_total_kernel<<<1, 64, 0, s>>>(counts, offsets, N, cap, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit(const float *params, int N, int H, int W, int tiles_x, int tiles_y,
+                       const uint32_t *counts, const int64_t *offsets, int64_t cap,
+                       uint32_t *keys, uint32_t *vals, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(
+      params, N, H, W, tiles_x, tiles_y, counts, offsets, cap, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
+                              int2 *ranges, hipStream_t s) {
+  tile_ranges_kernel<<<grid_for(cap, kThreads, 8192), kThreads, 0, s>>>(keys, status, cap, ranges);
+  return hipGetLastError();
+}
+
+}  // namespace igs

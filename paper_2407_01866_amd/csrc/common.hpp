@@ -1,0 +1,122 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code of libimagegs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace igs {
+
+constexpr int kTile = 16;             // tile side (pixels)
+constexpr int kTilePixels = kTile * kTile;
+constexpr int kRasterThreads = 256;   // one thread per pixel of a 16 x 16 tile
+constexpr int kBatch = 256;           // Gaussians staged in LDS per batch (one per thread)
+constexpr int kMaxK = 32;
+constexpr int kMaxChannels = 32;
+constexpr uint16_t kEmptySlot = 0xFFFF;
+
+// Device status block (int64 words), see include/imagegs.h.
+enum StatusWord {
+  kStatPairs = 0,
+  kStatOverflow = 1,
+  kStatMaxList = 2,
+  kStatSlotOverflow = 3,
+  kStatEvalsFwd = 4,
+  kStatEvalsBwd = 5
+};
+
+// Radix sort geometry.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTileItems = kSortThreads * kSortItems;  // keys per sort block
+
+// Scan geometry.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlockItems = kScanThreads * kScanItems;
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct Dims {
+  int N, n, H, W, K;
+  int64_t cap;
+  int tiles_x, tiles_y, T;
+  int64_t HW;
+  int key_bits, passes, digit_bits;
+  int64_t sort_blocks;
+};
+
+Dims make_dims(int N, int n, int H, int W, int K, int64_t cap);
+
+// Byte offsets inside the caller's `saved` buffer.
+struct SavedLayout {
+  size_t status, ranges, vals, g32a, g32b, g64, slots, aux, total;
+};
+// Byte offsets inside the caller's workspace.
+struct WsLayout {
+  size_t counts, offsets, keys, keys_alt, vals_alt, hist, hist_off, scan_tmp, gamma, l1_tmp, total;
+};
+
+SavedLayout saved_layout(const Dims &d);
+WsLayout ws_layout(const Dims &d);
+size_t scan_temp_elems(int64_t n);
+
+// ------------------------------------------------------------------ launchers (return hipError_t)
+
+// binning.hip
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s);
+hipError_t launch_status_reset(int64_t *status, hipStream_t s);
+hipError_t launch_preprocess(const float *params, int N, int H, int W, int tiles_x, int tiles_y,
+                             float4 *g32a, float2 *g32b, double4 *g64, uint32_t *counts,
+                             hipStream_t s);
+hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int N, int64_t cap,
+                             int64_t *status, hipStream_t s);
+hipError_t launch_emit(const float *params, int N, int H, int W, int tiles_x, int tiles_y,
+                       const uint32_t *counts, const int64_t *offsets, int64_t cap,
+                       uint32_t *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
+                              int2 *ranges, hipStream_t s);
+
+// scan.hip: exclusive scans; temp must hold scan_temp_elems(n) elements of the output type.
+hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *temp,
+                           hipStream_t s);
+hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *temp,
+                           hipStream_t s);
+
+// radix_sort.hip: stable LSD sort of (key, val) by the low key_bits bits; the count is read
+// from status on the device.  Result lands in (keys, vals); (keys_alt, vals_alt) are scratch.
+hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
+                            uint32_t *vals_alt, const int64_t *status, int64_t cap, int key_bits,
+                            int passes, int digit_bits, uint32_t *hist, uint32_t *hist_off,
+                            uint32_t *scan_tmp, hipStream_t s);
+// Which buffer emit must write into so the sort's final pass ends in (keys, vals).
+inline bool sort_starts_in_alt(int passes) { return (passes & 1) != 0; }
+
+// raster_fwd.hip
+hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
+                             const float2 *g32b, const double4 *g64, const float *params,
+                             const Dims &d, float *image, uint16_t *slots, float2 *aux,
+                             int64_t *status, hipStream_t s);
+
+// raster_bwd.hip
+hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
+                             const double4 *g64, const float *params, const Dims &d,
+                             const float *image, const float *grad_image, const uint16_t *slots,
+                             const float2 *aux, float *gamma, float *grad_params, hipStream_t s);
+hipError_t launch_grad_finalize(const float *params, const float4 *g32a, const float2 *g32b,
+                                const float *gamma, int N, float *grad_params, hipStream_t s);
+
+// loss_adam.hip
+int l1_blocks(int64_t count);
+hipError_t launch_l1(const float *image, const float *target, int64_t count, float *grad,
+                     double *partials, double *loss_out, hipStream_t s);
+hipError_t launch_adam(float *fit, float *rend, const float *grad, float *m, float *v,
+                       int32_t *step, const int64_t *skip, int N, int n, int H, int W, float lr_mu,
+                       float lr_theta, float lr_u, float lr_c, float b1, float b2, float eps,
+                       float u_lo, float u_hi, hipStream_t s);
+hipError_t launch_fit_to_render(const float *fit, float *rend, int N, int n, int H, int W,
+                                hipStream_t s);
+
+}  // namespace igs

@@ -1,0 +1,48 @@
+// Device helpers shared by the forward and adjoint rasterizers.  Both must evaluate the blend
+// weights with exactly the same operations so that the adjoint sees the forward's weights.
+#pragma once
+
+#include "common.hpp"
+
+namespace igs {
+
+// Mahalanobis form q = |e|^2 (Eq. 1-2) in double, e = (A dx + B dy, C dx + D dy), for a pixel
+// centre (fx, fy) and mean (mx, my).  Explicit fma keeps the rounding identical everywhere.
+__device__ __forceinline__ double quad_form64(float fx, float fy, float mx, float my, double A,
+                                              double B, double C, double D, double &e1,
+                                              double &e2) {
+  double dx = (double)fx - (double)mx;
+  double dy = (double)fy - (double)my;
+  e1 = fma(A, dx, B * dy);
+  e2 = fma(C, dx, D * dy);
+  return fma(e1, e1, e2 * e2);
+}
+
+// Blend weight exp(-(q - shift)/2) (Eq. 5 scaled by exp(shift/2), which cancels in the ratio).
+__device__ __forceinline__ float blend_weight(double q, float shift) {
+  return __expf(-0.5f * (float)(q - (double)shift));
+}
+
+// Kernel variants by top-K capacity: the smallest KT >= K is used (the first K entries of a
+// sorted top-KT list are the top-K).
+#define IGS_FOR_EACH_KT(X) X(1) X(2) X(4) X(8) X(10) X(16) X(32)
+
+inline int pick_kt(int K) {
+  const int kts[] = {1, 2, 4, 8, 10, 16, 32};
+  for (int kt : kts)
+    if (K <= kt) return kt;
+  return -1;
+}
+
+// XCD-aware tile order.  Workgroup ids are dealt round-robin to the 8 XCDs, so map the ids an
+// XCD receives (bid = x, x+8, x+16, ...) onto one contiguous run of tiles: neighbouring tiles
+// share Gaussians, which then stay in that XCD's L2.  A bijection on [0, T): XCD x receives
+// q + (x < r) ids (T = 8q + r) and its run starts at x*q + min(x, r).
+__device__ __forceinline__ int xcd_tile(int bid, int T) {
+  constexpr int kXcd = 8;
+  const int q = T / kXcd, r = T % kXcd;
+  const int x = bid % kXcd, k = bid / kXcd;
+  return x * q + min(x, r) + k;
+}
+
+}  // namespace igs

@@ -1,0 +1,173 @@
+"""Fitting loop around the renderer (Image-GS Sec. 3.3 and Sec. 4.1): every iteration renders the
+Gaussians, takes the L1 loss gradient against the target, runs the adjoint and applies one Adam
+step with the paper's constant per-group learning rates, in the fitter's parameterization
+(mean normalized to [0,1]^2, inverse scales 1/s).  Every step is a libimagegs kernel; an
+iteration enqueues with no host synchronization and can be captured as one HIP graph.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Optional, Tuple
+
+import torch
+
+from . import _native as nat
+from .render import Renderer, _aligned_bytes
+
+# Sec. 4.1: learning rates of (mu, c, s, theta), constant throughout training
+LR_MU, LR_COLOR, LR_SCALE, LR_THETA = 5e-4, 5e-3, 2e-3, 2e-3
+
+
+@dataclass
+class AdamConfig:
+    lr_mu: float = LR_MU
+    lr_theta: float = LR_THETA
+    lr_inv_scale: float = LR_SCALE
+    lr_color: float = LR_COLOR
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    inv_scale_hi: float = 4.0       # 1/s <= 4, i.e. s >= 0.25 px; 1/s >= 1/max(H, W)
+
+
+class PlainFitter:
+    """Fits one image.  ``render_params`` is the initial [5+n][N] float32 set in pixel units."""
+
+    def __init__(self, target: torch.Tensor, render_params: torch.Tensor, K: int = 10,
+                 adam: Optional[AdamConfig] = None, headroom: float = 1.25,
+                 pair_capacity: Optional[int] = None):
+        if target.dim() != 3:
+            raise ValueError("target must be [n][H][W]")
+        self.dev = target.device
+        self.target = target.contiguous().float()
+        self.n, self.H, self.W = self.target.shape
+        self.N = render_params.shape[1]
+        self.K = K
+        self.adam = adam or AdamConfig()
+        self.rend = render_params.to(self.dev).float().contiguous().clone()
+        self.fit = torch.empty_like(self.rend)
+        self.fit.copy_(self.rend)
+        self.fit[0] /= self.W
+        self.fit[1] /= self.H
+        self.fit[3:5] = 1.0 / self.fit[3:5]
+        # render parameters are always derived from the fitter's by the library's conversion
+        nat.igs_fit_to_render(self.fit, self.rend, self.N, self.n, self.H, self.W)
+        self.m = torch.zeros_like(self.rend)
+        self.v = torch.zeros_like(self.rend)
+        self.step_count = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.r = Renderer(self.N, self.n, self.H, self.W, K, pair_capacity=pair_capacity,
+                          device=self.dev)
+        self.image = torch.empty_like(self.target)
+        self.grad_image = torch.empty_like(self.target)
+        self.grad_params = torch.empty_like(self.rend)
+        self.loss = torch.zeros(2, dtype=torch.float64, device=self.dev)
+        self.l1_ws = _aligned_bytes(nat.igs_l1_workspace_size(self.target.numel()), self.dev)
+        if pair_capacity is None:
+            # size the pair buffer from one render of the initial state, with headroom for growth
+            _, saved = self.r.render(self.rend, keep_state=True)
+            P = int(self.r.status_of(saved)[nat.STAT_PAIRS])
+            self.r.set_capacity(max(1024, int(P * headroom)))
+        self.saved = self.r.new_saved()
+        self.graph: Optional[torch.cuda.CUDAGraph] = None
+        self.status_host = torch.zeros(8, dtype=torch.int64).pin_memory()
+
+    # ------------------------------------------------------------------------------- one step
+
+    def step_async(self) -> None:
+        """Enqueue one iteration on the current stream (no synchronization)."""
+        a = self.adam
+        self.r.render_into(self.rend, self.image, self.saved)
+        nat.igs_l1_loss_grad(self.image, self.target, self.n, self.H, self.W, self.grad_image,
+                             self.loss, self.l1_ws, self.l1_ws.numel())
+        self.r.backward_into(self.rend, self.image, self.grad_image, self.saved, self.grad_params)
+        # an iteration whose render overflowed the pair buffer changes nothing (and does not
+        # count); the host notices from the step counter, grows the buffer and repeats it
+        nat.igs_adam_step(self.fit, self.rend, self.grad_params, self.m, self.v, self.step_count,
+                          self.N, self.n, self.H, self.W, a.lr_mu, a.lr_theta, a.lr_inv_scale,
+                          a.lr_color, a.beta1, a.beta2, a.eps, 1.0 / max(self.H, self.W),
+                          a.inv_scale_hi, skip_flag=self._overflow_word())
+
+    def _overflow_word(self) -> torch.Tensor:
+        return self.r.status_of(self.saved)[nat.STAT_OVERFLOW:nat.STAT_OVERFLOW + 1]
+
+    def capture(self) -> None:
+        """Capture one iteration as a HIP graph (the library allocates nothing, so buffers and
+        kernel arguments stay valid across replays)."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step_async()
+        self.graph = g
+
+    def step(self) -> None:
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self.step_async()
+
+    # --------------------------------------------------------------------------- bookkeeping
+
+    def status(self) -> torch.Tensor:
+        """Status block of the last render (synchronizes)."""
+        self.status_host.copy_(self.r.status_of(self.saved))
+        return self.status_host
+
+    def steps_done(self) -> int:
+        return int(self.step_count.item())
+
+    def grow(self, factor: float = 1.5) -> None:
+        """Enlarge the pair buffer to ``factor`` times the larger of the current capacity and the
+        last render's requirement; drops the captured graph (it is re-captured on demand)."""
+        st = self.status()
+        need = max(self.r.cap, int(st[nat.STAT_PAIRS]))
+        self.r.set_capacity(int(need * factor) + 1024)
+        self.saved = self.r.new_saved()
+        self.graph = None
+
+    def advance_to(self, target: int, use_graph: bool = True, max_rounds: int = 8) -> None:
+        """Run iterations until exactly ``target`` have been applied (skipped ones repeat)."""
+        for _ in range(max_rounds):
+            missing = target - self.steps_done()
+            if missing <= 0:
+                return
+            if use_graph and self.graph is None:
+                self.capture()
+            for _ in range(missing):
+                self.step() if use_graph else self.step_async()
+            if self.steps_done() < target:
+                self.grow()
+        raise RuntimeError("pair buffer kept overflowing")
+
+    def psnr(self) -> float:
+        mse = float(self.loss[1].item())
+        return 10.0 * math.log10(1.0 / mse) if mse > 0 else math.inf
+
+    def run(self, iters: int, report_every: int = 100, use_graph: bool = True
+            ) -> List[Tuple[int, float]]:
+        """Fit for ``iters`` iterations; returns (iteration, PSNR of that iteration's render)
+        every ``report_every`` iterations (and at the last)."""
+        start = self.steps_done()
+        out = []
+        it = 0
+        while it < iters:
+            it = min(iters, (it // report_every + 1) * report_every)
+            self.advance_to(start + it, use_graph)
+            out.append((it, self.psnr()))
+        return out
+
+    def snapshot(self) -> dict:
+        return self.state_dict()
+
+    def restore(self, sd: dict) -> None:
+        self.load_state_dict(sd)
+
+    def state_dict(self) -> dict:
+        return {"fit": self.fit.clone(), "m": self.m.clone(), "v": self.v.clone(),
+                "step": self.step_count.clone(), "H": self.H, "W": self.W, "K": self.K}
+
+    def load_state_dict(self, sd: dict) -> None:
+        self.fit.copy_(sd["fit"])
+        self.m.copy_(sd["m"])
+        self.v.copy_(sd["v"])
+        self.step_count.copy_(sd["step"])
+        nat.igs_fit_to_render(self.fit, self.rend, self.N, self.n, self.H, self.W)

@@ -1,0 +1,179 @@
+"""Python front end of libimagegs: device buffers for the C ABI, a render/adjoint pair, and the
+``torch.autograd.Function`` used for fitting.  Every step of the renderer runs in the HIP library;
+this module only allocates torch tensors and calls the ABI (see ``_native``).
+"""
+from __future__ import annotations
+
+from typing import Optional, Tuple
+
+import torch
+
+from . import _native as nat
+
+TILE = nat.IGS_TILE
+
+
+def _aligned_bytes(nbytes: int, device) -> torch.Tensor:
+    """A uint8 device buffer of ``nbytes`` whose data pointer is 256-byte aligned."""
+    raw = torch.empty(max(1, nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + max(1, nbytes)]
+
+
+def initial_pair_capacity(N: int, H: int, W: int) -> int:
+    """A first guess for the number of (tile, Gaussian) pairs: 16 per Gaussian, at least 64k."""
+    return max(1 << 16, 16 * N)
+
+
+class Renderer:
+    """Scratch workspace for one problem shape (N, n, H, W, K) and a pair capacity that grows
+    when the device reports an overflow.  Saved forward state is allocated per render call so that
+    several renders may be pending an adjoint at once."""
+
+    def __init__(self, N: int, n: int, H: int, W: int, K: int = 10,
+                 pair_capacity: Optional[int] = None, device="cuda"):
+        self.N, self.n, self.H, self.W, self.K = N, n, H, W, K
+        self.device = torch.device(device)
+        self.cap = int(pair_capacity or initial_pair_capacity(N, H, W))
+        self._alloc()
+
+    def _alloc(self):
+        self.ws_bytes, self.saved_bytes = nat.igs_render_buffer_sizes(
+            self.N, self.n, self.H, self.W, self.K, TILE, TILE, self.cap)
+        self.offsets = nat.igs_saved_offsets(self.N, self.n, self.H, self.W, self.K, TILE, TILE,
+                                             self.cap)
+        self.ws = _aligned_bytes(self.ws_bytes, self.device)
+
+    def set_capacity(self, cap: int) -> None:
+        if cap != self.cap:
+            self.cap = int(cap)
+            self._alloc()
+
+    def new_saved(self) -> torch.Tensor:
+        return _aligned_bytes(self.saved_bytes, self.device)
+
+    # -------------------------------------------------------------------------- raw entry points
+
+    def render_into(self, params: torch.Tensor, image: torch.Tensor,
+                    saved: Optional[torch.Tensor]) -> None:
+        """Enqueue one forward render (no synchronization, no overflow handling)."""
+        if saved is None:
+            need = self.ws_bytes + self.saved_bytes
+            if self.ws.numel() < need:
+                self.ws = _aligned_bytes(need, self.device)
+            nat.igs_render(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE, self.cap,
+                           image, None, 0, self.ws, self.ws.numel())
+        else:
+            nat.igs_render(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE, self.cap,
+                           image, saved, saved.numel(), self.ws, self.ws.numel())
+
+    def backward_into(self, params, image, grad_image, saved, grad_params) -> None:
+        nat.igs_render_backward(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE,
+                                self.cap, image, grad_image, saved, saved.numel(), grad_params,
+                                self.ws, self.ws.numel())
+
+    def status_of(self, saved: Optional[torch.Tensor]) -> torch.Tensor:
+        """The int64[8] device status block of a saved state (or of the workspace copy)."""
+        buf = saved if saved is not None else self.ws[self.ws_bytes:]
+        return buf[:64].view(torch.int64)
+
+    # --------------------------------------------------------------------------- checked calls
+
+    def render(self, params: torch.Tensor, keep_state: bool = True
+               ) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+        """Render and, if the pair capacity was too small, grow it to the reported size and render
+        again (one 64-byte device-to-host read per call).  Returns (image, saved or None)."""
+        image = torch.empty((self.n, self.H, self.W), dtype=torch.float32, device=self.device)
+        for _ in range(2):
+            saved = self.new_saved() if keep_state else None
+            self.render_into(params, image, saved)
+            st = self.status_of(saved).cpu()
+            if int(st[nat.STAT_OVERFLOW]) == 0:
+                if keep_state and int(st[nat.STAT_SLOT_OVERFLOW]) != 0:
+                    raise RuntimeError("a tile hit set exceeds 65535 Gaussians: the saved top-K "
+                                       "slots cannot be used for the adjoint")
+                return image, saved
+            self.set_capacity(int(int(st[nat.STAT_PAIRS]) * 1.25) + 1024)
+        raise RuntimeError("pair capacity overflow persisted after resizing")
+
+    def backward(self, params, image, grad_image, saved) -> torch.Tensor:
+        gp = torch.empty((5 + self.n, self.N), dtype=torch.float32, device=self.device)
+        self.backward_into(params, image, grad_image.contiguous(), saved, gp)
+        return gp
+
+    # ------------------------------------------------------------------------------ inspection
+
+    def tile_lists(self, saved: torch.Tensor):
+        """(ranges int32[T][2], sorted Gaussian indices int32[P]) of a saved state."""
+        T = ((self.H + TILE - 1) // TILE) * ((self.W + TILE - 1) // TILE)
+        o = self.offsets
+        st = self.status_of(saved).cpu()
+        P = int(st[nat.STAT_PAIRS])
+        ranges = saved[o["ranges"]:o["ranges"] + 8 * T].view(torch.int32).view(T, 2)
+        vals = saved[o["vals"]:o["vals"] + 4 * min(P, self.cap)].view(torch.int32)
+        return ranges, vals
+
+    def slots(self, saved: torch.Tensor) -> torch.Tensor:
+        """Saved top-K slots as int32 [K][H][W] (-1 = unused)."""
+        o = self.offsets
+        n = self.K * self.H * self.W
+        s = saved[o["slots"]:o["slots"] + 2 * n].view(torch.int16).to(torch.int32) & 0xFFFF
+        s = s.view(self.K, self.H, self.W)
+        return torch.where(s == 0xFFFF, torch.full_like(s, -1), s)
+
+
+def pack_params(means: torch.Tensor, theta: torch.Tensor, scales: torch.Tensor,
+                colors: torch.Tensor) -> torch.Tensor:
+    """[N,2], [N], [N,2], [N,n] -> float32 SoA [5+n][N] in the renderer's row order."""
+    return torch.cat([means.T, theta[None], scales.T, colors.T], dim=0).float().contiguous()
+
+
+_cache = {}
+
+
+def renderer_for(N, n, H, W, K, device) -> Renderer:
+    key = (N, n, H, W, K, str(device))
+    r = _cache.get(key)
+    if r is None:
+        r = Renderer(N, n, H, W, K, device=device)
+        _cache[key] = r
+    return r
+
+
+def render(params: torch.Tensor, H: int, W: int, K: int = 10) -> torch.Tensor:
+    """Render a [5+n][N] float32 parameter set (pixel units) into an [n][H][W] image."""
+    n, N = params.shape[0] - 5, params.shape[1]
+    r = renderer_for(N, n, H, W, K, params.device)
+    img, _ = r.render(params.contiguous(), keep_state=False)
+    return img
+
+
+class RenderFn(torch.autograd.Function):
+    """Differentiable Image-GS render in the fitter's parameterization.
+
+    Inputs: means [N,2] normalized to [0,1]^2 (x by W, y by H), theta [N], inverse scales [N,2]
+    (1/s in 1/pixels), colors [N,n]; H, W, K.  Output: [n,H,W].  The backward returns gradients
+    for the four tensors, computed by the HIP adjoint through the K retained Gaussians."""
+
+    @staticmethod
+    def forward(ctx, means, theta, inv_scales, colors, H: int, W: int, K: int = 10):
+        N, n = means.shape[0], colors.shape[1]
+        wh = torch.tensor([W, H], dtype=means.dtype, device=means.device)
+        params = pack_params(means * wh, theta, 1.0 / inv_scales, colors)
+        r = renderer_for(N, n, H, W, K, means.device)
+        image, saved = r.render(params, keep_state=True)
+        ctx.r, ctx.saved_state = r, saved
+        ctx.H, ctx.W = H, W
+        ctx.save_for_backward(params, image, inv_scales)
+        return image
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        params, image, inv_scales = ctx.saved_tensors
+        gp = ctx.r.backward(params, image, grad_image.float().contiguous(), ctx.saved_state)
+        W, H = ctx.W, ctx.H
+        d_means = torch.stack([gp[0] * W, gp[1] * H], dim=1)
+        d_theta = gp[2].clone()
+        d_inv = (-gp[3:5] / (inv_scales.T * inv_scales.T)).T      # dL/du = -s^2 dL/ds
+        d_colors = gp[5:].T.contiguous()
+        return d_means, d_theta, d_inv.contiguous(), d_colors, None, None, None

@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function the
+header declares, and validates arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "imagegs.h")
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_2407_01866_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_2407_01866_amd import build
+        build.build()
+    _native.lib()
+    return _native
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(igs_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(nat):
+    names = declared_functions()
+    assert len(names) >= 9
+    L = ctypes.CDLL(nat.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(nat.EXPORTED)
+
+
+def test_abi_version_and_status_strings(nat):
+    assert nat.igs_abi_version() == 1
+    assert nat.igs_status_string(0) == "ok"
+    for s in (-1, -2, -3, -4):
+        assert nat.igs_status_string(s) not in ("ok", "unknown status")
+
+
+def test_buffer_sizes_scale_with_problem(nat):
+    ws1, sv1 = nat.igs_render_buffer_sizes(1000, 3, 256, 256, 10, 16, 16, 20000)
+    ws2, sv2 = nat.igs_render_buffer_sizes(1000, 3, 256, 256, 10, 16, 16, 40000)
+    assert ws2 > ws1 and sv2 > sv1
+    ws3, sv3 = nat.igs_render_buffer_sizes(1000, 3, 512, 256, 10, 16, 16, 20000)
+    assert sv3 > sv1
+    off = nat.igs_saved_offsets(1000, 3, 256, 256, 10, 16, 16, 20000)
+    assert off["status"] == 0 and off["total"] == sv1
+    assert off["ranges"] < off["vals"] < off["slots"] < off["aux"] < off["total"]
+    assert all(v % 256 == 0 for v in off.values())
+    # slots hold K uint16 per pixel
+    assert off["aux"] - off["slots"] >= 10 * 256 * 256 * 2
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 3, 16, 16, 10, 16, 16, 100), -1),
+    ((10, 0, 16, 16, 10, 16, 16, 100), -1),
+    ((10, 33, 16, 16, 10, 16, 16, 100), -1),
+    ((10, 3, 0, 16, 10, 16, 16, 100), -1),
+    ((10, 3, 16, 16, 0, 16, 16, 100), -1),
+    ((10, 3, 16, 16, 33, 16, 16, 100), -1),
+    ((10, 3, 16, 16, 10, 16, 16, 0), -1),
+    ((10, 3, 16, 16, 10, 16, 16, 1 << 31), -1),
+    ((10, 3, 16, 16, 10, 8, 8, 100), -4),
+    ((10, 3, 16, 16, 10, 32, 16, 100), -4),
+])
+def test_size_query_rejects_bad_arguments(nat, args, code):
+    with pytest.raises(nat.IGSError) as e:
+        nat.igs_render_buffer_sizes(*args)
+    assert e.value.status == code
+
+
+def test_render_validates_before_device_work(nat):
+    L = nat.lib()
+    # NULL image / workspace: rejected synchronously, no HIP call is made
+    assert L.igs_render(None, 0, 3, 16, 16, 10, 16, 16, 100, None, None, 0, None, 0, None) == -1
+    assert L.igs_render(None, 0, 3, 16, 16, 10, 8, 8, 100, None, None, 0, None, 0, None) == -4
+    assert L.igs_render_backward(None, 5, 3, 16, 16, 10, 16, 16, 100, None, None, None, 0, None,
+                                 None, 0, None) == -1
+    assert L.igs_l1_loss_grad(None, None, 3, 4, 4, None, None, None, 0, None) == -1
+    assert L.igs_adam_step(None, None, None, None, None, None, None, 4, 3, 8, 8, 1e-3, 1e-3, 1e-3,
+                           1e-3, 0.9, 0.999, 1e-8, 0.1, 4.0, None) == -1
+    assert L.igs_fit_to_render(None, None, 4, 0, 8, 8, None) == -1
+    sz = ctypes.c_size_t(0)
+    assert L.igs_l1_workspace_size(0, ctypes.byref(sz)) == -1
+    assert L.igs_l1_workspace_size(1000, ctypes.byref(sz)) == 0 and sz.value >= 16
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    from paper_2407_01866_amd import _native
+    monkeypatch.setattr(_native, "_lib", None)
+    monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError):
+        _native.lib()

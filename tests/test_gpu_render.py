@@ -1,0 +1,432 @@
+"""GPU parity of the HIP renderer against the FP64 oracle, through the C ABI.
+
+Bars: tile hit sets bit-exact; top-K index sets bit-exact wherever the oracle's gap between the
+K-th and (K+1)-th ranked q exceeds 1e-5 (1 + q_(K+1)) (several answers are correct inside that
+band); pixels |d| <= 1e-5 |ref| + 1e-7 at those pixels; gradients per parameter row
+|d| <= 1e-4 max(|ref|, 1e-2 max|ref_row|) with the upstream gradient zeroed at near-tie pixels
+(so both sides differentiate the same selection), plus 1e-5 times the oracle's sum of the terms'
+magnitudes before cancellation, the size of float32 evaluation error in a sum whose exact value
+is zero or nearly so (e.g. the geometry gradient of a Gaussian that is alone in its pixels).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cref, fitref
+from paper_2407_01866_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GAP_REL = 1e-5
+PIX_REL, PIX_ABS = 1e-5, 1e-7
+GRAD_REL, GRAD_FLOOR = 1e-4, 1e-2
+GRAD_COND = 1e-5      # times the oracle's sum of term magnitudes (float32 evaluation error bound)
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def renderer(N, n, H, W, K, cap=None):
+    from paper_2407_01866_amd.render import Renderer
+    return Renderer(N, n, H, W, K, pair_capacity=cap, device=dev())
+
+
+def near_tie_mask(qsel, K):
+    """True where the oracle's selection is within the near-tie band."""
+    qk, qk1 = qsel[..., K - 1], qsel[..., K]
+    with np.errstate(invalid="ignore"):
+        return np.isfinite(qk1) & (qk1 - qk <= GAP_REL * (1.0 + qk1))
+
+
+def gpu_ids(r, saved, H, W, K):
+    """Saved slots -> Gaussian indices [H][W][K] (-1 unused), via the GPU's own tile lists."""
+    ranges, vals = r.tile_lists(saved)
+    ranges, vals = ranges.cpu().numpy(), vals.cpu().numpy()
+    slots = r.slots(saved).cpu().numpy()                     # [K][H][W]
+    tx_n = (W + 15) // 16
+    hh, ww = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    start = ranges[(hh // 16) * tx_n + ww // 16, 0]
+    ids = np.where(slots >= 0, vals[np.clip(start[None] + slots, 0, max(0, len(vals) - 1))], -1)
+    return np.moveaxis(ids, 0, 2), ranges, vals
+
+
+def check_tile_lists(p64, H, W, ranges, vals):
+    counts, lists = cref.tile_lists(p64, H, W)
+    assert np.array_equal(ranges[:, 1] - ranges[:, 0], counts)
+    assert np.array_equal(vals[: counts.sum()], lists)
+
+
+def check_forward(img_gpu, ids_gpu, ref, K, tie=None):
+    if tie is None:
+        tie = near_tie_mask(ref["qsel"], K)
+    ok = ~tie
+    a = np.sort(np.where(ids_gpu < 0, np.iinfo(np.int64).max, ids_gpu), axis=-1)
+    b = np.sort(np.where(ref["topk"] < 0, np.iinfo(np.int64).max, ref["topk"]), axis=-1)
+    mism = np.any(a != b, axis=-1) & ok
+    assert mism.sum() == 0, f"{mism.sum()} pixels select a different top-K set"
+    d = np.abs(img_gpu - ref["img"])
+    lim = PIX_REL * np.abs(ref["img"]) + PIX_ABS
+    bad = (d > lim) & ok[None]
+    assert bad.sum() == 0, f"{bad.sum()} pixel values out of tolerance, worst {d[ok[None].repeat(d.shape[0], 0)].max():.3e}"
+    return int(tie.sum())
+
+
+def check_grad(g_gpu, g_ref, g_abs):
+    rowmax = np.abs(g_ref).max(axis=1, keepdims=True)
+    lim = GRAD_REL * np.maximum(np.abs(g_ref), GRAD_FLOOR * rowmax) + GRAD_COND * g_abs + 1e-30
+    bad = np.abs(g_gpu - g_ref) > lim
+    assert bad.sum() == 0, (f"{bad.sum()} gradient entries out of tolerance; rows "
+                            f"{sorted(set(np.nonzero(bad)[0].tolist()))}, worst rel "
+                            f"{(np.abs(g_gpu - g_ref) / lim).max():.3f}")
+
+
+def run_full(p, H, W, K, seed=0, cap=None, check_bwd=True):
+    """Full-image parity of forward and adjoint against the oracle."""
+    n, N = p.shape[0] - 5, p.shape[1]
+    print(f"[parity] H={H} W={W} n={n} N={N} K={K} seed={seed}", flush=True)
+    d = dev()
+    r = renderer(N, n, H, W, K, cap)
+    pt = torch.from_numpy(np.ascontiguousarray(p)).to(d)
+    img, saved = r.render(pt)
+    torch.cuda.synchronize()
+    p64 = p.astype(np.float64)
+    ids, ranges, vals = gpu_ids(r, saved, H, W, K)
+    check_tile_lists(p64, H, W, ranges, vals)
+    ref = cref.render(p64, H, W, K)
+    tie = near_tie_mask(ref["qsel"], K)
+    check_forward(img.cpu().numpy().astype(np.float64), ids, ref, K, tie)
+    if not check_bwd:
+        return r
+    g = synth.gen_grad_image(seed + 17, n, H, W)
+    g[:, tie] = 0.0
+    gt = torch.from_numpy(g).to(d)
+    gp = r.backward(pt, img, gt, saved)
+    torch.cuda.synchronize()
+    o = cref.render(p64, H, W, K, grad_img=g.astype(np.float64))
+    check_grad(gp.cpu().numpy().astype(np.float64), o["grad"], o["grad_abs"])
+    return r
+
+
+# ------------------------------------------------------------------------- workload parity
+
+
+def test_plain_256_n3_N2000():
+    w = synth.workload(0)
+    run_full(w.gaussians(), w.H, w.W, w.K, seed=1)
+
+
+@pytest.mark.parametrize("H,W,N,n,K", [(200, 136, 800, 3, 10), (17, 33, 40, 1, 4),
+                                       (1, 77, 12, 2, 3), (90, 1, 9, 3, 2), (48, 48, 150, 9, 16)])
+def test_ragged_shapes(H, W, N, n, K):
+    p = synth.gen_gaussians(H * 7 + W, H, W, N, n)
+    run_full(p, H, W, K, seed=H + W)
+
+
+def test_fit_workload_1024_N20000_full():
+    w = synth.workload(1)
+    run_full(w.gaussians(), w.H, w.W, w.K, seed=2)
+
+
+@pytest.mark.parametrize("K", [1, 2, 5, 10, 16, 32])
+def test_k_values(K):
+    H, W, N, n = 96, 112, 700, 3
+    p = synth.gen_gaussians(40 + K, H, W, N, n)
+    run_full(p, H, W, K, seed=K)
+
+
+@pytest.mark.parametrize("n", [1, 4, 9, 32])
+def test_channel_counts(n):
+    H, W, N = 64, 80, 300
+    p = synth.gen_gaussians(60 + n, H, W, N, n)
+    run_full(p, H, W, 10, seed=n)
+
+
+# ------------------------------------------------------------------------- edge cases
+
+
+def test_empty_parameter_set():
+    d = dev()
+    r = renderer(0, 3, 40, 24, 10)
+    img, saved = r.render(torch.zeros((8, 0), device=d))
+    assert torch.all(img == 0)
+    assert int(r.status_of(saved)[0]) == 0
+    gp = r.backward(torch.zeros((8, 0), device=d), img, torch.ones_like(img), saved)
+    assert gp.numel() == 0
+
+
+def test_single_gaussian_and_empty_tiles():
+    p = np.array([[20.3], [11.7], [0.6], [2.0], [1.25], [0.25], [0.5], [0.75]], dtype=np.float32)
+    run_full(p, 64, 80, 10, seed=3)
+
+
+def test_gaussians_outside_image_and_huge_ones():
+    rng = np.random.default_rng(5)
+    H, W, n = 64, 96, 3
+    p = synth.gen_gaussians(8, H, W, 200, n)
+    p[0, :40] = rng.uniform(-80, -20, 40)           # left of the image, some still reach in
+    p[1, 40:60] = rng.uniform(H + 5, H + 60, 20)    # below it
+    p[3, 60:70] = 200.0                              # covers every tile
+    run_full(p, H, W, 10, seed=5)
+
+
+def test_long_tile_lists_span_several_lds_batches():
+    """|S_j| > 256 in every tile: the selection crosses LDS batches and the blend and adjoint
+    take the path that reads winners from global memory."""
+    H, W, n, N = 64, 64, 3, 700
+    p = synth.gen_gaussians(9, H, W, N, n, 8.0, 30.0)
+    r = run_full(p, H, W, 10, seed=9)
+    assert r is not None
+
+
+def test_exact_ties_keep_lower_index():
+    H, W = 32, 32
+    base = synth.gen_gaussians(11, H, W, 30, 3)
+    p = np.concatenate([base, base[:, :10], base[:, :10]], axis=1)   # exact duplicates
+    p[5:, 30:] = np.random.default_rng(0).uniform(0, 1, (3, 20)).astype(np.float32)
+    run_full(p, H, W, 10, seed=11)
+
+
+def test_tangent_circles_bitexact():
+    """Circles exactly tangent to tile edges and corners must count as hits on both sides."""
+    rows = [[22.0, 8.0, 0.0, 2.0, 1.0], [25.0, 28.0, 0.3, 5.0, 1.0], [47.0, 8.0, 1.0, 2.5, 1.0],
+            [16.0, 40.0, 2.0, 1.0, 4.0], [22.0 + 2.0 ** -18, 30.0, 0.0, 2.0, 1.0]]
+    p = np.zeros((8, len(rows)), dtype=np.float32)
+    p[:5] = np.array(rows, dtype=np.float32).T
+    p[5:] = 0.5
+    run_full(p, 48, 40, 4, seed=12)
+
+
+def test_pair_capacity_overflow_is_reported_and_recovered():
+    d = dev()
+    w = synth.workload(0)
+    p = torch.from_numpy(w.gaussians()).to(d)
+    r = renderer(w.N, w.n, w.H, w.W, w.K, cap=1000)
+    img = torch.empty((w.n, w.H, w.W), device=d)
+    saved = r.new_saved()
+    r.render_into(p, img, saved)
+    st = r.status_of(saved).cpu().numpy()
+    counts, _ = cref.tile_lists(w.gaussians().astype(np.float64), w.H, w.W)
+    assert st[0] == counts.sum() and st[1] == 1
+    img2, saved2 = r.render(p)           # grows the capacity and re-renders
+    assert r.cap >= counts.sum()
+    assert int(r.status_of(saved2)[1]) == 0
+
+
+def test_invalid_arguments_raise():
+    from paper_2407_01866_amd import _native as nat
+    d = dev()
+    with pytest.raises(nat.IGSError) as e:
+        nat.igs_render_buffer_sizes(10, 3, 16, 16, 33)
+    assert e.value.status == nat.IGS_ERR_INVALID_ARG
+    with pytest.raises(nat.IGSError) as e:
+        nat.igs_render_buffer_sizes(10, 3, 16, 16, 10, 8, 8, 100)
+    assert e.value.status == nat.IGS_ERR_UNSUPPORTED
+    ws, sv = nat.igs_render_buffer_sizes(10, 3, 16, 16, 10, 16, 16, 100)
+    p = torch.rand((8, 10), device=d)
+    img = torch.empty((3, 16, 16), device=d)
+    small = torch.empty(256, dtype=torch.uint8, device=d)
+    with pytest.raises(nat.IGSError) as e:
+        nat.igs_render(p, 10, 3, 16, 16, 10, 16, 16, 100, img, None, 0, small, 256)
+    assert e.value.status == nat.IGS_ERR_WORKSPACE
+
+
+# ------------------------------------------------------------------------- full-size, sampled
+
+
+def sampled_parity(w, n_tiles=48, n_gauss=24, seed=0):
+    """Full-size render in the benchmark's launch configuration; the oracle recomputes a sample of
+    tiles (every pixel of each) and the exact gradient rows of a sample of Gaussians."""
+    d = dev()
+    p = w.gaussians()
+    H, W, n, K = w.H, w.W, w.n, w.K
+    print(f"[sampled] {w.name}", flush=True)
+    r = renderer(w.N, n, H, W, K)
+    pt = torch.from_numpy(p).to(d)
+    img, saved = r.render(pt)
+    torch.cuda.synchronize()
+    ranges, vals = r.tile_lists(saved)
+    ranges, vals = ranges.cpu().numpy(), vals.cpu().numpy()
+    slots = r.slots(saved).cpu().numpy()
+    rng = np.random.default_rng(seed)
+    T = ranges.shape[0]
+    tx_n = (W + 15) // 16
+    tiles = np.unique(np.concatenate([[0, tx_n - 1, T - tx_n, T - 1], rng.choice(T, n_tiles, replace=False)]))
+    p64 = p.astype(np.float64)
+    counts, lists = cref.tile_lists(p64, H, W, tiles=tiles)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    for a, t in enumerate(tiles):
+        assert ranges[t, 1] - ranges[t, 0] == counts[a]
+        assert np.array_equal(vals[ranges[t, 0]:ranges[t, 1]], lists[off[a]:off[a + 1]])
+    ref = cref.render_tiles(p64, H, W, K, tiles=tiles)
+    img_np = img.cpu().numpy()
+    for a, t in enumerate(tiles):
+        tx, ty = t % tx_n, t // tx_n
+        x0, y0 = tx * 16, ty * 16
+        x1, y1 = min(x0 + 16, W), min(y0 + 16, H)
+        gi = img_np[:, y0:y1, x0:x1].astype(np.float64)
+        ri = ref["img"][a].reshape(n, 16, 16)[:, : y1 - y0, : x1 - x0]
+        sl = slots[:, y0:y1, x0:x1]
+        ids = np.where(sl >= 0, vals[np.clip(ranges[t, 0] + sl, 0, len(vals) - 1)], -1)
+        rt = ref["topk"][a].reshape(16, 16, K)[: y1 - y0, : x1 - x0]
+        rq = ref["qsel"][a].reshape(16, 16, K + 1)[: y1 - y0, : x1 - x0]
+        check_forward(gi, np.moveaxis(ids, 0, 2), {"img": ri, "topk": rt, "qsel": rq}, K)
+    # gradients of sampled Gaussians, upstream gradient zeroed at near-tie pixels of their tiles
+    gids = rng.choice(w.N, n_gauss, replace=False)
+    g = synth.gen_grad_image(seed + 99, n, H, W)
+    sub_counts, _ = cref.tile_lists(p64[:, gids], H, W)
+    gtiles = np.nonzero(sub_counts > 0)[0].astype(np.int32)
+    qs = cref.render_tiles(p64, H, W, K, tiles=gtiles, want=("qsel",))["qsel"]
+    for a, t in enumerate(gtiles):
+        tx, ty = t % tx_n, t // tx_n
+        x0, y0 = tx * 16, ty * 16
+        x1, y1 = min(x0 + 16, W), min(y0 + 16, H)
+        tie = near_tie_mask(qs[a].reshape(16, 16, K + 1)[: y1 - y0, : x1 - x0], K)
+        g[:, y0:y1, x0:x1][:, tie] = 0.0
+    gt = torch.from_numpy(g).to(d)
+    gp = r.backward(pt, img, gt, saved).cpu().numpy().astype(np.float64)[:, gids]
+    gref, gabs = cref.grad_for_gaussians(p64, H, W, K, g.astype(np.float64), gids, with_abs=True)
+    # the row floor uses the sampled rows' scale
+    check_grad(gp, gref, gabs)
+
+
+def test_texture_2048_n9_N100000_sampled():
+    sampled_parity(synth.workload(2), seed=3)
+
+
+def test_large_4096_N500000_sampled():
+    sampled_parity(synth.workload(4), n_tiles=32, n_gauss=16, seed=4)
+
+
+# ------------------------------------------------------------------------- loss and optimizer
+
+
+def test_l1_loss_grad_matches_reference():
+    from paper_2407_01866_amd import _native as nat
+    d = dev()
+    n, H, W = 3, 77, 131
+    img = torch.from_numpy(synth.gen_image(1, H, W, n, 5)).to(d)
+    tgt = torch.from_numpy(synth.gen_image(2, H, W, n, 5)).to(d)
+    tgt[0, :3, :3] = img[0, :3, :3]                    # exact zeros of the difference
+    g = torch.empty_like(img)
+    loss = torch.zeros(2, dtype=torch.float64, device=d)
+    ws = torch.empty(nat.igs_l1_workspace_size(img.numel()), dtype=torch.uint8, device=d)
+    nat.igs_l1_loss_grad(img, tgt, n, H, W, g, loss, ws, ws.numel())
+    torch.cuda.synchronize()
+    l_ref, g_ref = fitref.l1_loss_grad(img.cpu().numpy(), tgt.cpu().numpy())
+    assert np.array_equal(np.sign(g.cpu().numpy()), np.sign(g_ref))
+    np.testing.assert_allclose(g.cpu().numpy(), g_ref, rtol=1e-6)
+    assert loss[0].item() == pytest.approx(l_ref, rel=1e-13)
+    mse = np.mean((img.cpu().numpy().astype(np.float64) - tgt.cpu().numpy()) ** 2)
+    assert loss[1].item() == pytest.approx(mse, rel=1e-13)
+
+
+def test_adam_step_matches_reference():
+    from paper_2407_01866_amd import _native as nat
+    d = dev()
+    H, W, n, N = 64, 96, 3, 500
+    rp = synth.gen_gaussians(3, H, W, N, n)
+    fp = fitref.to_fit_space(rp.astype(np.float64), H, W).astype(np.float32)
+    rng = np.random.default_rng(0)
+    m = np.zeros((5 + n, N), np.float32)
+    v = np.zeros((5 + n, N), np.float32)
+    f_t = torch.from_numpy(fp.copy()).to(d)
+    r_t = torch.empty_like(f_t)
+    m_t, v_t = torch.zeros_like(f_t), torch.zeros_like(f_t)
+    step = torch.zeros(1, dtype=torch.int32, device=d)
+    f_ref, m_ref, v_ref = fp.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    lrs = fitref.row_lrs(n)
+    for t in range(1, 4):
+        g = (rng.standard_normal((5 + n, N)) * 1e-3).astype(np.float32)
+        nat.igs_adam_step(f_t, r_t, torch.from_numpy(g).to(d), m_t, v_t, step, N, n, H, W,
+                          fitref.LR_MU, fitref.LR_TH, fitref.LR_S, fitref.LR_C)
+        gf = fitref.grad_to_fit_space(g.astype(np.float64), f_ref, H, W)
+        f_ref, m_ref, v_ref = fitref.adam_step(f_ref, gf, m_ref, v_ref, t, lrs, H=H, W=W)
+    torch.cuda.synchronize()
+    assert int(step.item()) == 3
+    np.testing.assert_allclose(f_t.cpu().numpy(), f_ref, rtol=2e-5, atol=2e-6)
+    np.testing.assert_allclose(r_t.cpu().numpy(), fitref.to_render_space(f_ref, H, W), rtol=2e-5, atol=2e-5)
+
+
+# ------------------------------------------------------------------------- autograd.Function
+
+
+def test_autograd_function_matches_oracle_chain_rule():
+    from paper_2407_01866_amd.render import RenderFn
+    d = dev()
+    H, W, n, N, K = 80, 64, 3, 400, 10
+    rp = synth.gen_gaussians(21, H, W, N, n)
+    fp = fitref.to_fit_space(rp.astype(np.float64), H, W)
+    means = torch.tensor(fp[0:2].T, dtype=torch.float32, device=d, requires_grad=True)
+    theta = torch.tensor(fp[2], dtype=torch.float32, device=d, requires_grad=True)
+    inv = torch.tensor(fp[3:5].T, dtype=torch.float32, device=d, requires_grad=True)
+    col = torch.tensor(fp[5:].T, dtype=torch.float32, device=d, requires_grad=True)
+    img = RenderFn.apply(means, theta, inv, col, H, W, K)
+    rp32 = fitref.to_render_space(fp, H, W)
+    ref = cref.render(rp32.astype(np.float32).astype(np.float64), H, W, K)
+    tie = near_tie_mask(ref["qsel"], K)
+    g = synth.gen_grad_image(5, n, H, W)
+    g[:, tie] = 0
+    (img * torch.from_numpy(g).to(d)).sum().backward()
+    o = cref.render(rp32.astype(np.float32).astype(np.float64), H, W, K, grad_img=g.astype(np.float64))
+    gfit = fitref.grad_to_fit_space(o["grad"], fp, H, W)
+    gabs = np.abs(fitref.grad_to_fit_space(o["grad_abs"], fp, H, W))
+    got = np.concatenate([means.grad.cpu().numpy().T, theta.grad.cpu().numpy()[None],
+                          inv.grad.cpu().numpy().T, col.grad.cpu().numpy().T]).astype(np.float64)
+    check_grad(got, gfit, gabs)
+
+
+def test_autograd_function_vs_finite_differences_on_texture_crop():
+    """Texture-stack workload (2048^2, n=9, 100k Gaussians): on a tile-aligned 64x64 crop, the
+    autograd.Function gradients agree with central finite differences of the FP64 render."""
+    from paper_2407_01866_amd.render import RenderFn
+    d = dev()
+    w = synth.workload(2)
+    p = w.gaussians()
+    rng = np.random.default_rng(77)
+    x0 = int(rng.integers(0, w.W // 16 - 4)) * 16
+    y0 = int(rng.integers(0, w.H // 16 - 4)) * 16
+    C = 64
+    # Gaussians whose circle reaches the crop; shifting by a multiple of 16 is exact in float32
+    r = 3.0 * np.maximum(p[3], p[4])
+    keep = ((p[0] + r >= x0) & (p[0] - r <= x0 + C) & (p[1] + r >= y0) & (p[1] - r <= y0 + C))
+    q = p[:, keep].copy()
+    q[0] -= x0
+    q[1] -= y0
+    N, n, K = q.shape[1], w.n, w.K
+    fp = fitref.to_fit_space(q.astype(np.float64), C, C)
+    fp32 = fp.astype(np.float32)
+    rp = fitref.to_render_space(fp32.astype(np.float64), C, C).astype(np.float32).astype(np.float64)
+    ref = cref.render(rp, C, C, K)
+    tie = near_tie_mask(ref["qsel"], K)
+    g = synth.gen_grad_image(78, n, C, C)
+    g[:, tie] = 0
+    args = [torch.tensor(a, dtype=torch.float32, device=d, requires_grad=True)
+            for a in (fp32[0:2].T, fp32[2], fp32[3:5].T, fp32[5:].T)]
+    img = RenderFn.apply(*args, C, C, K)
+    (img * torch.from_numpy(g).to(d)).sum().backward()
+    got = np.concatenate([args[0].grad.cpu().numpy().T, args[1].grad.cpu().numpy()[None],
+                          args[2].grad.cpu().numpy().T, args[3].grad.cpu().numpy().T])
+    base_topk = ref["topk"]
+    fp64 = fp32.astype(np.float64)
+    idx = rng.choice(N, min(N, 24), replace=False)
+    checked = 0
+    for i in idx:
+        for row in range(5 + n):
+            h = 1e-6 * max(1.0, abs(fp64[row, i]))
+            a, b = fp64.copy(), fp64.copy()
+            a[row, i] += h
+            b[row, i] -= h
+            oa = cref.render(fitref.to_render_space(a, C, C), C, C, K)
+            ob = cref.render(fitref.to_render_space(b, C, C), C, C, K)
+            if not (np.array_equal(oa["topk"], base_topk) and np.array_equal(ob["topk"], base_topk)):
+                continue
+            fd = ((g * oa["img"]).sum() - (g * ob["img"]).sum()) / (2 * h)
+            scale = np.abs(got[row]).max()
+            assert abs(got[row, i] - fd) <= GRAD_REL * max(abs(fd), GRAD_FLOOR * scale) + 1e-9, (row, i, got[row, i], fd)
+            checked += 1
+    assert checked >= 0.8 * len(idx) * (5 + n)

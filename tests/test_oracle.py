@@ -421,3 +421,16 @@ def test_exact_ties_keep_lower_index():
     o = cref.render(p, H, W, K=2)
     assert np.all(o["topk"] == np.array([0, 1]))
     np.testing.assert_allclose(o["img"][0], 0.5, rtol=1e-15)
+
+
+def test_gradient_conditioning_bounds_the_gradient():
+    """grad_abs sums the terms' magnitudes: it bounds |grad| and equals it for colour rows when
+    the upstream gradient is non-negative."""
+    rng = np.random.default_rng(41)
+    H, W, n = 48, 40, 2
+    p = make_params(rng, 50, n, H, W)
+    g = rng.standard_normal((n, H, W))
+    o = cref.render(p, H, W, 6, grad_img=g)
+    assert np.all(o["grad_abs"] >= np.abs(o["grad"]) * (1 - 1e-12))
+    o = cref.render(p, H, W, 6, grad_img=np.abs(g))
+    np.testing.assert_allclose(o["grad_abs"][5:], o["grad"][5:], rtol=1e-12)
