@@ -250,8 +250,8 @@ IGS_API igs_status igs_render_backward(const float *params, int32_t N, int32_t n
   PhaseTimer timer(kPhaseRasterBwd, s);
   IGS_HIP(launch_fill_f32(gamma, 5 * (int64_t)N, 0.f, s));
   IGS_HIP(launch_fill_f32(grad_params + 5 * (size_t)N, (int64_t)n * N, 0.f, s));
-  IGS_HIP(launch_raster_bwd(ranges, vals, g32a, g64, params, d, image, grad_image, slots, aux,
-                            gamma, grad_params, s));
+  IGS_HIP(launch_raster_bwd(ranges, vals, g32a, g32b, g64, params, d, image, grad_image, slots,
+                            aux, gamma, grad_params, s));
   IGS_HIP(launch_grad_finalize(params, g32a, g32b, gamma, N, grad_params, s));
   return IGS_OK;
 }

@@ -102,7 +102,8 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
 
 // raster_bwd.hip
 hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
-                             const double4 *g64, const float *params, const Dims &d,
+                             const float2 *g32b, const double4 *g64, const float *params,
+                             const Dims &d,
                              const float *image, const float *grad_image, const uint16_t *slots,
                              const float2 *aux, float *gamma, float *grad_params, hipStream_t s);
 hipError_t launch_grad_finalize(const float *params, const float4 *g32a, const float2 *g32b,

@@ -1,24 +1,85 @@
 // Adjoint rasterizer (Image-GS Sec. 3.3: gradients flow through the K retained Gaussians, the
-// selection itself is held fixed).  One workgroup per 16 x 16 tile, one lane per pixel; the
-// top-K slots saved by the forward index into the tile's hit set S_j, which is staged through LDS
-// in batches of 256 together with one LDS accumulator row per gradient component.  Lanes add
-// their per-(pixel, Gaussian) terms into the LDS rows; each batch then issues at most one global
-// atomic per (Gaussian, component).
+// selection itself is held fixed).
 //
-// With alpha_i = w_i / Z, c_r = sum alpha_i c_i and g = dL/dc_r at the pixel:
+// With alpha_i = w_i / Z, c_r = sum alpha_i c_i and g = dL/dc_r at a pixel:
 //   dL/dc_i += alpha_i g
 //   dL/dq_i  = -1/2 alpha_i g.(c_i - c_r)
-// and, with e = (A dx + B dy, C dx + D dy), q = |e|^2, the geometry enters only through the five
+// and, with e = (A dx + B dy, C dx + D dy), q = |e|^2, the geometry enters only through five
 // per-Gaussian sums  G1 = sum gq e1, G2 = sum gq e2, G11 = sum gq e1^2, G22 = sum gq e2^2,
 // G12 = sum gq e1 e2  (gq = dL/dq_i at each pixel).  A per-Gaussian pass turns them into
 //   dL/dmu_x = -2 (A G1 + C G2)          dL/dmu_y = -2 (B G1 + D G2)
 //   dL/dtheta = 2 (u1/u2 - u2/u1) G12    dL/ds_a = -2 u_a G_aa       (u_a = 1/s_a).
+//
+// One workgroup per 16 x 16 tile, one lane per pixel while reading.  The tile's hit set S_j is
+// processed in batches of 256 positions: the (pixel, retained Gaussian) items of a batch are
+// counting-sorted by Gaussian in LDS and split into chunks of at most R items of one Gaussian.  A
+// lane loads its chunk's Gaussian once, accumulates the chunk's 5 + n sums in registers, adds
+// them to the Gaussian's LDS row once (a plain store when the chunk is the Gaussian's only one),
+// and each batch ends with one global atomic per (Gaussian, component) that received anything.
+// The blend weights are recomputed from the saved per-pixel shift and 1/Z with the forward's
+// exact double-precision expression.
 #include "raster_common.hpp"
 
 namespace igs {
 namespace {
 
-template <int KT>
+// Exclusive scan of v over the 256 threads of the block; returns the block total in *total.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kRasterThreads / 64; ++k) {
+    const int t = s_wave[k];
+    off += k < w ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+struct BwdLds {
+  unsigned g, gc, aux, acc, cnt, off, cho, wave, item, total;
+};
+
+// LDS layout of the adjoint kernel for K retained Gaussians per pixel (byte offsets; per-pixel
+// gradient rows are 16-byte aligned for float4 reads).
+template <int NC>
+__host__ __device__ constexpr BwdLds bwd_lds(int K) {
+  constexpr unsigned NCP = (NC + 3) & ~3;
+  BwdLds L{};
+  unsigned o = 0;
+  L.g = o;
+  o += 4 * kRasterThreads * NCP;
+  L.gc = o;
+  o += 4 * kRasterThreads;
+  L.aux = o;
+  o += 8 * kRasterThreads;
+  L.acc = o;
+  o += 4 * kBatch * (5 + NC);
+  L.cnt = o;
+  o += 4 * kBatch;
+  L.off = o;
+  o += 4 * kBatch;
+  L.cho = o;
+  o += 4 * (kBatch + 4);
+  L.wave = o;
+  o += 16;
+  L.item = o;
+  o += 2 * kRasterThreads * (unsigned)K;
+  L.total = (o + 15) & ~15u;
+  return L;
+}
+
+template <int NC>
 __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const double4 *__restrict__ g64,
@@ -26,12 +87,19 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
     int64_t HW, const float *__restrict__ image, const float *__restrict__ grad_image,
     const uint16_t *__restrict__ slots, const float2 *__restrict__ aux,
     float *__restrict__ gamma, float *__restrict__ grad_params) {
+  constexpr int NCP = (NC + 3) & ~3;  // padded per-pixel gradient row
+  constexpr int NACC = 5 + NC;
   extern __shared__ __align__(16) unsigned char smem[];
-  float2 *s_mu = reinterpret_cast<float2 *>(smem);                        // [kBatch]
-  double *s64 = reinterpret_cast<double *>(smem + 8 * kBatch);            // [kBatch][4]
-  float *s_col = reinterpret_cast<float *>(smem + 40 * kBatch);           // [n][kBatch]
-  float *s_g = s_col + (size_t)n * kBatch;                                // [n][256] per pixel
-  float *s_acc = s_g + (size_t)n * kRasterThreads;                        // [5+n][kBatch]
+  const BwdLds L = bwd_lds<NC>(K);
+  float *s_g = reinterpret_cast<float *>(smem + L.g);              // [256 px][NCP]
+  float *s_gc = reinterpret_cast<float *>(smem + L.gc);            // [256 px] g . c_r
+  float2 *s_aux = reinterpret_cast<float2 *>(smem + L.aux);        // [256 px] shift, 1/Z
+  float *s_acc = reinterpret_cast<float *>(smem + L.acc);          // [kBatch][NACC]
+  int *s_cnt = reinterpret_cast<int *>(smem + L.cnt);              // [kBatch]
+  int *s_off = reinterpret_cast<int *>(smem + L.off);              // [kBatch]
+  int *s_cho = reinterpret_cast<int *>(smem + L.cho);              // [kBatch + 1]
+  int *s_wave = reinterpret_cast<int *>(smem + L.wave);            // [4]
+  uint16_t *s_item = reinterpret_cast<uint16_t *>(smem + L.item);  // [256 * K] px | j << 8
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, T);
@@ -39,76 +107,148 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
   const int cnt = rg.y - rg.x;
   if (cnt <= 0) return;  // uniform over the workgroup
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int px = tx * kTile + (tid & (kTile - 1)), py = ty * kTile + tid / kTile;
+  const int x0 = tx * kTile, y0 = ty * kTile;
+  const int px = x0 + (tid & (kTile - 1)), py = y0 + tid / kTile;
   const bool inside = px < W && py < H;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const int64_t pix = inside ? (int64_t)py * W + px : 0;
 
-  int sl[KT];
+  // per-pixel upstream gradient, g . c_r, and the forward's blend normalization
+  {
+    float gc = 0.f;
 #pragma unroll
-  for (int k = 0; k < KT; ++k)
-    sl[k] = (inside && k < K) ? (int)slots[(int64_t)k * HW + pix] : (int)kEmptySlot;
-  const float2 ax = inside ? aux[pix] : make_float2(0.f, 0.f);
-  float gc = 0.f;  // g . c_r
-  for (int ch = 0; ch < n; ++ch) {
-    const float g = inside ? grad_image[(int64_t)ch * HW + pix] : 0.f;
-    const float c = inside ? image[(int64_t)ch * HW + pix] : 0.f;
-    s_g[ch * kRasterThreads + tid] = g;
-    gc = fmaf(g, c, gc);
+    for (int ch = 0; ch < NCP; ++ch) {
+      float g = 0.f;
+      if (ch < n && inside) {
+        g = grad_image[(int64_t)ch * HW + pix];
+        gc = fmaf(g, image[(int64_t)ch * HW + pix], gc);
+      }
+      s_g[tid * NCP + ch] = g;
+    }
+    s_gc[tid] = gc;
+    s_aux[tid] = inside ? aux[pix] : make_float2(0.f, 0.f);
   }
 
   for (int base = 0; base < cnt; base += kBatch) {
     const int nb = min(kBatch, cnt - base);
-    __syncthreads();
-    if (tid < nb) {
-      const uint32_t gid = vals[rg.x + base + tid];
-      const float4 a = g32a[gid];
-      s_mu[tid] = make_float2(a.x, a.y);
-      const double4 c = g64[gid];
-      s64[4 * tid + 0] = c.x;
-      s64[4 * tid + 1] = c.y;
-      s64[4 * tid + 2] = c.z;
-      s64[4 * tid + 3] = c.w;
-      for (int ch = 0; ch < n; ++ch) s_col[ch * kBatch + tid] = params[(size_t)(5 + ch) * N + gid];
-    }
-    for (int r = 0; r < 5 + n; ++r) s_acc[r * kBatch + tid] = 0.f;
-    __syncthreads();
-    if (inside) {
+    __syncthreads();  // previous batch fully consumed
+    s_cnt[tid] = 0;
 #pragma unroll
-      for (int k = 0; k < KT; ++k) {
-        const int j = sl[k] - base;
-        if (sl[k] != (int)kEmptySlot && j >= 0 && j < nb) {
-          double e1, e2;
-          const double q = quad_form64(fx, fy, s_mu[j].x, s_mu[j].y, s64[4 * j + 0],
-                                       s64[4 * j + 1], s64[4 * j + 2], s64[4 * j + 3], e1, e2);
-          const float alpha = blend_weight(q, ax.x) * ax.y;
-          float dot = -gc;
-          for (int ch = 0; ch < n; ++ch)
-            dot = fmaf(s_g[ch * kRasterThreads + tid], s_col[ch * kBatch + j], dot);
-          const float gq = -0.5f * alpha * dot;
-          const float f1 = (float)e1, f2 = (float)e2;
-          const float g1 = gq * f1, g2 = gq * f2;
-          atomicAdd(&s_acc[0 * kBatch + j], g1);
-          atomicAdd(&s_acc[1 * kBatch + j], g2);
-          atomicAdd(&s_acc[2 * kBatch + j], g1 * f1);
-          atomicAdd(&s_acc[3 * kBatch + j], g2 * f2);
-          atomicAdd(&s_acc[4 * kBatch + j], g1 * f2);
-          for (int ch = 0; ch < n; ++ch)
-            atomicAdd(&s_acc[(5 + ch) * kBatch + j], alpha * s_g[ch * kRasterThreads + tid]);
+    for (int r = 0; r < NACC; ++r) s_acc[tid * NACC + r] = 0.f;
+    __syncthreads();
+
+    // 1a: items per Gaussian of this batch
+    if (inside)
+      for (int k = 0; k < K; ++k) {
+        const int j = (int)slots[(int64_t)k * HW + pix] - base;
+        if (j >= 0 && j < nb) atomicAdd(&s_cnt[j], 1);
+      }
+    __syncthreads();
+    const int my_cnt = s_cnt[tid];  // tid indexes a Gaussian of the batch here
+    int total_items;
+    const int my_off = block_exclusive_scan(my_cnt, s_wave, &total_items);
+    // chunk length: about one chunk per lane
+    const int R = max(1, (total_items + kRasterThreads - 1) / kRasterThreads + 2);
+    const int my_ch = (my_cnt + R - 1) / R;
+    int total_chunks;
+    const int my_cho = block_exclusive_scan(my_ch, s_wave, &total_chunks);
+    s_off[tid] = my_off;
+    s_cho[tid] = my_cho;
+    s_cnt[tid] = my_off;  // becomes the fill cursor
+    if (tid == 0) s_cho[kBatch] = total_chunks;  // s_cho[j + 1] - s_cho[j] = chunks of j
+    __syncthreads();
+
+    // 1b: group the items by Gaussian
+    if (inside)
+      for (int k = 0; k < K; ++k) {
+        const int j = (int)slots[(int64_t)k * HW + pix] - base;
+        if (j >= 0 && j < nb) s_item[atomicAdd(&s_cnt[j], 1)] = (uint16_t)(tid | (j << 8));
+      }
+    __syncthreads();
+
+    // 2: chunks of one Gaussian each, accumulated in registers
+    for (int c = tid; c < total_chunks; c += kRasterThreads) {
+      // the Gaussian owning chunk c: the last j with s_cho[j] <= c
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_cho[mid] <= c) lo = mid;
+        else hi = mid - 1;
+      }
+      const int j = lo;
+      const int first = s_off[j] + (c - s_cho[j]) * R;
+      const int run_end = j + 1 < kBatch ? s_off[j + 1] : total_items;
+      const int end = min(first + R, run_end);
+      const uint32_t gid = vals[rg.x + base + j];
+      const float4 a = g32a[gid];
+      const double4 c64 = g64[gid];
+      float cj[NC];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) cj[ch] = ch < n ? params[(size_t)(5 + ch) * N + gid] : 0.f;
+      float G1 = 0.f, G2 = 0.f, G11 = 0.f, G22 = 0.f, G12 = 0.f;
+      float gcol[NC];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) gcol[ch] = 0.f;
+      for (int it = first; it < end; ++it) {
+        const int p = s_item[it] & 0xFF;
+        const float fx = (float)(x0 + (p & (kTile - 1))) + 0.5f;
+        const float fy = (float)(y0 + p / kTile) + 0.5f;
+        double d1, d2;
+        const double q = quad_form64(fx, fy, a.x, a.y, c64.x, c64.y, c64.z, c64.w, d1, d2);
+        const float2 ax = s_aux[p];
+        const float alpha = blend_weight(q, ax.x) * ax.y;
+        const float e1 = (float)d1, e2 = (float)d2;
+        float gv[NCP];
+#pragma unroll
+        for (int ch = 0; ch < NCP; ch += 4) {
+          const float4 v = *reinterpret_cast<const float4 *>(&s_g[p * NCP + ch]);
+          gv[ch] = v.x;
+          if (ch + 1 < NCP) gv[ch + 1] = v.y;
+          if (ch + 2 < NCP) gv[ch + 2] = v.z;
+          if (ch + 3 < NCP) gv[ch + 3] = v.w;
         }
+        float dot = -s_gc[p];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) dot = fmaf(gv[ch], cj[ch], dot);
+        const float gq = -0.5f * alpha * dot;
+        const float g1 = gq * e1, g2 = gq * e2;
+        G1 += g1;
+        G2 += g2;
+        G11 = fmaf(g1, e1, G11);
+        G22 = fmaf(g2, e2, G22);
+        G12 = fmaf(g1, e2, G12);
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) gcol[ch] = fmaf(alpha, gv[ch], gcol[ch]);
+      }
+      float *row = &s_acc[j * NACC];
+      if (s_cho[j + 1] - s_cho[j] == 1) {  // this lane holds the Gaussian's only chunk
+        row[0] = G1;
+        row[1] = G2;
+        row[2] = G11;
+        row[3] = G22;
+        row[4] = G12;
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) row[5 + ch] = gcol[ch];
+      } else {
+        atomicAdd(&row[0], G1);
+        atomicAdd(&row[1], G2);
+        atomicAdd(&row[2], G11);
+        atomicAdd(&row[3], G22);
+        atomicAdd(&row[4], G12);
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) atomicAdd(&row[5 + ch], gcol[ch]);
       }
     }
     __syncthreads();
-    if (tid < nb) {
+
+    // 3: one global add per (Gaussian, component) of this batch
+    if (tid < nb && my_cnt > 0) {
       const uint32_t gid = vals[rg.x + base + tid];
-      for (int r = 0; r < 5; ++r) {
-        const float v = s_acc[r * kBatch + tid];
-        if (v != 0.f) unsafeAtomicAdd(&gamma[(size_t)r * N + gid], v);
-      }
-      for (int ch = 0; ch < n; ++ch) {
-        const float v = s_acc[(5 + ch) * kBatch + tid];
-        if (v != 0.f) unsafeAtomicAdd(&grad_params[(size_t)(5 + ch) * N + gid], v);
-      }
+      const float *row = &s_acc[tid * NACC];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) unsafeAtomicAdd(&gamma[(size_t)r * N + gid], row[r]);
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch)
+        if (ch < n) unsafeAtomicAdd(&grad_params[(size_t)(5 + ch) * N + gid], row[5 + ch]);
     }
   }
 }
@@ -132,29 +272,43 @@ __global__ __launch_bounds__(256) void grad_finalize_kernel(const float *__restr
   grad[4 * (size_t)N + i] = -2.0f * u2 * G22;
 }
 
+template <int NC>
+hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
+                         const float2 *g32b, const double4 *g64, const float *params,
+                         const Dims &d, const float *image, const float *grad_image,
+                         const uint16_t *slots, const float2 *aux, float *gamma,
+                         float *grad_params, hipStream_t s) {
+  const size_t lds = bwd_lds<NC>(d.K).total;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)raster_bwd_kernel<NC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  raster_bwd_kernel<NC><<<d.T, kRasterThreads, lds, s>>>(ranges, vals, g32a, g64, params, d.N,
+                                                          d.n, d.H, d.W, d.K, d.tiles_x, d.T,
+                                                          d.HW, image, grad_image, slots, aux,
+                                                          gamma, grad_params);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
-                             const double4 *g64, const float *params, const Dims &d,
-                             const float *image, const float *grad_image, const uint16_t *slots,
-                             const float2 *aux, float *gamma, float *grad_params, hipStream_t s) {
-  const size_t lds = 40 * kBatch + (size_t)d.n * kBatch * 4 + (size_t)d.n * kRasterThreads * 4 +
-                     (size_t)(5 + d.n) * kBatch * 4;
-  const int kt = pick_kt(d.K);
-#define IGS_LAUNCH_BWD(KTV)                                                                     \
-  if (kt == KTV) {                                                                              \
-    if (lds > 65536) {                                                                          \
-      hipError_t e = hipFuncSetAttribute((const void *)raster_bwd_kernel<KTV>,                  \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-      if (e != hipSuccess) return e;                                                            \
-    }                                                                                           \
-    raster_bwd_kernel<KTV><<<d.T, kRasterThreads, lds, s>>>(                                    \
-        ranges, vals, g32a, g64, params, d.N, d.n, d.H, d.W, d.K, d.tiles_x, d.T, d.HW, image,  \
-        grad_image, slots, aux, gamma, grad_params);                                            \
-    return hipGetLastError();                                                                   \
-  }
-  IGS_FOR_EACH_KT(IGS_LAUNCH_BWD)
-#undef IGS_LAUNCH_BWD
+                             const float2 *g32b, const double4 *g64, const float *params,
+                             const Dims &d, const float *image, const float *grad_image,
+                             const uint16_t *slots, const float2 *aux, float *gamma,
+                             float *grad_params, hipStream_t s) {
+#define IGS_BWD_NC(NCV)                                                                        \
+  if (d.n <= NCV)                                                                              \
+    return launch_bwd_nc<NCV>(ranges, vals, g32a, g32b, g64, params, d, image, grad_image,     \
+                              slots, aux, gamma, grad_params, s);
+  IGS_BWD_NC(1)
+  IGS_BWD_NC(3)
+  IGS_BWD_NC(4)
+  IGS_BWD_NC(9)
+  IGS_BWD_NC(16)
+  IGS_BWD_NC(32)
+#undef IGS_BWD_NC
   return hipErrorInvalidValue;
 }
 
