@@ -213,6 +213,7 @@ IGS_API igs_status igs_render(const float *params, int32_t N, int32_t n, int32_t
                            d.passes, d.digit_bits, hist, hist_off,
                            static_cast<uint32_t *>(scan_tmp), s));
     IGS_HIP(launch_tile_ranges(keys, status, pair_capacity, ranges, s));
+    IGS_HIP(launch_tile_stats(ranges, d.T, d.tiles_x, H, W, K, status, s));
   }
   PhaseTimer timer(kPhaseRasterFwd, s);
   IGS_HIP(launch_raster_fwd(ranges, vals, g32a, g32b, g64, params, d, image, slots, aux, status,

@@ -152,6 +152,52 @@ __global__ __launch_bounds__(kThreads) void tile_ranges_kernel(const uint32_t *_
   }
 }
 
+// Per-render statistics from the tile ranges, in one workgroup with a fixed reduction order:
+// the largest |S_j|, whether any exceeds the 16-bit slot range, E_fwd = sum_j |S_j| times the
+// tile's pixel count and E_bwd = sum_j min(K, |S_j|) times the tile's pixel count.
+constexpr int kStatThreads = 1024;
+__global__ __launch_bounds__(kStatThreads) void tile_stats_kernel(const int2 *__restrict__ ranges,
+                                                                  int T, int tiles_x, int H, int W,
+                                                                  int K,
+                                                                  int64_t *__restrict__ status) {
+  __shared__ long long s_max[kStatThreads / 64], s_ef[kStatThreads / 64], s_eb[kStatThreads / 64];
+  long long mx = 0, ef = 0, eb = 0;
+  for (int t = threadIdx.x; t < T; t += kStatThreads) {
+    const int2 r = ranges[t];
+    const long long c = r.y - r.x;
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    const long long npx = (long long)min(W - tx * kTile, kTile) * min(H - ty * kTile, kTile);
+    mx = c > mx ? c : mx;
+    ef += c * npx;
+    eb += (c < K ? c : K) * npx;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const long long omx = __shfl_down(mx, d, 64);
+    mx = omx > mx ? omx : mx;
+    ef += __shfl_down(ef, d, 64);
+    eb += __shfl_down(eb, d, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_max[w] = mx;
+    s_ef[w] = ef;
+    s_eb[w] = eb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kStatThreads / 64; ++k) {
+      mx = s_max[k] > mx ? s_max[k] : mx;
+      ef += s_ef[k];
+      eb += s_eb[k];
+    }
+    status[kStatMaxList] = mx;
+    status[kStatSlotOverflow] = mx > 0xFFFF ? 1 : 0;
+    status[kStatEvalsFwd] = ef;
+    status[kStatEvalsBwd] = eb;
+  }
+}
+
 inline int grid_for(int64_t count, int threads, int max_blocks = 65536) {
   int64_t b = (count + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -205,6 +251,12 @@ hipError_t launch_emit(const float *params, int N, int H, int W, int tiles_x, in
 hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
                               int2 *ranges, hipStream_t s) {
   tile_ranges_kernel<<<grid_for(cap, kThreads, 8192), kThreads, 0, s>>>(keys, status, cap, ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_stats(const int2 *ranges, int T, int tiles_x, int H, int W, int K,
+                             int64_t *status, hipStream_t s) {
+  tile_stats_kernel<<<1, kStatThreads, 0, s>>>(ranges, T, tiles_x, H, W, K, status);
   return hipGetLastError();
 }
 

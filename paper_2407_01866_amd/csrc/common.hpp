@@ -78,6 +78,8 @@ hipError_t launch_emit(const float *params, int N, int H, int W, int tiles_x, in
                        uint32_t *keys, uint32_t *vals, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
                               int2 *ranges, hipStream_t s);
+hipError_t launch_tile_stats(const int2 *ranges, int T, int tiles_x, int H, int W, int K,
+                             int64_t *status, hipStream_t s);
 
 // scan.hip: exclusive scans; temp must hold scan_temp_elems(n) elements of the output type.
 hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *temp,

@@ -104,8 +104,9 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, T);
   const int2 rg = ranges[tile];
-  const int cnt = rg.y - rg.x;
-  if (cnt <= 0) return;  // uniform over the workgroup
+  const int start = __builtin_amdgcn_readfirstlane(rg.x);  // uniform over the workgroup
+  const int cnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
+  if (cnt <= 0) return;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int x0 = tx * kTile, y0 = ty * kTile;
   const int px = x0 + (tid & (kTile - 1)), py = y0 + tid / kTile;
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
       const int first = s_off[j] + (c - s_cho[j]) * R;
       const int run_end = j + 1 < kBatch ? s_off[j + 1] : total_items;
       const int end = min(first + R, run_end);
-      const uint32_t gid = vals[rg.x + base + j];
+      const uint32_t gid = vals[start + base + j];
       const float4 a = g32a[gid];
       const double4 c64 = g64[gid];
       float cj[NC];
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
 
     // 3: one global add per (Gaussian, component) of this batch
     if (tid < nb && my_cnt > 0) {
-      const uint32_t gid = vals[rg.x + base + tid];
+      const uint32_t gid = vals[start + base + tid];
       const float *row = &s_acc[tid * NACC];
 #pragma unroll
       for (int r = 0; r < 5; ++r) unsafeAtomicAdd(&gamma[(size_t)r * N + gid], row[r]);

@@ -1,29 +1,42 @@
 // Forward rasterizer (Image-GS Sec. 3.2, Eq. 5): one workgroup per 16 x 16 tile, one lane per
 // pixel.  The tile's hit set S_j is staged through LDS in batches of 256 Gaussians; every lane
 // ranks every member by its float32 Mahalanobis form q and keeps a register-resident sorted top-K
-// of (q, slot), slot being the member's position in S_j (ties keep the earlier slot, i.e. the
-// lower Gaussian index).  The K winners are then re-evaluated in double so that the normalized
-// blend weights exp(-(q_i - q_min)/2) carry no float32 cancellation error.
+// of (q, slot), slot being the member's position in S_j, so that equal q rank the lower Gaussian
+// index first.  The K winners are then re-evaluated in double so that the normalized blend weights
+// exp(-(q_i - q_min)/2) carry no float32 cancellation error.
+//
+// Ranking key: the pair (q, slot) packed as the bit pattern of a positive double, high word =
+// float bits of q plus one exponent step (keeps the double normal when q = 0), low word = slot.
+// For non-negative floats the bit pattern orders like the value, and so does a positive double's,
+// so comparing the doubles compares (q, slot) lexicographically; every position of the sorted
+// insertion is then one v_max_f64 and one v_min_f64 (full rate on this GPU), and the result does not
+// depend on the order in which candidates arrive.  This file is built with -fno-honor-nans so the
+// min/max are not wrapped in NaN-quieting instructions; q is clamped below 1e38 before packing so a
+// non-finite value can only rank last.
 #include "raster_common.hpp"
 
 namespace igs {
 namespace {
 
-// Insert (q, s) into the ascending list; once a position takes the new entry every later
-// position shifts down by one (the carry), so equal keys keep their arrival order.
+constexpr uint32_t kKeyBias = 0x00800000u;
+constexpr float kQMax = 1e38f;
+
+__device__ __forceinline__ double rank_key(float q, int slot) {
+  return __hiloint2double((int)(__float_as_uint(fminf(q, kQMax)) + kKeyBias), slot);
+}
+__device__ __forceinline__ int key_slot(double k) { return __double2loint(k); }
+__device__ __forceinline__ bool key_valid(double k) {
+  return (uint32_t)__double2hiint(k) < 0x7F000000u;  // not the +inf sentinel
+}
+
+// Sorted insertion of a key (ascending, unique keys): a compare-exchange down the list.
 template <int KT>
-__device__ __forceinline__ void topk_insert(float (&tq)[KT], int (&ts)[KT], float q, int s) {
-  bool carry = false;
+__device__ __forceinline__ void topk_insert(double (&tk)[KT], double key) {
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    const bool take = carry || (q < tq[k]);
-    const float oq = tq[k];
-    const int os = ts[k];
-    tq[k] = take ? q : oq;
-    ts[k] = take ? s : os;
-    q = take ? oq : q;
-    s = take ? os : s;
-    carry = take;
+    const double hi = __builtin_fmax(key, tk[k]);
+    tk[k] = __builtin_fmin(key, tk[k]);
+    key = hi;
   }
 }
 
@@ -33,7 +46,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
     const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n, int H,
     int W, int K, int tiles_x, int T, int64_t HW, float *__restrict__ image,
-    uint16_t *__restrict__ slots, float2 *__restrict__ aux, int64_t *__restrict__ status) {
+    uint16_t *__restrict__ slots, float2 *__restrict__ aux) {
   extern __shared__ __align__(16) unsigned char smem[];
   float4 *s_geo = reinterpret_cast<float4 *>(smem);                    // mu_x, mu_y, A, B
   float2 *s_cd = reinterpret_cast<float2 *>(smem + 16 * kBatch);       // C, D
@@ -47,33 +60,20 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
   const bool inside = px < W && py < H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   const int2 rg = ranges[tile];
-  const int cnt = rg.y - rg.x;
+  // uniform over the workgroup; readfirstlane keeps the loop bounds in scalar registers
+  const int start = __builtin_amdgcn_readfirstlane(rg.x);
+  const int cnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
   const bool single = cnt <= kBatch;  // whole S_j stays resident for the blend
 
-  if (tid == 0 && cnt > 0) {
-    atomicMax(reinterpret_cast<unsigned long long *>(&status[kStatMaxList]),
-              (unsigned long long)cnt);
-    if (cnt > 0xFFFF) status[kStatSlotOverflow] = 1;
-    const long long npx = (long long)(min(W - tx * kTile, kTile) * min(H - ty * kTile, kTile));
-    atomicAdd(reinterpret_cast<unsigned long long *>(&status[kStatEvalsFwd]),
-              (unsigned long long)(npx * cnt));
-    atomicAdd(reinterpret_cast<unsigned long long *>(&status[kStatEvalsBwd]),
-              (unsigned long long)(npx * min(K, cnt)));
-  }
-
-  float tq[KT];
-  int ts[KT];
+  double tk[KT];
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    tq[k] = INFINITY;
-    ts[k] = -1;
-  }
+  for (int k = 0; k < KT; ++k) tk[k] = __longlong_as_double(0x7FF0000000000000ll);  // +inf
 
   for (int base = 0; base < cnt; base += kBatch) {
     const int nb = min(kBatch, cnt - base);
     __syncthreads();
     if (tid < nb) {
-      const uint32_t gid = vals[rg.x + base + tid];
+      const uint32_t gid = vals[start + base + tid];
       s_geo[tid] = g32a[gid];
       s_cd[tid] = g32b[gid];
       if (single) {
@@ -86,20 +86,40 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
       }
     }
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
+    int j = 0;
+    // four candidates per step: their loads and quadratic forms overlap before the insertions
+    for (; j + 4 <= nb; j += 4) {
+      double key[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 a = s_geo[j + u];
+        const float2 b = s_cd[j + u];
+        const float dx = fx - a.x, dy = fy - a.y;
+        const float e1 = fmaf(a.z, dx, a.w * dy);
+        const float e2 = fmaf(b.x, dx, b.y * dy);
+        key[u] = rank_key(fmaf(e1, e1, e2 * e2), base + j + u);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (key[u] < tk[KT - 1]) topk_insert<KT>(tk, key[u]);
+    }
+    for (; j < nb; ++j) {
       const float4 a = s_geo[j];
       const float2 b = s_cd[j];
       const float dx = fx - a.x, dy = fy - a.y;
       const float e1 = fmaf(a.z, dx, a.w * dy);
       const float e2 = fmaf(b.x, dx, b.y * dy);
-      const float q = fmaf(e1, e1, e2 * e2);
-      if (q < tq[KT - 1]) topk_insert<KT>(tq, ts, q, base + j);
+      const double key = rank_key(fmaf(e1, e1, e2 * e2), base + j);
+      if (key < tk[KT - 1]) topk_insert<KT>(tk, key);
     }
   }
 
   if (!inside) return;
   const int64_t pix = (int64_t)py * W + px;
   const int keff = min(K, cnt);
+  int ts[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) ts[k] = key_valid(tk[k]) ? key_slot(tk[k]) : -1;
   float w[KT];
   int src[KT];
   float Z = 0.f, shift = 0.f;
@@ -120,7 +140,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
         my = s_geo[slot].y;
         src[k] = slot;
       } else {
-        const uint32_t gid = vals[rg.x + slot];
+        const uint32_t gid = vals[start + slot];
         const double4 c = g64[gid];
         const float4 a = g32a[gid];
         A = c.x;
@@ -170,7 +190,7 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
     raster_fwd_kernel<KTV><<<d.T, kRasterThreads, lds, s>>>(ranges, vals, g32a, g32b, g64,     \
                                                             params, d.N, d.n, d.H, d.W, d.K,   \
                                                             d.tiles_x, d.T, d.HW, image,       \
-                                                            slots, aux, status);               \
+                                                            slots, aux);                       \
     return hipGetLastError();                                                                  \
   }
   IGS_FOR_EACH_KT(IGS_LAUNCH_FWD)
