@@ -180,6 +180,78 @@ igs_status igs_adam_step(float *fit_params, float *render_params, const float *g
 igs_status igs_fit_to_render(const float *fit_params, float *render_params, int32_t N, int32_t n,
                              int32_t H, int32_t W, void *stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Batches: many images of uneven size and Gaussian count rendered, differentiated and optimized
+ * by one launch per phase.  The images are concatenated: the parameter array is [5+n][Ntot]
+ * (image b's Gaussians are columns gauss_off .. gauss_off+N-1), images/targets/gradients are
+ * concatenated planar blocks (image b occupies floats n*pix_off .. n*(pix_off+H*W)-1 as
+ * [n][H][W]).  Tiles of all images share one global numbering and one sort; the forward builds a
+ * queue of all tiles ordered by decreasing |S_j| (stable), kept in the saved state, and both
+ * raster passes take their tiles from it, so long tile lists start first.  Images are
+ * independent: a Gaussian only bins into its own image's tiles, so every image renders exactly as
+ * igs_render would render it alone.
+ * Every batched entry point takes the descriptor array twice: on the host (sizes and validation)
+ * and in device memory (read by the kernels; same bytes, caller-owned).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct igs_image_desc {
+  int32_t H, W, N, tiles_x;
+  int32_t tiles_y, tile_off, gauss_off, l1_block_off;
+  int64_t pix_off, reserved;
+} igs_image_desc;
+
+/*
+ * Fill B descriptors for images H[b] x W[b] with N[b] Gaussians and n channels, in order.
+ * totals_out: [0] total Gaussians, [1] total tiles, [2] total pixels, [3] loss blocks.
+ * Errors: IGS_ERR_INVALID_ARG (sizes out of range, totals beyond 2^31 Gaussians or 2^24 tiles).
+ */
+igs_status igs_batch_describe(int32_t B, int32_t n, const int32_t *H, const int32_t *W,
+                              const int32_t *N, igs_image_desc *descs_out, int64_t totals_out[4]);
+
+/* As igs_render_buffer_sizes / igs_saved_offsets for a batch (out[6]: the tile queue, int32[T]). */
+igs_status igs_batch_buffer_sizes(const igs_image_desc *descs, int32_t B, int32_t n, int32_t K,
+                                  int64_t pair_capacity, size_t *ws_bytes, size_t *saved_bytes);
+igs_status igs_batch_saved_offsets(const igs_image_desc *descs, int32_t B, int32_t n, int32_t K,
+                                   int64_t pair_capacity, int64_t out[7]);
+
+/* igs_render for a batch (Sec. 3.2, Eq. 5 per image); pair_capacity bounds the pairs of all
+   images together.  Errors: as igs_render. */
+igs_status igs_render_batched(const float *params, const igs_image_desc *descs_host,
+                              const igs_image_desc *descs_dev, int32_t B, int32_t n, int32_t K,
+                              int64_t pair_capacity, float *images, void *saved,
+                              size_t saved_bytes, void *workspace, size_t ws_bytes, void *stream);
+
+/* igs_render_backward for a batch (Sec. 3.3).  grad_params [5+n][Ntot] is overwritten. */
+igs_status igs_render_backward_batched(const float *params, const igs_image_desc *descs_host,
+                                       const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                       int32_t K, int64_t pair_capacity, const float *images,
+                                       const float *grad_images, const void *saved,
+                                       size_t saved_bytes, float *grad_params, void *workspace,
+                                       size_t ws_bytes, void *stream);
+
+/* L1 term per image (each normalized by its own n*H*W); loss_out is device double[B][2]
+   (mean |d|, mean d^2 per image).  Deterministic.  Errors: as igs_l1_loss_grad. */
+igs_status igs_l1_batched_workspace_size(const igs_image_desc *descs, int32_t B, int32_t n,
+                                         size_t *ws_bytes);
+igs_status igs_l1_loss_grad_batched(const float *images, const float *targets,
+                                    const igs_image_desc *descs_host,
+                                    const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                    float *grad_images, double *loss_out, void *workspace,
+                                    size_t ws_bytes, void *stream);
+
+/* igs_adam_step for a batch: each Gaussian's mean is normalized by its own image's W and H and
+   its inverse scales are clipped to [1/max(H,W), inv_scale_hi] of its image. */
+igs_status igs_adam_step_batched(float *fit_params, float *render_params,
+                                 const float *grad_render, float *m, float *v, int32_t *step,
+                                 const int64_t *skip_flag, const igs_image_desc *descs_host,
+                                 const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                 float lr_mu, float lr_theta, float lr_inv_scale, float lr_color,
+                                 float beta1, float beta2, float eps, float inv_scale_hi,
+                                 void *stream);
+igs_status igs_fit_to_render_batched(const float *fit_params, float *render_params,
+                                     const igs_image_desc *descs_host,
+                                     const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                     void *stream);
+
 /*
  * Kernel timers (measurement aid, off by default).  While enabled, every entry point records a
  * pair of HIP events on its stream around each of its phases; igs_timing_read waits for the

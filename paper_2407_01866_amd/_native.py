@@ -29,9 +29,21 @@ STAT_PAIRS, STAT_OVERFLOW, STAT_MAX_LIST, STAT_SLOT_OVERFLOW, STAT_EVALS_FWD, ST
 EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "igs_saved_offsets",
             "igs_render",
             "igs_render_backward", "igs_l1_workspace_size", "igs_l1_loss_grad", "igs_adam_step",
-            "igs_fit_to_render", "igs_timing_enable", "igs_timing_read")
+            "igs_fit_to_render", "igs_timing_enable", "igs_timing_read", "igs_batch_describe",
+            "igs_batch_buffer_sizes", "igs_batch_saved_offsets", "igs_render_batched",
+            "igs_render_backward_batched", "igs_l1_batched_workspace_size",
+            "igs_l1_loss_grad_batched", "igs_adam_step_batched", "igs_fit_to_render_batched")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam")
+
+
+class ImageDesc(ctypes.Structure):
+    """Mirror of igs_image_desc (include/imagegs.h)."""
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
+                ("tile_off", ctypes.c_int32), ("gauss_off", ctypes.c_int32),
+                ("l1_block_off", ctypes.c_int32), ("pix_off", ctypes.c_int64),
+                ("reserved", ctypes.c_int64)]
 
 
 class IGSError(RuntimeError):
@@ -76,6 +88,28 @@ def lib() -> ctypes.CDLL:
     L.igs_adam_step.restype = i32
     L.igs_fit_to_render.argtypes = [vp, vp, i32, i32, i32, i32, vp]
     L.igs_fit_to_render.restype = i32
+    dp = ctypes.POINTER(ImageDesc)
+    i32p = ctypes.POINTER(i32)
+    L.igs_batch_describe.argtypes = [i32, i32, i32p, i32p, i32p, dp, ctypes.POINTER(i64)]
+    L.igs_batch_describe.restype = i32
+    L.igs_batch_buffer_sizes.argtypes = [dp, i32, i32, i32, i64, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.igs_batch_buffer_sizes.restype = i32
+    L.igs_batch_saved_offsets.argtypes = [dp, i32, i32, i32, i64, ctypes.POINTER(i64)]
+    L.igs_batch_saved_offsets.restype = i32
+    L.igs_render_batched.argtypes = [vp, dp, vp, i32, i32, i32, i64, vp, vp, sz, vp, sz, vp]
+    L.igs_render_batched.restype = i32
+    L.igs_render_backward_batched.argtypes = [vp, dp, vp, i32, i32, i32, i64, vp, vp, vp, sz, vp,
+                                              vp, sz, vp]
+    L.igs_render_backward_batched.restype = i32
+    L.igs_l1_batched_workspace_size.argtypes = [dp, i32, i32, ctypes.POINTER(sz)]
+    L.igs_l1_batched_workspace_size.restype = i32
+    L.igs_l1_loss_grad_batched.argtypes = [vp, vp, dp, vp, i32, i32, vp, vp, vp, sz, vp]
+    L.igs_l1_loss_grad_batched.restype = i32
+    L.igs_adam_step_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp, dp, vp, i32, i32, f32, f32, f32,
+                                        f32, f32, f32, f32, f32, vp]
+    L.igs_adam_step_batched.restype = i32
+    L.igs_fit_to_render_batched.argtypes = [vp, vp, dp, vp, i32, i32, vp]
+    L.igs_fit_to_render_batched.restype = i32
     L.igs_timing_enable.argtypes = [i32]
     L.igs_timing_enable.restype = i32
     L.igs_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
@@ -211,3 +245,87 @@ def igs_timing_read(reset: bool = True) -> dict:
     calls = (ctypes.c_int64 * len(PHASES))()
     _check("igs_timing_read", lib().igs_timing_read(ms, calls, 1 if reset else 0))
     return {p: (ms[i], calls[i]) for i, p in enumerate(PHASES)}
+
+
+# ------------------------------------------------------------------------------------ batches
+
+
+def igs_batch_describe(H, W, N, n: int):
+    """Host descriptors (ctypes array of ImageDesc) and totals (Ntot, T, pixels, loss blocks)."""
+    B = len(H)
+    arr = (ImageDesc * B)()
+    tot = (ctypes.c_int64 * 4)()
+    h = (ctypes.c_int32 * B)(*H)
+    w = (ctypes.c_int32 * B)(*W)
+    g = (ctypes.c_int32 * B)(*N)
+    _check("igs_batch_describe", lib().igs_batch_describe(B, n, h, w, g, arr, tot))
+    return arr, tuple(tot)
+
+
+def descs_to_device(descs, device) -> torch.Tensor:
+    """Copy host descriptors into a device byte tensor (the kernels' copy)."""
+    raw = bytes(descs)
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+
+
+def igs_batch_buffer_sizes(descs, n, K, pair_capacity) -> Tuple[int, int]:
+    ws, sv = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _check("igs_batch_buffer_sizes", lib().igs_batch_buffer_sizes(
+        descs, len(descs), n, K, pair_capacity, ctypes.byref(ws), ctypes.byref(sv)))
+    return ws.value, sv.value
+
+
+def igs_batch_saved_offsets(descs, n, K, pair_capacity) -> dict:
+    out = (ctypes.c_int64 * 7)()
+    _check("igs_batch_saved_offsets",
+           lib().igs_batch_saved_offsets(descs, len(descs), n, K, pair_capacity, out))
+    return dict(zip(("status", "ranges", "vals", "slots", "aux", "total", "order"), list(out)))
+
+
+def igs_render_batched(params, descs, d_descs, n, K, pair_capacity, images, saved, saved_bytes,
+                       workspace, ws_bytes, stream=None) -> None:
+    _check("igs_render_batched", lib().igs_render_batched(
+        _f32(params, "params") if params.numel() else None, descs, _ptr(d_descs), len(descs), n,
+        K, pair_capacity, _f32(images, "images"), _ptr(saved), saved_bytes, _ptr(workspace),
+        ws_bytes, _stream(stream)))
+
+
+def igs_render_backward_batched(params, descs, d_descs, n, K, pair_capacity, images, grad_images,
+                                saved, saved_bytes, grad_params, workspace, ws_bytes,
+                                stream=None) -> None:
+    _check("igs_render_backward_batched", lib().igs_render_backward_batched(
+        _f32(params, "params") if params.numel() else None, descs, _ptr(d_descs), len(descs), n,
+        K, pair_capacity, _f32(images, "images"), _f32(grad_images, "grad_images"), _ptr(saved),
+        saved_bytes, _f32(grad_params, "grad_params") if grad_params.numel() else None,
+        _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_l1_batched_workspace_size(descs, n) -> int:
+    ws = ctypes.c_size_t(0)
+    _check("igs_l1_batched_workspace_size",
+           lib().igs_l1_batched_workspace_size(descs, len(descs), n, ctypes.byref(ws)))
+    return ws.value
+
+
+def igs_l1_loss_grad_batched(images, targets, descs, d_descs, n, grad_images, loss_out, workspace,
+                             ws_bytes, stream=None) -> None:
+    _check("igs_l1_loss_grad_batched", lib().igs_l1_loss_grad_batched(
+        _f32(images, "images"), _f32(targets, "targets"), descs, _ptr(d_descs), len(descs), n,
+        _f32(grad_images, "grad_images"), _ptr(loss_out), _ptr(workspace), ws_bytes,
+        _stream(stream)))
+
+
+def igs_adam_step_batched(fit_params, render_params, grad_render, m, v, step, descs, d_descs, n,
+                          lr_mu, lr_theta, lr_inv_scale, lr_color, beta1=0.9, beta2=0.999,
+                          eps=1e-8, inv_scale_hi=4.0, skip_flag=None, stream=None) -> None:
+    _check("igs_adam_step_batched", lib().igs_adam_step_batched(
+        _f32(fit_params, "fit_params"), _f32(render_params, "render_params"),
+        _f32(grad_render, "grad_render"), _f32(m, "m"), _f32(v, "v"), _ptr(step),
+        _ptr(skip_flag), descs, _ptr(d_descs), len(descs), n, lr_mu, lr_theta, lr_inv_scale,
+        lr_color, beta1, beta2, eps, inv_scale_hi, _stream(stream)))
+
+
+def igs_fit_to_render_batched(fit_params, render_params, descs, d_descs, n, stream=None) -> None:
+    _check("igs_fit_to_render_batched", lib().igs_fit_to_render_batched(
+        _f32(fit_params, "fit_params"), _f32(render_params, "render_params"), descs,
+        _ptr(d_descs), len(descs), n, _stream(stream)))

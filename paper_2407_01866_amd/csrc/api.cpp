@@ -37,6 +37,28 @@ Dims make_dims(int N, int n, int H, int W, int K, int64_t cap) {
   return d;
 }
 
+Dims make_batch_dims(const ImageDesc *descs, int B, int n, int K, int64_t cap) {
+  Dims d{};
+  int64_t N = 0, T = 0, HW = 0;
+  for (int b = 0; b < B; ++b) {
+    N += descs[b].N;
+    T += (int64_t)descs[b].tiles_x * descs[b].tiles_y;
+    HW += (int64_t)descs[b].H * descs[b].W;
+  }
+  d.N = (int)N;
+  d.n = n;
+  d.K = K;
+  d.cap = cap;
+  d.T = (int)T;
+  d.HW = HW;
+  d.H = d.W = d.tiles_x = d.tiles_y = 0;
+  d.key_bits = std::max(1, ceil_log2(d.T));
+  d.passes = (d.key_bits + 7) / 8;
+  d.digit_bits = (d.key_bits + d.passes - 1) / d.passes;
+  d.sort_blocks = (std::max<int64_t>(cap, d.T) + kSortTileItems - 1) / kSortTileItems;
+  return d;
+}
+
 SavedLayout saved_layout(const Dims &d) {
   SavedLayout L{};
   size_t o = 0;
@@ -44,6 +66,8 @@ SavedLayout saved_layout(const Dims &d) {
   o = align_up(o + 8 * sizeof(int64_t));
   L.ranges = o;
   o = align_up(o + (size_t)d.T * sizeof(int2));
+  L.order = o;
+  o = align_up(o + (size_t)d.T * sizeof(int32_t));
   L.vals = o;
   o = align_up(o + (size_t)d.cap * sizeof(uint32_t));
   L.g32a = o;
@@ -63,7 +87,8 @@ SavedLayout saved_layout(const Dims &d) {
 WsLayout ws_layout(const Dims &d) {
   WsLayout L{};
   size_t o = 0;
-  const int64_t hist_elems = ((int64_t)1 << d.digit_bits) * d.sort_blocks;
+  // 256 digits: the widest pass of either sort (pairs, or the batch's 16-bit tile queue keys)
+  const int64_t hist_elems = (int64_t)256 * d.sort_blocks;
   L.counts = o;
   o = align_up(o + (size_t)d.N * sizeof(uint32_t));
   L.offsets = o;
@@ -79,10 +104,18 @@ WsLayout ws_layout(const Dims &d) {
   L.hist_off = o;
   o = align_up(o + (size_t)hist_elems * sizeof(uint32_t));
   L.scan_tmp = o;
-  o = align_up(o + std::max(scan_temp_elems(d.N) * sizeof(int64_t),
+  o = align_up(o + std::max(scan_temp_elems(std::max<int64_t>(d.N, 1)) * sizeof(int64_t),
                             scan_temp_elems(hist_elems) * sizeof(uint32_t)));
   L.gamma = o;
   o = align_up(o + (size_t)5 * d.N * sizeof(float));
+  L.order_keys = o;  // largest-first tile queue of a batch: sort scratch
+  o = align_up(o + (size_t)d.T * sizeof(uint32_t));
+  L.order_keys_alt = o;
+  o = align_up(o + (size_t)d.T * sizeof(uint32_t));
+  L.order_vals_alt = o;
+  o = align_up(o + (size_t)d.T * sizeof(uint32_t));
+  L.order_count = o;
+  o = align_up(o + sizeof(int64_t));
   L.l1_tmp = o;
   L.total = o;
   return L;
@@ -162,14 +195,12 @@ IGS_API igs_status igs_saved_offsets(int32_t N, int32_t n, int32_t H, int32_t W,
   return IGS_OK;
 }
 
-IGS_API igs_status igs_render(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
-                              int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
-                              float *image, void *saved, size_t saved_bytes, void *workspace,
-                              size_t ws_bytes, void *stream) {
-  igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
-  if (st != IGS_OK) return st;
-  if ((N > 0 && !params) || !image || !workspace) return IGS_ERR_INVALID_ARG;
-  const Dims d = make_dims(N, n, H, W, K, pair_capacity);
+namespace {
+
+// Forward of one call (single image or batch); saved may be NULL (inference).
+igs_status render_impl(const float *params, const Dims &d, const Images &imgs, bool batched,
+                       float *image, void *saved, size_t saved_bytes, void *workspace,
+                       size_t ws_bytes, hipStream_t s) {
   const SavedLayout SL = saved_layout(d);
   const WsLayout WL = ws_layout(d);
   void *sv = saved;
@@ -180,10 +211,10 @@ IGS_API igs_status igs_render(const float *params, int32_t N, int32_t n, int32_t
     return IGS_ERR_WORKSPACE;
   }
   if (!aligned(sv) || !aligned(workspace)) return IGS_ERR_WORKSPACE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
 
   int64_t *status = at<int64_t>(sv, SL.status);
   int2 *ranges = at<int2>(sv, SL.ranges);
+  int *order = at<int>(sv, SL.order);
   uint32_t *vals = at<uint32_t>(sv, SL.vals);
   float4 *g32a = at<float4>(sv, SL.g32a);
   float2 *g32b = at<float2>(sv, SL.g32b);
@@ -203,22 +234,120 @@ IGS_API igs_status igs_render(const float *params, int32_t N, int32_t n, int32_t
     PhaseTimer timer(kPhaseBinning, s);
     IGS_HIP(launch_status_reset(status, s));
     IGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 2 * (int64_t)d.T, 0u, s));
-  IGS_HIP(launch_preprocess(params, N, H, W, d.tiles_x, d.tiles_y, g32a, g32b, g64, counts, s));
-  IGS_HIP(scan_u32_to_i64(counts, offsets, N, static_cast<int64_t *>(scan_tmp), s));
-  IGS_HIP(launch_pair_total(counts, offsets, N, pair_capacity, status, s));
-  const bool alt = sort_starts_in_alt(d.passes);
-  IGS_HIP(launch_emit(params, N, H, W, d.tiles_x, d.tiles_y, counts, offsets, pair_capacity,
-                      alt ? keys_alt : keys, alt ? vals_alt : vals, s));
-  IGS_HIP(radix_sort_pairs(keys, vals, keys_alt, vals_alt, status, pair_capacity, d.key_bits,
-                           d.passes, d.digit_bits, hist, hist_off,
-                           static_cast<uint32_t *>(scan_tmp), s));
-    IGS_HIP(launch_tile_ranges(keys, status, pair_capacity, ranges, s));
-    IGS_HIP(launch_tile_stats(ranges, d.T, d.tiles_x, H, W, K, status, s));
+    IGS_HIP(launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, s));
+    IGS_HIP(scan_u32_to_i64(counts, offsets, d.N, static_cast<int64_t *>(scan_tmp), s));
+    IGS_HIP(launch_pair_total(counts, offsets, d.N, d.cap, status, s));
+    const bool alt = sort_starts_in_alt(d.passes);
+    IGS_HIP(launch_emit(params, d.N, imgs, counts, offsets, d.cap, alt ? keys_alt : keys,
+                        alt ? vals_alt : vals, s));
+    IGS_HIP(radix_sort_pairs(keys, vals, keys_alt, vals_alt, status, d.cap, d.key_bits, d.passes,
+                             d.digit_bits, hist, hist_off, static_cast<uint32_t *>(scan_tmp), s));
+    IGS_HIP(launch_tile_ranges(keys, status, d.cap, ranges, s));
+    IGS_HIP(launch_tile_stats(ranges, d.T, imgs, d.K, status, s));
+    if (batched) {
+      // largest-first queue: tiles by descending |S_j| (16-bit keys, stable, so ties keep the
+      // tile order)
+      uint32_t *ok = at<uint32_t>(workspace, WL.order_keys);
+      uint32_t *oka = at<uint32_t>(workspace, WL.order_keys_alt);
+      uint32_t *ova = at<uint32_t>(workspace, WL.order_vals_alt);
+      int64_t *ocount = at<int64_t>(workspace, WL.order_count);
+      IGS_HIP(launch_tile_order_keys(ranges, d.T, ok, reinterpret_cast<uint32_t *>(order), ocount,
+                                     s));
+      IGS_HIP(radix_sort_pairs(ok, reinterpret_cast<uint32_t *>(order), oka, ova, ocount, d.T, 16,
+                               2, 8, hist, hist_off, static_cast<uint32_t *>(scan_tmp), s,
+                               false));
+    }
   }
   PhaseTimer timer(kPhaseRasterFwd, s);
-  IGS_HIP(launch_raster_fwd(ranges, vals, g32a, g32b, g64, params, d, image, slots, aux, status,
-                            s));
+  IGS_HIP(launch_raster_fwd(ranges, vals, g32a, g32b, g64, params, d, imgs,
+                            batched ? order : nullptr, image, slots, aux, s));
   return IGS_OK;
+}
+
+igs_status backward_impl(const float *params, const Dims &d, const Images &imgs, bool batched,
+                         const float *image, const float *grad_image, const void *saved,
+                         size_t saved_bytes, float *grad_params, void *workspace, size_t ws_bytes,
+                         hipStream_t s) {
+  const SavedLayout SL = saved_layout(d);
+  const WsLayout WL = ws_layout(d);
+  if (saved_bytes < SL.total || ws_bytes < WL.total) return IGS_ERR_WORKSPACE;
+  if (!aligned(saved) || !aligned(workspace)) return IGS_ERR_WORKSPACE;
+  if (d.N == 0) return IGS_OK;
+  void *sv = const_cast<void *>(saved);
+  const int2 *ranges = at<int2>(sv, SL.ranges);
+  const int *order = at<int>(sv, SL.order);
+  const uint32_t *vals = at<uint32_t>(sv, SL.vals);
+  const float4 *g32a = at<float4>(sv, SL.g32a);
+  const float2 *g32b = at<float2>(sv, SL.g32b);
+  const double4 *g64 = at<double4>(sv, SL.g64);
+  const uint16_t *slots = at<uint16_t>(sv, SL.slots);
+  const float2 *aux = at<float2>(sv, SL.aux);
+  float *gamma = at<float>(workspace, WL.gamma);
+
+  PhaseTimer timer(kPhaseRasterBwd, s);
+  IGS_HIP(launch_fill_f32(gamma, 5 * (int64_t)d.N, 0.f, s));
+  IGS_HIP(launch_fill_f32(grad_params + 5 * (size_t)d.N, (int64_t)d.n * d.N, 0.f, s));
+  IGS_HIP(launch_raster_bwd(ranges, vals, g32a, g32b, g64, params, d, imgs,
+                            batched ? order : nullptr, image, grad_image, slots, aux, gamma,
+                            grad_params, s));
+  IGS_HIP(launch_grad_finalize(params, g32a, g32b, gamma, d.N, grad_params, s));
+  return IGS_OK;
+}
+
+Images single_view(int H, int W, int N) {
+  Images v{};
+  v.one = single_image(H, W, N);
+  v.arr = nullptr;
+  v.B = 1;
+  return v;
+}
+
+// Checks a host descriptor array as written by igs_batch_describe for n channels; *blocks_out
+// receives the number of loss blocks.
+igs_status check_descs(const igs_image_desc *descs, int32_t B, int32_t n, int64_t *blocks_out) {
+  if (!descs || B < 1 || n < 1 || n > IGS_MAX_CHANNELS) return IGS_ERR_INVALID_ARG;
+  const int64_t items = l1_batch_block_items();
+  int64_t g = 0, t = 0, p = 0, blk = 0;
+  for (int b = 0; b < B; ++b) {
+    const igs_image_desc &d = descs[b];
+    if (d.H < 1 || d.W < 1 || d.H > 65536 || d.W > 65536 || d.N < 0) return IGS_ERR_INVALID_ARG;
+    if (d.tiles_x != (d.W + kTile - 1) / kTile || d.tiles_y != (d.H + kTile - 1) / kTile ||
+        d.gauss_off != g || d.tile_off != t || d.pix_off != p || d.l1_block_off != blk)
+      return IGS_ERR_INVALID_ARG;
+    g += d.N;
+    t += (int64_t)d.tiles_x * d.tiles_y;
+    p += (int64_t)d.H * d.W;
+    blk += ((int64_t)n * d.H * d.W + items - 1) / items;
+  }
+  if (g > 0x7FFFFFFF || t > ((int64_t)1 << 24) || blk > 0x7FFFFFFF) return IGS_ERR_INVALID_ARG;
+  if (blocks_out) *blocks_out = blk;
+  return IGS_OK;
+}
+
+igs_status check_batch(const igs_image_desc *descs, int32_t B, int32_t n, int32_t K, int64_t cap) {
+  if (K < 1 || K > IGS_MAX_K || cap < 1 || cap > (int64_t)0x7FFFFFFF) return IGS_ERR_INVALID_ARG;
+  return check_descs(descs, B, n, nullptr);
+}
+
+Images batch_view(const igs_image_desc *descs_dev, int32_t B) {
+  Images v{};
+  v.arr = reinterpret_cast<const ImageDesc *>(descs_dev);
+  v.B = B;
+  return v;
+}
+
+}  // namespace
+
+IGS_API igs_status igs_render(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
+                              int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                              float *image, void *saved, size_t saved_bytes, void *workspace,
+                              size_t ws_bytes, void *stream) {
+  igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
+  if (st != IGS_OK) return st;
+  if ((N > 0 && !params) || !image || !workspace) return IGS_ERR_INVALID_ARG;
+  return render_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N), false,
+                     image, saved, saved_bytes, workspace, ws_bytes,
+                     static_cast<hipStream_t>(stream));
 }
 
 IGS_API igs_status igs_render_backward(const float *params, int32_t N, int32_t n, int32_t H,
@@ -231,30 +360,106 @@ IGS_API igs_status igs_render_backward(const float *params, int32_t N, int32_t n
   if (st != IGS_OK) return st;
   if ((N > 0 && (!params || !grad_params)) || !image || !grad_image || !saved || !workspace)
     return IGS_ERR_INVALID_ARG;
-  const Dims d = make_dims(N, n, H, W, K, pair_capacity);
-  const SavedLayout SL = saved_layout(d);
-  const WsLayout WL = ws_layout(d);
-  if (saved_bytes < SL.total || ws_bytes < WL.total) return IGS_ERR_WORKSPACE;
-  if (!aligned(saved) || !aligned(workspace)) return IGS_ERR_WORKSPACE;
-  if (N == 0) return IGS_OK;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  void *sv = const_cast<void *>(saved);
-  const int2 *ranges = at<int2>(sv, SL.ranges);
-  const uint32_t *vals = at<uint32_t>(sv, SL.vals);
-  const float4 *g32a = at<float4>(sv, SL.g32a);
-  const float2 *g32b = at<float2>(sv, SL.g32b);
-  const double4 *g64 = at<double4>(sv, SL.g64);
-  const uint16_t *slots = at<uint16_t>(sv, SL.slots);
-  const float2 *aux = at<float2>(sv, SL.aux);
-  float *gamma = at<float>(workspace, WL.gamma);
+  return backward_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N),
+                       false, image, grad_image, saved, saved_bytes, grad_params, workspace,
+                       ws_bytes, static_cast<hipStream_t>(stream));
+}
 
-  PhaseTimer timer(kPhaseRasterBwd, s);
-  IGS_HIP(launch_fill_f32(gamma, 5 * (int64_t)N, 0.f, s));
-  IGS_HIP(launch_fill_f32(grad_params + 5 * (size_t)N, (int64_t)n * N, 0.f, s));
-  IGS_HIP(launch_raster_bwd(ranges, vals, g32a, g32b, g64, params, d, image, grad_image, slots,
-                            aux, gamma, grad_params, s));
-  IGS_HIP(launch_grad_finalize(params, g32a, g32b, gamma, N, grad_params, s));
+// ------------------------------------------------------------------------------ batches
+
+IGS_API igs_status igs_batch_describe(int32_t B, int32_t n, const int32_t *H, const int32_t *W,
+                                      const int32_t *N, igs_image_desc *descs_out,
+                                      int64_t totals_out[4]) {
+  if (B < 1 || n < 1 || n > IGS_MAX_CHANNELS || !H || !W || !N || !descs_out || !totals_out)
+    return IGS_ERR_INVALID_ARG;
+  int64_t g = 0, t = 0, p = 0, blk = 0;
+  const int64_t items = l1_batch_block_items();
+  for (int b = 0; b < B; ++b) {
+    if (H[b] < 1 || W[b] < 1 || H[b] > 65536 || W[b] > 65536 || N[b] < 0) return IGS_ERR_INVALID_ARG;
+    igs_image_desc &d = descs_out[b];
+    d.H = H[b];
+    d.W = W[b];
+    d.N = N[b];
+    d.tiles_x = (W[b] + kTile - 1) / kTile;
+    d.tiles_y = (H[b] + kTile - 1) / kTile;
+    d.tile_off = (int32_t)t;
+    d.gauss_off = (int32_t)g;
+    d.l1_block_off = (int32_t)blk;
+    d.pix_off = p;
+    d.reserved = 0;
+    g += N[b];
+    t += (int64_t)d.tiles_x * d.tiles_y;
+    p += (int64_t)H[b] * W[b];
+    blk += ((int64_t)n * H[b] * W[b] + items - 1) / items;
+    if (g > 0x7FFFFFFF || t > ((int64_t)1 << 24) || blk > 0x7FFFFFFF) return IGS_ERR_INVALID_ARG;
+  }
+  totals_out[0] = g;
+  totals_out[1] = t;
+  totals_out[2] = p;
+  totals_out[3] = blk;
   return IGS_OK;
+}
+
+IGS_API igs_status igs_batch_buffer_sizes(const igs_image_desc *descs, int32_t B, int32_t n,
+                                          int32_t K, int64_t pair_capacity, size_t *ws_bytes,
+                                          size_t *saved_bytes) {
+  if (!ws_bytes || !saved_bytes) return IGS_ERR_INVALID_ARG;
+  igs_status st = check_batch(descs, B, n, K, pair_capacity);
+  if (st != IGS_OK) return st;
+  const Dims d = make_batch_dims(reinterpret_cast<const ImageDesc *>(descs), B, n, K, pair_capacity);
+  *ws_bytes = ws_layout(d).total;
+  *saved_bytes = saved_layout(d).total;
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_batch_saved_offsets(const igs_image_desc *descs, int32_t B, int32_t n,
+                                           int32_t K, int64_t pair_capacity, int64_t out[7]) {
+  if (!out) return IGS_ERR_INVALID_ARG;
+  igs_status st = check_batch(descs, B, n, K, pair_capacity);
+  if (st != IGS_OK) return st;
+  const SavedLayout L = saved_layout(
+      make_batch_dims(reinterpret_cast<const ImageDesc *>(descs), B, n, K, pair_capacity));
+  out[0] = (int64_t)L.status;
+  out[1] = (int64_t)L.ranges;
+  out[2] = (int64_t)L.vals;
+  out[3] = (int64_t)L.slots;
+  out[4] = (int64_t)L.aux;
+  out[5] = (int64_t)L.total;
+  out[6] = (int64_t)L.order;
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_render_batched(const float *params, const igs_image_desc *descs_host,
+                                      const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                      int32_t K, int64_t pair_capacity, float *images, void *saved,
+                                      size_t saved_bytes, void *workspace, size_t ws_bytes,
+                                      void *stream) {
+  igs_status st = check_batch(descs_host, B, n, K, pair_capacity);
+  if (st != IGS_OK) return st;
+  const Dims d =
+      make_batch_dims(reinterpret_cast<const ImageDesc *>(descs_host), B, n, K, pair_capacity);
+  if ((d.N > 0 && !params) || !descs_dev || !images || !workspace) return IGS_ERR_INVALID_ARG;
+  return render_impl(params, d, batch_view(descs_dev, B), true, images, saved, saved_bytes,
+                     workspace, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+IGS_API igs_status igs_render_backward_batched(const float *params, const igs_image_desc *descs_host,
+                                               const igs_image_desc *descs_dev, int32_t B,
+                                               int32_t n, int32_t K, int64_t pair_capacity,
+                                               const float *images, const float *grad_images,
+                                               const void *saved, size_t saved_bytes,
+                                               float *grad_params, void *workspace,
+                                               size_t ws_bytes, void *stream) {
+  igs_status st = check_batch(descs_host, B, n, K, pair_capacity);
+  if (st != IGS_OK) return st;
+  const Dims d =
+      make_batch_dims(reinterpret_cast<const ImageDesc *>(descs_host), B, n, K, pair_capacity);
+  if ((d.N > 0 && (!params || !grad_params)) || !descs_dev || !images || !grad_images || !saved ||
+      !workspace)
+    return IGS_ERR_INVALID_ARG;
+  return backward_impl(params, d, batch_view(descs_dev, B), true, images, grad_images, saved,
+                       saved_bytes, grad_params, workspace, ws_bytes,
+                       static_cast<hipStream_t>(stream));
 }
 
 IGS_API igs_status igs_l1_workspace_size(int64_t count, size_t *ws_bytes) {
@@ -288,9 +493,9 @@ IGS_API igs_status igs_adam_step(float *fit_params, float *render_params, const 
         inv_scale_lo > 0.f && inv_scale_hi >= inv_scale_lo))
     return IGS_ERR_INVALID_ARG;
   PhaseTimer timer(kPhaseAdam, static_cast<hipStream_t>(stream));
-  IGS_HIP(launch_adam(fit_params, render_params, grad_render, m, v, step, skip_flag, N, n, H, W, lr_mu,
-                      lr_theta, lr_inv_scale, lr_color, beta1, beta2, eps, inv_scale_lo,
-                      inv_scale_hi, static_cast<hipStream_t>(stream)));
+  IGS_HIP(launch_adam_lo(fit_params, render_params, grad_render, m, v, step, skip_flag, N, n,
+                         single_view(H, W, N), lr_mu, lr_theta, lr_inv_scale, lr_color, beta1,
+                         beta2, eps, inv_scale_lo, inv_scale_hi, static_cast<hipStream_t>(stream)));
   return IGS_OK;
 }
 
@@ -298,7 +503,73 @@ IGS_API igs_status igs_fit_to_render(const float *fit_params, float *render_para
                                      int32_t n, int32_t H, int32_t W, void *stream) {
   if (N < 0 || n < 1 || n > IGS_MAX_CHANNELS || H < 1 || W < 1) return IGS_ERR_INVALID_ARG;
   if (N > 0 && (!fit_params || !render_params)) return IGS_ERR_INVALID_ARG;
-  IGS_HIP(launch_fit_to_render(fit_params, render_params, N, n, H, W,
+  IGS_HIP(launch_fit_to_render(fit_params, render_params, N, n, single_view(H, W, N),
+                               static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_l1_batched_workspace_size(const igs_image_desc *descs, int32_t B, int32_t n,
+                                                 size_t *ws_bytes) {
+  int64_t blocks = 0;
+  if (!ws_bytes) return IGS_ERR_INVALID_ARG;
+  igs_status st = check_descs(descs, B, n, &blocks);
+  if (st != IGS_OK) return st;
+  *ws_bytes = align_up((size_t)std::max<int64_t>(blocks, 1) * 2 * sizeof(double));
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_l1_loss_grad_batched(const float *images, const float *targets,
+                                            const igs_image_desc *descs_host,
+                                            const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                            float *grad_images, double *loss_out,
+                                            void *workspace, size_t ws_bytes, void *stream) {
+  int64_t blocks = 0;
+  igs_status st = check_descs(descs_host, B, n, &blocks);
+  if (st != IGS_OK) return st;
+  if (!images || !targets || !descs_dev || !grad_images || !loss_out || !workspace)
+    return IGS_ERR_INVALID_ARG;
+  if (ws_bytes < (size_t)blocks * 2 * sizeof(double)) return IGS_ERR_WORKSPACE;
+  PhaseTimer timer(kPhaseLoss, static_cast<hipStream_t>(stream));
+  IGS_HIP(launch_l1_batched(images, targets, batch_view(descs_dev, B), n, (int)blocks, grad_images,
+                            static_cast<double *>(workspace), loss_out,
+                            static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_adam_step_batched(float *fit_params, float *render_params,
+                                         const float *grad_render, float *m, float *v,
+                                         int32_t *step, const int64_t *skip_flag,
+                                         const igs_image_desc *descs_host,
+                                         const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                         float lr_mu, float lr_theta, float lr_inv_scale,
+                                         float lr_color, float beta1, float beta2, float eps,
+                                         float inv_scale_hi, void *stream) {
+  igs_status st = check_descs(descs_host, B, n, nullptr);
+  if (st != IGS_OK) return st;
+  int64_t N = 0;
+  for (int b = 0; b < B; ++b) N += descs_host[b].N;
+  if (!step || !descs_dev || (N > 0 && (!fit_params || !render_params || !grad_render || !m || !v)))
+    return IGS_ERR_INVALID_ARG;
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f &&
+        inv_scale_hi > 0.f))
+    return IGS_ERR_INVALID_ARG;
+  PhaseTimer timer(kPhaseAdam, static_cast<hipStream_t>(stream));
+  IGS_HIP(launch_adam_lo(fit_params, render_params, grad_render, m, v, step, skip_flag, (int)N, n,
+                         batch_view(descs_dev, B), lr_mu, lr_theta, lr_inv_scale, lr_color, beta1,
+                         beta2, eps, 0.f, inv_scale_hi, static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_fit_to_render_batched(const float *fit_params, float *render_params,
+                                             const igs_image_desc *descs_host,
+                                             const igs_image_desc *descs_dev, int32_t B,
+                                             int32_t n, void *stream) {
+  igs_status st = check_descs(descs_host, B, n, nullptr);
+  if (st != IGS_OK) return st;
+  int64_t N = 0;
+  for (int b = 0; b < B; ++b) N += descs_host[b].N;
+  if (!descs_dev || (N > 0 && (!fit_params || !render_params))) return IGS_ERR_INVALID_ARG;
+  IGS_HIP(launch_fit_to_render(fit_params, render_params, (int)N, n, batch_view(descs_dev, B),
                                static_cast<hipStream_t>(stream)));
   return IGS_OK;
 }

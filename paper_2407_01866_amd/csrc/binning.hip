@@ -81,11 +81,11 @@ __device__ __forceinline__ TileBox tile_box(float fmx, float fmy, float fs1, flo
 // C dx + D dy) = diag(1/s1, 1/s2) R(theta)^T (x - mu), so that q = |e|^2 (Eq. 1-2); kept in
 // float for ranking and in double for the blend weights; plus the exact tile-hit count.
 __global__ __launch_bounds__(kThreads) void preprocess_kernel(
-    const float *__restrict__ params, int N, int H, int W, int tiles_x, int tiles_y,
-    float4 *__restrict__ g32a, float2 *__restrict__ g32b, double4 *__restrict__ g64,
-    uint32_t *__restrict__ counts) {
+    const float *__restrict__ params, int N, Images imgs, float4 *__restrict__ g32a,
+    float2 *__restrict__ g32b, double4 *__restrict__ g64, uint32_t *__restrict__ counts) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
+  const ImageDesc im = imgs.by_gauss(i);
   float mx = params[i], my = params[(size_t)N + i], th = params[2 * (size_t)N + i];
   float s1 = params[3 * (size_t)N + i], s2 = params[4 * (size_t)N + i];
   double sn, cs;
@@ -95,10 +95,11 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
   g64[i] = make_double4(A, B, C, D);
   g32a[i] = make_float4(mx, my, (float)A, (float)B);
   g32b[i] = make_float2((float)C, (float)D);
-  TileBox b = tile_box(mx, my, s1, s2, tiles_x, tiles_y);
+  TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
   uint32_t c = 0;
   for (int ty = b.ty0; ty <= b.ty1; ++ty)
-    for (int tx = b.tx0; tx <= b.tx1; ++tx) c += circle_meets_tile(b.mx, b.my, b.r2, tx, ty, H, W);
+    for (int tx = b.tx0; tx <= b.tx1; ++tx)
+      c += circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W);
   counts[i] = c;
 }
 
@@ -115,22 +116,23 @@ __global__ void pair_total_kernel(const uint32_t *__restrict__ counts,
 // offset; the pair list is thereby in ascending Gaussian index, which the stable sort keeps
 // within each tile.  Nothing is written past the capacity.
 __global__ __launch_bounds__(kThreads) void emit_kernel(
-    const float *__restrict__ params, int N, int H, int W, int tiles_x, int tiles_y,
-    const uint32_t *__restrict__ counts, const int64_t *__restrict__ offsets, int64_t cap,
-    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
+    const int64_t *__restrict__ offsets, int64_t cap, uint32_t *__restrict__ keys,
+    uint32_t *__restrict__ vals) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   uint32_t c = counts[i];
   int64_t o = offsets[i];
   if (c == 0 || o + (int64_t)c > cap) return;
+  const ImageDesc im = imgs.by_gauss(i);
   float mx = params[i], my = params[(size_t)N + i];
   float s1 = params[3 * (size_t)N + i], s2 = params[4 * (size_t)N + i];
-  TileBox b = tile_box(mx, my, s1, s2, tiles_x, tiles_y);
+  TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
   uint32_t k = 0;
   for (int ty = b.ty0; ty <= b.ty1; ++ty)
     for (int tx = b.tx0; tx <= b.tx1; ++tx)
-      if (circle_meets_tile(b.mx, b.my, b.r2, tx, ty, H, W) && k < c) {
-        keys[o + k] = (uint32_t)(ty * tiles_x + tx);
+      if (circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W) && k < c) {
+        keys[o + k] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
         vals[o + k] = (uint32_t)i;
         ++k;
       }
@@ -157,16 +159,18 @@ __global__ __launch_bounds__(kThreads) void tile_ranges_kernel(const uint32_t *_
 // tile's pixel count and E_bwd = sum_j min(K, |S_j|) times the tile's pixel count.
 constexpr int kStatThreads = 1024;
 __global__ __launch_bounds__(kStatThreads) void tile_stats_kernel(const int2 *__restrict__ ranges,
-                                                                  int T, int tiles_x, int H, int W,
-                                                                  int K,
+                                                                  int T, Images imgs, int K,
                                                                   int64_t *__restrict__ status) {
   __shared__ long long s_max[kStatThreads / 64], s_ef[kStatThreads / 64], s_eb[kStatThreads / 64];
   long long mx = 0, ef = 0, eb = 0;
   for (int t = threadIdx.x; t < T; t += kStatThreads) {
     const int2 r = ranges[t];
     const long long c = r.y - r.x;
-    const int tx = t % tiles_x, ty = t / tiles_x;
-    const long long npx = (long long)min(W - tx * kTile, kTile) * min(H - ty * kTile, kTile);
+    const ImageDesc im = imgs.by_tile(t);
+    const int lt = t - im.tile_off;
+    const int tx = lt % im.tiles_x, ty = lt / im.tiles_x;
+    const long long npx =
+        (long long)min(im.W - tx * kTile, kTile) * min(im.H - ty * kTile, kTile);
     mx = c > mx ? c : mx;
     ef += c * npx;
     eb += (c < K ? c : K) * npx;
@@ -198,6 +202,19 @@ __global__ __launch_bounds__(kStatThreads) void tile_stats_kernel(const int2 *__
   }
 }
 
+__global__ __launch_bounds__(kThreads) void tile_order_keys_kernel(const int2 *__restrict__ ranges,
+                                                                   int T, uint32_t *__restrict__ keys,
+                                                                   uint32_t *__restrict__ vals,
+                                                                   int64_t *__restrict__ count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) count[0] = T;
+  if (t >= T) return;
+  const int2 r = ranges[t];
+  const int c = min(r.y - r.x, 0xFFFF);
+  keys[t] = (uint32_t)(0xFFFF - c);
+  vals[t] = (uint32_t)t;
+}
+
 inline int grid_for(int64_t count, int threads, int max_blocks = 65536) {
   int64_t b = (count + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -224,12 +241,11 @@ hipError_t launch_status_reset(int64_t *status, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_preprocess(const float *params, int N, int H, int W, int tiles_x, int tiles_y,
-                             float4 *g32a, float2 *g32b, double4 *g64, uint32_t *counts,
-                             hipStream_t s) {
+hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
+                             float2 *g32b, double4 *g64, uint32_t *counts, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  preprocess_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(
-      params, N, H, W, tiles_x, tiles_y, g32a, g32b, g64, counts);
+  preprocess_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(params, N, imgs, g32a,
+                                                                        g32b, g64, counts);
   return hipGetLastError();
 }
 
@@ -239,12 +255,12 @@ hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int
   return hipGetLastError();
 }
 
-hipError_t launch_emit(const float *params, int N, int H, int W, int tiles_x, int tiles_y,
-                       const uint32_t *counts, const int64_t *offsets, int64_t cap,
-                       uint32_t *keys, uint32_t *vals, hipStream_t s) {
+hipError_t launch_emit(const float *params, int N, const Images &imgs, const uint32_t *counts,
+                       const int64_t *offsets, int64_t cap, uint32_t *keys, uint32_t *vals,
+                       hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(
-      params, N, H, W, tiles_x, tiles_y, counts, offsets, cap, keys, vals);
+  emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(params, N, imgs, counts, offsets,
+                                                                  cap, keys, vals);
   return hipGetLastError();
 }
 
@@ -254,9 +270,16 @@ hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64
   return hipGetLastError();
 }
 
-hipError_t launch_tile_stats(const int2 *ranges, int T, int tiles_x, int H, int W, int K,
+hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uint32_t *vals,
+                                  int64_t *count, hipStream_t s) {
+  tile_order_keys_kernel<<<(T + kThreads - 1) / kThreads, kThreads, 0, s>>>(ranges, T, keys, vals,
+                                                                            count);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K,
                              int64_t *status, hipStream_t s) {
-  tile_stats_kernel<<<1, kStatThreads, 0, s>>>(ranges, T, tiles_x, H, W, K, status);
+  tile_stats_kernel<<<1, kStatThreads, 0, s>>>(ranges, T, imgs, K, status);
   return hipGetLastError();
 }
 

@@ -38,6 +38,63 @@ constexpr int kScanBlockItems = kScanThreads * kScanItems;
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// One image of a render call.  A batch concatenates its images: the Gaussians of image b are the
+// global indices [gauss_off, gauss_off + N) (parameter row stride = total N of the batch), its
+// tiles [tile_off, tile_off + tiles_x * tiles_y) of the global tile numbering, and its pixels
+// [pix_off, pix_off + H * W): its image and image gradient start at float n * pix_off, its top-K
+// slots at K * pix_off, its per-pixel blend normalization at pix_off.  l1_block_off numbers the
+// loss kernel's blocks (image b owns blocks [l1_block_off[b], l1_block_off[b + 1])).
+// Layout identical to igs_image_desc in include/imagegs.h.
+struct ImageDesc {
+  int32_t H, W, N, tiles_x;
+  int32_t tiles_y, tile_off, gauss_off, l1_block_off;
+  int64_t pix_off, reserved;
+};
+static_assert(sizeof(ImageDesc) == 48, "ImageDesc layout");
+
+// The images of a call, passed by value: a single image inline, or a device array.
+struct Images {
+  ImageDesc one;
+  const ImageDesc *arr;  // nullptr: the single image `one`
+  int B;
+
+  __device__ __forceinline__ ImageDesc at(int b) const { return arr ? arr[b] : one; }
+  // the image owning global Gaussian gi (the last image whose first Gaussian is <= gi)
+  __device__ __forceinline__ ImageDesc by_gauss(int gi) const {
+    if (!arr) return one;
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (arr[mid].gauss_off <= gi) lo = mid;
+      else hi = mid - 1;
+    }
+    return arr[lo];
+  }
+  // the image owning global tile gt
+  __device__ __forceinline__ ImageDesc by_tile(int gt) const {
+    if (!arr) return one;
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (arr[mid].tile_off <= gt) lo = mid;
+      else hi = mid - 1;
+    }
+    return arr[lo];
+  }
+};
+
+inline ImageDesc single_image(int H, int W, int N) {
+  ImageDesc d{};
+  d.H = H;
+  d.W = W;
+  d.N = N;
+  d.tiles_x = (W + kTile - 1) / kTile;
+  d.tiles_y = (H + kTile - 1) / kTile;
+  return d;
+}
+
+// Sizes of a call.  For a batch N, T and HW are totals over its images (H, W, tiles_x, tiles_y
+// then describe no single image and are unused by the kernels).
 struct Dims {
   int N, n, H, W, K;
   int64_t cap;
@@ -48,14 +105,16 @@ struct Dims {
 };
 
 Dims make_dims(int N, int n, int H, int W, int K, int64_t cap);
+Dims make_batch_dims(const ImageDesc *descs, int B, int n, int K, int64_t cap);
 
 // Byte offsets inside the caller's `saved` buffer.
 struct SavedLayout {
-  size_t status, ranges, vals, g32a, g32b, g64, slots, aux, total;
+  size_t status, ranges, order, vals, g32a, g32b, g64, slots, aux, total;
 };
 // Byte offsets inside the caller's workspace.
 struct WsLayout {
-  size_t counts, offsets, keys, keys_alt, vals_alt, hist, hist_off, scan_tmp, gamma, l1_tmp, total;
+  size_t counts, offsets, keys, keys_alt, vals_alt, hist, hist_off, scan_tmp, gamma, order_keys,
+      order_keys_alt, order_vals_alt, order_count, l1_tmp, total;
 };
 
 SavedLayout saved_layout(const Dims &d);
@@ -68,18 +127,21 @@ size_t scan_temp_elems(int64_t n);
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s);
 hipError_t launch_status_reset(int64_t *status, hipStream_t s);
-hipError_t launch_preprocess(const float *params, int N, int H, int W, int tiles_x, int tiles_y,
-                             float4 *g32a, float2 *g32b, double4 *g64, uint32_t *counts,
-                             hipStream_t s);
+hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
+                             float2 *g32b, double4 *g64, uint32_t *counts, hipStream_t s);
 hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int N, int64_t cap,
                              int64_t *status, hipStream_t s);
-hipError_t launch_emit(const float *params, int N, int H, int W, int tiles_x, int tiles_y,
-                       const uint32_t *counts, const int64_t *offsets, int64_t cap,
-                       uint32_t *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_emit(const float *params, int N, const Images &imgs, const uint32_t *counts,
+                       const int64_t *offsets, int64_t cap, uint32_t *keys, uint32_t *vals,
+                       hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
                               int2 *ranges, hipStream_t s);
-hipError_t launch_tile_stats(const int2 *ranges, int T, int tiles_x, int H, int W, int K,
+hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K,
                              int64_t *status, hipStream_t s);
+// Sort keys for the largest-first tile queue: key = 0xFFFF - min(|S_j|, 0xFFFF), value = tile;
+// also writes T to *count.
+hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uint32_t *vals,
+                                  int64_t *count, hipStream_t s);
 
 // scan.hip: exclusive scans; temp must hold scan_temp_elems(n) elements of the output type.
 hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *temp,
@@ -89,23 +151,27 @@ hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_
 
 // radix_sort.hip: stable LSD sort of (key, val) by the low key_bits bits; the count is read
 // from status on the device.  Result lands in (keys, vals); (keys_alt, vals_alt) are scratch.
+// count_word: the device word holding the number of pairs (a render's status block, whose
+// overflow flag then also empties the sort), or a plain count when status_semantics is false.
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                             uint32_t *vals_alt, const int64_t *status, int64_t cap, int key_bits,
                             int passes, int digit_bits, uint32_t *hist, uint32_t *hist_off,
-                            uint32_t *scan_tmp, hipStream_t s);
+                            uint32_t *scan_tmp, hipStream_t s, bool status_semantics = true);
 // Which buffer emit must write into so the sort's final pass ends in (keys, vals).
 inline bool sort_starts_in_alt(int passes) { return (passes & 1) != 0; }
 
 // raster_fwd.hip
+// tile_order: optional device array of the T global tile ids in the order workgroups take them
+// (a largest-first queue for batches); nullptr = XCD-aware order of a single image's tiles.
 hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
-                             const Dims &d, float *image, uint16_t *slots, float2 *aux,
-                             int64_t *status, hipStream_t s);
+                             const Dims &d, const Images &imgs, const int *tile_order,
+                             float *image, uint16_t *slots, float2 *aux, hipStream_t s);
 
 // raster_bwd.hip
 hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
-                             const Dims &d,
+                             const Dims &d, const Images &imgs, const int *tile_order,
                              const float *image, const float *grad_image, const uint16_t *slots,
                              const float2 *aux, float *gamma, float *grad_params, hipStream_t s);
 hipError_t launch_grad_finalize(const float *params, const float4 *g32a, const float2 *g32b,
@@ -116,10 +182,19 @@ int l1_blocks(int64_t count);
 hipError_t launch_l1(const float *image, const float *target, int64_t count, float *grad,
                      double *partials, double *loss_out, hipStream_t s);
 hipError_t launch_adam(float *fit, float *rend, const float *grad, float *m, float *v,
-                       int32_t *step, const int64_t *skip, int N, int n, int H, int W, float lr_mu,
-                       float lr_theta, float lr_u, float lr_c, float b1, float b2, float eps,
-                       float u_lo, float u_hi, hipStream_t s);
-hipError_t launch_fit_to_render(const float *fit, float *rend, int N, int n, int H, int W,
+                       int32_t *step, const int64_t *skip, int N, int n, const Images &imgs,
+                       float lr_mu, float lr_theta, float lr_u, float lr_c, float b1, float b2,
+                       float eps, float u_hi, hipStream_t s);
+hipError_t launch_adam_lo(float *fit, float *rend, const float *grad, float *m, float *v,
+                          int32_t *step, const int64_t *skip, int N, int n, const Images &imgs,
+                          float lr_mu, float lr_theta, float lr_u, float lr_c, float b1, float b2,
+                          float eps, float u_lo, float u_hi, hipStream_t s);
+hipError_t launch_fit_to_render(const float *fit, float *rend, int N, int n, const Images &imgs,
                                 hipStream_t s);
+// Batched L1: per-image mean normalization; loss_out is double[B][2].
+int l1_batch_block_items();
+hipError_t launch_l1_batched(const float *images, const float *targets, const Images &imgs,
+                             int n, int total_blocks, float *grad, double *partials,
+                             double *loss_out, hipStream_t s);
 
 }  // namespace igs

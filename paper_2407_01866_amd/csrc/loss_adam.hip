@@ -71,17 +71,20 @@ __device__ __forceinline__ float to_render(int r, float p, float W, float H) {
   return p;
 }
 
+// u_lo > 0: lower clip of the inverse scales; u_lo <= 0: 1/max(H, W) of each Gaussian's image.
 __global__ __launch_bounds__(256) void adam_kernel(
     float *__restrict__ fit, float *__restrict__ rend, const float *__restrict__ grad,
     float *__restrict__ m, float *__restrict__ v, const int32_t *__restrict__ step,
-    const int64_t *__restrict__ skip, int N, int n,
-    float W, float H, float lr_mu, float lr_theta, float lr_u, float lr_c, float b1, float b2,
-    float eps, float u_lo, float u_hi) {
+    const int64_t *__restrict__ skip, int N, int n, Images imgs, float lr_mu, float lr_theta,
+    float lr_u, float lr_c, float b1, float b2, float eps, float u_lo_arg, float u_hi) {
   const int64_t total = (int64_t)(5 + n) * N;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   if (skip != nullptr && skip[0] != 0) return;
   const int r = (int)(e / N);
+  const ImageDesc im = imgs.by_gauss((int)(e - (int64_t)r * N));
+  const float W = (float)im.W, H = (float)im.H;
+  const float u_lo = u_lo_arg > 0.f ? u_lo_arg : 1.0f / fmaxf(W, H);
   const float t = (float)(step[0] + 1);
   const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
   const float p = fit[e];
@@ -116,11 +119,78 @@ __global__ void step_increment_kernel(int32_t *step, const int64_t *skip) {
 
 __global__ __launch_bounds__(256) void fit_to_render_kernel(const float *__restrict__ fit,
                                                             float *__restrict__ rend, int N, int n,
-                                                            float W, float H) {
+                                                            Images imgs) {
   const int64_t total = (int64_t)(5 + n) * N;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  rend[e] = to_render((int)(e / N), fit[e], W, H);
+  const int r = (int)(e / N);
+  const ImageDesc im = imgs.by_gauss((int)(e - (int64_t)r * N));
+  rend[e] = to_render(r, fit[e], (float)im.W, (float)im.H);
+}
+
+// Batched L1: block k belongs to the image b with l1_block_off[b] <= k < l1_block_off[b+1] and
+// covers kL1BatchItems consecutive values of it; each image is normalized by its own n*H*W.
+constexpr int kL1BatchItems = 8192;
+
+__device__ __forceinline__ int image_of_block(const Images &imgs, int k) {
+  int lo = 0, hi = imgs.B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (imgs.arr[mid].l1_block_off <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kL1Threads) void l1_batched_kernel(const float *__restrict__ images,
+                                                                const float *__restrict__ targets,
+                                                                Images imgs, int n,
+                                                                float *__restrict__ grad,
+                                                                double *__restrict__ partials) {
+  __shared__ double sh[kL1Threads / 64];
+  const int b = image_of_block(imgs, blockIdx.x);
+  const ImageDesc im = imgs.arr[b];
+  const int64_t count = (int64_t)n * im.H * im.W;
+  const int64_t base = (int64_t)n * im.pix_off;
+  const int64_t first = (int64_t)(blockIdx.x - im.l1_block_off) * kL1BatchItems;
+  const int64_t last = min(first + kL1BatchItems, count);
+  const float inv_count = (float)(1.0 / (double)count);
+  double a = 0.0, q = 0.0;
+  for (int64_t i = first + threadIdx.x; i < last; i += kL1Threads) {
+    const double d = (double)images[base + i] - (double)targets[base + i];
+    grad[base + i] = d > 0.0 ? inv_count : (d < 0.0 ? -inv_count : 0.f);
+    a += fabs(d);
+    q += d * d;
+  }
+  const double sa = block_sum(a, sh);
+  const double sq = block_sum(q, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = sa;
+    partials[2 * blockIdx.x + 1] = sq;
+  }
+}
+
+// One block per image: its blocks' partial sums in a fixed order -> loss_out[b] = (L1, MSE).
+__global__ __launch_bounds__(kL1Threads) void l1_batched_final_kernel(
+    const double *__restrict__ partials, Images imgs, int n, int total_blocks,
+    double *__restrict__ out) {
+  __shared__ double sh[kL1Threads / 64];
+  const int b = blockIdx.x;
+  const ImageDesc im = imgs.arr[b];
+  const int k0 = im.l1_block_off;
+  const int k1 = b + 1 < imgs.B ? imgs.arr[b + 1].l1_block_off : total_blocks;
+  double a = 0.0, q = 0.0;
+  for (int k = k0 + threadIdx.x; k < k1; k += kL1Threads) {
+    a += partials[2 * k];
+    q += partials[2 * k + 1];
+  }
+  const double sa = block_sum(a, sh);
+  const double sq = block_sum(q, sh);
+  if (threadIdx.x == 0) {
+    const double inv = 1.0 / ((double)n * im.H * im.W);
+    out[2 * b] = sa * inv;
+    out[2 * b + 1] = sq * inv;
+  }
 }
 
 }  // namespace
@@ -144,15 +214,22 @@ hipError_t launch_l1(const float *image, const float *target, int64_t count, flo
 }
 
 hipError_t launch_adam(float *fit, float *rend, const float *grad, float *m, float *v,
-                       int32_t *step, const int64_t *skip, int N, int n, int H, int W,
-                       float lr_mu, float lr_theta,
-                       float lr_u, float lr_c, float b1, float b2, float eps, float u_lo,
-                       float u_hi, hipStream_t s) {
+                       int32_t *step, const int64_t *skip, int N, int n, const Images &imgs,
+                       float lr_mu, float lr_theta, float lr_u, float lr_c, float b1, float b2,
+                       float eps, float u_hi, hipStream_t s) {
+  return launch_adam_lo(fit, rend, grad, m, v, step, skip, N, n, imgs, lr_mu, lr_theta, lr_u,
+                        lr_c, b1, b2, eps, 0.f, u_hi, s);
+}
+
+hipError_t launch_adam_lo(float *fit, float *rend, const float *grad, float *m, float *v,
+                          int32_t *step, const int64_t *skip, int N, int n, const Images &imgs,
+                          float lr_mu, float lr_theta, float lr_u, float lr_c, float b1, float b2,
+                          float eps, float u_lo, float u_hi, hipStream_t s) {
   const int64_t total = (int64_t)(5 + n) * N;
   if (total > 0) {
     adam_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
-        fit, rend, grad, m, v, step, skip, N, n, (float)W, (float)H, lr_mu, lr_theta, lr_u, lr_c, b1,
-        b2, eps, u_lo, u_hi);
+        fit, rend, grad, m, v, step, skip, N, n, imgs, lr_mu, lr_theta, lr_u, lr_c, b1, b2, eps,
+        u_lo, u_hi);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -160,12 +237,24 @@ hipError_t launch_adam(float *fit, float *rend, const float *grad, float *m, flo
   return hipGetLastError();
 }
 
-hipError_t launch_fit_to_render(const float *fit, float *rend, int N, int n, int H, int W,
+hipError_t launch_fit_to_render(const float *fit, float *rend, int N, int n, const Images &imgs,
                                 hipStream_t s) {
   const int64_t total = (int64_t)(5 + n) * N;
   if (total <= 0) return hipSuccess;
-  fit_to_render_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(fit, rend, N, n, (float)W,
-                                                                       (float)H);
+  fit_to_render_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(fit, rend, N, n, imgs);
+  return hipGetLastError();
+}
+
+int l1_batch_block_items() { return kL1BatchItems; }
+
+hipError_t launch_l1_batched(const float *images, const float *targets, const Images &imgs,
+                             int n, int total_blocks, float *grad, double *partials,
+                             double *loss_out, hipStream_t s) {
+  if (total_blocks <= 0) return hipSuccess;
+  l1_batched_kernel<<<total_blocks, kL1Threads, 0, s>>>(images, targets, imgs, n, grad, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  l1_batched_final_kernel<<<imgs.B, kL1Threads, 0, s>>>(partials, imgs, n, total_blocks, loss_out);
   return hipGetLastError();
 }
 

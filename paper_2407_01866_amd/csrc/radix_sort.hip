@@ -7,20 +7,21 @@
 namespace igs {
 namespace {
 
-__device__ __forceinline__ int64_t live_pairs(const int64_t *status, int64_t cap) {
-  int64_t P = status[kStatOverflow] ? 0 : status[kStatPairs];
+// Number of pairs to sort: a render status block (pairs, overflow flag) or a plain count.
+__device__ __forceinline__ int64_t live_pairs(const int64_t *status, int64_t cap, bool st) {
+  int64_t P = st ? (status[kStatOverflow] ? 0 : status[kStatPairs]) : status[0];
   return P > cap ? 0 : P;
 }
 
 // Per-block digit histogram, stored digit-major: hist[d * nblocks + b].
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
     const uint32_t *__restrict__ keys, const int64_t *__restrict__ status, int64_t cap, int shift,
-    int digit_bits, uint32_t *__restrict__ hist, int64_t nblocks) {
+    int digit_bits, uint32_t *__restrict__ hist, int64_t nblocks, bool st) {
   __shared__ uint32_t lh[256];
   const int tid = threadIdx.x;
   const int R = 1 << digit_bits;
   const uint32_t mask = (uint32_t)R - 1;
-  const int64_t P = live_pairs(status, cap);
+  const int64_t P = live_pairs(status, cap, st);
   const int64_t base = (int64_t)blockIdx.x * kSortTileItems;
   if (tid < R) lh[tid] = 0;
   __syncthreads();
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const int64_t *__restrict__ status, int64_t cap, int shift, int digit_bits,
-    const uint32_t *__restrict__ hist_off, int64_t nblocks) {
+    const uint32_t *__restrict__ hist_off, int64_t nblocks, bool st) {
   constexpr int kWaves = kSortThreads / 64;
   __shared__ uint32_t digit_run[256];
   __shared__ uint32_t wave_cnt[2][kWaves][256];
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
   const int lane = tid & 63, w = tid >> 6;
   const int R = 1 << digit_bits;
   const uint32_t mask = (uint32_t)R - 1;
-  const int64_t P = live_pairs(status, cap);
+  const int64_t P = live_pairs(status, cap, st);
   const int64_t base = (int64_t)blockIdx.x * kSortTileItems;
   if (base >= P) return;  // uniform over the block
   if (tid < R) {
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                             uint32_t *vals_alt, const int64_t *status, int64_t cap, int key_bits,
                             int passes, int digit_bits, uint32_t *hist, uint32_t *hist_off,
-                            uint32_t *scan_tmp, hipStream_t s) {
+                            uint32_t *scan_tmp, hipStream_t s, bool status_semantics) {
   const int64_t nblocks = (cap + kSortTileItems - 1) / kSortTileItems;
   const int R = 1 << digit_bits;
   // pass p reads from src and writes to dst; with an odd pass count the data starts in alt
@@ -115,13 +116,14 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
     if (shift + bits > key_bits) bits = key_bits - shift;
     if (bits < 1) bits = 1;
     radix_upsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(src_k, status, cap, shift, bits,
-                                                                     hist, nblocks);
+                                                                     hist, nblocks,
+                                                                     status_semantics);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = scan_u32_to_u32(hist, hist_off, (int64_t)(1 << bits) * nblocks, scan_tmp, s);
     if (e != hipSuccess) return e;
     radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-        src_k, src_v, dst_k, dst_v, status, cap, shift, bits, hist_off, nblocks);
+        src_k, src_v, dst_k, dst_v, status, cap, shift, bits, hist_off, nblocks, status_semantics);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t *tk = src_k, *tv = src_v;

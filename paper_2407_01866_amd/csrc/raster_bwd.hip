@@ -47,8 +47,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *tot
 }
 
 struct BwdLds {
-  unsigned g, gc, aux, acc, cnt, off, cho, wave, item, total;
+  unsigned g, gc, aux, acc, cnt8, off, cho, owner, wave, tmp, item, total;
 };
+
+constexpr int kSub = 8;  // per-Gaussian counters are split by lane & 7 to spread LDS atomics
 
 // LDS layout of the adjoint kernel for K retained Gaussians per pixel (byte offsets; per-pixel
 // gradient rows are 16-byte aligned for float4 reads).
@@ -65,14 +67,18 @@ __host__ __device__ constexpr BwdLds bwd_lds(int K) {
   o += 8 * kRasterThreads;
   L.acc = o;
   o += 4 * kBatch * (5 + NC);
-  L.cnt = o;
-  o += 4 * kBatch;
+  L.cnt8 = o;
+  o += 4 * kBatch * kSub;
   L.off = o;
-  o += 4 * kBatch;
+  o += 4 * (kBatch + 4);
   L.cho = o;
   o += 4 * (kBatch + 4);
+  L.owner = o;
+  o += 2 * 2 * kBatch;
   L.wave = o;
   o += 16;
+  L.tmp = o;
+  o += 2 * kRasterThreads * (unsigned)K;
   L.item = o;
   o += 2 * kRasterThreads * (unsigned)K;
   L.total = (o + 15) & ~15u;
@@ -83,10 +89,11 @@ template <int NC>
 __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const double4 *__restrict__ g64,
-    const float *__restrict__ params, int N, int n, int H, int W, int K, int tiles_x, int T,
-    int64_t HW, const float *__restrict__ image, const float *__restrict__ grad_image,
-    const uint16_t *__restrict__ slots, const float2 *__restrict__ aux,
-    float *__restrict__ gamma, float *__restrict__ grad_params) {
+    const float *__restrict__ params, int N, int n, int K, int T, Images imgs,
+    const int *__restrict__ tile_order, const float *__restrict__ image_all,
+    const float *__restrict__ grad_image_all, const uint16_t *__restrict__ slots_all,
+    const float2 *__restrict__ aux_all, float *__restrict__ gamma,
+    float *__restrict__ grad_params) {
   constexpr int NCP = (NC + 3) & ~3;  // padded per-pixel gradient row
   constexpr int NACC = 5 + NC;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -95,19 +102,30 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
   float *s_gc = reinterpret_cast<float *>(smem + L.gc);            // [256 px] g . c_r
   float2 *s_aux = reinterpret_cast<float2 *>(smem + L.aux);        // [256 px] shift, 1/Z
   float *s_acc = reinterpret_cast<float *>(smem + L.acc);          // [kBatch][NACC]
-  int *s_cnt = reinterpret_cast<int *>(smem + L.cnt);              // [kBatch]
-  int *s_off = reinterpret_cast<int *>(smem + L.off);              // [kBatch]
-  int *s_cho = reinterpret_cast<int *>(smem + L.cho);              // [kBatch + 1]
+  int *s_cnt8 = reinterpret_cast<int *>(smem + L.cnt8);            // [kBatch][kSub]
+  int *s_off = reinterpret_cast<int *>(smem + L.off);              // [kBatch + 1] run starts
+  int *s_cho = reinterpret_cast<int *>(smem + L.cho);              // [kBatch + 1] chunk starts
+  uint16_t *s_owner = reinterpret_cast<uint16_t *>(smem + L.owner);  // [2 kBatch] chunk -> j
   int *s_wave = reinterpret_cast<int *>(smem + L.wave);            // [4]
+  uint16_t *s_tmp = reinterpret_cast<uint16_t *>(smem + L.tmp);    // [256 * K] j | rank << 8
   uint16_t *s_item = reinterpret_cast<uint16_t *>(smem + L.item);  // [256 * K] px | j << 8
 
   const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, T);
+  const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[blockIdx.x]
+                                                             : xcd_tile(blockIdx.x, T));
   const int2 rg = ranges[tile];
   const int start = __builtin_amdgcn_readfirstlane(rg.x);  // uniform over the workgroup
   const int cnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
   if (cnt <= 0) return;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const ImageDesc im = imgs.by_tile(tile);
+  const int W = im.W, H = im.H;
+  const int64_t HW = (int64_t)H * W;
+  const float *__restrict__ image = image_all + (int64_t)n * im.pix_off;
+  const float *__restrict__ grad_image = grad_image_all + (int64_t)n * im.pix_off;
+  const uint16_t *__restrict__ slots = slots_all + (int64_t)K * im.pix_off;
+  const float2 *__restrict__ aux = aux_all + im.pix_off;
+  const int lt = tile - im.tile_off;
+  const int tx = lt % im.tiles_x, ty = lt / im.tiles_x;
   const int x0 = tx * kTile, y0 = ty * kTile;
   const int px = x0 + (tid & (kTile - 1)), py = y0 + tid / kTile;
   const bool inside = px < W && py < H;
@@ -132,19 +150,31 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
   for (int base = 0; base < cnt; base += kBatch) {
     const int nb = min(kBatch, cnt - base);
     __syncthreads();  // previous batch fully consumed
-    s_cnt[tid] = 0;
+#pragma unroll
+    for (int c = 0; c < kSub; ++c) s_cnt8[tid * kSub + c] = 0;
 #pragma unroll
     for (int r = 0; r < NACC; ++r) s_acc[tid * NACC + r] = 0.f;
     __syncthreads();
 
-    // 1a: items per Gaussian of this batch
+    // 1a: count the items of every Gaussian of the batch; the returned count is the item's rank
+    // inside its (Gaussian, lane & 7) sub-run (at most 32 items: one per pixel of the class)
+    const int sub = tid & (kSub - 1);
     if (inside)
       for (int k = 0; k < K; ++k) {
         const int j = (int)slots[(int64_t)k * HW + pix] - base;
-        if (j >= 0 && j < nb) atomicAdd(&s_cnt[j], 1);
+        uint16_t e = 0xFFFF;
+        if (j >= 0 && j < nb) e = (uint16_t)(j | (atomicAdd(&s_cnt8[j * kSub + sub], 1) << 8));
+        s_tmp[tid * K + k] = e;
       }
     __syncthreads();
-    const int my_cnt = s_cnt[tid];  // tid indexes a Gaussian of the batch here
+    // Gaussian tid: its run (sub-runs in lane-class order), its chunks and its sub-run starts
+    int c8[kSub];
+    int my_cnt = 0;
+#pragma unroll
+    for (int c = 0; c < kSub; ++c) {
+      c8[c] = s_cnt8[tid * kSub + c];
+      my_cnt += c8[c];
+    }
     int total_items;
     const int my_off = block_exclusive_scan(my_cnt, s_wave, &total_items);
     // chunk length: about one chunk per lane
@@ -152,39 +182,68 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
     const int my_ch = (my_cnt + R - 1) / R;
     int total_chunks;
     const int my_cho = block_exclusive_scan(my_ch, s_wave, &total_chunks);
+    {
+      int o = my_off;
+#pragma unroll
+      for (int c = 0; c < kSub; ++c) {
+        s_cnt8[tid * kSub + c] = o;
+        o += c8[c];
+      }
+    }
     s_off[tid] = my_off;
     s_cho[tid] = my_cho;
-    s_cnt[tid] = my_off;  // becomes the fill cursor
-    if (tid == 0) s_cho[kBatch] = total_chunks;  // s_cho[j + 1] - s_cho[j] = chunks of j
+    for (int c = 0; c < my_ch; ++c) s_owner[my_cho + c] = (uint16_t)tid;
+    if (tid == 0) {
+      s_off[kBatch] = total_items;
+      s_cho[kBatch] = total_chunks;  // s_cho[j + 1] - s_cho[j] = chunks of j
+    }
     __syncthreads();
 
-    // 1b: group the items by Gaussian
+    // the lane's first chunk: fetch its Gaussian now so the loads overlap the placement below
+    const bool has0 = tid < total_chunks;
+    const int j0 = has0 ? (int)s_owner[tid] : 0;
+    const uint32_t gid0 = vals[start + base + j0];
+    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    double4 c640 = make_double4(0.0, 0.0, 0.0, 0.0);
+    float col0[NC];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) col0[ch] = 0.f;
+    if (has0) {
+      a0 = g32a[gid0];
+      c640 = g64[gid0];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch)
+        if (ch < n) col0[ch] = params[(size_t)(5 + ch) * N + gid0];
+    }
+
+    // 1b: place every item in its Gaussian's run
     if (inside)
       for (int k = 0; k < K; ++k) {
-        const int j = (int)slots[(int64_t)k * HW + pix] - base;
-        if (j >= 0 && j < nb) s_item[atomicAdd(&s_cnt[j], 1)] = (uint16_t)(tid | (j << 8));
+        const uint16_t e = s_tmp[tid * K + k];
+        if (e != 0xFFFF) {
+          const int j = e & 0xFF;
+          s_item[s_cnt8[j * kSub + sub] + (e >> 8)] = (uint16_t)(tid | (j << 8));
+        }
       }
     __syncthreads();
 
     // 2: chunks of one Gaussian each, accumulated in registers
     for (int c = tid; c < total_chunks; c += kRasterThreads) {
-      // the Gaussian owning chunk c: the last j with s_cho[j] <= c
-      int lo = 0, hi = nb - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_cho[mid] <= c) lo = mid;
-        else hi = mid - 1;
-      }
-      const int j = lo;
+      const int j = c == tid ? j0 : (int)s_owner[c];
       const int first = s_off[j] + (c - s_cho[j]) * R;
-      const int run_end = j + 1 < kBatch ? s_off[j + 1] : total_items;
-      const int end = min(first + R, run_end);
-      const uint32_t gid = vals[start + base + j];
-      const float4 a = g32a[gid];
-      const double4 c64 = g64[gid];
+      const int end = min(first + R, s_off[j + 1]);
+      float4 a = a0;
+      double4 c64 = c640;
       float cj[NC];
 #pragma unroll
-      for (int ch = 0; ch < NC; ++ch) cj[ch] = ch < n ? params[(size_t)(5 + ch) * N + gid] : 0.f;
+      for (int ch = 0; ch < NC; ++ch) cj[ch] = col0[ch];
+      if (c != tid) {
+        const uint32_t gid = vals[start + base + j];
+        a = g32a[gid];
+        c64 = g64[gid];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) cj[ch] = ch < n ? params[(size_t)(5 + ch) * N + gid] : 0.f;
+      }
       float G1 = 0.f, G2 = 0.f, G11 = 0.f, G22 = 0.f, G12 = 0.f;
       float gcol[NC];
 #pragma unroll
@@ -243,7 +302,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
 
     // 3: one global add per (Gaussian, component) of this batch
     if (tid < nb && my_cnt > 0) {
-      const uint32_t gid = vals[start + base + tid];
+      const uint32_t gid = vals[start + base + tid];  // Gaussian tid of the batch
       const float *row = &s_acc[tid * NACC];
 #pragma unroll
       for (int r = 0; r < 5; ++r) unsafeAtomicAdd(&gamma[(size_t)r * N + gid], row[r]);
@@ -275,10 +334,10 @@ __global__ __launch_bounds__(256) void grad_finalize_kernel(const float *__restr
 
 template <int NC>
 hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
-                         const float2 *g32b, const double4 *g64, const float *params,
-                         const Dims &d, const float *image, const float *grad_image,
-                         const uint16_t *slots, const float2 *aux, float *gamma,
-                         float *grad_params, hipStream_t s) {
+                         const double4 *g64, const float *params, const Dims &d,
+                         const Images &imgs, const int *tile_order, const float *image,
+                         const float *grad_image, const uint16_t *slots, const float2 *aux,
+                         float *gamma, float *grad_params, hipStream_t s) {
   const size_t lds = bwd_lds<NC>(d.K).total;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)raster_bwd_kernel<NC>,
@@ -286,9 +345,9 @@ hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 
     if (e != hipSuccess) return e;
   }
   raster_bwd_kernel<NC><<<d.T, kRasterThreads, lds, s>>>(ranges, vals, g32a, g64, params, d.N,
-                                                          d.n, d.H, d.W, d.K, d.tiles_x, d.T,
-                                                          d.HW, image, grad_image, slots, aux,
-                                                          gamma, grad_params);
+                                                          d.n, d.K, d.T, imgs, tile_order, image,
+                                                          grad_image, slots, aux, gamma,
+                                                          grad_params);
   return hipGetLastError();
 }
 
@@ -296,13 +355,14 @@ hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 
 
 hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
-                             const Dims &d, const float *image, const float *grad_image,
-                             const uint16_t *slots, const float2 *aux, float *gamma,
-                             float *grad_params, hipStream_t s) {
+                             const Dims &d, const Images &imgs, const int *tile_order,
+                             const float *image, const float *grad_image, const uint16_t *slots,
+                             const float2 *aux, float *gamma, float *grad_params, hipStream_t s) {
+  (void)g32b;
 #define IGS_BWD_NC(NCV)                                                                        \
   if (d.n <= NCV)                                                                              \
-    return launch_bwd_nc<NCV>(ranges, vals, g32a, g32b, g64, params, d, image, grad_image,     \
-                              slots, aux, gamma, grad_params, s);
+    return launch_bwd_nc<NCV>(ranges, vals, g32a, g64, params, d, imgs, tile_order, image,     \
+                              grad_image, slots, aux, gamma, grad_params, s);
   IGS_BWD_NC(1)
   IGS_BWD_NC(3)
   IGS_BWD_NC(4)

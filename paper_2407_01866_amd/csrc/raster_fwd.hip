@@ -44,9 +44,9 @@ template <int KT>
 __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
-    const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n, int H,
-    int W, int K, int tiles_x, int T, int64_t HW, float *__restrict__ image,
-    uint16_t *__restrict__ slots, float2 *__restrict__ aux) {
+    const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n, int K, int T,
+    Images imgs, const int *__restrict__ tile_order, float *__restrict__ image_all,
+    uint16_t *__restrict__ slots_all, float2 *__restrict__ aux_all) {
   extern __shared__ __align__(16) unsigned char smem[];
   float4 *s_geo = reinterpret_cast<float4 *>(smem);                    // mu_x, mu_y, A, B
   float2 *s_cd = reinterpret_cast<float2 *>(smem + 16 * kBatch);       // C, D
@@ -54,8 +54,16 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
   float *s_col = reinterpret_cast<float *>(smem + 56 * kBatch);        // [n][kBatch]
 
   const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, T);
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[blockIdx.x]
+                                                             : xcd_tile(blockIdx.x, T));
+  const ImageDesc im = imgs.by_tile(tile);
+  const int W = im.W, H = im.H;
+  const int64_t HW = (int64_t)H * W;
+  float *__restrict__ image = image_all + (int64_t)n * im.pix_off;
+  uint16_t *__restrict__ slots = slots_all + (int64_t)K * im.pix_off;
+  float2 *__restrict__ aux = aux_all + im.pix_off;
+  const int lt = tile - im.tile_off;
+  const int tx = lt % im.tiles_x, ty = lt / im.tiles_x;
   const int px = tx * kTile + (tid & (kTile - 1)), py = ty * kTile + tid / kTile;
   const bool inside = px < W && py < H;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
@@ -181,16 +189,15 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
 
 hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
-                             const Dims &d, float *image, uint16_t *slots, float2 *aux,
-                             int64_t *status, hipStream_t s) {
+                             const Dims &d, const Images &imgs, const int *tile_order,
+                             float *image, uint16_t *slots, float2 *aux, hipStream_t s) {
   const size_t lds = 56 * kBatch + (size_t)d.n * kBatch * sizeof(float);
   const int kt = pick_kt(d.K);
 #define IGS_LAUNCH_FWD(KTV)                                                                    \
   if (kt == KTV) {                                                                             \
     raster_fwd_kernel<KTV><<<d.T, kRasterThreads, lds, s>>>(ranges, vals, g32a, g32b, g64,     \
-                                                            params, d.N, d.n, d.H, d.W, d.K,   \
-                                                            d.tiles_x, d.T, d.HW, image,       \
-                                                            slots, aux);                       \
+                                                            params, d.N, d.n, d.K, d.T, imgs,  \
+                                                            tile_order, image, slots, aux);    \
     return hipGetLastError();                                                                  \
   }
   IGS_FOR_EACH_KT(IGS_LAUNCH_FWD)

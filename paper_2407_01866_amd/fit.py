@@ -31,7 +31,80 @@ class AdamConfig:
     inv_scale_hi: float = 4.0       # 1/s <= 4, i.e. s >= 0.25 px; 1/s >= 1/max(H, W)
 
 
-class PlainFitter:
+class _FitLoop:
+    """Iteration bookkeeping shared by the plain and batched fitters: graph capture, the device
+    step counter, and repetition of iterations whose render overflowed the pair buffer."""
+
+    graph = None
+
+    def capture(self) -> None:
+        """Capture one iteration as a HIP graph (the library allocates nothing, so buffers and
+        kernel arguments stay valid across replays)."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step_async()
+        self.graph = g
+
+    def step(self) -> None:
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self.step_async()
+
+    def status(self) -> torch.Tensor:
+        """Status block of the last render (synchronizes)."""
+        self.status_host.copy_(self.r.status_of(self.saved))
+        return self.status_host
+
+    def steps_done(self) -> int:
+        return int(self.step_count.item())
+
+    def grow(self, factor: float = 1.5) -> None:
+        """Enlarge the pair buffer to ``factor`` times the larger of the current capacity and the
+        last render's requirement; drops the captured graph (it is re-captured on demand)."""
+        st = self.status()
+        need = max(self.r.cap, int(st[nat.STAT_PAIRS]))
+        self.r.set_capacity(int(need * factor) + 1024)
+        self.saved = self.r.new_saved()
+        self.graph = None
+
+    def advance_to(self, target: int, use_graph: bool = True, max_rounds: int = 8) -> None:
+        """Run iterations until exactly ``target`` have been applied (skipped ones repeat)."""
+        for _ in range(max_rounds):
+            missing = target - self.steps_done()
+            if missing <= 0:
+                return
+            if use_graph and self.graph is None:
+                self.capture()
+            for _ in range(missing):
+                self.step() if use_graph else self.step_async()
+            if self.steps_done() < target:
+                self.grow()
+        raise RuntimeError("pair buffer kept overflowing")
+
+    def run(self, iters: int, report_every: int = 100, use_graph: bool = True):
+        """Fit for ``iters`` iterations; returns (iteration, PSNR of that iteration's render)
+        every ``report_every`` iterations (and at the last)."""
+        start = self.steps_done()
+        out = []
+        it = 0
+        while it < iters:
+            it = min(iters, (it // report_every + 1) * report_every)
+            self.advance_to(start + it, use_graph)
+            out.append((it, self.psnr()))
+        return out
+
+    def _overflow_word(self) -> torch.Tensor:
+        return self.r.status_of(self.saved)[nat.STAT_OVERFLOW:nat.STAT_OVERFLOW + 1]
+
+    def snapshot(self) -> dict:
+        return self.state_dict()
+
+    def restore(self, sd: dict) -> None:
+        self.load_state_dict(sd)
+
+
+class PlainFitter(_FitLoop):
     """Fits one image.  ``render_params`` is the initial [5+n][N] float32 set in pixel units."""
 
     def __init__(self, target: torch.Tensor, render_params: torch.Tensor, K: int = 10,
@@ -88,78 +161,11 @@ class PlainFitter:
                           a.lr_color, a.beta1, a.beta2, a.eps, 1.0 / max(self.H, self.W),
                           a.inv_scale_hi, skip_flag=self._overflow_word())
 
-    def _overflow_word(self) -> torch.Tensor:
-        return self.r.status_of(self.saved)[nat.STAT_OVERFLOW:nat.STAT_OVERFLOW + 1]
-
-    def capture(self) -> None:
-        """Capture one iteration as a HIP graph (the library allocates nothing, so buffers and
-        kernel arguments stay valid across replays)."""
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.step_async()
-        self.graph = g
-
-    def step(self) -> None:
-        if self.graph is not None:
-            self.graph.replay()
-        else:
-            self.step_async()
-
     # --------------------------------------------------------------------------- bookkeeping
-
-    def status(self) -> torch.Tensor:
-        """Status block of the last render (synchronizes)."""
-        self.status_host.copy_(self.r.status_of(self.saved))
-        return self.status_host
-
-    def steps_done(self) -> int:
-        return int(self.step_count.item())
-
-    def grow(self, factor: float = 1.5) -> None:
-        """Enlarge the pair buffer to ``factor`` times the larger of the current capacity and the
-        last render's requirement; drops the captured graph (it is re-captured on demand)."""
-        st = self.status()
-        need = max(self.r.cap, int(st[nat.STAT_PAIRS]))
-        self.r.set_capacity(int(need * factor) + 1024)
-        self.saved = self.r.new_saved()
-        self.graph = None
-
-    def advance_to(self, target: int, use_graph: bool = True, max_rounds: int = 8) -> None:
-        """Run iterations until exactly ``target`` have been applied (skipped ones repeat)."""
-        for _ in range(max_rounds):
-            missing = target - self.steps_done()
-            if missing <= 0:
-                return
-            if use_graph and self.graph is None:
-                self.capture()
-            for _ in range(missing):
-                self.step() if use_graph else self.step_async()
-            if self.steps_done() < target:
-                self.grow()
-        raise RuntimeError("pair buffer kept overflowing")
 
     def psnr(self) -> float:
         mse = float(self.loss[1].item())
         return 10.0 * math.log10(1.0 / mse) if mse > 0 else math.inf
-
-    def run(self, iters: int, report_every: int = 100, use_graph: bool = True
-            ) -> List[Tuple[int, float]]:
-        """Fit for ``iters`` iterations; returns (iteration, PSNR of that iteration's render)
-        every ``report_every`` iterations (and at the last)."""
-        start = self.steps_done()
-        out = []
-        it = 0
-        while it < iters:
-            it = min(iters, (it // report_every + 1) * report_every)
-            self.advance_to(start + it, use_graph)
-            out.append((it, self.psnr()))
-        return out
-
-    def snapshot(self) -> dict:
-        return self.state_dict()
-
-    def restore(self, sd: dict) -> None:
-        self.load_state_dict(sd)
 
     def state_dict(self) -> dict:
         return {"fit": self.fit.clone(), "m": self.m.clone(), "v": self.v.clone(),
@@ -171,3 +177,83 @@ class PlainFitter:
         self.v.copy_(sd["v"])
         self.step_count.copy_(sd["step"])
         nat.igs_fit_to_render(self.fit, self.rend, self.N, self.n, self.H, self.W)
+
+
+class BatchFitter(_FitLoop):
+    """Fits many images of uneven size and Gaussian count at once: every iteration is one batched
+    render, one batched L1 gradient, one batched adjoint and one batched Adam step (one launch per
+    phase over all images), captured as one HIP graph.  Each image is fitted exactly as a
+    ``PlainFitter`` would fit it alone."""
+
+    def __init__(self, targets: List[torch.Tensor], render_params: List[torch.Tensor], K: int = 10,
+                 adam: Optional[AdamConfig] = None, headroom: float = 1.25,
+                 pair_capacity: Optional[int] = None, device=None):
+        from .render import BatchRenderer
+        self.dev = torch.device(device) if device is not None else targets[0].device
+        self.n = int(targets[0].shape[0])
+        self.K = K
+        self.adam = adam or AdamConfig()
+        sizes = [(int(t.shape[1]), int(t.shape[2]), int(p.shape[1]))
+                 for t, p in zip(targets, render_params)]
+        self.r = BatchRenderer(sizes, self.n, K, pair_capacity=pair_capacity, device=self.dev)
+        self.B, self.N = self.r.B, self.r.N
+        self.target = self.r.pack_images(targets)
+        rend = self.r.pack_params(render_params)
+        # fitter parameterization: mean / (W, H) of its own image, inverse scales
+        self.fit = rend.clone()
+        for (H, W, N), go in zip(sizes, self.r.gauss_off):
+            self.fit[0, go:go + N] /= W
+            self.fit[1, go:go + N] /= H
+        self.fit[3:5] = 1.0 / self.fit[3:5]
+        self.rend = torch.empty_like(self.fit)
+        nat.igs_fit_to_render_batched(self.fit, self.rend, self.r.descs, self.r.d_descs, self.n)
+        self.m = torch.zeros_like(self.fit)
+        self.v = torch.zeros_like(self.fit)
+        self.step_count = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.image = self.r.new_images()
+        self.grad_image = torch.empty_like(self.image)
+        self.grad_params = torch.empty_like(self.fit)
+        self.loss = torch.zeros((self.B, 2), dtype=torch.float64, device=self.dev)
+        self.l1_ws = _aligned_bytes(nat.igs_l1_batched_workspace_size(self.r.descs, self.n), self.dev)
+        if pair_capacity is None:
+            _, saved = self.r.render(self.rend)
+            P = int(self.r.status_of(saved)[nat.STAT_PAIRS])
+            self.r.set_capacity(max(1024, int(P * headroom)))
+        self.saved = self.r.new_saved()
+        self.graph = None
+        self.status_host = torch.zeros(8, dtype=torch.int64).pin_memory()
+
+    def step_async(self) -> None:
+        a = self.adam
+        r = self.r
+        r.render_into(self.rend, self.image, self.saved)
+        nat.igs_l1_loss_grad_batched(self.image, self.target, r.descs, r.d_descs, self.n,
+                                     self.grad_image, self.loss, self.l1_ws, self.l1_ws.numel())
+        r.backward_into(self.rend, self.image, self.grad_image, self.saved, self.grad_params)
+        nat.igs_adam_step_batched(self.fit, self.rend, self.grad_params, self.m, self.v,
+                                  self.step_count, r.descs, r.d_descs, self.n, a.lr_mu, a.lr_theta,
+                                  a.lr_inv_scale, a.lr_color, a.beta1, a.beta2, a.eps,
+                                  a.inv_scale_hi, skip_flag=self._overflow_word())
+
+    def psnrs(self) -> List[float]:
+        mse = self.loss[:, 1].cpu().tolist()
+        return [10.0 * math.log10(1.0 / m) if m > 0 else math.inf for m in mse]
+
+    def psnr(self) -> float:
+        """Mean PSNR over the batch (per-image values: ``psnrs``)."""
+        return sum(self.psnrs()) / self.B
+
+    def image_params(self, b: int) -> torch.Tensor:
+        go, N = self.r.gauss_off[b], self.r.sizes[b][2]
+        return self.rend[:, go:go + N]
+
+    def state_dict(self) -> dict:
+        return {"fit": self.fit.clone(), "m": self.m.clone(), "v": self.v.clone(),
+                "step": self.step_count.clone(), "sizes": list(self.r.sizes), "K": self.K}
+
+    def load_state_dict(self, sd: dict) -> None:
+        self.fit.copy_(sd["fit"])
+        self.m.copy_(sd["m"])
+        self.v.copy_(sd["v"])
+        self.step_count.copy_(sd["step"])
+        nat.igs_fit_to_render_batched(self.fit, self.rend, self.r.descs, self.r.d_descs, self.n)

@@ -177,3 +177,98 @@ class RenderFn(torch.autograd.Function):
         d_inv = (-gp[3:5] / (inv_scales.T * inv_scales.T)).T      # dL/du = -s^2 dL/ds
         d_colors = gp[5:].T.contiguous()
         return d_means, d_theta, d_inv.contiguous(), d_colors, None, None, None
+
+
+class BatchRenderer:
+    """Device buffers for rendering a batch of images of uneven size and Gaussian count with one
+    launch per phase.  ``sizes`` is a list of (H, W, N); parameters are the concatenation of the
+    images' [5+n][N_b] sets along the Gaussian axis; images are concatenated planar blocks (see
+    ``image_views``)."""
+
+    def __init__(self, sizes, n: int, K: int = 10, pair_capacity: Optional[int] = None,
+                 device="cuda"):
+        self.sizes = [tuple(int(v) for v in s) for s in sizes]
+        self.n, self.K, self.B = n, K, len(self.sizes)
+        self.device = torch.device(device)
+        H = [s[0] for s in self.sizes]
+        W = [s[1] for s in self.sizes]
+        N = [s[2] for s in self.sizes]
+        self.descs, (self.N, self.T, self.P, self.loss_blocks) = nat.igs_batch_describe(H, W, N, n)
+        self.d_descs = nat.descs_to_device(self.descs, self.device)
+        self.gauss_off = [d.gauss_off for d in self.descs]
+        self.pix_off = [d.pix_off for d in self.descs]
+        self.cap = int(pair_capacity or initial_pair_capacity(self.N, 0, 0))
+        self._alloc()
+
+    def _alloc(self):
+        self.ws_bytes, self.saved_bytes = nat.igs_batch_buffer_sizes(self.descs, self.n, self.K,
+                                                                     self.cap)
+        self.offsets = nat.igs_batch_saved_offsets(self.descs, self.n, self.K, self.cap)
+        self.ws = _aligned_bytes(self.ws_bytes, self.device)
+
+    def set_capacity(self, cap: int) -> None:
+        if cap != self.cap:
+            self.cap = int(cap)
+            self._alloc()
+
+    def new_saved(self) -> torch.Tensor:
+        return _aligned_bytes(self.saved_bytes, self.device)
+
+    def new_images(self) -> torch.Tensor:
+        return torch.empty(self.n * self.P, dtype=torch.float32, device=self.device)
+
+    def image_views(self, flat: torch.Tensor):
+        """[n][H][W] views of each image inside a concatenated buffer."""
+        out = []
+        for (H, W, _), po in zip(self.sizes, self.pix_off):
+            out.append(flat[self.n * po:self.n * (po + H * W)].view(self.n, H, W))
+        return out
+
+    def pack_images(self, images) -> torch.Tensor:
+        return torch.cat([im.reshape(-1) for im in images]).to(self.device, torch.float32).contiguous()
+
+    def pack_params(self, params_list) -> torch.Tensor:
+        return torch.cat([torch.as_tensor(p) for p in params_list], dim=1).to(
+            self.device, torch.float32).contiguous()
+
+    def render_into(self, params, images, saved) -> None:
+        nat.igs_render_batched(params, self.descs, self.d_descs, self.n, self.K, self.cap, images,
+                               saved, saved.numel(), self.ws, self.ws.numel())
+
+    def backward_into(self, params, images, grad_images, saved, grad_params) -> None:
+        nat.igs_render_backward_batched(params, self.descs, self.d_descs, self.n, self.K, self.cap,
+                                        images, grad_images, saved, saved.numel(), grad_params,
+                                        self.ws, self.ws.numel())
+
+    def status_of(self, saved: torch.Tensor) -> torch.Tensor:
+        return saved[:64].view(torch.int64)
+
+    def render(self, params, keep_state=True):
+        images = self.new_images()
+        for _ in range(2):
+            saved = self.new_saved()
+            self.render_into(params, images, saved)
+            st = self.status_of(saved).cpu()
+            if int(st[nat.STAT_OVERFLOW]) == 0:
+                return images, saved
+            self.set_capacity(int(int(st[nat.STAT_PAIRS]) * 1.25) + 1024)
+        raise RuntimeError("pair capacity overflow persisted after resizing")
+
+    def tile_lists(self, saved):
+        o = self.offsets
+        P = int(self.status_of(saved)[nat.STAT_PAIRS])
+        ranges = saved[o["ranges"]:o["ranges"] + 8 * self.T].view(torch.int32).view(self.T, 2)
+        vals = saved[o["vals"]:o["vals"] + 4 * min(P, self.cap)].view(torch.int32)
+        return ranges, vals
+
+    def tile_queue(self, saved) -> torch.Tensor:
+        o = self.offsets
+        return saved[o["order"]:o["order"] + 4 * self.T].view(torch.int32)
+
+    def slots(self, saved):
+        """Per image: slots int32 [K][H][W] (-1 unused)."""
+        o = self.offsets
+        raw = saved[o["slots"]:o["slots"] + 2 * self.K * self.P].view(torch.int16).to(torch.int32) & 0xFFFF
+        raw = torch.where(raw == 0xFFFF, torch.full_like(raw, -1), raw)
+        return [raw[self.K * po:self.K * (po + H * W)].view(self.K, H, W)
+                for (H, W, _), po in zip(self.sizes, self.pix_off)]

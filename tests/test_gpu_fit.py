@@ -76,14 +76,22 @@ def test_first_step_matches_reference_pipeline():
 
 
 def test_checkpoint_resume_reproduces_next_report():
+    """Resuming from a checkpoint continues the same trajectory.  The adjoint sums with float
+    atomics, whose order varies between runs, and Adam amplifies such last-bit differences in
+    near-zero gradient entries, so the comparison allows 0.02 dB; a fitter that did not load the
+    state is far off."""
     f, w = make_fitter(0)
     f.run(60, report_every=60, use_graph=False)
     sd = f.state_dict()
     a = f.run(40, report_every=40, use_graph=False)[-1][1]
     g, _ = make_fitter(0)
     g.load_state_dict(sd)
+    assert g.steps_done() == 60
     b = g.run(40, report_every=40, use_graph=False)[-1][1]
-    assert a == pytest.approx(b, abs=2e-3)
+    assert a == pytest.approx(b, abs=0.02)
+    h, _ = make_fitter(0)
+    c = h.run(40, report_every=40, use_graph=False)[-1][1]
+    assert abs(c - a) > 0.5
 
 
 def test_phase_timers_record_every_phase():
