@@ -127,6 +127,146 @@ def paper_context(torch, dev, K=10):
     return out
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_raster_texture-2048x2048-n9-N100000.txt")
+KERNEL_SOURCES = {"raster_fwd": "raster_fwd.hip", "raster_bwd": "raster_bwd.hip"}
+PROFILE_CMDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- "
+             "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'raster|elementwise' -f csv "
+             "-d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --steps 3 --warmup 1 "
+             "--no-cpu-baseline --no-context --batch-iters 0",
+    "write": "rocprofv3 --pmc WRITE_SIZE (otherwise as fetch) -d gpurun_out/pmc_write -o write",
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_copy_fetch -o cf -- "
+                  "python3 bench.py --copy-calibration",
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_copy_write -o cw -- "
+                  "python3 bench.py --copy-calibration",
+}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2407_01866_amd", "csrc", KERNEL_SOURCES[kernel])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def summarize_profiles(out_dir):
+    """Write the committed text summaries of a profiling run (rocprofv3 CSVs under out_dir)."""
+    import csv
+    import collections
+    os.makedirs(PROFILES, exist_ok=True)
+    rows = list(csv.DictReader(open(os.path.join(out_dir, "prof_trace", "trace_kernel_stats.csv"))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Kernel trace: fitting iteration, texture-2048x2048-n9-N100000 (2048^2, n=9, "
+             "N=100k, K=10)", "", "Command (run from the repository root on the GPU box):", "",
+             "    " + PROFILE_CMDS["trace"], "",
+             "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows[:20]:
+        name = r["Name"].replace("igs::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        lines.append(f"| {name} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    open(os.path.join(PROFILES, "kernel_trace_texture-2048x2048-n9-N100000.md"), "w").write(
+        "\n".join(lines) + "\n")
+
+    def counter(sub, fname):
+        d = collections.defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(out_dir, sub, fname))):
+            d[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in d.items()}
+
+    cf = counter("pmc_copy_fetch", "cf_counter_collection.csv")
+    cw = counter("pmc_copy_write", "cw_counter_collection.csv")
+    copy_bytes = float(1 << 30)
+    f_factor = copy_bytes / (1024.0 * max(v for k, v in cf.items() if "copy" in k.lower()))
+    w_factor = copy_bytes / (1024.0 * max(v for k, v in cw.items() if "copy" in k.lower()))
+    fetch = counter("pmc_fetch", "fetch_counter_collection.csv")
+    write = counter("pmc_write", "write_counter_collection.csv")
+    out = ["# HBM traffic of the raster kernels, texture-2048x2048-n9-N100000 (per dispatch)",
+           "# FETCH_SIZE and WRITE_SIZE (KiB) from separate rocprofv3 --pmc passes, scaled by what the",
+           "# same counters read for the runtime's copy of 1 GiB (bytes per counted KiB below).",
+           "# commands: " + PROFILE_CMDS["fetch"], "#           " + PROFILE_CMDS["write"],
+           "#           " + PROFILE_CMDS["copy_fetch"], "#           " + PROFILE_CMDS["copy_write"],
+           f"copy_calibration fetch_bytes_per_kib {f_factor * 1024:.1f} write_bytes_per_kib {w_factor * 1024:.1f}"]
+    for kern in ("raster_fwd", "raster_bwd"):
+        fk = [v for k, v in fetch.items() if kern in k]
+        wk = [v for k, v in write.items() if kern in k]
+        if not fk or not wk:
+            continue
+        rb, wb = fk[0] * 1024 * f_factor, wk[0] * 1024 * w_factor
+        out.append(f"kernel {kern} source_sha256 {kernel_source_hash(kern)} fetch_kib {fk[0]:.1f} "
+                   f"write_kib {wk[0]:.1f} read_bytes {rb:.4g} write_bytes {wb:.4g} "
+                   f"traffic_bytes {rb + wb:.4g}")
+    open(TRAFFIC_FILE, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, or None when the kernel's source
+    has changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        f = line.split()
+        if len(f) > 2 and f[0] == "kernel" and f[1] == kernel:
+            kv = dict(zip(f[2::2], f[3::2]))
+            if kv.get("source_sha256") != kernel_source_hash(kernel):
+                return None
+            return float(kv["traffic_bytes"])
+    return None
+
+
+def timed_fit(fitter, iters, torch):
+    """Untimed dry run of the trajectory (sizes the pair buffer), then the same iterations replayed
+    from the initial state as one captured graph each; returns seconds."""
+    init = fitter.snapshot()
+    fitter.advance_to(iters, use_graph=True)
+    fitter.restore(init)
+    if fitter.graph is None:
+        fitter.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        fitter.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if fitter.steps_done() != iters:
+        raise RuntimeError("an iteration overflowed the pair buffer during a timed fit")
+    return dt
+
+
+def batched_vs_plain(torch, dev, iters, count=64):
+    """Uneven batch (H, W in {256, 512, 1024, 2048}, 5k-80k Gaussians): one BatchFitter vs the
+    same images fitted one after another by graph-captured PlainFitters."""
+    from paper_2407_01866_amd import synth
+    from paper_2407_01866_amd.fit import BatchFitter, PlainFitter
+    wl = synth.batch_workloads(count)
+    log(f"[bench] batch of {count} images: generating inputs")
+    targets = [torch.from_numpy(w.target()).to(dev) for w in wl]
+    params = [torch.from_numpy(w.gaussians()).to(dev) for w in wl]
+    bf = BatchFitter(targets, params, 10)
+    t_batch = timed_fit(bf, iters, torch)
+    p_batch = bf.psnrs()
+    del bf
+    log(f"[bench] batched: {t_batch:.3f} s for {iters} iterations; sequential plain fits")
+    t_plain, p_plain = 0.0, []
+    for t, p in zip(targets, params):
+        pf = PlainFitter(t, p, 10)
+        t_plain += timed_fit(pf, iters, torch)
+        p_plain.append(pf.psnr())
+        del pf
+    dps = [abs(a - b) for a, b in zip(p_batch, p_plain)]
+    pixels = sum(w.H * w.W for w in wl)
+    return {"images": count, "iterations": iters, "pixels": pixels,
+            "gaussians": sum(w.N for w in wl),
+            "batched_s": round(t_batch, 4), "sequential_plain_s": round(t_plain, 4),
+            "batched_images_per_s": count / t_batch, "plain_images_per_s": count / t_plain,
+            "speedup": t_plain / t_batch,
+            "mean_psnr_batched": sum(p_batch) / count, "mean_psnr_plain": sum(p_plain) / count,
+            "max_abs_dpsnr": max(dps), "mean_abs_dpsnr": sum(dps) / count,
+            "psnr_match": max(dps) <= 0.1 and sum(dps) / count <= 0.02}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,9 +275,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--batch-iters", type=int, default=100,
+                    help="iterations of the batched-vs-plain comparison (0 skips it)")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from a rocprofv3 output directory and exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
               "on a single MI355X; see the sharding notes in the design document)", file=sys.stderr)
@@ -223,7 +371,7 @@ def main():
     fwdbwd_ms = avg["binning"] + avg["raster_fwd"] + avg["loss"] + avg["raster_bwd"]
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
-                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": measured_traffic(dom),
                 "avg_ms": round(avg[dom], 4),
                 "work_per_launch": f"{ops[dom]:.4g} VALU lane-ops"}
 
@@ -233,6 +381,9 @@ def main():
         g = fitter.grad_image.double().cpu().numpy()
         cpu = cpu_baseline(w.gaussians(), w.H, w.W, w.K, g, args.cpu_budget)
     ctx = None if args.no_context else paper_context(torch, dev)
+    batch = None
+    if args.batch_iters > 0:
+        batch = batched_vs_plain(torch, dev, args.batch_iters, args.batch_count)
 
     out = {
         "metric": METRIC, "value": value, "unit": "Gaussian-pixel evals/s", "n_gpus": 1,
@@ -247,6 +398,7 @@ def main():
         "E_fwd": e_fwd, "E_bwd": e_bwd, "pairs": pairs,
         "E_fwd_first_last": [evals[args.warmup][0], evals[-1][0]],
         "roofline": roofline, "cpu_baseline": cpu, "paper_context": ctx,
+        "batched_vs_plain": batch,
     }
     print(json.dumps(out), flush=True)
 
