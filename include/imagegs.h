@@ -132,6 +132,40 @@ igs_status igs_render_backward(const float *params, int32_t N, int32_t n, int32_
                                size_t saved_bytes, float *grad_params, void *workspace,
                                size_t ws_bytes, void *stream);
 
+/*
+ * Forward render fused with the L1 term of the fitting loss (Sec. 3.2 / Eq. 5 and Sec. 3.3,
+ * Sec. 4.1), for a fitting iteration whose loss is the mean absolute error.  Renders exactly as
+ * igs_render, and in the same pass compares every pixel with the target:
+ *   target    [n][H][W] float32
+ *   image     [n][H][W] float32 output, identical to igs_render's
+ *   loss_out  device double[2]: [0] mean |image - target|, [1] mean (image - target)^2 (as
+ *             igs_l1_loss_grad; sums are taken per tile, then over tiles in a fixed order)
+ *   saved     required: besides igs_render's state it receives, per pixel, the signs of
+ *             image - target and g . c_r with g = sign(image - target) / (n*H*W), which is all
+ *             igs_render_backward_l1 needs from the loss
+ *   workspace / sizes: as igs_render (igs_render_buffer_sizes covers this call)
+ * n must be <= 16 (two bits per channel in the per-pixel record).
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_UNSUPPORTED (n > 16 or tile size), IGS_ERR_WORKSPACE,
+ *         IGS_ERR_HIP.
+ */
+igs_status igs_render_l1(const float *params, int32_t N, int32_t n, int32_t H, int32_t W, int32_t K,
+                         int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                         const float *target, float *image, double *loss_out, void *saved,
+                         size_t saved_bytes, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of igs_render_l1 (Sec. 3.3): the gradient of the mean absolute error with respect to
+ * the parameters, through the K retained Gaussians, with the selection held fixed.  Gives the
+ * same result as igs_l1_loss_grad followed by igs_render_backward, without the gradient image.
+ *   saved        the state written by igs_render_l1 (not igs_render) for the same arguments
+ *   grad_params  [5+n][N] float32 output, overwritten
+ * Errors: as igs_render_l1.
+ */
+igs_status igs_render_backward_l1(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
+                                  int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                                  const void *saved, size_t saved_bytes, float *grad_params,
+                                  void *workspace, size_t ws_bytes, void *stream);
+
 /* Scratch bytes igs_l1_loss_grad needs for an image of count = n*H*W values. */
 igs_status igs_l1_workspace_size(int64_t count, size_t *ws_bytes);
 
@@ -227,6 +261,25 @@ igs_status igs_render_backward_batched(const float *params, const igs_image_desc
                                        const float *grad_images, const void *saved,
                                        size_t saved_bytes, float *grad_params, void *workspace,
                                        size_t ws_bytes, void *stream);
+
+/*
+ * igs_render_l1 for a batch: targets are concatenated like the images; loss_out is device
+ * double[B][2] (per image: mean |d| and mean d^2 over its own n*H_b*W_b values, d = image -
+ * target), and the gradient of image b's loss is normalized by its own n*H_b*W_b, so each image
+ * is fitted exactly as it would be alone.  n <= 16.
+ */
+igs_status igs_render_l1_batched(const float *params, const igs_image_desc *descs_host,
+                                 const igs_image_desc *descs_dev, int32_t B, int32_t n, int32_t K,
+                                 int64_t pair_capacity, const float *targets, float *images,
+                                 double *loss_out, void *saved, size_t saved_bytes,
+                                 void *workspace, size_t ws_bytes, void *stream);
+
+/* Adjoint of igs_render_l1_batched; grad_params [5+n][Ntot] is overwritten. */
+igs_status igs_render_backward_l1_batched(const float *params, const igs_image_desc *descs_host,
+                                          const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                          int32_t K, int64_t pair_capacity, const void *saved,
+                                          size_t saved_bytes, float *grad_params, void *workspace,
+                                          size_t ws_bytes, void *stream);
 
 /* L1 term per image (each normalized by its own n*H*W); loss_out is device double[B][2]
    (mean |d|, mean d^2 per image).  Deterministic.  Errors: as igs_l1_loss_grad. */

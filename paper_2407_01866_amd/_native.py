@@ -32,7 +32,9 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_fit_to_render", "igs_timing_enable", "igs_timing_read", "igs_batch_describe",
             "igs_batch_buffer_sizes", "igs_batch_saved_offsets", "igs_render_batched",
             "igs_render_backward_batched", "igs_l1_batched_workspace_size",
-            "igs_l1_loss_grad_batched", "igs_adam_step_batched", "igs_fit_to_render_batched")
+            "igs_l1_loss_grad_batched", "igs_adam_step_batched", "igs_fit_to_render_batched",
+            "igs_render_l1", "igs_render_backward_l1", "igs_render_l1_batched",
+            "igs_render_backward_l1_batched")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam")
 
@@ -110,6 +112,18 @@ def lib() -> ctypes.CDLL:
     L.igs_adam_step_batched.restype = i32
     L.igs_fit_to_render_batched.argtypes = [vp, vp, dp, vp, i32, i32, vp]
     L.igs_fit_to_render_batched.restype = i32
+    L.igs_render_l1.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp,
+                                sz, vp]
+    L.igs_render_l1.restype = i32
+    L.igs_render_backward_l1.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, sz, vp, vp,
+                                         sz, vp]
+    L.igs_render_backward_l1.restype = i32
+    L.igs_render_l1_batched.argtypes = [vp, dp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz, vp, sz,
+                                        vp]
+    L.igs_render_l1_batched.restype = i32
+    L.igs_render_backward_l1_batched.argtypes = [vp, dp, vp, i32, i32, i32, i64, vp, sz, vp, vp,
+                                                 sz, vp]
+    L.igs_render_backward_l1_batched.restype = i32
     L.igs_timing_enable.argtypes = [i32]
     L.igs_timing_enable.restype = i32
     L.igs_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
@@ -195,6 +209,24 @@ def igs_render_backward(params, N, n, H, W, K, tile_h, tile_w, pair_capacity, im
         _f32(image, "image"), _f32(grad_image, "grad_image"), _ptr(saved), saved_bytes,
         _f32(grad_params, "grad_params") if N > 0 else None, _ptr(workspace), ws_bytes,
         _stream(stream)))
+
+
+def igs_render_l1(params, N, n, H, W, K, tile_h, tile_w, pair_capacity, target, image, loss_out,
+                  saved, saved_bytes, workspace, ws_bytes, stream=None) -> None:
+    if loss_out.dtype != torch.float64:
+        raise TypeError("loss_out must be float64[2]")
+    _check("igs_render_l1", lib().igs_render_l1(
+        _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, pair_capacity,
+        _f32(target, "target"), _f32(image, "image"), _ptr(loss_out), _ptr(saved), saved_bytes,
+        _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_render_backward_l1(params, N, n, H, W, K, tile_h, tile_w, pair_capacity, saved,
+                           saved_bytes, grad_params, workspace, ws_bytes, stream=None) -> None:
+    _check("igs_render_backward_l1", lib().igs_render_backward_l1(
+        _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, pair_capacity,
+        _ptr(saved), saved_bytes, _f32(grad_params, "grad_params") if N > 0 else None,
+        _ptr(workspace), ws_bytes, _stream(stream)))
 
 
 def igs_l1_workspace_size(count: int) -> int:
@@ -298,6 +330,25 @@ def igs_render_backward_batched(params, descs, d_descs, n, K, pair_capacity, ima
         K, pair_capacity, _f32(images, "images"), _f32(grad_images, "grad_images"), _ptr(saved),
         saved_bytes, _f32(grad_params, "grad_params") if grad_params.numel() else None,
         _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_render_l1_batched(params, descs, d_descs, n, K, pair_capacity, targets, images, loss_out,
+                          saved, saved_bytes, workspace, ws_bytes, stream=None) -> None:
+    if loss_out.dtype != torch.float64:
+        raise TypeError("loss_out must be float64[B][2]")
+    _check("igs_render_l1_batched", lib().igs_render_l1_batched(
+        _f32(params, "params") if params.numel() else None, descs, _ptr(d_descs), len(descs), n,
+        K, pair_capacity, _f32(targets, "targets"), _f32(images, "images"), _ptr(loss_out),
+        _ptr(saved), saved_bytes, _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_render_backward_l1_batched(params, descs, d_descs, n, K, pair_capacity, saved, saved_bytes,
+                                   grad_params, workspace, ws_bytes, stream=None) -> None:
+    _check("igs_render_backward_l1_batched", lib().igs_render_backward_l1_batched(
+        _f32(params, "params") if params.numel() else None, descs, _ptr(d_descs), len(descs), n,
+        K, pair_capacity, _ptr(saved), saved_bytes,
+        _f32(grad_params, "grad_params") if grad_params.numel() else None, _ptr(workspace),
+        ws_bytes, _stream(stream)))
 
 
 def igs_l1_batched_workspace_size(descs, n) -> int:

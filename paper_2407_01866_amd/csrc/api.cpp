@@ -80,6 +80,8 @@ SavedLayout saved_layout(const Dims &d) {
   o = align_up(o + (size_t)d.K * d.HW * sizeof(uint16_t));
   L.aux = o;
   o = align_up(o + (size_t)d.HW * sizeof(float2));
+  L.l1_rec = o;
+  o = align_up(o + (size_t)d.HW * sizeof(float2));
   L.total = o;
   return L;
 }
@@ -116,6 +118,8 @@ WsLayout ws_layout(const Dims &d) {
   o = align_up(o + (size_t)d.T * sizeof(uint32_t));
   L.order_count = o;
   o = align_up(o + sizeof(int64_t));
+  L.l1_part = o;
+  o = align_up(o + (size_t)d.T * sizeof(double2));
   L.l1_tmp = o;
   L.total = o;
   return L;
@@ -197,10 +201,12 @@ IGS_API igs_status igs_saved_offsets(int32_t N, int32_t n, int32_t H, int32_t W,
 
 namespace {
 
-// Forward of one call (single image or batch); saved may be NULL (inference).
+// Forward of one call (single image or batch); saved may be NULL (inference).  target != NULL
+// selects the fused mean-absolute-error epilogue (loss_out: double[B][2]).
 igs_status render_impl(const float *params, const Dims &d, const Images &imgs, bool batched,
                        float *image, void *saved, size_t saved_bytes, void *workspace,
-                       size_t ws_bytes, hipStream_t s) {
+                       size_t ws_bytes, hipStream_t s, const float *target = nullptr,
+                       double *loss_out = nullptr) {
   const SavedLayout SL = saved_layout(d);
   const WsLayout WL = ws_layout(d);
   void *sv = saved;
@@ -258,16 +264,27 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
                                false));
     }
   }
-  PhaseTimer timer(kPhaseRasterFwd, s);
-  IGS_HIP(launch_raster_fwd(ranges, vals, g32a, g32b, g64, params, d, imgs,
-                            batched ? order : nullptr, image, slots, aux, s));
+  float2 *l1_rec = target ? at<float2>(sv, SL.l1_rec) : nullptr;
+  double2 *l1_part = target ? at<double2>(workspace, WL.l1_part) : nullptr;
+  {
+    PhaseTimer timer(kPhaseRasterFwd, s);
+    IGS_HIP(launch_raster_fwd(ranges, vals, g32a, g32b, g64, params, d, imgs,
+                              batched ? order : nullptr, image, slots, aux, target, l1_rec,
+                              l1_part, s));
+  }
+  if (target) {
+    PhaseTimer timer(kPhaseLoss, s);
+    IGS_HIP(launch_l1_tiles_final(l1_part, imgs, d.n, loss_out, s));
+  }
   return IGS_OK;
 }
 
+// fused = true: the upstream gradient is the L1 record of a fused forward (image and
+// grad_image unused).
 igs_status backward_impl(const float *params, const Dims &d, const Images &imgs, bool batched,
                          const float *image, const float *grad_image, const void *saved,
                          size_t saved_bytes, float *grad_params, void *workspace, size_t ws_bytes,
-                         hipStream_t s) {
+                         hipStream_t s, bool fused = false) {
   const SavedLayout SL = saved_layout(d);
   const WsLayout WL = ws_layout(d);
   if (saved_bytes < SL.total || ws_bytes < WL.total) return IGS_ERR_WORKSPACE;
@@ -287,9 +304,10 @@ igs_status backward_impl(const float *params, const Dims &d, const Images &imgs,
   PhaseTimer timer(kPhaseRasterBwd, s);
   IGS_HIP(launch_fill_f32(gamma, 5 * (int64_t)d.N, 0.f, s));
   IGS_HIP(launch_fill_f32(grad_params + 5 * (size_t)d.N, (int64_t)d.n * d.N, 0.f, s));
+  const float2 *l1_rec = fused ? at<float2>(sv, SL.l1_rec) : nullptr;
   IGS_HIP(launch_raster_bwd(ranges, vals, g32a, g32b, g64, params, d, imgs,
-                            batched ? order : nullptr, image, grad_image, slots, aux, gamma,
-                            grad_params, s));
+                            batched ? order : nullptr, image, grad_image, l1_rec, slots, aux,
+                            gamma, grad_params, s));
   IGS_HIP(launch_grad_finalize(params, g32a, g32b, gamma, d.N, grad_params, s));
   return IGS_OK;
 }
@@ -363,6 +381,35 @@ IGS_API igs_status igs_render_backward(const float *params, int32_t N, int32_t n
   return backward_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N),
                        false, image, grad_image, saved, saved_bytes, grad_params, workspace,
                        ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+IGS_API igs_status igs_render_l1(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
+                                 int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                                 const float *target, float *image, double *loss_out, void *saved,
+                                 size_t saved_bytes, void *workspace, size_t ws_bytes,
+                                 void *stream) {
+  igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
+  if (st != IGS_OK) return st;
+  if (n > kMaxFusedChannels) return IGS_ERR_UNSUPPORTED;
+  if ((N > 0 && !params) || !target || !image || !loss_out || !saved || !workspace)
+    return IGS_ERR_INVALID_ARG;
+  return render_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N), false,
+                     image, saved, saved_bytes, workspace, ws_bytes,
+                     static_cast<hipStream_t>(stream), target, loss_out);
+}
+
+IGS_API igs_status igs_render_backward_l1(const float *params, int32_t N, int32_t n, int32_t H,
+                                          int32_t W, int32_t K, int32_t tile_h, int32_t tile_w,
+                                          int64_t pair_capacity, const void *saved,
+                                          size_t saved_bytes, float *grad_params, void *workspace,
+                                          size_t ws_bytes, void *stream) {
+  igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
+  if (st != IGS_OK) return st;
+  if (n > kMaxFusedChannels) return IGS_ERR_UNSUPPORTED;
+  if ((N > 0 && (!params || !grad_params)) || !saved || !workspace) return IGS_ERR_INVALID_ARG;
+  return backward_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N),
+                       false, nullptr, nullptr, saved, saved_bytes, grad_params, workspace,
+                       ws_bytes, static_cast<hipStream_t>(stream), true);
 }
 
 // ------------------------------------------------------------------------------ batches
@@ -460,6 +507,43 @@ IGS_API igs_status igs_render_backward_batched(const float *params, const igs_im
   return backward_impl(params, d, batch_view(descs_dev, B), true, images, grad_images, saved,
                        saved_bytes, grad_params, workspace, ws_bytes,
                        static_cast<hipStream_t>(stream));
+}
+
+IGS_API igs_status igs_render_l1_batched(const float *params, const igs_image_desc *descs_host,
+                                         const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                         int32_t K, int64_t pair_capacity, const float *targets,
+                                         float *images, double *loss_out, void *saved,
+                                         size_t saved_bytes, void *workspace, size_t ws_bytes,
+                                         void *stream) {
+  igs_status st = check_batch(descs_host, B, n, K, pair_capacity);
+  if (st != IGS_OK) return st;
+  if (n > kMaxFusedChannels) return IGS_ERR_UNSUPPORTED;
+  const Dims d =
+      make_batch_dims(reinterpret_cast<const ImageDesc *>(descs_host), B, n, K, pair_capacity);
+  if ((d.N > 0 && !params) || !descs_dev || !targets || !images || !loss_out || !saved ||
+      !workspace)
+    return IGS_ERR_INVALID_ARG;
+  return render_impl(params, d, batch_view(descs_dev, B), true, images, saved, saved_bytes,
+                     workspace, ws_bytes, static_cast<hipStream_t>(stream), targets, loss_out);
+}
+
+IGS_API igs_status igs_render_backward_l1_batched(const float *params,
+                                                  const igs_image_desc *descs_host,
+                                                  const igs_image_desc *descs_dev, int32_t B,
+                                                  int32_t n, int32_t K, int64_t pair_capacity,
+                                                  const void *saved, size_t saved_bytes,
+                                                  float *grad_params, void *workspace,
+                                                  size_t ws_bytes, void *stream) {
+  igs_status st = check_batch(descs_host, B, n, K, pair_capacity);
+  if (st != IGS_OK) return st;
+  if (n > kMaxFusedChannels) return IGS_ERR_UNSUPPORTED;
+  const Dims d =
+      make_batch_dims(reinterpret_cast<const ImageDesc *>(descs_host), B, n, K, pair_capacity);
+  if ((d.N > 0 && (!params || !grad_params)) || !descs_dev || !saved || !workspace)
+    return IGS_ERR_INVALID_ARG;
+  return backward_impl(params, d, batch_view(descs_dev, B), true, nullptr, nullptr, saved,
+                       saved_bytes, grad_params, workspace, ws_bytes,
+                       static_cast<hipStream_t>(stream), true);
 }
 
 IGS_API igs_status igs_l1_workspace_size(int64_t count, size_t *ws_bytes) {

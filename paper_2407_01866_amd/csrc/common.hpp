@@ -109,12 +109,12 @@ Dims make_batch_dims(const ImageDesc *descs, int B, int n, int K, int64_t cap);
 
 // Byte offsets inside the caller's `saved` buffer.
 struct SavedLayout {
-  size_t status, ranges, order, vals, g32a, g32b, g64, slots, aux, total;
+  size_t status, ranges, order, vals, g32a, g32b, g64, slots, aux, l1_rec, total;
 };
 // Byte offsets inside the caller's workspace.
 struct WsLayout {
   size_t counts, offsets, keys, keys_alt, vals_alt, hist, hist_off, scan_tmp, gamma, order_keys,
-      order_keys_alt, order_vals_alt, order_count, l1_tmp, total;
+      order_keys_alt, order_vals_alt, order_count, l1_part, l1_tmp, total;
 };
 
 SavedLayout saved_layout(const Dims &d);
@@ -163,17 +163,25 @@ inline bool sort_starts_in_alt(int passes) { return (passes & 1) != 0; }
 // raster_fwd.hip
 // tile_order: optional device array of the T global tile ids in the order workgroups take them
 // (a largest-first queue for batches); nullptr = XCD-aware order of a single image's tiles.
+// target != nullptr: fused mean-absolute-error epilogue (n <= kMaxFusedChannels) writing the
+// per-pixel adjoint record l1_rec [pixels] and the per-tile sums l1_part [T].
+constexpr int kMaxFusedChannels = 16;
 hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
-                             float *image, uint16_t *slots, float2 *aux, hipStream_t s);
+                             float *image, uint16_t *slots, float2 *aux, const float *target,
+                             float2 *l1_rec, double2 *l1_part, hipStream_t s);
+// Per image b: loss_out[2b] = mean |d|, loss_out[2b+1] = mean d^2 from the per-tile sums.
+hipError_t launch_l1_tiles_final(const double2 *l1_part, const Images &imgs, int n,
+                                 double *loss_out, hipStream_t s);
 
 // raster_bwd.hip
 hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
-                             const float *image, const float *grad_image, const uint16_t *slots,
-                             const float2 *aux, float *gamma, float *grad_params, hipStream_t s);
+                             const float *image, const float *grad_image, const float2 *l1_rec,
+                             const uint16_t *slots, const float2 *aux, float *gamma,
+                             float *grad_params, hipStream_t s);
 hipError_t launch_grad_finalize(const float *params, const float4 *g32a, const float2 *g32b,
                                 const float *gamma, int N, float *grad_params, hipStream_t s);
 

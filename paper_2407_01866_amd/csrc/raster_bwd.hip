@@ -10,12 +10,16 @@
 //   dL/dmu_x = -2 (A G1 + C G2)          dL/dmu_y = -2 (B G1 + D G2)
 //   dL/dtheta = 2 (u1/u2 - u2/u1) G12    dL/ds_a = -2 u_a G_aa       (u_a = 1/s_a).
 //
-// One workgroup per 16 x 16 tile, one lane per pixel while reading.  The tile's hit set S_j is
-// processed in batches of 256 positions: the (pixel, retained Gaussian) items of a batch are
-// counting-sorted by Gaussian in LDS and split into chunks of at most R items of one Gaussian.  A
-// lane loads its chunk's Gaussian once, accumulates the chunk's 5 + n sums in registers, adds
-// them to the Gaussian's LDS row once (a plain store when the chunk is the Gaussian's only one),
-// and each batch ends with one global atomic per (Gaussian, component) that received anything.
+// One workgroup per 16 x 16 tile.  Every per-pixel input (the KT saved slots, the upstream
+// gradient, the rendered colour and the blend normalization) is loaded once, up front, with all
+// loads in flight together; the pixel's row (g, g.c_r, shift, 1/Z) then lives in LDS.  The tile's
+// hit set S_j is processed in batches of 256 positions: the (pixel, retained Gaussian) items of a
+// batch are counting-sorted by Gaussian in LDS (item ranks come from LDS counters split by
+// lane & 7 and stay in registers), and each Gaussian's run is cut into chunks of at most R items,
+// R chosen so that the batch has at most 256 chunks.  Lane c accumulates chunk c's 5 + n sums in
+// registers and stores them to its own LDS row; lane j then adds up the rows of Gaussian j and
+// issues one global atomic per component.  No LDS atomics touch floating point and nothing in LDS
+// needs clearing besides the counters.
 // The blend weights are recomputed from the saved per-pixel shift and 1/Z with the forward's
 // exact double-precision expression.
 #include "raster_common.hpp"
@@ -23,13 +27,15 @@
 namespace igs {
 namespace {
 
+constexpr int kSub = 8;  // per-Gaussian counters are split by lane & 7 to spread LDS atomics
+
 // Exclusive scan of v over the 256 threads of the block; returns the block total in *total.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int inc = v;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    int o = __shfl_up(inc, d, 64);
+    const int o = __shfl_up(inc, d, 64);
     if (lane >= d) inc += o;
   }
   if (lane == 63) s_wave[w] = inc;
@@ -41,74 +47,73 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *tot
     off += k < w ? t : 0;
     tot += t;
   }
-  __syncthreads();
   *total = tot;
   return off + inc - v;
 }
 
+// LDS layout (byte offsets).  The per-chunk sums (written after the items are placed) reuse the
+// space of the per-Gaussian counters (dead by then).
 struct BwdLds {
-  unsigned g, gc, aux, acc, cnt8, off, cho, owner, wave, tmp, item, total;
+  unsigned px, part, off, cho, owner, gid, wave, item, total;
 };
 
-constexpr int kSub = 8;  // per-Gaussian counters are split by lane & 7 to spread LDS atomics
-
-// LDS layout of the adjoint kernel for K retained Gaussians per pixel (byte offsets; per-pixel
-// gradient rows are 16-byte aligned for float4 reads).
-template <int NC>
-__host__ __device__ constexpr BwdLds bwd_lds(int K) {
-  constexpr unsigned NCP = (NC + 3) & ~3;
+template <int NC, int KT>
+__host__ __device__ constexpr BwdLds bwd_lds() {
+  constexpr unsigned ROW = (NC + 3 + 3) & ~3;
+  constexpr unsigned NACC = 5 + NC;
+  constexpr unsigned cnt_bytes = 4 * (kBatch * kSub + kRasterThreads);  // + one dummy per lane
+  constexpr unsigned part_bytes = 4 * kRasterThreads * NACC;
   BwdLds L{};
   unsigned o = 0;
-  L.g = o;
-  o += 4 * kRasterThreads * NCP;
-  L.gc = o;
-  o += 4 * kRasterThreads;
-  L.aux = o;
-  o += 8 * kRasterThreads;
-  L.acc = o;
-  o += 4 * kBatch * (5 + NC);
-  L.cnt8 = o;
-  o += 4 * kBatch * kSub;
+  L.px = o;
+  o += 4 * kRasterThreads * ROW;
+  L.part = o;
+  o += part_bytes > cnt_bytes ? part_bytes : cnt_bytes;
   L.off = o;
   o += 4 * (kBatch + 4);
   L.cho = o;
   o += 4 * (kBatch + 4);
   L.owner = o;
-  o += 2 * 2 * kBatch;
+  o += 2 * kRasterThreads;
+  L.gid = o;
+  o += 4 * kBatch;
   L.wave = o;
-  o += 16;
-  L.tmp = o;
-  o += 2 * kRasterThreads * (unsigned)K;
+  o += 32;
   L.item = o;
-  o += 2 * kRasterThreads * (unsigned)K;
+  o += 2 * kRasterThreads * KT;
   L.total = (o + 15) & ~15u;
   return L;
 }
 
-template <int NC>
-__global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
+// Register budget: four waves per SIMD (<= 128 VGPRs) where that fits without spilling.
+__host__ __device__ constexpr int bwd_min_waves(int nc, int kt) { return nc + kt <= 26 ? 4 : 2; }
+
+// L1 = true: the upstream gradient is the mean-absolute-error gradient recorded by the fused
+// forward (per pixel: g . c_r and 2-bit sign codes, g = sign / (n H W)) instead of explicit
+// gradient and colour images; image_all and grad_image_all are then unused.
+template <int NC, int KT, bool L1>
+__global__ __launch_bounds__(kRasterThreads)
+__attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const double4 *__restrict__ g64,
     const float *__restrict__ params, int N, int n, int K, int T, Images imgs,
     const int *__restrict__ tile_order, const float *__restrict__ image_all,
-    const float *__restrict__ grad_image_all, const uint16_t *__restrict__ slots_all,
-    const float2 *__restrict__ aux_all, float *__restrict__ gamma,
-    float *__restrict__ grad_params) {
-  constexpr int NCP = (NC + 3) & ~3;  // padded per-pixel gradient row
+    const float *__restrict__ grad_image_all, const float2 *__restrict__ l1_rec,
+    const uint16_t *__restrict__ slots_all, const float2 *__restrict__ aux_all,
+    float *__restrict__ gamma, float *__restrict__ grad_params) {
+  constexpr int ROW = (NC + 3 + 3) & ~3;  // g[0..NC), g.c_r, shift, 1/Z, padding
   constexpr int NACC = 5 + NC;
+  constexpr BwdLds L = bwd_lds<NC, KT>();
   extern __shared__ __align__(16) unsigned char smem[];
-  const BwdLds L = bwd_lds<NC>(K);
-  float *s_g = reinterpret_cast<float *>(smem + L.g);              // [256 px][NCP]
-  float *s_gc = reinterpret_cast<float *>(smem + L.gc);            // [256 px] g . c_r
-  float2 *s_aux = reinterpret_cast<float2 *>(smem + L.aux);        // [256 px] shift, 1/Z
-  float *s_acc = reinterpret_cast<float *>(smem + L.acc);          // [kBatch][NACC]
-  int *s_cnt8 = reinterpret_cast<int *>(smem + L.cnt8);            // [kBatch][kSub]
+  float *s_px = reinterpret_cast<float *>(smem + L.px);            // [256 px][ROW]
+  int *s_cnt8 = reinterpret_cast<int *>(smem + L.part);            // [kBatch][kSub] + dummies
+  float *s_part = reinterpret_cast<float *>(smem + L.part);        // [256 chunks][NACC]
   int *s_off = reinterpret_cast<int *>(smem + L.off);              // [kBatch + 1] run starts
   int *s_cho = reinterpret_cast<int *>(smem + L.cho);              // [kBatch + 1] chunk starts
-  uint16_t *s_owner = reinterpret_cast<uint16_t *>(smem + L.owner);  // [2 kBatch] chunk -> j
-  int *s_wave = reinterpret_cast<int *>(smem + L.wave);            // [4]
-  uint16_t *s_tmp = reinterpret_cast<uint16_t *>(smem + L.tmp);    // [256 * K] j | rank << 8
-  uint16_t *s_item = reinterpret_cast<uint16_t *>(smem + L.item);  // [256 * K] px | j << 8
+  uint16_t *s_owner = reinterpret_cast<uint16_t *>(smem + L.owner);  // [256] chunk -> j
+  uint32_t *s_gid = reinterpret_cast<uint32_t *>(smem + L.gid);    // [kBatch] j -> Gaussian
+  int *s_wave = reinterpret_cast<int *>(smem + L.wave);
+  uint16_t *s_item = reinterpret_cast<uint16_t *>(smem + L.item);  // [256 * KT] px | j << 8
 
   const int tid = threadIdx.x;
   const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[blockIdx.x]
@@ -120,10 +125,6 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
   const ImageDesc im = imgs.by_tile(tile);
   const int W = im.W, H = im.H;
   const int64_t HW = (int64_t)H * W;
-  const float *__restrict__ image = image_all + (int64_t)n * im.pix_off;
-  const float *__restrict__ grad_image = grad_image_all + (int64_t)n * im.pix_off;
-  const uint16_t *__restrict__ slots = slots_all + (int64_t)K * im.pix_off;
-  const float2 *__restrict__ aux = aux_all + im.pix_off;
   const int lt = tile - im.tile_off;
   const int tx = lt % im.tiles_x, ty = lt / im.tiles_x;
   const int x0 = tx * kTile, y0 = ty * kTile;
@@ -131,43 +132,76 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
   const bool inside = px < W && py < H;
   const int64_t pix = inside ? (int64_t)py * W + px : 0;
 
-  // per-pixel upstream gradient, g . c_r, and the forward's blend normalization
+  // every per-pixel load of the tile, issued together
+  int sl[KT];
   {
-    float gc = 0.f;
+    const uint16_t *__restrict__ slots = slots_all + (int64_t)K * im.pix_off + pix;
 #pragma unroll
-    for (int ch = 0; ch < NCP; ++ch) {
-      float g = 0.f;
-      if (ch < n && inside) {
-        g = grad_image[(int64_t)ch * HW + pix];
-        gc = fmaf(g, image[(int64_t)ch * HW + pix], gc);
+    for (int k = 0; k < KT; ++k) sl[k] = (inside && k < K) ? (int)slots[(int64_t)k * HW] : 0xFFFF;
+    const float2 ax = inside ? aux_all[im.pix_off + pix] : make_float2(0.f, 0.f);
+    float gv[NC];
+    float gc = 0.f;
+    if constexpr (L1) {
+      const float2 rec = inside ? l1_rec[im.pix_off + pix] : make_float2(0.f, 0.f);
+      const float inv_count = (float)(1.0 / ((double)n * (double)HW));
+      const uint32_t codes = __float_as_uint(rec.y);
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) {
+        const int sgn = (int)(codes << (30 - 2 * ch)) >> 30;  // 2-bit field, sign-extended
+        gv[ch] = sgn > 0 ? inv_count : (sgn < 0 ? -inv_count : 0.f);
       }
-      s_g[tid * NCP + ch] = g;
+      gc = rec.x;
+    } else {
+      const float *__restrict__ image = image_all + (int64_t)n * im.pix_off + pix;
+      const float *__restrict__ grad_image = grad_image_all + (int64_t)n * im.pix_off + pix;
+      float cv[NC];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) {
+        const bool ok = ch < n && inside;
+        gv[ch] = ok ? grad_image[(int64_t)ch * HW] : 0.f;
+        cv[ch] = ok ? image[(int64_t)ch * HW] : 0.f;
+      }
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) gc = fmaf(gv[ch], cv[ch], gc);
     }
-    s_gc[tid] = gc;
-    s_aux[tid] = inside ? aux[pix] : make_float2(0.f, 0.f);
+    float row[ROW];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) row[ch] = gv[ch];
+    row[NC] = gc;
+    row[NC + 1] = ax.x;
+    row[NC + 2] = ax.y;
+#pragma unroll
+    for (int r = NC + 3; r < ROW; ++r) row[r] = 0.f;
+#pragma unroll
+    for (int r = 0; r < ROW; r += 4)
+      *reinterpret_cast<float4 *>(&s_px[tid * ROW + r]) =
+          make_float4(row[r], row[r + 1], row[r + 2], row[r + 3]);
   }
 
+  const int sub = tid & (kSub - 1);
   for (int base = 0; base < cnt; base += kBatch) {
     const int nb = min(kBatch, cnt - base);
-    __syncthreads();  // previous batch fully consumed
+    if (base > 0) __syncthreads();  // previous batch fully consumed
+    if (tid < nb) s_gid[tid] = vals[start + base + tid];
 #pragma unroll
     for (int c = 0; c < kSub; ++c) s_cnt8[tid * kSub + c] = 0;
-#pragma unroll
-    for (int r = 0; r < NACC; ++r) s_acc[tid * NACC + r] = 0.f;
     __syncthreads();
 
-    // 1a: count the items of every Gaussian of the batch; the returned count is the item's rank
-    // inside its (Gaussian, lane & 7) sub-run (at most 32 items: one per pixel of the class)
-    const int sub = tid & (kSub - 1);
-    if (inside)
-      for (int k = 0; k < K; ++k) {
-        const int j = (int)slots[(int64_t)k * HW + pix] - base;
-        uint16_t e = 0xFFFF;
-        if (j >= 0 && j < nb) e = (uint16_t)(j | (atomicAdd(&s_cnt8[j * kSub + sub], 1) << 8));
-        s_tmp[tid * K + k] = e;
-      }
+    // 1a: rank of each item inside its (Gaussian, lane & 7) sub-run; items outside the batch
+    // count on a private dummy counter so the atomics need no branches
+    uint32_t e[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const int j = sl[k] - base;
+      const bool ok = (unsigned)j < (unsigned)nb;
+      const int a = ok ? j * kSub + sub : kBatch * kSub + tid;
+      const int r = atomicAdd(&s_cnt8[a], 1);
+      e[k] = ok ? (uint32_t)(j | (r << 8)) : 0xFFFFFFFFu;
+    }
     __syncthreads();
-    // Gaussian tid: its run (sub-runs in lane-class order), its chunks and its sub-run starts
+
+    // Gaussian tid: its run length; one packed scan gives run starts and the number of
+    // Gaussians with items (a Gaussian occurs at most once per pixel, so runs are <= 256)
     int c8[kSub];
     int my_cnt = 0;
 #pragma unroll
@@ -175,12 +209,19 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
       c8[c] = s_cnt8[tid * kSub + c];
       my_cnt += c8[c];
     }
-    int total_items;
-    const int my_off = block_exclusive_scan(my_cnt, s_wave, &total_items);
-    // chunk length: about one chunk per lane
-    const int R = max(1, (total_items + kRasterThreads - 1) / kRasterThreads + 2);
+    int packed_total;
+    const int packed_off =
+        block_exclusive_scan(my_cnt | ((my_cnt > 0 ? 1 : 0) << 16), s_wave, &packed_total);
+    const int my_off = packed_off & 0xFFFF;
+    const int total_items = packed_total & 0xFFFF;
+    const int busy = packed_total >> 16;
+    // chunk length: sum_j ceil(cnt_j / R) <= total / R + busy <= 256
+    const int R = busy < kRasterThreads
+                      ? max(1, (total_items + (kRasterThreads - busy) - 1) / (kRasterThreads - busy))
+                      : kRasterThreads;
     const int my_ch = (my_cnt + R - 1) / R;
     int total_chunks;
+    __syncthreads();  // s_wave reused
     const int my_cho = block_exclusive_scan(my_ch, s_wave, &total_chunks);
     {
       int o = my_off;
@@ -195,80 +236,66 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
     for (int c = 0; c < my_ch; ++c) s_owner[my_cho + c] = (uint16_t)tid;
     if (tid == 0) {
       s_off[kBatch] = total_items;
-      s_cho[kBatch] = total_chunks;  // s_cho[j + 1] - s_cho[j] = chunks of j
+      s_cho[kBatch] = total_chunks;
     }
     __syncthreads();
 
-    // the lane's first chunk: fetch its Gaussian now so the loads overlap the placement below
-    const bool has0 = tid < total_chunks;
-    const int j0 = has0 ? (int)s_owner[tid] : 0;
-    const uint32_t gid0 = vals[start + base + j0];
-    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f);
-    double4 c640 = make_double4(0.0, 0.0, 0.0, 0.0);
-    float col0[NC];
+    // the lane's chunk: fetch its Gaussian now so the loads overlap the placement below
+    const bool has = tid < total_chunks;
+    const int j = has ? (int)s_owner[tid] : 0;
+    const uint32_t gid = s_gid[j];
+    float2 mu = make_float2(0.f, 0.f);
+    double4 c64 = make_double4(0.0, 0.0, 0.0, 0.0);
+    float cj[NC];
 #pragma unroll
-    for (int ch = 0; ch < NC; ++ch) col0[ch] = 0.f;
-    if (has0) {
-      a0 = g32a[gid0];
-      c640 = g64[gid0];
+    for (int ch = 0; ch < NC; ++ch) cj[ch] = 0.f;
+    if (has) {
+      const float4 a = g32a[gid];
+      mu = make_float2(a.x, a.y);
+      c64 = g64[gid];
 #pragma unroll
       for (int ch = 0; ch < NC; ++ch)
-        if (ch < n) col0[ch] = params[(size_t)(5 + ch) * N + gid0];
+        if (ch < n) cj[ch] = params[(size_t)(5 + ch) * N + gid];
     }
 
     // 1b: place every item in its Gaussian's run
-    if (inside)
-      for (int k = 0; k < K; ++k) {
-        const uint16_t e = s_tmp[tid * K + k];
-        if (e != 0xFFFF) {
-          const int j = e & 0xFF;
-          s_item[s_cnt8[j * kSub + sub] + (e >> 8)] = (uint16_t)(tid | (j << 8));
-        }
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (e[k] != 0xFFFFFFFFu) {
+        const int jj = e[k] & 0xFF;
+        s_item[s_cnt8[jj * kSub + sub] + (e[k] >> 8)] = (uint16_t)(tid | (jj << 8));
       }
+    }
     __syncthreads();
 
-    // 2: chunks of one Gaussian each, accumulated in registers
-    for (int c = tid; c < total_chunks; c += kRasterThreads) {
-      const int j = c == tid ? j0 : (int)s_owner[c];
-      const int first = s_off[j] + (c - s_cho[j]) * R;
+    // 2: chunk tid, one Gaussian, accumulated in registers
+    if (has) {
+      const int first = s_off[j] + (tid - s_cho[j]) * R;
       const int end = min(first + R, s_off[j + 1]);
-      float4 a = a0;
-      double4 c64 = c640;
-      float cj[NC];
-#pragma unroll
-      for (int ch = 0; ch < NC; ++ch) cj[ch] = col0[ch];
-      if (c != tid) {
-        const uint32_t gid = vals[start + base + j];
-        a = g32a[gid];
-        c64 = g64[gid];
-#pragma unroll
-        for (int ch = 0; ch < NC; ++ch) cj[ch] = ch < n ? params[(size_t)(5 + ch) * N + gid] : 0.f;
-      }
       float G1 = 0.f, G2 = 0.f, G11 = 0.f, G22 = 0.f, G12 = 0.f;
       float gcol[NC];
 #pragma unroll
       for (int ch = 0; ch < NC; ++ch) gcol[ch] = 0.f;
       for (int it = first; it < end; ++it) {
         const int p = s_item[it] & 0xFF;
-        const float fx = (float)(x0 + (p & (kTile - 1))) + 0.5f;
-        const float fy = (float)(y0 + p / kTile) + 0.5f;
-        double d1, d2;
-        const double q = quad_form64(fx, fy, a.x, a.y, c64.x, c64.y, c64.z, c64.w, d1, d2);
-        const float2 ax = s_aux[p];
-        const float alpha = blend_weight(q, ax.x) * ax.y;
-        const float e1 = (float)d1, e2 = (float)d2;
-        float gv[NCP];
+        float rw[ROW];
 #pragma unroll
-        for (int ch = 0; ch < NCP; ch += 4) {
-          const float4 v = *reinterpret_cast<const float4 *>(&s_g[p * NCP + ch]);
-          gv[ch] = v.x;
-          if (ch + 1 < NCP) gv[ch + 1] = v.y;
-          if (ch + 2 < NCP) gv[ch + 2] = v.z;
-          if (ch + 3 < NCP) gv[ch + 3] = v.w;
+        for (int r = 0; r < ROW; r += 4) {
+          const float4 v = *reinterpret_cast<const float4 *>(&s_px[p * ROW + r]);
+          rw[r] = v.x;
+          rw[r + 1] = v.y;
+          rw[r + 2] = v.z;
+          rw[r + 3] = v.w;
         }
-        float dot = -s_gc[p];
+        const float fx = (float)(x0 + (p & (kTile - 1))) + 0.5f;
+        const float fy = (float)(y0 + (p >> 4)) + 0.5f;
+        double d1, d2;
+        const double q = quad_form64(fx, fy, mu.x, mu.y, c64.x, c64.y, c64.z, c64.w, d1, d2);
+        const float alpha = blend_weight(q, rw[NC + 1]) * rw[NC + 2];
+        const float e1 = (float)d1, e2 = (float)d2;
+        float dot = -rw[NC];
 #pragma unroll
-        for (int ch = 0; ch < NC; ++ch) dot = fmaf(gv[ch], cj[ch], dot);
+        for (int ch = 0; ch < NC; ++ch) dot = fmaf(rw[ch], cj[ch], dot);
         const float gq = -0.5f * alpha * dot;
         const float g1 = gq * e1, g2 = gq * e2;
         G1 += g1;
@@ -277,38 +304,34 @@ __global__ __launch_bounds__(kRasterThreads) void raster_bwd_kernel(
         G22 = fmaf(g2, e2, G22);
         G12 = fmaf(g1, e2, G12);
 #pragma unroll
-        for (int ch = 0; ch < NC; ++ch) gcol[ch] = fmaf(alpha, gv[ch], gcol[ch]);
+        for (int ch = 0; ch < NC; ++ch) gcol[ch] = fmaf(alpha, rw[ch], gcol[ch]);
       }
-      float *row = &s_acc[j * NACC];
-      if (s_cho[j + 1] - s_cho[j] == 1) {  // this lane holds the Gaussian's only chunk
-        row[0] = G1;
-        row[1] = G2;
-        row[2] = G11;
-        row[3] = G22;
-        row[4] = G12;
+      float *prow = &s_part[tid * NACC];
+      prow[0] = G1;
+      prow[1] = G2;
+      prow[2] = G11;
+      prow[3] = G22;
+      prow[4] = G12;
 #pragma unroll
-        for (int ch = 0; ch < NC; ++ch) row[5 + ch] = gcol[ch];
-      } else {
-        atomicAdd(&row[0], G1);
-        atomicAdd(&row[1], G2);
-        atomicAdd(&row[2], G11);
-        atomicAdd(&row[3], G22);
-        atomicAdd(&row[4], G12);
-#pragma unroll
-        for (int ch = 0; ch < NC; ++ch) atomicAdd(&row[5 + ch], gcol[ch]);
-      }
+      for (int ch = 0; ch < NC; ++ch) prow[5 + ch] = gcol[ch];
     }
     __syncthreads();
 
-    // 3: one global add per (Gaussian, component) of this batch
+    // 3: Gaussian tid adds up its chunks; one global add per (Gaussian, component)
     if (tid < nb && my_cnt > 0) {
-      const uint32_t gid = vals[start + base + tid];  // Gaussian tid of the batch
-      const float *row = &s_acc[tid * NACC];
+      float acc[NACC];
 #pragma unroll
-      for (int r = 0; r < 5; ++r) unsafeAtomicAdd(&gamma[(size_t)r * N + gid], row[r]);
+      for (int r = 0; r < NACC; ++r) acc[r] = s_part[my_cho * NACC + r];
+      for (int c = 1; c < my_ch; ++c) {
+#pragma unroll
+        for (int r = 0; r < NACC; ++r) acc[r] += s_part[(my_cho + c) * NACC + r];
+      }
+      const uint32_t g = s_gid[tid];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) unsafeAtomicAdd(&gamma[(size_t)r * N + g], acc[r]);
 #pragma unroll
       for (int ch = 0; ch < NC; ++ch)
-        if (ch < n) unsafeAtomicAdd(&grad_params[(size_t)(5 + ch) * N + gid], row[5 + ch]);
+        if (ch < n) unsafeAtomicAdd(&grad_params[(size_t)(5 + ch) * N + g], acc[5 + ch]);
     }
   }
 }
@@ -332,23 +355,39 @@ __global__ __launch_bounds__(256) void grad_finalize_kernel(const float *__restr
   grad[4 * (size_t)N + i] = -2.0f * u2 * G22;
 }
 
-template <int NC>
-hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
-                         const double4 *g64, const float *params, const Dims &d,
-                         const Images &imgs, const int *tile_order, const float *image,
-                         const float *grad_image, const uint16_t *slots, const float2 *aux,
-                         float *gamma, float *grad_params, hipStream_t s) {
-  const size_t lds = bwd_lds<NC>(d.K).total;
+template <int NC, int KT, bool L1>
+hipError_t launch_bwd_t(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
+                        const double4 *g64, const float *params, const Dims &d,
+                        const Images &imgs, const int *tile_order, const float *image,
+                        const float *grad_image, const float2 *l1_rec, const uint16_t *slots,
+                        const float2 *aux, float *gamma, float *grad_params, hipStream_t s) {
+  constexpr size_t lds = bwd_lds<NC, KT>().total;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)raster_bwd_kernel<NC>,
+    hipError_t e = hipFuncSetAttribute((const void *)raster_bwd_kernel<NC, KT, L1>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  raster_bwd_kernel<NC><<<d.T, kRasterThreads, lds, s>>>(ranges, vals, g32a, g64, params, d.N,
-                                                          d.n, d.K, d.T, imgs, tile_order, image,
-                                                          grad_image, slots, aux, gamma,
-                                                          grad_params);
+  raster_bwd_kernel<NC, KT, L1><<<d.T, kRasterThreads, lds, s>>>(
+      ranges, vals, g32a, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image, grad_image,
+      l1_rec, slots, aux, gamma, grad_params);
   return hipGetLastError();
+}
+
+template <int NC, bool L1>
+hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
+                         const double4 *g64, const float *params, const Dims &d,
+                         const Images &imgs, const int *tile_order, const float *image,
+                         const float *grad_image, const float2 *l1_rec, const uint16_t *slots,
+                         const float2 *aux, float *gamma, float *grad_params, hipStream_t s) {
+  const int kt = pick_kt(d.K);
+#define IGS_BWD_KT(KTV)                                                                         \
+  if (kt == KTV)                                                                                \
+    return launch_bwd_t<NC, KTV, L1>(ranges, vals, g32a, g64, params, d, imgs, tile_order,      \
+                                     image, grad_image, l1_rec, slots, aux, gamma, grad_params, \
+                                     s);
+  IGS_FOR_EACH_KT(IGS_BWD_KT)
+#undef IGS_BWD_KT
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -356,13 +395,29 @@ hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 
 hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
-                             const float *image, const float *grad_image, const uint16_t *slots,
-                             const float2 *aux, float *gamma, float *grad_params, hipStream_t s) {
+                             const float *image, const float *grad_image, const float2 *l1_rec,
+                             const uint16_t *slots, const float2 *aux, float *gamma,
+                             float *grad_params, hipStream_t s) {
   (void)g32b;
+  if (l1_rec != nullptr) {
 #define IGS_BWD_NC(NCV)                                                                        \
   if (d.n <= NCV)                                                                              \
-    return launch_bwd_nc<NCV>(ranges, vals, g32a, g64, params, d, imgs, tile_order, image,     \
-                              grad_image, slots, aux, gamma, grad_params, s);
+    return launch_bwd_nc<NCV, true>(ranges, vals, g32a, g64, params, d, imgs, tile_order,      \
+                                    image, grad_image, l1_rec, slots, aux, gamma, grad_params, \
+                                    s);
+    IGS_BWD_NC(1)
+    IGS_BWD_NC(3)
+    IGS_BWD_NC(4)
+    IGS_BWD_NC(9)
+    IGS_BWD_NC(16)
+#undef IGS_BWD_NC
+    return hipErrorInvalidValue;
+  }
+#define IGS_BWD_NC(NCV)                                                                        \
+  if (d.n <= NCV)                                                                              \
+    return launch_bwd_nc<NCV, false>(ranges, vals, g32a, g64, params, d, imgs, tile_order,     \
+                                     image, grad_image, nullptr, slots, aux, gamma,            \
+                                     grad_params, s);
   IGS_BWD_NC(1)
   IGS_BWD_NC(3)
   IGS_BWD_NC(4)

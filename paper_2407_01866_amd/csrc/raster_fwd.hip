@@ -40,13 +40,45 @@ __device__ __forceinline__ void topk_insert(double (&tk)[KT], double key) {
   }
 }
 
-template <int KT>
+// Fused L1 epilogue (L1 = true): besides the image, each pixel compares its colour with the
+// target, d = c_r - c_t per channel (in double, exact), and keeps what the adjoint of the mean
+// absolute error needs: the sign of every d as a 2-bit code (01 = +, 11 = -, 00 = 0) and
+// g . c_r with g = sign(d) / (n H W), evaluated exactly as the adjoint would evaluate it from an
+// explicit gradient image.  The tile's sums of |d| and d^2 go to loss_part[tile].
+struct L1Out {
+  const float *target;  // [n][H][W] per image, concatenated like the images
+  float2 *rec;          // per pixel: (g . c_r, sign codes)
+  double2 *part;        // per tile: (sum |d|, sum d^2)
+};
+
+__device__ __forceinline__ double2 block_sum2(double a, double b, double *sh) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += __shfl_down(a, d, 64);
+    b += __shfl_down(b, d, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[2 * w] = a;
+    sh[2 * w + 1] = b;
+  }
+  __syncthreads();
+  double2 t = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kRasterThreads / 64; ++k) {
+      t.x += sh[2 * k];
+      t.y += sh[2 * k + 1];
+    }
+  return t;  // valid in thread 0
+}
+
+template <int KT, bool L1>
 __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
     const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n, int K, int T,
     Images imgs, const int *__restrict__ tile_order, float *__restrict__ image_all,
-    uint16_t *__restrict__ slots_all, float2 *__restrict__ aux_all) {
+    uint16_t *__restrict__ slots_all, float2 *__restrict__ aux_all, L1Out l1) {
   extern __shared__ __align__(16) unsigned char smem[];
   float4 *s_geo = reinterpret_cast<float4 *>(smem);                    // mu_x, mu_y, A, B
   float2 *s_cd = reinterpret_cast<float2 *>(smem + 16 * kBatch);       // C, D
@@ -122,7 +154,9 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
     }
   }
 
-  if (!inside) return;
+  if (!L1 && !inside) return;
+  double l1_abs = 0.0, l1_sq = 0.0;
+  if (inside) {
   const int64_t pix = (int64_t)py * W + px;
   const int keff = min(K, cnt);
   int ts[KT];
@@ -167,6 +201,10 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
     }
   }
   const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
+  const float *__restrict__ target = L1 ? l1.target + (int64_t)n * im.pix_off : nullptr;
+  const float inv_count = L1 ? (float)(1.0 / ((double)n * (double)HW)) : 0.f;
+  float gc = 0.f;
+  uint32_t codes = 0;
   for (int ch = 0; ch < n; ++ch) {
     float acc = 0.f;
 #pragma unroll
@@ -176,13 +214,50 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
         acc = fmaf(w[k], c, acc);
       }
     }
-    image[(int64_t)ch * HW + pix] = acc * invZ;
+    const float v = acc * invZ;
+    image[(int64_t)ch * HW + pix] = v;
+    if constexpr (L1) {
+      const double d = (double)v - (double)target[(int64_t)ch * HW + pix];
+      const float g = d > 0.0 ? inv_count : (d < 0.0 ? -inv_count : 0.f);
+      codes |= (d > 0.0 ? 1u : (d < 0.0 ? 3u : 0u)) << (2 * ch);
+      gc = fmaf(g, v, gc);
+      l1_abs += fabs(d);
+      l1_sq += d * d;
+    }
   }
+  if constexpr (L1) l1.rec[im.pix_off + pix] = make_float2(gc, __uint_as_float(codes));
 #pragma unroll
   for (int k = 0; k < KT; ++k)
     if (k < K)
       slots[(int64_t)k * HW + pix] = (k < keff && ts[k] >= 0) ? (uint16_t)min(ts[k], 0xFFFF) : kEmptySlot;
   aux[pix] = make_float2(shift, invZ);
+  }
+  if (L1) {
+    __syncthreads();  // LDS staging area is reused for the reduction
+    const double2 t = block_sum2(l1_abs, l1_sq, reinterpret_cast<double *>(smem));
+    if (tid == 0) l1.part[tile] = t;
+  }
+}
+
+// Per image: mean |d| and mean d^2 from the per-tile sums of its tiles (fixed order).
+__global__ __launch_bounds__(256) void l1_tiles_final_kernel(const double2 *__restrict__ part,
+                                                             Images imgs, int n,
+                                                             double *__restrict__ out) {
+  __shared__ double sh[8];
+  const ImageDesc im = imgs.at(blockIdx.x);
+  const int T = im.tiles_x * im.tiles_y;
+  double a = 0.0, b = 0.0;
+  for (int t = threadIdx.x; t < T; t += blockDim.x) {
+    const double2 v = part[im.tile_off + t];
+    a += v.x;
+    b += v.y;
+  }
+  const double2 s = block_sum2(a, b, sh);
+  if (threadIdx.x == 0) {
+    const double inv = 1.0 / ((double)n * (double)im.H * (double)im.W);
+    out[2 * blockIdx.x] = s.x * inv;
+    out[2 * blockIdx.x + 1] = s.y * inv;
+  }
 }
 
 }  // namespace
@@ -190,19 +265,33 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
 hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
-                             float *image, uint16_t *slots, float2 *aux, hipStream_t s) {
+                             float *image, uint16_t *slots, float2 *aux, const float *target,
+                             float2 *l1_rec, double2 *l1_part, hipStream_t s) {
   const size_t lds = 56 * kBatch + (size_t)d.n * kBatch * sizeof(float);
   const int kt = pick_kt(d.K);
+  const L1Out l1{target, l1_rec, l1_part};
+  const bool fused = target != nullptr;
 #define IGS_LAUNCH_FWD(KTV)                                                                    \
   if (kt == KTV) {                                                                             \
-    raster_fwd_kernel<KTV><<<d.T, kRasterThreads, lds, s>>>(ranges, vals, g32a, g32b, g64,     \
-                                                            params, d.N, d.n, d.K, d.T, imgs,  \
-                                                            tile_order, image, slots, aux);    \
+    if (fused)                                                                                 \
+      raster_fwd_kernel<KTV, true><<<d.T, kRasterThreads, lds, s>>>(                           \
+          ranges, vals, g32a, g32b, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image,  \
+          slots, aux, l1);                                                                     \
+    else                                                                                       \
+      raster_fwd_kernel<KTV, false><<<d.T, kRasterThreads, lds, s>>>(                          \
+          ranges, vals, g32a, g32b, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image,  \
+          slots, aux, l1);                                                                     \
     return hipGetLastError();                                                                  \
   }
   IGS_FOR_EACH_KT(IGS_LAUNCH_FWD)
 #undef IGS_LAUNCH_FWD
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_l1_tiles_final(const double2 *l1_part, const Images &imgs, int n,
+                                 double *loss_out, hipStream_t s) {
+  l1_tiles_final_kernel<<<imgs.B, 256, 0, s>>>(l1_part, imgs, n, loss_out);
+  return hipGetLastError();
 }
 
 }  // namespace igs

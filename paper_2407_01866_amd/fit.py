@@ -1,7 +1,8 @@
 """Fitting loop around the renderer (Image-GS Sec. 3.3 and Sec. 4.1): every iteration renders the
-Gaussians, takes the L1 loss gradient against the target, runs the adjoint and applies one Adam
-step with the paper's constant per-group learning rates, in the fitter's parameterization
-(mean normalized to [0,1]^2, inverse scales 1/s).  Every step is a libimagegs kernel; an
+Gaussians, takes the L1 loss gradient against the target (fused into the render pass for up to 16
+channels), runs the adjoint and applies one Adam step with the paper's constant per-group
+learning rates, in the fitter's parameterization (mean normalized to [0,1]^2, inverse scales
+1/s).  Every step is a libimagegs kernel; an
 iteration enqueues with no host synchronization and can be captured as one HIP graph.
 """
 from __future__ import annotations
@@ -17,6 +18,8 @@ from .render import Renderer, _aligned_bytes
 
 # Sec. 4.1: learning rates of (mu, c, s, theta), constant throughout training
 LR_MU, LR_COLOR, LR_SCALE, LR_THETA = 5e-4, 5e-3, 2e-3, 2e-3
+# the fused render+L1 entry points record 2-bit loss signs per channel
+MAX_FUSED_CHANNELS = 16
 
 
 @dataclass
@@ -109,7 +112,7 @@ class PlainFitter(_FitLoop):
 
     def __init__(self, target: torch.Tensor, render_params: torch.Tensor, K: int = 10,
                  adam: Optional[AdamConfig] = None, headroom: float = 1.25,
-                 pair_capacity: Optional[int] = None):
+                 pair_capacity: Optional[int] = None, fused: Optional[bool] = None):
         if target.dim() != 3:
             raise ValueError("target must be [n][H][W]")
         self.dev = target.device
@@ -118,6 +121,9 @@ class PlainFitter(_FitLoop):
         self.N = render_params.shape[1]
         self.K = K
         self.adam = adam or AdamConfig()
+        # fused: the forward computes the L1 loss and its gradient record in the same pass and the
+        # adjoint reads that record (no gradient image); otherwise render, L1, adjoint separately
+        self.fused = (self.n <= MAX_FUSED_CHANNELS) if fused is None else bool(fused)
         self.rend = render_params.to(self.dev).float().contiguous().clone()
         self.fit = torch.empty_like(self.rend)
         self.fit.copy_(self.rend)
@@ -150,10 +156,15 @@ class PlainFitter(_FitLoop):
     def step_async(self) -> None:
         """Enqueue one iteration on the current stream (no synchronization)."""
         a = self.adam
-        self.r.render_into(self.rend, self.image, self.saved)
-        nat.igs_l1_loss_grad(self.image, self.target, self.n, self.H, self.W, self.grad_image,
-                             self.loss, self.l1_ws, self.l1_ws.numel())
-        self.r.backward_into(self.rend, self.image, self.grad_image, self.saved, self.grad_params)
+        if self.fused:
+            self.r.render_l1_into(self.rend, self.target, self.image, self.loss, self.saved)
+            self.r.backward_l1_into(self.rend, self.saved, self.grad_params)
+        else:
+            self.r.render_into(self.rend, self.image, self.saved)
+            nat.igs_l1_loss_grad(self.image, self.target, self.n, self.H, self.W, self.grad_image,
+                                 self.loss, self.l1_ws, self.l1_ws.numel())
+            self.r.backward_into(self.rend, self.image, self.grad_image, self.saved,
+                                 self.grad_params)
         # an iteration whose render overflowed the pair buffer changes nothing (and does not
         # count); the host notices from the step counter, grows the buffer and repeats it
         nat.igs_adam_step(self.fit, self.rend, self.grad_params, self.m, self.v, self.step_count,
@@ -187,12 +198,13 @@ class BatchFitter(_FitLoop):
 
     def __init__(self, targets: List[torch.Tensor], render_params: List[torch.Tensor], K: int = 10,
                  adam: Optional[AdamConfig] = None, headroom: float = 1.25,
-                 pair_capacity: Optional[int] = None, device=None):
+                 pair_capacity: Optional[int] = None, device=None, fused: Optional[bool] = None):
         from .render import BatchRenderer
         self.dev = torch.device(device) if device is not None else targets[0].device
         self.n = int(targets[0].shape[0])
         self.K = K
         self.adam = adam or AdamConfig()
+        self.fused = (self.n <= MAX_FUSED_CHANNELS) if fused is None else bool(fused)
         sizes = [(int(t.shape[1]), int(t.shape[2]), int(p.shape[1]))
                  for t, p in zip(targets, render_params)]
         self.r = BatchRenderer(sizes, self.n, K, pair_capacity=pair_capacity, device=self.dev)
@@ -226,10 +238,15 @@ class BatchFitter(_FitLoop):
     def step_async(self) -> None:
         a = self.adam
         r = self.r
-        r.render_into(self.rend, self.image, self.saved)
-        nat.igs_l1_loss_grad_batched(self.image, self.target, r.descs, r.d_descs, self.n,
-                                     self.grad_image, self.loss, self.l1_ws, self.l1_ws.numel())
-        r.backward_into(self.rend, self.image, self.grad_image, self.saved, self.grad_params)
+        if self.fused:
+            r.render_l1_into(self.rend, self.target, self.image, self.loss, self.saved)
+            r.backward_l1_into(self.rend, self.saved, self.grad_params)
+        else:
+            r.render_into(self.rend, self.image, self.saved)
+            nat.igs_l1_loss_grad_batched(self.image, self.target, r.descs, r.d_descs, self.n,
+                                         self.grad_image, self.loss, self.l1_ws,
+                                         self.l1_ws.numel())
+            r.backward_into(self.rend, self.image, self.grad_image, self.saved, self.grad_params)
         nat.igs_adam_step_batched(self.fit, self.rend, self.grad_params, self.m, self.v,
                                   self.step_count, r.descs, r.d_descs, self.n, a.lr_mu, a.lr_theta,
                                   a.lr_inv_scale, a.lr_color, a.beta1, a.beta2, a.eps,

@@ -72,6 +72,18 @@ class Renderer:
                                 self.cap, image, grad_image, saved, saved.numel(), grad_params,
                                 self.ws, self.ws.numel())
 
+    def render_l1_into(self, params, target, image, loss_out, saved) -> None:
+        """Forward render fused with the mean-absolute-error loss against ``target``
+        (loss_out: float64[2] = mean |d|, mean d^2); ``saved`` is required."""
+        nat.igs_render_l1(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE, self.cap,
+                          target, image, loss_out, saved, saved.numel(), self.ws, self.ws.numel())
+
+    def backward_l1_into(self, params, saved, grad_params) -> None:
+        """Gradient of the fused forward's mean absolute error (no gradient image needed)."""
+        nat.igs_render_backward_l1(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE,
+                                   self.cap, saved, saved.numel(), grad_params, self.ws,
+                                   self.ws.numel())
+
     def status_of(self, saved: Optional[torch.Tensor]) -> torch.Tensor:
         """The int64[8] device status block of a saved state (or of the workspace copy)."""
         buf = saved if saved is not None else self.ws[self.ws_bytes:]
@@ -239,6 +251,16 @@ class BatchRenderer:
         nat.igs_render_backward_batched(params, self.descs, self.d_descs, self.n, self.K, self.cap,
                                         images, grad_images, saved, saved.numel(), grad_params,
                                         self.ws, self.ws.numel())
+
+    def render_l1_into(self, params, targets, images, loss_out, saved) -> None:
+        nat.igs_render_l1_batched(params, self.descs, self.d_descs, self.n, self.K, self.cap,
+                                  targets, images, loss_out, saved, saved.numel(), self.ws,
+                                  self.ws.numel())
+
+    def backward_l1_into(self, params, saved, grad_params) -> None:
+        nat.igs_render_backward_l1_batched(params, self.descs, self.d_descs, self.n, self.K,
+                                           self.cap, saved, saved.numel(), grad_params, self.ws,
+                                           self.ws.numel())
 
     def status_of(self, saved: torch.Tensor) -> torch.Tensor:
         return saved[:64].view(torch.int64)

@@ -1,0 +1,160 @@
+"""GPU parity of the fused render + L1 path (igs_render_l1, igs_render_backward_l1 and their
+batched forms) through the C ABI.
+
+The fused forward must give the image igs_render gives (bit for bit), the loss of the separate L1
+step (the same sums taken in another order: 1e-12 relative), and the fused adjoint must give the
+gradient of the separate path (igs_l1_loss_grad, then igs_render_backward) bit for bit, since it
+evaluates the same float expressions.  Independently of the separate path, the fused gradient is
+checked against the FP64 oracle on targets built so that no pixel lies in a top-K near tie and
+every |image - target| is far above float32 error, so both sides take the same sign decisions.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cref, fitref
+from paper_2407_01866_amd import synth
+import paper_2407_01866_amd._native as nat
+
+from test_gpu_render import check_grad, near_tie_mask
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _separate_and_fused(p, tgt, H, W, K):
+    from paper_2407_01866_amd.render import Renderer
+    d = dev()
+    n, N = p.shape[0] - 5, p.shape[1]
+    r = Renderer(N, n, H, W, K, device=d)
+    pt = torch.from_numpy(np.ascontiguousarray(p)).to(d)
+    tt = torch.from_numpy(np.ascontiguousarray(tgt)).to(d)
+    img_a, saved_a = r.render(pt)                        # sizes the pair buffer
+    g = torch.empty_like(img_a)
+    loss_a = torch.zeros(2, dtype=torch.float64, device=d)
+    ws = torch.empty(nat.igs_l1_workspace_size(img_a.numel()), dtype=torch.uint8, device=d)
+    nat.igs_l1_loss_grad(img_a, tt, n, H, W, g, loss_a, ws, ws.numel())
+    gp_a = r.backward(pt, img_a, g, saved_a)
+    img_b = torch.empty_like(img_a)
+    saved_b = r.new_saved()
+    loss_b = torch.zeros(2, dtype=torch.float64, device=d)
+    gp_b = torch.empty_like(gp_a)
+    r.render_l1_into(pt, tt, img_b, loss_b, saved_b)
+    r.backward_l1_into(pt, saved_b, gp_b)
+    torch.cuda.synchronize()
+    assert int(r.status_of(saved_b)[nat.STAT_OVERFLOW]) == 0
+    return (img_a, loss_a, gp_a), (img_b, loss_b, gp_b)
+
+
+@pytest.mark.parametrize("H,W,n,N,K", [(256, 256, 3, 2000, 10), (200, 136, 9, 700, 10),
+                                       (17, 33, 1, 40, 1), (90, 77, 16, 300, 32),
+                                       (64, 48, 4, 150, 5), (33, 160, 3, 0, 10)])
+def test_fused_equals_separate_path(H, W, n, N, K):
+    print(f"[fused] H={H} W={W} n={n} N={N} K={K}", flush=True)
+    p = synth.gen_gaussians(11 + N, H, W, N, n)
+    tgt = synth.gen_image(5 + H, H, W, n, 20) if n % 3 == 0 else \
+        np.random.default_rng(H).random((n, H, W), dtype=np.float64).astype(np.float32)
+    (ia, la, ga), (ib, lb, gb) = _separate_and_fused(p, tgt, H, W, K)
+    assert torch.equal(ia, ib)
+    assert torch.equal(ga, gb)
+    la, lb = la.cpu().numpy(), lb.cpu().numpy()
+    assert np.allclose(la, lb, rtol=1e-12, atol=0)
+    ref_l1, _ = fitref.l1_loss_grad(ib.cpu().numpy(), tgt)
+    assert abs(lb[0] - ref_l1) <= 1e-12 * max(1.0, ref_l1)
+    ref_mse = np.mean((ib.cpu().numpy().astype(np.float64) - tgt.astype(np.float64)) ** 2)
+    assert abs(lb[1] - ref_mse) <= 1e-12 * max(1.0, ref_mse)
+
+
+@pytest.mark.parametrize("H,W,n,N,K,seed", [(96, 80, 3, 300, 10, 1), (50, 70, 9, 120, 4, 2),
+                                            (40, 40, 1, 60, 1, 3)])
+def test_fused_gradient_matches_oracle(H, W, n, N, K, seed):
+    """Targets = oracle image -/+ an offset of 0.02..0.1, so every sign is decided far from 0."""
+    print(f"[fused-oracle] H={H} W={W} n={n} N={N} K={K} seed={seed}", flush=True)
+    from paper_2407_01866_amd.render import Renderer
+    d = dev()
+    p = synth.gen_gaussians(seed, H, W, N, n)
+    p64 = p.astype(np.float64)
+    ref = cref.render(p64, H, W, K)
+    tie = near_tie_mask(ref["qsel"], K)
+    assert tie.sum() == 0, "seed chosen to have no near-tie pixel"
+    rng = np.random.default_rng(seed + 99)
+    off = rng.uniform(0.02, 0.1, size=(n, H, W)) * rng.choice([-1.0, 1.0], size=(n, H, W))
+    tgt = (ref["img"] - off).astype(np.float32)
+    g = np.sign(ref["img"] - tgt.astype(np.float64)) / (n * H * W)
+    o = cref.render(p64, H, W, K, grad_img=g)
+    r = Renderer(N, n, H, W, K, device=d)
+    pt = torch.from_numpy(p).to(d)
+    r.render(pt)                                          # sizes the pair buffer
+    img = torch.empty((n, H, W), device=d)
+    saved = r.new_saved()
+    loss = torch.zeros(2, dtype=torch.float64, device=d)
+    gp = torch.empty((5 + n, N), device=d)
+    r.render_l1_into(pt, torch.from_numpy(tgt).to(d), img, loss, saved)
+    r.backward_l1_into(pt, saved, gp)
+    torch.cuda.synchronize()
+    check_grad(gp.cpu().numpy().astype(np.float64), o["grad"], o["grad_abs"])
+    l1_ref = np.abs(ref["img"] - tgt.astype(np.float64)).mean()
+    assert abs(float(loss[0]) - l1_ref) <= 1e-6 * l1_ref
+
+
+def test_fused_texture_2048_n9_N100000_equals_separate():
+    """The benchmark's workload (2048^2, n = 9, N = 100k) in the launch configuration it times."""
+    w = synth.workload(2)
+    print(f"[fused] {w.name}", flush=True)
+    (ia, la, ga), (ib, lb, gb) = _separate_and_fused(w.gaussians(), w.target(), w.H, w.W, w.K)
+    assert torch.equal(ia, ib)
+    assert torch.equal(ga, gb)
+    assert np.allclose(la.cpu().numpy(), lb.cpu().numpy(), rtol=1e-12, atol=0)
+
+
+def test_fused_batched_equals_plain_fused():
+    from paper_2407_01866_amd.render import BatchRenderer, Renderer
+    d = dev()
+    sizes = [(64, 96, 300), (130, 47, 150), (16, 16, 20), (200, 180, 900)]
+    n, K = 3, 10
+    ps = [synth.gen_gaussians(40 + b, H, W, N, n) for b, (H, W, N) in enumerate(sizes)]
+    ts = [synth.gen_image(60 + b, H, W, n, 10) for b, (H, W, N) in enumerate(sizes)]
+    br = BatchRenderer(sizes, n, K, device=d)
+    bp = br.pack_params(ps)
+    _, _ = br.render(bp)                                   # sizes the pair buffer
+    imgs = br.new_images()
+    saved = br.new_saved()
+    loss = torch.zeros((len(sizes), 2), dtype=torch.float64, device=d)
+    gp = torch.empty((5 + n, br.N), device=d)
+    br.render_l1_into(bp, br.pack_images(ts), imgs, loss, saved)
+    br.backward_l1_into(bp, saved, gp)
+    torch.cuda.synchronize()
+    views = br.image_views(imgs)
+    for b, (H, W, N) in enumerate(sizes):
+        r = Renderer(N, n, H, W, K, device=d)
+        pt = torch.from_numpy(ps[b]).to(d)
+        r.render(pt)
+        img = torch.empty((n, H, W), device=d)
+        sv = r.new_saved()
+        lo = torch.zeros(2, dtype=torch.float64, device=d)
+        g1 = torch.empty((5 + n, N), device=d)
+        r.render_l1_into(pt, torch.from_numpy(ts[b]).to(d), img, lo, sv)
+        r.backward_l1_into(pt, sv, g1)
+        torch.cuda.synchronize()
+        assert torch.equal(views[b], img)
+        go = br.gauss_off[b]
+        assert torch.equal(gp[:, go:go + N], g1)
+        assert np.allclose(loss[b].cpu().numpy(), lo.cpu().numpy(), rtol=1e-12, atol=0)
+
+
+def test_fused_rejects_more_than_16_channels():
+    from paper_2407_01866_amd.render import Renderer
+    d = dev()
+    H = W = 32
+    n, N, K = 17, 10, 4
+    r = Renderer(N, n, H, W, K, device=d)
+    p = torch.from_numpy(synth.gen_gaussians(1, H, W, N, n)).to(d)
+    with pytest.raises(nat.IGSError) as e:
+        r.render_l1_into(p, torch.zeros((n, H, W), device=d), torch.empty((n, H, W), device=d),
+                         torch.zeros(2, dtype=torch.float64, device=d), r.new_saved())
+    assert e.value.status == nat.IGS_ERR_UNSUPPORTED
