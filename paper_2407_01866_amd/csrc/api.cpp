@@ -70,6 +70,12 @@ SavedLayout saved_layout(const Dims &d) {
   o = align_up(o + (size_t)d.T * sizeof(int32_t));
   L.vals = o;
   o = align_up(o + (size_t)d.cap * sizeof(uint32_t));
+  L.src = o;
+  o = align_up(o + (size_t)d.cap * sizeof(uint32_t));
+  L.counts = o;
+  o = align_up(o + (size_t)d.N * sizeof(uint32_t));
+  L.offsets = o;
+  o = align_up(o + (size_t)d.N * sizeof(int64_t));
   L.g32a = o;
   o = align_up(o + (size_t)d.N * sizeof(float4));
   L.g32b = o;
@@ -91,15 +97,13 @@ WsLayout ws_layout(const Dims &d) {
   size_t o = 0;
   // 256 digits: the widest pass of either sort (pairs, or the batch's 16-bit tile queue keys)
   const int64_t hist_elems = (int64_t)256 * d.sort_blocks;
-  L.counts = o;
-  o = align_up(o + (size_t)d.N * sizeof(uint32_t));
-  L.offsets = o;
-  o = align_up(o + (size_t)d.N * sizeof(int64_t));
   L.keys = o;
   o = align_up(o + (size_t)d.cap * sizeof(uint32_t));
   L.keys_alt = o;
   o = align_up(o + (size_t)d.cap * sizeof(uint32_t));
   L.vals_alt = o;
+  o = align_up(o + (size_t)d.cap * sizeof(uint32_t));
+  L.pair_gid = o;
   o = align_up(o + (size_t)d.cap * sizeof(uint32_t));
   L.hist = o;
   o = align_up(o + (size_t)hist_elems * sizeof(uint32_t));
@@ -108,8 +112,8 @@ WsLayout ws_layout(const Dims &d) {
   L.scan_tmp = o;
   o = align_up(o + std::max(scan_temp_elems(std::max<int64_t>(d.N, 1)) * sizeof(int64_t),
                             scan_temp_elems(hist_elems) * sizeof(uint32_t)));
-  L.gamma = o;
-  o = align_up(o + (size_t)5 * d.N * sizeof(float));
+  L.part = o;
+  o = align_up(o + (size_t)d.cap * part_stride(d.n) * sizeof(float));
   L.order_keys = o;  // largest-first tile queue of a batch: sort scratch
   o = align_up(o + (size_t)d.T * sizeof(uint32_t));
   L.order_keys_alt = o;
@@ -222,13 +226,15 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
   int2 *ranges = at<int2>(sv, SL.ranges);
   int *order = at<int>(sv, SL.order);
   uint32_t *vals = at<uint32_t>(sv, SL.vals);
+  uint32_t *src = at<uint32_t>(sv, SL.src);
   float4 *g32a = at<float4>(sv, SL.g32a);
   float2 *g32b = at<float2>(sv, SL.g32b);
   double4 *g64 = at<double4>(sv, SL.g64);
   uint16_t *slots = at<uint16_t>(sv, SL.slots);
   float2 *aux = at<float2>(sv, SL.aux);
-  uint32_t *counts = at<uint32_t>(workspace, WL.counts);
-  int64_t *offsets = at<int64_t>(workspace, WL.offsets);
+  uint32_t *counts = at<uint32_t>(sv, SL.counts);
+  int64_t *offsets = at<int64_t>(sv, SL.offsets);
+  uint32_t *pair_gid = at<uint32_t>(workspace, WL.pair_gid);
   uint32_t *keys = at<uint32_t>(workspace, WL.keys);
   uint32_t *keys_alt = at<uint32_t>(workspace, WL.keys_alt);
   uint32_t *vals_alt = at<uint32_t>(workspace, WL.vals_alt);
@@ -245,9 +251,10 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
     IGS_HIP(launch_pair_total(counts, offsets, d.N, d.cap, status, s));
     const bool alt = sort_starts_in_alt(d.passes);
     IGS_HIP(launch_emit(params, d.N, imgs, counts, offsets, d.cap, alt ? keys_alt : keys,
-                        alt ? vals_alt : vals, s));
-    IGS_HIP(radix_sort_pairs(keys, vals, keys_alt, vals_alt, status, d.cap, d.key_bits, d.passes,
+                        alt ? vals_alt : src, pair_gid, s));
+    IGS_HIP(radix_sort_pairs(keys, src, keys_alt, vals_alt, status, d.cap, d.key_bits, d.passes,
                              d.digit_bits, hist, hist_off, static_cast<uint32_t *>(scan_tmp), s));
+    IGS_HIP(launch_pair_resolve(src, pair_gid, status, d.cap, vals, s));
     IGS_HIP(launch_tile_ranges(keys, status, d.cap, ranges, s));
     IGS_HIP(launch_tile_stats(ranges, d.T, imgs, d.K, status, s));
     if (batched) {
@@ -294,21 +301,23 @@ igs_status backward_impl(const float *params, const Dims &d, const Images &imgs,
   const int2 *ranges = at<int2>(sv, SL.ranges);
   const int *order = at<int>(sv, SL.order);
   const uint32_t *vals = at<uint32_t>(sv, SL.vals);
+  const uint32_t *src = at<uint32_t>(sv, SL.src);
+  const uint32_t *counts = at<uint32_t>(sv, SL.counts);
+  const int64_t *offsets = at<int64_t>(sv, SL.offsets);
   const float4 *g32a = at<float4>(sv, SL.g32a);
   const float2 *g32b = at<float2>(sv, SL.g32b);
   const double4 *g64 = at<double4>(sv, SL.g64);
   const uint16_t *slots = at<uint16_t>(sv, SL.slots);
   const float2 *aux = at<float2>(sv, SL.aux);
-  float *gamma = at<float>(workspace, WL.gamma);
+  float *part = at<float>(workspace, WL.part);
 
   PhaseTimer timer(kPhaseRasterBwd, s);
-  IGS_HIP(launch_fill_f32(gamma, 5 * (int64_t)d.N, 0.f, s));
-  IGS_HIP(launch_fill_f32(grad_params + 5 * (size_t)d.N, (int64_t)d.n * d.N, 0.f, s));
   const float2 *l1_rec = fused ? at<float2>(sv, SL.l1_rec) : nullptr;
-  IGS_HIP(launch_raster_bwd(ranges, vals, g32a, g32b, g64, params, d, imgs,
+  IGS_HIP(launch_raster_bwd(ranges, vals, src, g32a, g64, params, d, imgs,
                             batched ? order : nullptr, image, grad_image, l1_rec, slots, aux,
-                            gamma, grad_params, s));
-  IGS_HIP(launch_grad_finalize(params, g32a, g32b, gamma, d.N, grad_params, s));
+                            part, s));
+  IGS_HIP(launch_grad_reduce(params, g32a, g32b, counts, offsets, at<int64_t>(sv, SL.status),
+                             part, d.N, d.n, grad_params, s));
   return IGS_OK;
 }
 

@@ -112,13 +112,14 @@ __global__ void pair_total_kernel(const uint32_t *__restrict__ counts,
   status[kStatOverflow] = P > cap ? 1 : 0;
 }
 
-// Writes (tile key, Gaussian index) for every tile the Gaussian hits, at the Gaussian's scanned
-// offset; the pair list is thereby in ascending Gaussian index, which the stable sort keeps
-// within each tile.  Nothing is written past the capacity.
+// Writes (tile key, emit index u) for every tile the Gaussian hits, at the Gaussian's scanned
+// offset, and records the Gaussian of each emit index; the pair list is thereby in ascending
+// Gaussian index, which the stable sort keeps within each tile, and the pairs of Gaussian i are
+// the emit indices [offsets[i], offsets[i] + counts[i]).  Nothing is written past the capacity.
 __global__ __launch_bounds__(kThreads) void emit_kernel(
     const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
     const int64_t *__restrict__ offsets, int64_t cap, uint32_t *__restrict__ keys,
-    uint32_t *__restrict__ vals) {
+    uint32_t *__restrict__ vals, uint32_t *__restrict__ pair_gid) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   uint32_t c = counts[i];
@@ -133,9 +134,23 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
     for (int tx = b.tx0; tx <= b.tx1; ++tx)
       if (circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W) && k < c) {
         keys[o + k] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
-        vals[o + k] = (uint32_t)i;
+        vals[o + k] = (uint32_t)(o + k);
+        pair_gid[o + k] = (uint32_t)i;
         ++k;
       }
+}
+
+// After the sort: the Gaussian of every sorted pair, from its emit index.
+__global__ __launch_bounds__(kThreads) void pair_resolve_kernel(const uint32_t *__restrict__ src,
+                                                                const uint32_t *__restrict__ pair_gid,
+                                                                const int64_t *__restrict__ status,
+                                                                int64_t cap,
+                                                                uint32_t *__restrict__ vals) {
+  int64_t P = status[kStatOverflow] ? 0 : status[kStatPairs];
+  if (P > cap) P = 0;
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; p < P; p += stride) vals[p] = pair_gid[src[p]];
 }
 
 // [start, end) of every tile in the sorted pair list (ranges zeroed beforehand).
@@ -257,10 +272,18 @@ hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int
 
 hipError_t launch_emit(const float *params, int N, const Images &imgs, const uint32_t *counts,
                        const int64_t *offsets, int64_t cap, uint32_t *keys, uint32_t *vals,
-                       hipStream_t s) {
+                       uint32_t *pair_gid, hipStream_t s) {
   if (N <= 0) return hipSuccess;
   emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(params, N, imgs, counts, offsets,
-                                                                  cap, keys, vals);
+                                                                  cap, keys, vals, pair_gid);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_resolve(const uint32_t *src, const uint32_t *pair_gid,
+                               const int64_t *status, int64_t cap, uint32_t *vals,
+                               hipStream_t s) {
+  pair_resolve_kernel<<<grid_for(cap, kThreads, 8192), kThreads, 0, s>>>(src, pair_gid, status,
+                                                                         cap, vals);
   return hipGetLastError();
 }
 

@@ -109,13 +109,17 @@ Dims make_batch_dims(const ImageDesc *descs, int B, int n, int K, int64_t cap);
 
 // Byte offsets inside the caller's `saved` buffer.
 struct SavedLayout {
-  size_t status, ranges, order, vals, g32a, g32b, g64, slots, aux, l1_rec, total;
+  size_t status, ranges, order, vals, src, counts, offsets, g32a, g32b, g64, slots, aux, l1_rec,
+      total;
 };
 // Byte offsets inside the caller's workspace.
 struct WsLayout {
-  size_t counts, offsets, keys, keys_alt, vals_alt, hist, hist_off, scan_tmp, gamma, order_keys,
+  size_t keys, keys_alt, vals_alt, pair_gid, hist, hist_off, scan_tmp, part, order_keys,
       order_keys_alt, order_vals_alt, order_count, l1_part, l1_tmp, total;
 };
+// Floats per (tile, Gaussian) partial-gradient record of the adjoint: 5 geometry sums and n
+// colour sums, padded to a multiple of four (16-byte aligned records).
+__host__ __device__ inline int part_stride(int n) { return (5 + n + 3) & ~3; }
 
 SavedLayout saved_layout(const Dims &d);
 WsLayout ws_layout(const Dims &d);
@@ -131,9 +135,13 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
                              float2 *g32b, double4 *g64, uint32_t *counts, hipStream_t s);
 hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int N, int64_t cap,
                              int64_t *status, hipStream_t s);
+// vals receives emit indices (sorted along with the keys), pair_gid[u] the Gaussian of emit
+// index u; launch_pair_resolve then maps sorted emit indices to Gaussians.
 hipError_t launch_emit(const float *params, int N, const Images &imgs, const uint32_t *counts,
                        const int64_t *offsets, int64_t cap, uint32_t *keys, uint32_t *vals,
-                       hipStream_t s);
+                       uint32_t *pair_gid, hipStream_t s);
+hipError_t launch_pair_resolve(const uint32_t *src, const uint32_t *pair_gid,
+                               const int64_t *status, int64_t cap, uint32_t *vals, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
                               int2 *ranges, hipStream_t s);
 hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K,
@@ -175,15 +183,18 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
 hipError_t launch_l1_tiles_final(const double2 *l1_part, const Images &imgs, int n,
                                  double *loss_out, hipStream_t s);
 
-// raster_bwd.hip
-hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
-                             const float2 *g32b, const double4 *g64, const float *params,
+// raster_bwd.hip: the adjoint writes one partial record (part_stride(n) floats) per pair at its
+// emit index src[pos]; launch_grad_reduce sums each Gaussian's records in emit order.
+hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uint32_t *src,
+                             const float4 *g32a, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
                              const float *image, const float *grad_image, const float2 *l1_rec,
-                             const uint16_t *slots, const float2 *aux, float *gamma,
-                             float *grad_params, hipStream_t s);
-hipError_t launch_grad_finalize(const float *params, const float4 *g32a, const float2 *g32b,
-                                const float *gamma, int N, float *grad_params, hipStream_t s);
+                             const uint16_t *slots, const float2 *aux, float *part,
+                             hipStream_t s);
+hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const float2 *g32b,
+                              const uint32_t *counts, const int64_t *offsets,
+                              const int64_t *status, const float *part, int N, int n,
+                              float *grad_params, hipStream_t s);
 
 // loss_adam.hip
 int l1_blocks(int64_t count);

@@ -14,12 +14,14 @@
 // gradient, the rendered colour and the blend normalization) is loaded once, up front, with all
 // loads in flight together; the pixel's row (g, g.c_r, shift, 1/Z) then lives in LDS.  The tile's
 // hit set S_j is processed in batches of 256 positions: the (pixel, retained Gaussian) items of a
-// batch are counting-sorted by Gaussian in LDS (item ranks come from LDS counters split by
-// lane & 7 and stay in registers), and each Gaussian's run is cut into chunks of at most R items,
+// batch are counting-sorted by Gaussian in LDS (item ranks come from per-wave LDS sub-counters and
+// stay in registers), and each Gaussian's run is cut into chunks of at most R items,
 // R chosen so that the batch has at most 256 chunks.  Lane c accumulates chunk c's 5 + n sums in
-// registers and stores them to its own LDS row; lane j then adds up the rows of Gaussian j and
-// issues one global atomic per component.  No LDS atomics touch floating point and nothing in LDS
-// needs clearing besides the counters.
+// registers and stores them to its own LDS row; lane j then adds up the rows of Gaussian j (in
+// chunk order) and writes them as one record at the pair's emit index.  No atomics touch floating
+// point, in LDS or in memory: a second kernel sums each Gaussian's records, which are contiguous
+// in emit order (one per tile it hits, in tile order), in that fixed order, so the gradient is
+// reproducible bit for bit.
 // The blend weights are recomputed from the saved per-pixel shift and 1/Z with the forward's
 // exact double-precision expression.
 #include "raster_common.hpp"
@@ -27,7 +29,12 @@
 namespace igs {
 namespace {
 
-constexpr int kSub = 8;  // per-Gaussian counters are split by lane & 7 to spread LDS atomics
+// Per-Gaussian item counters are split into kSub sub-counters, (wave, lane & 3): each is touched
+// by one wave only, so the ranks it hands out follow the program and lane order (no dependence on
+// how waves interleave) and the order of items in a run, hence every float sum, is reproducible;
+// the lane split spreads same-address LDS atomics.
+constexpr int kSub = 16;
+__device__ __forceinline__ int item_sub(int tid) { return ((tid >> 6) << 2) | (tid & 3); }
 
 // Exclusive scan of v over the 256 threads of the block; returns the block total in *total.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total) {
@@ -86,7 +93,7 @@ __host__ __device__ constexpr BwdLds bwd_lds() {
 }
 
 // Register budget: four waves per SIMD (<= 128 VGPRs) where that fits without spilling.
-__host__ __device__ constexpr int bwd_min_waves(int nc, int kt) { return nc + kt <= 26 ? 4 : 2; }
+__host__ __device__ constexpr int bwd_min_waves(int nc, int kt) { return nc + kt <= 25 ? 4 : 2; }
 
 // L1 = true: the upstream gradient is the mean-absolute-error gradient recorded by the fused
 // forward (per pixel: g . c_r and 2-bit sign codes, g = sign / (n H W)) instead of explicit
@@ -95,12 +102,12 @@ template <int NC, int KT, bool L1>
 __global__ __launch_bounds__(kRasterThreads)
 __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-    const float4 *__restrict__ g32a, const double4 *__restrict__ g64,
-    const float *__restrict__ params, int N, int n, int K, int T, Images imgs,
-    const int *__restrict__ tile_order, const float *__restrict__ image_all,
+    const uint32_t *__restrict__ src, const float4 *__restrict__ g32a,
+    const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n, int K, int T,
+    Images imgs, const int *__restrict__ tile_order, const float *__restrict__ image_all,
     const float *__restrict__ grad_image_all, const float2 *__restrict__ l1_rec,
     const uint16_t *__restrict__ slots_all, const float2 *__restrict__ aux_all,
-    float *__restrict__ gamma, float *__restrict__ grad_params) {
+    float *__restrict__ part) {
   constexpr int ROW = (NC + 3 + 3) & ~3;  // g[0..NC), g.c_r, shift, 1/Z, padding
   constexpr int NACC = 5 + NC;
   constexpr BwdLds L = bwd_lds<NC, KT>();
@@ -178,11 +185,15 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
           make_float4(row[r], row[r + 1], row[r + 2], row[r + 3]);
   }
 
-  const int sub = tid & (kSub - 1);
+  const int sub = item_sub(tid);
   for (int base = 0; base < cnt; base += kBatch) {
     const int nb = min(kBatch, cnt - base);
     if (base > 0) __syncthreads();  // previous batch fully consumed
-    if (tid < nb) s_gid[tid] = vals[start + base + tid];
+    uint32_t my_src = 0;  // emit index of the batch's Gaussian tid
+    if (tid < nb) {
+      s_gid[tid] = vals[start + base + tid];
+      my_src = src[start + base + tid];
+    }
 #pragma unroll
     for (int c = 0; c < kSub; ++c) s_cnt8[tid * kSub + c] = 0;
     __syncthreads();
@@ -317,34 +328,68 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
     }
     __syncthreads();
 
-    // 3: Gaussian tid adds up its chunks; one global add per (Gaussian, component)
-    if (tid < nb && my_cnt > 0) {
-      float acc[NACC];
+    // 3: Gaussian tid adds up its chunks and writes the pair's record (zeros when no pixel of
+    // the tile retained it)
+    if (tid < nb) {
+      constexpr int NR = (NACC + 3) & ~3;
+      float acc[NR];
 #pragma unroll
-      for (int r = 0; r < NACC; ++r) acc[r] = s_part[my_cho * NACC + r];
-      for (int c = 1; c < my_ch; ++c) {
+      for (int r = 0; r < NR; ++r) acc[r] = 0.f;
+      for (int c = 0; c < my_ch; ++c) {
 #pragma unroll
         for (int r = 0; r < NACC; ++r) acc[r] += s_part[(my_cho + c) * NACC + r];
       }
-      const uint32_t g = s_gid[tid];
+      const int stride = part_stride(n);
+      float4 *rec = reinterpret_cast<float4 *>(part + (size_t)my_src * stride);
 #pragma unroll
-      for (int r = 0; r < 5; ++r) unsafeAtomicAdd(&gamma[(size_t)r * N + g], acc[r]);
+      for (int q = 0; q < NR / 4; ++q) {
+        if (4 * q < stride) {
+          float v[4];
 #pragma unroll
-      for (int ch = 0; ch < NC; ++ch)
-        if (ch < n) unsafeAtomicAdd(&grad_params[(size_t)(5 + ch) * N + g], acc[5 + ch]);
+          for (int e = 0; e < 4; ++e) v[e] = (4 * q + e < 5 + n) ? acc[4 * q + e] : 0.f;
+          rec[q] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+      }
     }
   }
 }
 
-__global__ __launch_bounds__(256) void grad_finalize_kernel(const float *__restrict__ params,
-                                                            const float4 *__restrict__ g32a,
-                                                            const float2 *__restrict__ g32b,
-                                                            const float *__restrict__ gamma,
-                                                            int N, float *__restrict__ grad) {
+// Per Gaussian: the sum of its pair records in emit order (a fixed order), turned into
+// dL/d(mu_x, mu_y, theta, s_1, s_2) with
+//   dL/dmu_x = -2 (A G1 + C G2), dL/dmu_y = -2 (B G1 + D G2),
+//   dL/dtheta = 2 (u1/u2 - u2/u1) G12, dL/ds_a = -2 u_a G_aa,
+// and the colour sums as dL/dc.  Every row of grad is written (zeros for a Gaussian that no pixel
+// retained).
+template <int NC>
+__global__ __launch_bounds__(256) void grad_reduce_kernel(
+    const float *__restrict__ params, const float4 *__restrict__ g32a,
+    const float2 *__restrict__ g32b, const uint32_t *__restrict__ counts,
+    const int64_t *__restrict__ offsets, const int64_t *__restrict__ status,
+    const float *__restrict__ part, int N, int n, float *__restrict__ grad) {
+  constexpr int NR = (5 + NC + 3) & ~3;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const float G1 = gamma[i], G2 = gamma[(size_t)N + i], G11 = gamma[2 * (size_t)N + i];
-  const float G22 = gamma[3 * (size_t)N + i], G12 = gamma[4 * (size_t)N + i];
+  const int stride = part_stride(n);
+  // an overflowed render wrote no records (its pairs did not fit): the gradient is zero
+  const uint32_t c = status[kStatOverflow] ? 0u : counts[i];
+  const float4 *__restrict__ rec =
+      reinterpret_cast<const float4 *>(part + (size_t)offsets[i] * stride);
+  float acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.f;
+  for (uint32_t t = 0; t < c; ++t) {
+#pragma unroll
+    for (int q = 0; q < NR / 4; ++q) {
+      if (4 * q < stride) {
+        const float4 v = rec[(size_t)t * (stride / 4) + q];
+        acc[4 * q] += v.x;
+        acc[4 * q + 1] += v.y;
+        acc[4 * q + 2] += v.z;
+        acc[4 * q + 3] += v.w;
+      }
+    }
+  }
+  const float G1 = acc[0], G2 = acc[1], G11 = acc[2], G22 = acc[3], G12 = acc[4];
   const float4 a = g32a[i];
   const float2 cd = g32b[i];
   const float u1 = 1.0f / params[3 * (size_t)N + i], u2 = 1.0f / params[4 * (size_t)N + i];
@@ -353,14 +398,17 @@ __global__ __launch_bounds__(256) void grad_finalize_kernel(const float *__restr
   grad[2 * (size_t)N + i] = 2.0f * (u1 / u2 - u2 / u1) * G12;
   grad[3 * (size_t)N + i] = -2.0f * u1 * G11;
   grad[4 * (size_t)N + i] = -2.0f * u2 * G22;
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch)
+    if (ch < n) grad[(size_t)(5 + ch) * N + i] = acc[5 + ch];
 }
 
 template <int NC, int KT, bool L1>
-hipError_t launch_bwd_t(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
-                        const double4 *g64, const float *params, const Dims &d,
-                        const Images &imgs, const int *tile_order, const float *image,
-                        const float *grad_image, const float2 *l1_rec, const uint16_t *slots,
-                        const float2 *aux, float *gamma, float *grad_params, hipStream_t s) {
+hipError_t launch_bwd_t(const int2 *ranges, const uint32_t *vals, const uint32_t *src,
+                        const float4 *g32a, const double4 *g64, const float *params,
+                        const Dims &d, const Images &imgs, const int *tile_order,
+                        const float *image, const float *grad_image, const float2 *l1_rec,
+                        const uint16_t *slots, const float2 *aux, float *part, hipStream_t s) {
   constexpr size_t lds = bwd_lds<NC, KT>().total;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)raster_bwd_kernel<NC, KT, L1>,
@@ -368,23 +416,22 @@ hipError_t launch_bwd_t(const int2 *ranges, const uint32_t *vals, const float4 *
     if (e != hipSuccess) return e;
   }
   raster_bwd_kernel<NC, KT, L1><<<d.T, kRasterThreads, lds, s>>>(
-      ranges, vals, g32a, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image, grad_image,
-      l1_rec, slots, aux, gamma, grad_params);
+      ranges, vals, src, g32a, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image,
+      grad_image, l1_rec, slots, aux, part);
   return hipGetLastError();
 }
 
 template <int NC, bool L1>
-hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
-                         const double4 *g64, const float *params, const Dims &d,
-                         const Images &imgs, const int *tile_order, const float *image,
-                         const float *grad_image, const float2 *l1_rec, const uint16_t *slots,
-                         const float2 *aux, float *gamma, float *grad_params, hipStream_t s) {
+hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const uint32_t *src,
+                         const float4 *g32a, const double4 *g64, const float *params,
+                         const Dims &d, const Images &imgs, const int *tile_order,
+                         const float *image, const float *grad_image, const float2 *l1_rec,
+                         const uint16_t *slots, const float2 *aux, float *part, hipStream_t s) {
   const int kt = pick_kt(d.K);
 #define IGS_BWD_KT(KTV)                                                                         \
   if (kt == KTV)                                                                                \
-    return launch_bwd_t<NC, KTV, L1>(ranges, vals, g32a, g64, params, d, imgs, tile_order,      \
-                                     image, grad_image, l1_rec, slots, aux, gamma, grad_params, \
-                                     s);
+    return launch_bwd_t<NC, KTV, L1>(ranges, vals, src, g32a, g64, params, d, imgs, tile_order, \
+                                     image, grad_image, l1_rec, slots, aux, part, s);
   IGS_FOR_EACH_KT(IGS_BWD_KT)
 #undef IGS_BWD_KT
   return hipErrorInvalidValue;
@@ -392,19 +439,17 @@ hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const float4 
 
 }  // namespace
 
-hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
-                             const float2 *g32b, const double4 *g64, const float *params,
+hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uint32_t *src,
+                             const float4 *g32a, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
                              const float *image, const float *grad_image, const float2 *l1_rec,
-                             const uint16_t *slots, const float2 *aux, float *gamma,
-                             float *grad_params, hipStream_t s) {
-  (void)g32b;
+                             const uint16_t *slots, const float2 *aux, float *part,
+                             hipStream_t s) {
   if (l1_rec != nullptr) {
 #define IGS_BWD_NC(NCV)                                                                        \
   if (d.n <= NCV)                                                                              \
-    return launch_bwd_nc<NCV, true>(ranges, vals, g32a, g64, params, d, imgs, tile_order,      \
-                                    image, grad_image, l1_rec, slots, aux, gamma, grad_params, \
-                                    s);
+    return launch_bwd_nc<NCV, true>(ranges, vals, src, g32a, g64, params, d, imgs, tile_order, \
+                                    image, grad_image, l1_rec, slots, aux, part, s);
     IGS_BWD_NC(1)
     IGS_BWD_NC(3)
     IGS_BWD_NC(4)
@@ -415,9 +460,9 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const flo
   }
 #define IGS_BWD_NC(NCV)                                                                        \
   if (d.n <= NCV)                                                                              \
-    return launch_bwd_nc<NCV, false>(ranges, vals, g32a, g64, params, d, imgs, tile_order,     \
-                                     image, grad_image, nullptr, slots, aux, gamma,            \
-                                     grad_params, s);
+    return launch_bwd_nc<NCV, false>(ranges, vals, src, g32a, g64, params, d, imgs,            \
+                                     tile_order, image, grad_image, nullptr, slots, aux, part, \
+                                     s);
   IGS_BWD_NC(1)
   IGS_BWD_NC(3)
   IGS_BWD_NC(4)
@@ -428,11 +473,26 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const flo
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_grad_finalize(const float *params, const float4 *g32a, const float2 *g32b,
-                                const float *gamma, int N, float *grad_params, hipStream_t s) {
+hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const float2 *g32b,
+                              const uint32_t *counts, const int64_t *offsets,
+                              const int64_t *status, const float *part, int N, int n,
+                              float *grad_params, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  grad_finalize_kernel<<<(N + 255) / 256, 256, 0, s>>>(params, g32a, g32b, gamma, N, grad_params);
-  return hipGetLastError();
+  const int blocks = (N + 255) / 256;
+#define IGS_RED_NC(NCV)                                                                        \
+  if (n <= NCV) {                                                                              \
+    grad_reduce_kernel<NCV><<<blocks, 256, 0, s>>>(params, g32a, g32b, counts, offsets,        \
+                                                   status, part, N, n, grad_params);            \
+    return hipGetLastError();                                                                  \
+  }
+  IGS_RED_NC(1)
+  IGS_RED_NC(3)
+  IGS_RED_NC(4)
+  IGS_RED_NC(9)
+  IGS_RED_NC(16)
+  IGS_RED_NC(32)
+#undef IGS_RED_NC
+  return hipErrorInvalidValue;
 }
 
 }  // namespace igs

@@ -13,12 +13,23 @@
 // depend on the order in which candidates arrive.  This file is built with -fno-honor-nans so the
 // min/max are not wrapped in NaN-quieting instructions; q is clamped below 1e38 before packing so a
 // non-finite value can only rank last.
+//
+// Candidate order and wave-level culling.  Because the keys are unique, any processing order gives
+// the same lists, so each batch is visited in ascending order of a lower bound of q over the tile
+// (16 coarse buckets of a counting sort).  Each wave (16 x 4 pixels) also has, per candidate, a
+// lower bound of the float32 q over its own pixel rectangle, shrunk by a margin that covers float32
+// evaluation error; a candidate whose bound exceeds the largest K-th key of the wave's lanes cannot
+// enter any of their lists and is skipped by the whole wave, and once the bucket floor exceeds it
+// the wave stops.  Winners come early in this order, so most of the tail is skipped.
 #include "raster_common.hpp"
 
 namespace igs {
 namespace {
 
 constexpr uint32_t kKeyBias = 0x00800000u;
+// LDS bytes before the colour rows: per candidate 48 B of ranking data in visiting order and 40 B
+// of blend geometry in slot order, then the bucket counters.
+constexpr unsigned kFwdLdsFixed = 88 * kBatch + 2 * 16 * 4;
 constexpr float kQMax = 1e38f;
 
 __device__ __forceinline__ double rank_key(float q, int slot) {
@@ -29,7 +40,66 @@ __device__ __forceinline__ bool key_valid(double k) {
   return (uint32_t)__double2hiint(k) < 0x7F000000u;  // not the +inf sentinel
 }
 
-// Sorted insertion of a key (ascending, unique keys): a compare-exchange down the list.
+constexpr int kBuckets = 16;
+constexpr int kWaves = kRasterThreads / 64;  // each wave covers 4 rows of the tile
+
+// Minimum over the rectangle [dxa, dxb] x [dya, dyb] of the quadratic form
+// p11 dx^2 + 2 p12 dx dy + p22 dy^2 (positive definite): 0 if the rectangle holds the origin,
+// else the least of the four edge minima (each a clamped 1-D minimum).
+__device__ __forceinline__ double rect_min_q(double p11, double p12, double p22, double i11,
+                                             double i22, double dxa, double dxb, double dya,
+                                             double dyb) {
+  if (dxa <= 0.0 && dxb >= 0.0 && dya <= 0.0 && dyb >= 0.0) return 0.0;
+  double best = __longlong_as_double(0x7FF0000000000000ll);
+  const double xs[2] = {dxa, dxb}, ys[2] = {dya, dyb};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const double dx = xs[e];
+    const double dy = fmin(fmax(-p12 * dx * i22, dya), dyb);
+    best = fmin(best, p11 * dx * dx + 2.0 * p12 * dx * dy + p22 * dy * dy);
+    const double ey = ys[e];
+    const double ex = fmin(fmax(-p12 * ey * i11, dxa), dxb);
+    best = fmin(best, p11 * ex * ex + 2.0 * p12 * ex * ey + p22 * ey * ey);
+  }
+  return best;
+}
+
+// A lower bound, as float, of the float32 q = (A dx + B dy)^2 + (C dx + D dy)^2 that the ranking
+// evaluates at any pixel centre of the rectangle: the exact minimum over the rectangle shrunk by
+// 64 ulp(1) times the condition number s_max/s_min of the Gaussian, which exceeds the float32
+// evaluation error of q.  0 (never skip) when the margin reaches 1 or the input is not finite;
+// capped at 1e37 so that a lane with fewer than K keys (sentinel threshold) never skips.
+__device__ __forceinline__ float safe_lb(double m, double kappa) {
+  const double f = 1.0 - 64.0 * 5.9604644775390625e-8 * kappa;
+  const double v = m * f;
+  if (!(f > 0.0) || !(v >= 0.0)) return 0.f;
+  return (float)fmin(v, 1e37);
+}
+
+// Bucket of a lower bound: 0 for 0, 1 for (0, 1/4), then one per octave from 1/4 up to >= 2048.
+__device__ __forceinline__ int lb_bucket(float lb) {
+  if (!(lb > 0.f)) return 0;
+  const int e = (int)((__float_as_uint(lb) >> 23) & 0xFF) - 127;  // floor(log2 lb) for normals
+  return 1 + min(max(e + 3, 0), kBuckets - 2);
+}
+// Smallest value any bound in bucket b can have.
+__device__ __forceinline__ float bucket_floor(int b) {
+  return b <= 1 ? 0.f : __uint_as_float((uint32_t)(127 + b - 4) << 23);  // 2^(b-4)
+}
+
+// Maximum over the 64 lanes of a wave, with DPP row shifts and row broadcasts (no LDS); every
+// lane of a row sees the partial maxima of lower lanes, lane 63 the total, which is returned to
+// all lanes as a scalar.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false));  // shr 1
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false));  // shr 2
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));  // shr 4
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));  // shr 8
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // bcast 15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // bcast 31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 template <int KT>
 __device__ __forceinline__ void topk_insert(double (&tk)[KT], double key) {
 #pragma unroll
@@ -51,7 +121,8 @@ struct L1Out {
   double2 *part;        // per tile: (sum |d|, sum d^2)
 };
 
-__device__ __forceinline__ double2 block_sum2(double a, double b, double *sh) {
+__device__ __forceinline__ double2 block_sum2(double a, double b, double *sh,
+                                              int nwaves = kRasterThreads / 64) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     a += __shfl_down(a, d, 64);
@@ -65,7 +136,7 @@ __device__ __forceinline__ double2 block_sum2(double a, double b, double *sh) {
   __syncthreads();
   double2 t = make_double2(0.0, 0.0);
   if (threadIdx.x == 0)
-    for (int k = 0; k < kRasterThreads / 64; ++k) {
+    for (int k = 0; k < nwaves; ++k) {
       t.x += sh[2 * k];
       t.y += sh[2 * k + 1];
     }
@@ -80,10 +151,16 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
     Images imgs, const int *__restrict__ tile_order, float *__restrict__ image_all,
     uint16_t *__restrict__ slots_all, float2 *__restrict__ aux_all, L1Out l1) {
   extern __shared__ __align__(16) unsigned char smem[];
-  float4 *s_geo = reinterpret_cast<float4 *>(smem);                    // mu_x, mu_y, A, B
-  float2 *s_cd = reinterpret_cast<float2 *>(smem + 16 * kBatch);       // C, D
-  double *s64 = reinterpret_cast<double *>(smem + 24 * kBatch);        // [kBatch][4] A,B,C,D
-  float *s_col = reinterpret_cast<float *>(smem + 56 * kBatch);        // [n][kBatch]
+  // ranking data in visiting order (position m of the batch's candidate order)
+  float4 *s_pgeo = reinterpret_cast<float4 *>(smem);                  // mu_x, mu_y, A, B
+  float4 *s_pcd = reinterpret_cast<float4 *>(smem + 16 * kBatch);     // C, D, slot, bucket floor
+  float *s_plbw = reinterpret_cast<float *>(smem + 32 * kBatch);      // [kWaves][kBatch] bounds
+  // blend data in slot order (position j in S_j minus the batch base)
+  float2 *s_mu = reinterpret_cast<float2 *>(smem + 48 * kBatch);      // mu_x, mu_y
+  double *s64 = reinterpret_cast<double *>(smem + 56 * kBatch);       // [kBatch][4] A,B,C,D
+  int *s_bcnt = reinterpret_cast<int *>(smem + 88 * kBatch);          // [kBuckets] counters
+  int *s_bstart = s_bcnt + kBuckets;                                  // [kBuckets] starts
+  float *s_col = reinterpret_cast<float *>(smem + kFwdLdsFixed);      // [n][kBatch]
 
   const int tid = threadIdx.x;
   const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[blockIdx.x]
@@ -109,14 +186,21 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
 #pragma unroll
   for (int k = 0; k < KT; ++k) tk[k] = __longlong_as_double(0x7FF0000000000000ll);  // +inf
 
+  const int wave = tid >> 6;
+  if (tid < kBuckets) s_bcnt[tid] = 0;
   for (int base = 0; base < cnt; base += kBatch) {
     const int nb = min(kBatch, cnt - base);
     __syncthreads();
+    int bucket = 0, brank = 0;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 b = make_float2(0.f, 0.f);
+    float lbw[kWaves];
     if (tid < nb) {
       const uint32_t gid = vals[start + base + tid];
-      s_geo[tid] = g32a[gid];
-      s_cd[tid] = g32b[gid];
+      a = g32a[gid];
+      b = g32b[gid];
       if (single) {
+        s_mu[tid] = make_float2(a.x, a.y);
         const double4 c = g64[gid];
         s64[4 * tid + 0] = c.x;
         s64[4 * tid + 1] = c.y;
@@ -124,33 +208,70 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
         s64[4 * tid + 3] = c.w;
         for (int ch = 0; ch < n; ++ch) s_col[ch * kBatch + tid] = params[(size_t)(5 + ch) * N + gid];
       }
+      // lower bounds of q over each wave's pixel-centre rectangle, from the float32 coefficients
+      const double A = a.z, B = a.w, C = b.x, D = b.y;
+      const double p11 = A * A + C * C, p12 = A * B + C * D, p22 = B * B + D * D;
+      const double r1 = A * A + B * B, r2 = C * C + D * D;  // 1/s_1^2, 1/s_2^2
+      const float kappa = sqrtf((float)(fmax(r1, r2) / fmin(r1, r2))) * 1.001f;
+      // the clamp points only select where each edge is evaluated: float reciprocals move them by
+      // a relative 1e-7, which changes the edge minimum by a relative 1e-14
+      const double i11 = (double)(1.0f / (float)p11), i22 = (double)(1.0f / (float)p22);
+      const double dxa = (double)(tx * kTile) + 0.5 - (double)a.x;
+      const double dxb = dxa + (kTile - 1);
+      float tile_lb = 3.0e38f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const double dya = (double)(ty * kTile + 4 * w) + 0.5 - (double)a.y;
+        lbw[w] = safe_lb(rect_min_q(p11, p12, p22, i11, i22, dxa, dxb, dya, dya + 3.0), kappa);
+        tile_lb = fminf(tile_lb, lbw[w]);
+      }
+      bucket = lb_bucket(tile_lb);
+      brank = atomicAdd(&s_bcnt[bucket], 1);
     }
     __syncthreads();
-    int j = 0;
-    // four candidates per step: their loads and quadratic forms overlap before the insertions
-    for (; j + 4 <= nb; j += 4) {
-      double key[4];
+    if (tid < 64) {  // bucket starts: exclusive scan of the counters (one wave)
+      const int c = tid < kBuckets ? s_bcnt[tid] : 0;
+      int inc = c;
+#pragma unroll
+      for (int d = 1; d < kBuckets; d <<= 1) {
+        const int o = __shfl_up(inc, d, 64);
+        if (tid >= d) inc += o;
+      }
+      if (tid < kBuckets) s_bstart[tid] = inc - c;
+    }
+    __syncthreads();
+    if (tid < nb) {  // scatter the ranking data into visiting order
+      const int pos = s_bstart[bucket] + brank;
+      s_pgeo[pos] = a;
+      s_pcd[pos] = make_float4(b.x, b.y, __int_as_float(base + tid), bucket_floor(bucket));
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) s_plbw[w * kBatch + pos] = lbw[w];
+    }
+    if (tid < kBuckets) s_bcnt[tid] = 0;  // ready for the next batch
+    __syncthreads();
+    // four positions per step; the skip decisions are wave-uniform (scalar branches)
+    for (int m = 0; m < nb; m += 4) {
+      // the largest K-th key of the wave (the lists only shrink, so a stale value is safe)
+      const uint32_t th = wave_max_u32((uint32_t)__double2hiint(tk[KT - 1]));
+      const float q_tau = __uint_as_float(th - kKeyBias);
+      // every later candidate's bound is at least the floor of this position's bucket
+      if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_pcd[m].w))) > q_tau)
+        break;
+      const float4 lb4 = *reinterpret_cast<const float4 *>(&s_plbw[wave * kBatch + m]);
+      const float lbu[4] = {lb4.x, lb4.y, lb4.z, lb4.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const float4 a = s_geo[j + u];
-        const float2 b = s_cd[j + u];
-        const float dx = fx - a.x, dy = fy - a.y;
-        const float e1 = fmaf(a.z, dx, a.w * dy);
-        const float e2 = fmaf(b.x, dx, b.y * dy);
-        key[u] = rank_key(fmaf(e1, e1, e2 * e2), base + j + u);
+        if (m + u >= nb) break;
+        if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbu[u]))) > q_tau)
+          continue;
+        const float4 g = s_pgeo[m + u];
+        const float4 cd = s_pcd[m + u];
+        const float dx = fx - g.x, dy = fy - g.y;
+        const float e1 = fmaf(g.z, dx, g.w * dy);
+        const float e2 = fmaf(cd.x, dx, cd.y * dy);
+        const double key = rank_key(fmaf(e1, e1, e2 * e2), __float_as_int(cd.z));
+        if (key < tk[KT - 1]) topk_insert<KT>(tk, key);
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (key[u] < tk[KT - 1]) topk_insert<KT>(tk, key[u]);
-    }
-    for (; j < nb; ++j) {
-      const float4 a = s_geo[j];
-      const float2 b = s_cd[j];
-      const float dx = fx - a.x, dy = fy - a.y;
-      const float e1 = fmaf(a.z, dx, a.w * dy);
-      const float e2 = fmaf(b.x, dx, b.y * dy);
-      const double key = rank_key(fmaf(e1, e1, e2 * e2), base + j);
-      if (key < tk[KT - 1]) topk_insert<KT>(tk, key);
     }
   }
 
@@ -178,8 +299,8 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
         B = s64[4 * slot + 1];
         C = s64[4 * slot + 2];
         D = s64[4 * slot + 3];
-        mx = s_geo[slot].x;
-        my = s_geo[slot].y;
+        mx = s_mu[slot].x;
+        my = s_mu[slot].y;
         src[k] = slot;
       } else {
         const uint32_t gid = vals[start + slot];
@@ -239,20 +360,33 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
   }
 }
 
-// Per image: mean |d| and mean d^2 from the per-tile sums of its tiles (fixed order).
-__global__ __launch_bounds__(256) void l1_tiles_final_kernel(const double2 *__restrict__ part,
-                                                             Images imgs, int n,
-                                                             double *__restrict__ out) {
-  __shared__ double sh[8];
+// Per image: mean |d| and mean d^2 from the per-tile sums of its tiles (fixed order: thread t
+// adds tiles t, t + 1024, ... in sequence, then a fixed tree over the threads).
+constexpr int kFinalThreads = 1024;
+
+__global__ __launch_bounds__(kFinalThreads) void l1_tiles_final_kernel(
+    const double2 *__restrict__ part, Images imgs, int n, double *__restrict__ out) {
+  __shared__ double sh[2 * kFinalThreads / 64];
   const ImageDesc im = imgs.at(blockIdx.x);
   const int T = im.tiles_x * im.tiles_y;
   double a = 0.0, b = 0.0;
-  for (int t = threadIdx.x; t < T; t += blockDim.x) {
+  int t = threadIdx.x;
+  for (; t + 3 * kFinalThreads < T; t += 4 * kFinalThreads) {  // four loads in flight
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[im.tile_off + t + u * kFinalThreads];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a += v[u].x;
+      b += v[u].y;
+    }
+  }
+  for (; t < T; t += kFinalThreads) {
     const double2 v = part[im.tile_off + t];
     a += v.x;
     b += v.y;
   }
-  const double2 s = block_sum2(a, b, sh);
+  const double2 s = block_sum2(a, b, sh, kFinalThreads / 64);
   if (threadIdx.x == 0) {
     const double inv = 1.0 / ((double)n * (double)im.H * (double)im.W);
     out[2 * blockIdx.x] = s.x * inv;
@@ -267,7 +401,7 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
                              const Dims &d, const Images &imgs, const int *tile_order,
                              float *image, uint16_t *slots, float2 *aux, const float *target,
                              float2 *l1_rec, double2 *l1_part, hipStream_t s) {
-  const size_t lds = 56 * kBatch + (size_t)d.n * kBatch * sizeof(float);
+  const size_t lds = kFwdLdsFixed + (size_t)d.n * kBatch * sizeof(float);
   const int kt = pick_kt(d.K);
   const L1Out l1{target, l1_rec, l1_part};
   const bool fused = target != nullptr;
@@ -290,7 +424,7 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
 
 hipError_t launch_l1_tiles_final(const double2 *l1_part, const Images &imgs, int n,
                                  double *loss_out, hipStream_t s) {
-  l1_tiles_final_kernel<<<imgs.B, 256, 0, s>>>(l1_part, imgs, n, loss_out);
+  l1_tiles_final_kernel<<<imgs.B, kFinalThreads, 0, s>>>(l1_part, imgs, n, loss_out);
   return hipGetLastError();
 }
 

@@ -93,8 +93,8 @@ def test_batched_backward_equals_plain_backward():
         ref = r.backward(pb, img, gviews[b].contiguous(), sv)
         go = br.descs[b].gauss_off
         got = gp[:, go:go + N]
-        scale = ref.abs().amax(dim=1, keepdim=True) + 1e-30
-        assert torch.all((got - ref).abs() <= 1e-5 * scale + 1e-6 * ref.abs()), b
+        # the same per-tile records summed in the same emit order: identical bits
+        assert torch.equal(got, ref), b
 
 
 def test_tile_queue_is_stable_largest_first():
@@ -166,6 +166,6 @@ def test_batch_fitter_tracks_plain_fitters():
     for b in range(len(sizes)):
         pf = PlainFitter(tg[b], ps[b], K)
         pf.run(40, report_every=40)
-        assert pf.psnr() == pytest.approx(bp[b], abs=2e-3), b
-        np.testing.assert_allclose(bf.image_params(b).cpu().numpy(), pf.rend.cpu().numpy(),
-                                   rtol=1e-3, atol=1e-3)
+        # every kernel of the batched iteration evaluates each image exactly as the plain one
+        assert pf.psnr() == bp[b], b
+        assert torch.equal(bf.image_params(b), pf.rend), b
