@@ -27,9 +27,12 @@ namespace igs {
 namespace {
 
 constexpr uint32_t kKeyBias = 0x00800000u;
+// Candidates staged in LDS per batch: 192 keeps the kernel's LDS (124 B per candidate for n = 9)
+// small enough for six workgroups per CU, the occupancy its registers allow.
+constexpr int kFwdBatch = 192;
 // LDS bytes before the colour rows: per candidate 48 B of ranking data in visiting order and 40 B
 // of blend geometry in slot order, then the bucket counters.
-constexpr unsigned kFwdLdsFixed = 88 * kBatch + 2 * 16 * 4;
+constexpr unsigned kFwdLdsFixed = 88 * kFwdBatch + 2 * 16 * 4;
 constexpr float kQMax = 1e38f;
 
 __device__ __forceinline__ double rank_key(float q, int slot) {
@@ -43,37 +46,39 @@ __device__ __forceinline__ bool key_valid(double k) {
 constexpr int kBuckets = 16;
 constexpr int kWaves = kRasterThreads / 64;  // each wave covers 4 rows of the tile
 
-// Minimum over the rectangle [dxa, dxb] x [dya, dyb] of the quadratic form
-// p11 dx^2 + 2 p12 dx dy + p22 dy^2 (positive definite): 0 if the rectangle holds the origin,
-// else the least of the four edge minima (each a clamped 1-D minimum).
-__device__ __forceinline__ double rect_min_q(double p11, double p12, double p22, double i11,
-                                             double i22, double dxa, double dxb, double dya,
-                                             double dyb) {
-  if (dxa <= 0.0 && dxb >= 0.0 && dya <= 0.0 && dyb >= 0.0) return 0.0;
-  double best = __longlong_as_double(0x7FF0000000000000ll);
-  const double xs[2] = {dxa, dxb}, ys[2] = {dya, dyb};
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const double dx = xs[e];
-    const double dy = fmin(fmax(-p12 * dx * i22, dya), dyb);
-    best = fmin(best, p11 * dx * dx + 2.0 * p12 * dx * dy + p22 * dy * dy);
-    const double ey = ys[e];
-    const double ex = fmin(fmax(-p12 * ey * i11, dxa), dxb);
-    best = fmin(best, p11 * ex * ex + 2.0 * p12 * ex * ey + p22 * ey * ey);
-  }
+// q = (A dx + B dy)^2 + (C dx + D dy)^2 evaluated as the ranking evaluates it.
+__device__ __forceinline__ float quad_q32(float A, float B, float C, float D, float dx, float dy) {
+  const float e1 = fmaf(A, dx, B * dy), e2 = fmaf(C, dx, D * dy);
+  return fmaf(e1, e1, e2 * e2);
+}
+
+// Minimum of q over the rectangle [dxa, dxb] x [dya, dyb] of offsets from the mean: 0 if the
+// rectangle holds the mean, else the least of the four edge minima, each the 1-D minimum of the
+// quadratic along the edge (at -p12 dx / p22, resp. -p12 dy / p11) clamped to the edge.  tya, tyb
+// are the unclamped minimizers along the edges x = dxa and x = dxb.  In float32 with the same
+// factored expression as the ranking, so its error is that of the ranking's q; an inexact
+// minimizer changes an edge minimum only in second order.
+__device__ __forceinline__ float rect_min_q(float A, float B, float C, float D, float i11,
+                                            float p12, float tya, float tyb, float dxa, float dxb,
+                                            float dya, float dyb) {
+  if (dxa <= 0.f && dxb >= 0.f && dya <= 0.f && dyb >= 0.f) return 0.f;
+  float best = quad_q32(A, B, C, D, dxa, fminf(fmaxf(tya, dya), dyb));
+  best = fminf(best, quad_q32(A, B, C, D, dxb, fminf(fmaxf(tyb, dya), dyb)));
+  best = fminf(best, quad_q32(A, B, C, D, fminf(fmaxf(-p12 * dya * i11, dxa), dxb), dya));
+  best = fminf(best, quad_q32(A, B, C, D, fminf(fmaxf(-p12 * dyb * i11, dxa), dxb), dyb));
   return best;
 }
 
-// A lower bound, as float, of the float32 q = (A dx + B dy)^2 + (C dx + D dy)^2 that the ranking
-// evaluates at any pixel centre of the rectangle: the exact minimum over the rectangle shrunk by
-// 64 ulp(1) times the condition number s_max/s_min of the Gaussian, which exceeds the float32
-// evaluation error of q.  0 (never skip) when the margin reaches 1 or the input is not finite;
+// A lower bound of the float32 q that the ranking evaluates at any pixel centre of the
+// rectangle: the minimum over the rectangle, itself evaluated in float32 (relative error below
+// 16 ulp(1) times the condition number kappa = s_max/s_min, like the ranking's q), shrunk by
+// 64 ulp(1) times kappa.  0 (never skip) when the margin reaches 1 or the input is not finite;
 // capped at 1e37 so that a lane with fewer than K keys (sentinel threshold) never skips.
-__device__ __forceinline__ float safe_lb(double m, double kappa) {
-  const double f = 1.0 - 64.0 * 5.9604644775390625e-8 * kappa;
-  const double v = m * f;
-  if (!(f > 0.0) || !(v >= 0.0)) return 0.f;
-  return (float)fmin(v, 1e37);
+__device__ __forceinline__ float safe_lb(float m, float kappa) {
+  const float f = 1.0f - 64.0f * 5.9604644775390625e-8f * kappa;
+  const float v = m * f;
+  if (!(f > 0.f) || !(v >= 0.f)) return 0.f;
+  return fminf(v, 1e37f);
 }
 
 // Bucket of a lower bound: 0 for 0, 1 for (0, 1/4), then one per octave from 1/4 up to >= 2048.
@@ -143,8 +148,12 @@ __device__ __forceinline__ double2 block_sum2(double a, double b, double *sh,
   return t;  // valid in thread 0
 }
 
+// Register budget: six waves per SIMD (<= 80 VGPRs) for lists of up to 10 keys.
+__host__ __device__ constexpr int fwd_min_waves(int kt) { return kt <= 10 ? 6 : (kt <= 16 ? 4 : 2); }
+
 template <int KT, bool L1>
-__global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
+__global__ __launch_bounds__(kRasterThreads)
+__attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
     const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n, int K, int T,
@@ -153,14 +162,15 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
   extern __shared__ __align__(16) unsigned char smem[];
   // ranking data in visiting order (position m of the batch's candidate order)
   float4 *s_pgeo = reinterpret_cast<float4 *>(smem);                  // mu_x, mu_y, A, B
-  float4 *s_pcd = reinterpret_cast<float4 *>(smem + 16 * kBatch);     // C, D, slot, bucket floor
-  float *s_plbw = reinterpret_cast<float *>(smem + 32 * kBatch);      // [kWaves][kBatch] bounds
+  float4 *s_pcd = reinterpret_cast<float4 *>(smem + 16 * kFwdBatch);     // C, D, slot, bucket floor
+  float *s_plbw = reinterpret_cast<float *>(smem + 32 * kFwdBatch);      // [kWaves][kFwdBatch] bounds
   // blend data in slot order (position j in S_j minus the batch base)
-  float2 *s_mu = reinterpret_cast<float2 *>(smem + 48 * kBatch);      // mu_x, mu_y
-  double *s64 = reinterpret_cast<double *>(smem + 56 * kBatch);       // [kBatch][4] A,B,C,D
-  int *s_bcnt = reinterpret_cast<int *>(smem + 88 * kBatch);          // [kBuckets] counters
+  float2 *s_mu = reinterpret_cast<float2 *>(smem + 48 * kFwdBatch);      // mu_x, mu_y
+  double *s64 = reinterpret_cast<double *>(smem + 56 * kFwdBatch);       // [kFwdBatch][4] A,B,C,D
+  int *s_bcnt = reinterpret_cast<int *>(smem + 88 * kFwdBatch);          // [kBuckets] counters
   int *s_bstart = s_bcnt + kBuckets;                                  // [kBuckets] starts
-  float *s_col = reinterpret_cast<float *>(smem + kFwdLdsFixed);      // [n][kBatch]
+  float *s_col = reinterpret_cast<float *>(smem + kFwdLdsFixed);      // [kFwdBatch][n]
+  const int ncp = n;
 
   const int tid = threadIdx.x;
   const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[blockIdx.x]
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
   // uniform over the workgroup; readfirstlane keeps the loop bounds in scalar registers
   const int start = __builtin_amdgcn_readfirstlane(rg.x);
   const int cnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
-  const bool single = cnt <= kBatch;  // whole S_j stays resident for the blend
+  const bool single = cnt <= kFwdBatch;  // whole S_j stays resident for the blend
 
   double tk[KT];
 #pragma unroll
@@ -188,8 +198,8 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
 
   const int wave = tid >> 6;
   if (tid < kBuckets) s_bcnt[tid] = 0;
-  for (int base = 0; base < cnt; base += kBatch) {
-    const int nb = min(kBatch, cnt - base);
+  for (int base = 0; base < cnt; base += kFwdBatch) {
+    const int nb = min(kFwdBatch, cnt - base);
     __syncthreads();
     int bucket = 0, brank = 0;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -206,23 +216,23 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
         s64[4 * tid + 1] = c.y;
         s64[4 * tid + 2] = c.z;
         s64[4 * tid + 3] = c.w;
-        for (int ch = 0; ch < n; ++ch) s_col[ch * kBatch + tid] = params[(size_t)(5 + ch) * N + gid];
+        for (int ch = 0; ch < n; ++ch) s_col[tid * ncp + ch] = params[(size_t)(5 + ch) * N + gid];
       }
-      // lower bounds of q over each wave's pixel-centre rectangle, from the float32 coefficients
-      const double A = a.z, B = a.w, C = b.x, D = b.y;
-      const double p11 = A * A + C * C, p12 = A * B + C * D, p22 = B * B + D * D;
-      const double r1 = A * A + B * B, r2 = C * C + D * D;  // 1/s_1^2, 1/s_2^2
-      const float kappa = sqrtf((float)(fmax(r1, r2) / fmin(r1, r2))) * 1.001f;
-      // the clamp points only select where each edge is evaluated: float reciprocals move them by
-      // a relative 1e-7, which changes the edge minimum by a relative 1e-14
-      const double i11 = (double)(1.0f / (float)p11), i22 = (double)(1.0f / (float)p22);
-      const double dxa = (double)(tx * kTile) + 0.5 - (double)a.x;
-      const double dxb = dxa + (kTile - 1);
+      // lower bounds of q over each wave's pixel-centre rectangle (16 x 4 centres)
+      const float A = a.z, B = a.w, C = b.x, D = b.y;
+      const float p11 = fmaf(A, A, C * C), p12 = fmaf(A, B, C * D), p22 = fmaf(B, B, D * D);
+      const float r1 = fmaf(A, A, B * B), r2 = fmaf(C, C, D * D);  // 1/s_1^2, 1/s_2^2
+      const float kappa = sqrtf(fmaxf(r1, r2) / fminf(r1, r2)) * 1.001f;
+      const float i11 = 1.0f / p11, i22 = 1.0f / p22;
+      const float dxa = ((float)(tx * kTile) + 0.5f) - a.x;
+      const float dxb = ((float)(tx * kTile + kTile - 1) + 0.5f) - a.x;
+      const float tya = -p12 * dxa * i22, tyb = -p12 * dxb * i22;
       float tile_lb = 3.0e38f;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) {
-        const double dya = (double)(ty * kTile + 4 * w) + 0.5 - (double)a.y;
-        lbw[w] = safe_lb(rect_min_q(p11, p12, p22, i11, i22, dxa, dxb, dya, dya + 3.0), kappa);
+        const float dya = ((float)(ty * kTile + 4 * w) + 0.5f) - a.y;
+        const float dyb = ((float)(ty * kTile + 4 * w + 3) + 0.5f) - a.y;
+        lbw[w] = safe_lb(rect_min_q(A, B, C, D, i11, p12, tya, tyb, dxa, dxb, dya, dyb), kappa);
         tile_lb = fminf(tile_lb, lbw[w]);
       }
       bucket = lb_bucket(tile_lb);
@@ -245,7 +255,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
       s_pgeo[pos] = a;
       s_pcd[pos] = make_float4(b.x, b.y, __int_as_float(base + tid), bucket_floor(bucket));
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) s_plbw[w * kBatch + pos] = lbw[w];
+      for (int w = 0; w < kWaves; ++w) s_plbw[w * kFwdBatch + pos] = lbw[w];
     }
     if (tid < kBuckets) s_bcnt[tid] = 0;  // ready for the next batch
     __syncthreads();
@@ -257,7 +267,7 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
       // every later candidate's bound is at least the floor of this position's bucket
       if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_pcd[m].w))) > q_tau)
         break;
-      const float4 lb4 = *reinterpret_cast<const float4 *>(&s_plbw[wave * kBatch + m]);
+      const float4 lb4 = *reinterpret_cast<const float4 *>(&s_plbw[wave * kFwdBatch + m]);
       const float lbu[4] = {lb4.x, lb4.y, lb4.z, lb4.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -279,6 +289,10 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
   double l1_abs = 0.0, l1_sq = 0.0;
   if (inside) {
   const int64_t pix = (int64_t)py * W + px;
+  // the target of the first channel, loaded now so that it arrives during the blend
+  const float *__restrict__ target = L1 ? l1.target + (int64_t)n * im.pix_off + pix : nullptr;
+  float tnext = 0.f;
+  if constexpr (L1) tnext = target[0];
   const int keff = min(K, cnt);
   int ts[KT];
 #pragma unroll
@@ -322,29 +336,40 @@ __global__ __launch_bounds__(kRasterThreads) void raster_fwd_kernel(
     }
   }
   const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
-  const float *__restrict__ target = L1 ? l1.target + (int64_t)n * im.pix_off : nullptr;
   const float inv_count = L1 ? (float)(1.0 / ((double)n * (double)HW)) : 0.f;
   float gc = 0.f;
   uint32_t codes = 0;
-  for (int ch = 0; ch < n; ++ch) {
-    float acc = 0.f;
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      if (k < keff && ts[k] >= 0) {
-        const float c = single ? s_col[ch * kBatch + src[k]] : params[(size_t)(5 + ch) * N + src[k]];
-        acc = fmaf(w[k], c, acc);
-      }
-    }
+  // finishes channel ch of the pixel: the normalized colour, and with the L1 epilogue the sign of
+  // d = c_r - c_t, g . c_r and the loss sums, in channel order
+  auto finish = [&](int ch, float acc, float t) {
     const float v = acc * invZ;
     image[(int64_t)ch * HW + pix] = v;
     if constexpr (L1) {
-      const double d = (double)v - (double)target[(int64_t)ch * HW + pix];
+      const double d = (double)v - (double)t;
       const float g = d > 0.0 ? inv_count : (d < 0.0 ? -inv_count : 0.f);
       codes |= (d > 0.0 ? 1u : (d < 0.0 ? 3u : 0u)) << (2 * ch);
       gc = fmaf(g, v, gc);
       l1_abs += fabs(d);
       l1_sq += d * d;
     }
+  };
+  // channel-major: every channel sums its retained Gaussians in rank order; with the L1
+  // epilogue the next channel's target is loaded one channel ahead
+  float tcur = tnext;
+  for (int ch = 0; ch < n; ++ch) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < keff && ts[k] >= 0) {
+        const float c = single ? s_col[src[k] * ncp + ch] : params[(size_t)(5 + ch) * N + src[k]];
+        acc = fmaf(w[k], c, acc);
+      }
+    }
+    if constexpr (L1) {
+      if (ch + 1 < n) tnext = target[(int64_t)(ch + 1) * HW];
+    }
+    finish(ch, acc, tcur);
+    tcur = tnext;
   }
   if constexpr (L1) l1.rec[im.pix_off + pix] = make_float2(gc, __uint_as_float(codes));
 #pragma unroll
@@ -401,7 +426,7 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
                              const Dims &d, const Images &imgs, const int *tile_order,
                              float *image, uint16_t *slots, float2 *aux, const float *target,
                              float2 *l1_rec, double2 *l1_part, hipStream_t s) {
-  const size_t lds = kFwdLdsFixed + (size_t)d.n * kBatch * sizeof(float);
+  const size_t lds = kFwdLdsFixed + (size_t)d.n * kFwdBatch * sizeof(float);
   const int kt = pick_kt(d.K);
   const L1Out l1{target, l1_rec, l1_part};
   const bool fused = target != nullptr;
