@@ -310,16 +310,20 @@ igs_status igs_fit_to_render_batched(const float *fit_params, float *render_para
  * pair of HIP events on its stream around each of its phases; igs_timing_read waits for the
  * recorded events, returns the accumulated milliseconds and call counts per phase and, if reset is
  * non-zero, clears them.  Phases: IGS_PHASE_BINNING (footprint bound, scan, pair emission, sort
- * and tile ranges), IGS_PHASE_RASTER_FWD, IGS_PHASE_RASTER_BWD (adjoint incl. its per-Gaussian
- * finishing pass), IGS_PHASE_LOSS, IGS_PHASE_ADAM.  At most 65536 event pairs are kept between
- * reads; further phases go untimed.  Not thread-safe; do not enable during graph capture.
+ * and tile ranges), IGS_PHASE_RASTER_FWD (the forward raster kernel, with the fused L1 epilogue
+ * when called through igs_render_l1), IGS_PHASE_RASTER_BWD (the adjoint raster kernel),
+ * IGS_PHASE_GRAD_REDUCE (the adjoint's per-Gaussian reduction), IGS_PHASE_LOSS (the loss
+ * kernels, or the fused forward's final loss reduction), IGS_PHASE_ADAM.  At most 65536 event
+ * pairs are kept between reads; further phases go untimed.  Not thread-safe; do not enable during
+ * graph capture.
  */
 #define IGS_PHASE_BINNING 0
 #define IGS_PHASE_RASTER_FWD 1
 #define IGS_PHASE_RASTER_BWD 2
 #define IGS_PHASE_LOSS 3
 #define IGS_PHASE_ADAM 4
-#define IGS_NUM_PHASES 5
+#define IGS_PHASE_GRAD_REDUCE 5
+#define IGS_NUM_PHASES 6
 igs_status igs_timing_enable(int32_t on);
 igs_status igs_timing_read(double ms_out[IGS_NUM_PHASES], int64_t calls_out[IGS_NUM_PHASES],
                            int32_t reset);

@@ -36,7 +36,7 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_render_l1", "igs_render_backward_l1", "igs_render_l1_batched",
             "igs_render_backward_l1_batched")
 
-PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam")
+PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce")
 
 
 class ImageDesc(ctypes.Structure):

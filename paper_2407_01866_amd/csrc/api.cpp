@@ -311,11 +311,14 @@ igs_status backward_impl(const float *params, const Dims &d, const Images &imgs,
   const float2 *aux = at<float2>(sv, SL.aux);
   float *part = at<float>(workspace, WL.part);
 
-  PhaseTimer timer(kPhaseRasterBwd, s);
   const float2 *l1_rec = fused ? at<float2>(sv, SL.l1_rec) : nullptr;
-  IGS_HIP(launch_raster_bwd(ranges, vals, src, g32a, g64, params, d, imgs,
-                            batched ? order : nullptr, image, grad_image, l1_rec, slots, aux,
-                            part, s));
+  {
+    PhaseTimer timer(kPhaseRasterBwd, s);
+    IGS_HIP(launch_raster_bwd(ranges, vals, src, g32a, g64, params, d, imgs,
+                              batched ? order : nullptr, image, grad_image, l1_rec, slots, aux,
+                              part, s));
+  }
+  PhaseTimer timer(kPhaseGradReduce, s);
   IGS_HIP(launch_grad_reduce(params, g32a, g32b, counts, offsets, at<int64_t>(sv, SL.status),
                              part, d.N, d.n, grad_params, s));
   return IGS_OK;

@@ -77,17 +77,76 @@ __device__ __forceinline__ TileBox tile_box(float fmx, float fmy, float fs1, flo
   return b;
 }
 
+// Gaussians whose candidate tile box has more than this many tiles are enumerated by their
+// whole wave (lane t tests tiles t, t + 64, ... of the box, in the box's row-major order) instead
+// of by their own lane, so one very large Gaussian does not serialize the kernel.
+constexpr int kCoopTiles = 64;
+
+struct CoopBox {  // the candidate box of one Gaussian, broadcast from its lane
+  double mx, my, r2;
+  int tx0, ty0, w, area, H, W;
+};
+
+__device__ __forceinline__ double bcast_f64(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ CoopBox coop_box(const TileBox &b, const ImageDesc &im, int src) {
+  CoopBox c;
+  c.mx = bcast_f64(b.mx, src);
+  c.my = bcast_f64(b.my, src);
+  c.r2 = bcast_f64(b.r2, src);
+  c.tx0 = __builtin_amdgcn_readlane(b.tx0, src);
+  c.ty0 = __builtin_amdgcn_readlane(b.ty0, src);
+  c.w = __builtin_amdgcn_readlane(b.tx1 - b.tx0 + 1, src);
+  c.area = c.w * __builtin_amdgcn_readlane(b.ty1 - b.ty0 + 1, src);
+  c.H = __builtin_amdgcn_readlane(im.H, src);
+  c.W = __builtin_amdgcn_readlane(im.W, src);
+  return c;
+}
+
+__device__ __forceinline__ int box_area(const TileBox &b) {
+  return b.tx0 > b.tx1 ? 0 : (b.tx1 - b.tx0 + 1) * (b.ty1 - b.ty0 + 1);
+}
+
 // Per Gaussian: rotation/inverse-scale coefficients (A, B; C, D) with e = (A dx + B dy,
 // C dx + D dy) = diag(1/s1, 1/s2) R(theta)^T (x - mu), so that q = |e|^2 (Eq. 1-2); kept in
 // float for ranking and in double for the blend weights; plus the exact tile-hit count.
 __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     const float *__restrict__ params, int N, Images imgs, float4 *__restrict__ g32a,
     float2 *__restrict__ g32b, double4 *__restrict__ g64, uint32_t *__restrict__ counts) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const ImageDesc im = imgs.by_gauss(i);
-  float mx = params[i], my = params[(size_t)N + i], th = params[2 * (size_t)N + i];
-  float s1 = params[3 * (size_t)N + i], s2 = params[4 * (size_t)N + i];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < N;
+  const int lane = threadIdx.x & 63;
+  const int ii = valid ? i : N - 1;  // lanes past N mirror the last Gaussian and write nothing
+  const ImageDesc im = imgs.by_gauss(ii);
+  float mx = params[ii], my = params[(size_t)N + ii], th = params[2 * (size_t)N + ii];
+  float s1 = params[3 * (size_t)N + ii], s2 = params[4 * (size_t)N + ii];
+  TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
+  const int area = valid ? box_area(b) : 0;
+  uint32_t c = 0;
+  if (valid && area <= kCoopTiles) {
+    for (int ty = b.ty0; ty <= b.ty1; ++ty)
+      for (int tx = b.tx0; tx <= b.tx1; ++tx)
+        c += circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W);
+  }
+  uint64_t big = __ballot(area > kCoopTiles);
+  while (big) {
+    const int src = __ffsll((unsigned long long)big) - 1;
+    big &= big - 1;
+    const CoopBox cb = coop_box(b, im, src);
+    uint32_t hits = 0;
+    for (int t0 = 0; t0 < cb.area; t0 += 64) {
+      const int t = t0 + lane;
+      const bool hit = t < cb.area && circle_meets_tile(cb.mx, cb.my, cb.r2, cb.tx0 + t % cb.w,
+                                                        cb.ty0 + t / cb.w, cb.H, cb.W);
+      hits += (uint32_t)__popcll(__ballot(hit));
+    }
+    if (lane == src) c = hits;
+  }
+  if (!valid) return;
   double sn, cs;
   sincos((double)th, &sn, &cs);
   double u1 = 1.0 / (double)s1, u2 = 1.0 / (double)s2;
@@ -95,11 +154,6 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
   g64[i] = make_double4(A, B, C, D);
   g32a[i] = make_float4(mx, my, (float)A, (float)B);
   g32b[i] = make_float2((float)C, (float)D);
-  TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
-  uint32_t c = 0;
-  for (int ty = b.ty0; ty <= b.ty1; ++ty)
-    for (int tx = b.tx0; tx <= b.tx1; ++tx)
-      c += circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W);
   counts[i] = c;
 }
 
@@ -115,29 +169,60 @@ __global__ void pair_total_kernel(const uint32_t *__restrict__ counts,
 // Writes (tile key, emit index u) for every tile the Gaussian hits, at the Gaussian's scanned
 // offset, and records the Gaussian of each emit index; the pair list is thereby in ascending
 // Gaussian index, which the stable sort keeps within each tile, and the pairs of Gaussian i are
-// the emit indices [offsets[i], offsets[i] + counts[i]).  Nothing is written past the capacity.
+// the emit indices [offsets[i], offsets[i] + counts[i]), in row-major tile order.  Nothing is
+// written past the capacity.
 __global__ __launch_bounds__(kThreads) void emit_kernel(
     const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
     const int64_t *__restrict__ offsets, int64_t cap, uint32_t *__restrict__ keys,
     uint32_t *__restrict__ vals, uint32_t *__restrict__ pair_gid) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  uint32_t c = counts[i];
-  int64_t o = offsets[i];
-  if (c == 0 || o + (int64_t)c > cap) return;
-  const ImageDesc im = imgs.by_gauss(i);
-  float mx = params[i], my = params[(size_t)N + i];
-  float s1 = params[3 * (size_t)N + i], s2 = params[4 * (size_t)N + i];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int ii = i < N ? i : N - 1;
+  const uint32_t c = i < N ? counts[ii] : 0u;
+  const int64_t o = offsets[ii];
+  const bool active = c != 0 && o + (int64_t)c <= cap;
+  const ImageDesc im = imgs.by_gauss(ii);
+  float mx = params[ii], my = params[(size_t)N + ii];
+  float s1 = params[3 * (size_t)N + ii], s2 = params[4 * (size_t)N + ii];
   TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
-  uint32_t k = 0;
-  for (int ty = b.ty0; ty <= b.ty1; ++ty)
-    for (int tx = b.tx0; tx <= b.tx1; ++tx)
-      if (circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W) && k < c) {
-        keys[o + k] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
-        vals[o + k] = (uint32_t)(o + k);
-        pair_gid[o + k] = (uint32_t)i;
-        ++k;
+  const int area = active ? box_area(b) : 0;
+  if (area <= kCoopTiles) {
+    uint32_t k = 0;
+    for (int ty = b.ty0; ty <= b.ty1 && active; ++ty)
+      for (int tx = b.tx0; tx <= b.tx1; ++tx)
+        if (circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W) && k < c) {
+          keys[o + k] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
+          vals[o + k] = (uint32_t)(o + k);
+          pair_gid[o + k] = (uint32_t)i;
+          ++k;
+        }
+  }
+  uint64_t big = __ballot(area > kCoopTiles);
+  while (big) {
+    const int src = __ffsll((unsigned long long)big) - 1;
+    big &= big - 1;
+    const CoopBox cb = coop_box(b, im, src);
+    const int64_t so = __builtin_amdgcn_readlane((int)(o & 0xFFFFFFFF), src) & 0xFFFFFFFFll;
+    const int64_t sbase = so | ((int64_t)__builtin_amdgcn_readlane((int)(o >> 32), src) << 32);
+    const uint32_t sc = (uint32_t)__builtin_amdgcn_readlane((int)c, src);
+    const int tiles_x = __builtin_amdgcn_readlane(im.tiles_x, src);
+    const int tile_off = __builtin_amdgcn_readlane(im.tile_off, src);
+    const uint32_t gid = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63u) + src);
+    uint32_t k = 0;  // hits written so far (uniform)
+    for (int t0 = 0; t0 < cb.area; t0 += 64) {
+      const int t = t0 + lane;
+      const int tx = cb.tx0 + t % cb.w, ty = cb.ty0 + t / cb.w;
+      const bool hit = t < cb.area && circle_meets_tile(cb.mx, cb.my, cb.r2, tx, ty, cb.H, cb.W);
+      const uint64_t m = __ballot(hit);
+      const uint32_t rank = k + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (hit && rank < sc) {
+        keys[sbase + rank] = (uint32_t)(tile_off + ty * tiles_x + tx);
+        vals[sbase + rank] = (uint32_t)(sbase + rank);
+        pair_gid[sbase + rank] = gid;
       }
+      k += (uint32_t)__popcll(m);
+    }
+  }
 }
 
 // After the sort: the Gaussian of every sorted pair, from its emit index.
@@ -273,7 +358,7 @@ hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int
 hipError_t launch_emit(const float *params, int N, const Images &imgs, const uint32_t *counts,
                        const int64_t *offsets, int64_t cap, uint32_t *keys, uint32_t *vals,
                        uint32_t *pair_gid, hipStream_t s) {
-  if (N <= 0) return hipSuccess;
+  if (N <= 0) return hipSuccess;  // (the kernels read entry N - 1 for lanes past N)
   emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(params, N, imgs, counts, offsets,
                                                                   cap, keys, vals, pair_gid);
   return hipGetLastError();

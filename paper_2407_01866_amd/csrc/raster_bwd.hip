@@ -354,12 +354,26 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
   }
 }
 
-// Per Gaussian: the sum of its pair records in emit order (a fixed order), turned into
-// dL/d(mu_x, mu_y, theta, s_1, s_2) with
+// Sum over the 16 lanes of a DPP row, into the row's last lane (a fixed tree: shifts by 1, 2, 4
+// and 8 within the row).
+__device__ __forceinline__ float row_sum16(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, false));
+  return v;
+}
+
+// Per Gaussian, one row of 16 lanes: lane l adds the Gaussian's pair records l, l + 16, ... (its
+// records are contiguous in emit order, so each step of the row reads 16 consecutive records),
+// then the row sums its lanes with a fixed tree; both orders depend only on the record count, so
+// the result is reproducible bit for bit.  The sums become
 //   dL/dmu_x = -2 (A G1 + C G2), dL/dmu_y = -2 (B G1 + D G2),
 //   dL/dtheta = 2 (u1/u2 - u2/u1) G12, dL/ds_a = -2 u_a G_aa,
-// and the colour sums as dL/dc.  Every row of grad is written (zeros for a Gaussian that no pixel
-// retained).
+// and the colour sums dL/dc.  Every row of grad is written (zeros for a Gaussian that no pixel
+// retained, or when the render overflowed and wrote no records).
+constexpr int kReduceLanes = 16;
+
 template <int NC>
 __global__ __launch_bounds__(256) void grad_reduce_kernel(
     const float *__restrict__ params, const float4 *__restrict__ g32a,
@@ -367,17 +381,18 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(
     const int64_t *__restrict__ offsets, const int64_t *__restrict__ status,
     const float *__restrict__ part, int N, int n, float *__restrict__ grad) {
   constexpr int NR = (5 + NC + 3) & ~3;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const int l = threadIdx.x & (kReduceLanes - 1);
+  const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kReduceLanes);
+  const bool valid = i < N;
+  const int ii = valid ? i : N - 1;
   const int stride = part_stride(n);
-  // an overflowed render wrote no records (its pairs did not fit): the gradient is zero
-  const uint32_t c = status[kStatOverflow] ? 0u : counts[i];
+  const uint32_t c = (valid && status[kStatOverflow] == 0) ? counts[ii] : 0u;
   const float4 *__restrict__ rec =
-      reinterpret_cast<const float4 *>(part + (size_t)offsets[i] * stride);
+      reinterpret_cast<const float4 *>(part + (size_t)offsets[ii] * stride);
   float acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.f;
-  for (uint32_t t = 0; t < c; ++t) {
+  for (uint32_t t = l; t < c; t += kReduceLanes) {
 #pragma unroll
     for (int q = 0; q < NR / 4; ++q) {
       if (4 * q < stride) {
@@ -389,6 +404,9 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(
       }
     }
   }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = row_sum16(acc[r]);
+  if (!valid || l != kReduceLanes - 1) return;
   const float G1 = acc[0], G2 = acc[1], G11 = acc[2], G22 = acc[3], G12 = acc[4];
   const float4 a = g32a[i];
   const float2 cd = g32b[i];
@@ -478,7 +496,7 @@ hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const flo
                               const int64_t *status, const float *part, int N, int n,
                               float *grad_params, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  const int blocks = (N + 255) / 256;
+  const int blocks = (int)(((int64_t)N * kReduceLanes + 255) / 256);
 #define IGS_RED_NC(NCV)                                                                        \
   if (n <= NCV) {                                                                              \
     grad_reduce_kernel<NCV><<<blocks, 256, 0, s>>>(params, g32a, g32b, counts, offsets,        \

@@ -7,8 +7,15 @@
 
 namespace igs {
 
-constexpr int kNumPhases = 5;
-enum Phase { kPhaseBinning = 0, kPhaseRasterFwd = 1, kPhaseRasterBwd = 2, kPhaseLoss = 3, kPhaseAdam = 4 };
+constexpr int kNumPhases = 6;
+enum Phase {
+  kPhaseBinning = 0,
+  kPhaseRasterFwd = 1,
+  kPhaseRasterBwd = 2,
+  kPhaseLoss = 3,
+  kPhaseAdam = 4,
+  kPhaseGradReduce = 5
+};
 
 bool timing_on();
 void timing_enable(bool on);

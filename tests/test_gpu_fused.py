@@ -124,6 +124,7 @@ def test_fused_batched_equals_plain_fused():
     sizes = [(64, 96, 300), (130, 47, 150), (16, 16, 20), (200, 180, 900)]
     n, K = 3, 10
     ps = [synth.gen_gaussians(40 + b, H, W, N, n) for b, (H, W, N) in enumerate(sizes)]
+    ps[3][3:5, :5] = 150.0          # boxes of every tile of image 3: the cooperative binning path
     ts = [synth.gen_image(60 + b, H, W, n, 10) for b, (H, W, N) in enumerate(sizes)]
     br = BatchRenderer(sizes, n, K, device=d)
     bp = br.pack_params(ps)

@@ -174,6 +174,19 @@ def test_gaussians_outside_image_and_huge_ones():
     run_full(p, H, W, 10, seed=5)
 
 
+def test_large_footprints_use_cooperative_binning():
+    """Gaussians whose candidate tile box exceeds 64 tiles are binned by their whole wave; the
+    tile lists (and with them the pair order of every Gaussian) must not change."""
+    H, W, n = 256, 320, 3
+    p = synth.gen_gaussians(21, H, W, 300, n)
+    rng = np.random.default_rng(21)
+    big = np.r_[0:4, 70:74, 140:144, 210:214, 290:294]               # in every wave of 64
+    p[3, big] = rng.uniform(30.0, 80.0, big.size).astype(np.float32)  # boxes of ~50-200 tiles
+    p[4, big] = rng.uniform(5.0, 40.0, big.size).astype(np.float32)
+    p[3, [5, 133, 299]] = 600.0                                       # every tile
+    run_full(p, H, W, 10, seed=21)
+
+
 def test_long_tile_lists_span_several_lds_batches():
     """|S_j| > 256 in every tile: the selection crosses LDS batches and the blend and adjoint
     take the path that reads winners from global memory."""
