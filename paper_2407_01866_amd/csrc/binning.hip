@@ -254,30 +254,33 @@ __global__ __launch_bounds__(kThreads) void tile_ranges_kernel(const uint32_t *_
   }
 }
 
-// Per-render statistics from the tile ranges, in one workgroup with a fixed reduction order:
-// the largest |S_j|, whether any exceeds the 16-bit slot range, E_fwd = sum_j |S_j| times the
-// tile's pixel count and E_bwd = sum_j min(K, |S_j|) times the tile's pixel count.
-constexpr int kStatThreads = 1024;
+// Per-render statistics from the tile ranges: the largest |S_j|, whether any exceeds the 16-bit
+// slot range, E_fwd = sum_j |S_j| times the tile's pixel count and E_bwd = sum_j min(K, |S_j|)
+// times the tile's pixel count.  Every block reduces its tiles and adds them with 64-bit integer
+// atomics (exact and order independent) into the status block, zeroed beforehand.
+constexpr int kStatThreads = 256;
 __global__ __launch_bounds__(kStatThreads) void tile_stats_kernel(const int2 *__restrict__ ranges,
                                                                   int T, Images imgs, int K,
                                                                   int64_t *__restrict__ status) {
-  __shared__ long long s_max[kStatThreads / 64], s_ef[kStatThreads / 64], s_eb[kStatThreads / 64];
-  long long mx = 0, ef = 0, eb = 0;
-  for (int t = threadIdx.x; t < T; t += kStatThreads) {
+  __shared__ unsigned long long s_max[kStatThreads / 64], s_ef[kStatThreads / 64],
+      s_eb[kStatThreads / 64];
+  unsigned long long mx = 0, ef = 0, eb = 0;
+  const int t = blockIdx.x * kStatThreads + threadIdx.x;
+  if (t < T) {
     const int2 r = ranges[t];
-    const long long c = r.y - r.x;
+    const unsigned long long c = (unsigned long long)(r.y - r.x);
     const ImageDesc im = imgs.by_tile(t);
     const int lt = t - im.tile_off;
     const int tx = lt % im.tiles_x, ty = lt / im.tiles_x;
-    const long long npx =
-        (long long)min(im.W - tx * kTile, kTile) * min(im.H - ty * kTile, kTile);
-    mx = c > mx ? c : mx;
-    ef += c * npx;
-    eb += (c < K ? c : K) * npx;
+    const unsigned long long npx =
+        (unsigned long long)min(im.W - tx * kTile, kTile) * min(im.H - ty * kTile, kTile);
+    mx = c;
+    ef = c * npx;
+    eb = (c < (unsigned long long)K ? c : (unsigned long long)K) * npx;
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
-    const long long omx = __shfl_down(mx, d, 64);
+    const unsigned long long omx = __shfl_down(mx, d, 64);
     mx = omx > mx ? omx : mx;
     ef += __shfl_down(ef, d, 64);
     eb += __shfl_down(eb, d, 64);
@@ -295,10 +298,11 @@ __global__ __launch_bounds__(kStatThreads) void tile_stats_kernel(const int2 *__
       ef += s_ef[k];
       eb += s_eb[k];
     }
-    status[kStatMaxList] = mx;
-    status[kStatSlotOverflow] = mx > 0xFFFF ? 1 : 0;
-    status[kStatEvalsFwd] = ef;
-    status[kStatEvalsBwd] = eb;
+    unsigned long long *st = reinterpret_cast<unsigned long long *>(status);
+    atomicMax(&st[kStatMaxList], mx);
+    if (mx > 0xFFFF) atomicMax(&st[kStatSlotOverflow], 1ull);
+    atomicAdd(&st[kStatEvalsFwd], ef);
+    atomicAdd(&st[kStatEvalsBwd], eb);
   }
 }
 
@@ -387,7 +391,9 @@ hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uin
 
 hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K,
                              int64_t *status, hipStream_t s) {
-  tile_stats_kernel<<<1, kStatThreads, 0, s>>>(ranges, T, imgs, K, status);
+  if (T <= 0) return hipSuccess;
+  tile_stats_kernel<<<(T + kStatThreads - 1) / kStatThreads, kStatThreads, 0, s>>>(ranges, T, imgs,
+                                                                                 K, status);
   return hipGetLastError();
 }
 

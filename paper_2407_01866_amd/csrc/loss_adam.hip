@@ -71,18 +71,41 @@ __device__ __forceinline__ float to_render(int r, float p, float W, float H) {
   return p;
 }
 
-// u_lo > 0: lower clip of the inverse scales; u_lo <= 0: 1/max(H, W) of each Gaussian's image.
+// The image of Gaussian i for a block whose Gaussians start at i0: the image of i0 is found once
+// per block by binary search; the block's other Gaussians lie in it or in the next few images.
+__device__ __forceinline__ ImageDesc block_image_of(const Images &imgs, int i, int i0, int *s_b0) {
+  if (!imgs.arr) return imgs.one;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = imgs.B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (imgs.arr[mid].gauss_off <= i0) lo = mid;
+      else hi = mid - 1;
+    }
+    *s_b0 = lo;
+  }
+  __syncthreads();
+  int b = *s_b0;
+  while (b + 1 < imgs.B && imgs.arr[b + 1].gauss_off <= i) ++b;
+  return imgs.arr[b];
+}
+
+// One thread per (row, Gaussian): blockIdx.y is the row of the [5+n][N] arrays, so loads and
+// stores of a block are contiguous.  u_lo > 0: lower clip of the inverse scales; u_lo <= 0:
+// 1/max(H, W) of each Gaussian's image.
 __global__ __launch_bounds__(256) void adam_kernel(
     float *__restrict__ fit, float *__restrict__ rend, const float *__restrict__ grad,
     float *__restrict__ m, float *__restrict__ v, const int32_t *__restrict__ step,
     const int64_t *__restrict__ skip, int N, int n, Images imgs, float lr_mu, float lr_theta,
     float lr_u, float lr_c, float b1, float b2, float eps, float u_lo_arg, float u_hi) {
-  const int64_t total = (int64_t)(5 + n) * N;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  if (skip != nullptr && skip[0] != 0) return;
-  const int r = (int)(e / N);
-  const ImageDesc im = imgs.by_gauss((int)(e - (int64_t)r * N));
+  __shared__ int s_b0;
+  if (skip != nullptr && skip[0] != 0) return;  // uniform: the whole grid skips
+  const int i0 = blockIdx.x * blockDim.x;
+  const int i = i0 + threadIdx.x;
+  const int r = blockIdx.y;
+  const ImageDesc im = block_image_of(imgs, min(i, N - 1), i0, &s_b0);
+  if (i >= N) return;
+  const size_t e = (size_t)r * N + i;
   const float W = (float)im.W, H = (float)im.H;
   const float u_lo = u_lo_arg > 0.f ? u_lo_arg : 1.0f / fmaxf(W, H);
   const float t = (float)(step[0] + 1);
@@ -225,9 +248,8 @@ hipError_t launch_adam_lo(float *fit, float *rend, const float *grad, float *m, 
                           int32_t *step, const int64_t *skip, int N, int n, const Images &imgs,
                           float lr_mu, float lr_theta, float lr_u, float lr_c, float b1, float b2,
                           float eps, float u_lo, float u_hi, hipStream_t s) {
-  const int64_t total = (int64_t)(5 + n) * N;
-  if (total > 0) {
-    adam_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
+  if (N > 0) {
+    adam_kernel<<<dim3((unsigned)((N + 255) / 256), (unsigned)(5 + n)), 256, 0, s>>>(
         fit, rend, grad, m, v, step, skip, N, n, imgs, lr_mu, lr_theta, lr_u, lr_c, b1, b2, eps,
         u_lo, u_hi);
     hipError_t e = hipGetLastError();
