@@ -306,6 +306,27 @@ igs_status igs_fit_to_render_batched(const float *fit_params, float *render_para
                                      void *stream);
 
 /*
+ * Launch settings of the raster kernels, process-wide; they apply to calls issued afterwards
+ * (a captured graph keeps the settings it was captured with).  No setting changes any output
+ * bit; they only trade scheduling strategies, which is what an autotuner may choose among:
+ *   persistent  0: one workgroup per tile (default); 1: a resident grid of wgs_per_cu workgroups
+ *               per CU pulls tiles from per-XCD queues in the same order (the queues live in the
+ *               workspace and are cleared by a kernel before each launch, so capture is safe)
+ *   wgs_per_cu  persistent grid size per CU, 0..64 (0 = as many as the kernel's resources allow)
+ *   fwd_cull    1 (default): the forward visits candidates in ascending order of a lower bound of
+ *               the Mahalanobis form over the tile and skips, per wave, candidates that cannot
+ *               enter any of the wave's lists; 0: every candidate is ranked at every pixel
+ * Errors: IGS_ERR_INVALID_ARG (NULL or out-of-range fields).
+ */
+typedef struct {
+  int32_t persistent;
+  int32_t wgs_per_cu;
+  int32_t fwd_cull;
+} igs_launch_config;
+igs_status igs_set_launch_config(const igs_launch_config *cfg);
+igs_status igs_get_launch_config(igs_launch_config *cfg);
+
+/*
  * Kernel timers (measurement aid, off by default).  While enabled, every entry point records a
  * pair of HIP events on its stream around each of its phases; igs_timing_read waits for the
  * recorded events, returns the accumulated milliseconds and call counts per phase and, if reset is

@@ -34,7 +34,7 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_render_backward_batched", "igs_l1_batched_workspace_size",
             "igs_l1_loss_grad_batched", "igs_adam_step_batched", "igs_fit_to_render_batched",
             "igs_render_l1", "igs_render_backward_l1", "igs_render_l1_batched",
-            "igs_render_backward_l1_batched")
+            "igs_render_backward_l1_batched", "igs_set_launch_config", "igs_get_launch_config")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce")
 
@@ -46,6 +46,19 @@ class ImageDesc(ctypes.Structure):
                 ("tile_off", ctypes.c_int32), ("gauss_off", ctypes.c_int32),
                 ("l1_block_off", ctypes.c_int32), ("pix_off", ctypes.c_int64),
                 ("reserved", ctypes.c_int64)]
+
+
+class LaunchConfig(ctypes.Structure):
+    """Mirror of igs_launch_config (include/imagegs.h)."""
+    _fields_ = [("persistent", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("fwd_cull", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.persistent, self.wgs_per_cu, self.fwd_cull)
+
+    def __repr__(self):
+        return (f"LaunchConfig(persistent={self.persistent}, wgs_per_cu={self.wgs_per_cu}, "
+                f"fwd_cull={self.fwd_cull})")
 
 
 class IGSError(RuntimeError):
@@ -124,6 +137,10 @@ def lib() -> ctypes.CDLL:
     L.igs_render_backward_l1_batched.argtypes = [vp, dp, vp, i32, i32, i32, i64, vp, sz, vp, vp,
                                                  sz, vp]
     L.igs_render_backward_l1_batched.restype = i32
+    L.igs_set_launch_config.argtypes = [ctypes.POINTER(LaunchConfig)]
+    L.igs_set_launch_config.restype = i32
+    L.igs_get_launch_config.argtypes = [ctypes.POINTER(LaunchConfig)]
+    L.igs_get_launch_config.restype = i32
     L.igs_timing_enable.argtypes = [i32]
     L.igs_timing_enable.restype = i32
     L.igs_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
@@ -265,6 +282,17 @@ def igs_fit_to_render(fit_params, render_params, N, n, H, W, stream=None) -> Non
     _check("igs_fit_to_render", lib().igs_fit_to_render(
         _f32(fit_params, "fit_params"), _f32(render_params, "render_params"), N, n, H, W,
         _stream(stream)))
+
+
+def igs_set_launch_config(persistent: int = 0, wgs_per_cu: int = 0, fwd_cull: int = 1) -> None:
+    cfg = LaunchConfig(persistent, wgs_per_cu, fwd_cull)
+    _check("igs_set_launch_config", lib().igs_set_launch_config(ctypes.byref(cfg)))
+
+
+def igs_get_launch_config() -> LaunchConfig:
+    cfg = LaunchConfig()
+    _check("igs_get_launch_config", lib().igs_get_launch_config(ctypes.byref(cfg)))
+    return cfg
 
 
 def igs_timing_enable(on: bool) -> None:

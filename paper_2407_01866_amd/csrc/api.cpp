@@ -124,6 +124,10 @@ WsLayout ws_layout(const Dims &d) {
   o = align_up(o + sizeof(int64_t));
   L.l1_part = o;
   o = align_up(o + (size_t)d.T * sizeof(double2));
+  L.queue_fwd = o;
+  o = align_up(o + 8 * sizeof(int));
+  L.queue_bwd = o;
+  o = align_up(o + 8 * sizeof(int));
   L.l1_tmp = o;
   L.total = o;
   return L;
@@ -145,6 +149,28 @@ static bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 template <typename T>
 static T *at(void *base, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+}  // namespace igs
+
+namespace igs {
+
+static LaunchConfig g_launch_config{0, 0, 1};
+
+LaunchConfig launch_config() { return g_launch_config; }
+void set_launch_config(const LaunchConfig &c) { g_launch_config = c; }
+
+int persistent_grid(int per_cu, int T) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  int64_t g = (int64_t)cus * std::max(per_cu, 1);
+  const int64_t need = ((int64_t)T + 7) / 8 * 8;
+  g = std::min(g, std::max<int64_t>(need, 8));
+  g = std::max<int64_t>(g / 8 * 8, 8);
+  return (int)g;
 }
 
 }  // namespace igs
@@ -277,7 +303,7 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
     PhaseTimer timer(kPhaseRasterFwd, s);
     IGS_HIP(launch_raster_fwd(ranges, vals, g32a, g32b, g64, params, d, imgs,
                               batched ? order : nullptr, image, slots, aux, target, l1_rec,
-                              l1_part, s));
+                              l1_part, at<int>(workspace, WL.queue_fwd), s));
   }
   if (target) {
     PhaseTimer timer(kPhaseLoss, s);
@@ -316,7 +342,7 @@ igs_status backward_impl(const float *params, const Dims &d, const Images &imgs,
     PhaseTimer timer(kPhaseRasterBwd, s);
     IGS_HIP(launch_raster_bwd(ranges, vals, src, g32a, g64, params, d, imgs,
                               batched ? order : nullptr, image, grad_image, l1_rec, slots, aux,
-                              part, s));
+                              part, at<int>(workspace, WL.queue_bwd), s));
   }
   PhaseTimer timer(kPhaseGradReduce, s);
   IGS_HIP(launch_grad_reduce(params, g32a, g32b, counts, offsets, at<int64_t>(sv, SL.status),
@@ -667,6 +693,23 @@ IGS_API igs_status igs_fit_to_render_batched(const float *fit_params, float *ren
   if (!descs_dev || (N > 0 && (!fit_params || !render_params))) return IGS_ERR_INVALID_ARG;
   IGS_HIP(launch_fit_to_render(fit_params, render_params, (int)N, n, batch_view(descs_dev, B),
                                static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_set_launch_config(const igs_launch_config *cfg) {
+  if (!cfg || (cfg->persistent != 0 && cfg->persistent != 1) || cfg->wgs_per_cu < 0 ||
+      cfg->wgs_per_cu > 64 || (cfg->fwd_cull != 0 && cfg->fwd_cull != 1))
+    return IGS_ERR_INVALID_ARG;
+  set_launch_config(LaunchConfig{cfg->persistent, cfg->wgs_per_cu, cfg->fwd_cull});
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_get_launch_config(igs_launch_config *cfg) {
+  if (!cfg) return IGS_ERR_INVALID_ARG;
+  const LaunchConfig c = launch_config();
+  cfg->persistent = c.persistent;
+  cfg->wgs_per_cu = c.wgs_per_cu;
+  cfg->fwd_cull = c.fwd_cull;
   return IGS_OK;
 }
 

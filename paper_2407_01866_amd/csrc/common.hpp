@@ -38,6 +38,20 @@ constexpr int kScanBlockItems = kScanThreads * kScanItems;
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// Process-wide launch settings of the raster kernels (igs_set_launch_config).  None of them
+// changes a result bit: they choose how tiles are scheduled and whether the forward may skip
+// candidates that provably cannot enter a list.
+struct LaunchConfig {
+  int persistent;  // 0: one workgroup per tile; 1: resident workgroups pulling tiles
+  int wgs_per_cu;  // persistent grid size per CU; <= 0: as many as fit
+  int fwd_cull;    // forward candidate ordering and wave-level culling
+};
+LaunchConfig launch_config();
+void set_launch_config(const LaunchConfig &c);
+// Persistent grid: per_cu workgroups on every CU of the current device, a multiple of 8 (one
+// share per XCD), at least 8, and no more than needed for T tiles (rounded up to 8).
+int persistent_grid(int per_cu, int T);
+
 // One image of a render call.  A batch concatenates its images: the Gaussians of image b are the
 // global indices [gauss_off, gauss_off + N) (parameter row stride = total N of the batch), its
 // tiles [tile_off, tile_off + tiles_x * tiles_y) of the global tile numbering, and its pixels
@@ -115,7 +129,7 @@ struct SavedLayout {
 // Byte offsets inside the caller's workspace.
 struct WsLayout {
   size_t keys, keys_alt, vals_alt, pair_gid, hist, hist_off, scan_tmp, part, order_keys,
-      order_keys_alt, order_vals_alt, order_count, l1_part, l1_tmp, total;
+      order_keys_alt, order_vals_alt, order_count, l1_part, queue_fwd, queue_bwd, l1_tmp, total;
 };
 // Floats per (tile, Gaussian) partial-gradient record of the adjoint: 5 geometry sums and n
 // colour sums, padded to a multiple of four (16-byte aligned records).
@@ -178,7 +192,7 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
                              const float2 *g32b, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
                              float *image, uint16_t *slots, float2 *aux, const float *target,
-                             float2 *l1_rec, double2 *l1_part, hipStream_t s);
+                             float2 *l1_rec, double2 *l1_part, int *queue, hipStream_t s);
 // Per image b: loss_out[2b] = mean |d|, loss_out[2b+1] = mean d^2 from the per-tile sums.
 hipError_t launch_l1_tiles_final(const double2 *l1_part, const Images &imgs, int n,
                                  double *loss_out, hipStream_t s);
@@ -189,7 +203,7 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uin
                              const float4 *g32a, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
                              const float *image, const float *grad_image, const float2 *l1_rec,
-                             const uint16_t *slots, const float2 *aux, float *part,
+                             const uint16_t *slots, const float2 *aux, float *part, int *queue,
                              hipStream_t s);
 hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const float2 *g32b,
                               const uint32_t *counts, const int64_t *offsets,

@@ -107,7 +107,7 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
     Images imgs, const int *__restrict__ tile_order, const float *__restrict__ image_all,
     const float *__restrict__ grad_image_all, const float2 *__restrict__ l1_rec,
     const uint16_t *__restrict__ slots_all, const float2 *__restrict__ aux_all,
-    float *__restrict__ part) {
+    float *__restrict__ part, TileQueue queue) {
   constexpr int ROW = (NC + 3 + 3) & ~3;  // g[0..NC), g.c_r, shift, 1/Z, padding
   constexpr int NACC = 5 + NC;
   constexpr BwdLds L = bwd_lds<NC, KT>();
@@ -123,12 +123,13 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
   uint16_t *s_item = reinterpret_cast<uint16_t *>(smem + L.item);  // [256 * KT] px | j << 8
 
   const int tid = threadIdx.x;
-  const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[blockIdx.x]
-                                                             : xcd_tile(blockIdx.x, T));
+  int idx = 0;
+  for (bool first = true; next_tile_index(queue, T, first, idx); first = false) {
+  const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[idx] : xcd_tile(idx, T));
   const int2 rg = ranges[tile];
   const int start = __builtin_amdgcn_readfirstlane(rg.x);  // uniform over the workgroup
   const int cnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
-  if (cnt <= 0) return;
+  if (cnt <= 0) continue;
   const ImageDesc im = imgs.by_tile(tile);
   const int W = im.W, H = im.H;
   const int64_t HW = (int64_t)H * W;
@@ -352,6 +353,8 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
       }
     }
   }
+  __syncthreads();  // LDS is reused by the next tile
+  }
 }
 
 // Sum over the 16 lanes of a DPP row, into the row's last lane (a fixed tree: shifts by 1, 2, 4
@@ -426,16 +429,32 @@ hipError_t launch_bwd_t(const int2 *ranges, const uint32_t *vals, const uint32_t
                         const float4 *g32a, const double4 *g64, const float *params,
                         const Dims &d, const Images &imgs, const int *tile_order,
                         const float *image, const float *grad_image, const float2 *l1_rec,
-                        const uint16_t *slots, const float2 *aux, float *part, hipStream_t s) {
+                        const uint16_t *slots, const float2 *aux, float *part, int *queue,
+                        hipStream_t s) {
   constexpr size_t lds = bwd_lds<NC, KT>().total;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)raster_bwd_kernel<NC, KT, L1>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  raster_bwd_kernel<NC, KT, L1><<<d.T, kRasterThreads, lds, s>>>(
+  const LaunchConfig cfg = launch_config();
+  TileQueue q{queue, 0};
+  int grid = d.T;
+  if (cfg.persistent) {
+    int per_cu = cfg.wgs_per_cu;
+    if (per_cu <= 0) {
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, (const void *)raster_bwd_kernel<NC, KT, L1>, kRasterThreads, lds);
+      if (e != hipSuccess) return e;
+    }
+    grid = persistent_grid(per_cu, d.T);
+    q.persistent = 1;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(queue), 8, 0u, s);
+    if (e != hipSuccess) return e;
+  }
+  raster_bwd_kernel<NC, KT, L1><<<grid, kRasterThreads, lds, s>>>(
       ranges, vals, src, g32a, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image,
-      grad_image, l1_rec, slots, aux, part);
+      grad_image, l1_rec, slots, aux, part, q);
   return hipGetLastError();
 }
 
@@ -444,12 +463,13 @@ hipError_t launch_bwd_nc(const int2 *ranges, const uint32_t *vals, const uint32_
                          const float4 *g32a, const double4 *g64, const float *params,
                          const Dims &d, const Images &imgs, const int *tile_order,
                          const float *image, const float *grad_image, const float2 *l1_rec,
-                         const uint16_t *slots, const float2 *aux, float *part, hipStream_t s) {
+                         const uint16_t *slots, const float2 *aux, float *part, int *queue,
+                         hipStream_t s) {
   const int kt = pick_kt(d.K);
 #define IGS_BWD_KT(KTV)                                                                         \
   if (kt == KTV)                                                                                \
     return launch_bwd_t<NC, KTV, L1>(ranges, vals, src, g32a, g64, params, d, imgs, tile_order, \
-                                     image, grad_image, l1_rec, slots, aux, part, s);
+                                     image, grad_image, l1_rec, slots, aux, part, queue, s);
   IGS_FOR_EACH_KT(IGS_BWD_KT)
 #undef IGS_BWD_KT
   return hipErrorInvalidValue;
@@ -461,13 +481,13 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uin
                              const float4 *g32a, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
                              const float *image, const float *grad_image, const float2 *l1_rec,
-                             const uint16_t *slots, const float2 *aux, float *part,
+                             const uint16_t *slots, const float2 *aux, float *part, int *queue,
                              hipStream_t s) {
   if (l1_rec != nullptr) {
 #define IGS_BWD_NC(NCV)                                                                        \
   if (d.n <= NCV)                                                                              \
     return launch_bwd_nc<NCV, true>(ranges, vals, src, g32a, g64, params, d, imgs, tile_order, \
-                                    image, grad_image, l1_rec, slots, aux, part, s);
+                                    image, grad_image, l1_rec, slots, aux, part, queue, s);
     IGS_BWD_NC(1)
     IGS_BWD_NC(3)
     IGS_BWD_NC(4)
@@ -480,7 +500,7 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uin
   if (d.n <= NCV)                                                                              \
     return launch_bwd_nc<NCV, false>(ranges, vals, src, g32a, g64, params, d, imgs,            \
                                      tile_order, image, grad_image, nullptr, slots, aux, part, \
-                                     s);
+                                     queue, s);
   IGS_BWD_NC(1)
   IGS_BWD_NC(3)
   IGS_BWD_NC(4)

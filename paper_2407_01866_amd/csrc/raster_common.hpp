@@ -45,4 +45,33 @@ __device__ __forceinline__ int xcd_tile(int bid, int T) {
   return x * q + min(x, r) + k;
 }
 
+// Tile scheduling of the raster kernels.  Queue index idx names tile xcd_tile(idx, T) (or
+// tile_order[idx]).  One workgroup per tile: workgroup b takes index b.  Persistent: a grid of
+// resident workgroups, a multiple of 8, where workgroup b (on XCD b % 8 under the round-robin
+// dispatch) pulls k = counters[b % 8]++ and takes index 8k + b % 8, i.e. the indices the
+// one-per-tile launch would send to the same XCD, in the same order, until they run out.  The
+// counters are zeroed before every persistent launch.
+struct TileQueue {
+  int *counters;  // [8], zero at launch (persistent only)
+  int persistent;
+};
+
+// Advances to the workgroup's next queue index; false when there is none.  Every thread of the
+// workgroup must call it (it synchronizes the workgroup in the persistent mode).
+__device__ __forceinline__ bool next_tile_index(const TileQueue &q, int T, bool first, int &idx) {
+  __shared__ int s_next;
+  if (!q.persistent) {
+    idx = blockIdx.x;
+    return first && idx < T;
+  }
+  __syncthreads();  // every thread has read the previous index
+  if (threadIdx.x == 0) {
+    const int x = blockIdx.x & 7;
+    s_next = atomicAdd(&q.counters[x], 1) * 8 + x;
+  }
+  __syncthreads();
+  idx = s_next;
+  return idx < T;
+}
+
 }  // namespace igs

@@ -148,17 +148,23 @@ __device__ __forceinline__ double2 block_sum2(double a, double b, double *sh,
   return t;  // valid in thread 0
 }
 
-// Register budget: six waves per SIMD (<= 80 VGPRs) for lists of up to 10 keys.
-__host__ __device__ constexpr int fwd_min_waves(int kt) { return kt <= 10 ? 6 : (kt <= 16 ? 4 : 2); }
+// Register budget: six waves per SIMD (<= 80 VGPRs) for lists of up to 10 keys; five with the
+// fused L1 epilogue at 8 and 10 keys, where 80 registers would spill.
+__host__ __device__ constexpr int fwd_min_waves(int kt, bool l1, bool p) {
+  return kt <= 10 ? ((p && kt >= 8) ? 5 : 6) : (kt <= 16 ? 4 : 2);
+}
 
-template <int KT, bool L1>
+// P: persistent scheduling (a compile-time choice so that the one-workgroup-per-tile kernel keeps
+// the register budget of straight-line code).
+template <int KT, bool L1, bool P>
 __global__ __launch_bounds__(kRasterThreads)
-__attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
+__attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
     const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n, int K, int T,
     Images imgs, const int *__restrict__ tile_order, float *__restrict__ image_all,
-    uint16_t *__restrict__ slots_all, float2 *__restrict__ aux_all, L1Out l1) {
+    uint16_t *__restrict__ slots_all, float2 *__restrict__ aux_all, L1Out l1, TileQueue queue,
+    int cull) {
   extern __shared__ __align__(16) unsigned char smem[];
   // ranking data in visiting order (position m of the batch's candidate order)
   float4 *s_pgeo = reinterpret_cast<float4 *>(smem);                  // mu_x, mu_y, A, B
@@ -173,8 +179,10 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
   const int ncp = n;
 
   const int tid = threadIdx.x;
-  const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[blockIdx.x]
-                                                             : xcd_tile(blockIdx.x, T));
+  int idx = 0;
+  if (!P) queue.persistent = 0;
+  for (bool first = true; next_tile_index(queue, T, first, idx); first = false) {
+  const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[idx] : xcd_tile(idx, T));
   const ImageDesc im = imgs.by_tile(tile);
   const int W = im.W, H = im.H;
   const int64_t HW = (int64_t)H * W;
@@ -218,7 +226,12 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
         s64[4 * tid + 3] = c.w;
         for (int ch = 0; ch < n; ++ch) s_col[tid * ncp + ch] = params[(size_t)(5 + ch) * N + gid];
       }
-      // lower bounds of q over each wave's pixel-centre rectangle (16 x 4 centres)
+      // lower bounds of q over each wave's pixel-centre rectangle (16 x 4 centres); without
+      // culling every bound is 0 (nothing is skipped) and the order is the slot order
+      float tile_lb = 0.f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) lbw[w] = 0.f;
+      if (cull) {
       const float A = a.z, B = a.w, C = b.x, D = b.y;
       const float p11 = fmaf(A, A, C * C), p12 = fmaf(A, B, C * D), p22 = fmaf(B, B, D * D);
       const float r1 = fmaf(A, A, B * B), r2 = fmaf(C, C, D * D);  // 1/s_1^2, 1/s_2^2
@@ -227,13 +240,14 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
       const float dxa = ((float)(tx * kTile) + 0.5f) - a.x;
       const float dxb = ((float)(tx * kTile + kTile - 1) + 0.5f) - a.x;
       const float tya = -p12 * dxa * i22, tyb = -p12 * dxb * i22;
-      float tile_lb = 3.0e38f;
+      tile_lb = 3.0e38f;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) {
         const float dya = ((float)(ty * kTile + 4 * w) + 0.5f) - a.y;
         const float dyb = ((float)(ty * kTile + 4 * w + 3) + 0.5f) - a.y;
         lbw[w] = safe_lb(rect_min_q(A, B, C, D, i11, p12, tya, tyb, dxa, dxb, dya, dyb), kappa);
         tile_lb = fminf(tile_lb, lbw[w]);
+      }
       }
       bucket = lb_bucket(tile_lb);
       brank = atomicAdd(&s_bcnt[bucket], 1);
@@ -285,7 +299,6 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
     }
   }
 
-  if (!L1 && !inside) return;
   double l1_abs = 0.0, l1_sq = 0.0;
   if (inside) {
   const int64_t pix = (int64_t)py * W + px;
@@ -316,6 +329,9 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
         mx = s_mu[slot].x;
         my = s_mu[slot].y;
         src[k] = slot;
+        // keeps these LDS loads and the global loads below in their own branches (merging them
+        // into loads through a pointer that is LDS or global miscompiles for gfx950)
+        asm volatile("" ::: "memory");
       } else {
         const uint32_t gid = vals[start + slot];
         const double4 c = g64[gid];
@@ -327,6 +343,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
         mx = a.x;
         my = a.y;
         src[k] = (int)gid;
+        asm volatile("" ::: "memory");
       }
       double e1, e2;
       const double q = quad_form64(fx, fy, mx, my, A, B, C, D, e1, e2);
@@ -335,6 +352,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
       Z += w[k];
     }
   }
+  if constexpr (!P) {
   const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
   const float inv_count = L1 ? (float)(1.0 / ((double)n * (double)HW)) : 0.f;
   float gc = 0.f;
@@ -377,11 +395,83 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT)))) void raster_fwd_kernel(
     if (k < K)
       slots[(int64_t)k * HW + pix] = (k < keff && ts[k] >= 0) ? (uint16_t)min(ts[k], 0xFFFF) : kEmptySlot;
   aux[pix] = make_float2(shift, invZ);
+  } else {
+  const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
+  const float inv_count = L1 ? (float)(1.0 / ((double)n * (double)HW)) : 0.f;
+  float gc = 0.f;
+  uint32_t codes = 0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k)
+    if (k < K)
+      slots[(int64_t)k * HW + pix] = (k < keff && ts[k] >= 0) ? (uint16_t)min(ts[k], 0xFFFF) : kEmptySlot;
+  aux[pix] = make_float2(shift, invZ);
+  // channel-major: every channel sums its retained Gaussians in rank order, then stores the
+  // normalized colour; with the L1 epilogue also the sign of d = c_r - c_t, g . c_r and the loss
+  // sums, in channel order, the next channel's target being loaded one channel ahead.  Entries
+  // past the retained ones have weight 0 and index 0 (a valid member when cnt > 0), so they add
+  // exactly 0 and the sums need no branches.  The LDS and global colour reads stay in separate
+  // loops (a read through a pointer that may be either miscompiles for gfx950).
+  float tcur = tnext;
+  auto finish = [&](int ch, float acc) {
+    if constexpr (L1) {
+      if (ch + 1 < n) tnext = target[(int64_t)(ch + 1) * HW];
+    }
+    const float v = acc * invZ;
+    image[(int64_t)ch * HW + pix] = v;
+    if constexpr (L1) {
+      const double d = (double)v - (double)tcur;
+      const float g = d > 0.0 ? inv_count : (d < 0.0 ? -inv_count : 0.f);
+      codes |= (d > 0.0 ? 1u : (d < 0.0 ? 3u : 0u)) << (2 * ch);
+      gc = fmaf(g, v, gc);
+      l1_abs += fabs(d);
+      l1_sq += d * d;
+    }
+    tcur = tnext;
+  };
+  if (cnt == 0) {
+    for (int ch = 0; ch < n; ++ch) finish(ch, 0.f);
+  } else if (single) {
+    for (int ch = 0; ch < n; ++ch) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) acc = fmaf(w[k], s_col[src[k] * ncp + ch], acc);
+      finish(ch, acc);
+    }
+  } else {
+    for (int ch = 0; ch < n; ++ch) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) acc = fmaf(w[k], params[(size_t)(5 + ch) * N + src[k]], acc);
+      finish(ch, acc);
+    }
+  }
+  if constexpr (L1) l1.rec[im.pix_off + pix] = make_float2(gc, __uint_as_float(codes));
+  }
   }
   if (L1) {
-    __syncthreads();  // LDS staging area is reused for the reduction
-    const double2 t = block_sum2(l1_abs, l1_sq, reinterpret_cast<double *>(smem));
-    if (tid == 0) l1.part[tile] = t;
+    // the tile's loss sums: wave sums by shuffles, then a fixed order over the four waves
+    __shared__ double s_red[2 * kWaves];
+    double a = l1_abs, b = l1_sq;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      a += __shfl_down(a, d, 64);
+      b += __shfl_down(b, d, 64);
+    }
+    if ((tid & 63) == 0) {
+      s_red[2 * wave] = a;
+      s_red[2 * wave + 1] = b;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double2 t = make_double2(0.0, 0.0);
+      for (int k = 0; k < kWaves; ++k) {
+        t.x += s_red[2 * k];
+        t.y += s_red[2 * k + 1];
+      }
+      l1.part[tile] = t;
+    }
+  }
+  __syncthreads();  // LDS is reused by the next tile
   }
 }
 
@@ -419,31 +509,60 @@ __global__ __launch_bounds__(kFinalThreads) void l1_tiles_final_kernel(
   }
 }
 
+template <int KT, bool L1, bool P>
+hipError_t launch_fwd_t(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
+                        const float2 *g32b, const double4 *g64, const float *params,
+                        const Dims &d, const Images &imgs, const int *tile_order, float *image,
+                        uint16_t *slots, float2 *aux, const L1Out &l1, int *queue,
+                        hipStream_t s) {
+  const size_t lds = kFwdLdsFixed + (size_t)d.n * kFwdBatch * sizeof(float);
+  const LaunchConfig cfg = launch_config();
+  TileQueue q{queue, 0};
+  int grid = d.T;
+  if (P) {
+    int per_cu = cfg.wgs_per_cu;
+    if (per_cu <= 0) {
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, (const void *)raster_fwd_kernel<KT, L1, P>, kRasterThreads, lds);
+      if (e != hipSuccess) return e;
+    }
+    grid = persistent_grid(per_cu, d.T);
+    q.persistent = 1;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(queue), 8, 0u, s);
+    if (e != hipSuccess) return e;
+  }
+  raster_fwd_kernel<KT, L1, P><<<grid, kRasterThreads, lds, s>>>(
+      ranges, vals, g32a, g32b, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image, slots,
+      aux, l1, q, cfg.fwd_cull);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                              const float2 *g32b, const double4 *g64, const float *params,
                              const Dims &d, const Images &imgs, const int *tile_order,
                              float *image, uint16_t *slots, float2 *aux, const float *target,
-                             float2 *l1_rec, double2 *l1_part, hipStream_t s) {
-  const size_t lds = kFwdLdsFixed + (size_t)d.n * kFwdBatch * sizeof(float);
+                             float2 *l1_rec, double2 *l1_part, int *queue, hipStream_t s) {
   const int kt = pick_kt(d.K);
   const L1Out l1{target, l1_rec, l1_part};
   const bool fused = target != nullptr;
+  const bool pers = launch_config().persistent != 0;
+#define IGS_FWD_CALL(KTV, L1V, PV)                                                             \
+  return launch_fwd_t<KTV, L1V, PV>(ranges, vals, g32a, g32b, g64, params, d, imgs, tile_order, \
+                                    image, slots, aux, l1, queue, s);
 #define IGS_LAUNCH_FWD(KTV)                                                                    \
   if (kt == KTV) {                                                                             \
-    if (fused)                                                                                 \
-      raster_fwd_kernel<KTV, true><<<d.T, kRasterThreads, lds, s>>>(                           \
-          ranges, vals, g32a, g32b, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image,  \
-          slots, aux, l1);                                                                     \
-    else                                                                                       \
-      raster_fwd_kernel<KTV, false><<<d.T, kRasterThreads, lds, s>>>(                          \
-          ranges, vals, g32a, g32b, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image,  \
-          slots, aux, l1);                                                                     \
-    return hipGetLastError();                                                                  \
+    if (fused) {                                                                               \
+      if (pers) IGS_FWD_CALL(KTV, true, true)                                                  \
+      IGS_FWD_CALL(KTV, true, false)                                                           \
+    }                                                                                          \
+    if (pers) IGS_FWD_CALL(KTV, false, true)                                                   \
+    IGS_FWD_CALL(KTV, false, false)                                                            \
   }
   IGS_FOR_EACH_KT(IGS_LAUNCH_FWD)
 #undef IGS_LAUNCH_FWD
+#undef IGS_FWD_CALL
   return hipErrorInvalidValue;
 }
 

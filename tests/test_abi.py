@@ -99,6 +99,22 @@ def test_render_validates_before_device_work(nat):
     assert L.igs_l1_workspace_size(1000, ctypes.byref(sz)) == 0 and sz.value >= 16
 
 
+def test_launch_config_roundtrip_and_validation(nat):
+    L = nat.lib()
+    try:
+        nat.igs_set_launch_config(1, 6, 0)
+        assert nat.igs_get_launch_config().as_tuple() == (1, 6, 0)
+        for bad in ((2, 0, 1), (0, -1, 1), (0, 65, 1), (0, 0, 2)):
+            with pytest.raises(nat.IGSError) as e:
+                nat.igs_set_launch_config(*bad)
+            assert e.value.status == -1
+        assert nat.igs_get_launch_config().as_tuple() == (1, 6, 0)
+        assert L.igs_set_launch_config(None) == -1 and L.igs_get_launch_config(None) == -1
+    finally:
+        nat.igs_set_launch_config(0, 0, 1)
+    assert nat.igs_get_launch_config().as_tuple() == (0, 0, 1)
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_2407_01866_amd import _native
     monkeypatch.setattr(_native, "_lib", None)

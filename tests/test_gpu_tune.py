@@ -1,0 +1,102 @@
+"""Launch settings (one workgroup per tile or persistent tile queues, forward culling on or off)
+must not change a single output bit, and the autotuner must leave the fitter's state as it was."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2407_01866_amd import synth
+import paper_2407_01866_amd._native as nat
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = [(0, 0, 1), (0, 0, 0), (1, 0, 1), (1, 4, 0), (1, 1, 1), (1, 8, 1)]
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(autouse=True)
+def default_config():
+    yield
+    nat.igs_set_launch_config(0, 0, 1)
+
+
+def _plain_outputs(p, tgt, H, W, K):
+    from paper_2407_01866_amd.render import Renderer
+    d = dev()
+    n, N = p.shape[0] - 5, p.shape[1]
+    r = Renderer(N, n, H, W, K, pair_capacity=40 * N + 4096, device=d)
+    pt = torch.from_numpy(p).to(d)
+    img = torch.empty((n, H, W), device=d)
+    sv = r.new_saved()
+    r.render_into(pt, img, sv)
+    g = torch.from_numpy(synth.gen_grad_image(3, n, H, W)).to(d)
+    gp = torch.empty((5 + n, N), device=d)
+    r.backward_into(pt, img, g, sv, gp)
+    img2 = torch.empty_like(img)
+    sv2 = r.new_saved()
+    loss = torch.zeros(2, dtype=torch.float64, device=d)
+    gp2 = torch.empty_like(gp)
+    r.render_l1_into(pt, torch.from_numpy(tgt).to(d), img2, loss, sv2)
+    r.backward_l1_into(pt, sv2, gp2)
+    torch.cuda.synchronize()
+    assert int(r.status_of(sv)[nat.STAT_OVERFLOW]) == 0
+    return img, r.slots(sv), gp, img2, loss, gp2
+
+
+@pytest.mark.parametrize("H,W,n,N,K", [(512, 384, 3, 3000, 10), (200, 136, 9, 900, 16),
+                                       (70, 90, 1, 300, 1)])
+def test_launch_configs_give_identical_results(H, W, n, N, K):
+    print(f"[tune] H={H} W={W} n={n} N={N} K={K}", flush=True)
+    p = synth.gen_gaussians(31 + N, H, W, N, n)
+    p[3:5, :3] = 200.0                       # a few Gaussians over every tile
+    tgt = synth.gen_image(7, H, W, n, 20) if n % 3 == 0 else \
+        np.random.default_rng(2).random((n, H, W)).astype(np.float32)
+    nat.igs_set_launch_config(0, 0, 1)
+    ref = _plain_outputs(p, tgt, H, W, K)
+    for cfg in CONFIGS[1:]:
+        nat.igs_set_launch_config(*cfg)
+        got = _plain_outputs(p, tgt, H, W, K)
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), cfg
+
+
+def test_launch_configs_batched_identical():
+    from paper_2407_01866_amd.render import BatchRenderer
+    d = dev()
+    sizes = [(64, 96, 300), (130, 47, 150), (16, 16, 20), (256, 180, 1200)]
+    n, K = 3, 10
+    ps = [synth.gen_gaussians(60 + b, H, W, N, n) for b, (H, W, N) in enumerate(sizes)]
+    outs = []
+    for cfg in CONFIGS:
+        nat.igs_set_launch_config(*cfg)
+        br = BatchRenderer(sizes, n, K, pair_capacity=200000, device=d)
+        bp = br.pack_params([torch.from_numpy(q) for q in ps])
+        imgs = br.new_images()
+        sv = br.new_saved()
+        br.render_into(bp, imgs, sv)
+        g = torch.from_numpy(synth.gen_grad_image(5, 1, 1, n * br.P).reshape(-1)).to(d)
+        gp = torch.empty_like(bp)
+        br.backward_into(bp, imgs, g, sv, gp)
+        torch.cuda.synchronize()
+        outs.append((imgs, gp))
+    for cfg, (a, b) in zip(CONFIGS[1:], outs[1:]):
+        assert torch.equal(a, outs[0][0]) and torch.equal(b, outs[0][1]), cfg
+
+
+def test_autotune_restores_fitter_state():
+    from paper_2407_01866_amd.fit import PlainFitter
+    from paper_2407_01866_amd.tune import autotune
+    d = dev()
+    w = synth.workload(0)
+    f = PlainFitter(torch.from_numpy(w.target()).to(d), torch.from_numpy(w.gaussians()).to(d),
+                    w.K, headroom=3.0)
+    f.advance_to(3, use_graph=False)
+    fit0, step0 = f.fit.clone(), f.steps_done()
+    best, times = autotune(f, candidates=[(0, 0, 1), (1, 0, 1)], iters=2, warmup=1)
+    assert best in times and len(times) == 2 and all(t > 0 for t in times.values())
+    assert f.steps_done() == step0 and torch.equal(f.fit, fit0)
+    assert nat.igs_get_launch_config().as_tuple() == best
