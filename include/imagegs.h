@@ -180,6 +180,31 @@ igs_status igs_l1_loss_grad(const float *image, const float *target, int32_t n, 
                             int32_t W, float *grad_image, double *loss_out, void *workspace,
                             size_t ws_bytes, void *stream);
 
+/* Scratch bytes igs_l1_ssim_loss_grad needs for an [n][H][W] image. */
+igs_status igs_l1_ssim_workspace_size(int32_t n, int32_t H, int32_t W, size_t *ws_bytes);
+
+/*
+ * The paper's fitting loss with its SSIM term (Sec. 3.3, Sec. 4.1: L1 + 0.1 L_SSIM), taken as
+ *   L = mean|image - target| + ssim_weight * (1 - SSIM)
+ * where SSIM is the mean, over all n*H*W positions (every channel on its own), of the
+ * structural-similarity map of Wang et al. with an 11 x 11 Gaussian window (sigma 1.5, weights
+ * summing to 1), the images extended by zeros outside [0,H) x [0,W) (one map value per pixel),
+ * C1 = 0.01^2 and C2 = 0.03^2 (values in [0, 1] units).  Local means and second moments are
+ * accumulated in fp64.
+ *   image, target  [n][H][W] float32 device
+ *   ssim_weight    weight of 1 - SSIM (the paper uses 0.1), finite and >= 0
+ *   grad_image     [n][H][W] float32 device output: dL/d(image), overwritten
+ *   loss_out       device double[4] output: L, mean |image - target|, mean squared error, SSIM
+ *   workspace      device scratch of at least igs_l1_ssim_workspace_size bytes (three fp32
+ *                  partial-derivative maps and the per-block sums)
+ * Deterministic (fixed-order reductions).  Errors: IGS_ERR_INVALID_ARG, IGS_ERR_WORKSPACE,
+ * IGS_ERR_HIP.
+ */
+igs_status igs_l1_ssim_loss_grad(const float *image, const float *target, int32_t n, int32_t H,
+                                 int32_t W, double ssim_weight, float *grad_image,
+                                 double *loss_out, void *workspace, size_t ws_bytes,
+                                 void *stream);
+
 /*
  * One Adam step (Sec. 4.1: Adam with constant per-group learning rates) in the fitter's
  * parameterization, fused with the chain rules from the renderer's units and the clipping of

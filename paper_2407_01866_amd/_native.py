@@ -34,7 +34,8 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_render_backward_batched", "igs_l1_batched_workspace_size",
             "igs_l1_loss_grad_batched", "igs_adam_step_batched", "igs_fit_to_render_batched",
             "igs_render_l1", "igs_render_backward_l1", "igs_render_l1_batched",
-            "igs_render_backward_l1_batched", "igs_set_launch_config", "igs_get_launch_config")
+            "igs_render_backward_l1_batched", "igs_set_launch_config", "igs_get_launch_config",
+            "igs_l1_ssim_workspace_size", "igs_l1_ssim_loss_grad")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce")
 
@@ -98,6 +99,11 @@ def lib() -> ctypes.CDLL:
     L.igs_l1_workspace_size.restype = i32
     L.igs_l1_loss_grad.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]
     L.igs_l1_loss_grad.restype = i32
+    L.igs_l1_ssim_workspace_size.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+    L.igs_l1_ssim_workspace_size.restype = i32
+    L.igs_l1_ssim_loss_grad.argtypes = [vp, vp, i32, i32, i32, ctypes.c_double, vp, vp, vp, sz,
+                                        vp]
+    L.igs_l1_ssim_loss_grad.restype = i32
     L.igs_adam_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, f32, f32, f32, f32,
                                 f32, f32, f32, f32, f32, vp]
     L.igs_adam_step.restype = i32
@@ -259,6 +265,23 @@ def igs_l1_loss_grad(image, target, n, H, W, grad_image, loss_out, workspace, ws
     _check("igs_l1_loss_grad", lib().igs_l1_loss_grad(
         _f32(image, "image"), _f32(target, "target"), n, H, W, _f32(grad_image, "grad_image"),
         _ptr(loss_out), _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_l1_ssim_workspace_size(n: int, H: int, W: int) -> int:
+    ws = ctypes.c_size_t(0)
+    _check("igs_l1_ssim_workspace_size",
+           lib().igs_l1_ssim_workspace_size(n, H, W, ctypes.byref(ws)))
+    return ws.value
+
+
+def igs_l1_ssim_loss_grad(image, target, n, H, W, ssim_weight, grad_image, loss_out, workspace,
+                          ws_bytes, stream=None) -> None:
+    if loss_out.dtype != torch.float64 or loss_out.numel() < 4:
+        raise TypeError("loss_out must be float64[4]")
+    _check("igs_l1_ssim_loss_grad", lib().igs_l1_ssim_loss_grad(
+        _f32(image, "image"), _f32(target, "target"), n, H, W, float(ssim_weight),
+        _f32(grad_image, "grad_image"), _ptr(loss_out), _ptr(workspace), ws_bytes,
+        _stream(stream)))
 
 
 def igs_adam_step(fit_params, render_params, grad_render, m, v, step, N, n, H, W, lr_mu, lr_theta,

@@ -603,6 +603,45 @@ IGS_API igs_status igs_l1_loss_grad(const float *image, const float *target, int
   return IGS_OK;
 }
 
+namespace {
+struct SsimWs {
+  size_t d_mx, d_exx, d_exy, partial, total;
+};
+SsimWs ssim_ws(int n, int H, int W) {
+  const size_t plane = align_up((size_t)n * H * W * sizeof(float));
+  SsimWs L{};
+  L.d_mx = 0;
+  L.d_exx = plane;
+  L.d_exy = 2 * plane;
+  L.partial = 3 * plane;
+  L.total = L.partial + align_up((size_t)ssim_blocks(n, H, W) * 3 * sizeof(double));
+  return L;
+}
+}  // namespace
+
+IGS_API igs_status igs_l1_ssim_workspace_size(int32_t n, int32_t H, int32_t W, size_t *ws_bytes) {
+  if (n < 1 || H < 1 || W < 1 || !ws_bytes) return IGS_ERR_INVALID_ARG;
+  *ws_bytes = ssim_ws(n, H, W).total;
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_l1_ssim_loss_grad(const float *image, const float *target, int32_t n,
+                                         int32_t H, int32_t W, double ssim_weight,
+                                         float *grad_image, double *loss_out, void *workspace,
+                                         size_t ws_bytes, void *stream) {
+  if (n < 1 || H < 1 || W < 1 || !image || !target || !grad_image || !loss_out || !workspace ||
+      !(ssim_weight >= 0.0 && ssim_weight <= 1.0e30))
+    return IGS_ERR_INVALID_ARG;
+  const SsimWs L = ssim_ws(n, H, W);
+  if (ws_bytes < L.total) return IGS_ERR_WORKSPACE;
+  PhaseTimer timer(kPhaseLoss, static_cast<hipStream_t>(stream));
+  IGS_HIP(launch_l1_ssim(image, target, n, H, W, ssim_weight, grad_image,
+                         at<float>(workspace, L.d_mx), at<float>(workspace, L.d_exx),
+                         at<float>(workspace, L.d_exy), at<double>(workspace, L.partial),
+                         loss_out, static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
 IGS_API igs_status igs_adam_step(float *fit_params, float *render_params, const float *grad_render,
                                  float *m, float *v, int32_t *step, const int64_t *skip_flag,
                                  int32_t N, int32_t n,

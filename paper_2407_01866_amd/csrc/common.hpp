@@ -211,6 +211,12 @@ hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const flo
                               float *grad_params, hipStream_t s);
 
 // loss_adam.hip
+// SSIM term of the loss (ssim.hip): blocks of the stencil kernels for an [n][H][W] image, and
+// the forward, final reduction and backward kernels of one call.
+int64_t ssim_blocks(int n, int H, int W);
+hipError_t launch_l1_ssim(const float *image, const float *target, int n, int H, int W,
+                          double weight, float *grad, float *d_mx, float *d_exx, float *d_exy,
+                          double *partial, double *loss_out, hipStream_t s);
 int l1_blocks(int64_t count);
 hipError_t launch_l1(const float *image, const float *target, int64_t count, float *grad,
                      double *partials, double *loss_out, hipStream_t s);

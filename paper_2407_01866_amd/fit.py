@@ -1,6 +1,7 @@
 """Fitting loop around the renderer (Image-GS Sec. 3.3 and Sec. 4.1): every iteration renders the
-Gaussians, takes the L1 loss gradient against the target (fused into the render pass for up to 16
-channels), runs the adjoint and applies one Adam step with the paper's constant per-group
+Gaussians, takes the loss gradient against the target (L1, fused into the render pass for up to
+16 channels, or the paper's L1 + 0.1 SSIM as a separate stencil step), runs the adjoint and
+applies one Adam step with the paper's constant per-group
 learning rates, in the fitter's parameterization (mean normalized to [0,1]^2, inverse scales
 1/s).  Every step is a libimagegs kernel; an
 iteration enqueues with no host synchronization and can be captured as one HIP graph.
@@ -112,9 +113,18 @@ class PlainFitter(_FitLoop):
 
     def __init__(self, target: torch.Tensor, render_params: torch.Tensor, K: int = 10,
                  adam: Optional[AdamConfig] = None, headroom: float = 1.25,
-                 pair_capacity: Optional[int] = None, fused: Optional[bool] = None):
+                 pair_capacity: Optional[int] = None, fused: Optional[bool] = None,
+                 ssim_weight: float = 0.0):
         if target.dim() != 3:
             raise ValueError("target must be [n][H][W]")
+        # ssim_weight > 0: the loss is L1 + ssim_weight * (1 - SSIM) (the paper uses 0.1); the
+        # SSIM term needs neighbouring pixels of the rendered image, so that path renders, takes
+        # the loss gradient image and runs the adjoint as separate steps
+        self.ssim_weight = float(ssim_weight)
+        if self.ssim_weight < 0:
+            raise ValueError("ssim_weight must be >= 0")
+        if self.ssim_weight > 0 and fused:
+            raise ValueError("the SSIM term is not fused into the render pass")
         self.dev = target.device
         self.target = target.contiguous().float()
         self.n, self.H, self.W = self.target.shape
@@ -123,7 +133,10 @@ class PlainFitter(_FitLoop):
         self.adam = adam or AdamConfig()
         # fused: the forward computes the L1 loss and its gradient record in the same pass and the
         # adjoint reads that record (no gradient image); otherwise render, L1, adjoint separately
-        self.fused = (self.n <= MAX_FUSED_CHANNELS) if fused is None else bool(fused)
+        if self.ssim_weight > 0:
+            self.fused = False
+        else:
+            self.fused = (self.n <= MAX_FUSED_CHANNELS) if fused is None else bool(fused)
         self.rend = render_params.to(self.dev).float().contiguous().clone()
         self.fit = torch.empty_like(self.rend)
         self.fit.copy_(self.rend)
@@ -140,8 +153,14 @@ class PlainFitter(_FitLoop):
         self.image = torch.empty_like(self.target)
         self.grad_image = torch.empty_like(self.target)
         self.grad_params = torch.empty_like(self.rend)
-        self.loss = torch.zeros(2, dtype=torch.float64, device=self.dev)
-        self.l1_ws = _aligned_bytes(nat.igs_l1_workspace_size(self.target.numel()), self.dev)
+        # L1 alone: [mean |x - y|, MSE]; with SSIM: [L, mean |x - y|, MSE, SSIM]
+        self.loss = torch.zeros(4 if self.ssim_weight > 0 else 2, dtype=torch.float64,
+                                device=self.dev)
+        if self.ssim_weight > 0:
+            self.l1_ws = _aligned_bytes(
+                nat.igs_l1_ssim_workspace_size(self.n, self.H, self.W), self.dev)
+        else:
+            self.l1_ws = _aligned_bytes(nat.igs_l1_workspace_size(self.target.numel()), self.dev)
         if pair_capacity is None:
             # size the pair buffer from one render of the initial state, with headroom for growth
             _, saved = self.r.render(self.rend, keep_state=True)
@@ -161,8 +180,13 @@ class PlainFitter(_FitLoop):
             self.r.backward_l1_into(self.rend, self.saved, self.grad_params)
         else:
             self.r.render_into(self.rend, self.image, self.saved)
-            nat.igs_l1_loss_grad(self.image, self.target, self.n, self.H, self.W, self.grad_image,
-                                 self.loss, self.l1_ws, self.l1_ws.numel())
+            if self.ssim_weight > 0:
+                nat.igs_l1_ssim_loss_grad(self.image, self.target, self.n, self.H, self.W,
+                                          self.ssim_weight, self.grad_image, self.loss,
+                                          self.l1_ws, self.l1_ws.numel())
+            else:
+                nat.igs_l1_loss_grad(self.image, self.target, self.n, self.H, self.W,
+                                     self.grad_image, self.loss, self.l1_ws, self.l1_ws.numel())
             self.r.backward_into(self.rend, self.image, self.grad_image, self.saved,
                                  self.grad_params)
         # an iteration whose render overflowed the pair buffer changes nothing (and does not
@@ -175,8 +199,14 @@ class PlainFitter(_FitLoop):
     # --------------------------------------------------------------------------- bookkeeping
 
     def psnr(self) -> float:
-        mse = float(self.loss[1].item())
+        mse = float(self.loss[2 if self.ssim_weight > 0 else 1].item())
         return 10.0 * math.log10(1.0 / mse) if mse > 0 else math.inf
+
+    def ssim(self) -> float:
+        """SSIM of the last iteration's render (only with the SSIM term in the loss)."""
+        if self.ssim_weight <= 0:
+            raise RuntimeError("the loss has no SSIM term")
+        return float(self.loss[3].item())
 
     def state_dict(self) -> dict:
         return {"fit": self.fit.clone(), "m": self.m.clone(), "v": self.v.clone(),

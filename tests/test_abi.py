@@ -99,6 +99,23 @@ def test_render_validates_before_device_work(nat):
     assert L.igs_l1_workspace_size(1000, ctypes.byref(sz)) == 0 and sz.value >= 16
 
 
+def test_l1_ssim_validates_before_device_work(nat):
+    L = nat.lib()
+    sz = ctypes.c_size_t(0)
+    assert L.igs_l1_ssim_workspace_size(0, 8, 8, ctypes.byref(sz)) == -1
+    assert L.igs_l1_ssim_workspace_size(3, 100, 70, ctypes.byref(sz)) == 0
+    # three fp32 maps of the image and the per-block sums
+    assert sz.value >= 3 * 3 * 100 * 70 * 4 + 3 * 8
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation
+    assert L.igs_l1_ssim_loss_grad(None, fake, 3, 8, 8, 0.1, fake, fake, fake, 1 << 20, None) == -1
+    assert L.igs_l1_ssim_loss_grad(fake, fake, 3, 8, 8, -0.1, fake, fake, fake, 1 << 20,
+                                   None) == -1
+    assert L.igs_l1_ssim_loss_grad(fake, fake, 3, 8, 8, float("nan"), fake, fake, fake, 1 << 20,
+                                   None) == -1
+    assert L.igs_l1_ssim_loss_grad(fake, fake, 0, 8, 8, 0.1, fake, fake, fake, 1 << 20, None) == -1
+    assert L.igs_l1_ssim_loss_grad(fake, fake, 3, 8, 8, 0.1, fake, fake, fake, 16, None) == -2
+
+
 def test_launch_config_roundtrip_and_validation(nat):
     L = nat.lib()
     try:
