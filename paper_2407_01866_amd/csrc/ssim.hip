@@ -7,12 +7,17 @@
 // with variances and covariance taken as second moments minus products of means; SSIM is the mean
 // of S over every channel and pixel and L = mean|x - y| + w (1 - SSIM).
 //
-// Forward (ssim_fwd_kernel): per 32 x 16 output tile of one channel plane, x and y are staged in
-// LDS with their 5-pixel halo, the five moments mx, my, E[x^2], E[y^2], E[xy] are blurred by a
-// horizontal then a vertical 11-tap pass, in fp64 (the variances are differences of nearly equal
-// moments and are compared with C2 = 9e-4, so fp32 moments would lose up to four digits), and
-// each pixel writes the partial derivatives of S with respect to mx, E[x^2] and E[xy] (fp32) and
-// adds S, |x - y| and (x - y)^2 to the block's sums.
+// Both kernels walk a strip of 32 output columns and up to 128 rows of one channel plane in
+// chunks of 16 rows.  Each chunk stages its 16 new input rows (with the 5-column halo on either
+// side) through LDS, while the next chunk's rows are already being fetched into registers; a
+// horizontal 11-tap pass turns them into 16 new rows of horizontal sums, appended to the 10 rows
+// kept from the previous chunk (the vertical halo is computed once per strip, not once per
+// chunk), and a vertical 11-tap pass over those 26 rows gives the chunk's outputs.
+//
+// Forward (ssim_fwd_kernel): the five moments mx, my, E[x^2], E[y^2], E[xy] are blurred in fp64
+// (the variances are differences of nearly equal moments compared with C2 = 9e-4, so fp32 moments
+// would lose up to four digits); each pixel writes the partial derivatives of S with respect to
+// mx, E[x^2] and E[xy] (fp32) and adds S, |x - y| and (x - y)^2 to the block's sums.
 // Backward (ssim_bwd_kernel): the three partial maps are blurred with the same window (the window
 // is symmetric and zero outside the image, so the blur is its own adjoint) and combined,
 //   dL/dx = sign(x - y)/count - (w/count)(blur(dS/dmx) + 2 x blur(dS/dE[x^2]) + y blur(dS/dE[xy])).
@@ -24,19 +29,36 @@
 namespace igs {
 namespace {
 
-constexpr int kSsimR = 5;                      // window radius
-constexpr int kSsimTW = 32;                    // output tile width
-constexpr int kSsimTH = 16;                    // output tile height
-constexpr int kSsimInW = kSsimTW + 2 * kSsimR;  // 42
-constexpr int kSsimInH = kSsimTH + 2 * kSsimR;  // 26
+constexpr int kSsimR = 5;                        // window radius
+constexpr int kTaps = 2 * kSsimR + 1;
+constexpr int kStripW = 32;                      // output columns of a strip
+constexpr int kChunkH = 16;                      // output rows per chunk
+constexpr int kChunks = 8;                       // chunks per strip (128 rows)
+constexpr int kStripH = kChunkH * kChunks;
+constexpr int kInW = kStripW + 2 * kSsimR;       // 42 staged columns
+constexpr int kRing = kChunkH + 2 * kSsimR;      // 26 rows of horizontal sums
 constexpr int kSsimThreads = 256;
-constexpr int kRunH = 4;                        // horizontal pass: outputs per thread (one row)
-constexpr int kRunV = 2;                        // vertical pass: outputs per thread (one column)
-constexpr int kHItems = kSsimInH * (kSsimTW / kRunH);  // 208 threads busy in the horizontal pass
-static_assert(kSsimTW / kRunH * kSsimInH <= kSsimThreads, "horizontal pass: one item per thread");
-static_assert(kSsimTW * (kSsimTH / kRunV) == kSsimThreads, "vertical pass: one item per thread");
+constexpr int kRunH = 2;                         // horizontal pass: outputs per thread (one row)
+constexpr int kRunsPerRow = kStripW / kRunH;     // 16
+constexpr int kRunV = 2;                         // vertical pass: outputs per thread (one column)
+constexpr int kStageN = kChunkH * kInW;          // 672 staged values per plane and chunk
+constexpr int kStageRegs = (kStageN + kSsimThreads - 1) / kSsimThreads;  // 3
+static_assert(kChunkH * kRunsPerRow == kSsimThreads, "horizontal pass: one item per thread");
+static_assert(kStripW * (kChunkH / kRunV) == kSsimThreads, "vertical pass: one item per thread");
+static_assert(2 * kSsimR <= kChunkH, "the carried halo rows come from the previous chunk");
 constexpr double kC1 = 0.01 * 0.01;
 constexpr double kC2 = 0.03 * 0.03;
+
+template <typename T>
+struct Win {
+  T w[kSsimR + 1];  // w[j]: weight at offset +-j
+};
+
+// Tap weight for offset k - R of the 11-tap window, k = 0..10.
+template <typename T>
+__device__ __forceinline__ T tap(const Win<T> &w, int k) {
+  return w.w[k < kSsimR ? kSsimR - k : k - kSsimR];
+}
 
 __device__ __forceinline__ double wsum64(double v) {
 #pragma unroll
@@ -44,125 +66,227 @@ __device__ __forceinline__ double wsum64(double v) {
   return v;
 }
 
-// The tile's input region (rows y0 - R .. y0 + TH + R - 1, same for columns) of one plane into
-// LDS, zero outside the image.
-__device__ __forceinline__ void stage_plane(const float *__restrict__ src, int H, int W, int x0,
-                                            int y0, float *dst) {
-  for (int i = threadIdx.x; i < kSsimInH * kSsimInW; i += kSsimThreads) {
-    const int r = i / kSsimInW, c = i - r * kSsimInW;
-    const int h = y0 - kSsimR + r, w = x0 - kSsimR + c;
-    dst[i] = (h >= 0 && h < H && w >= 0 && w < W) ? src[(size_t)h * W + w] : 0.f;
+// Rows row0 .. row0 + nrows - 1, columns x0 - R .. x0 + 32 + R - 1 of NP planes into registers
+// (zero outside the image), then from registers into LDS.  nrows <= 16.
+template <int NP>
+struct Stage {
+  float v[NP][kStageRegs];
+
+  __device__ __forceinline__ void load(const float *const (&src)[NP], int H, int W, int x0,
+                                       int row0, int nrows) {
+#pragma unroll
+    for (int k = 0; k < kStageRegs; ++k) {
+      const int i = threadIdx.x + k * kSsimThreads;
+      const int r = i / kInW, c = i - r * kInW;
+      const int h = row0 + r, w = x0 - kSsimR + c;
+      const bool in = i < nrows * kInW && h >= 0 && h < H && w >= 0 && w < W;
+      const size_t e = in ? (size_t)h * W + w : 0;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) v[p][k] = in ? src[p][e] : 0.f;
+    }
   }
-}
-
-// Tap weight for offset k - R of the 11-tap window, k = 0..10, from the six distinct weights.
-template <typename T>
-__device__ __forceinline__ T tap(const T (&w)[6], int k) {
-  return w[k < kSsimR ? kSsimR - k : k - kSsimR];
-}
-
-template <typename T>
-struct Win {
-  T w[6];  // w[j]: weight at offset +-j
+  __device__ __forceinline__ void store(float (*dst)[kStageN], int nrows) const {
+#pragma unroll
+    for (int k = 0; k < kStageRegs; ++k) {
+      const int i = threadIdx.x + k * kSsimThreads;
+      if (i < nrows * kInW)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) dst[p][i] = v[p][k];
+    }
+  }
 };
 
-__global__ __launch_bounds__(kSsimThreads) void ssim_fwd_kernel(
-    const float *__restrict__ img, const float *__restrict__ tgt, int H, int W, int tiles_x,
-    Win<double> win, float *__restrict__ d_mx, float *__restrict__ d_exx,
-    float *__restrict__ d_exy, double *__restrict__ partial) {
-  __shared__ float s_x[kSsimInH * kSsimInW];
-  __shared__ float s_y[kSsimInH * kSsimInW];
-  __shared__ double s_h[5][kSsimInH * kSsimTW];
-  __shared__ double s_red[3][kSsimThreads / 64];
-
-  const int tile = blockIdx.x;
-  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-  const int x0 = tx * kSsimTW, y0 = ty * kSsimTH;
-  const size_t plane = (size_t)blockIdx.y * H * W;
+// Forward horizontal pass: staged rows 0 .. nrows - 1 of x and y (image rows row0 + r) -> rows
+// ring0 + r of the five moment sums.  Every image row of the strip is staged exactly once, so the
+// L1 and squared-error sums are taken here, over the staged pixels of rows [row_lo, row_hi) and
+// columns < W.
+__device__ __forceinline__ void fwd_horizontal(const float (*s_in)[kStageN],
+                                               double (*s_h)[kRing * kStripW], int nrows,
+                                               int ring0, const Win<double> &win, int row0,
+                                               int row_lo, int row_hi, int x0, int W,
+                                               double &sum_a, double &sum_q) {
   const int tid = threadIdx.x;
-  stage_plane(img + plane, H, W, x0, y0, s_x);
-  stage_plane(tgt + plane, H, W, x0, y0, s_y);
-  __syncthreads();
-
-  // horizontal pass: row r, output columns c0 .. c0 + 3 of the tile
-  if (tid < kHItems) {
-    const int r = tid / (kSsimTW / kRunH), c0 = (tid - r * (kSsimTW / kRunH)) * kRunH;
-    double acc[kRunH][5];
+  if (tid >= nrows * kRunsPerRow) return;
+  const int r = tid / kRunsPerRow, c0 = (tid - r * kRunsPerRow) * kRunH;
+  const int h = row0 + r;
+  if (h >= row_lo && h < row_hi) {
 #pragma unroll
-    for (int o = 0; o < kRunH; ++o)
-#pragma unroll
-      for (int m = 0; m < 5; ++m) acc[o][m] = 0.0;
-#pragma unroll
-    for (int t = 0; t < kRunH + 2 * kSsimR; ++t) {
-      const double xv = (double)s_x[r * kSsimInW + c0 + t];
-      const double yv = (double)s_y[r * kSsimInW + c0 + t];
-      const double v[5] = {xv, yv, xv * xv, yv * yv, xv * yv};  // products exact in fp64
-#pragma unroll
-      for (int o = 0; o < kRunH; ++o) {
-        const int k = t - o;
-        if (k >= 0 && k <= 2 * kSsimR) {
-          const double wk = tap(win.w, k);
-#pragma unroll
-          for (int m = 0; m < 5; ++m) acc[o][m] = fma(wk, v[m], acc[o][m]);
-        }
+    for (int o = 0; o < kRunH; ++o) {
+      if (x0 + c0 + o < W) {
+        const int li = r * kInW + c0 + o + kSsimR;
+        const double d = (double)s_in[0][li] - (double)s_in[1][li];  // exact
+        sum_a += fabs(d);
+        sum_q += d * d;
       }
     }
-#pragma unroll
-    for (int o = 0; o < kRunH; ++o)
-#pragma unroll
-      for (int m = 0; m < 5; ++m) s_h[m][r * kSsimTW + c0 + o] = acc[o][m];
   }
-  __syncthreads();
-
-  // vertical pass: column c, output rows r0, r0 + 1 of the tile
-  const int c = tid & (kSsimTW - 1), r0 = (tid / kSsimTW) * kRunV;
-  double acc[kRunV][5];
+  double acc[kRunH][5];
 #pragma unroll
-  for (int o = 0; o < kRunV; ++o)
+  for (int o = 0; o < kRunH; ++o)
 #pragma unroll
     for (int m = 0; m < 5; ++m) acc[o][m] = 0.0;
 #pragma unroll
-  for (int t = 0; t < kRunV + 2 * kSsimR; ++t) {
-    double v[5];
+  for (int t = 0; t < kRunH + 2 * kSsimR; ++t) {
+    const double xv = (double)s_in[0][r * kInW + c0 + t];
+    const double yv = (double)s_in[1][r * kInW + c0 + t];
+    const double v[5] = {xv, yv, xv * xv, yv * yv, xv * yv};  // products exact in fp64
 #pragma unroll
-    for (int m = 0; m < 5; ++m) v[m] = s_h[m][(r0 + t) * kSsimTW + c];
-#pragma unroll
-    for (int o = 0; o < kRunV; ++o) {
+    for (int o = 0; o < kRunH; ++o) {
       const int k = t - o;
-      if (k >= 0 && k <= 2 * kSsimR) {
-        const double wk = tap(win.w, k);
+      if (k >= 0 && k < kTaps) {
+        const double wk = tap(win, k);
 #pragma unroll
         for (int m = 0; m < 5; ++m) acc[o][m] = fma(wk, v[m], acc[o][m]);
       }
     }
   }
-  double sum_s = 0.0, sum_a = 0.0, sum_q = 0.0;
-  const int w = x0 + c;
 #pragma unroll
-  for (int o = 0; o < kRunV; ++o) {
-    const int h = y0 + r0 + o;
-    if (h < H && w < W) {
-      const double mx = acc[o][0], my = acc[o][1];
-      const double a1 = 2.0 * mx * my + kC1;
-      const double a2 = 2.0 * (acc[o][4] - mx * my) + kC2;
-      const double b1 = mx * mx + my * my + kC1;
-      const double b2 = (acc[o][2] - mx * mx) + (acc[o][3] - my * my) + kC2;
-      const double inv = 1.0 / (b1 * b2);
-      const double s = a1 * a2 * inv;
-      // quotient rule on S = a1 a2 / (b1 b2): d/dmx, d/dE[x^2], d/dE[xy]
-      const double gmx = (2.0 * my * (a2 - a1) - s * 2.0 * mx * (b2 - b1)) * inv;
-      const double gxx = -s * b1 * inv;
-      const double gxy = 2.0 * a1 * inv;
-      const size_t e = plane + (size_t)h * W + w;
-      d_mx[e] = (float)gmx;
-      d_exx[e] = (float)gxx;
-      d_exy[e] = (float)gxy;
-      const int li = (r0 + o + kSsimR) * kSsimInW + c + kSsimR;
-      const double d = (double)s_x[li] - (double)s_y[li];
-      sum_s += s;
-      sum_a += fabs(d);
-      sum_q += d * d;
+  for (int o = 0; o < kRunH; ++o)
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s_h[m][(ring0 + r) * kStripW + c0 + o] = acc[o][m];
+}
+
+// Backward horizontal pass over the three partial-derivative planes.
+__device__ __forceinline__ void bwd_horizontal(const float (*s_in)[kStageN],
+                                               float (*s_h)[kRing * kStripW], int nrows,
+                                               int ring0, const Win<float> &win) {
+  const int tid = threadIdx.x;
+  if (tid >= nrows * kRunsPerRow) return;
+  const int r = tid / kRunsPerRow, c0 = (tid - r * kRunsPerRow) * kRunH;
+  float acc[kRunH][3];
+#pragma unroll
+  for (int o = 0; o < kRunH; ++o)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc[o][m] = 0.f;
+#pragma unroll
+  for (int t = 0; t < kRunH + 2 * kSsimR; ++t) {
+    float v[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) v[m] = s_in[m][r * kInW + c0 + t];
+#pragma unroll
+    for (int o = 0; o < kRunH; ++o) {
+      const int k = t - o;
+      if (k >= 0 && k < kTaps) {
+        const float wk = tap(win, k);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) acc[o][m] = fmaf(wk, v[m], acc[o][m]);
+      }
     }
+  }
+#pragma unroll
+  for (int o = 0; o < kRunH; ++o)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) s_h[m][(ring0 + r) * kStripW + c0 + o] = acc[o][m];
+}
+
+// Vertical pass for column c, chunk rows r0 .. r0 + kRunV - 1: ring rows r0 .. r0 + 2R + 1, one
+// moment at a time in a loop that is not unrolled, so that only one moment's 12 loads are live
+// (unrolled, the compiler issues the loads of every moment first, which exceeds the register
+// budget of the fp64 forward).
+template <typename T, int M>
+__device__ __forceinline__ void vertical(const T (*s_h)[kRing * kStripW], int c, int r0,
+                                         const Win<T> &win, T (&acc)[kRunV][M]) {
+#pragma unroll 1
+  for (int m = 0; m < M; ++m) {
+    T v[kRunV + 2 * kSsimR];
+#pragma unroll
+    for (int t = 0; t < kRunV + 2 * kSsimR; ++t) v[t] = s_h[m][(r0 + t) * kStripW + c];
+    T a[kRunV];
+#pragma unroll
+    for (int o = 0; o < kRunV; ++o) a[o] = T(0);
+#pragma unroll
+    for (int t = 0; t < kRunV + 2 * kSsimR; ++t)
+#pragma unroll
+      for (int o = 0; o < kRunV; ++o) {
+        const int k = t - o;
+        if (k >= 0 && k < kTaps) a[o] = fma(tap(win, k), v[t], a[o]);
+      }
+    // m is uniform: place the results without indexing registers dynamically
+#pragma unroll
+    for (int mm = 0; mm < M; ++mm)
+      if (mm == m)
+#pragma unroll
+        for (int o = 0; o < kRunV; ++o) acc[o][mm] = a[o];
+  }
+}
+
+// Ring rows 16..25 become rows 0..9 for the next chunk.
+template <typename T, int M>
+__device__ __forceinline__ void carry_halo(T (*s_h)[kRing * kStripW]) {
+  constexpr int kCarry = 2 * kSsimR * kStripW;
+  for (int i = threadIdx.x; i < M * kCarry; i += kSsimThreads) {
+    const int m = i / kCarry, j = i - m * kCarry;
+    s_h[m][j] = s_h[m][kChunkH * kStripW + j];
+  }
+}
+
+__device__ __forceinline__ int strip_chunks(int H, int ys) {
+  return min(kChunks, (H - ys + kChunkH - 1) / kChunkH);
+}
+
+// Four workgroups fit a CU's LDS; the register budget is held to match (128 VGPRs).
+__global__ __launch_bounds__(kSsimThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+ssim_fwd_kernel(
+    const float *__restrict__ img, const float *__restrict__ tgt, int H, int W, int strips_x,
+    Win<double> win, float *__restrict__ d_mx, float *__restrict__ d_exx,
+    float *__restrict__ d_exy, double *__restrict__ partial) {
+  __shared__ float s_in[2][kStageN];
+  __shared__ double s_h[5][kRing * kStripW];
+  __shared__ double s_red[3][kSsimThreads / 64];
+
+  const int sy = blockIdx.x / strips_x, sx = blockIdx.x - sy * strips_x;
+  const int x0 = sx * kStripW, ys = sy * kStripH;
+  const size_t plane = (size_t)blockIdx.y * H * W;
+  const float *const src[2] = {img + plane, tgt + plane};
+  const int tid = threadIdx.x;
+  const int nchunks = strip_chunks(H, ys);
+
+  // prologue: the 10 rows above the strip's first output row
+  Stage<2> st;
+  st.load(src, H, W, x0, ys - kSsimR, 2 * kSsimR);
+  st.store(s_in, 2 * kSsimR);
+  st.load(src, H, W, x0, ys + kSsimR, kChunkH);
+  __syncthreads();
+  const int row_hi = min(ys + nchunks * kChunkH, H);
+  double sum_s = 0.0, sum_a = 0.0, sum_q = 0.0;
+  fwd_horizontal(s_in, s_h, 2 * kSsimR, 0, win, ys - kSsimR, ys, row_hi, x0, W, sum_a, sum_q);
+
+  const int c = tid & (kStripW - 1), r0 = (tid / kStripW) * kRunV;
+  const int w = x0 + c;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    __syncthreads();  // the previous horizontal pass has read s_in, the halo carry is done
+    st.store(s_in, kChunkH);
+    __syncthreads();
+    if (ch + 1 < nchunks) st.load(src, H, W, x0, ys + (ch + 1) * kChunkH + kSsimR, kChunkH);
+    fwd_horizontal(s_in, s_h, kChunkH, 2 * kSsimR, win, ys + ch * kChunkH + kSsimR, ys, row_hi,
+                   x0, W, sum_a, sum_q);
+    __syncthreads();
+    double acc[kRunV][5];
+    vertical<double, 5>(s_h, c, r0, win, acc);
+#pragma unroll
+    for (int o = 0; o < kRunV; ++o) {
+      const int h = ys + ch * kChunkH + r0 + o;
+      if (h < H && w < W) {
+        const double mx = acc[o][0], my = acc[o][1];
+        const double a1 = 2.0 * mx * my + kC1;
+        const double a2 = 2.0 * (acc[o][4] - mx * my) + kC2;
+        const double b1 = mx * mx + my * my + kC1;
+        const double b2 = (acc[o][2] - mx * mx) + (acc[o][3] - my * my) + kC2;
+        const double inv = 1.0 / (b1 * b2);
+        const double s = a1 * a2 * inv;
+        // quotient rule on S = a1 a2 / (b1 b2): d/dmx, d/dE[x^2], d/dE[xy]
+        const double gmx = (2.0 * my * (a2 - a1) - s * 2.0 * mx * (b2 - b1)) * inv;
+        const double gxx = -s * b1 * inv;
+        const double gxy = 2.0 * a1 * inv;
+        const size_t e = plane + (size_t)h * W + w;
+        d_mx[e] = (float)gmx;
+        d_exx[e] = (float)gxx;
+        d_exy[e] = (float)gxy;
+        sum_s += s;
+      }
+    }
+    __syncthreads();
+    if (ch + 1 < nchunks) carry_halo<double, 5>(s_h);
   }
   sum_s = wsum64(sum_s);
   sum_a = wsum64(sum_a);
@@ -215,90 +339,57 @@ __global__ __launch_bounds__(1024) void ssim_final_kernel(const double *__restri
 __global__ __launch_bounds__(kSsimThreads) void ssim_bwd_kernel(
     const float *__restrict__ img, const float *__restrict__ tgt,
     const float *__restrict__ d_mx, const float *__restrict__ d_exx,
-    const float *__restrict__ d_exy, int H, int W, int tiles_x, Win<float> win, float l1_scale,
+    const float *__restrict__ d_exy, int H, int W, int strips_x, Win<float> win, float l1_scale,
     float ssim_scale, float *__restrict__ grad) {
-  __shared__ float s_p[3][kSsimInH * kSsimInW];
-  __shared__ float s_h[3][kSsimInH * kSsimTW];
+  __shared__ float s_in[3][kStageN];
+  __shared__ float s_h[3][kRing * kStripW];
 
-  const int tile = blockIdx.x;
-  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-  const int x0 = tx * kSsimTW, y0 = ty * kSsimTH;
+  const int sy = blockIdx.x / strips_x, sx = blockIdx.x - sy * strips_x;
+  const int x0 = sx * kStripW, ys = sy * kStripH;
   const size_t plane = (size_t)blockIdx.y * H * W;
+  const float *const src[3] = {d_mx + plane, d_exx + plane, d_exy + plane};
   const int tid = threadIdx.x;
-  stage_plane(d_mx + plane, H, W, x0, y0, s_p[0]);
-  stage_plane(d_exx + plane, H, W, x0, y0, s_p[1]);
-  stage_plane(d_exy + plane, H, W, x0, y0, s_p[2]);
-  __syncthreads();
+  const int nchunks = strip_chunks(H, ys);
 
-  if (tid < kHItems) {
-    const int r = tid / (kSsimTW / kRunH), c0 = (tid - r * (kSsimTW / kRunH)) * kRunH;
-    float acc[kRunH][3];
-#pragma unroll
-    for (int o = 0; o < kRunH; ++o)
-#pragma unroll
-      for (int m = 0; m < 3; ++m) acc[o][m] = 0.f;
-#pragma unroll
-    for (int t = 0; t < kRunH + 2 * kSsimR; ++t) {
-      float v[3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) v[m] = s_p[m][r * kSsimInW + c0 + t];
-#pragma unroll
-      for (int o = 0; o < kRunH; ++o) {
-        const int k = t - o;
-        if (k >= 0 && k <= 2 * kSsimR) {
-          const float wk = tap(win.w, k);
-#pragma unroll
-          for (int m = 0; m < 3; ++m) acc[o][m] = fmaf(wk, v[m], acc[o][m]);
-        }
-      }
-    }
-#pragma unroll
-    for (int o = 0; o < kRunH; ++o)
-#pragma unroll
-      for (int m = 0; m < 3; ++m) s_h[m][r * kSsimTW + c0 + o] = acc[o][m];
-  }
+  Stage<3> st;
+  st.load(src, H, W, x0, ys - kSsimR, 2 * kSsimR);
+  st.store(s_in, 2 * kSsimR);
+  st.load(src, H, W, x0, ys + kSsimR, kChunkH);
   __syncthreads();
+  bwd_horizontal(s_in, s_h, 2 * kSsimR, 0, win);
 
-  const int c = tid & (kSsimTW - 1), r0 = (tid / kSsimTW) * kRunV;
-  float acc[kRunV][3];
-#pragma unroll
-  for (int o = 0; o < kRunV; ++o)
-#pragma unroll
-    for (int m = 0; m < 3; ++m) acc[o][m] = 0.f;
-#pragma unroll
-  for (int t = 0; t < kRunV + 2 * kSsimR; ++t) {
-    float v[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) v[m] = s_h[m][(r0 + t) * kSsimTW + c];
+  const int c = tid & (kStripW - 1), r0 = (tid / kStripW) * kRunV;
+  const int w = x0 + c;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    __syncthreads();
+    st.store(s_in, kChunkH);
+    __syncthreads();
+    if (ch + 1 < nchunks) st.load(src, H, W, x0, ys + (ch + 1) * kChunkH + kSsimR, kChunkH);
+    bwd_horizontal(s_in, s_h, kChunkH, 2 * kSsimR, win);
+    __syncthreads();
+    float acc[kRunV][3];
+    vertical<float, 3>(s_h, c, r0, win, acc);
 #pragma unroll
     for (int o = 0; o < kRunV; ++o) {
-      const int k = t - o;
-      if (k >= 0 && k <= 2 * kSsimR) {
-        const float wk = tap(win.w, k);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) acc[o][m] = fmaf(wk, v[m], acc[o][m]);
+      const int h = ys + ch * kChunkH + r0 + o;
+      if (h < H && w < W) {
+        const size_t e = plane + (size_t)h * W + w;
+        const float xv = img[e], yv = tgt[e];
+        const float d = xv - yv;  // exact sign; zero only when equal
+        const float sg = d > 0.f ? l1_scale : (d < 0.f ? -l1_scale : 0.f);
+        const float gs = acc[o][0] + 2.f * xv * acc[o][1] + yv * acc[o][2];
+        grad[e] = fmaf(ssim_scale, gs, sg);
       }
     }
-  }
-  const int w = x0 + c;
-#pragma unroll
-  for (int o = 0; o < kRunV; ++o) {
-    const int h = y0 + r0 + o;
-    if (h < H && w < W) {
-      const size_t e = plane + (size_t)h * W + w;
-      const float xv = img[e], yv = tgt[e];
-      const float d = xv - yv;  // exact sign; zero only when equal
-      const float sg = d > 0.f ? l1_scale : (d < 0.f ? -l1_scale : 0.f);
-      const float gs = acc[o][0] + 2.f * xv * acc[o][1] + yv * acc[o][2];
-      grad[e] = fmaf(ssim_scale, gs, sg);
-    }
+    __syncthreads();
+    if (ch + 1 < nchunks) carry_halo<float, 3>(s_h);
   }
 }
 
 template <typename T>
 Win<T> make_window() {
   // exp(-j^2 / (2 sigma^2)), sigma = 1.5, normalized over j = -5..5
-  double raw[6], total = 0.0;
+  double raw[kSsimR + 1], total = 0.0;
   for (int j = 0; j <= kSsimR; ++j) {
     raw[j] = std::exp(-(double)(j * j) / (2.0 * 1.5 * 1.5));
     total += (j == 0 ? 1.0 : 2.0) * raw[j];
@@ -311,24 +402,25 @@ Win<T> make_window() {
 }  // namespace
 
 int64_t ssim_blocks(int n, int H, int W) {
-  const int64_t tx = (W + kSsimTW - 1) / kSsimTW, ty = (H + kSsimTH - 1) / kSsimTH;
-  return tx * ty * n;
+  const int64_t sx = (W + kStripW - 1) / kStripW, sy = (H + kStripH - 1) / kStripH;
+  return sx * sy * n;
 }
 
 hipError_t launch_l1_ssim(const float *image, const float *target, int n, int H, int W,
                           double weight, float *grad, float *d_mx, float *d_exx, float *d_exy,
                           double *partial, double *loss_out, hipStream_t s) {
-  const int tiles_x = (W + kSsimTW - 1) / kSsimTW, tiles_y = (H + kSsimTH - 1) / kSsimTH;
-  const dim3 grid(tiles_x * tiles_y, n);
+  const int strips_x = (W + kStripW - 1) / kStripW, strips_y = (H + kStripH - 1) / kStripH;
+  const dim3 grid(strips_x * strips_y, n);
   const int64_t count = (int64_t)n * H * W;
-  ssim_fwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, H, W, tiles_x,
+  ssim_fwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, H, W, strips_x,
                                                 make_window<double>(), d_mx, d_exx, d_exy,
                                                 partial);
   ssim_final_kernel<<<1, 1024, 0, s>>>(partial, (int64_t)grid.x * grid.y, 1.0 / (double)count,
                                        weight, loss_out);
-  ssim_bwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, d_mx, d_exx, d_exy, H, W, tiles_x,
-                                                make_window<float>(), (float)(1.0 / count),
-                                                (float)(-weight / count), grad);
+  ssim_bwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, d_mx, d_exx, d_exy, H, W,
+                                                strips_x, make_window<float>(),
+                                                (float)(1.0 / count), (float)(-weight / count),
+                                                grad);
   return hipGetLastError();
 }
 
