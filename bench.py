@@ -104,27 +104,97 @@ def paper_context(torch, dev, K=10):
             r.render_into(p, img, None)
         torch.cuda.synchronize()
         render_ms = (time.perf_counter() - t0) / 20 * 1e3
-        f = PlainFitter(tgt, p, K, headroom=3.0)
-        init = f.snapshot()
-        f.advance_to(23, use_graph=False)          # sizes the pair buffer for this trajectory
-        f.restore(init)
-        f.capture()
-        for _ in range(3):
-            f.step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(20):
-            f.step()
-        torch.cuda.synchronize()
-        iter_ms = (time.perf_counter() - t0) / 20 * 1e3
-        ok = f.steps_done() == 23
-        out[f"N{N // 1000}k"] = {"render_ms": round(render_ms, 4),
-                                 "fit_iter_ms": round(iter_ms, 4) if ok else None}
+        rec = {"render_ms": round(render_ms, 4)}
+        for key, wgt in (("fit_iter_ms_l1", 0.0), ("fit_iter_ms_l1_ssim", 0.1)):
+            f = PlainFitter(tgt, p, K, headroom=3.0, ssim_weight=wgt)
+            init = f.snapshot()
+            f.advance_to(23, use_graph=False)      # sizes the pair buffer for this trajectory
+            f.restore(init)
+            f.capture()
+            for _ in range(3):
+                f.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                f.step()
+            torch.cuda.synchronize()
+            iter_ms = (time.perf_counter() - t0) / 20 * 1e3
+            rec[key] = round(iter_ms, 4) if f.steps_done() == 23 else None
+            del f
+        out[f"N{N // 1000}k"] = rec
     out["paper_a6000"] = {"N10k": {"render_ms": 3.7, "fit_iter_ms": 18.74},
                           "N50k": {"render_ms": 4.5, "fit_iter_ms": 26.32},
-                          "note": "Sec. 4.4, NVIDIA A6000, L1+0.1 SSIM loss, Gaussians at init "
-                                  "scale 5 px here"}
+                          "note": "Sec. 4.4, NVIDIA A6000, L1 + 0.1 SSIM loss (compare with "
+                                  "fit_iter_ms_l1_ssim), Gaussians at init scale 5 px here"}
     return out
+
+
+# Algorithmic work of the L1 + SSIM loss per image value (one channel of one pixel): the forward
+# blurs five moments with a separable 11-tap window (5 x 11 horizontal + 5 x 11 vertical
+# multiply-adds and 3 products) and evaluates the map and its three partial derivatives (about
+# 30 operations); the adjoint blurs the three partials (3 x 22) and combines them with the L1
+# sign (6).  Bytes: image and target read twice (16), three fp32 partial maps written and read
+# (24), the gradient written (4).
+SSIM_OPS_PER_VALUE = 5 * 11 * 2 + 3 + 30 + 3 * 22 + 6
+SSIM_BYTES_PER_VALUE = 16 + 24 + 4
+
+
+def _ssim_calls(torch, dev, w, image, target, calls):
+    """Average duration of igs_l1_ssim_loss_grad (library phase timer: HIP events on the call's
+    stream)."""
+    from paper_2407_01866_amd import _native as nat
+    n, H, W = w.n, w.H, w.W
+    g = torch.empty_like(image)
+    loss = torch.zeros(4, dtype=torch.float64, device=dev)
+    ws = torch.empty(nat.igs_l1_ssim_workspace_size(n, H, W), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        nat.igs_l1_ssim_loss_grad(image, target, n, H, W, 0.1, g, loss, ws, ws.numel())
+    torch.cuda.synchronize()
+    nat.igs_timing_read(reset=True)
+    nat.igs_timing_enable(True)
+    torch.cuda._sleep(200_000_000)          # hold the stream while the calls are enqueued
+    for _ in range(calls):
+        nat.igs_l1_ssim_loss_grad(image, target, n, H, W, 0.1, g, loss, ws, ws.numel())
+    ph = nat.igs_timing_read(reset=True)
+    nat.igs_timing_enable(False)
+    call_ms = ph["loss"][0] / ph["loss"][1]
+    log(f"[bench] L1 + SSIM loss call: {call_ms:.4f} ms")
+    return call_ms
+
+
+def ssim_step(torch, dev, w, image, target, calls=20, iters=10):
+    """The paper's full loss, L1 + 0.1 (1 - SSIM), at the benchmark workload: the loss-and-gradient
+    call alone (HIP events on its stream, library phase timer) and a whole fitting iteration with
+    it (render, loss, adjoint, Adam as one HIP graph)."""
+    from paper_2407_01866_amd.fit import PlainFitter
+    call_ms = _ssim_calls(torch, dev, w, image, target, calls)
+    values = w.n * w.H * w.W
+    ops = SSIM_OPS_PER_VALUE * values
+    byts = SSIM_BYTES_PER_VALUE * values
+    f = PlainFitter(target, torch.from_numpy(w.gaussians()).to(dev), w.K, ssim_weight=0.1)
+    init = f.snapshot()
+    f.advance_to(iters + 3, use_graph=False)
+    f.restore(init)
+    f.capture()
+    for _ in range(3):
+        f.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        f.step()
+    torch.cuda.synchronize()
+    iter_ms = (time.perf_counter() - t0) / iters * 1e3
+    ok = f.steps_done() == iters + 3
+    return {"loss": "L1 + 0.1 (1 - SSIM), 11x11 Gaussian window sigma 1.5",
+            "loss_call_ms": round(call_ms, 4),
+            "values_per_s": values / (call_ms * 1e-3),
+            "roofline": {"bound": "alu+hbm", "alu_frac": round(ops / (call_ms * 1e-3) /
+                                                              PEAK_LANE_OPS, 4),
+                         "hbm_frac": round(byts / (call_ms * 1e-3) / HBM_PEAK, 4),
+                         "work_per_call": f"{ops:.4g} lane-ops (fp64 forward moments), "
+                                          f"{byts:.4g} B"},
+            "fit_iter_ms": round(iter_ms, 4) if ok else None,
+            "ssim_after_iters": round(f.ssim(), 6)}
 
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -132,16 +202,18 @@ TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_raster_texture-2048x2048-n9-N
 KERNEL_SOURCES = {"raster_fwd": "raster_fwd.hip", "raster_bwd": "raster_bwd.hip"}
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- "
-             "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0 "
+             "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0 --no-ssim "
              "--launch-config 0,0,1",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'raster|elementwise' -f csv "
              "-d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --steps 3 --warmup 1 "
-             "--no-cpu-baseline --no-context --batch-iters 0 --launch-config 0,0,1",
+             "--no-cpu-baseline --no-context --batch-iters 0 --no-ssim --launch-config 0,0,1",
     "write": "rocprofv3 --pmc WRITE_SIZE (otherwise as fetch) -d gpurun_out/pmc_write -o write",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_copy_fetch -o cf -- "
                   "python3 bench.py --copy-calibration",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_copy_write -o cw -- "
                   "python3 bench.py --copy-calibration",
+    "ssim": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_ssim -o ssim -- "
+            "python3 bench.py --ssim-profile",
 }
 
 
@@ -174,6 +246,20 @@ def summarize_profiles(out_dir):
                      f"{float(r['Percentage']):.2f} |")
     open(os.path.join(PROFILES, "kernel_trace_texture-2048x2048-n9-N100000.md"), "w").write(
         "\n".join(lines) + "\n")
+    ssim_csv = os.path.join(out_dir, "prof_ssim", "ssim_kernel_stats.csv")
+    if os.path.exists(ssim_csv):
+        rows = [r for r in csv.DictReader(open(ssim_csv)) if "ssim" in r["Name"]]
+        lines = ["# Kernel trace: L1 + 0.1 (1 - SSIM) loss and gradient, 2048^2, n=9 (the texture "
+                 "workload's target against a render of its initial Gaussians)", "",
+                 "Command (run from the repository root on the GPU box):", "",
+                 "    " + PROFILE_CMDS["ssim"], "",
+                 "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            name = r["Name"].replace("igs::(anonymous namespace)::", "").split("(")[0]
+            lines.append(f"| {name} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                         f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+        open(os.path.join(PROFILES, "kernel_trace_ssim_texture-2048x2048-n9.md"), "w").write(
+            "\n".join(lines) + "\n")
 
     def counter(sub, fname):
         d = collections.defaultdict(list)
@@ -293,6 +379,10 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=100,
                     help="iterations of the batched-vs-plain comparison (0 skips it)")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--no-ssim", action="store_true",
+                    help="skip the L1 + SSIM loss measurement")
+    ap.add_argument("--ssim-profile", action="store_true",
+                    help="only run 20 L1 + SSIM loss calls at the workload (for kernel traces)")
     ap.add_argument("--launch-config", metavar="P,W,C",
                     help="fixed launch settings (persistent, wgs_per_cu, fwd_cull) instead of "
                          "autotuning (profiling runs use the autotuner's choice)")
@@ -305,8 +395,8 @@ def main():
         summarize_profiles(args.summarize_profiles)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
-              "on a single MI355X; see the sharding notes in the design document)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path runs "
+              "on a single MI355X)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -329,6 +419,10 @@ def main():
     target = torch.from_numpy(w.target()).to(dev)
     params = torch.from_numpy(w.gaussians()).to(dev)
     fitter = PlainFitter(target, params, w.K)
+    if args.ssim_profile:
+        fitter.step_async()                     # a rendered image of the workload
+        _ssim_calls(torch, dev, w, fitter.image, target, 20)
+        return
     init = fitter.snapshot()
     # dry run of the same trajectory, one iteration at a time: sizes the pair buffer for every
     # iteration and records each iteration's work counts (the timed run repeats the trajectory)
@@ -420,6 +514,10 @@ def main():
         log("[bench] CPU oracle baseline")
         g = synth.gen_grad_image(1, w.n, w.H, w.W).astype(np.float64) / (w.n * w.H * w.W)
         cpu = cpu_baseline(w.gaussians(), w.H, w.W, w.K, g, args.cpu_budget)
+    ssim = None
+    if not args.no_ssim:
+        log("[bench] L1 + SSIM loss")
+        ssim = ssim_step(torch, dev, w, fitter.image, fitter.target)
     ctx = None if args.no_context else paper_context(torch, dev)
     batch = None
     if args.batch_iters > 0:
@@ -443,7 +541,7 @@ def main():
         "launch_config": {"persistent": tuned[0], "wgs_per_cu": tuned[1], "fwd_cull": tuned[2],
                           "autotune_ms": {str(c): round(t * 1e3, 4) for c, t in tune_times.items()}},
         "roofline": roofline, "roofline_adjoint": roofline_bwd,
-        "cpu_baseline": cpu, "paper_context": ctx,
+        "cpu_baseline": cpu, "ssim_step": ssim, "paper_context": ctx,
         "batched_vs_plain": batch,
     }
     print(json.dumps(out), flush=True)

@@ -25,6 +25,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "raster_common.hpp"
 
 namespace igs {
 namespace {
@@ -33,8 +34,7 @@ constexpr int kSsimR = 5;                        // window radius
 constexpr int kTaps = 2 * kSsimR + 1;
 constexpr int kStripW = 32;                      // output columns of a strip
 constexpr int kChunkH = 16;                      // output rows per chunk
-constexpr int kChunks = 8;                       // chunks per strip (128 rows)
-constexpr int kStripH = kChunkH * kChunks;
+constexpr int kMaxChunks = 8;                    // chunks per strip: at most 128 rows
 constexpr int kInW = kStripW + 2 * kSsimR;       // 42 staged columns
 constexpr int kRing = kChunkH + 2 * kSsimR;      // 26 rows of horizontal sums
 constexpr int kSsimThreads = 256;
@@ -220,26 +220,29 @@ __device__ __forceinline__ void carry_halo(T (*s_h)[kRing * kStripW]) {
   }
 }
 
-__device__ __forceinline__ int strip_chunks(int H, int ys) {
-  return min(kChunks, (H - ys + kChunkH - 1) / kChunkH);
+__device__ __forceinline__ int strip_chunks(int H, int ys, int cps) {
+  return min(cps, (H - ys + kChunkH - 1) / kChunkH);
 }
 
 // Four workgroups fit a CU's LDS; the register budget is held to match (128 VGPRs).
 __global__ __launch_bounds__(kSsimThreads) __attribute__((amdgpu_waves_per_eu(4))) void
 ssim_fwd_kernel(
     const float *__restrict__ img, const float *__restrict__ tgt, int H, int W, int strips_x,
-    Win<double> win, float *__restrict__ d_mx, float *__restrict__ d_exx,
+    int cps, Win<double> win, float *__restrict__ d_mx, float *__restrict__ d_exx,
     float *__restrict__ d_exy, double *__restrict__ partial) {
   __shared__ float s_in[2][kStageN];
   __shared__ double s_h[5][kRing * kStripW];
   __shared__ double s_red[3][kSsimThreads / 64];
 
-  const int sy = blockIdx.x / strips_x, sx = blockIdx.x - sy * strips_x;
-  const int x0 = sx * kStripW, ys = sy * kStripH;
+  // neighbouring strips share their 5-column halos: give each XCD a contiguous run of strips so
+  // the halo re-reads hit that XCD's L2
+  const int strip = xcd_tile(blockIdx.x, gridDim.x);
+  const int sy = strip / strips_x, sx = strip - sy * strips_x;
+  const int x0 = sx * kStripW, ys = sy * cps * kChunkH;
   const size_t plane = (size_t)blockIdx.y * H * W;
   const float *const src[2] = {img + plane, tgt + plane};
   const int tid = threadIdx.x;
-  const int nchunks = strip_chunks(H, ys);
+  const int nchunks = strip_chunks(H, ys, cps);
 
   // prologue: the 10 rows above the strip's first output row
   Stage<2> st;
@@ -336,20 +339,26 @@ __global__ __launch_bounds__(1024) void ssim_final_kernel(const double *__restri
   }
 }
 
-__global__ __launch_bounds__(kSsimThreads) void ssim_bwd_kernel(
+// Eight workgroups fit a CU's LDS; the register budget is held to match (64 VGPRs).
+__global__ __launch_bounds__(kSsimThreads) __attribute__((amdgpu_waves_per_eu(8))) void
+ssim_bwd_kernel(
     const float *__restrict__ img, const float *__restrict__ tgt,
     const float *__restrict__ d_mx, const float *__restrict__ d_exx,
-    const float *__restrict__ d_exy, int H, int W, int strips_x, Win<float> win, float l1_scale,
+    const float *__restrict__ d_exy, int H, int W, int strips_x, int cps, Win<float> win,
+    float l1_scale,
     float ssim_scale, float *__restrict__ grad) {
   __shared__ float s_in[3][kStageN];
   __shared__ float s_h[3][kRing * kStripW];
 
-  const int sy = blockIdx.x / strips_x, sx = blockIdx.x - sy * strips_x;
-  const int x0 = sx * kStripW, ys = sy * kStripH;
+  // neighbouring strips share their 5-column halos: give each XCD a contiguous run of strips so
+  // the halo re-reads hit that XCD's L2
+  const int strip = xcd_tile(blockIdx.x, gridDim.x);
+  const int sy = strip / strips_x, sx = strip - sy * strips_x;
+  const int x0 = sx * kStripW, ys = sy * cps * kChunkH;
   const size_t plane = (size_t)blockIdx.y * H * W;
   const float *const src[3] = {d_mx + plane, d_exx + plane, d_exy + plane};
   const int tid = threadIdx.x;
-  const int nchunks = strip_chunks(H, ys);
+  const int nchunks = strip_chunks(H, ys, cps);
 
   Stage<3> st;
   st.load(src, H, W, x0, ys - kSsimR, 2 * kSsimR);
@@ -365,6 +374,15 @@ __global__ __launch_bounds__(kSsimThreads) void ssim_bwd_kernel(
     st.store(s_in, kChunkH);
     __syncthreads();
     if (ch + 1 < nchunks) st.load(src, H, W, x0, ys + (ch + 1) * kChunkH + kSsimR, kChunkH);
+    float xs[kRunV], ysv[kRunV];  // this chunk's output pixels, fetched before the passes
+#pragma unroll
+    for (int o = 0; o < kRunV; ++o) {
+      const int h = ys + ch * kChunkH + r0 + o;
+      const bool in = h < H && w < W;
+      const size_t e = in ? plane + (size_t)h * W + w : 0;
+      xs[o] = in ? img[e] : 0.f;
+      ysv[o] = in ? tgt[e] : 0.f;
+    }
     bwd_horizontal(s_in, s_h, kChunkH, 2 * kSsimR, win);
     __syncthreads();
     float acc[kRunV][3];
@@ -374,7 +392,7 @@ __global__ __launch_bounds__(kSsimThreads) void ssim_bwd_kernel(
       const int h = ys + ch * kChunkH + r0 + o;
       if (h < H && w < W) {
         const size_t e = plane + (size_t)h * W + w;
-        const float xv = img[e], yv = tgt[e];
+        const float xv = xs[o], yv = ysv[o];
         const float d = xv - yv;  // exact sign; zero only when equal
         const float sg = d > 0.f ? l1_scale : (d < 0.f ? -l1_scale : 0.f);
         const float gs = acc[o][0] + 2.f * xv * acc[o][1] + yv * acc[o][2];
@@ -401,24 +419,37 @@ Win<T> make_window() {
 
 }  // namespace
 
+// Chunks per strip: the tallest strips (at most 128 rows, least halo recomputation) that still
+// give at least 2048 workgroups (two rounds of four per CU), so small images fill the GPU.
+static int ssim_chunks_per_strip(int n, int H, int W) {
+  const int64_t sx = (W + kStripW - 1) / kStripW, rows = (H + kChunkH - 1) / kChunkH;
+  int cps = kMaxChunks;
+  while (cps > 1 && sx * ((rows + cps - 1) / cps) * n < 2048) --cps;
+  return cps;
+}
+
 int64_t ssim_blocks(int n, int H, int W) {
-  const int64_t sx = (W + kStripW - 1) / kStripW, sy = (H + kStripH - 1) / kStripH;
+  const int cps = ssim_chunks_per_strip(n, H, W);
+  const int64_t sx = (W + kStripW - 1) / kStripW;
+  const int64_t sy = (H + cps * kChunkH - 1) / (cps * kChunkH);
   return sx * sy * n;
 }
 
 hipError_t launch_l1_ssim(const float *image, const float *target, int n, int H, int W,
                           double weight, float *grad, float *d_mx, float *d_exx, float *d_exy,
                           double *partial, double *loss_out, hipStream_t s) {
-  const int strips_x = (W + kStripW - 1) / kStripW, strips_y = (H + kStripH - 1) / kStripH;
+  const int cps = ssim_chunks_per_strip(n, H, W);
+  const int strips_x = (W + kStripW - 1) / kStripW;
+  const int strips_y = (H + cps * kChunkH - 1) / (cps * kChunkH);
   const dim3 grid(strips_x * strips_y, n);
   const int64_t count = (int64_t)n * H * W;
-  ssim_fwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, H, W, strips_x,
+  ssim_fwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, H, W, strips_x, cps,
                                                 make_window<double>(), d_mx, d_exx, d_exy,
                                                 partial);
   ssim_final_kernel<<<1, 1024, 0, s>>>(partial, (int64_t)grid.x * grid.y, 1.0 / (double)count,
                                        weight, loss_out);
   ssim_bwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, d_mx, d_exx, d_exy, H, W,
-                                                strips_x, make_window<float>(),
+                                                strips_x, cps, make_window<float>(),
                                                 (float)(1.0 / count), (float)(-weight / count),
                                                 grad);
   return hipGetLastError();
