@@ -6,5 +6,7 @@ package.  It shares no code with the HIP implementation in ``paper_2407_01866_am
 * ``cref``   - ctypes wrapper of ``oracle.c`` (brute-force FP64 render + adjoint, OpenMP);
 * ``dense``  - an independent NumPy FP64 evaluation of the same definition for tiny inputs;
 * ``fitref`` - NumPy FP64 L1 loss/gradient, PSNR and the Adam step of the fitter;
-* ``ssimref`` - NumPy FP64 SSIM map, the L1 + 0.1 SSIM loss and its gradient.
+* ``ssimref`` - NumPy FP64 SSIM map, the L1 + 0.1 SSIM loss and its gradient;
+* ``initref`` - NumPy FP64 content-adaptive initialization (Eq. 6), error-guided addition
+  (Eq. 7) and the progressive schedule.
 """
