@@ -205,6 +205,49 @@ igs_status igs_l1_ssim_loss_grad(const float *image, const float *target, int32_
                                  double *loss_out, void *workspace, size_t ws_bytes,
                                  void *stream);
 
+/* Scratch bytes igs_init_gaussians / igs_add_gaussians need for an H x W image. */
+igs_status igs_place_workspace_size(int32_t H, int32_t W, size_t *ws_bytes);
+
+/*
+ * Content-adaptive initialization (Sec. 3.3, Eq. 6; Sec. 4.1): draws `count` pixels, each
+ * independently with probability
+ *   P(x) = (1 - lambda_init) |grad I(x)| / sum_x |grad I| + lambda_init / (H W)
+ * where grad I is the per-channel central difference of the target inside the image and the
+ * one-sided difference at its border (zero along an axis of length 1) and |.| the Euclidean norm
+ * over both directions and all channels (uniform if the target has no gradient).  Pixel i is the
+ * first pixel, in row-major order, whose cumulative probability exceeds uniforms[i].  The new
+ * Gaussian j = first + i sits at the pixel centre (w + 1/2, h + 1/2) with rotation 0, both
+ * scales `scale` pixels (the paper uses 5) and the target's colour at that pixel.
+ *   target         [n][H][W] float32 device
+ *   lambda_init    in [0, 1] (the paper uses 0.3)
+ *   uniforms       device float32[count], each in [0, 1) (the caller's random numbers)
+ *   render_params  [5+n][N_total] float32 device: columns [first, first + count) are written in
+ *                  igs_render's units; other columns are untouched
+ *   fit_params     NULL, or [5+n][N_total] float32 device: the same columns in the fitter's
+ *                  parameterization (mean / (W, H), 1 / scale), as igs_adam_step keeps them
+ *   workspace      device scratch of at least igs_place_workspace_size bytes
+ * Deterministic.  Errors: IGS_ERR_INVALID_ARG (shapes, first + count > N_total, scale <= 0,
+ * lambda outside [0, 1]), IGS_ERR_WORKSPACE, IGS_ERR_HIP.
+ */
+igs_status igs_init_gaussians(const float *target, int32_t n, int32_t H, int32_t W,
+                              double lambda_init, const float *uniforms, int32_t count,
+                              float scale, float *render_params, float *fit_params,
+                              int32_t N_total, int32_t first, void *workspace, size_t ws_bytes,
+                              void *stream);
+
+/*
+ * Error-guided addition of Gaussians (Sec. 3.3, Eq. 7; Sec. 4.1): as igs_init_gaussians, with
+ * pixels drawn with probability P(x) = e(x) / sum_x e, e(x) = sum over channels of
+ * |image - target| (uniform if the image equals the target); new Gaussians are initialized like
+ * the content-adaptive ones (pixel centre, rotation 0, `scale` pixels, the target's colour).
+ *   image  [n][H][W] float32 device: the current render
+ * Errors: as igs_init_gaussians.
+ */
+igs_status igs_add_gaussians(const float *image, const float *target, int32_t n, int32_t H,
+                             int32_t W, const float *uniforms, int32_t count, float scale,
+                             float *render_params, float *fit_params, int32_t N_total,
+                             int32_t first, void *workspace, size_t ws_bytes, void *stream);
+
 /*
  * One Adam step (Sec. 4.1: Adam with constant per-group learning rates) in the fitter's
  * parameterization, fused with the chain rules from the renderer's units and the clipping of

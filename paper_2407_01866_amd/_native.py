@@ -35,7 +35,8 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_l1_loss_grad_batched", "igs_adam_step_batched", "igs_fit_to_render_batched",
             "igs_render_l1", "igs_render_backward_l1", "igs_render_l1_batched",
             "igs_render_backward_l1_batched", "igs_set_launch_config", "igs_get_launch_config",
-            "igs_l1_ssim_workspace_size", "igs_l1_ssim_loss_grad")
+            "igs_l1_ssim_workspace_size", "igs_l1_ssim_loss_grad", "igs_place_workspace_size",
+            "igs_init_gaussians", "igs_add_gaussians")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce")
 
@@ -104,6 +105,14 @@ def lib() -> ctypes.CDLL:
     L.igs_l1_ssim_loss_grad.argtypes = [vp, vp, i32, i32, i32, ctypes.c_double, vp, vp, vp, sz,
                                         vp]
     L.igs_l1_ssim_loss_grad.restype = i32
+    L.igs_place_workspace_size.argtypes = [i32, i32, ctypes.POINTER(sz)]
+    L.igs_place_workspace_size.restype = i32
+    L.igs_init_gaussians.argtypes = [vp, i32, i32, i32, ctypes.c_double, vp, i32, f32, vp, vp, i32,
+                                     i32, vp, sz, vp]
+    L.igs_init_gaussians.restype = i32
+    L.igs_add_gaussians.argtypes = [vp, vp, i32, i32, i32, vp, i32, f32, vp, vp, i32, i32, vp, sz,
+                                    vp]
+    L.igs_add_gaussians.restype = i32
     L.igs_adam_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, f32, f32, f32, f32,
                                 f32, f32, f32, f32, f32, vp]
     L.igs_adam_step.restype = i32
@@ -282,6 +291,30 @@ def igs_l1_ssim_loss_grad(image, target, n, H, W, ssim_weight, grad_image, loss_
         _f32(image, "image"), _f32(target, "target"), n, H, W, float(ssim_weight),
         _f32(grad_image, "grad_image"), _ptr(loss_out), _ptr(workspace), ws_bytes,
         _stream(stream)))
+
+
+def igs_place_workspace_size(H: int, W: int) -> int:
+    ws = ctypes.c_size_t(0)
+    _check("igs_place_workspace_size", lib().igs_place_workspace_size(H, W, ctypes.byref(ws)))
+    return ws.value
+
+
+def igs_init_gaussians(target, n, H, W, lambda_init, uniforms, count, scale, render_params,
+                       fit_params, N_total, first, workspace, ws_bytes, stream=None) -> None:
+    _check("igs_init_gaussians", lib().igs_init_gaussians(
+        _f32(target, "target"), n, H, W, float(lambda_init), _f32(uniforms, "uniforms"), count,
+        float(scale), _f32(render_params, "render_params"),
+        None if fit_params is None else _f32(fit_params, "fit_params"), N_total, first,
+        _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_add_gaussians(image, target, n, H, W, uniforms, count, scale, render_params, fit_params,
+                      N_total, first, workspace, ws_bytes, stream=None) -> None:
+    _check("igs_add_gaussians", lib().igs_add_gaussians(
+        _f32(image, "image"), _f32(target, "target"), n, H, W, _f32(uniforms, "uniforms"), count,
+        float(scale), _f32(render_params, "render_params"),
+        None if fit_params is None else _f32(fit_params, "fit_params"), N_total, first,
+        _ptr(workspace), ws_bytes, _stream(stream)))
 
 
 def igs_adam_step(fit_params, render_params, grad_render, m, v, step, N, n, H, W, lr_mu, lr_theta,

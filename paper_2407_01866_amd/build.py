@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["binning.hip", "scan.hip", "radix_sort.hip", "raster_fwd.hip", "raster_bwd.hip",
-           "loss_adam.hip", "ssim.hip", "timing.cpp", "api.cpp"]
+           "loss_adam.hip", "ssim.hip", "place.hip", "timing.cpp", "api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-fvisibility=hidden",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

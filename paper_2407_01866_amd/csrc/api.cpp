@@ -642,6 +642,47 @@ IGS_API igs_status igs_l1_ssim_loss_grad(const float *image, const float *target
   return IGS_OK;
 }
 
+IGS_API igs_status igs_place_workspace_size(int32_t H, int32_t W, size_t *ws_bytes) {
+  if (H < 1 || W < 1 || !ws_bytes) return IGS_ERR_INVALID_ARG;
+  *ws_bytes = place_workspace_bytes((int64_t)H * W);
+  return IGS_OK;
+}
+
+static igs_status place_impl(const float *image, const float *target, int32_t n, int32_t H,
+                             int32_t W, double lam, const float *uniforms, int32_t count,
+                             float scale, float *render_params, float *fit_params,
+                             int32_t N_total, int32_t first, void *workspace, size_t ws_bytes,
+                             void *stream) {
+  if (n < 1 || n > IGS_MAX_CHANNELS || H < 1 || W < 1 || !target || count < 0 || first < 0 ||
+      N_total < 0 || (int64_t)first + count > N_total || !(scale > 0.f && scale < 1e30f) ||
+      !(lam >= 0.0 && lam <= 1.0) || !workspace)
+    return IGS_ERR_INVALID_ARG;
+  if (count > 0 && (!uniforms || !render_params)) return IGS_ERR_INVALID_ARG;
+  if (ws_bytes < place_workspace_bytes((int64_t)H * W)) return IGS_ERR_WORKSPACE;
+  IGS_HIP(launch_place(image, target, n, H, W, lam, uniforms, count, scale, render_params,
+                       fit_params, N_total, first, workspace, static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_init_gaussians(const float *target, int32_t n, int32_t H, int32_t W,
+                                      double lambda_init, const float *uniforms, int32_t count,
+                                      float scale, float *render_params, float *fit_params,
+                                      int32_t N_total, int32_t first, void *workspace,
+                                      size_t ws_bytes, void *stream) {
+  return place_impl(nullptr, target, n, H, W, lambda_init, uniforms, count, scale, render_params,
+                    fit_params, N_total, first, workspace, ws_bytes, stream);
+}
+
+IGS_API igs_status igs_add_gaussians(const float *image, const float *target, int32_t n,
+                                     int32_t H, int32_t W, const float *uniforms, int32_t count,
+                                     float scale, float *render_params, float *fit_params,
+                                     int32_t N_total, int32_t first, void *workspace,
+                                     size_t ws_bytes, void *stream) {
+  if (!image) return IGS_ERR_INVALID_ARG;
+  return place_impl(image, target, n, H, W, 0.0, uniforms, count, scale, render_params,
+                    fit_params, N_total, first, workspace, ws_bytes, stream);
+}
+
 IGS_API igs_status igs_adam_step(float *fit_params, float *render_params, const float *grad_render,
                                  float *m, float *v, int32_t *step, const int64_t *skip_flag,
                                  int32_t N, int32_t n,

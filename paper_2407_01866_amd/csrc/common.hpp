@@ -211,6 +211,15 @@ hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const flo
                               float *grad_params, hipStream_t s);
 
 // loss_adam.hip
+// Placement of new Gaussians (place.hip): workspace bytes for an H x W image; image == nullptr
+// samples Eq. 6 from the target's gradient, otherwise Eq. 7 from |image - target|.
+size_t place_workspace_bytes(int64_t HW);
+hipError_t launch_place(const float *image, const float *target, int n, int H, int W,
+                        double lam, const float *uniforms, int count, float scale,
+                        float *render_params, float *fit_params, int N_total, int first,
+                        void *ws, hipStream_t s);
+hipError_t scan_f64(const double *in, double *out, int64_t n, double *temp, hipStream_t s);
+
 // SSIM term of the loss (ssim.hip): blocks of the stencil kernels for an [n][H][W] image, and
 // the forward, final reduction and backward kernels of one call.
 int64_t ssim_blocks(int n, int H, int W);

@@ -1,5 +1,6 @@
 // Exclusive prefix sums (reduce-then-scan, recursive over block totals), used for the per-Gaussian
-// pair offsets and the radix-sort digit offsets.
+// pair offsets, the radix-sort digit offsets and the sampling distributions of the placement
+// kernels (fp64, in a fixed order).
 #include "common.hpp"
 
 namespace igs {
@@ -104,6 +105,10 @@ hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t 
 hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *temp,
                            hipStream_t s) {
   return scan_rec<uint32_t, uint32_t>(in, out, n, temp, s);
+}
+
+hipError_t scan_f64(const double *in, double *out, int64_t n, double *temp, hipStream_t s) {
+  return scan_rec<double, double>(in, out, n, temp, s);
 }
 
 }  // namespace igs

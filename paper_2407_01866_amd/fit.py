@@ -21,6 +21,24 @@ from .render import Renderer, _aligned_bytes
 LR_MU, LR_COLOR, LR_SCALE, LR_THETA = 5e-4, 5e-3, 2e-3, 2e-3
 # the fused render+L1 entry points record 2-bit loss signs per channel
 MAX_FUSED_CHANNELS = 16
+# Sec. 4.1: initial scale of every placed Gaussian (pixels), weight of the uniform term of Eq. 6,
+# and the period of the error-guided additions
+INIT_SCALE = 5.0
+LAMBDA_INIT = 0.3
+GROW_EVERY = 500
+
+
+def progressive_growth(budget: int, every: int = GROW_EVERY) -> List[Tuple[int, int]]:
+    """(step, count) of the error-guided additions after the initial budget // 2 Gaussians
+    (Sec. 4.1): budget // 8 more every 500 steps until the budget is reached (the last addition
+    tops up what integer division leaves)."""
+    out, active, k = [], budget // 2, 1
+    while active < budget:
+        add = min(max(budget // 8, 1), budget - active)
+        out.append((k * every, add))
+        active += add
+        k += 1
+    return out
 
 
 @dataclass
@@ -169,6 +187,87 @@ class PlainFitter(_FitLoop):
         self.saved = self.r.new_saved()
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self.status_host = torch.zeros(8, dtype=torch.int64).pin_memory()
+        self.headroom = headroom
+        self.growth: List[Tuple[int, int]] = []     # pending (step, count) additions
+        self.gen: Optional[torch.Generator] = None
+        self.scale_init = INIT_SCALE
+        self.place_ws: Optional[torch.Tensor] = None
+
+    @classmethod
+    def from_target(cls, target: torch.Tensor, budget: int, K: int = 10, progressive: bool = True,
+                    lambda_init: float = LAMBDA_INIT, scale: float = INIT_SCALE, seed: int = 0,
+                    **kw) -> "PlainFitter":
+        """The paper's fit from scratch (Sec. 3.3, Sec. 4.1): budget // 2 Gaussians (all of them
+        when not progressive) placed by content-adaptive sampling (Eq. 6), then budget // 8 more
+        every 500 iterations placed where the render's error is largest (Eq. 7).  Random numbers
+        come from a device generator seeded with ``seed``."""
+        target = target.contiguous().float()
+        n, H, W = target.shape
+        dev = target.device
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed)
+        N0 = budget // 2 if progressive else budget
+        rp = torch.empty((5 + n, N0), dtype=torch.float32, device=dev)
+        ws = _aligned_bytes(nat.igs_place_workspace_size(H, W), dev)
+        u = torch.rand(N0, generator=gen, device=dev)
+        nat.igs_init_gaussians(target, n, H, W, lambda_init, u, N0, scale, rp, None, N0, 0, ws,
+                               ws.numel())
+        f = cls(target, rp, K, **kw)
+        f.gen, f.place_ws, f.scale_init = gen, ws, float(scale)
+        f.growth = progressive_growth(budget) if progressive else []
+        return f
+
+    # ----------------------------------------------------------------------- densification
+
+    def _resize(self, N_new: int) -> None:
+        """Grow (or shrink, when loading a checkpoint) every per-Gaussian buffer to N_new
+        columns, keeping the common columns; new Adam moments are zero."""
+        def cols(t):
+            out = torch.zeros((5 + self.n, N_new), dtype=t.dtype, device=self.dev)
+            k = min(self.N, N_new)
+            out[:, :k] = t[:, :k]
+            return out
+        self.fit, self.rend, self.m, self.v = (cols(t) for t in (self.fit, self.rend, self.m,
+                                                                 self.v))
+        self.grad_params = torch.empty_like(self.rend)
+        self.N = N_new
+        self.r = Renderer(self.N, self.n, self.H, self.W, self.K, device=self.dev)
+        self.graph = None
+
+    def _size_pairs(self) -> None:
+        _, saved = self.r.render(self.rend, keep_state=True)
+        P = int(self.r.status_of(saved)[nat.STAT_PAIRS])
+        self.r.set_capacity(max(1024, int(P * self.headroom)))
+        self.saved = self.r.new_saved()
+
+    def densify(self, count: int) -> None:
+        """Error-guided addition of ``count`` Gaussians (Eq. 7) from the last iteration's render,
+        initialized like the content-adaptive ones (Sec. 4.1); drops the captured graph."""
+        if count <= 0:
+            return
+        if self.gen is None:
+            self.gen = torch.Generator(device=self.dev)
+            self.gen.manual_seed(0)
+        if self.place_ws is None:
+            self.place_ws = _aligned_bytes(nat.igs_place_workspace_size(self.H, self.W),
+                                           self.dev)
+        N_old = self.N
+        self._resize(N_old + count)
+        u = torch.rand(count, generator=self.gen, device=self.dev)
+        nat.igs_add_gaussians(self.image, self.target, self.n, self.H, self.W, u, count,
+                              self.scale_init, self.rend, self.fit, self.N, N_old, self.place_ws,
+                              self.place_ws.numel())
+        self._size_pairs()
+
+    def advance_to(self, target: int, use_graph: bool = True, max_rounds: int = 8) -> None:
+        """As the base loop, with the pending error-guided additions applied when the fit reaches
+        their step."""
+        while self.growth and self.growth[0][0] <= target:
+            step, count = self.growth[0]
+            super().advance_to(step, use_graph, max_rounds)
+            self.growth.pop(0)
+            self.densify(count)
+        super().advance_to(target, use_graph, max_rounds)
 
     # ------------------------------------------------------------------------------- one step
 
@@ -210,14 +309,27 @@ class PlainFitter(_FitLoop):
 
     def state_dict(self) -> dict:
         return {"fit": self.fit.clone(), "m": self.m.clone(), "v": self.v.clone(),
-                "step": self.step_count.clone(), "H": self.H, "W": self.W, "K": self.K}
+                "step": self.step_count.clone(), "H": self.H, "W": self.W, "K": self.K,
+                "growth": list(self.growth),
+                "gen": None if self.gen is None else self.gen.get_state()}
 
     def load_state_dict(self, sd: dict) -> None:
+        N = int(sd["fit"].shape[1])
+        if N != self.N:
+            self._resize(N)
+            self.fit.copy_(sd["fit"])
+            nat.igs_fit_to_render(self.fit, self.rend, self.N, self.n, self.H, self.W)
+            self._size_pairs()
         self.fit.copy_(sd["fit"])
         self.m.copy_(sd["m"])
         self.v.copy_(sd["v"])
         self.step_count.copy_(sd["step"])
         nat.igs_fit_to_render(self.fit, self.rend, self.N, self.n, self.H, self.W)
+        self.growth = list(sd.get("growth", []))
+        if sd.get("gen") is not None:
+            if self.gen is None:
+                self.gen = torch.Generator(device=self.dev)
+            self.gen.set_state(sd["gen"])
 
 
 class BatchFitter(_FitLoop):

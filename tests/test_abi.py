@@ -116,6 +116,30 @@ def test_l1_ssim_validates_before_device_work(nat):
     assert L.igs_l1_ssim_loss_grad(fake, fake, 3, 8, 8, 0.1, fake, fake, fake, 16, None) == -2
 
 
+def test_placement_validates_before_device_work(nat):
+    L = nat.lib()
+    sz = ctypes.c_size_t(0)
+    assert L.igs_place_workspace_size(0, 8, ctypes.byref(sz)) == -1
+    assert L.igs_place_workspace_size(100, 70, ctypes.byref(sz)) == 0 and sz.value >= 2 * 7000 * 8
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation
+    big = 1 << 30
+    # first + count beyond N_total, negative count, bad lambda, bad scale, no target
+    assert L.igs_init_gaussians(fake, 3, 8, 8, 0.3, fake, 10, 5.0, fake, None, 15, 6, fake, big,
+                                None) == -1
+    assert L.igs_init_gaussians(fake, 3, 8, 8, 0.3, fake, -1, 5.0, fake, None, 15, 0, fake, big,
+                                None) == -1
+    assert L.igs_init_gaussians(fake, 3, 8, 8, 1.5, fake, 10, 5.0, fake, None, 15, 0, fake, big,
+                                None) == -1
+    assert L.igs_init_gaussians(fake, 3, 8, 8, 0.3, fake, 10, 0.0, fake, None, 15, 0, fake, big,
+                                None) == -1
+    assert L.igs_init_gaussians(None, 3, 8, 8, 0.3, fake, 10, 5.0, fake, None, 15, 0, fake, big,
+                                None) == -1
+    assert L.igs_init_gaussians(fake, 3, 8, 8, 0.3, fake, 10, 5.0, fake, None, 15, 0, fake, 8,
+                                None) == -2
+    assert L.igs_add_gaussians(None, fake, 3, 8, 8, fake, 10, 5.0, fake, None, 15, 0, fake, big,
+                               None) == -1
+
+
 def test_launch_config_roundtrip_and_validation(nat):
     L = nat.lib()
     try:

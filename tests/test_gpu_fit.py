@@ -173,3 +173,93 @@ def test_overflowed_iteration_is_a_no_op_and_is_repeated():
     f.advance_to(3, use_graph=False)
     assert f.steps_done() == 3 and f.r.cap > 500
     assert not torch.equal(f.fit, fit0)
+
+
+# --------------------------------------------------------------- placement and densification
+
+
+def _target256():
+    w = synth.workload(0)
+    return torch.from_numpy(w.target()).to(dev()), w
+
+
+def test_from_target_places_gaussians_as_the_oracle():
+    """The fitter's initial Gaussians are Eq. 6 samples at the generator's uniforms (pixel
+    centres, rotation 0, 5 px, target colours), up to the fitter's own unit conversion."""
+    from oracle import initref as ir
+    from paper_2407_01866_amd.fit import PlainFitter
+    t, w = _target256()
+    f = PlainFitter.from_target(t, 4000, w.K, seed=3)
+    assert f.N == 2000 and [s for s, _ in f.growth] == [500, 1000, 1500, 2000]
+    gen = torch.Generator(device=t.device)
+    gen.manual_seed(3)
+    u = torch.rand(2000, generator=gen, device=t.device).cpu().numpy()
+    ref = ir.init_gaussians(w.target().astype(np.float64), u)
+    got = f.rend.cpu().numpy().astype(np.float64)
+    # the sampled pixel of every Gaussian (a uniform within 1e-9 of a boundary may pick either
+    # neighbour; none does at this seed)
+    assert np.array_equal(np.floor(got[0]), np.floor(ref[0]))
+    assert np.array_equal(np.floor(got[1]), np.floor(ref[1]))
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-6)
+
+
+def test_densify_equals_direct_placement_call():
+    """The fitter's error-guided addition is igs_add_gaussians on its last render with the next
+    uniforms of its generator; new columns start with zero Adam moments."""
+    from paper_2407_01866_amd import _native as nat
+    from paper_2407_01866_amd.fit import PlainFitter
+    t, w = _target256()
+    f = PlainFitter.from_target(t, 2400, w.K, seed=5)
+    f.run(40, report_every=40)
+    img = f.image.clone()
+    fit0, m0 = f.fit.clone(), f.m.clone()
+    state = f.gen.get_state()
+    f.densify(300)
+    gen = torch.Generator(device=t.device)
+    gen.set_state(state)
+    u = torch.rand(300, generator=gen, device=t.device)
+    rp = torch.zeros((5 + w.n, 1500), device=t.device)
+    fp = torch.zeros_like(rp)
+    ws = torch.empty(nat.igs_place_workspace_size(w.H, w.W), dtype=torch.uint8, device=t.device)
+    nat.igs_add_gaussians(img, f.target, w.n, w.H, w.W, u, 300, 5.0, rp, fp, 1500, 1200, ws,
+                          ws.numel())
+    torch.cuda.synchronize()
+    assert f.N == 1500
+    assert torch.equal(f.rend[:, 1200:], rp[:, 1200:])
+    assert torch.equal(f.fit[:, 1200:], fp[:, 1200:])
+    assert torch.equal(f.fit[:, :1200], fit0) and torch.equal(f.m[:, :1200], m0)
+    assert torch.count_nonzero(f.m[:, 1200:]) == 0 and torch.count_nonzero(f.v[:, 1200:]) == 0
+
+
+def test_progressive_fit_grows_on_schedule_and_beats_random_init():
+    from paper_2407_01866_amd.fit import PlainFitter
+    t, w = _target256()
+    f = PlainFitter.from_target(t, 3000, w.K, seed=1)
+    rep = f.run(1100, report_every=100)
+    ps = [p for _, p in rep]
+    print("progressive PSNR", [round(p, 2) for p in ps], "N", f.N, flush=True)
+    assert f.N == 1500 + 2 * 375 and f.steps_done() == 1100
+    assert ps[-1] > ps[0] + 1.5
+    g = PlainFitter(t, torch.from_numpy(synth.gen_gaussians(9, w.H, w.W, 3000, w.n)).to(t.device),
+                    w.K)
+    h = PlainFitter.from_target(t, 3000, w.K, progressive=False, seed=1)
+    pg = g.run(300, report_every=300)[-1][1]
+    ph = h.run(300, report_every=300)[-1][1]
+    print("300 iterations: random init", pg, "content-adaptive", ph, flush=True)
+    assert ph > pg + 1.0
+
+
+def test_checkpoint_resume_across_a_densification():
+    from paper_2407_01866_amd.fit import PlainFitter
+    t, w = _target256()
+    f = PlainFitter.from_target(t, 2000, w.K, seed=2)
+    f.run(520, report_every=520)
+    assert f.N == 1250
+    sd = f.state_dict()
+    a = f.run(500, report_every=500)[-1][1]
+    g = PlainFitter.from_target(t, 2000, w.K, seed=2)
+    g.load_state_dict(sd)
+    assert g.N == 1250 and g.steps_done() == 520 and g.growth == sd["growth"]
+    b = g.run(500, report_every=500)[-1][1]
+    assert g.N == f.N == 1500
+    assert a == b and torch.equal(f.fit, g.fit)
