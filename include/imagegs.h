@@ -166,6 +166,52 @@ igs_status igs_render_backward_l1(const float *params, int32_t N, int32_t n, int
                                   const void *saved, size_t saved_bytes, float *grad_params,
                                   void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Binning alone (Sec. 3.2): the footprint bound, pair emission, sort and tile ranges of
+ * igs_render, written into `saved` without rasterizing, for decoders that answer point queries
+ * (igs_query).  Arguments, sizes, status block and errors as igs_render (image not needed).
+ */
+igs_status igs_bin(const float *params, int32_t N, int32_t n, int32_t H, int32_t W, int32_t K,
+                   int32_t tile_h, int32_t tile_w, int64_t pair_capacity, void *saved,
+                   size_t saved_bytes, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Random access (Sec. 1, Sec. 3.2): the colour of the representation at M arbitrary points of
+ * the image plane, each evaluated on its own by Eq. 5: the point (x, y) belongs to tile
+ * (floor(x/16), floor(y/16)), every member of that tile's S_j is ranked by q at the point (then
+ * by index) and the top K are blended.  The ranking and blend are igs_render's operations, so at
+ * a pixel centre (w + 1/2, h + 1/2) the result equals the rendered pixel bit for bit.
+ *   params, N, n, H, W, K, tiles, pair_capacity: as the igs_bin or igs_render call that wrote
+ *          `saved` (whose status block must report no overflow)
+ *   points [2][M] float32 device: x row then y row, in pixels; points outside [0,W) x [0,H) or
+ *          not finite give 0
+ *   out    [n][M] float32 device output
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_UNSUPPORTED (tile size), IGS_ERR_WORKSPACE (saved too
+ * small or misaligned), IGS_ERR_HIP.
+ */
+igs_status igs_query(const float *params, int32_t N, int32_t n, int32_t H, int32_t W, int32_t K,
+                     int32_t tile_h, int32_t tile_w, int64_t pair_capacity, const void *saved,
+                     size_t saved_bytes, const float *points, int32_t M, float *out,
+                     void *stream);
+
+/*
+ * Float16 storage (Sec. 4.1: the trained attributes are quantized to float16): every value of
+ * a [5+n][N] float32 array (normally the fitter's parameters: normalized mean, rotation, inverse
+ * scales, colour) rounded to IEEE binary16, nearest with ties to even, as uint16 bit patterns.
+ */
+igs_status igs_params_to_fp16(const float *params, int32_t N, int32_t n, uint16_t *out,
+                              void *stream);
+
+/*
+ * Decoding of stored float16 fitter parameters [5+n][N_stored] into igs_render's float32 units
+ * for the first N_prefix Gaussians (a level of detail: the error-guided schedule appends
+ * Gaussians, so each of its stages is a prefix): mean x W and x H, rotation, scale =
+ * 1 / inverse scale, colour.  render_params is [5+n][N_prefix].
+ * Errors: IGS_ERR_INVALID_ARG (N_prefix > N_stored, shapes), IGS_ERR_HIP.
+ */
+igs_status igs_decode_fp16(const uint16_t *stored, int32_t N_stored, int32_t n, int32_t N_prefix,
+                           int32_t H, int32_t W, float *render_params, void *stream);
+
 /* Scratch bytes igs_l1_loss_grad needs for an image of count = n*H*W values. */
 igs_status igs_l1_workspace_size(int64_t count, size_t *ws_bytes);
 

@@ -36,7 +36,8 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_render_l1", "igs_render_backward_l1", "igs_render_l1_batched",
             "igs_render_backward_l1_batched", "igs_set_launch_config", "igs_get_launch_config",
             "igs_l1_ssim_workspace_size", "igs_l1_ssim_loss_grad", "igs_place_workspace_size",
-            "igs_init_gaussians", "igs_add_gaussians")
+            "igs_init_gaussians", "igs_add_gaussians", "igs_bin", "igs_query",
+            "igs_params_to_fp16", "igs_decode_fp16")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce")
 
@@ -105,6 +106,14 @@ def lib() -> ctypes.CDLL:
     L.igs_l1_ssim_loss_grad.argtypes = [vp, vp, i32, i32, i32, ctypes.c_double, vp, vp, vp, sz,
                                         vp]
     L.igs_l1_ssim_loss_grad.restype = i32
+    L.igs_bin.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, sz, vp, sz, vp]
+    L.igs_bin.restype = i32
+    L.igs_query.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, sz, vp, i32, vp, vp]
+    L.igs_query.restype = i32
+    L.igs_params_to_fp16.argtypes = [vp, i32, i32, vp, vp]
+    L.igs_params_to_fp16.restype = i32
+    L.igs_decode_fp16.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
+    L.igs_decode_fp16.restype = i32
     L.igs_place_workspace_size.argtypes = [i32, i32, ctypes.POINTER(sz)]
     L.igs_place_workspace_size.restype = i32
     L.igs_init_gaussians.argtypes = [vp, i32, i32, i32, ctypes.c_double, vp, i32, f32, vp, vp, i32,
@@ -291,6 +300,37 @@ def igs_l1_ssim_loss_grad(image, target, n, H, W, ssim_weight, grad_image, loss_
         _f32(image, "image"), _f32(target, "target"), n, H, W, float(ssim_weight),
         _f32(grad_image, "grad_image"), _ptr(loss_out), _ptr(workspace), ws_bytes,
         _stream(stream)))
+
+
+def igs_bin(params, N, n, H, W, K, tile_h, tile_w, cap, saved, saved_bytes, workspace, ws_bytes,
+            stream=None) -> None:
+    _check("igs_bin", lib().igs_bin(
+        _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, cap,
+        _ptr(saved), saved_bytes, _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_query(params, N, n, H, W, K, tile_h, tile_w, cap, saved, saved_bytes, points, M, out,
+              stream=None) -> None:
+    _check("igs_query", lib().igs_query(
+        _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, cap,
+        _ptr(saved), saved_bytes, _f32(points, "points") if M > 0 else None, M,
+        _f32(out, "out") if M > 0 else None, _stream(stream)))
+
+
+def igs_params_to_fp16(params, N, n, out, stream=None) -> None:
+    if out.dtype not in (torch.int16, torch.float16):
+        raise TypeError("out must be a 16-bit tensor")
+    _check("igs_params_to_fp16", lib().igs_params_to_fp16(
+        _f32(params, "params") if N > 0 else None, N, n, _ptr(out) if N > 0 else None,
+        _stream(stream)))
+
+
+def igs_decode_fp16(stored, N_stored, n, N_prefix, H, W, render_params, stream=None) -> None:
+    if stored.dtype not in (torch.int16, torch.float16):
+        raise TypeError("stored must be a 16-bit tensor")
+    _check("igs_decode_fp16", lib().igs_decode_fp16(
+        _ptr(stored), N_stored, n, N_prefix, H, W,
+        _f32(render_params, "render_params") if N_prefix > 0 else None, _stream(stream)))
 
 
 def igs_place_workspace_size(H: int, W: int) -> int:

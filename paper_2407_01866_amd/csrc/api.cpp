@@ -236,7 +236,7 @@ namespace {
 igs_status render_impl(const float *params, const Dims &d, const Images &imgs, bool batched,
                        float *image, void *saved, size_t saved_bytes, void *workspace,
                        size_t ws_bytes, hipStream_t s, const float *target = nullptr,
-                       double *loss_out = nullptr) {
+                       double *loss_out = nullptr, bool raster = true) {
   const SavedLayout SL = saved_layout(d);
   const WsLayout WL = ws_layout(d);
   void *sv = saved;
@@ -297,6 +297,7 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
                                false));
     }
   }
+  if (!raster) return IGS_OK;
   float2 *l1_rec = target ? at<float2>(sv, SL.l1_rec) : nullptr;
   double2 *l1_part = target ? at<double2>(workspace, WL.l1_part) : nullptr;
   {
@@ -404,6 +405,56 @@ IGS_API igs_status igs_render(const float *params, int32_t N, int32_t n, int32_t
   return render_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N), false,
                      image, saved, saved_bytes, workspace, ws_bytes,
                      static_cast<hipStream_t>(stream));
+}
+
+IGS_API igs_status igs_bin(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
+                           int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                           void *saved, size_t saved_bytes, void *workspace, size_t ws_bytes,
+                           void *stream) {
+  igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
+  if (st != IGS_OK) return st;
+  if ((N > 0 && !params) || !saved || !workspace) return IGS_ERR_INVALID_ARG;
+  return render_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N), false,
+                     nullptr, saved, saved_bytes, workspace, ws_bytes,
+                     static_cast<hipStream_t>(stream), nullptr, nullptr, false);
+}
+
+IGS_API igs_status igs_query(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
+                             int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                             const void *saved, size_t saved_bytes, const float *points,
+                             int32_t M, float *out, void *stream) {
+  igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
+  if (st != IGS_OK) return st;
+  if ((N > 0 && !params) || !saved || M < 0 || (M > 0 && (!points || !out)))
+    return IGS_ERR_INVALID_ARG;
+  const Dims d = make_dims(N, n, H, W, K, pair_capacity);
+  const SavedLayout SL = saved_layout(d);
+  if (saved_bytes < SL.total) return IGS_ERR_WORKSPACE;
+  if (!aligned(saved)) return IGS_ERR_WORKSPACE;
+  void *sv = const_cast<void *>(saved);
+  IGS_HIP(launch_query(params, N, n, H, W, K, at<int2>(sv, SL.ranges), at<uint32_t>(sv, SL.vals),
+                       at<float4>(sv, SL.g32a), at<float2>(sv, SL.g32b), at<double4>(sv, SL.g64),
+                       points, M, out, static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_params_to_fp16(const float *params, int32_t N, int32_t n, uint16_t *out,
+                                      void *stream) {
+  if (N < 0 || n < 1 || n > IGS_MAX_CHANNELS || (N > 0 && (!params || !out)))
+    return IGS_ERR_INVALID_ARG;
+  IGS_HIP(launch_to_fp16(params, (int64_t)(5 + n) * N, out, static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_decode_fp16(const uint16_t *stored, int32_t N_stored, int32_t n,
+                                   int32_t N_prefix, int32_t H, int32_t W, float *render_params,
+                                   void *stream) {
+  if (N_stored < 0 || n < 1 || n > IGS_MAX_CHANNELS || N_prefix < 0 || N_prefix > N_stored ||
+      H < 1 || W < 1 || (N_prefix > 0 && (!stored || !render_params)))
+    return IGS_ERR_INVALID_ARG;
+  IGS_HIP(launch_decode_fp16(stored, N_stored, n, N_prefix, H, W, render_params,
+                             static_cast<hipStream_t>(stream)));
+  return IGS_OK;
 }
 
 IGS_API igs_status igs_render_backward(const float *params, int32_t N, int32_t n, int32_t H,

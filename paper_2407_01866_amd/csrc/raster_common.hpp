@@ -18,6 +18,39 @@ __device__ __forceinline__ double quad_form64(float fx, float fy, float mx, floa
   return fma(e1, e1, e2 * e2);
 }
 
+// Ranking key of a candidate at a pixel: the pair (q, slot), slot = its position in S_j, packed
+// as the bit pattern of a positive double (high word = float bits of q plus one exponent step,
+// low word = slot), so comparing keys compares (q, slot) lexicographically.  q is clamped below
+// 1e38, so a non-finite value can only rank last.  kKeyEmpty (+inf) marks an unused list entry.
+constexpr uint32_t kKeyBias = 0x00800000u;
+constexpr float kQMax = 1e38f;
+
+__device__ __forceinline__ double rank_key(float q, int slot) {
+  return __hiloint2double((int)(__float_as_uint(fminf(q, kQMax)) + kKeyBias), slot);
+}
+__device__ __forceinline__ int key_slot(double k) { return __double2loint(k); }
+__device__ __forceinline__ bool key_valid(double k) {
+  return (uint32_t)__double2hiint(k) < 0x7F000000u;  // not the +inf sentinel
+}
+#define kKeyEmpty __longlong_as_double(0x7FF0000000000000ll)
+
+// q = (A dx + B dy)^2 + (C dx + D dy)^2 in float32, as the ranking evaluates it.
+__device__ __forceinline__ float quad_q32(float A, float B, float C, float D, float dx, float dy) {
+  const float e1 = fmaf(A, dx, B * dy), e2 = fmaf(C, dx, D * dy);
+  return fmaf(e1, e1, e2 * e2);
+}
+
+// Sorted insertion into a register-resident top-KT list of keys: one max and one min per entry.
+template <int KT>
+__device__ __forceinline__ void topk_insert(double (&tk)[KT], double key) {
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const double hi = __builtin_fmax(key, tk[k]);
+    tk[k] = __builtin_fmin(key, tk[k]);
+    key = hi;
+  }
+}
+
 // Blend weight exp(-(q - shift)/2) (Eq. 5 scaled by exp(shift/2), which cancels in the ratio).
 __device__ __forceinline__ float blend_weight(double q, float shift) {
   return __expf(-0.5f * (float)(q - (double)shift));

@@ -26,31 +26,14 @@
 namespace igs {
 namespace {
 
-constexpr uint32_t kKeyBias = 0x00800000u;
 // Candidates staged in LDS per batch: 192 keeps the kernel's LDS (124 B per candidate for n = 9)
 // small enough for six workgroups per CU, the occupancy its registers allow.
 constexpr int kFwdBatch = 192;
 // LDS bytes before the colour rows: per candidate 48 B of ranking data in visiting order and 40 B
 // of blend geometry in slot order, then the bucket counters.
 constexpr unsigned kFwdLdsFixed = 88 * kFwdBatch + 2 * 16 * 4;
-constexpr float kQMax = 1e38f;
-
-__device__ __forceinline__ double rank_key(float q, int slot) {
-  return __hiloint2double((int)(__float_as_uint(fminf(q, kQMax)) + kKeyBias), slot);
-}
-__device__ __forceinline__ int key_slot(double k) { return __double2loint(k); }
-__device__ __forceinline__ bool key_valid(double k) {
-  return (uint32_t)__double2hiint(k) < 0x7F000000u;  // not the +inf sentinel
-}
-
 constexpr int kBuckets = 16;
 constexpr int kWaves = kRasterThreads / 64;  // each wave covers 4 rows of the tile
-
-// q = (A dx + B dy)^2 + (C dx + D dy)^2 evaluated as the ranking evaluates it.
-__device__ __forceinline__ float quad_q32(float A, float B, float C, float D, float dx, float dy) {
-  const float e1 = fmaf(A, dx, B * dy), e2 = fmaf(C, dx, D * dy);
-  return fmaf(e1, e1, e2 * e2);
-}
 
 // Minimum of q over the rectangle [dxa, dxb] x [dya, dyb] of offsets from the mean: 0 if the
 // rectangle holds the mean, else the least of the four edge minima, each the 1-D minimum of the
@@ -103,16 +86,6 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // bcast 15
   v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // bcast 31
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
-
-template <int KT>
-__device__ __forceinline__ void topk_insert(double (&tk)[KT], double key) {
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    const double hi = __builtin_fmax(key, tk[k]);
-    tk[k] = __builtin_fmin(key, tk[k]);
-    key = hi;
-  }
 }
 
 // Fused L1 epilogue (L1 = true): besides the image, each pixel compares its colour with the
@@ -202,7 +175,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
 
   double tk[KT];
 #pragma unroll
-  for (int k = 0; k < KT; ++k) tk[k] = __longlong_as_double(0x7FF0000000000000ll);  // +inf
+  for (int k = 0; k < KT; ++k) tk[k] = kKeyEmpty;
 
   const int wave = tid >> 6;
   if (tid < kBuckets) s_bcnt[tid] = 0;

@@ -108,6 +108,32 @@ class Renderer:
             self.set_capacity(int(int(st[nat.STAT_PAIRS]) * 1.25) + 1024)
         raise RuntimeError("pair capacity overflow persisted after resizing")
 
+    def bin(self, params: torch.Tensor) -> torch.Tensor:
+        """Binning alone (the tile lists point queries read), growing the pair capacity on
+        overflow like ``render``.  Returns the saved state."""
+        for _ in range(2):
+            saved = self.new_saved()
+            nat.igs_bin(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE, self.cap,
+                        saved, saved.numel(), self.ws, self.ws.numel())
+            st = self.status_of(saved).cpu()
+            if int(st[nat.STAT_OVERFLOW]) == 0:
+                return saved
+            self.set_capacity(int(int(st[nat.STAT_PAIRS]) * 1.25) + 1024)
+        raise RuntimeError("pair capacity overflow persisted after resizing")
+
+    def query_into(self, params, saved, points, out) -> None:
+        """Colours [n][M] at points [2][M] (x row, y row, pixels) from the tile lists in
+        ``saved`` (written by ``bin`` or a render of the same parameters)."""
+        M = int(points.shape[1])
+        nat.igs_query(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE, self.cap, saved,
+                      saved.numel(), points, M, out)
+
+    def query(self, params, saved, points) -> torch.Tensor:
+        out = torch.empty((self.n, int(points.shape[1])), dtype=torch.float32,
+                          device=self.device)
+        self.query_into(params, saved, points.contiguous(), out)
+        return out
+
     def backward(self, params, image, grad_image, saved) -> torch.Tensor:
         gp = torch.empty((5 + self.n, self.N), dtype=torch.float32, device=self.device)
         self.backward_into(params, image, grad_image.contiguous(), saved, gp)
@@ -294,3 +320,36 @@ class BatchRenderer:
         raw = torch.where(raw == 0xFFFF, torch.full_like(raw, -1), raw)
         return [raw[self.K * po:self.K * (po + H * W)].view(self.K, H, W)
                 for (H, W, _), po in zip(self.sizes, self.pix_off)]
+
+
+class Decoder:
+    """A stored representation (float16 fitter parameters, Sec. 4.1) decoded for use: the first
+    ``n_prefix`` Gaussians (a level of detail of a progressive fit; all by default) in the
+    renderer's units, binned once, then rendered or sampled at arbitrary points."""
+
+    def __init__(self, stored: torch.Tensor, n: int, H: int, W: int, K: int = 10,
+                 n_prefix: Optional[int] = None):
+        self.device = stored.device
+        N_stored = int(stored.shape[1])
+        N = N_stored if n_prefix is None else int(n_prefix)
+        self.n, self.H, self.W, self.K, self.N = n, H, W, K, N
+        self.params = torch.empty((5 + n, N), dtype=torch.float32, device=self.device)
+        nat.igs_decode_fp16(stored.contiguous(), N_stored, n, N, H, W, self.params)
+        self.r = Renderer(N, n, H, W, K, device=self.device)
+        self.saved = self.r.bin(self.params)
+
+    def query(self, points: torch.Tensor) -> torch.Tensor:
+        """Colours [n][M] at points [2][M] (x row, y row, in pixels)."""
+        return self.r.query(self.params, self.saved, points)
+
+    def render(self) -> torch.Tensor:
+        img, _ = self.r.render(self.params, keep_state=False)
+        return img
+
+
+def store_fp16(fit_params: torch.Tensor) -> torch.Tensor:
+    """The float16 storage of a [5+n][N] float32 set of fitter parameters (int16 bit patterns)."""
+    n, N = fit_params.shape[0] - 5, fit_params.shape[1]
+    out = torch.empty((5 + n, N), dtype=torch.int16, device=fit_params.device)
+    nat.igs_params_to_fp16(fit_params.contiguous(), N, n, out)
+    return out

@@ -140,6 +140,21 @@ def test_placement_validates_before_device_work(nat):
                                None) == -1
 
 
+def test_decoding_validates_before_device_work(nat):
+    L = nat.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation
+    assert L.igs_bin(fake, 10, 3, 16, 16, 10, 16, 16, 100, None, 0, fake, 1 << 30, None) == -1
+    assert L.igs_bin(fake, 10, 3, 16, 16, 10, 8, 8, 100, fake, 1 << 30, fake, 1 << 30, None) == -4
+    assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 1 << 30, None, 5, fake,
+                       None) == -1
+    assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 1 << 30, fake, -1, fake,
+                       None) == -1
+    assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 64, fake, 5, fake, None) == -2
+    assert L.igs_params_to_fp16(None, 10, 3, fake, None) == -1
+    assert L.igs_decode_fp16(fake, 10, 3, 11, 16, 16, fake, None) == -1
+    assert L.igs_decode_fp16(fake, 10, 3, 5, 0, 16, fake, None) == -1
+
+
 def test_launch_config_roundtrip_and_validation(nat):
     L = nat.lib()
     try:
