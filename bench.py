@@ -197,16 +197,59 @@ def ssim_step(torch, dev, w, image, target, calls=20, iters=10):
             "ssim_after_iters": round(f.ssim(), 6)}
 
 
+def decode_step(torch, dev, w, params, M=1 << 22, calls=10):
+    """Random access at the benchmark workload: binning alone (once per decoded set), then M
+    points drawn uniformly over the image decoded per call (HIP events on the call's stream).
+    Algorithmic work per point as the forward's per pixel: 9 lane-ops per member of the point's
+    S_j (the mean |S_j| over the image, which uniform points sample) plus 60 + 10n for the
+    blend."""
+    from paper_2407_01866_amd import _native as nat
+    from paper_2407_01866_amd.render import Renderer
+    r = Renderer(w.N, w.n, w.H, w.W, w.K, device=dev)
+    saved = r.bin(params)
+    nat.igs_timing_read(reset=True)
+    nat.igs_timing_enable(True)
+    for _ in range(5):
+        r.bin(params)
+    ph = nat.igs_timing_read(reset=True)
+    nat.igs_timing_enable(False)
+    bin_ms = ph["binning"][0] / ph["binning"][1]
+    g = torch.Generator(device=dev)
+    g.manual_seed(123)
+    pts = torch.stack([torch.rand(M, generator=g, device=dev) * w.W,
+                       torch.rand(M, generator=g, device=dev) * w.H]).contiguous()
+    out = torch.empty((w.n, M), device=dev)
+    for _ in range(2):
+        r.query_into(params, saved, pts, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(200_000_000)
+    e0.record()
+    for _ in range(calls):
+        r.query_into(params, saved, pts, out)
+    e1.record()
+    torch.cuda.synchronize()
+    q_ms = e0.elapsed_time(e1) / calls
+    st = r.status_of(saved).cpu()
+    mean_sj = float(st[nat.STAT_EVALS_FWD]) / (w.H * w.W)
+    ops = (9.0 * mean_sj + 60.0 + 10.0 * w.n) * M
+    return {"bin_ms": round(bin_ms, 4), "points": M, "query_ms": round(q_ms, 4),
+            "points_per_s": M / (q_ms * 1e-3), "mean_candidates_per_point": round(mean_sj, 2),
+            "roofline": {"bound": "alu", "achieved": round(ops / (q_ms * 1e-3) / 1e12, 3),
+                         "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
+                         "frac": round(ops / (q_ms * 1e-3) / PEAK_LANE_OPS, 4)}}
+
+
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_raster_texture-2048x2048-n9-N100000.txt")
 KERNEL_SOURCES = {"raster_fwd": "raster_fwd.hip", "raster_bwd": "raster_bwd.hip"}
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- "
-             "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0 --no-ssim "
+             "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0 --no-ssim --no-decode "
              "--launch-config 0,0,1",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'raster|elementwise' -f csv "
              "-d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --steps 3 --warmup 1 "
-             "--no-cpu-baseline --no-context --batch-iters 0 --no-ssim --launch-config 0,0,1",
+             "--no-cpu-baseline --no-context --batch-iters 0 --no-ssim --no-decode --launch-config 0,0,1",
     "write": "rocprofv3 --pmc WRITE_SIZE (otherwise as fetch) -d gpurun_out/pmc_write -o write",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_copy_fetch -o cf -- "
                   "python3 bench.py --copy-calibration",
@@ -381,6 +424,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--no-ssim", action="store_true",
                     help="skip the L1 + SSIM loss measurement")
+    ap.add_argument("--no-decode", action="store_true",
+                    help="skip the random-access decoding measurement")
     ap.add_argument("--ssim-profile", action="store_true",
                     help="only run 20 L1 + SSIM loss calls at the workload (for kernel traces)")
     ap.add_argument("--launch-config", metavar="P,W,C",
@@ -514,6 +559,10 @@ def main():
         log("[bench] CPU oracle baseline")
         g = synth.gen_grad_image(1, w.n, w.H, w.W).astype(np.float64) / (w.n * w.H * w.W)
         cpu = cpu_baseline(w.gaussians(), w.H, w.W, w.K, g, args.cpu_budget)
+    decode = None
+    if not args.no_decode:
+        log("[bench] random-access decoding")
+        decode = decode_step(torch, dev, w, fitter.rend)
     ssim = None
     if not args.no_ssim:
         log("[bench] L1 + SSIM loss")
@@ -541,7 +590,7 @@ def main():
         "launch_config": {"persistent": tuned[0], "wgs_per_cu": tuned[1], "fwd_cull": tuned[2],
                           "autotune_ms": {str(c): round(t * 1e3, 4) for c, t in tune_times.items()}},
         "roofline": roofline, "roofline_adjoint": roofline_bwd,
-        "cpu_baseline": cpu, "ssim_step": ssim, "paper_context": ctx,
+        "cpu_baseline": cpu, "ssim_step": ssim, "decode": decode, "paper_context": ctx,
         "batched_vs_plain": batch,
     }
     print(json.dumps(out), flush=True)
