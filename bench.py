@@ -217,8 +217,8 @@ def decode_step(torch, dev, w, params, M=1 << 22, calls=10):
     g = torch.Generator(device=dev)
     g.manual_seed(123)
     pts = torch.stack([torch.rand(M, generator=g, device=dev) * w.W,
-                       torch.rand(M, generator=g, device=dev) * w.H]).contiguous()
-    out = torch.empty((w.n, M), device=dev)
+                       torch.rand(M, generator=g, device=dev) * w.H], dim=1).contiguous()
+    out = torch.empty((M, w.n), device=dev)
     for _ in range(2):
         r.query_into(params, saved, pts, out)
     torch.cuda.synchronize()

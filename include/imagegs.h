@@ -175,6 +175,9 @@ igs_status igs_bin(const float *params, int32_t N, int32_t n, int32_t H, int32_t
                    int32_t tile_h, int32_t tile_w, int64_t pair_capacity, void *saved,
                    size_t saved_bytes, void *workspace, size_t ws_bytes, void *stream);
 
+/* Scratch bytes igs_query needs to sort M points by tile for an H x W image. */
+igs_status igs_query_workspace_size(int32_t M, int32_t H, int32_t W, size_t *ws_bytes);
+
 /*
  * Random access (Sec. 1, Sec. 3.2): the colour of the representation at M arbitrary points of
  * the image plane, each evaluated on its own by Eq. 5: the point (x, y) belongs to tile
@@ -183,16 +186,21 @@ igs_status igs_bin(const float *params, int32_t N, int32_t n, int32_t H, int32_t
  * a pixel centre (w + 1/2, h + 1/2) the result equals the rendered pixel bit for bit.
  *   params, N, n, H, W, K, tiles, pair_capacity: as the igs_bin or igs_render call that wrote
  *          `saved` (whose status block must report no overflow)
- *   points [2][M] float32 device: x row then y row, in pixels; points outside [0,W) x [0,H) or
- *          not finite give 0
- *   out    [n][M] float32 device output
- * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_UNSUPPORTED (tile size), IGS_ERR_WORKSPACE (saved too
- * small or misaligned), IGS_ERR_HIP.
+ *   points [M][2] float32 device: (x, y) of each point, in pixels; points outside [0,W) x [0,H)
+ *          or not finite give 0
+ *   out    [M][n] float32 device output: the n channels of each point together
+ *   workspace  NULL: the points are evaluated in input order (right when they are already
+ *          grouped by tile, e.g. in scanline order); else device scratch of at least
+ *          igs_query_workspace_size bytes, 256-byte aligned, used to sort the points by tile
+ *          first (a stable sort, so results do not depend on it) so that neighbouring lanes
+ *          share a hit set
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_UNSUPPORTED (tile size), IGS_ERR_WORKSPACE (saved or
+ * workspace too small or misaligned), IGS_ERR_HIP.
  */
 igs_status igs_query(const float *params, int32_t N, int32_t n, int32_t H, int32_t W, int32_t K,
                      int32_t tile_h, int32_t tile_w, int64_t pair_capacity, const void *saved,
                      size_t saved_bytes, const float *points, int32_t M, float *out,
-                     void *stream);
+                     void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * Float16 storage (Sec. 4.1: the trained attributes are quantized to float16): every value of

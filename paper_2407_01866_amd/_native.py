@@ -37,6 +37,7 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_render_backward_l1_batched", "igs_set_launch_config", "igs_get_launch_config",
             "igs_l1_ssim_workspace_size", "igs_l1_ssim_loss_grad", "igs_place_workspace_size",
             "igs_init_gaussians", "igs_add_gaussians", "igs_bin", "igs_query",
+            "igs_query_workspace_size",
             "igs_params_to_fp16", "igs_decode_fp16")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce")
@@ -108,7 +109,10 @@ def lib() -> ctypes.CDLL:
     L.igs_l1_ssim_loss_grad.restype = i32
     L.igs_bin.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, sz, vp, sz, vp]
     L.igs_bin.restype = i32
-    L.igs_query.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, sz, vp, i32, vp, vp]
+    L.igs_query.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, sz, vp, i32, vp, vp,
+                            sz, vp]
+    L.igs_query_workspace_size.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+    L.igs_query_workspace_size.restype = i32
     L.igs_query.restype = i32
     L.igs_params_to_fp16.argtypes = [vp, i32, i32, vp, vp]
     L.igs_params_to_fp16.restype = i32
@@ -309,12 +313,18 @@ def igs_bin(params, N, n, H, W, K, tile_h, tile_w, cap, saved, saved_bytes, work
         _ptr(saved), saved_bytes, _ptr(workspace), ws_bytes, _stream(stream)))
 
 
+def igs_query_workspace_size(M: int, H: int, W: int) -> int:
+    ws = ctypes.c_size_t(0)
+    _check("igs_query_workspace_size", lib().igs_query_workspace_size(M, H, W, ctypes.byref(ws)))
+    return ws.value
+
+
 def igs_query(params, N, n, H, W, K, tile_h, tile_w, cap, saved, saved_bytes, points, M, out,
-              stream=None) -> None:
+              workspace=None, ws_bytes=0, stream=None) -> None:
     _check("igs_query", lib().igs_query(
         _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, cap,
         _ptr(saved), saved_bytes, _f32(points, "points") if M > 0 else None, M,
-        _f32(out, "out") if M > 0 else None, _stream(stream)))
+        _f32(out, "out") if M > 0 else None, _ptr(workspace), ws_bytes, _stream(stream)))
 
 
 def igs_params_to_fp16(params, N, n, out, stream=None) -> None:

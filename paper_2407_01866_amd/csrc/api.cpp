@@ -419,10 +419,17 @@ IGS_API igs_status igs_bin(const float *params, int32_t N, int32_t n, int32_t H,
                      static_cast<hipStream_t>(stream), nullptr, nullptr, false);
 }
 
+IGS_API igs_status igs_query_workspace_size(int32_t M, int32_t H, int32_t W, size_t *ws_bytes) {
+  if (M < 0 || H < 1 || W < 1 || !ws_bytes) return IGS_ERR_INVALID_ARG;
+  *ws_bytes = query_workspace_bytes(M, H, W);
+  return IGS_OK;
+}
+
 IGS_API igs_status igs_query(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
                              int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
                              const void *saved, size_t saved_bytes, const float *points,
-                             int32_t M, float *out, void *stream) {
+                             int32_t M, float *out, void *workspace, size_t ws_bytes,
+                             void *stream) {
   igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
   if (st != IGS_OK) return st;
   if ((N > 0 && !params) || !saved || M < 0 || (M > 0 && (!points || !out)))
@@ -431,10 +438,12 @@ IGS_API igs_status igs_query(const float *params, int32_t N, int32_t n, int32_t 
   const SavedLayout SL = saved_layout(d);
   if (saved_bytes < SL.total) return IGS_ERR_WORKSPACE;
   if (!aligned(saved)) return IGS_ERR_WORKSPACE;
+  if (workspace && (ws_bytes < query_workspace_bytes(M, H, W) || !aligned(workspace)))
+    return IGS_ERR_WORKSPACE;
   void *sv = const_cast<void *>(saved);
   IGS_HIP(launch_query(params, N, n, H, W, K, at<int2>(sv, SL.ranges), at<uint32_t>(sv, SL.vals),
                        at<float4>(sv, SL.g32a), at<float2>(sv, SL.g32b), at<double4>(sv, SL.g64),
-                       points, M, out, static_cast<hipStream_t>(stream)));
+                       points, M, out, workspace, static_cast<hipStream_t>(stream)));
   return IGS_OK;
 }
 

@@ -213,10 +213,12 @@ hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const flo
 // loss_adam.hip
 // Decoding (query.hip): colours at arbitrary points from a binning pass's tile lists; float16
 // storage of the fitter's parameters and decoding of a prefix into renderer units.
+size_t query_workspace_bytes(int64_t M, int H, int W);
+// ws == nullptr: points processed in input order; else they are first sorted by tile.
 hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
                         const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                         const float2 *g32b, const double4 *g64, const float *points, int M,
-                        float *out, hipStream_t s);
+                        float *out, void *ws, hipStream_t s);
 hipError_t launch_to_fp16(const float *src, int64_t count, uint16_t *dst, hipStream_t s);
 hipError_t launch_decode_fp16(const uint16_t *src, int N_src, int n, int N_prefix, int H, int W,
                               float *dst, hipStream_t s);

@@ -21,34 +21,81 @@ namespace {
 
 constexpr int kQueryThreads = 256;
 
-// One thread per point.  Points outside [0, W) x [0, H) (or not finite) decode to 0.
+// Sort keys of the points: the tile of each point (T for a point outside the image), with the
+// point's index as the value, so that a stable sort groups the points by tile in input order.
+__global__ __launch_bounds__(kQueryThreads) void query_keys_kernel(
+    const float *__restrict__ pts, int M, int H, int W, int tiles_x, int tiles_y,
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t *__restrict__ count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) count[0] = M;
+  if (i >= M) return;
+  const float2 pt = reinterpret_cast<const float2 *>(pts)[i];
+  const float fx = pt.x, fy = pt.y;
+  const bool inside = fx >= 0.f && fx < (float)W && fy >= 0.f && fy < (float)H;
+  keys[i] = inside ? (uint32_t)(min((int)fy / kTile, tiles_y - 1) * tiles_x +
+                                min((int)fx / kTile, tiles_x - 1))
+                   : (uint32_t)(tiles_x * tiles_y);
+  vals[i] = (uint32_t)i;
+}
+
+// One thread per point, in the order `order` gives (points grouped by tile, so that the lanes of
+// a wave walk the same hit set and load the same candidates), or in input order when order is
+// null.  Points outside [0, W) x [0, H) (or not finite) decode to 0.
 template <int KT>
 __global__ __launch_bounds__(kQueryThreads) void query_kernel(
     const float *__restrict__ params, int N, int n, int H, int W, int K, int tiles_x,
     int tiles_y, const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
     const double4 *__restrict__ g64, const float *__restrict__ pts, int M,
-    float *__restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  const float fx = pts[i], fy = pts[(size_t)M + i];
+    const uint32_t *__restrict__ order, float *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < M;  // lanes past the end stay for the wave-wide broadcasts
+  const int i = valid ? (order ? (int)order[t] : t) : 0;
+  const float2 pt = valid ? reinterpret_cast<const float2 *>(pts)[i] : make_float2(-1.f, -1.f);
+  const float fx = pt.x, fy = pt.y;
   const bool inside = fx >= 0.f && fx < (float)W && fy >= 0.f && fy < (float)H;
-  int start = 0, cnt = 0;
+  int tile = -1, start = 0, cnt = 0;
   if (inside) {
-    const int tx = min((int)fx / kTile, tiles_x - 1), ty = min((int)fy / kTile, tiles_y - 1);
-    const int2 rg = ranges[ty * tiles_x + tx];
+    tile = min((int)fy / kTile, tiles_y - 1) * tiles_x + min((int)fx / kTile, tiles_x - 1);
+    const int2 rg = ranges[tile];
     start = rg.x;
     cnt = rg.y - rg.x;
   }
   double tk[KT];
 #pragma unroll
   for (int k = 0; k < KT; ++k) tk[k] = kKeyEmpty;
-  for (int s = 0; s < cnt; ++s) {
-    const uint32_t gid = vals[start + s];
-    const float4 a = g32a[gid];
-    const float2 b = g32b[gid];
-    const double key = rank_key(quad_q32(a.z, a.w, b.x, b.y, fx - a.x, fy - a.y), s);
-    if (key < tk[KT - 1]) topk_insert<KT>(tk, key);
+  // one pass per distinct tile among the wave's lanes (one or two once the points are grouped):
+  // the wave loads that tile's candidates 64 at a time, one per lane, and broadcasts each to
+  // every lane with readlane; the lanes of that tile rank it
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(tile >= 0);
+  while (todo) {
+    const int tc = __builtin_amdgcn_readlane(tile, __ffsll((unsigned long long)todo) - 1);
+    const int2 rg = ranges[tc];
+    const int ustart = __builtin_amdgcn_readfirstlane(rg.x);
+    const int ucnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
+    const bool mine = tile == tc;
+    for (int b0 = 0; b0 < ucnt; b0 += 64) {
+      const int nb = min(64, ucnt - b0);
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+      float2 b = make_float2(0.f, 0.f);
+      if (lane < nb) {
+        const uint32_t gid = vals[ustart + b0 + lane];
+        a = g32a[gid];
+        b = g32b[gid];
+      }
+      for (int k = 0; k < nb; ++k) {
+        const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.x), k));
+        const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.y), k));
+        const float A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.z), k));
+        const float B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.w), k));
+        const float C = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.x), k));
+        const float D = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.y), k));
+        const double key = rank_key(quad_q32(A, B, C, D, fx - mx, fy - my), b0 + k);
+        if (mine && key < tk[KT - 1]) topk_insert<KT>(tk, key);
+      }
+    }
+    todo &= ~__ballot(mine);
   }
   // blend: the winners re-evaluated in double, weights relative to the best, in rank order
   const int keff = min(K, cnt);
@@ -72,13 +119,14 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
     }
   }
   const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
+  if (!valid) return;
   for (int ch = 0; ch < n; ++ch) {
     float acc = 0.f;
 #pragma unroll
     for (int k = 0; k < KT; ++k)
       if (k < keff && key_valid(tk[k]))
         acc = fmaf(w[k], params[(size_t)(5 + ch) * N + src[k]], acc);
-    out[(size_t)ch * M + i] = acc * invZ;
+    out[(size_t)i * n + ch] = acc * invZ;
   }
 }
 
@@ -108,19 +156,82 @@ __global__ __launch_bounds__(256) void decode_fp16_kernel(const uint16_t *__rest
 
 }  // namespace
 
+namespace {
+struct QueryWs {
+  size_t keys, vals, keys_alt, vals_alt, hist, hist_off, scan_tmp, count, total;
+  int key_bits, passes, digit_bits;
+  int64_t nblocks;
+};
+
+QueryWs query_ws(int64_t M, int H, int W) {
+  const int64_t T = (int64_t)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+  QueryWs L{};
+  L.key_bits = 1;
+  while ((int64_t)1 << L.key_bits <= T) ++L.key_bits;  // keys 0..T
+  L.passes = (L.key_bits + 7) / 8;
+  L.digit_bits = (L.key_bits + L.passes - 1) / L.passes;
+  L.nblocks = (std::max<int64_t>(M, 1) + kSortTileItems - 1) / kSortTileItems;
+  const size_t arr = align_up((size_t)std::max<int64_t>(M, 1) * sizeof(uint32_t));
+  const int64_t hist_elems = ((int64_t)1 << L.digit_bits) * L.nblocks;
+  size_t o = 0;
+  L.keys = o;
+  o += arr;
+  L.vals = o;
+  o += arr;
+  L.keys_alt = o;
+  o += arr;
+  L.vals_alt = o;
+  o += arr;
+  L.hist = o;
+  o += align_up((size_t)hist_elems * sizeof(uint32_t));
+  L.hist_off = o;
+  o += align_up((size_t)hist_elems * sizeof(uint32_t));
+  L.scan_tmp = o;
+  o += align_up(scan_temp_elems(hist_elems) * sizeof(uint32_t));
+  L.count = o;
+  o += align_up(sizeof(int64_t));
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+size_t query_workspace_bytes(int64_t M, int H, int W) { return query_ws(M, H, W).total; }
+
 hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
                         const int2 *ranges, const uint32_t *vals, const float4 *g32a,
                         const float2 *g32b, const double4 *g64, const float *points, int M,
-                        float *out, hipStream_t s) {
+                        float *out, void *ws, hipStream_t s) {
   if (M <= 0) return hipSuccess;
   const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
   const int grid = (M + kQueryThreads - 1) / kQueryThreads;
+  const uint32_t *order = nullptr;
+  if (ws) {
+    const QueryWs L = query_ws(M, H, W);
+    char *b = static_cast<char *>(ws);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(b + L.keys);
+    uint32_t *vs = reinterpret_cast<uint32_t *>(b + L.vals);
+    uint32_t *keys_alt = reinterpret_cast<uint32_t *>(b + L.keys_alt);
+    uint32_t *vals_alt = reinterpret_cast<uint32_t *>(b + L.vals_alt);
+    int64_t *count = reinterpret_cast<int64_t *>(b + L.count);
+    const bool alt = sort_starts_in_alt(L.passes);
+    query_keys_kernel<<<grid, kQueryThreads, 0, s>>>(points, M, H, W, tiles_x, tiles_y,
+                                                     alt ? keys_alt : keys, alt ? vals_alt : vs,
+                                                     count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = radix_sort_pairs(keys, vs, keys_alt, vals_alt, count, M, L.key_bits, L.passes,
+                         L.digit_bits, reinterpret_cast<uint32_t *>(b + L.hist),
+                         reinterpret_cast<uint32_t *>(b + L.hist_off),
+                         reinterpret_cast<uint32_t *>(b + L.scan_tmp), s, false);
+    if (e != hipSuccess) return e;
+    order = vs;
+  }
   switch (pick_kt(K)) {
 #define IGS_QUERY_CASE(KT)                                                                    \
   case KT:                                                                                    \
     query_kernel<KT><<<grid, kQueryThreads, 0, s>>>(params, N, n, H, W, K, tiles_x, tiles_y, \
                                                     ranges, vals, g32a, g32b, g64, points, M, \
-                                                    out);                                     \
+                                                    order, out);                              \
     break;
     IGS_FOR_EACH_KT(IGS_QUERY_CASE)
 #undef IGS_QUERY_CASE

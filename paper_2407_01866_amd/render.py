@@ -121,17 +121,24 @@ class Renderer:
             self.set_capacity(int(int(st[nat.STAT_PAIRS]) * 1.25) + 1024)
         raise RuntimeError("pair capacity overflow persisted after resizing")
 
-    def query_into(self, params, saved, points, out) -> None:
-        """Colours [n][M] at points [2][M] (x row, y row, pixels) from the tile lists in
-        ``saved`` (written by ``bin`` or a render of the same parameters)."""
-        M = int(points.shape[1])
+    def query_into(self, params, saved, points, out, sort: bool = True) -> None:
+        """Colours [M][n] at points [M][2] ((x, y) in pixels) from the tile lists in ``saved``
+        (written by ``bin`` or a render of the same parameters).  ``sort``: group the points by
+        tile first (for scattered points; results are the same either way)."""
+        M = int(points.shape[0])
+        ws, nbytes = None, 0
+        if sort and M > 0:
+            nbytes = nat.igs_query_workspace_size(M, self.H, self.W)
+            if getattr(self, "_qws", None) is None or self._qws.numel() < nbytes:
+                self._qws = _aligned_bytes(nbytes, self.device)
+            ws = self._qws
         nat.igs_query(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE, self.cap, saved,
-                      saved.numel(), points, M, out)
+                      saved.numel(), points, M, out, ws, nbytes)
 
-    def query(self, params, saved, points) -> torch.Tensor:
-        out = torch.empty((self.n, int(points.shape[1])), dtype=torch.float32,
+    def query(self, params, saved, points, sort: bool = True) -> torch.Tensor:
+        out = torch.empty((int(points.shape[0]), self.n), dtype=torch.float32,
                           device=self.device)
-        self.query_into(params, saved, points.contiguous(), out)
+        self.query_into(params, saved, points.contiguous(), out, sort)
         return out
 
     def backward(self, params, image, grad_image, saved) -> torch.Tensor:
@@ -339,7 +346,7 @@ class Decoder:
         self.saved = self.r.bin(self.params)
 
     def query(self, points: torch.Tensor) -> torch.Tensor:
-        """Colours [n][M] at points [2][M] (x row, y row, in pixels)."""
+        """Colours [M][n] at points [M][2] ((x, y) in pixels)."""
         return self.r.query(self.params, self.saved, points)
 
     def render(self) -> torch.Tensor:

@@ -146,10 +146,17 @@ def test_decoding_validates_before_device_work(nat):
     assert L.igs_bin(fake, 10, 3, 16, 16, 10, 16, 16, 100, None, 0, fake, 1 << 30, None) == -1
     assert L.igs_bin(fake, 10, 3, 16, 16, 10, 8, 8, 100, fake, 1 << 30, fake, 1 << 30, None) == -4
     assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 1 << 30, None, 5, fake,
-                       None) == -1
+                       None, 0, None) == -1
     assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 1 << 30, fake, -1, fake,
-                       None) == -1
-    assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 64, fake, 5, fake, None) == -2
+                       None, 0, None) == -1
+    assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 64, fake, 5, fake, None, 0,
+                       None) == -2
+    # a sorting workspace that is too small
+    assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 1 << 30, fake, 5, fake, fake,
+                       8, None) == -2
+    sz = ctypes.c_size_t(0)
+    assert L.igs_query_workspace_size(1000, 64, 64, ctypes.byref(sz)) == 0 and sz.value >= 16000
+    assert L.igs_query_workspace_size(-1, 64, 64, ctypes.byref(sz)) == -1
     assert L.igs_params_to_fp16(None, 10, 3, fake, None) == -1
     assert L.igs_decode_fp16(fake, 10, 3, 11, 16, 16, fake, None) == -1
     assert L.igs_decode_fp16(fake, 10, 3, 5, 0, 16, fake, None) == -1

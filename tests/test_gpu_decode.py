@@ -35,10 +35,10 @@ def test_queries_at_pixel_centres_equal_the_render(H, W, N, n, K):
     saved = r.bin(p)
     hh, ww = torch.meshgrid(torch.arange(H, device=dev()), torch.arange(W, device=dev()),
                             indexing="ij")
-    pts = torch.stack([ww.reshape(-1).float() + 0.5, hh.reshape(-1).float() + 0.5])
-    got = r.query(p, saved, pts)
+    pts = torch.stack([ww.reshape(-1).float() + 0.5, hh.reshape(-1).float() + 0.5], dim=1)
+    got = r.query(p, saved, pts.contiguous())
     torch.cuda.synchronize()
-    assert torch.equal(got, img.reshape(n, -1))
+    assert torch.equal(got.T, img.reshape(n, -1))
 
 
 def _check_points(got, ref, tie):
@@ -59,7 +59,11 @@ def test_queries_at_arbitrary_points_match_oracle(H, W, N, n, K, seed):
     r = renderer(N, n, H, W, K)
     pt = torch.from_numpy(p).to(dev())
     saved = r.bin(pt)
-    got = r.query(pt, saved, torch.from_numpy(pts).to(dev())).cpu().numpy().astype(np.float64)
+    dpts = torch.from_numpy(np.ascontiguousarray(pts.T)).to(dev())
+    got_t = r.query(pt, saved, dpts)
+    unsorted = r.query(pt, saved, dpts, sort=False)
+    assert torch.equal(got_t, unsorted)      # grouping the points by tile changes no bit
+    got = got_t.cpu().numpy().T.astype(np.float64)
     p64 = p.astype(np.float64)
     ref = dr.evaluate_points(p64, H, W, K, pts.astype(np.float64))
     tie = dr.near_tie_points(p64, H, W, K, pts.astype(np.float64))
@@ -72,10 +76,10 @@ def test_points_outside_or_not_finite_are_zero_and_empty_query():
     r = renderer(50, 3, 30, 30, 10)
     saved = r.bin(p)
     pts = torch.tensor([[-0.5, 30.0, 3.0, float("nan"), float("inf")],
-                        [3.0, 3.0, 30.5, 3.0, 3.0]], device=dev())
+                        [3.0, 3.0, 30.5, 3.0, 3.0]], device=dev()).T.contiguous()
     assert torch.count_nonzero(r.query(p, saved, pts)) == 0
-    out = r.query(p, saved, torch.zeros((2, 0), device=dev()))
-    assert out.shape == (3, 0)
+    out = r.query(p, saved, torch.zeros((0, 2), device=dev()))
+    assert out.shape == (0, 3)
 
 
 def test_texture_2048_n9_queries_sampled():
@@ -89,7 +93,8 @@ def test_texture_2048_n9_queries_sampled():
     saved = r.bin(pt)
     rng = np.random.default_rng(11)
     pts = np.stack([rng.uniform(0, w.W, 500_000), rng.uniform(0, w.H, 500_000)]).astype(np.float32)
-    got = r.query(pt, saved, torch.from_numpy(pts).to(dev())).cpu().numpy().astype(np.float64)
+    got = r.query(pt, saved, torch.from_numpy(np.ascontiguousarray(pts.T)).to(dev()))
+    got = got.cpu().numpy().T.astype(np.float64)
     sub = rng.choice(pts.shape[1], 300, replace=False)
     p64 = p.astype(np.float64)
     ref = dr.evaluate_points(p64, w.H, w.W, w.K, pts[:, sub].astype(np.float64))
@@ -97,9 +102,9 @@ def test_texture_2048_n9_queries_sampled():
     _check_points(got[:, sub], ref, tie)
     img, _ = r.render(pt, keep_state=False)
     hh, ww = np.meshgrid(np.arange(1008, 1024), np.arange(512, 528), indexing="ij")
-    cen = torch.tensor(np.stack([ww.ravel() + 0.5, hh.ravel() + 0.5]), dtype=torch.float32,
-                       device=dev())
-    assert torch.equal(r.query(pt, saved, cen), img[:, 1008:1024, 512:528].reshape(w.n, -1))
+    cen = torch.tensor(np.stack([ww.ravel() + 0.5, hh.ravel() + 0.5], axis=1),
+                       dtype=torch.float32, device=dev())
+    assert torch.equal(r.query(pt, saved, cen).T, img[:, 1008:1024, 512:528].reshape(w.n, -1))
 
 
 def test_fp16_storage_and_decode_are_exact():
