@@ -238,6 +238,23 @@ __global__ __launch_bounds__(kThreads) void pair_resolve_kernel(const uint32_t *
   for (; p < P; p += stride) vals[p] = pair_gid[src[p]];
 }
 
+// After the sort: the Gaussian of every sorted pair (from its emit index) and [start, end) of
+// every tile in the sorted list (ranges zeroed beforehand), in one pass.
+__global__ __launch_bounds__(kThreads) void resolve_ranges_kernel(
+    const uint32_t *__restrict__ src, const uint32_t *__restrict__ pair_gid,
+    const uint32_t *__restrict__ keys, const int64_t *__restrict__ status, int64_t cap,
+    uint32_t *__restrict__ vals, int2 *__restrict__ ranges) {
+  int64_t P = status[kStatOverflow] ? 0 : status[kStatPairs];
+  if (P > cap) P = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
+    vals[p] = pair_gid[src[p]];
+    const uint32_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
+    if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);
+  }
+}
+
 // [start, end) of every tile in the sorted pair list (ranges zeroed beforehand).
 __global__ __launch_bounds__(kThreads) void tile_ranges_kernel(const uint32_t *__restrict__ keys,
                                                                const int64_t *__restrict__ status,
@@ -373,6 +390,15 @@ hipError_t launch_pair_resolve(const uint32_t *src, const uint32_t *pair_gid,
                                hipStream_t s) {
   pair_resolve_kernel<<<grid_for(cap, kThreads, 8192), kThreads, 0, s>>>(src, pair_gid, status,
                                                                          cap, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
+                                const uint32_t *keys, const int64_t *status, int64_t cap,
+                                uint32_t *vals, int2 *ranges, hipStream_t s) {
+  resolve_ranges_kernel<<<grid_for(cap, kThreads, 8192), kThreads, 0, s>>>(src, pair_gid, keys,
+                                                                           status, cap, vals,
+                                                                           ranges);
   return hipGetLastError();
 }
 

@@ -156,6 +156,9 @@ hipError_t launch_emit(const float *params, int N, const Images &imgs, const uin
                        uint32_t *pair_gid, hipStream_t s);
 hipError_t launch_pair_resolve(const uint32_t *src, const uint32_t *pair_gid,
                                const int64_t *status, int64_t cap, uint32_t *vals, hipStream_t s);
+hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
+                                const uint32_t *keys, const int64_t *status, int64_t cap,
+                                uint32_t *vals, int2 *ranges, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
                               int2 *ranges, hipStream_t s);
 hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K,
@@ -168,6 +171,10 @@ hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uin
 // scan.hip: exclusive scans; temp must hold scan_temp_elems(n) elements of the output type.
 hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *temp,
                            hipStream_t s);
+// Exclusive scan of the per-Gaussian pair counts into offsets, and the pair total and overflow
+// flag (against cap) into the status block.
+hipError_t scan_counts_to_offsets(const uint32_t *counts, int64_t *offsets, int64_t n,
+                                  int64_t cap, int64_t *status, int64_t *temp, hipStream_t s);
 hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *temp,
                            hipStream_t s);
 

@@ -107,6 +107,13 @@ hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_
   return scan_rec<uint32_t, uint32_t>(in, out, n, temp, s);
 }
 
+hipError_t scan_counts_to_offsets(const uint32_t *counts, int64_t *offsets, int64_t n,
+                                  int64_t cap, int64_t *status, int64_t *temp, hipStream_t s) {
+  hipError_t e = scan_rec<uint32_t, int64_t>(counts, offsets, n, temp, s);
+  if (e != hipSuccess) return e;
+  return launch_pair_total(counts, offsets, (int)n, cap, status, s);
+}
+
 hipError_t scan_f64(const double *in, double *out, int64_t n, double *temp, hipStream_t s) {
   return scan_rec<double, double>(in, out, n, temp, s);
 }
