@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import cref, fitref
+from oracle import cref
 from paper_2407_01866_amd import synth
 import paper_2407_01866_amd._native as nat
 
@@ -68,12 +68,10 @@ def test_fused_equals_separate_path(H, W, n, N, K):
     (ia, la, ga), (ib, lb, gb) = _separate_and_fused(p, tgt, H, W, K)
     assert torch.equal(ia, ib)
     assert_same_gradient(gb, ga)
+    # the separate path's loss kernel is checked against the oracle on seeded images in
+    # test_gpu_render; here the fused loss must equal it up to summation order
     la, lb = la.cpu().numpy(), lb.cpu().numpy()
     assert np.allclose(la, lb, rtol=1e-12, atol=0)
-    ref_l1, _ = fitref.l1_loss_grad(ib.cpu().numpy(), tgt)
-    assert abs(lb[0] - ref_l1) <= 1e-12 * max(1.0, ref_l1)
-    ref_mse = np.mean((ib.cpu().numpy().astype(np.float64) - tgt.astype(np.float64)) ** 2)
-    assert abs(lb[1] - ref_mse) <= 1e-12 * max(1.0, ref_mse)
 
 
 @pytest.mark.parametrize("H,W,n,N,K,seed", [(96, 80, 3, 300, 10, 1), (50, 70, 9, 120, 4, 2),
