@@ -352,7 +352,7 @@ igs_status igs_fit_to_render(const float *fit_params, float *render_params, int3
 typedef struct igs_image_desc {
   int32_t H, W, N, tiles_x;
   int32_t tiles_y, tile_off, gauss_off, l1_block_off;
-  int64_t pix_off, reserved;
+  int64_t pix_off, ssim_block_off;  /* first workgroup of the image in the batched SSIM grid */
 } igs_image_desc;
 
 /*
@@ -412,6 +412,25 @@ igs_status igs_l1_loss_grad_batched(const float *images, const float *targets,
                                     const igs_image_desc *descs_dev, int32_t B, int32_t n,
                                     float *grad_images, double *loss_out, void *workspace,
                                     size_t ws_bytes, void *stream);
+
+/* Scratch bytes igs_l1_ssim_loss_grad_batched needs for the batch. */
+igs_status igs_l1_ssim_batched_workspace_size(const igs_image_desc *descs, int32_t B, int32_t n,
+                                              size_t *ws_bytes);
+
+/*
+ * igs_l1_ssim_loss_grad for every image of a batch in one launch per stencil pass: each image's
+ * loss, SSIM and gradient are those igs_l1_ssim_loss_grad gives for that image alone (gradients
+ * bit for bit; the loss sums in another order).  Strip s of a channel plane belongs to the last
+ * image whose ssim_block_off <= s (igs_batch_describe sets it).
+ *   images, targets, grad_images: concatenated [n][H][W] blocks as for the batched render
+ *   loss_out  device double[B][4]: per image L, mean |image - target|, MSE, SSIM
+ * Errors: as igs_l1_ssim_loss_grad, and IGS_ERR_INVALID_ARG for inconsistent descriptors.
+ */
+igs_status igs_l1_ssim_loss_grad_batched(const float *images, const float *targets,
+                                         const igs_image_desc *descs_host,
+                                         const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                         double ssim_weight, float *grad_images, double *loss_out,
+                                         void *workspace, size_t ws_bytes, void *stream);
 
 /* igs_adam_step for a batch: each Gaussian's mean is normalized by its own image's W and H and
    its inverse scales are clipped to [1/max(H,W), inv_scale_hi] of its image. */

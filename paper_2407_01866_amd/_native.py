@@ -37,7 +37,8 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_render_backward_l1_batched", "igs_set_launch_config", "igs_get_launch_config",
             "igs_l1_ssim_workspace_size", "igs_l1_ssim_loss_grad", "igs_place_workspace_size",
             "igs_init_gaussians", "igs_add_gaussians", "igs_bin", "igs_query",
-            "igs_query_workspace_size",
+            "igs_query_workspace_size", "igs_l1_ssim_batched_workspace_size",
+            "igs_l1_ssim_loss_grad_batched",
             "igs_params_to_fp16", "igs_decode_fp16")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce")
@@ -49,7 +50,7 @@ class ImageDesc(ctypes.Structure):
                 ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
                 ("tile_off", ctypes.c_int32), ("gauss_off", ctypes.c_int32),
                 ("l1_block_off", ctypes.c_int32), ("pix_off", ctypes.c_int64),
-                ("reserved", ctypes.c_int64)]
+                ("ssim_block_off", ctypes.c_int64)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -133,6 +134,11 @@ def lib() -> ctypes.CDLL:
     L.igs_fit_to_render.restype = i32
     dp = ctypes.POINTER(ImageDesc)
     i32p = ctypes.POINTER(i32)
+    L.igs_l1_ssim_batched_workspace_size.argtypes = [dp, i32, i32, ctypes.POINTER(sz)]
+    L.igs_l1_ssim_batched_workspace_size.restype = i32
+    L.igs_l1_ssim_loss_grad_batched.argtypes = [vp, vp, dp, vp, i32, i32, ctypes.c_double, vp, vp,
+                                                vp, sz, vp]
+    L.igs_l1_ssim_loss_grad_batched.restype = i32
     L.igs_batch_describe.argtypes = [i32, i32, i32p, i32p, i32p, dp, ctypes.POINTER(i64)]
     L.igs_batch_describe.restype = i32
     L.igs_batch_buffer_sizes.argtypes = [dp, i32, i32, i32, i64, ctypes.POINTER(sz), ctypes.POINTER(sz)]
@@ -498,6 +504,23 @@ def igs_l1_loss_grad_batched(images, targets, descs, d_descs, n, grad_images, lo
         _f32(images, "images"), _f32(targets, "targets"), descs, _ptr(d_descs), len(descs), n,
         _f32(grad_images, "grad_images"), _ptr(loss_out), _ptr(workspace), ws_bytes,
         _stream(stream)))
+
+
+def igs_l1_ssim_batched_workspace_size(descs, n) -> int:
+    ws = ctypes.c_size_t(0)
+    _check("igs_l1_ssim_batched_workspace_size",
+           lib().igs_l1_ssim_batched_workspace_size(descs, len(descs), n, ctypes.byref(ws)))
+    return ws.value
+
+
+def igs_l1_ssim_loss_grad_batched(images, targets, descs, d_descs, n, ssim_weight, grad_images,
+                                  loss_out, workspace, ws_bytes, stream=None) -> None:
+    if loss_out.dtype != torch.float64 or loss_out.numel() < 4 * len(descs):
+        raise TypeError("loss_out must be float64[B][4]")
+    _check("igs_l1_ssim_loss_grad_batched", lib().igs_l1_ssim_loss_grad_batched(
+        _f32(images, "images"), _f32(targets, "targets"), descs, _ptr(d_descs), len(descs), n,
+        float(ssim_weight), _f32(grad_images, "grad_images"), _ptr(loss_out), _ptr(workspace),
+        ws_bytes, _stream(stream)))
 
 
 def igs_adam_step_batched(fit_params, render_params, grad_render, m, v, step, descs, d_descs, n,

@@ -363,13 +363,15 @@ Images single_view(int H, int W, int N) {
 igs_status check_descs(const igs_image_desc *descs, int32_t B, int32_t n, int64_t *blocks_out) {
   if (!descs || B < 1 || n < 1 || n > IGS_MAX_CHANNELS) return IGS_ERR_INVALID_ARG;
   const int64_t items = l1_batch_block_items();
-  int64_t g = 0, t = 0, p = 0, blk = 0;
+  int64_t g = 0, t = 0, p = 0, blk = 0, sblk = 0;
   for (int b = 0; b < B; ++b) {
     const igs_image_desc &d = descs[b];
     if (d.H < 1 || d.W < 1 || d.H > 65536 || d.W > 65536 || d.N < 0) return IGS_ERR_INVALID_ARG;
     if (d.tiles_x != (d.W + kTile - 1) / kTile || d.tiles_y != (d.H + kTile - 1) / kTile ||
-        d.gauss_off != g || d.tile_off != t || d.pix_off != p || d.l1_block_off != blk)
+        d.gauss_off != g || d.tile_off != t || d.pix_off != p || d.l1_block_off != blk ||
+        d.ssim_block_off != sblk)
       return IGS_ERR_INVALID_ARG;
+    sblk += ssim_strips(d.H, d.W);
     g += d.N;
     t += (int64_t)d.tiles_x * d.tiles_y;
     p += (int64_t)d.H * d.W;
@@ -516,7 +518,7 @@ IGS_API igs_status igs_batch_describe(int32_t B, int32_t n, const int32_t *H, co
                                       int64_t totals_out[4]) {
   if (B < 1 || n < 1 || n > IGS_MAX_CHANNELS || !H || !W || !N || !descs_out || !totals_out)
     return IGS_ERR_INVALID_ARG;
-  int64_t g = 0, t = 0, p = 0, blk = 0;
+  int64_t g = 0, t = 0, p = 0, blk = 0, sblk = 0;
   const int64_t items = l1_batch_block_items();
   for (int b = 0; b < B; ++b) {
     if (H[b] < 1 || W[b] < 1 || H[b] > 65536 || W[b] > 65536 || N[b] < 0) return IGS_ERR_INVALID_ARG;
@@ -530,7 +532,8 @@ IGS_API igs_status igs_batch_describe(int32_t B, int32_t n, const int32_t *H, co
     d.gauss_off = (int32_t)g;
     d.l1_block_off = (int32_t)blk;
     d.pix_off = p;
-    d.reserved = 0;
+    d.ssim_block_off = sblk;
+    sblk += ssim_strips(H[b], W[b]);
     g += N[b];
     t += (int64_t)d.tiles_x * d.tiles_y;
     p += (int64_t)H[b] * W[b];
@@ -794,6 +797,54 @@ IGS_API igs_status igs_l1_loss_grad_batched(const float *images, const float *ta
   IGS_HIP(launch_l1_batched(images, targets, batch_view(descs_dev, B), n, (int)blocks, grad_images,
                             static_cast<double *>(workspace), loss_out,
                             static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
+static int64_t ssim_total_strips(const igs_image_desc *descs, int32_t B) {
+  int64_t t = 0;
+  for (int b = 0; b < B; ++b) t += ssim_strips(descs[b].H, descs[b].W);
+  return t;
+}
+
+static size_t ssim_batched_bytes(const igs_image_desc *descs, int32_t B, int32_t n,
+                                 size_t *maps_plane) {
+  int64_t P = 0;
+  for (int b = 0; b < B; ++b) P += (int64_t)descs[b].H * descs[b].W;
+  const size_t plane = align_up((size_t)n * P * sizeof(float));
+  if (maps_plane) *maps_plane = plane;
+  return 3 * plane + align_up((size_t)n * ssim_total_strips(descs, B) * 3 * sizeof(double));
+}
+
+IGS_API igs_status igs_l1_ssim_batched_workspace_size(const igs_image_desc *descs, int32_t B,
+                                                      int32_t n, size_t *ws_bytes) {
+  if (!ws_bytes) return IGS_ERR_INVALID_ARG;
+  igs_status st = check_descs(descs, B, n, nullptr);
+  if (st != IGS_OK) return st;
+  *ws_bytes = ssim_batched_bytes(descs, B, n, nullptr);
+  return IGS_OK;
+}
+
+IGS_API igs_status igs_l1_ssim_loss_grad_batched(const float *images, const float *targets,
+                                                 const igs_image_desc *descs_host,
+                                                 const igs_image_desc *descs_dev, int32_t B,
+                                                 int32_t n, double ssim_weight, float *grad_images,
+                                                 double *loss_out, void *workspace,
+                                                 size_t ws_bytes, void *stream) {
+  igs_status st = check_descs(descs_host, B, n, nullptr);
+  if (st != IGS_OK) return st;
+  if (!images || !targets || !descs_dev || !grad_images || !loss_out || !workspace ||
+      !(ssim_weight >= 0.0 && ssim_weight <= 1.0e30))
+    return IGS_ERR_INVALID_ARG;
+  size_t plane = 0;
+  if (ws_bytes < ssim_batched_bytes(descs_host, B, n, &plane)) return IGS_ERR_WORKSPACE;
+  char *w = static_cast<char *>(workspace);
+  PhaseTimer timer(kPhaseLoss, static_cast<hipStream_t>(stream));
+  IGS_HIP(launch_l1_ssim_batched(images, targets, batch_view(descs_dev, B), n,
+                                 ssim_total_strips(descs_host, B), ssim_weight, grad_images,
+                                 reinterpret_cast<float *>(w), reinterpret_cast<float *>(w + plane),
+                                 reinterpret_cast<float *>(w + 2 * plane),
+                                 reinterpret_cast<double *>(w + 3 * plane), loss_out,
+                                 static_cast<hipStream_t>(stream)));
   return IGS_OK;
 }
 

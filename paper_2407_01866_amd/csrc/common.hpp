@@ -57,12 +57,13 @@ int persistent_grid(int per_cu, int T);
 // tiles [tile_off, tile_off + tiles_x * tiles_y) of the global tile numbering, and its pixels
 // [pix_off, pix_off + H * W): its image and image gradient start at float n * pix_off, its top-K
 // slots at K * pix_off, its per-pixel blend normalization at pix_off.  l1_block_off numbers the
-// loss kernel's blocks (image b owns blocks [l1_block_off[b], l1_block_off[b + 1])).
+// loss kernel's blocks (image b owns blocks [l1_block_off[b], l1_block_off[b + 1])), and
+// ssim_block_off the SSIM stencils' strips (ssim_strips(H, W) per image and channel).
 // Layout identical to igs_image_desc in include/imagegs.h.
 struct ImageDesc {
   int32_t H, W, N, tiles_x;
   int32_t tiles_y, tile_off, gauss_off, l1_block_off;
-  int64_t pix_off, reserved;
+  int64_t pix_off, ssim_block_off;
 };
 static_assert(sizeof(ImageDesc) == 48, "ImageDesc layout");
 
@@ -218,6 +219,13 @@ hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const flo
                               float *grad_params, hipStream_t s);
 
 // loss_adam.hip
+// SSIM strips of one channel plane of an H x W image in the batched stencils (32 x 128 each).
+inline int64_t ssim_strips(int H, int W) { return (int64_t)((W + 31) / 32) * ((H + 127) / 128); }
+hipError_t launch_l1_ssim_batched(const float *images, const float *targets, const Images &imgs,
+                                  int n, int64_t strips, double weight, float *grad, float *d_mx,
+                                  float *d_exx, float *d_exy, double *partial, double *loss_out,
+                                  hipStream_t s);
+
 // Decoding (query.hip): colours at arbitrary points from a binning pass's tile lists; float16
 // storage of the fitter's parameters and decoding of a prefix into renderer units.
 size_t query_workspace_bytes(int64_t M, int H, int W);

@@ -224,25 +224,68 @@ __device__ __forceinline__ int strip_chunks(int H, int ys, int cps) {
   return min(cps, (H - ys + kChunkH - 1) / kChunkH);
 }
 
+static_assert(kStripW == 32 && kMaxChunks * kChunkH == 128, "batched strips: ssim_strips()");
+
+// The strip a workgroup processes and its image: a single image (H, W given; strips dealt so
+// that each XCD gets a contiguous run, whose 5-column halos then hit that XCD's L2), or a batch
+// (the image found by its first strip, ssim_block_off; strips of up to 128 rows).  blockIdx.y is
+// the channel.
+struct StripSpec {
+  int H, W, x0, ys, cps;
+  size_t plane;   // first value of the channel plane
+  int64_t count;  // n H W of the image
+};
+
+__device__ __forceinline__ StripSpec strip_of(const Images &imgs, int n, int H, int W,
+                                              int strips_x, int cps) {
+  StripSpec r;
+  if (imgs.arr) {
+    int lo = 0, hi = imgs.B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (imgs.arr[mid].ssim_block_off <= (int64_t)blockIdx.x) lo = mid;
+      else hi = mid - 1;
+    }
+    const ImageDesc im = imgs.arr[lo];
+    const int sxn = (im.W + kStripW - 1) / kStripW;
+    const int local = (int)(blockIdx.x - im.ssim_block_off);
+    const int sy = local / sxn, sx = local - sy * sxn;
+    r.H = im.H;
+    r.W = im.W;
+    r.cps = kMaxChunks;
+    r.x0 = sx * kStripW;
+    r.ys = sy * kMaxChunks * kChunkH;
+    r.plane = (size_t)n * im.pix_off + (size_t)blockIdx.y * im.H * im.W;
+  } else {
+    const int strip = xcd_tile(blockIdx.x, gridDim.x);
+    const int sy = strip / strips_x, sx = strip - sy * strips_x;
+    r.H = H;
+    r.W = W;
+    r.cps = cps;
+    r.x0 = sx * kStripW;
+    r.ys = sy * cps * kChunkH;
+    r.plane = (size_t)blockIdx.y * H * W;
+  }
+  r.count = (int64_t)n * r.H * r.W;
+  return r;
+}
+
 // Four workgroups fit a CU's LDS; the register budget is held to match (128 VGPRs).
 __global__ __launch_bounds__(kSsimThreads) __attribute__((amdgpu_waves_per_eu(4))) void
 ssim_fwd_kernel(
-    const float *__restrict__ img, const float *__restrict__ tgt, int H, int W, int strips_x,
-    int cps, Win<double> win, float *__restrict__ d_mx, float *__restrict__ d_exx,
-    float *__restrict__ d_exy, double *__restrict__ partial) {
+    const float *__restrict__ img, const float *__restrict__ tgt, Images imgs, int n, int H0,
+    int W0, int strips_x, int cps0, Win<double> win, float *__restrict__ d_mx,
+    float *__restrict__ d_exx, float *__restrict__ d_exy, double *__restrict__ partial) {
   __shared__ float s_in[2][kStageN];
   __shared__ double s_h[5][kRing * kStripW];
   __shared__ double s_red[3][kSsimThreads / 64];
 
-  // neighbouring strips share their 5-column halos: give each XCD a contiguous run of strips so
-  // the halo re-reads hit that XCD's L2
-  const int strip = xcd_tile(blockIdx.x, gridDim.x);
-  const int sy = strip / strips_x, sx = strip - sy * strips_x;
-  const int x0 = sx * kStripW, ys = sy * cps * kChunkH;
-  const size_t plane = (size_t)blockIdx.y * H * W;
+  const StripSpec sp = strip_of(imgs, n, H0, W0, strips_x, cps0);
+  const int H = sp.H, W = sp.W, x0 = sp.x0, ys = sp.ys;
+  const size_t plane = sp.plane;
   const float *const src[2] = {img + plane, tgt + plane};
   const int tid = threadIdx.x;
-  const int nchunks = strip_chunks(H, ys, cps);
+  const int nchunks = strip_chunks(H, ys, sp.cps);
 
   // prologue: the 10 rows above the strip's first output row
   Stage<2> st;
@@ -339,26 +382,62 @@ __global__ __launch_bounds__(1024) void ssim_final_kernel(const double *__restri
   }
 }
 
-// Eight workgroups fit a CU's LDS; the register budget is held to match (64 VGPRs).
-__global__ __launch_bounds__(kSsimThreads) __attribute__((amdgpu_waves_per_eu(8))) void
+// One block per image of a batch: its strips' sums over every channel, in a fixed order;
+// out[4 b ..] = {L, L1, MSE, SSIM} of image b.
+__global__ __launch_bounds__(256) void ssim_final_batched_kernel(
+    const double *__restrict__ partial, Images imgs, int n, int64_t strips_total, double weight,
+    double *__restrict__ out) {
+  __shared__ double s_red[3][256 / 64];
+  const ImageDesc im = imgs.arr[blockIdx.x];
+  const int64_t nb = (int64_t)((im.W + kStripW - 1) / kStripW) *
+                     ((im.H + kMaxChunks * kChunkH - 1) / (kMaxChunks * kChunkH));
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < n; ++c)
+    for (int64_t j = threadIdx.x; j < nb; j += blockDim.x) {
+      const double *pr = partial + ((size_t)c * strips_total + im.ssim_block_off + j) * 3;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t[k] += pr[k];
+    }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double v = wsum64(t[k]);
+    if ((threadIdx.x & 63) == 0) s_red[k][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum[3] = {0.0, 0.0, 0.0};
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sum[k] += s_red[k][w];
+    const double inv = 1.0 / ((double)n * im.H * im.W);
+    const double ssim = sum[0] * inv, l1 = sum[1] * inv;
+    double *o = out + 4 * (size_t)blockIdx.x;
+    o[0] = l1 + weight * (1.0 - ssim);
+    o[1] = l1;
+    o[2] = sum[2] * inv;
+    o[3] = ssim;
+  }
+}
+
+// Seven waves per SIMD: the register budget (72 VGPRs) that holds the strip lookup without
+// spilling; LDS would allow eight workgroups per CU.
+__global__ __launch_bounds__(kSsimThreads) __attribute__((amdgpu_waves_per_eu(7))) void
 ssim_bwd_kernel(
     const float *__restrict__ img, const float *__restrict__ tgt,
     const float *__restrict__ d_mx, const float *__restrict__ d_exx,
-    const float *__restrict__ d_exy, int H, int W, int strips_x, int cps, Win<float> win,
-    float l1_scale,
-    float ssim_scale, float *__restrict__ grad) {
+    const float *__restrict__ d_exy, Images imgs, int n, int H0, int W0, int strips_x, int cps0,
+    Win<float> win, double weight, float *__restrict__ grad) {
   __shared__ float s_in[3][kStageN];
   __shared__ float s_h[3][kRing * kStripW];
 
-  // neighbouring strips share their 5-column halos: give each XCD a contiguous run of strips so
-  // the halo re-reads hit that XCD's L2
-  const int strip = xcd_tile(blockIdx.x, gridDim.x);
-  const int sy = strip / strips_x, sx = strip - sy * strips_x;
-  const int x0 = sx * kStripW, ys = sy * cps * kChunkH;
-  const size_t plane = (size_t)blockIdx.y * H * W;
+  const StripSpec sp = strip_of(imgs, n, H0, W0, strips_x, cps0);
+  const int H = sp.H, W = sp.W, x0 = sp.x0, ys = sp.ys;
+  const size_t plane = sp.plane;
+  const float l1_scale = (float)(1.0 / (double)sp.count);
+  const float ssim_scale = (float)(-weight / (double)sp.count);
   const float *const src[3] = {d_mx + plane, d_exx + plane, d_exy + plane};
   const int tid = threadIdx.x;
-  const int nchunks = strip_chunks(H, ys, cps);
+  const int nchunks = strip_chunks(H, ys, sp.cps);
 
   Stage<3> st;
   st.load(src, H, W, x0, ys - kSsimR, 2 * kSsimR);
@@ -443,15 +522,32 @@ hipError_t launch_l1_ssim(const float *image, const float *target, int n, int H,
   const int strips_y = (H + cps * kChunkH - 1) / (cps * kChunkH);
   const dim3 grid(strips_x * strips_y, n);
   const int64_t count = (int64_t)n * H * W;
-  ssim_fwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, H, W, strips_x, cps,
+  Images none{};
+  none.arr = nullptr;
+  none.B = 0;
+  ssim_fwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, none, n, H, W, strips_x, cps,
                                                 make_window<double>(), d_mx, d_exx, d_exy,
                                                 partial);
   ssim_final_kernel<<<1, 1024, 0, s>>>(partial, (int64_t)grid.x * grid.y, 1.0 / (double)count,
                                        weight, loss_out);
-  ssim_bwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, d_mx, d_exx, d_exy, H, W,
-                                                strips_x, cps, make_window<float>(),
-                                                (float)(1.0 / count), (float)(-weight / count),
+  ssim_bwd_kernel<<<grid, kSsimThreads, 0, s>>>(image, target, d_mx, d_exx, d_exy, none, n, H, W,
+                                                strips_x, cps, make_window<float>(), weight,
                                                 grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_ssim_batched(const float *images, const float *targets, const Images &imgs,
+                                  int n, int64_t strips, double weight, float *grad, float *d_mx,
+                                  float *d_exx, float *d_exy, double *partial, double *loss_out,
+                                  hipStream_t s) {
+  if (strips <= 0) return hipSuccess;
+  const dim3 grid((unsigned)strips, n);
+  ssim_fwd_kernel<<<grid, kSsimThreads, 0, s>>>(images, targets, imgs, n, 0, 0, 0, kMaxChunks,
+                                                make_window<double>(), d_mx, d_exx, d_exy,
+                                                partial);
+  ssim_final_batched_kernel<<<imgs.B, 256, 0, s>>>(partial, imgs, n, strips, weight, loss_out);
+  ssim_bwd_kernel<<<grid, kSsimThreads, 0, s>>>(images, targets, d_mx, d_exx, d_exy, imgs, n, 0, 0,
+                                                0, kMaxChunks, make_window<float>(), weight, grad);
   return hipGetLastError();
 }
 

@@ -340,13 +340,22 @@ class BatchFitter(_FitLoop):
 
     def __init__(self, targets: List[torch.Tensor], render_params: List[torch.Tensor], K: int = 10,
                  adam: Optional[AdamConfig] = None, headroom: float = 1.25,
-                 pair_capacity: Optional[int] = None, device=None, fused: Optional[bool] = None):
+                 pair_capacity: Optional[int] = None, device=None, fused: Optional[bool] = None,
+                 ssim_weight: float = 0.0):
         from .render import BatchRenderer
         self.dev = torch.device(device) if device is not None else targets[0].device
         self.n = int(targets[0].shape[0])
         self.K = K
         self.adam = adam or AdamConfig()
-        self.fused = (self.n <= MAX_FUSED_CHANNELS) if fused is None else bool(fused)
+        self.ssim_weight = float(ssim_weight)
+        if self.ssim_weight < 0:
+            raise ValueError("ssim_weight must be >= 0")
+        if self.ssim_weight > 0 and fused:
+            raise ValueError("the SSIM term is not fused into the render pass")
+        if self.ssim_weight > 0:
+            self.fused = False
+        else:
+            self.fused = (self.n <= MAX_FUSED_CHANNELS) if fused is None else bool(fused)
         sizes = [(int(t.shape[1]), int(t.shape[2]), int(p.shape[1]))
                  for t, p in zip(targets, render_params)]
         self.r = BatchRenderer(sizes, self.n, K, pair_capacity=pair_capacity, device=self.dev)
@@ -367,8 +376,15 @@ class BatchFitter(_FitLoop):
         self.image = self.r.new_images()
         self.grad_image = torch.empty_like(self.image)
         self.grad_params = torch.empty_like(self.fit)
-        self.loss = torch.zeros((self.B, 2), dtype=torch.float64, device=self.dev)
-        self.l1_ws = _aligned_bytes(nat.igs_l1_batched_workspace_size(self.r.descs, self.n), self.dev)
+        # L1 alone: per image [mean |x - y|, MSE]; with SSIM: [L, mean |x - y|, MSE, SSIM]
+        self.loss = torch.zeros((self.B, 4 if self.ssim_weight > 0 else 2), dtype=torch.float64,
+                                device=self.dev)
+        if self.ssim_weight > 0:
+            self.l1_ws = _aligned_bytes(
+                nat.igs_l1_ssim_batched_workspace_size(self.r.descs, self.n), self.dev)
+        else:
+            self.l1_ws = _aligned_bytes(nat.igs_l1_batched_workspace_size(self.r.descs, self.n),
+                                        self.dev)
         if pair_capacity is None:
             _, saved = self.r.render(self.rend)
             P = int(self.r.status_of(saved)[nat.STAT_PAIRS])
@@ -385,9 +401,14 @@ class BatchFitter(_FitLoop):
             r.backward_l1_into(self.rend, self.saved, self.grad_params)
         else:
             r.render_into(self.rend, self.image, self.saved)
-            nat.igs_l1_loss_grad_batched(self.image, self.target, r.descs, r.d_descs, self.n,
-                                         self.grad_image, self.loss, self.l1_ws,
-                                         self.l1_ws.numel())
+            if self.ssim_weight > 0:
+                nat.igs_l1_ssim_loss_grad_batched(self.image, self.target, r.descs, r.d_descs,
+                                                  self.n, self.ssim_weight, self.grad_image,
+                                                  self.loss, self.l1_ws, self.l1_ws.numel())
+            else:
+                nat.igs_l1_loss_grad_batched(self.image, self.target, r.descs, r.d_descs, self.n,
+                                             self.grad_image, self.loss, self.l1_ws,
+                                             self.l1_ws.numel())
             r.backward_into(self.rend, self.image, self.grad_image, self.saved, self.grad_params)
         nat.igs_adam_step_batched(self.fit, self.rend, self.grad_params, self.m, self.v,
                                   self.step_count, r.descs, r.d_descs, self.n, a.lr_mu, a.lr_theta,
@@ -395,7 +416,7 @@ class BatchFitter(_FitLoop):
                                   a.inv_scale_hi, skip_flag=self._overflow_word())
 
     def psnrs(self) -> List[float]:
-        mse = self.loss[:, 1].cpu().tolist()
+        mse = self.loss[:, 2 if self.ssim_weight > 0 else 1].cpu().tolist()
         return [10.0 * math.log10(1.0 / m) if m > 0 else math.inf for m in mse]
 
     def psnr(self) -> float:

@@ -169,3 +169,55 @@ def test_batch_fitter_tracks_plain_fitters():
         # every kernel of the batched iteration evaluates each image exactly as the plain one
         assert pf.psnr() == bp[b], b
         assert torch.equal(bf.image_params(b), pf.rend), b
+
+
+def test_batched_ssim_loss_equals_plain_calls():
+    """igs_l1_ssim_loss_grad_batched gives every image the gradient igs_l1_ssim_loss_grad gives it
+    alone (bit for bit: the same per-pixel operations) and its loss terms (sums in another
+    order)."""
+    from paper_2407_01866_amd import _native as nat
+    from paper_2407_01866_amd.render import BatchRenderer
+    d = dev()
+    n = 3
+    sizes = [(64, 96, 10), (130, 47, 10), (5, 7, 10), (300, 200, 10), (1, 77, 10), (128, 32, 10)]
+    print(f"[batch-ssim] {len(sizes)} images", flush=True)
+    br = BatchRenderer(sizes, n, 10, device=d)
+    rng = np.random.default_rng(12)
+    imgs = [torch.from_numpy(synth.gen_image(80 + b, H, W, n, 6)) for b, (H, W, _) in enumerate(sizes)]
+    tgts = [torch.from_numpy((synth.gen_image(80 + b, H, W, n, 6) +
+                              rng.normal(0, 0.05, (n, H, W))).astype(np.float32))
+            for b, (H, W, _) in enumerate(sizes)]
+    I, T = br.pack_images(imgs), br.pack_images(tgts)
+    G = torch.empty_like(I)
+    loss = torch.zeros((len(sizes), 4), dtype=torch.float64, device=d)
+    ws = torch.empty(nat.igs_l1_ssim_batched_workspace_size(br.descs, n), dtype=torch.uint8,
+                     device=d)
+    nat.igs_l1_ssim_loss_grad_batched(I, T, br.descs, br.d_descs, n, 0.1, G, loss, ws, ws.numel())
+    torch.cuda.synchronize()
+    gv = br.image_views(G)
+    for b, (H, W, _) in enumerate(sizes):
+        x, y = imgs[b].to(d), tgts[b].to(d)
+        g = torch.empty_like(x)
+        lo = torch.zeros(4, dtype=torch.float64, device=d)
+        w1 = torch.empty(nat.igs_l1_ssim_workspace_size(n, H, W), dtype=torch.uint8, device=d)
+        nat.igs_l1_ssim_loss_grad(x, y, n, H, W, 0.1, g, lo, w1, w1.numel())
+        torch.cuda.synchronize()
+        assert torch.equal(gv[b], g), b
+        assert np.allclose(loss[b].cpu().numpy(), lo.cpu().numpy(), rtol=1e-12, atol=1e-15), b
+
+
+def test_batch_fitter_with_ssim_tracks_plain_fitters():
+    from paper_2407_01866_amd.fit import BatchFitter, PlainFitter
+    d = dev()
+    n, K = 3, 10
+    sizes = [(64, 96, 400), (200, 136, 900), (32, 48, 100)]
+    tg = [torch.from_numpy(synth.gen_image(40 + b, H, W, n, 10)).to(d) for b, (H, W, _) in enumerate(sizes)]
+    ps = [torch.from_numpy(synth.gen_gaussians(50 + b, H, W, N, n)).to(d) for b, (H, W, N) in enumerate(sizes)]
+    bf = BatchFitter(tg, ps, K, ssim_weight=0.1)
+    bf.run(30, report_every=30)
+    bp = bf.psnrs()
+    for b in range(len(sizes)):
+        pf = PlainFitter(tg[b], ps[b], K, ssim_weight=0.1)
+        pf.run(30, report_every=30)
+        assert torch.equal(bf.image_params(b), pf.rend), b
+        assert abs(pf.psnr() - bp[b]) < 1e-9, b
