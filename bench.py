@@ -257,7 +257,13 @@ PROFILE_CMDS = {
                   "python3 bench.py --copy-calibration",
     "ssim": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_ssim -o ssim -- "
             "python3 bench.py --ssim-profile",
+    "valu": "rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_INSTS_VALU SQ_INSTS_LDS "
+            "SQ_WAVES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE GRBM_COUNT --kernel-include-regex raster "
+            "-f csv -d gpurun_out/pmc_valu -o valu -- python3 bench.py --steps 3 --warmup 1 "
+            "--no-cpu-baseline --no-context --batch-iters 0 --no-ssim --no-decode "
+            "--launch-config 0,0,1",
 }
+VALU_FILE = os.path.join(PROFILES, "valu_counters_raster_texture-2048x2048-n9-N100000.txt")
 
 
 def kernel_source_hash(kernel):
@@ -304,6 +310,33 @@ def summarize_profiles(out_dir):
         open(os.path.join(PROFILES, "kernel_trace_ssim_texture-2048x2048-n9.md"), "w").write(
             "\n".join(lines) + "\n")
 
+    valu_csv = os.path.join(out_dir, "pmc_valu", "valu_counter_collection.csv")
+    if os.path.exists(valu_csv):
+        import re
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(valu_csv)):
+            m = re.search(r"(raster_\w+<[^>]*>)", r["Kernel_Name"])
+            if m:
+                per[m.group(1)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        out = ["# VALU issue of the raster kernels, texture-2048x2048-n9-N100000 (per dispatch)",
+               "# SQ_* summed over all SIMDs; GRBM_GUI_ACTIVE summed over the 8 XCDs.  A wave64",
+               "# VALU instruction occupies a SIMD for 4 cycles (16 lanes, packed FP32 off), so",
+               "# issue_busy = SQ_INSTS_VALU * 4 / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8) and",
+               "# active_lanes = SQ_THREAD_CYCLES_VALU / (64 SQ_INSTS_VALU).",
+               "# command: " + PROFILE_CMDS["valu"]]
+        for k, c in sorted(per.items()):
+            a = {n: sum(v) / len(v) for n, v in c.items()}
+            cyc = a["GRBM_GUI_ACTIVE"] / 8
+            kern = "raster_fwd" if "raster_fwd" in k else "raster_bwd"
+            out.append(f"kernel {k.replace(' ', '')} family {kern} source_sha256 "
+                       f"{kernel_source_hash(kern)} dispatches {len(c['SQ_WAVES'])} "
+                       f"valu_insts {a['SQ_INSTS_VALU']:.4g} lds_insts {a['SQ_INSTS_LDS']:.4g} "
+                       f"cycles_per_xcd {cyc:.4g} "
+                       f"issue_busy {a['SQ_INSTS_VALU'] * 4 / 1024 / cyc:.3f} "
+                       f"active_lanes {a['SQ_THREAD_CYCLES_VALU'] / (64 * a['SQ_INSTS_VALU']):.3f} "
+                       f"executed_lane_slots {64 * a['SQ_INSTS_VALU']:.4g}")
+        open(VALU_FILE, "w").write("\n".join(out) + "\n")
+
     def counter(sub, fname):
         d = collections.defaultdict(list)
         for r in csv.DictReader(open(os.path.join(out_dir, sub, fname))):
@@ -334,6 +367,25 @@ def summarize_profiles(out_dir):
                    f"traffic_bytes {rb + wb:.4g}")
     open(TRAFFIC_FILE, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
+
+
+def measured_valu(kernel, fused=True):
+    """(issue_busy, active_lanes, executed lane slots) of the kernel from the committed counter
+    summary, or None when that summary is missing or was taken from another source."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    want = "raster_fwd_kernel<10,true,false>" if kernel == "raster_fwd" else \
+        "raster_bwd_kernel<9,10,true>"
+    for line in open(VALU_FILE):
+        f = line.split()
+        if len(f) > 2 and f[0] == "kernel" and f[1] == want:
+            kv = dict(zip(f[2::2], f[3::2]))
+            if kv.get("source_sha256") != kernel_source_hash(kernel):
+                return None
+            return {"issue_busy": float(kv["issue_busy"]),
+                    "active_lanes": float(kv["active_lanes"]),
+                    "executed_lane_slots": float(kv["executed_lane_slots"])}
+    return None
 
 
 def measured_traffic(kernel):
@@ -545,6 +597,7 @@ def main():
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
                 "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": measured_traffic(dom),
+                "valu_counters": measured_valu(dom),
                 "avg_ms": round(avg[dom], 4),
                 "work_per_launch": f"{ops[dom]:.4g} VALU lane-ops"}
 
@@ -552,7 +605,8 @@ def main():
     roofline_bwd = {"kernel": other, "achieved": round(ops[other] / (avg[other] * 1e-3) / 1e12, 3),
                     "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
                     "frac": round(ops[other] / (avg[other] * 1e-3) / PEAK_LANE_OPS, 4),
-                    "traffic": measured_traffic(other), "avg_ms": round(avg[other], 4),
+                    "traffic": measured_traffic(other), "valu_counters": measured_valu(other),
+                    "avg_ms": round(avg[other], 4),
                     "work_per_launch": f"{ops[other]:.4g} VALU lane-ops"}
     cpu = None
     if not args.no_cpu_baseline:
