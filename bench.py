@@ -257,6 +257,10 @@ PROFILE_CMDS = {
                   "python3 bench.py --copy-calibration",
     "ssim": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_ssim -o ssim -- "
             "python3 bench.py --ssim-profile",
+    "valu_ssim": "rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_INSTS_VALU "
+                 "SQ_INSTS_LDS SQ_WAVES SQ_WAIT_INST_LDS GRBM_GUI_ACTIVE GRBM_COUNT "
+                 "--kernel-include-regex ssim -f csv -d gpurun_out/pmc_ssim -o s -- python3 "
+                 "bench.py --ssim-profile",
     "valu": "rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_INSTS_VALU SQ_INSTS_LDS "
             "SQ_WAVES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE GRBM_COUNT --kernel-include-regex raster "
             "-f csv -d gpurun_out/pmc_valu -o valu -- python3 bench.py --steps 3 --warmup 1 "
@@ -336,6 +340,30 @@ def summarize_profiles(out_dir):
                        f"active_lanes {a['SQ_THREAD_CYCLES_VALU'] / (64 * a['SQ_INSTS_VALU']):.3f} "
                        f"executed_lane_slots {64 * a['SQ_INSTS_VALU']:.4g}")
         open(VALU_FILE, "w").write("\n".join(out) + "\n")
+
+    ssim_pmc = os.path.join(out_dir, "pmc_ssim", "s_counter_collection.csv")
+    if os.path.exists(ssim_pmc):
+        import re
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(ssim_pmc)):
+            m = re.search(r"(ssim_\w+_kernel)", r["Kernel_Name"])
+            if m:
+                per[m.group(1)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        values = 9 * 2048 * 2048
+        out = ["# VALU issue of the SSIM stencils, L1 + 0.1 SSIM loss at 2048^2, n=9 (per dispatch)",
+               "# issue_busy = SQ_INSTS_VALU * 4 / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8); "
+               "lane_ops_per_value = 64 SQ_INSTS_VALU / (n H W)",
+               "# command: " + PROFILE_CMDS["valu_ssim"]]
+        for k, c in sorted(per.items()):
+            a = {n: sum(v) / len(v) for n, v in c.items()}
+            cyc = a["GRBM_GUI_ACTIVE"] / 8
+            out.append(f"kernel {k} dispatches {len(c['SQ_WAVES'])} valu_insts "
+                       f"{a['SQ_INSTS_VALU']:.4g} cycles_per_xcd {cyc:.4g} issue_busy "
+                       f"{a['SQ_INSTS_VALU'] * 4 / 1024 / cyc:.3f} active_lanes "
+                       f"{a['SQ_THREAD_CYCLES_VALU'] / (64 * a['SQ_INSTS_VALU']):.3f} "
+                       f"lane_ops_per_value {64 * a['SQ_INSTS_VALU'] / values:.4g}")
+        open(os.path.join(PROFILES, "valu_counters_ssim_texture-2048x2048-n9.txt"), "w").write(
+            "\n".join(out) + "\n")
 
     def counter(sub, fname):
         d = collections.defaultdict(list)
