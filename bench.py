@@ -242,7 +242,10 @@ def decode_step(torch, dev, w, params, M=1 << 22, calls=10):
 
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "hbm_traffic_raster_texture-2048x2048-n9-N100000.txt")
-KERNEL_SOURCES = {"raster_fwd": "raster_fwd.hip", "raster_bwd": "raster_bwd.hip"}
+KERNEL_SOURCES = {"raster_fwd": "raster_fwd.hip", "raster_bwd": "raster_bwd.hip",
+                  "raster_fit": "raster_fit.hip"}
+# headers whose device code the raster kernels inline
+KERNEL_HEADERS = ("raster_tile.hpp", "raster_common.hpp")
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- "
              "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0 --no-ssim --no-decode "
@@ -272,8 +275,10 @@ VALU_FILE = os.path.join(PROFILES, "valu_counters_raster_texture-2048x2048-n9-N1
 
 def kernel_source_hash(kernel):
     import hashlib
-    path = os.path.join(ROOT, "paper_2407_01866_amd", "csrc", KERNEL_SOURCES[kernel])
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in (KERNEL_SOURCES[kernel],) + KERNEL_HEADERS:
+        h.update(open(os.path.join(ROOT, "paper_2407_01866_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def summarize_profiles(out_dir):
@@ -331,7 +336,7 @@ def summarize_profiles(out_dir):
         for k, c in sorted(per.items()):
             a = {n: sum(v) / len(v) for n, v in c.items()}
             cyc = a["GRBM_GUI_ACTIVE"] / 8
-            kern = "raster_fwd" if "raster_fwd" in k else "raster_bwd"
+            kern = next(f for f in KERNEL_SOURCES if f in k)
             out.append(f"kernel {k.replace(' ', '')} family {kern} source_sha256 "
                        f"{kernel_source_hash(kern)} dispatches {len(c['SQ_WAVES'])} "
                        f"valu_insts {a['SQ_INSTS_VALU']:.4g} lds_insts {a['SQ_INSTS_LDS']:.4g} "
@@ -384,7 +389,7 @@ def summarize_profiles(out_dir):
            "# commands: " + PROFILE_CMDS["fetch"], "#           " + PROFILE_CMDS["write"],
            "#           " + PROFILE_CMDS["copy_fetch"], "#           " + PROFILE_CMDS["copy_write"],
            f"copy_calibration fetch_bytes_per_kib {f_factor * 1024:.1f} write_bytes_per_kib {w_factor * 1024:.1f}"]
-    for kern in ("raster_fwd", "raster_bwd"):
+    for kern in KERNEL_SOURCES:
         fk = [v for k, v in fetch.items() if kern in k]
         wk = [v for k, v in write.items() if kern in k]
         if not fk or not wk:
@@ -402,8 +407,9 @@ def measured_valu(kernel, fused=True):
     summary, or None when that summary is missing or was taken from another source."""
     if not os.path.exists(VALU_FILE):
         return None
-    want = "raster_fwd_kernel<10,true,false>" if kernel == "raster_fwd" else \
-        "raster_bwd_kernel<9,10,true>"
+    want = {"raster_fwd": "raster_fwd_kernel<10,true,false>",
+            "raster_bwd": "raster_bwd_kernel<9,10,true>",
+            "raster_fit": "raster_fit_kernel<9,10>"}[kernel]
     for line in open(VALU_FILE):
         f = line.split()
         if len(f) > 2 and f[0] == "kernel" and f[1] == want:
@@ -448,6 +454,54 @@ def timed_fit(fitter, iters, torch):
     if fitter.steps_done() != iters:
         raise RuntimeError("an iteration overflowed the pair buffer during a timed fit")
     return dt
+
+
+def single_pass_step(torch, nat, w, target, params, cap, steps, warmup, ref_fit, e_fwd, e_bwd):
+    """The same fit (same initial state, trajectory and pair capacity) with the single-pass L1
+    kernel in place of the fused forward + adjoint pair: graph-replayed iterations, then the
+    kernels timed with HIP events on eager launches; the parameters after warmup + steps
+    iterations must equal the two-pass fitter's."""
+    from paper_2407_01866_amd.fit import PlainFitter
+    f = PlainFitter(target, params, w.K, pair_capacity=cap, single_pass=True)
+    init = f.snapshot()
+    total = warmup + steps
+    f.capture()
+    for _ in range(warmup):
+        f.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if f.steps_done() != total:
+        raise RuntimeError("an iteration overflowed the pair buffer during the single-pass run")
+    same = bool(torch.equal(f.fit, ref_fit))
+    f.restore(init)
+    for _ in range(warmup):
+        f.step_async()
+    torch.cuda.synchronize()
+    nat.igs_timing_read(reset=True)
+    nat.igs_timing_enable(True)
+    torch.cuda._sleep(int(2.4e9 * 0.2))
+    for _ in range(steps):
+        f.step_async()
+    torch.cuda.synchronize()
+    ph = nat.igs_timing_read(reset=True)
+    nat.igs_timing_enable(False)
+    avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in ph.items()}
+    ops = fwd_valu_ops(e_fwd, w.H * w.W, w.n, True) + bwd_valu_ops(e_bwd, w.n)
+    ach = ops / (avg["raster_fit"] * 1e-3)
+    ms = dt / steps * 1e3
+    return {"ms_per_step": round(ms, 4), "fit_iters_per_s": round(1e3 / ms, 2),
+            "identical_to_two_pass": same,
+            "phase_ms": {k: round(v, 4) for k, v in avg.items() if v > 0},
+            "roofline": {"bound": "alu", "kernel": "raster_fit", "avg_ms": round(avg["raster_fit"], 4),
+                         "achieved": round(ach / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
+                         "unit": "Tlane-op/s", "frac": round(ach / PEAK_LANE_OPS, 4),
+                         "traffic": measured_traffic("raster_fit"),
+                         "valu_counters": measured_valu("raster_fit"),
+                         "work_per_launch": f"{ops:.4g} VALU lane-ops"}}
 
 
 def batched_vs_plain(torch, dev, iters, count=64):
@@ -504,6 +558,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--no-ssim", action="store_true",
                     help="skip the L1 + SSIM loss measurement")
+    ap.add_argument("--no-single-pass", action="store_true",
+                    help="skip the single-pass L1 fitting kernel's run")
     ap.add_argument("--no-decode", action="store_true",
                     help="skip the random-access decoding measurement")
     ap.add_argument("--ssim-profile", action="store_true",
@@ -636,6 +692,11 @@ def main():
                     "traffic": measured_traffic(other), "valu_counters": measured_valu(other),
                     "avg_ms": round(avg[other], 4),
                     "work_per_launch": f"{ops[other]:.4g} VALU lane-ops"}
+    single = None
+    if not args.no_single_pass:
+        log("[bench] single-pass L1 fitting kernel (same trajectory)")
+        single = single_pass_step(torch, nat, w, target, params, fitter.r.cap, args.steps,
+                                  args.warmup, fitter.fit, e_fwd, e_bwd)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -672,7 +733,7 @@ def main():
         "launch_config": {"persistent": tuned[0], "wgs_per_cu": tuned[1], "fwd_cull": tuned[2],
                           "autotune_ms": {str(c): round(t * 1e3, 4) for c, t in tune_times.items()}},
         "roofline": roofline, "roofline_adjoint": roofline_bwd,
-        "cpu_baseline": cpu, "ssim_step": ssim, "decode": decode, "paper_context": ctx,
+        "single_pass": single, "cpu_baseline": cpu, "ssim_step": ssim, "decode": decode, "paper_context": ctx,
         "batched_vs_plain": batch,
     }
     print(json.dumps(out), flush=True)

@@ -167,6 +167,29 @@ igs_status igs_render_backward_l1(const float *params, int32_t N, int32_t n, int
                                   void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * One fitting evaluation of the L1 loss in a single rasterization pass (Sec. 3.2 Eq. 5, Sec. 3.3,
+ * loss of Sec. 4.1): binning as igs_render, then one kernel in which each tile's workgroup
+ * renders the tile, compares it with the target and runs the adjoint of that comparison, keeping
+ * every per-pixel quantity on chip.  The loss and the gradient are bit for bit those of
+ * igs_render_l1 followed by igs_render_backward_l1; no image is produced.
+ *   target       [n][H][W] float32
+ *   loss_out     device double[2]: mean |image - target|, mean (image - target)^2
+ *   grad_params  [5+n][N] float32 output, overwritten: dL/dparams of the mean absolute error
+ *   saved        required, saved_bytes as igs_render's: receives the binning state and the status
+ *                block (on pair-capacity overflow the loss is that of an all-zero image and
+ *                grad_params is zero, as in the two-pass path)
+ *   workspace / sizes: as igs_render (igs_render_buffer_sizes covers this call)
+ * n must be <= 16.
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_UNSUPPORTED (n > 16 or tile size), IGS_ERR_WORKSPACE,
+ *         IGS_ERR_HIP.
+ */
+igs_status igs_render_l1_grad(const float *params, int32_t N, int32_t n, int32_t H, int32_t W,
+                              int32_t K, int32_t tile_h, int32_t tile_w, int64_t pair_capacity,
+                              const float *target, double *loss_out, float *grad_params,
+                              void *saved, size_t saved_bytes, void *workspace, size_t ws_bytes,
+                              void *stream);
+
+/*
  * Binning alone (Sec. 3.2): the footprint bound, pair emission, sort and tile ranges of
  * igs_render, written into `saved` without rasterizing, for decoders that answer point queries
  * (igs_query).  Arguments, sizes, status block and errors as igs_render (image not needed).
@@ -403,6 +426,15 @@ igs_status igs_render_backward_l1_batched(const float *params, const igs_image_d
                                           size_t saved_bytes, float *grad_params, void *workspace,
                                           size_t ws_bytes, void *stream);
 
+/* igs_render_l1_grad for a batch: per-image loss and gradient normalization as
+   igs_render_l1_batched; tiles are taken largest hit set first.  n <= 16. */
+igs_status igs_render_l1_grad_batched(const float *params, const igs_image_desc *descs_host,
+                                      const igs_image_desc *descs_dev, int32_t B, int32_t n,
+                                      int32_t K, int64_t pair_capacity, const float *targets,
+                                      double *loss_out, float *grad_params, void *saved,
+                                      size_t saved_bytes, void *workspace, size_t ws_bytes,
+                                      void *stream);
+
 /* L1 term per image (each normalized by its own n*H*W); loss_out is device double[B][2]
    (mean |d|, mean d^2 per image).  Deterministic.  Errors: as igs_l1_loss_grad. */
 igs_status igs_l1_batched_workspace_size(const igs_image_desc *descs, int32_t B, int32_t n,
@@ -475,7 +507,8 @@ igs_status igs_get_launch_config(igs_launch_config *cfg);
  * and tile ranges), IGS_PHASE_RASTER_FWD (the forward raster kernel, with the fused L1 epilogue
  * when called through igs_render_l1), IGS_PHASE_RASTER_BWD (the adjoint raster kernel),
  * IGS_PHASE_GRAD_REDUCE (the adjoint's per-Gaussian reduction), IGS_PHASE_LOSS (the loss
- * kernels, or the fused forward's final loss reduction), IGS_PHASE_ADAM.  At most 65536 event
+ * kernels, or the fused forward's final loss reduction), IGS_PHASE_ADAM, IGS_PHASE_RASTER_FIT (the
+ * single-pass kernel of igs_render_l1_grad).  At most 65536 event
  * pairs are kept between reads; further phases go untimed.  Not thread-safe; do not enable during
  * graph capture.
  */
@@ -485,7 +518,8 @@ igs_status igs_get_launch_config(igs_launch_config *cfg);
 #define IGS_PHASE_LOSS 3
 #define IGS_PHASE_ADAM 4
 #define IGS_PHASE_GRAD_REDUCE 5
-#define IGS_NUM_PHASES 6
+#define IGS_PHASE_RASTER_FIT 6
+#define IGS_NUM_PHASES 7
 igs_status igs_timing_enable(int32_t on);
 igs_status igs_timing_read(double ms_out[IGS_NUM_PHASES], int64_t calls_out[IGS_NUM_PHASES],
                            int32_t reset);

@@ -39,9 +39,10 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_init_gaussians", "igs_add_gaussians", "igs_bin", "igs_query",
             "igs_query_workspace_size", "igs_l1_ssim_batched_workspace_size",
             "igs_l1_ssim_loss_grad_batched",
-            "igs_params_to_fp16", "igs_decode_fp16")
+            "igs_params_to_fp16", "igs_decode_fp16", "igs_render_l1_grad",
+            "igs_render_l1_grad_batched")
 
-PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce")
+PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce", "raster_fit")
 
 
 class ImageDesc(ctypes.Structure):
@@ -171,6 +172,12 @@ def lib() -> ctypes.CDLL:
     L.igs_render_backward_l1_batched.argtypes = [vp, dp, vp, i32, i32, i32, i64, vp, sz, vp, vp,
                                                  sz, vp]
     L.igs_render_backward_l1_batched.restype = i32
+    L.igs_render_l1_grad.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, vp, vp, vp,
+                                     sz, vp, sz, vp]
+    L.igs_render_l1_grad.restype = i32
+    L.igs_render_l1_grad_batched.argtypes = [vp, dp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz,
+                                             vp, sz, vp]
+    L.igs_render_l1_grad_batched.restype = i32
     L.igs_set_launch_config.argtypes = [ctypes.POINTER(LaunchConfig)]
     L.igs_set_launch_config.restype = i32
     L.igs_get_launch_config.argtypes = [ctypes.POINTER(LaunchConfig)]
@@ -278,6 +285,16 @@ def igs_render_backward_l1(params, N, n, H, W, K, tile_h, tile_w, pair_capacity,
         _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, pair_capacity,
         _ptr(saved), saved_bytes, _f32(grad_params, "grad_params") if N > 0 else None,
         _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_render_l1_grad(params, N, n, H, W, K, tile_h, tile_w, pair_capacity, target, loss_out,
+                       grad_params, saved, saved_bytes, workspace, ws_bytes, stream=None) -> None:
+    if loss_out.dtype != torch.float64:
+        raise TypeError("loss_out must be float64[2]")
+    _check("igs_render_l1_grad", lib().igs_render_l1_grad(
+        _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, pair_capacity,
+        _f32(target, "target"), _ptr(loss_out), _f32(grad_params, "grad_params") if N > 0 else None,
+        _ptr(saved), saved_bytes, _ptr(workspace), ws_bytes, _stream(stream)))
 
 
 def igs_l1_workspace_size(count: int) -> int:
@@ -489,6 +506,18 @@ def igs_render_backward_l1_batched(params, descs, d_descs, n, K, pair_capacity, 
         K, pair_capacity, _ptr(saved), saved_bytes,
         _f32(grad_params, "grad_params") if grad_params.numel() else None, _ptr(workspace),
         ws_bytes, _stream(stream)))
+
+
+def igs_render_l1_grad_batched(params, descs, d_descs, n, K, pair_capacity, targets, loss_out,
+                               grad_params, saved, saved_bytes, workspace, ws_bytes,
+                               stream=None) -> None:
+    if loss_out.dtype != torch.float64:
+        raise TypeError("loss_out must be float64[B][2]")
+    _check("igs_render_l1_grad_batched", lib().igs_render_l1_grad_batched(
+        _f32(params, "params") if params.numel() else None, descs, _ptr(d_descs), len(descs), n,
+        K, pair_capacity, _f32(targets, "targets"), _ptr(loss_out),
+        _f32(grad_params, "grad_params") if grad_params.numel() else None, _ptr(saved),
+        saved_bytes, _ptr(workspace), ws_bytes, _stream(stream)))
 
 
 def igs_l1_batched_workspace_size(descs, n) -> int:

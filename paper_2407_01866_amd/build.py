@@ -20,17 +20,19 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["binning.hip", "scan.hip", "radix_sort.hip", "raster_fwd.hip", "raster_bwd.hip",
-           "loss_adam.hip", "ssim.hip", "place.hip", "query.hip", "timing.cpp", "api.cpp"]
+           "raster_fit.hip", "loss_adam.hip", "ssim.hip", "place.hip", "query.hip", "timing.cpp",
+           "api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-fvisibility=hidden",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
 
 
-# Per-file extra flags.  The forward rasterizer and the point queries rank candidates with FP64
-# min/max on packed keys that are never NaN; -fno-honor-nans stops the compiler from quieting
-# their inputs.
-EXTRA = {"raster_fwd.hip": ["-fno-honor-nans"], "query.hip": ["-fno-honor-nans"]}
+# Per-file extra flags.  The forward rasterizer, the single-pass fitting kernel and the point
+# queries rank candidates with FP64 min/max on packed keys that are never NaN; -fno-honor-nans
+# stops the compiler from quieting their inputs.
+EXTRA = {"raster_fwd.hip": ["-fno-honor-nans"], "raster_fit.hip": ["-fno-honor-nans"],
+         "query.hip": ["-fno-honor-nans"]}
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -350,6 +350,41 @@ igs_status backward_impl(const float *params, const Dims &d, const Images &imgs,
   return IGS_OK;
 }
 
+// Single-pass L1 evaluation: binning as render_impl, then the fitting kernel (loss sums and
+// per-pair records), the loss reduction and the adjoint's per-Gaussian reduction.
+igs_status fit_l1_impl(const float *params, const Dims &d, const Images &imgs, bool batched,
+                       const float *target, double *loss_out, float *grad_params, void *saved,
+                       size_t saved_bytes, void *workspace, size_t ws_bytes, hipStream_t s) {
+  igs_status st = render_impl(params, d, imgs, batched, nullptr, saved, saved_bytes, workspace,
+                              ws_bytes, s, nullptr, nullptr, false);
+  if (st != IGS_OK) return st;
+  const SavedLayout SL = saved_layout(d);
+  const WsLayout WL = ws_layout(d);
+  const int2 *ranges = at<int2>(saved, SL.ranges);
+  const int *order = at<int>(saved, SL.order);
+  const uint32_t *vals = at<uint32_t>(saved, SL.vals);
+  const uint32_t *src = at<uint32_t>(saved, SL.src);
+  const float4 *g32a = at<float4>(saved, SL.g32a);
+  const float2 *g32b = at<float2>(saved, SL.g32b);
+  const double4 *g64 = at<double4>(saved, SL.g64);
+  double2 *l1_part = at<double2>(workspace, WL.l1_part);
+  float *part = at<float>(workspace, WL.part);
+  {
+    PhaseTimer timer(kPhaseRasterFit, s);
+    IGS_HIP(launch_raster_fit(ranges, vals, src, g32a, g32b, g64, params, d, imgs,
+                              batched ? order : nullptr, target, l1_part, part, s));
+  }
+  {
+    PhaseTimer timer(kPhaseLoss, s);
+    IGS_HIP(launch_l1_tiles_final(l1_part, imgs, d.n, loss_out, s));
+  }
+  PhaseTimer timer(kPhaseGradReduce, s);
+  IGS_HIP(launch_grad_reduce(params, g32a, g32b, at<uint32_t>(saved, SL.counts),
+                             at<int64_t>(saved, SL.offsets), at<int64_t>(saved, SL.status), part,
+                             d.N, d.n, grad_params, s));
+  return IGS_OK;
+}
+
 Images single_view(int H, int W, int N) {
   Images v{};
   v.one = single_image(H, W, N);
@@ -511,6 +546,22 @@ IGS_API igs_status igs_render_backward_l1(const float *params, int32_t N, int32_
                        ws_bytes, static_cast<hipStream_t>(stream), true);
 }
 
+IGS_API igs_status igs_render_l1_grad(const float *params, int32_t N, int32_t n, int32_t H,
+                                      int32_t W, int32_t K, int32_t tile_h, int32_t tile_w,
+                                      int64_t pair_capacity, const float *target,
+                                      double *loss_out, float *grad_params, void *saved,
+                                      size_t saved_bytes, void *workspace, size_t ws_bytes,
+                                      void *stream) {
+  igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
+  if (st != IGS_OK) return st;
+  if (n > kMaxFusedChannels) return IGS_ERR_UNSUPPORTED;
+  if ((N > 0 && (!params || !grad_params)) || !target || !loss_out || !saved || !workspace)
+    return IGS_ERR_INVALID_ARG;
+  return fit_l1_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N), false,
+                     target, loss_out, grad_params, saved, saved_bytes, workspace, ws_bytes,
+                     static_cast<hipStream_t>(stream));
+}
+
 // ------------------------------------------------------------------------------ batches
 
 IGS_API igs_status igs_batch_describe(int32_t B, int32_t n, const int32_t *H, const int32_t *W,
@@ -644,6 +695,25 @@ IGS_API igs_status igs_render_backward_l1_batched(const float *params,
   return backward_impl(params, d, batch_view(descs_dev, B), true, nullptr, nullptr, saved,
                        saved_bytes, grad_params, workspace, ws_bytes,
                        static_cast<hipStream_t>(stream), true);
+}
+
+IGS_API igs_status igs_render_l1_grad_batched(const float *params,
+                                              const igs_image_desc *descs_host,
+                                              const igs_image_desc *descs_dev, int32_t B,
+                                              int32_t n, int32_t K, int64_t pair_capacity,
+                                              const float *targets, double *loss_out,
+                                              float *grad_params, void *saved, size_t saved_bytes,
+                                              void *workspace, size_t ws_bytes, void *stream) {
+  igs_status st = check_batch(descs_host, B, n, K, pair_capacity);
+  if (st != IGS_OK) return st;
+  if (n > kMaxFusedChannels) return IGS_ERR_UNSUPPORTED;
+  const Dims d =
+      make_batch_dims(reinterpret_cast<const ImageDesc *>(descs_host), B, n, K, pair_capacity);
+  if ((d.N > 0 && (!params || !grad_params)) || !descs_dev || !targets || !loss_out || !saved ||
+      !workspace)
+    return IGS_ERR_INVALID_ARG;
+  return fit_l1_impl(params, d, batch_view(descs_dev, B), true, targets, loss_out, grad_params,
+                     saved, saved_bytes, workspace, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 IGS_API igs_status igs_l1_workspace_size(int64_t count, size_t *ws_bytes) {

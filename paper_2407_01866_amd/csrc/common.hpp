@@ -218,6 +218,15 @@ hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const flo
                               const int64_t *status, const float *part, int N, int n,
                               float *grad_params, hipStream_t s);
 
+// raster_fit.hip: render, L1 comparison and adjoint of every tile in one pass; writes the tile loss
+// sums (as the fused forward) and the adjoint's per-pair records (as launch_raster_bwd), nothing
+// per pixel.
+hipError_t launch_raster_fit(const int2 *ranges, const uint32_t *vals, const uint32_t *src,
+                             const float4 *g32a, const float2 *g32b, const double4 *g64,
+                             const float *params, const Dims &d, const Images &imgs,
+                             const int *tile_order, const float *target, double2 *loss_part,
+                             float *part, hipStream_t s);
+
 // loss_adam.hip
 // SSIM strips of one channel plane of an H x W image in the batched stencils (32 x 128 each).
 inline int64_t ssim_strips(int H, int W) { return (int64_t)((W + 31) / 32) * ((H + 127) / 128); }

@@ -24,73 +24,10 @@
 // reproducible bit for bit.
 // The blend weights are recomputed from the saved per-pixel shift and 1/Z with the forward's
 // exact double-precision expression.
-#include "raster_common.hpp"
+#include "raster_tile.hpp"
 
 namespace igs {
 namespace {
-
-// Per-Gaussian item counters are split into kSub sub-counters, (wave, lane & 3): each is touched
-// by one wave only, so the ranks it hands out follow the program and lane order (no dependence on
-// how waves interleave) and the order of items in a run, hence every float sum, is reproducible;
-// the lane split spreads same-address LDS atomics.
-constexpr int kSub = 16;
-__device__ __forceinline__ int item_sub(int tid) { return ((tid >> 6) << 2) | (tid & 3); }
-
-// Exclusive scan of v over the 256 threads of the block; returns the block total in *total.
-__device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int o = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += o;
-  }
-  if (lane == 63) s_wave[w] = inc;
-  __syncthreads();
-  int off = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < kRasterThreads / 64; ++k) {
-    const int t = s_wave[k];
-    off += k < w ? t : 0;
-    tot += t;
-  }
-  *total = tot;
-  return off + inc - v;
-}
-
-// LDS layout (byte offsets).  The per-chunk sums (written after the items are placed) reuse the
-// space of the per-Gaussian counters (dead by then).
-struct BwdLds {
-  unsigned px, part, off, cho, owner, gid, wave, item, total;
-};
-
-template <int NC, int KT>
-__host__ __device__ constexpr BwdLds bwd_lds() {
-  constexpr unsigned ROW = (NC + 3 + 3) & ~3;
-  constexpr unsigned NACC = 5 + NC;
-  constexpr unsigned cnt_bytes = 4 * (kBatch * kSub + kRasterThreads);  // + one dummy per lane
-  constexpr unsigned part_bytes = 4 * kRasterThreads * NACC;
-  BwdLds L{};
-  unsigned o = 0;
-  L.px = o;
-  o += 4 * kRasterThreads * ROW;
-  L.part = o;
-  o += part_bytes > cnt_bytes ? part_bytes : cnt_bytes;
-  L.off = o;
-  o += 4 * (kBatch + 4);
-  L.cho = o;
-  o += 4 * (kBatch + 4);
-  L.owner = o;
-  o += 2 * kRasterThreads;
-  L.gid = o;
-  o += 4 * kBatch;
-  L.wave = o;
-  o += 32;
-  L.item = o;
-  o += 2 * kRasterThreads * KT;
-  L.total = (o + 15) & ~15u;
-  return L;
-}
 
 // Register budget: four waves per SIMD (<= 128 VGPRs) where that fits without spilling.
 __host__ __device__ constexpr int bwd_min_waves(int nc, int kt) { return nc + kt <= 25 ? 4 : 2; }
@@ -108,19 +45,8 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
     const float *__restrict__ grad_image_all, const float2 *__restrict__ l1_rec,
     const uint16_t *__restrict__ slots_all, const float2 *__restrict__ aux_all,
     float *__restrict__ part, TileQueue queue) {
-  constexpr int ROW = (NC + 3 + 3) & ~3;  // g[0..NC), g.c_r, shift, 1/Z, padding
-  constexpr int NACC = 5 + NC;
-  constexpr BwdLds L = bwd_lds<NC, KT>();
+  constexpr int ROW = px_row<NC>();  // g[0..NC), g.c_r, shift, 1/Z, padding
   extern __shared__ __align__(16) unsigned char smem[];
-  float *s_px = reinterpret_cast<float *>(smem + L.px);            // [256 px][ROW]
-  int *s_cnt8 = reinterpret_cast<int *>(smem + L.part);            // [kBatch][kSub] + dummies
-  float *s_part = reinterpret_cast<float *>(smem + L.part);        // [256 chunks][NACC]
-  int *s_off = reinterpret_cast<int *>(smem + L.off);              // [kBatch + 1] run starts
-  int *s_cho = reinterpret_cast<int *>(smem + L.cho);              // [kBatch + 1] chunk starts
-  uint16_t *s_owner = reinterpret_cast<uint16_t *>(smem + L.owner);  // [256] chunk -> j
-  uint32_t *s_gid = reinterpret_cast<uint32_t *>(smem + L.gid);    // [kBatch] j -> Gaussian
-  int *s_wave = reinterpret_cast<int *>(smem + L.wave);
-  uint16_t *s_item = reinterpret_cast<uint16_t *>(smem + L.item);  // [256 * KT] px | j << 8
 
   const int tid = threadIdx.x;
   int idx = 0;
@@ -180,180 +106,11 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
     row[NC + 2] = ax.y;
 #pragma unroll
     for (int r = NC + 3; r < ROW; ++r) row[r] = 0.f;
-#pragma unroll
-    for (int r = 0; r < ROW; r += 4)
-      *reinterpret_cast<float4 *>(&s_px[tid * ROW + r]) =
-          make_float4(row[r], row[r + 1], row[r + 2], row[r + 3]);
+    store_px_row<NC>(smem, row);
   }
 
-  const int sub = item_sub(tid);
-  for (int base = 0; base < cnt; base += kBatch) {
-    const int nb = min(kBatch, cnt - base);
-    if (base > 0) __syncthreads();  // previous batch fully consumed
-    uint32_t my_src = 0;  // emit index of the batch's Gaussian tid
-    if (tid < nb) {
-      s_gid[tid] = vals[start + base + tid];
-      my_src = src[start + base + tid];
-    }
-#pragma unroll
-    for (int c = 0; c < kSub; ++c) s_cnt8[tid * kSub + c] = 0;
-    __syncthreads();
-
-    // 1a: rank of each item inside its (Gaussian, lane & 7) sub-run; items outside the batch
-    // count on a private dummy counter so the atomics need no branches
-    uint32_t e[KT];
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      const int j = sl[k] - base;
-      const bool ok = (unsigned)j < (unsigned)nb;
-      const int a = ok ? j * kSub + sub : kBatch * kSub + tid;
-      const int r = atomicAdd(&s_cnt8[a], 1);
-      e[k] = ok ? (uint32_t)(j | (r << 8)) : 0xFFFFFFFFu;
-    }
-    __syncthreads();
-
-    // Gaussian tid: its run length; one packed scan gives run starts and the number of
-    // Gaussians with items (a Gaussian occurs at most once per pixel, so runs are <= 256)
-    int c8[kSub];
-    int my_cnt = 0;
-#pragma unroll
-    for (int c = 0; c < kSub; ++c) {
-      c8[c] = s_cnt8[tid * kSub + c];
-      my_cnt += c8[c];
-    }
-    int packed_total;
-    const int packed_off =
-        block_exclusive_scan(my_cnt | ((my_cnt > 0 ? 1 : 0) << 16), s_wave, &packed_total);
-    const int my_off = packed_off & 0xFFFF;
-    const int total_items = packed_total & 0xFFFF;
-    const int busy = packed_total >> 16;
-    // chunk length: sum_j ceil(cnt_j / R) <= total / R + busy <= 256
-    const int R = busy < kRasterThreads
-                      ? max(1, (total_items + (kRasterThreads - busy) - 1) / (kRasterThreads - busy))
-                      : kRasterThreads;
-    const int my_ch = (my_cnt + R - 1) / R;
-    int total_chunks;
-    __syncthreads();  // s_wave reused
-    const int my_cho = block_exclusive_scan(my_ch, s_wave, &total_chunks);
-    {
-      int o = my_off;
-#pragma unroll
-      for (int c = 0; c < kSub; ++c) {
-        s_cnt8[tid * kSub + c] = o;
-        o += c8[c];
-      }
-    }
-    s_off[tid] = my_off;
-    s_cho[tid] = my_cho;
-    for (int c = 0; c < my_ch; ++c) s_owner[my_cho + c] = (uint16_t)tid;
-    if (tid == 0) {
-      s_off[kBatch] = total_items;
-      s_cho[kBatch] = total_chunks;
-    }
-    __syncthreads();
-
-    // the lane's chunk: fetch its Gaussian now so the loads overlap the placement below
-    const bool has = tid < total_chunks;
-    const int j = has ? (int)s_owner[tid] : 0;
-    const uint32_t gid = s_gid[j];
-    float2 mu = make_float2(0.f, 0.f);
-    double4 c64 = make_double4(0.0, 0.0, 0.0, 0.0);
-    float cj[NC];
-#pragma unroll
-    for (int ch = 0; ch < NC; ++ch) cj[ch] = 0.f;
-    if (has) {
-      const float4 a = g32a[gid];
-      mu = make_float2(a.x, a.y);
-      c64 = g64[gid];
-#pragma unroll
-      for (int ch = 0; ch < NC; ++ch)
-        if (ch < n) cj[ch] = params[(size_t)(5 + ch) * N + gid];
-    }
-
-    // 1b: place every item in its Gaussian's run
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      if (e[k] != 0xFFFFFFFFu) {
-        const int jj = e[k] & 0xFF;
-        s_item[s_cnt8[jj * kSub + sub] + (e[k] >> 8)] = (uint16_t)(tid | (jj << 8));
-      }
-    }
-    __syncthreads();
-
-    // 2: chunk tid, one Gaussian, accumulated in registers
-    if (has) {
-      const int first = s_off[j] + (tid - s_cho[j]) * R;
-      const int end = min(first + R, s_off[j + 1]);
-      float G1 = 0.f, G2 = 0.f, G11 = 0.f, G22 = 0.f, G12 = 0.f;
-      float gcol[NC];
-#pragma unroll
-      for (int ch = 0; ch < NC; ++ch) gcol[ch] = 0.f;
-      for (int it = first; it < end; ++it) {
-        const int p = s_item[it] & 0xFF;
-        float rw[ROW];
-#pragma unroll
-        for (int r = 0; r < ROW; r += 4) {
-          const float4 v = *reinterpret_cast<const float4 *>(&s_px[p * ROW + r]);
-          rw[r] = v.x;
-          rw[r + 1] = v.y;
-          rw[r + 2] = v.z;
-          rw[r + 3] = v.w;
-        }
-        const float fx = (float)(x0 + (p & (kTile - 1))) + 0.5f;
-        const float fy = (float)(y0 + (p >> 4)) + 0.5f;
-        double d1, d2;
-        const double q = quad_form64(fx, fy, mu.x, mu.y, c64.x, c64.y, c64.z, c64.w, d1, d2);
-        const float alpha = blend_weight(q, rw[NC + 1]) * rw[NC + 2];
-        const float e1 = (float)d1, e2 = (float)d2;
-        float dot = -rw[NC];
-#pragma unroll
-        for (int ch = 0; ch < NC; ++ch) dot = fmaf(rw[ch], cj[ch], dot);
-        const float gq = -0.5f * alpha * dot;
-        const float g1 = gq * e1, g2 = gq * e2;
-        G1 += g1;
-        G2 += g2;
-        G11 = fmaf(g1, e1, G11);
-        G22 = fmaf(g2, e2, G22);
-        G12 = fmaf(g1, e2, G12);
-#pragma unroll
-        for (int ch = 0; ch < NC; ++ch) gcol[ch] = fmaf(alpha, rw[ch], gcol[ch]);
-      }
-      float *prow = &s_part[tid * NACC];
-      prow[0] = G1;
-      prow[1] = G2;
-      prow[2] = G11;
-      prow[3] = G22;
-      prow[4] = G12;
-#pragma unroll
-      for (int ch = 0; ch < NC; ++ch) prow[5 + ch] = gcol[ch];
-    }
-    __syncthreads();
-
-    // 3: Gaussian tid adds up its chunks and writes the pair's record (zeros when no pixel of
-    // the tile retained it)
-    if (tid < nb) {
-      constexpr int NR = (NACC + 3) & ~3;
-      float acc[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] = 0.f;
-      for (int c = 0; c < my_ch; ++c) {
-#pragma unroll
-        for (int r = 0; r < NACC; ++r) acc[r] += s_part[(my_cho + c) * NACC + r];
-      }
-      const int stride = part_stride(n);
-      float4 *rec = reinterpret_cast<float4 *>(part + (size_t)my_src * stride);
-#pragma unroll
-      for (int q = 0; q < NR / 4; ++q) {
-        if (4 * q < stride) {
-          float v[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (4 * q + e < 5 + n) ? acc[4 * q + e] : 0.f;
-          rec[q] = make_float4(v[0], v[1], v[2], v[3]);
-        }
-      }
-    }
-  }
-  __syncthreads();  // LDS is reused by the next tile
+  adjoint_batches<NC, KT>(smem, start, cnt, x0, y0, sl, vals, src, g32a, g64, params, N, n,
+                          part);
   }
 }
 

@@ -13,80 +13,11 @@
 // depend on the order in which candidates arrive.  This file is built with -fno-honor-nans so the
 // min/max are not wrapped in NaN-quieting instructions; q is clamped below 1e38 before packing so a
 // non-finite value can only rank last.
-//
-// Candidate order and wave-level culling.  Because the keys are unique, any processing order gives
-// the same lists, so each batch is visited in ascending order of a lower bound of q over the tile
-// (16 coarse buckets of a counting sort).  Each wave (16 x 4 pixels) also has, per candidate, a
-// lower bound of the float32 q over its own pixel rectangle, shrunk by a margin that covers float32
-// evaluation error; a candidate whose bound exceeds the largest K-th key of the wave's lanes cannot
-// enter any of their lists and is skipped by the whole wave, and once the bucket floor exceeds it
-// the wave stops.  Winners come early in this order, so most of the tail is skipped.
-#include "raster_common.hpp"
+// Candidate order and wave-level culling are described with rank_tile.
+#include "raster_tile.hpp"
 
 namespace igs {
 namespace {
-
-// Candidates staged in LDS per batch: 192 keeps the kernel's LDS (124 B per candidate for n = 9)
-// small enough for six workgroups per CU, the occupancy its registers allow.
-constexpr int kFwdBatch = 192;
-// LDS bytes before the colour rows: per candidate 48 B of ranking data in visiting order and 40 B
-// of blend geometry in slot order, then the bucket counters.
-constexpr unsigned kFwdLdsFixed = 88 * kFwdBatch + 2 * 16 * 4;
-constexpr int kBuckets = 16;
-constexpr int kWaves = kRasterThreads / 64;  // each wave covers 4 rows of the tile
-
-// Minimum of q over the rectangle [dxa, dxb] x [dya, dyb] of offsets from the mean: 0 if the
-// rectangle holds the mean, else the least of the four edge minima, each the 1-D minimum of the
-// quadratic along the edge (at -p12 dx / p22, resp. -p12 dy / p11) clamped to the edge.  tya, tyb
-// are the unclamped minimizers along the edges x = dxa and x = dxb.  In float32 with the same
-// factored expression as the ranking, so its error is that of the ranking's q; an inexact
-// minimizer changes an edge minimum only in second order.
-__device__ __forceinline__ float rect_min_q(float A, float B, float C, float D, float i11,
-                                            float p12, float tya, float tyb, float dxa, float dxb,
-                                            float dya, float dyb) {
-  if (dxa <= 0.f && dxb >= 0.f && dya <= 0.f && dyb >= 0.f) return 0.f;
-  float best = quad_q32(A, B, C, D, dxa, fminf(fmaxf(tya, dya), dyb));
-  best = fminf(best, quad_q32(A, B, C, D, dxb, fminf(fmaxf(tyb, dya), dyb)));
-  best = fminf(best, quad_q32(A, B, C, D, fminf(fmaxf(-p12 * dya * i11, dxa), dxb), dya));
-  best = fminf(best, quad_q32(A, B, C, D, fminf(fmaxf(-p12 * dyb * i11, dxa), dxb), dyb));
-  return best;
-}
-
-// A lower bound of the float32 q that the ranking evaluates at any pixel centre of the
-// rectangle: the minimum over the rectangle, itself evaluated in float32 (relative error below
-// 16 ulp(1) times the condition number kappa = s_max/s_min, like the ranking's q), shrunk by
-// 64 ulp(1) times kappa.  0 (never skip) when the margin reaches 1 or the input is not finite;
-// capped at 1e37 so that a lane with fewer than K keys (sentinel threshold) never skips.
-__device__ __forceinline__ float safe_lb(float m, float kappa) {
-  const float f = 1.0f - 64.0f * 5.9604644775390625e-8f * kappa;
-  const float v = m * f;
-  if (!(f > 0.f) || !(v >= 0.f)) return 0.f;
-  return fminf(v, 1e37f);
-}
-
-// Bucket of a lower bound: 0 for 0, 1 for (0, 1/4), then one per octave from 1/4 up to >= 2048.
-__device__ __forceinline__ int lb_bucket(float lb) {
-  if (!(lb > 0.f)) return 0;
-  const int e = (int)((__float_as_uint(lb) >> 23) & 0xFF) - 127;  // floor(log2 lb) for normals
-  return 1 + min(max(e + 3, 0), kBuckets - 2);
-}
-// Smallest value any bound in bucket b can have.
-__device__ __forceinline__ float bucket_floor(int b) {
-  return b <= 1 ? 0.f : __uint_as_float((uint32_t)(127 + b - 4) << 23);  // 2^(b-4)
-}
-
-// Maximum over the 64 lanes of a wave, with DPP row shifts and row broadcasts (no LDS); every
-// lane of a row sees the partial maxima of lower lanes, lane 63 the total, which is returned to
-// all lanes as a scalar.
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false));  // shr 1
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false));  // shr 2
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));  // shr 4
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));  // shr 8
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // bcast 15
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // bcast 31
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
 
 // Fused L1 epilogue (L1 = true): besides the image, each pixel compares its colour with the
 // target, d = c_r - c_t per channel (in double, exact), and keeps what the adjoint of the mean
@@ -139,16 +70,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
     uint16_t *__restrict__ slots_all, float2 *__restrict__ aux_all, L1Out l1, TileQueue queue,
     int cull) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // ranking data in visiting order (position m of the batch's candidate order)
-  float4 *s_pgeo = reinterpret_cast<float4 *>(smem);                  // mu_x, mu_y, A, B
-  float4 *s_pcd = reinterpret_cast<float4 *>(smem + 16 * kFwdBatch);     // C, D, slot, bucket floor
-  float *s_plbw = reinterpret_cast<float *>(smem + 32 * kFwdBatch);      // [kWaves][kFwdBatch] bounds
-  // blend data in slot order (position j in S_j minus the batch base)
-  float2 *s_mu = reinterpret_cast<float2 *>(smem + 48 * kFwdBatch);      // mu_x, mu_y
-  double *s64 = reinterpret_cast<double *>(smem + 56 * kFwdBatch);       // [kFwdBatch][4] A,B,C,D
-  int *s_bcnt = reinterpret_cast<int *>(smem + 88 * kFwdBatch);          // [kBuckets] counters
-  int *s_bstart = s_bcnt + kBuckets;                                  // [kBuckets] starts
-  float *s_col = reinterpret_cast<float *>(smem + kFwdLdsFixed);      // [kFwdBatch][n]
+  const FwdLds S = fwd_lds(smem);
   const int ncp = n;
 
   const int tid = threadIdx.x;
@@ -174,103 +96,8 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
   const bool single = cnt <= kFwdBatch;  // whole S_j stays resident for the blend
 
   double tk[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) tk[k] = kKeyEmpty;
-
-  const int wave = tid >> 6;
-  if (tid < kBuckets) s_bcnt[tid] = 0;
-  for (int base = 0; base < cnt; base += kFwdBatch) {
-    const int nb = min(kFwdBatch, cnt - base);
-    __syncthreads();
-    int bucket = 0, brank = 0;
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    float2 b = make_float2(0.f, 0.f);
-    float lbw[kWaves];
-    if (tid < nb) {
-      const uint32_t gid = vals[start + base + tid];
-      a = g32a[gid];
-      b = g32b[gid];
-      if (single) {
-        s_mu[tid] = make_float2(a.x, a.y);
-        const double4 c = g64[gid];
-        s64[4 * tid + 0] = c.x;
-        s64[4 * tid + 1] = c.y;
-        s64[4 * tid + 2] = c.z;
-        s64[4 * tid + 3] = c.w;
-        for (int ch = 0; ch < n; ++ch) s_col[tid * ncp + ch] = params[(size_t)(5 + ch) * N + gid];
-      }
-      // lower bounds of q over each wave's pixel-centre rectangle (16 x 4 centres); without
-      // culling every bound is 0 (nothing is skipped) and the order is the slot order
-      float tile_lb = 0.f;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) lbw[w] = 0.f;
-      if (cull) {
-      const float A = a.z, B = a.w, C = b.x, D = b.y;
-      const float p11 = fmaf(A, A, C * C), p12 = fmaf(A, B, C * D), p22 = fmaf(B, B, D * D);
-      const float r1 = fmaf(A, A, B * B), r2 = fmaf(C, C, D * D);  // 1/s_1^2, 1/s_2^2
-      const float kappa = sqrtf(fmaxf(r1, r2) / fminf(r1, r2)) * 1.001f;
-      const float i11 = 1.0f / p11, i22 = 1.0f / p22;
-      const float dxa = ((float)(tx * kTile) + 0.5f) - a.x;
-      const float dxb = ((float)(tx * kTile + kTile - 1) + 0.5f) - a.x;
-      const float tya = -p12 * dxa * i22, tyb = -p12 * dxb * i22;
-      tile_lb = 3.0e38f;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        const float dya = ((float)(ty * kTile + 4 * w) + 0.5f) - a.y;
-        const float dyb = ((float)(ty * kTile + 4 * w + 3) + 0.5f) - a.y;
-        lbw[w] = safe_lb(rect_min_q(A, B, C, D, i11, p12, tya, tyb, dxa, dxb, dya, dyb), kappa);
-        tile_lb = fminf(tile_lb, lbw[w]);
-      }
-      }
-      bucket = lb_bucket(tile_lb);
-      brank = atomicAdd(&s_bcnt[bucket], 1);
-    }
-    __syncthreads();
-    if (tid < 64) {  // bucket starts: exclusive scan of the counters (one wave)
-      const int c = tid < kBuckets ? s_bcnt[tid] : 0;
-      int inc = c;
-#pragma unroll
-      for (int d = 1; d < kBuckets; d <<= 1) {
-        const int o = __shfl_up(inc, d, 64);
-        if (tid >= d) inc += o;
-      }
-      if (tid < kBuckets) s_bstart[tid] = inc - c;
-    }
-    __syncthreads();
-    if (tid < nb) {  // scatter the ranking data into visiting order
-      const int pos = s_bstart[bucket] + brank;
-      s_pgeo[pos] = a;
-      s_pcd[pos] = make_float4(b.x, b.y, __int_as_float(base + tid), bucket_floor(bucket));
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) s_plbw[w * kFwdBatch + pos] = lbw[w];
-    }
-    if (tid < kBuckets) s_bcnt[tid] = 0;  // ready for the next batch
-    __syncthreads();
-    // four positions per step; the skip decisions are wave-uniform (scalar branches)
-    for (int m = 0; m < nb; m += 4) {
-      // the largest K-th key of the wave (the lists only shrink, so a stale value is safe)
-      const uint32_t th = wave_max_u32((uint32_t)__double2hiint(tk[KT - 1]));
-      const float q_tau = __uint_as_float(th - kKeyBias);
-      // every later candidate's bound is at least the floor of this position's bucket
-      if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_pcd[m].w))) > q_tau)
-        break;
-      const float4 lb4 = *reinterpret_cast<const float4 *>(&s_plbw[wave * kFwdBatch + m]);
-      const float lbu[4] = {lb4.x, lb4.y, lb4.z, lb4.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (m + u >= nb) break;
-        if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbu[u]))) > q_tau)
-          continue;
-        const float4 g = s_pgeo[m + u];
-        const float4 cd = s_pcd[m + u];
-        const float dx = fx - g.x, dy = fy - g.y;
-        const float e1 = fmaf(g.z, dx, g.w * dy);
-        const float e2 = fmaf(cd.x, dx, cd.y * dy);
-        const double key = rank_key(fmaf(e1, e1, e2 * e2), __float_as_int(cd.z));
-        if (key < tk[KT - 1]) topk_insert<KT>(tk, key);
-      }
-    }
-  }
+  rank_tile<KT>(S, start, cnt, single, tx, ty, fx, fy, vals, g32a, g32b, g64, params, N, n, cull,
+                tk);
 
   double l1_abs = 0.0, l1_sq = 0.0;
   if (inside) {
@@ -280,51 +107,9 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
   float tnext = 0.f;
   if constexpr (L1) tnext = target[0];
   const int keff = min(K, cnt);
-  int ts[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) ts[k] = key_valid(tk[k]) ? key_slot(tk[k]) : -1;
-  float w[KT];
-  int src[KT];
-  float Z = 0.f, shift = 0.f;
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    w[k] = 0.f;
-    src[k] = 0;
-    if (k < keff && ts[k] >= 0) {  // a non-finite q never enters the list
-      const int slot = ts[k];
-      double A, B, C, D;
-      float mx, my;
-      if (single) {
-        A = s64[4 * slot + 0];
-        B = s64[4 * slot + 1];
-        C = s64[4 * slot + 2];
-        D = s64[4 * slot + 3];
-        mx = s_mu[slot].x;
-        my = s_mu[slot].y;
-        src[k] = slot;
-        // keeps these LDS loads and the global loads below in their own branches (merging them
-        // into loads through a pointer that is LDS or global miscompiles for gfx950)
-        asm volatile("" ::: "memory");
-      } else {
-        const uint32_t gid = vals[start + slot];
-        const double4 c = g64[gid];
-        const float4 a = g32a[gid];
-        A = c.x;
-        B = c.y;
-        C = c.z;
-        D = c.w;
-        mx = a.x;
-        my = a.y;
-        src[k] = (int)gid;
-        asm volatile("" ::: "memory");
-      }
-      double e1, e2;
-      const double q = quad_form64(fx, fy, mx, my, A, B, C, D, e1, e2);
-      if (k == 0) shift = (float)q;
-      w[k] = blend_weight(q, shift);
-      Z += w[k];
-    }
-  }
+  int ts[KT], src[KT];
+  float w[KT], Z, shift;
+  winners<KT>(S, single, start, keff, tk, fx, fy, vals, g32a, g64, ts, w, src, Z, shift);
   if constexpr (!P) {
   const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
   const float inv_count = L1 ? (float)(1.0 / ((double)n * (double)HW)) : 0.f;
@@ -352,7 +137,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
       if (k < keff && ts[k] >= 0) {
-        const float c = single ? s_col[src[k] * ncp + ch] : params[(size_t)(5 + ch) * N + src[k]];
+        const float c = single ? S.col[src[k] * ncp + ch] : params[(size_t)(5 + ch) * N + src[k]];
         acc = fmaf(w[k], c, acc);
       }
     }
@@ -407,7 +192,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
     for (int ch = 0; ch < n; ++ch) {
       float acc = 0.f;
 #pragma unroll
-      for (int k = 0; k < KT; ++k) acc = fmaf(w[k], s_col[src[k] * ncp + ch], acc);
+      for (int k = 0; k < KT; ++k) acc = fmaf(w[k], S.col[src[k] * ncp + ch], acc);
       finish(ch, acc);
     }
   } else {
@@ -422,27 +207,9 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
   }
   }
   if (L1) {
-    // the tile's loss sums: wave sums by shuffles, then a fixed order over the four waves
     __shared__ double s_red[2 * kWaves];
-    double a = l1_abs, b = l1_sq;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      a += __shfl_down(a, d, 64);
-      b += __shfl_down(b, d, 64);
-    }
-    if ((tid & 63) == 0) {
-      s_red[2 * wave] = a;
-      s_red[2 * wave + 1] = b;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double2 t = make_double2(0.0, 0.0);
-      for (int k = 0; k < kWaves; ++k) {
-        t.x += s_red[2 * k];
-        t.y += s_red[2 * k + 1];
-      }
-      l1.part[tile] = t;
-    }
+    const double2 t = tile_loss_sums(l1_abs, l1_sq, s_red);
+    if (tid == 0) l1.part[tile] = t;
   }
   __syncthreads();  // LDS is reused by the next tile
   }

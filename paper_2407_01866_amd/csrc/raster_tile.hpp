@@ -1,0 +1,605 @@
+// Per-tile phases of the rasterizers, shared by the forward (raster_fwd.hip), the adjoint
+// (raster_bwd.hip) and the single-pass fitting kernel (raster_fit.hip), which runs the first two
+// on one tile in one workgroup.  Everything here is inlined into its kernel.
+//
+//  * rank_tile: stages the tile's hit set S_j through LDS and leaves every lane with its sorted
+//    top-KT (q, slot) keys (Sec. 3.2); winners: re-evaluates the retained members in double and
+//    returns their blend weights (Eq. 5).
+//  * adjoint_batches: given every pixel's retained slots and its row (dL/dc_r, g . c_r, weight
+//    shift, 1/Z) in LDS, writes one gradient record per (tile, Gaussian) pair (Sec. 3.3).
+#pragma once
+
+#include "raster_common.hpp"
+
+namespace igs {
+
+// ------------------------------------------------------------------------------- forward side
+//
+// Candidate order and wave-level culling.  Because the keys are unique, any processing order gives
+// the same lists, so each batch is visited in ascending order of a lower bound of q over the tile
+// (16 coarse buckets of a counting sort).  Each wave (16 x 4 pixels) also has, per candidate, a
+// lower bound of the float32 q over its own pixel rectangle, shrunk by a margin that covers float32
+// evaluation error; a candidate whose bound exceeds the largest K-th key of the wave's lanes cannot
+// enter any of their lists and is skipped by the whole wave, and once the bucket floor exceeds it
+// the wave stops.  Winners come early in this order, so most of the tail is skipped.
+
+// Candidates staged in LDS per batch: 192 keeps the forward's LDS (124 B per candidate for n = 9)
+// small enough for six workgroups per CU, the occupancy its registers allow.
+constexpr int kFwdBatch = 192;
+// LDS bytes before the colour rows: per candidate 48 B of ranking data in visiting order and 40 B
+// of blend geometry in slot order, then the bucket counters.
+constexpr unsigned kFwdLdsFixed = 88 * kFwdBatch + 2 * 16 * 4;
+constexpr int kBuckets = 16;
+constexpr int kWaves = kRasterThreads / 64;  // each wave covers 4 rows of the tile
+
+__host__ __device__ constexpr size_t fwd_lds_bytes(int n) {
+  return kFwdLdsFixed + (size_t)n * kFwdBatch * sizeof(float);
+}
+
+// Minimum of q over the rectangle [dxa, dxb] x [dya, dyb] of offsets from the mean: 0 if the
+// rectangle holds the mean, else the least of the four edge minima, each the 1-D minimum of the
+// quadratic along the edge (at -p12 dx / p22, resp. -p12 dy / p11) clamped to the edge.  tya, tyb
+// are the unclamped minimizers along the edges x = dxa and x = dxb.  In float32 with the same
+// factored expression as the ranking, so its error is that of the ranking's q; an inexact
+// minimizer changes an edge minimum only in second order.
+__device__ __forceinline__ float rect_min_q(float A, float B, float C, float D, float i11,
+                                            float p12, float tya, float tyb, float dxa, float dxb,
+                                            float dya, float dyb) {
+  if (dxa <= 0.f && dxb >= 0.f && dya <= 0.f && dyb >= 0.f) return 0.f;
+  float best = quad_q32(A, B, C, D, dxa, fminf(fmaxf(tya, dya), dyb));
+  best = fminf(best, quad_q32(A, B, C, D, dxb, fminf(fmaxf(tyb, dya), dyb)));
+  best = fminf(best, quad_q32(A, B, C, D, fminf(fmaxf(-p12 * dya * i11, dxa), dxb), dya));
+  best = fminf(best, quad_q32(A, B, C, D, fminf(fmaxf(-p12 * dyb * i11, dxa), dxb), dyb));
+  return best;
+}
+
+// A lower bound of the float32 q that the ranking evaluates at any pixel centre of the
+// rectangle: the minimum over the rectangle, itself evaluated in float32 (relative error below
+// 16 ulp(1) times the condition number kappa = s_max/s_min, like the ranking's q), shrunk by
+// 64 ulp(1) times kappa.  0 (never skip) when the margin reaches 1 or the input is not finite;
+// capped at 1e37 so that a lane with fewer than K keys (sentinel threshold) never skips.
+__device__ __forceinline__ float safe_lb(float m, float kappa) {
+  const float f = 1.0f - 64.0f * 5.9604644775390625e-8f * kappa;
+  const float v = m * f;
+  if (!(f > 0.f) || !(v >= 0.f)) return 0.f;
+  return fminf(v, 1e37f);
+}
+
+// Bucket of a lower bound: 0 for 0, 1 for (0, 1/4), then one per octave from 1/4 up to >= 2048.
+__device__ __forceinline__ int lb_bucket(float lb) {
+  if (!(lb > 0.f)) return 0;
+  const int e = (int)((__float_as_uint(lb) >> 23) & 0xFF) - 127;  // floor(log2 lb) for normals
+  return 1 + min(max(e + 3, 0), kBuckets - 2);
+}
+// Smallest value any bound in bucket b can have.
+__device__ __forceinline__ float bucket_floor(int b) {
+  return b <= 1 ? 0.f : __uint_as_float((uint32_t)(127 + b - 4) << 23);  // 2^(b-4)
+}
+
+// Maximum over the 64 lanes of a wave, with DPP row shifts and row broadcasts (no LDS); every
+// lane of a row sees the partial maxima of lower lanes, lane 63 the total, which is returned to
+// all lanes as a scalar.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false));  // shr 1
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false));  // shr 2
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));  // shr 4
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));  // shr 8
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // bcast 15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // bcast 31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// The forward's LDS: ranking data in visiting order (position m of the batch's candidate order),
+// blend data in slot order (position j in S_j minus the batch base), bucket counters, colours.
+struct FwdLds {
+  float4 *pgeo;   // mu_x, mu_y, A, B
+  float4 *pcd;    // C, D, slot, bucket floor
+  float *plbw;    // [kWaves][kFwdBatch] bounds
+  float2 *mu;     // mu_x, mu_y
+  double *s64;    // [kFwdBatch][4] A, B, C, D
+  int *bcnt;      // [kBuckets] counters
+  int *bstart;    // [kBuckets] starts
+  float *col;     // [kFwdBatch][n]
+};
+
+__device__ __forceinline__ FwdLds fwd_lds(unsigned char *smem) {
+  FwdLds S;
+  S.pgeo = reinterpret_cast<float4 *>(smem);
+  S.pcd = reinterpret_cast<float4 *>(smem + 16 * kFwdBatch);
+  S.plbw = reinterpret_cast<float *>(smem + 32 * kFwdBatch);
+  S.mu = reinterpret_cast<float2 *>(smem + 48 * kFwdBatch);
+  S.s64 = reinterpret_cast<double *>(smem + 56 * kFwdBatch);
+  S.bcnt = reinterpret_cast<int *>(smem + 88 * kFwdBatch);
+  S.bstart = S.bcnt + kBuckets;
+  S.col = reinterpret_cast<float *>(smem + kFwdLdsFixed);
+  return S;
+}
+
+// Ranks the tile's hit set S_j = vals[start, start + cnt) at the pixel centre (fx, fy) of the
+// calling lane: tk receives the lane's KT smallest keys in ascending order (kKeyEmpty past the
+// last member).  single (cnt <= kFwdBatch): the blend geometry and colours of every member are
+// left in LDS, in slot order, for the blend.  Every thread of the workgroup calls it.
+template <int KT>
+__device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, bool single, int tx,
+                                          int ty, float fx, float fy,
+                                          const uint32_t *__restrict__ vals,
+                                          const float4 *__restrict__ g32a,
+                                          const float2 *__restrict__ g32b,
+                                          const double4 *__restrict__ g64,
+                                          const float *__restrict__ params, int N, int n, int cull,
+                                          double (&tk)[KT]) {
+  const int tid = threadIdx.x;
+  const int ncp = n;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) tk[k] = kKeyEmpty;
+
+  const int wave = tid >> 6;
+  if (tid < kBuckets) S.bcnt[tid] = 0;
+  for (int base = 0; base < cnt; base += kFwdBatch) {
+    const int nb = min(kFwdBatch, cnt - base);
+    __syncthreads();
+    int bucket = 0, brank = 0;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 b = make_float2(0.f, 0.f);
+    float lbw[kWaves];
+    if (tid < nb) {
+      const uint32_t gid = vals[start + base + tid];
+      a = g32a[gid];
+      b = g32b[gid];
+      if (single) {
+        S.mu[tid] = make_float2(a.x, a.y);
+        const double4 c = g64[gid];
+        S.s64[4 * tid + 0] = c.x;
+        S.s64[4 * tid + 1] = c.y;
+        S.s64[4 * tid + 2] = c.z;
+        S.s64[4 * tid + 3] = c.w;
+        for (int ch = 0; ch < n; ++ch) S.col[tid * ncp + ch] = params[(size_t)(5 + ch) * N + gid];
+      }
+      // lower bounds of q over each wave's pixel-centre rectangle (16 x 4 centres); without
+      // culling every bound is 0 (nothing is skipped) and the order is the slot order
+      float tile_lb = 0.f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) lbw[w] = 0.f;
+      if (cull) {
+      const float A = a.z, B = a.w, C = b.x, D = b.y;
+      const float p11 = fmaf(A, A, C * C), p12 = fmaf(A, B, C * D), p22 = fmaf(B, B, D * D);
+      const float r1 = fmaf(A, A, B * B), r2 = fmaf(C, C, D * D);  // 1/s_1^2, 1/s_2^2
+      const float kappa = sqrtf(fmaxf(r1, r2) / fminf(r1, r2)) * 1.001f;
+      const float i11 = 1.0f / p11, i22 = 1.0f / p22;
+      const float dxa = ((float)(tx * kTile) + 0.5f) - a.x;
+      const float dxb = ((float)(tx * kTile + kTile - 1) + 0.5f) - a.x;
+      const float tya = -p12 * dxa * i22, tyb = -p12 * dxb * i22;
+      tile_lb = 3.0e38f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const float dya = ((float)(ty * kTile + 4 * w) + 0.5f) - a.y;
+        const float dyb = ((float)(ty * kTile + 4 * w + 3) + 0.5f) - a.y;
+        lbw[w] = safe_lb(rect_min_q(A, B, C, D, i11, p12, tya, tyb, dxa, dxb, dya, dyb), kappa);
+        tile_lb = fminf(tile_lb, lbw[w]);
+      }
+      }
+      bucket = lb_bucket(tile_lb);
+      brank = atomicAdd(&S.bcnt[bucket], 1);
+    }
+    __syncthreads();
+    if (tid < 64) {  // bucket starts: exclusive scan of the counters (one wave)
+      const int c = tid < kBuckets ? S.bcnt[tid] : 0;
+      int inc = c;
+#pragma unroll
+      for (int d = 1; d < kBuckets; d <<= 1) {
+        const int o = __shfl_up(inc, d, 64);
+        if (tid >= d) inc += o;
+      }
+      if (tid < kBuckets) S.bstart[tid] = inc - c;
+    }
+    __syncthreads();
+    if (tid < nb) {  // scatter the ranking data into visiting order
+      const int pos = S.bstart[bucket] + brank;
+      S.pgeo[pos] = a;
+      S.pcd[pos] = make_float4(b.x, b.y, __int_as_float(base + tid), bucket_floor(bucket));
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) S.plbw[w * kFwdBatch + pos] = lbw[w];
+    }
+    if (tid < kBuckets) S.bcnt[tid] = 0;  // ready for the next batch
+    __syncthreads();
+    // four positions per step; the skip decisions are wave-uniform (scalar branches)
+    for (int m = 0; m < nb; m += 4) {
+      // the largest K-th key of the wave (the lists only shrink, so a stale value is safe)
+      const uint32_t th = wave_max_u32((uint32_t)__double2hiint(tk[KT - 1]));
+      const float q_tau = __uint_as_float(th - kKeyBias);
+      // every later candidate's bound is at least the floor of this position's bucket
+      if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(S.pcd[m].w))) > q_tau)
+        break;
+      const float4 lb4 = *reinterpret_cast<const float4 *>(&S.plbw[wave * kFwdBatch + m]);
+      const float lbu[4] = {lb4.x, lb4.y, lb4.z, lb4.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (m + u >= nb) break;
+        if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbu[u]))) > q_tau)
+          continue;
+        const float4 g = S.pgeo[m + u];
+        const float4 cd = S.pcd[m + u];
+        const float dx = fx - g.x, dy = fy - g.y;
+        const float e1 = fmaf(g.z, dx, g.w * dy);
+        const float e2 = fmaf(cd.x, dx, cd.y * dy);
+        const double key = rank_key(fmaf(e1, e1, e2 * e2), __float_as_int(cd.z));
+        if (key < tk[KT - 1]) topk_insert<KT>(tk, key);
+      }
+    }
+  }
+}
+
+// The retained members of a pixel (its first keff = min(K, |S_j|) keys), re-evaluated in double:
+// ts[k] their slots (-1 when absent), src[k] where their colour is (LDS row when single, else the
+// Gaussian index), w[k] their weights exp(-(q_k - shift)/2) with shift = q of the first, and Z the
+// weights' sum.
+template <int KT>
+__device__ __forceinline__ void winners(const FwdLds &S, bool single, int start, int keff,
+                                        const double (&tk)[KT], float fx, float fy,
+                                        const uint32_t *__restrict__ vals,
+                                        const float4 *__restrict__ g32a,
+                                        const double4 *__restrict__ g64, int (&ts)[KT],
+                                        float (&w)[KT], int (&src)[KT], float &Z, float &shift) {
+#pragma unroll
+  for (int k = 0; k < KT; ++k) ts[k] = key_valid(tk[k]) ? key_slot(tk[k]) : -1;
+  Z = 0.f;
+  shift = 0.f;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    w[k] = 0.f;
+    src[k] = 0;
+    if (k < keff && ts[k] >= 0) {  // a non-finite q never enters the list
+      const int slot = ts[k];
+      double A, B, C, D;
+      float mx, my;
+      if (single) {
+        A = S.s64[4 * slot + 0];
+        B = S.s64[4 * slot + 1];
+        C = S.s64[4 * slot + 2];
+        D = S.s64[4 * slot + 3];
+        mx = S.mu[slot].x;
+        my = S.mu[slot].y;
+        src[k] = slot;
+        // keeps these LDS loads and the global loads below in their own branches (merging them
+        // into loads through a pointer that is LDS or global miscompiles for gfx950)
+        asm volatile("" ::: "memory");
+      } else {
+        const uint32_t gid = vals[start + slot];
+        const double4 c = g64[gid];
+        const float4 a = g32a[gid];
+        A = c.x;
+        B = c.y;
+        C = c.z;
+        D = c.w;
+        mx = a.x;
+        my = a.y;
+        src[k] = (int)gid;
+        asm volatile("" ::: "memory");
+      }
+      double e1, e2;
+      const double q = quad_form64(fx, fy, mx, my, A, B, C, D, e1, e2);
+      if (k == 0) shift = (float)q;
+      w[k] = blend_weight(q, shift);
+      Z += w[k];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------- adjoint side
+//
+// With alpha_i = w_i / Z, c_r = sum alpha_i c_i and g = dL/dc_r at a pixel:
+//   dL/dc_i += alpha_i g
+//   dL/dq_i  = -1/2 alpha_i g.(c_i - c_r)
+// and, with e = (A dx + B dy, C dx + D dy), q = |e|^2, the geometry enters only through five
+// per-Gaussian sums  G1 = sum gq e1, G2 = sum gq e2, G11 = sum gq e1^2, G22 = sum gq e2^2,
+// G12 = sum gq e1 e2  (gq = dL/dq_i at each pixel), which a per-Gaussian pass turns into the
+// parameter gradients.
+//
+// The tile's hit set S_j is processed in batches of 256 positions: the (pixel, retained Gaussian)
+// items of a batch are counting-sorted by Gaussian in LDS (item ranks come from per-wave LDS
+// sub-counters and stay in registers), and each Gaussian's run is cut into chunks of at most R
+// items, R chosen so that the batch has at most 256 chunks.  Lane c accumulates chunk c's 5 + n
+// sums in registers and stores them to its own LDS row; lane j then adds up the rows of Gaussian
+// j (in chunk order) and writes them as one record at the pair's emit index.  No atomics touch
+// floating point, in LDS or in memory, so the records are reproducible bit for bit.
+
+// Per-Gaussian item counters are split into kSub sub-counters, (wave, lane & 3): each is touched
+// by one wave only, so the ranks it hands out follow the program and lane order (no dependence on
+// how waves interleave) and the order of items in a run, hence every float sum, is reproducible;
+// the lane split spreads same-address LDS atomics.
+constexpr int kSub = 16;
+__device__ __forceinline__ int item_sub(int tid) { return ((tid >> 6) << 2) | (tid & 3); }
+
+// Exclusive scan of v over the 256 threads of the block; returns the block total in *total.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kRasterThreads / 64; ++k) {
+    const int t = s_wave[k];
+    off += k < w ? t : 0;
+    tot += t;
+  }
+  *total = tot;
+  return off + inc - v;
+}
+
+// The adjoint's LDS layout (byte offsets).  The per-chunk sums (written after the items are
+// placed) reuse the space of the per-Gaussian counters (dead by then).
+struct BwdLds {
+  unsigned px, part, off, cho, owner, gid, wave, item, total;
+};
+
+// Per-pixel row in LDS: g[0..NC), g.c_r, shift, 1/Z, padding to a multiple of 4 floats.
+template <int NC>
+__host__ __device__ constexpr int px_row() { return (NC + 3 + 3) & ~3; }
+
+template <int NC, int KT>
+__host__ __device__ constexpr BwdLds bwd_lds() {
+  constexpr unsigned ROW = px_row<NC>();
+  constexpr unsigned NACC = 5 + NC;
+  constexpr unsigned cnt_bytes = 4 * (kBatch * kSub + kRasterThreads);  // + one dummy per lane
+  constexpr unsigned part_bytes = 4 * kRasterThreads * NACC;
+  BwdLds L{};
+  unsigned o = 0;
+  L.px = o;
+  o += 4 * kRasterThreads * ROW;
+  L.part = o;
+  o += part_bytes > cnt_bytes ? part_bytes : cnt_bytes;
+  L.off = o;
+  o += 4 * (kBatch + 4);
+  L.cho = o;
+  o += 4 * (kBatch + 4);
+  L.owner = o;
+  o += 2 * kRasterThreads;
+  L.gid = o;
+  o += 4 * kBatch;
+  L.wave = o;
+  o += 32;
+  L.item = o;
+  o += 2 * kRasterThreads * KT;
+  L.total = (o + 15) & ~15u;
+  return L;
+}
+
+// Stores the calling lane's pixel row (the first NC + 3 entries of row; the rest must be 0).
+template <int NC>
+__device__ __forceinline__ void store_px_row(unsigned char *smem, const float (&row)[px_row<NC>()]) {
+  constexpr int ROW = px_row<NC>();
+  float *s_px = reinterpret_cast<float *>(smem);
+#pragma unroll
+  for (int r = 0; r < ROW; r += 4)
+    *reinterpret_cast<float4 *>(&s_px[threadIdx.x * ROW + r]) =
+        make_float4(row[r], row[r + 1], row[r + 2], row[r + 3]);
+}
+
+// The tile's records: sl[k] are the calling lane's retained slots (0xFFFF = none), the pixel
+// rows are in LDS (store_px_row; visible after the first barrier here), S_j = vals[start,
+// start + cnt) with emit indices src[start, start + cnt), and the tile's top-left pixel is
+// (x0, y0).  Every thread of the workgroup calls it; LDS is free again when it returns.
+template <int NC, int KT>
+__device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, int cnt, int x0,
+                                                int y0, const int (&sl)[KT],
+                                                const uint32_t *__restrict__ vals,
+                                                const uint32_t *__restrict__ src,
+                                                const float4 *__restrict__ g32a,
+                                                const double4 *__restrict__ g64,
+                                                const float *__restrict__ params, int N, int n,
+                                                float *__restrict__ part) {
+  constexpr int ROW = px_row<NC>();
+  constexpr int NACC = 5 + NC;
+  constexpr BwdLds L = bwd_lds<NC, KT>();
+  const float *s_px = reinterpret_cast<const float *>(smem + L.px);  // [256 px][ROW]
+  int *s_cnt8 = reinterpret_cast<int *>(smem + L.part);            // [kBatch][kSub] + dummies
+  float *s_part = reinterpret_cast<float *>(smem + L.part);        // [256 chunks][NACC]
+  int *s_off = reinterpret_cast<int *>(smem + L.off);              // [kBatch + 1] run starts
+  int *s_cho = reinterpret_cast<int *>(smem + L.cho);              // [kBatch + 1] chunk starts
+  uint16_t *s_owner = reinterpret_cast<uint16_t *>(smem + L.owner);  // [256] chunk -> j
+  uint32_t *s_gid = reinterpret_cast<uint32_t *>(smem + L.gid);    // [kBatch] j -> Gaussian
+  int *s_wave = reinterpret_cast<int *>(smem + L.wave);
+  uint16_t *s_item = reinterpret_cast<uint16_t *>(smem + L.item);  // [256 * KT] px | j << 8
+
+  const int tid = threadIdx.x;
+  const int sub = item_sub(tid);
+  for (int base = 0; base < cnt; base += kBatch) {
+    const int nb = min(kBatch, cnt - base);
+    if (base > 0) __syncthreads();  // previous batch fully consumed
+    uint32_t my_src = 0;  // emit index of the batch's Gaussian tid
+    if (tid < nb) {
+      s_gid[tid] = vals[start + base + tid];
+      my_src = src[start + base + tid];
+    }
+#pragma unroll
+    for (int c = 0; c < kSub; ++c) s_cnt8[tid * kSub + c] = 0;
+    __syncthreads();
+
+    // 1a: rank of each item inside its (Gaussian, lane & 7) sub-run; items outside the batch
+    // count on a private dummy counter so the atomics need no branches
+    uint32_t e[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const int j = sl[k] - base;
+      const bool ok = (unsigned)j < (unsigned)nb;
+      const int a = ok ? j * kSub + sub : kBatch * kSub + tid;
+      const int r = atomicAdd(&s_cnt8[a], 1);
+      e[k] = ok ? (uint32_t)(j | (r << 8)) : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+
+    // Gaussian tid: its run length; one packed scan gives run starts and the number of
+    // Gaussians with items (a Gaussian occurs at most once per pixel, so runs are <= 256)
+    int c8[kSub];
+    int my_cnt = 0;
+#pragma unroll
+    for (int c = 0; c < kSub; ++c) {
+      c8[c] = s_cnt8[tid * kSub + c];
+      my_cnt += c8[c];
+    }
+    int packed_total;
+    const int packed_off =
+        block_exclusive_scan(my_cnt | ((my_cnt > 0 ? 1 : 0) << 16), s_wave, &packed_total);
+    const int my_off = packed_off & 0xFFFF;
+    const int total_items = packed_total & 0xFFFF;
+    const int busy = packed_total >> 16;
+    // chunk length: sum_j ceil(cnt_j / R) <= total / R + busy <= 256
+    const int R = busy < kRasterThreads
+                      ? max(1, (total_items + (kRasterThreads - busy) - 1) / (kRasterThreads - busy))
+                      : kRasterThreads;
+    const int my_ch = (my_cnt + R - 1) / R;
+    int total_chunks;
+    __syncthreads();  // s_wave reused
+    const int my_cho = block_exclusive_scan(my_ch, s_wave, &total_chunks);
+    {
+      int o = my_off;
+#pragma unroll
+      for (int c = 0; c < kSub; ++c) {
+        s_cnt8[tid * kSub + c] = o;
+        o += c8[c];
+      }
+    }
+    s_off[tid] = my_off;
+    s_cho[tid] = my_cho;
+    for (int c = 0; c < my_ch; ++c) s_owner[my_cho + c] = (uint16_t)tid;
+    if (tid == 0) {
+      s_off[kBatch] = total_items;
+      s_cho[kBatch] = total_chunks;
+    }
+    __syncthreads();
+
+    // the lane's chunk: fetch its Gaussian now so the loads overlap the placement below
+    const bool has = tid < total_chunks;
+    const int j = has ? (int)s_owner[tid] : 0;
+    const uint32_t gid = s_gid[j];
+    float2 mu = make_float2(0.f, 0.f);
+    double4 c64 = make_double4(0.0, 0.0, 0.0, 0.0);
+    float cj[NC];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) cj[ch] = 0.f;
+    if (has) {
+      const float4 a = g32a[gid];
+      mu = make_float2(a.x, a.y);
+      c64 = g64[gid];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch)
+        if (ch < n) cj[ch] = params[(size_t)(5 + ch) * N + gid];
+    }
+
+    // 1b: place every item in its Gaussian's run
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (e[k] != 0xFFFFFFFFu) {
+        const int jj = e[k] & 0xFF;
+        s_item[s_cnt8[jj * kSub + sub] + (e[k] >> 8)] = (uint16_t)(tid | (jj << 8));
+      }
+    }
+    __syncthreads();
+
+    // 2: chunk tid, one Gaussian, accumulated in registers
+    if (has) {
+      const int first = s_off[j] + (tid - s_cho[j]) * R;
+      const int end = min(first + R, s_off[j + 1]);
+      float G1 = 0.f, G2 = 0.f, G11 = 0.f, G22 = 0.f, G12 = 0.f;
+      float gcol[NC];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) gcol[ch] = 0.f;
+      for (int it = first; it < end; ++it) {
+        const int p = s_item[it] & 0xFF;
+        float rw[ROW];
+#pragma unroll
+        for (int r = 0; r < ROW; r += 4) {
+          const float4 v = *reinterpret_cast<const float4 *>(&s_px[p * ROW + r]);
+          rw[r] = v.x;
+          rw[r + 1] = v.y;
+          rw[r + 2] = v.z;
+          rw[r + 3] = v.w;
+        }
+        const float fx = (float)(x0 + (p & (kTile - 1))) + 0.5f;
+        const float fy = (float)(y0 + (p >> 4)) + 0.5f;
+        double d1, d2;
+        const double q = quad_form64(fx, fy, mu.x, mu.y, c64.x, c64.y, c64.z, c64.w, d1, d2);
+        const float alpha = blend_weight(q, rw[NC + 1]) * rw[NC + 2];
+        const float e1 = (float)d1, e2 = (float)d2;
+        float dot = -rw[NC];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) dot = fmaf(rw[ch], cj[ch], dot);
+        const float gq = -0.5f * alpha * dot;
+        const float g1 = gq * e1, g2 = gq * e2;
+        G1 += g1;
+        G2 += g2;
+        G11 = fmaf(g1, e1, G11);
+        G22 = fmaf(g2, e2, G22);
+        G12 = fmaf(g1, e2, G12);
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) gcol[ch] = fmaf(alpha, rw[ch], gcol[ch]);
+      }
+      float *prow = &s_part[tid * NACC];
+      prow[0] = G1;
+      prow[1] = G2;
+      prow[2] = G11;
+      prow[3] = G22;
+      prow[4] = G12;
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) prow[5 + ch] = gcol[ch];
+    }
+    __syncthreads();
+
+    // 3: Gaussian tid adds up its chunks and writes the pair's record (zeros when no pixel of
+    // the tile retained it)
+    if (tid < nb) {
+      constexpr int NR = (NACC + 3) & ~3;
+      float acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = 0.f;
+      for (int c = 0; c < my_ch; ++c) {
+#pragma unroll
+        for (int r = 0; r < NACC; ++r) acc[r] += s_part[(my_cho + c) * NACC + r];
+      }
+      const int stride = part_stride(n);
+      float4 *rec = reinterpret_cast<float4 *>(part + (size_t)my_src * stride);
+#pragma unroll
+      for (int q = 0; q < NR / 4; ++q) {
+        if (4 * q < stride) {
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = (4 * q + e < 5 + n) ? acc[4 * q + e] : 0.f;
+          rec[q] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+      }
+    }
+  }
+  __syncthreads();  // LDS is reused by the next phase or tile
+}
+
+// Tile loss sums (sum |d|, sum d^2) over the workgroup: wave sums by shuffles, then a fixed order
+// over the four waves; the result is valid in thread 0.
+__device__ __forceinline__ double2 tile_loss_sums(double a, double b, double *s_red) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += __shfl_down(a, d, 64);
+    b += __shfl_down(b, d, 64);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_red[2 * wave] = a;
+    s_red[2 * wave + 1] = b;
+  }
+  __syncthreads();
+  double2 t = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < kWaves; ++k) {
+      t.x += s_red[2 * k];
+      t.y += s_red[2 * k + 1];
+    }
+  }
+  return t;
+}
+
+}  // namespace igs

@@ -7,14 +7,15 @@
 
 namespace igs {
 
-constexpr int kNumPhases = 6;
+constexpr int kNumPhases = 7;
 enum Phase {
   kPhaseBinning = 0,
   kPhaseRasterFwd = 1,
   kPhaseRasterBwd = 2,
   kPhaseLoss = 3,
   kPhaseAdam = 4,
-  kPhaseGradReduce = 5
+  kPhaseGradReduce = 5,
+  kPhaseRasterFit = 6
 };
 
 bool timing_on();

@@ -28,6 +28,16 @@ LAMBDA_INIT = 0.3
 GROW_EVERY = 500
 
 
+def _check_single_pass(single_pass: bool, ssim_weight: float, fused: bool, n: int) -> bool:
+    if not single_pass:
+        return False
+    if ssim_weight > 0:
+        raise ValueError("the single-pass kernel evaluates the L1 loss only")
+    if not fused or n > MAX_FUSED_CHANNELS:
+        raise ValueError(f"the single-pass kernel needs the fused L1 path (n <= {MAX_FUSED_CHANNELS})")
+    return True
+
+
 def progressive_growth(budget: int, every: int = GROW_EVERY) -> List[Tuple[int, int]]:
     """(step, count) of the error-guided additions after the initial budget // 2 Gaussians
     (Sec. 4.1): budget // 8 more every 500 steps until the budget is reached (the last addition
@@ -132,7 +142,7 @@ class PlainFitter(_FitLoop):
     def __init__(self, target: torch.Tensor, render_params: torch.Tensor, K: int = 10,
                  adam: Optional[AdamConfig] = None, headroom: float = 1.25,
                  pair_capacity: Optional[int] = None, fused: Optional[bool] = None,
-                 ssim_weight: float = 0.0):
+                 ssim_weight: float = 0.0, single_pass: bool = False):
         if target.dim() != 3:
             raise ValueError("target must be [n][H][W]")
         # ssim_weight > 0: the loss is L1 + ssim_weight * (1 - SSIM) (the paper uses 0.1); the
@@ -155,6 +165,9 @@ class PlainFitter(_FitLoop):
             self.fused = False
         else:
             self.fused = (self.n <= MAX_FUSED_CHANNELS) if fused is None else bool(fused)
+        # single_pass: render, L1 and adjoint of every tile in one kernel (same loss and gradient
+        # as the fused pair, no image); self.image is then rendered only when densifying
+        self.single_pass = _check_single_pass(single_pass, self.ssim_weight, self.fused, self.n)
         self.rend = render_params.to(self.dev).float().contiguous().clone()
         self.fit = torch.empty_like(self.rend)
         self.fit.copy_(self.rend)
@@ -251,6 +264,8 @@ class PlainFitter(_FitLoop):
         if self.place_ws is None:
             self.place_ws = _aligned_bytes(nat.igs_place_workspace_size(self.H, self.W),
                                            self.dev)
+        if self.single_pass:
+            self.r.render_into(self.rend, self.image, self.saved)
         N_old = self.N
         self._resize(N_old + count)
         u = torch.rand(count, generator=self.gen, device=self.dev)
@@ -274,7 +289,9 @@ class PlainFitter(_FitLoop):
     def step_async(self) -> None:
         """Enqueue one iteration on the current stream (no synchronization)."""
         a = self.adam
-        if self.fused:
+        if self.single_pass:
+            self.r.l1_grad_into(self.rend, self.target, self.loss, self.grad_params, self.saved)
+        elif self.fused:
             self.r.render_l1_into(self.rend, self.target, self.image, self.loss, self.saved)
             self.r.backward_l1_into(self.rend, self.saved, self.grad_params)
         else:
@@ -341,7 +358,7 @@ class BatchFitter(_FitLoop):
     def __init__(self, targets: List[torch.Tensor], render_params: List[torch.Tensor], K: int = 10,
                  adam: Optional[AdamConfig] = None, headroom: float = 1.25,
                  pair_capacity: Optional[int] = None, device=None, fused: Optional[bool] = None,
-                 ssim_weight: float = 0.0):
+                 ssim_weight: float = 0.0, single_pass: bool = False):
         from .render import BatchRenderer
         self.dev = torch.device(device) if device is not None else targets[0].device
         self.n = int(targets[0].shape[0])
@@ -356,6 +373,7 @@ class BatchFitter(_FitLoop):
             self.fused = False
         else:
             self.fused = (self.n <= MAX_FUSED_CHANNELS) if fused is None else bool(fused)
+        self.single_pass = _check_single_pass(single_pass, self.ssim_weight, self.fused, self.n)
         sizes = [(int(t.shape[1]), int(t.shape[2]), int(p.shape[1]))
                  for t, p in zip(targets, render_params)]
         self.r = BatchRenderer(sizes, self.n, K, pair_capacity=pair_capacity, device=self.dev)
@@ -396,7 +414,9 @@ class BatchFitter(_FitLoop):
     def step_async(self) -> None:
         a = self.adam
         r = self.r
-        if self.fused:
+        if self.single_pass:
+            r.l1_grad_into(self.rend, self.target, self.loss, self.grad_params, self.saved)
+        elif self.fused:
             r.render_l1_into(self.rend, self.target, self.image, self.loss, self.saved)
             r.backward_l1_into(self.rend, self.saved, self.grad_params)
         else:

@@ -84,6 +84,13 @@ class Renderer:
                                    self.cap, saved, saved.numel(), grad_params, self.ws,
                                    self.ws.numel())
 
+    def l1_grad_into(self, params, target, loss_out, grad_params, saved) -> None:
+        """Mean absolute error against ``target`` and its gradient in one rasterization pass (the
+        same numbers as render_l1_into + backward_l1_into, without an image)."""
+        nat.igs_render_l1_grad(params, self.N, self.n, self.H, self.W, self.K, TILE, TILE,
+                               self.cap, target, loss_out, grad_params, saved, saved.numel(),
+                               self.ws, self.ws.numel())
+
     def status_of(self, saved: Optional[torch.Tensor]) -> torch.Tensor:
         """The int64[8] device status block of a saved state (or of the workspace copy)."""
         buf = saved if saved is not None else self.ws[self.ws_bytes:]
@@ -294,6 +301,11 @@ class BatchRenderer:
         nat.igs_render_backward_l1_batched(params, self.descs, self.d_descs, self.n, self.K,
                                            self.cap, saved, saved.numel(), grad_params, self.ws,
                                            self.ws.numel())
+
+    def l1_grad_into(self, params, targets, loss_out, grad_params, saved) -> None:
+        nat.igs_render_l1_grad_batched(params, self.descs, self.d_descs, self.n, self.K, self.cap,
+                                       targets, loss_out, grad_params, saved, saved.numel(),
+                                       self.ws, self.ws.numel())
 
     def status_of(self, saved: torch.Tensor) -> torch.Tensor:
         return saved[:64].view(torch.int64)

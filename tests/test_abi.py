@@ -94,6 +94,27 @@ def test_render_validates_before_device_work(nat):
                                     None) == -1
     assert L.igs_render_backward_l1(None, 5, 17, 16, 16, 10, 16, 16, 100, None, 0, None, None, 0,
                                     None) == -4
+    # single-pass L1 evaluation: target, loss, gradient, saved state and workspace are required,
+    # n is limited to 16 channels, and a batch must describe itself consistently
+    assert L.igs_render_l1_grad(None, 0, 3, 16, 16, 10, 16, 16, 100, None, None, None, None, 0,
+                                None, 0, None) == -1
+    assert L.igs_render_l1_grad(None, 5, 3, 16, 16, 10, 16, 16, 100, None, None, None, None, 0,
+                                None, 0, None) == -1
+    assert L.igs_render_l1_grad(None, 0, 17, 16, 16, 10, 16, 16, 100, None, None, None, None, 0,
+                                None, 0, None) == -4
+    assert L.igs_render_l1_grad(None, 0, 3, 16, 16, 10, 8, 8, 100, None, None, None, None, 0,
+                                None, 0, None) == -4
+    descs = (nat.ImageDesc * 2)()
+    tot = (ctypes.c_int64 * 4)()
+    Hs, Ws, Ns = ((ctypes.c_int32 * 2)(*v) for v in ((16, 40), (16, 24), (5, 9)))
+    assert L.igs_batch_describe(2, 3, Hs, Ws, Ns, descs, tot) == 0
+    assert L.igs_render_l1_grad_batched(None, descs, None, 2, 3, 10, 100, None, None, None, None,
+                                        0, None, 0, None) == -1
+    assert L.igs_render_l1_grad_batched(None, descs, None, 2, 17, 10, 100, None, None, None, None,
+                                        0, None, 0, None) == -4
+    descs[1].pix_off += 1
+    assert L.igs_render_l1_grad_batched(None, descs, None, 2, 3, 10, 100, None, None, None, None,
+                                        0, None, 0, None) == -1
     sz = ctypes.c_size_t(0)
     assert L.igs_l1_workspace_size(0, ctypes.byref(sz)) == -1
     assert L.igs_l1_workspace_size(1000, ctypes.byref(sz)) == 0 and sz.value >= 16
