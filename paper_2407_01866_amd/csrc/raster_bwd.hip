@@ -124,49 +124,85 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
-// Per Gaussian, one row of 16 lanes: lane l adds the Gaussian's pair records l, l + 16, ... (its
-// records are contiguous in emit order, so each step of the row reads 16 consecutive records),
-// then the row sums its lanes with a fixed tree; both orders depend only on the record count, so
-// the result is reproducible bit for bit.  The sums become
+// Per Gaussian, the sum of its pair records (contiguous in emit order, one per tile it hits, in
+// tile order).  Up to kRowRecords records: one row of 16 lanes, lane l adding records l, l + 16,
+// ... in that order, then the row's lanes summed with a fixed tree.  More records (a footprint of
+// hundreds of tiles, which a fit can grow): the whole workgroup that holds the Gaussian's row,
+// thread t adding records t, t + 256, ... in that order, then a fixed shuffle tree per wave and
+// the four waves in order.  Every order depends only on the record count, so the result is
+// reproducible bit for bit.  The sums become
 //   dL/dmu_x = -2 (A G1 + C G2), dL/dmu_y = -2 (B G1 + D G2),
 //   dL/dtheta = 2 (u1/u2 - u2/u1) G12, dL/ds_a = -2 u_a G_aa,
 // and the colour sums dL/dc.  Every row of grad is written (zeros for a Gaussian that no pixel
 // retained, or when the render overflowed and wrote no records).
 constexpr int kReduceLanes = 16;
+constexpr int kReduceThreads = 256;
+constexpr int kReduceRows = kReduceThreads / kReduceLanes;  // Gaussians per workgroup
+constexpr uint32_t kRowRecords = 256;
 
-template <int NC>
-__global__ __launch_bounds__(256) void grad_reduce_kernel(
-    const float *__restrict__ params, const float4 *__restrict__ g32a,
-    const float2 *__restrict__ g32b, const uint32_t *__restrict__ counts,
-    const int64_t *__restrict__ offsets, const int64_t *__restrict__ status,
-    const float *__restrict__ part, int N, int n, float *__restrict__ grad) {
-  constexpr int NR = (5 + NC + 3) & ~3;
-  const int l = threadIdx.x & (kReduceLanes - 1);
-  const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kReduceLanes);
-  const bool valid = i < N;
-  const int ii = valid ? i : N - 1;
-  const int stride = part_stride(n);
-  const uint32_t c = (valid && status[kStatOverflow] == 0) ? counts[ii] : 0u;
-  const float4 *__restrict__ rec =
-      reinterpret_cast<const float4 *>(part + (size_t)offsets[ii] * stride);
-  float acc[NR];
+// acc += records t, t + step, t + 2 step, ... (below c), in that order.  stride4: float4s per
+// record.
+template <int NR>
+__device__ __forceinline__ void add_records(const float4 *__restrict__ rec, int stride4,
+                                            uint32_t t, uint32_t c, uint32_t step,
+                                            float (&acc)[NR]) {
+  for (; t < c; t += step) {
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = 0.f;
-  for (uint32_t t = l; t < c; t += kReduceLanes) {
-#pragma unroll
-    for (int q = 0; q < NR / 4; ++q) {
-      if (4 * q < stride) {
-        const float4 v = rec[(size_t)t * (stride / 4) + q];
+    for (int q = 0; q < NR / 4; ++q)
+      if (q < stride4) {
+        const float4 v = rec[(size_t)t * stride4 + q];
         acc[4 * q] += v.x;
         acc[4 * q + 1] += v.y;
         acc[4 * q + 2] += v.z;
         acc[4 * q + 3] += v.w;
       }
+  }
+}
+
+// The same sums, one float4 column of the records at a time with four records' loads in flight
+// (a long run per thread; few registers, so the common short rows keep their occupancy).
+template <int NR>
+__device__ __forceinline__ void add_records_long(const float4 *__restrict__ rec, int stride4,
+                                                 uint32_t t0, uint32_t c, uint32_t step,
+                                                 float (&acc)[NR]) {
+#pragma unroll
+  for (int q = 0; q < NR / 4; ++q) {
+    if (q < stride4) {
+      float4 a = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+      uint32_t t = t0;
+      for (; t + 3 * step < c; t += 4 * step) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = rec[(size_t)(t + u * step) * stride4 + q];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a.x += v[u].x;
+          a.y += v[u].y;
+          a.z += v[u].z;
+          a.w += v[u].w;
+        }
+      }
+      for (; t < c; t += step) {
+        const float4 v = rec[(size_t)t * stride4 + q];
+        a.x += v.x;
+        a.y += v.y;
+        a.z += v.z;
+        a.w += v.w;
+      }
+      acc[4 * q] = a.x;
+      acc[4 * q + 1] = a.y;
+      acc[4 * q + 2] = a.z;
+      acc[4 * q + 3] = a.w;
     }
   }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = row_sum16(acc[r]);
-  if (!valid || l != kReduceLanes - 1) return;
+}
+
+template <int NC, int NR>
+__device__ __forceinline__ void write_gradient(int i, const float (&acc)[NR],
+                                               const float *__restrict__ params,
+                                               const float4 *__restrict__ g32a,
+                                               const float2 *__restrict__ g32b, int N, int n,
+                                               float *__restrict__ grad) {
   const float G1 = acc[0], G2 = acc[1], G11 = acc[2], G22 = acc[3], G12 = acc[4];
   const float4 a = g32a[i];
   const float2 cd = g32b[i];
@@ -179,6 +215,69 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(
 #pragma unroll
   for (int ch = 0; ch < NC; ++ch)
     if (ch < n) grad[(size_t)(5 + ch) * N + i] = acc[5 + ch];
+}
+
+template <int NC>
+__global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(
+    const float *__restrict__ params, const float4 *__restrict__ g32a,
+    const float2 *__restrict__ g32b, const uint32_t *__restrict__ counts,
+    const int64_t *__restrict__ offsets, const int64_t *__restrict__ status,
+    const float *__restrict__ part, int N, int n, float *__restrict__ grad) {
+  constexpr int NR = (5 + NC + 3) & ~3;
+  __shared__ uint32_t s_big[kReduceRows];  // per row: record count if the workgroup reduces it
+  __shared__ float s_wave[kReduceThreads / 64][NR];
+  const int l = threadIdx.x & (kReduceLanes - 1);
+  const int row = threadIdx.x / kReduceLanes;
+  const int i = blockIdx.x * kReduceRows + row;
+  const bool valid = i < N;
+  const int ii = valid ? i : N - 1;
+  const int stride4 = part_stride(n) / 4;
+  const uint32_t c = (valid && status[kStatOverflow] == 0) ? counts[ii] : 0u;
+  const bool big = c > kRowRecords;
+  if (l == 0) s_big[row] = big ? c : 0u;
+  if (!big) {
+    const float4 *__restrict__ rec =
+        reinterpret_cast<const float4 *>(part + (size_t)offsets[ii] * (4 * stride4));
+    float acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.f;
+    add_records<NR>(rec, stride4, (uint32_t)l, c, kReduceLanes, acc);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = row_sum16(acc[r]);
+    if (valid && l == kReduceLanes - 1) write_gradient<NC>(i, acc, params, g32a, g32b, N, n, grad);
+  }
+  __syncthreads();
+  for (int r = 0; r < kReduceRows; ++r) {
+    const uint32_t cb = s_big[r];
+    if (cb == 0) continue;  // uniform over the workgroup
+    const int ib = blockIdx.x * kReduceRows + r;
+    const float4 *__restrict__ rec =
+        reinterpret_cast<const float4 *>(part + (size_t)offsets[ib] * (4 * stride4));
+    float acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = 0.f;
+    add_records_long<NR>(rec, stride4, threadIdx.x, cb, kReduceThreads, acc);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) acc[q] += __shfl_down(acc[q], d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) s_wave[threadIdx.x >> 6][q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float tot[NR];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        tot[q] = s_wave[0][q];
+        for (int w = 1; w < kReduceThreads / 64; ++w) tot[q] += s_wave[w][q];
+      }
+      write_gradient<NC>(ib, tot, params, g32a, g32b, N, n, grad);
+    }
+    __syncthreads();  // s_wave is reused
+  }
 }
 
 template <int NC, int KT, bool L1>
@@ -273,11 +372,11 @@ hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const flo
                               const int64_t *status, const float *part, int N, int n,
                               float *grad_params, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  const int blocks = (int)(((int64_t)N * kReduceLanes + 255) / 256);
+  const int blocks = (int)(((int64_t)N + kReduceRows - 1) / kReduceRows);
 #define IGS_RED_NC(NCV)                                                                        \
   if (n <= NCV) {                                                                              \
-    grad_reduce_kernel<NCV><<<blocks, 256, 0, s>>>(params, g32a, g32b, counts, offsets,        \
-                                                   status, part, N, n, grad_params);            \
+    grad_reduce_kernel<NCV><<<blocks, kReduceThreads, 0, s>>>(                                 \
+        params, g32a, g32b, counts, offsets, status, part, N, n, grad_params);                  \
     return hipGetLastError();                                                                  \
   }
   IGS_RED_NC(1)
