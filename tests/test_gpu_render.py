@@ -132,6 +132,27 @@ def test_fit_workload_1024_N20000_full():
     run_full(w.gaussians(), w.H, w.W, w.K, seed=2)
 
 
+def big_footprint_params():
+    """320 x 320 (400 tiles), 2000 Gaussians: six cover every tile, three hit 244-252 tiles and
+    three 268-270 (either side of the 256 records up to which one 16-lane row reduces a
+    Gaussian's gradient; above that its whole workgroup does)."""
+    H = W = 320
+    p = synth.gen_gaussians(77, H, W, 2000, 3)
+    p[3:5, :6] = 150.0
+    p[0, 6:12] = [150.3, 161.7, 170.2, 155.5, 165.9, 158.1]
+    p[1, 6:12] = [160.4, 149.8, 171.3, 166.6, 152.2, 158.9]
+    p[3:5, 6:9] = 44.0
+    p[3:5, 9:12] = 46.0
+    return p, H, W
+
+
+def test_gaussians_covering_hundreds_of_tiles():
+    p, H, W = big_footprint_params()
+    c = [int((cref.tile_lists(p[:, [g]].astype(np.float64), H, W)[0] > 0).sum()) for g in range(12)]
+    assert c[:6] == [400] * 6 and max(c[6:9]) <= 256 < min(c[9:12]), c
+    run_full(p, H, W, 10, seed=5)
+
+
 @pytest.mark.parametrize("K", [1, 2, 5, 10, 16, 32])
 def test_k_values(K):
     H, W, N, n = 96, 112, 700, 3

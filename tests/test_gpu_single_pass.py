@@ -97,6 +97,15 @@ def test_single_pass_large_hit_sets():
     assert_identical(a, b)
 
 
+def test_single_pass_big_footprints():
+    """Gaussians covering 244 to 400 tiles (both gradient reduction paths)."""
+    from test_gpu_render import big_footprint_params
+    p, H, W = big_footprint_params()
+    print(f"[single-pass] big footprints H={H} W={W}", flush=True)
+    _, _, a, b = _pair_and_single(p, _target(H, W, 3), H, W, 10)
+    assert_identical(a, b)
+
+
 def test_single_pass_on_overflow_matches_pair():
     """A pair buffer too small for the hit lists: both paths report the overflow, give the loss of
     an all-zero image and a zero gradient."""
