@@ -178,6 +178,11 @@ hipError_t scan_counts_to_offsets(const uint32_t *counts, int64_t *offsets, int6
                                   int64_t cap, int64_t *status, int64_t *temp, hipStream_t s);
 hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *temp,
                            hipStream_t s);
+// Level one of scan_u32_to_u32 alone: exclusive prefixes within each run of kScanBlockItems
+// inputs, and each run's total in block_sums[ceil(n / kScanBlockItems)]; the full prefix of
+// input i is out[i] plus the exclusive prefix of block_sums at i / kScanBlockItems.
+hipError_t scan_u32_blocks(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *block_sums,
+                           hipStream_t s);
 
 // radix_sort.hip: stable LSD sort of (key, val) by the low key_bits bits; the count is read
 // from status on the device.  Result lands in (keys, vals); (keys_alt, vals_alt) are scratch.

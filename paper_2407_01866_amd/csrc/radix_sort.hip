@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
   if (tid < R) lh[tid] = 0;
   __syncthreads();
   if (base < P) {
-#pragma unroll 4
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
       int64_t i = base + (int64_t)r * kSortThreads + tid;
       if (i < P) atomicAdd(&lh[(keys[i] >> shift) & mask], 1u);
@@ -39,14 +39,21 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
 // Stable scatter: block b places its keys, round by round and lane by lane, at
 // hist_off[d * nblocks + b] + (earlier rounds) + (earlier waves of this round) + (earlier lanes
 // of this wave with the same digit).  Lanes with equal digits are found with one ballot per bit.
+// Every thread loads its keys and values of all rounds first, so the loads are in flight together
+// instead of one round trip per round.  With block_sums, hist_off holds the digit-offset scan's
+// per-run prefixes only (scan_u32_blocks, at most kSortThreads runs), and the block adds the
+// exclusive prefix of the run totals itself, scanned in LDS.
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const int64_t *__restrict__ status, int64_t cap, int shift, int digit_bits,
-    const uint32_t *__restrict__ hist_off, int64_t nblocks, bool st) {
+    const uint32_t *__restrict__ hist_off, const uint32_t *__restrict__ block_sums, int nsums,
+    int64_t nblocks, bool st) {
   constexpr int kWaves = kSortThreads / 64;
   __shared__ uint32_t digit_run[256];
   __shared__ uint32_t wave_cnt[2][kWaves][256];
+  __shared__ uint32_t run_off[kSortThreads];
+  __shared__ uint32_t wave_sum[kWaves];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int R = 1 << digit_bits;
@@ -54,18 +61,42 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
   const int64_t P = live_pairs(status, cap, st);
   const int64_t base = (int64_t)blockIdx.x * kSortTileItems;
   if (base >= P) return;  // uniform over the block
+  if (block_sums) {  // exclusive scan of the run totals
+    const uint32_t v = tid < nsums ? block_sums[tid] : 0u;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    if (lane == 63) wave_sum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < w; ++k) off += wave_sum[k];
+    run_off[tid] = off + inc - v;
+    __syncthreads();
+  }
   if (tid < R) {
-    digit_run[tid] = hist_off[(int64_t)tid * nblocks + blockIdx.x];
+    const int64_t h = (int64_t)tid * nblocks + blockIdx.x;
+    digit_run[tid] = hist_off[h] + (block_sums ? run_off[h / kScanBlockItems] : 0u);
     for (int k = 0; k < kWaves; ++k) wave_cnt[0][k][tid] = wave_cnt[1][k][tid] = 0;
   }
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t kk[kSortItems], vv[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + (int64_t)r * kSortThreads + tid;
+    kk[r] = i < P ? keys_in[i] : 0u;
+    vv[r] = i < P ? vals_in[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int buf = r & 1;
     const int64_t i = base + (int64_t)r * kSortThreads + tid;
     const bool valid = i < P;
-    uint32_t key = valid ? keys_in[i] : 0u;
-    uint32_t val = valid ? vals_in[i] : 0u;
+    const uint32_t key = kk[r];
+    const uint32_t val = vv[r];
     uint32_t d = (key >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < digit_bits; ++b) {
@@ -120,10 +151,21 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                                                                      status_semantics);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = scan_u32_to_u32(hist, hist_off, (int64_t)(1 << bits) * nblocks, scan_tmp, s);
+    // digit offsets: the per-run prefixes here and the run totals' prefix inside the scatter
+    // kernel, or the whole recursive scan when there are more runs than its threads
+    const int64_t hn = (int64_t)(1 << bits) * nblocks;
+    const int64_t runs = (hn + kScanBlockItems - 1) / kScanBlockItems;
+    const uint32_t *run_sums = nullptr;
+    if (runs <= kSortThreads) {
+      e = scan_u32_blocks(hist, hist_off, hn, scan_tmp, s);
+      run_sums = scan_tmp;
+    } else {
+      e = scan_u32_to_u32(hist, hist_off, hn, scan_tmp, s);
+    }
     if (e != hipSuccess) return e;
     radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-        src_k, src_v, dst_k, dst_v, status, cap, shift, bits, hist_off, nblocks, status_semantics);
+        src_k, src_v, dst_k, dst_v, status, cap, shift, bits, hist_off, run_sums, (int)runs,
+        nblocks, status_semantics);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t *tk = src_k, *tv = src_v;

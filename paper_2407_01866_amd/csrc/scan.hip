@@ -107,6 +107,14 @@ hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_
   return scan_rec<uint32_t, uint32_t>(in, out, n, temp, s);
 }
 
+hipError_t scan_u32_blocks(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *block_sums,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  scan_block_kernel<uint32_t, uint32_t>
+      <<<(unsigned)blocks_for(n), kScanThreads, 0, s>>>(in, out, n, block_sums);
+  return hipGetLastError();
+}
+
 hipError_t scan_counts_to_offsets(const uint32_t *counts, int64_t *offsets, int64_t n,
                                   int64_t cap, int64_t *status, int64_t *temp, hipStream_t s) {
   hipError_t e = scan_rec<uint32_t, int64_t>(counts, offsets, n, temp, s);
