@@ -159,42 +159,31 @@ __device__ __forceinline__ void add_records(const float4 *__restrict__ rec, int 
   }
 }
 
-// The same sums, one float4 column of the records at a time with four records' loads in flight
-// (a long run per thread; few registers, so the common short rows keep their occupancy).
-template <int NR>
-__device__ __forceinline__ void add_records_long(const float4 *__restrict__ rec, int stride4,
-                                                 uint32_t t0, uint32_t c, uint32_t step,
-                                                 float (&acc)[NR]) {
+// Column q (a float4) of the sum of records t, t + step, ... (below c), in that order, with four
+// records' loads in flight.
+__device__ __forceinline__ float4 column_sum(const float4 *__restrict__ rec, int stride4, int q,
+                                             uint32_t t, uint32_t c, uint32_t step) {
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (; t + 3 * step < c; t += 4 * step) {
+    float4 v[4];
 #pragma unroll
-  for (int q = 0; q < NR / 4; ++q) {
-    if (q < stride4) {
-      float4 a = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
-      uint32_t t = t0;
-      for (; t + 3 * step < c; t += 4 * step) {
-        float4 v[4];
+    for (int u = 0; u < 4; ++u) v[u] = rec[(size_t)(t + u * step) * stride4 + q];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = rec[(size_t)(t + u * step) * stride4 + q];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a.x += v[u].x;
-          a.y += v[u].y;
-          a.z += v[u].z;
-          a.w += v[u].w;
-        }
-      }
-      for (; t < c; t += step) {
-        const float4 v = rec[(size_t)t * stride4 + q];
-        a.x += v.x;
-        a.y += v.y;
-        a.z += v.z;
-        a.w += v.w;
-      }
-      acc[4 * q] = a.x;
-      acc[4 * q + 1] = a.y;
-      acc[4 * q + 2] = a.z;
-      acc[4 * q + 3] = a.w;
+    for (int u = 0; u < 4; ++u) {
+      a.x += v[u].x;
+      a.y += v[u].y;
+      a.z += v[u].z;
+      a.w += v[u].w;
     }
   }
+  for (; t < c; t += step) {
+    const float4 v = rec[(size_t)t * stride4 + q];
+    a.x += v.x;
+    a.y += v.y;
+    a.z += v.z;
+    a.w += v.w;
+  }
+  return a;
 }
 
 template <int NC, int NR>
@@ -247,32 +236,42 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(
     if (valid && l == kReduceLanes - 1) write_gradient<NC>(i, acc, params, g32a, g32b, N, n, grad);
   }
   __syncthreads();
+  // Gaussians with long runs: the workgroup, one float4 column at a time (a runtime loop, so the
+  // path adds few registers to the kernel), wave sums in LDS, then the waves in order
   for (int r = 0; r < kReduceRows; ++r) {
     const uint32_t cb = s_big[r];
     if (cb == 0) continue;  // uniform over the workgroup
     const int ib = blockIdx.x * kReduceRows + r;
     const float4 *__restrict__ rec =
         reinterpret_cast<const float4 *>(part + (size_t)offsets[ib] * (4 * stride4));
-    float acc[NR];
+#pragma unroll 1
+    for (int q = 0; q < stride4; ++q) {
+      float4 a = column_sum(rec, stride4, q, threadIdx.x, cb, kReduceThreads);
 #pragma unroll
-    for (int q = 0; q < NR; ++q) acc[q] = 0.f;
-    add_records_long<NR>(rec, stride4, threadIdx.x, cb, kReduceThreads, acc);
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) acc[q] += __shfl_down(acc[q], d, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-      for (int q = 0; q < NR; ++q) s_wave[threadIdx.x >> 6][q] = acc[q];
+      for (int d = 32; d >= 1; d >>= 1) {
+        a.x += __shfl_down(a.x, d, 64);
+        a.y += __shfl_down(a.y, d, 64);
+        a.z += __shfl_down(a.z, d, 64);
+        a.w += __shfl_down(a.w, d, 64);
+      }
+      if ((threadIdx.x & 63) == 0) {
+        float *wr = &s_wave[threadIdx.x >> 6][4 * q];
+        wr[0] = a.x;
+        wr[1] = a.y;
+        wr[2] = a.z;
+        wr[3] = a.w;
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       float tot[NR];
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
-        tot[q] = s_wave[0][q];
-        for (int w = 1; w < kReduceThreads / 64; ++w) tot[q] += s_wave[w][q];
+        tot[q] = 0.f;
+        if (q < 4 * stride4) {
+          tot[q] = s_wave[0][q];
+          for (int w = 1; w < kReduceThreads / 64; ++w) tot[q] += s_wave[w][q];
+        }
       }
       write_gradient<NC>(ib, tot, params, g32a, g32b, N, n, grad);
     }
