@@ -270,14 +270,12 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
 
   {
     PhaseTimer timer(kPhaseBinning, s);
-    IGS_HIP(launch_status_reset(status, s));
-    IGS_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 2 * (int64_t)d.T, 0u, s));
+    IGS_HIP(launch_binning_reset(status, ranges, d.T, s));
     IGS_HIP(launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, s));
-    IGS_HIP(scan_counts_to_offsets(counts, offsets, d.N, d.cap, status,
-                                   static_cast<int64_t *>(scan_tmp), s));
     const bool alt = sort_starts_in_alt(d.passes);
-    IGS_HIP(launch_emit(params, d.N, imgs, counts, offsets, d.cap, alt ? keys_alt : keys,
-                        alt ? vals_alt : src, pair_gid, s));
+    IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status,
+                                alt ? keys_alt : keys, alt ? vals_alt : src, pair_gid,
+                                static_cast<int64_t *>(scan_tmp), s));
     IGS_HIP(radix_sort_pairs(keys, src, keys_alt, vals_alt, status, d.cap, d.key_bits, d.passes,
                              d.digit_bits, hist, hist_off, static_cast<uint32_t *>(scan_tmp), s));
     IGS_HIP(launch_resolve_ranges(src, pair_gid, keys, status, d.cap, vals, ranges, s));

@@ -19,8 +19,12 @@ __global__ void fill_f32_kernel(float *__restrict__ p, int64_t count, float valu
   for (; i < count; i += stride) p[i] = value;
 }
 
-__global__ void status_reset_kernel(int64_t *status) {
-  if (threadIdx.x < 8) status[threadIdx.x] = 0;
+__global__ void binning_reset_kernel(int64_t *__restrict__ status, uint32_t *__restrict__ words,
+                                     int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 8) status[i] = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) words[i] = 0u;
 }
 
 // Closed tile rectangle [x0, x1] x [y0, y1] (clipped to the image) against the circle of radius
@@ -157,29 +161,49 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
   counts[i] = c;
 }
 
-__global__ void pair_total_kernel(const uint32_t *__restrict__ counts,
-                                  const int64_t *__restrict__ offsets, int N, int64_t cap,
-                                  int64_t *__restrict__ status) {
-  if (threadIdx.x != 0) return;
-  int64_t P = N > 0 ? offsets[N - 1] + (int64_t)counts[N - 1] : 0;
-  status[kStatPairs] = P;
-  status[kStatOverflow] = P > cap ? 1 : 0;
-}
-
 // Writes (tile key, emit index u) for every tile the Gaussian hits, at the Gaussian's scanned
 // offset, and records the Gaussian of each emit index; the pair list is thereby in ascending
 // Gaussian index, which the stable sort keeps within each tile, and the pairs of Gaussian i are
 // the emit indices [offsets[i], offsets[i] + counts[i]), in row-major tile order.  Nothing is
 // written past the capacity.
+// offsets arrives as the scan's per-run prefixes (runs of kScanBlockItems counts, whose totals are
+// run_sums); a block's Gaussians lie in one run, so the block adds the sum of the earlier runs'
+// totals (integers: exact in any order), writes the finished offsets back, and the last Gaussian's
+// thread writes the pair total and the overflow flag.
+static_assert(kScanBlockItems % kThreads == 0, "an emit block must not straddle two scan runs");
 __global__ __launch_bounds__(kThreads) void emit_kernel(
     const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
-    const int64_t *__restrict__ offsets, int64_t cap, uint32_t *__restrict__ keys,
-    uint32_t *__restrict__ vals, uint32_t *__restrict__ pair_gid) {
+    int64_t *__restrict__ offsets, const int64_t *__restrict__ run_sums, int64_t cap,
+    int64_t *__restrict__ status, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+    uint32_t *__restrict__ pair_gid) {
+  __shared__ int64_t s_wave[kThreads / 64];
+  __shared__ int64_t s_prefix;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
+  {
+    const int run = (int)(((int64_t)blockIdx.x * kThreads) / kScanBlockItems);
+    int64_t part = 0;
+    for (int r = threadIdx.x; r < run; r += kThreads) part += run_sums[r];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) part += __shfl_down(part, d, 64);
+    if (lane == 0) s_wave[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+      for (int k = 0; k < kThreads / 64; ++k) t += s_wave[k];
+      s_prefix = t;
+    }
+    __syncthreads();
+  }
   const int ii = i < N ? i : N - 1;
   const uint32_t c = i < N ? counts[ii] : 0u;
-  const int64_t o = offsets[ii];
+  const int64_t o = i < N ? offsets[i] + s_prefix : 0;
+  if (i < N) offsets[i] = o;
+  if (i == N - 1) {
+    const int64_t P = o + (int64_t)c;
+    status[kStatPairs] = P;
+    status[kStatOverflow] = P > cap ? 1 : 0;
+  }
   const bool active = c != 0 && o + (int64_t)c <= cap;
   const ImageDesc im = imgs.by_gauss(ii);
   float mx = params[ii], my = params[(size_t)N + ii];
@@ -225,19 +249,6 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
   }
 }
 
-// After the sort: the Gaussian of every sorted pair, from its emit index.
-__global__ __launch_bounds__(kThreads) void pair_resolve_kernel(const uint32_t *__restrict__ src,
-                                                                const uint32_t *__restrict__ pair_gid,
-                                                                const int64_t *__restrict__ status,
-                                                                int64_t cap,
-                                                                uint32_t *__restrict__ vals) {
-  int64_t P = status[kStatOverflow] ? 0 : status[kStatPairs];
-  if (P > cap) P = 0;
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; p < P; p += stride) vals[p] = pair_gid[src[p]];
-}
-
 // After the sort: the Gaussian of every sorted pair (from its emit index) and [start, end) of
 // every tile in the sorted list (ranges zeroed beforehand), in one pass.
 __global__ __launch_bounds__(kThreads) void resolve_ranges_kernel(
@@ -250,22 +261,6 @@ __global__ __launch_bounds__(kThreads) void resolve_ranges_kernel(
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
     vals[p] = pair_gid[src[p]];
     const uint32_t k = keys[p];
-    if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
-    if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);
-  }
-}
-
-// [start, end) of every tile in the sorted pair list (ranges zeroed beforehand).
-__global__ __launch_bounds__(kThreads) void tile_ranges_kernel(const uint32_t *__restrict__ keys,
-                                                               const int64_t *__restrict__ status,
-                                                               int64_t cap,
-                                                               int2 *__restrict__ ranges) {
-  int64_t P = status[kStatOverflow] ? 0 : status[kStatPairs];
-  if (P > cap) P = 0;
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; p < P; p += stride) {
-    uint32_t k = keys[p];
     if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
     if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);
   }
@@ -357,8 +352,10 @@ hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_status_reset(int64_t *status, hipStream_t s) {
-  status_reset_kernel<<<1, 64, 0, s>>>(status);
+hipError_t launch_binning_reset(int64_t *status, int2 *ranges, int T, hipStream_t s) {
+  const int64_t count = 2 * (int64_t)T;
+  binning_reset_kernel<<<grid_for(count > 8 ? count : 8, kThreads, 4096), kThreads, 0, s>>>(
+      status, reinterpret_cast<uint32_t *>(ranges), count);
   return hipGetLastError();
 }
 
@@ -370,26 +367,15 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
   return hipGetLastError();
 }
 
-hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int N, int64_t cap,
-                             int64_t *status, hipStream_t s) {
-  pair_total_kernel<<<1, 64, 0, s>>>(counts, offsets, N, cap, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_emit(const float *params, int N, const Images &imgs, const uint32_t *counts,
-                       const int64_t *offsets, int64_t cap, uint32_t *keys, uint32_t *vals,
-                       uint32_t *pair_gid, hipStream_t s) {
-  if (N <= 0) return hipSuccess;  // (the kernels read entry N - 1 for lanes past N)
-  emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(params, N, imgs, counts, offsets,
-                                                                  cap, keys, vals, pair_gid);
-  return hipGetLastError();
-}
-
-hipError_t launch_pair_resolve(const uint32_t *src, const uint32_t *pair_gid,
-                               const int64_t *status, int64_t cap, uint32_t *vals,
-                               hipStream_t s) {
-  pair_resolve_kernel<<<grid_for(cap, kThreads, 8192), kThreads, 0, s>>>(src, pair_gid, status,
-                                                                         cap, vals);
+hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
+                               const uint32_t *counts, int64_t *offsets, int64_t cap,
+                               int64_t *status, uint32_t *keys, uint32_t *vals,
+                               uint32_t *pair_gid, int64_t *scan_tmp, hipStream_t s) {
+  if (N <= 0) return hipSuccess;  // the status block already holds 0 pairs, no overflow
+  hipError_t e = scan_u32_to_i64_blocks(counts, offsets, N, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(
+      params, N, imgs, counts, offsets, scan_tmp, cap, status, keys, vals, pair_gid);
   return hipGetLastError();
 }
 
@@ -399,12 +385,6 @@ hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
   resolve_ranges_kernel<<<grid_for(cap, kThreads, 8192), kThreads, 0, s>>>(src, pair_gid, keys,
                                                                            status, cap, vals,
                                                                            ranges);
-  return hipGetLastError();
-}
-
-hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
-                              int2 *ranges, hipStream_t s) {
-  tile_ranges_kernel<<<grid_for(cap, kThreads, 8192), kThreads, 0, s>>>(keys, status, cap, ranges);
   return hipGetLastError();
 }
 

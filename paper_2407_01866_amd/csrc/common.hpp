@@ -145,23 +145,22 @@ size_t scan_temp_elems(int64_t n);
 // binning.hip
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s);
-hipError_t launch_status_reset(int64_t *status, hipStream_t s);
+// Zeroes the status block and the T tile ranges in one launch.
+hipError_t launch_binning_reset(int64_t *status, int2 *ranges, int T, hipStream_t s);
 hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
                              float2 *g32b, double4 *g64, uint32_t *counts, hipStream_t s);
-hipError_t launch_pair_total(const uint32_t *counts, const int64_t *offsets, int N, int64_t cap,
-                             int64_t *status, hipStream_t s);
-// vals receives emit indices (sorted along with the keys), pair_gid[u] the Gaussian of emit
-// index u; launch_pair_resolve then maps sorted emit indices to Gaussians.
-hipError_t launch_emit(const float *params, int N, const Images &imgs, const uint32_t *counts,
-                       const int64_t *offsets, int64_t cap, uint32_t *keys, uint32_t *vals,
-                       uint32_t *pair_gid, hipStream_t s);
-hipError_t launch_pair_resolve(const uint32_t *src, const uint32_t *pair_gid,
-                               const int64_t *status, int64_t cap, uint32_t *vals, hipStream_t s);
+// Pair offsets and emission: offsets = exclusive scan of counts (finished inside the emit kernel,
+// which also writes the pair total and overflow flag into the status block); then every
+// Gaussian's (tile key, emit index) pairs.  vals receives emit indices (sorted along with the
+// keys), pair_gid[u] the Gaussian of emit index u; launch_resolve_ranges then maps sorted emit
+// indices to Gaussians.  scan_tmp holds scan_temp_elems(N) int64 values.
+hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
+                               const uint32_t *counts, int64_t *offsets, int64_t cap,
+                               int64_t *status, uint32_t *keys, uint32_t *vals,
+                               uint32_t *pair_gid, int64_t *scan_tmp, hipStream_t s);
 hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
                                 const uint32_t *keys, const int64_t *status, int64_t cap,
                                 uint32_t *vals, int2 *ranges, hipStream_t s);
-hipError_t launch_tile_ranges(const uint32_t *keys, const int64_t *status, int64_t cap,
-                              int2 *ranges, hipStream_t s);
 hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K,
                              int64_t *status, hipStream_t s);
 // Sort keys for the largest-first tile queue: key = 0xFFFF - min(|S_j|, 0xFFFF), value = tile;
@@ -170,12 +169,10 @@ hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uin
                                   int64_t *count, hipStream_t s);
 
 // scan.hip: exclusive scans; temp must hold scan_temp_elems(n) elements of the output type.
-hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *temp,
-                           hipStream_t s);
-// Exclusive scan of the per-Gaussian pair counts into offsets, and the pair total and overflow
-// flag (against cap) into the status block.
-hipError_t scan_counts_to_offsets(const uint32_t *counts, int64_t *offsets, int64_t n,
-                                  int64_t cap, int64_t *status, int64_t *temp, hipStream_t s);
+// Level one of an exclusive scan of uint32 counts into int64 offsets (per-run prefixes and run
+// totals, as scan_u32_blocks).
+hipError_t scan_u32_to_i64_blocks(const uint32_t *in, int64_t *out, int64_t n,
+                                  int64_t *block_sums, hipStream_t s);
 hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *temp,
                            hipStream_t s);
 // Level one of scan_u32_to_u32 alone: exclusive prefixes within each run of kScanBlockItems

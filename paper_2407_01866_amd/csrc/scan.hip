@@ -1,6 +1,7 @@
 // Exclusive prefix sums (reduce-then-scan, recursive over block totals), used for the per-Gaussian
 // pair offsets, the radix-sort digit offsets and the sampling distributions of the placement
-// kernels (fp64, in a fixed order).
+// kernels (fp64, in a fixed order).  The pair offsets and the digit offsets use level one only;
+// the kernel that consumes them adds the prefix of the run totals itself.
 #include "common.hpp"
 
 namespace igs {
@@ -97,11 +98,6 @@ size_t scan_temp_elems(int64_t n) {
   return total + 2;
 }
 
-hipError_t scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *temp,
-                           hipStream_t s) {
-  return scan_rec<uint32_t, int64_t>(in, out, n, temp, s);
-}
-
 hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *temp,
                            hipStream_t s) {
   return scan_rec<uint32_t, uint32_t>(in, out, n, temp, s);
@@ -115,11 +111,12 @@ hipError_t scan_u32_blocks(const uint32_t *in, uint32_t *out, int64_t n, uint32_
   return hipGetLastError();
 }
 
-hipError_t scan_counts_to_offsets(const uint32_t *counts, int64_t *offsets, int64_t n,
-                                  int64_t cap, int64_t *status, int64_t *temp, hipStream_t s) {
-  hipError_t e = scan_rec<uint32_t, int64_t>(counts, offsets, n, temp, s);
-  if (e != hipSuccess) return e;
-  return launch_pair_total(counts, offsets, (int)n, cap, status, s);
+hipError_t scan_u32_to_i64_blocks(const uint32_t *in, int64_t *out, int64_t n,
+                                  int64_t *block_sums, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  scan_block_kernel<uint32_t, int64_t>
+      <<<(unsigned)blocks_for(n), kScanThreads, 0, s>>>(in, out, n, block_sums);
+  return hipGetLastError();
 }
 
 hipError_t scan_f64(const double *in, double *out, int64_t n, double *temp, hipStream_t s) {
