@@ -274,10 +274,11 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
     IGS_HIP(launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, s));
     const bool alt = sort_starts_in_alt(d.passes);
     IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status,
-                                alt ? keys_alt : keys, alt ? vals_alt : src, pair_gid,
-                                static_cast<int64_t *>(scan_tmp), s));
+                                alt ? keys_alt : keys, pair_gid, static_cast<int64_t *>(scan_tmp),
+                                s));
     IGS_HIP(radix_sort_pairs(keys, src, keys_alt, vals_alt, status, d.cap, d.key_bits, d.passes,
-                             d.digit_bits, hist, hist_off, static_cast<uint32_t *>(scan_tmp), s));
+                             d.digit_bits, hist, hist_off, static_cast<uint32_t *>(scan_tmp), s,
+                             true, true));
     IGS_HIP(launch_resolve_ranges(src, pair_gid, keys, status, d.cap, vals, ranges, s));
     IGS_HIP(launch_tile_stats(ranges, d.T, imgs, d.K, status, s));
     if (batched) {

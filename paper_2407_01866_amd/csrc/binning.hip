@@ -161,8 +161,8 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
   counts[i] = c;
 }
 
-// Writes (tile key, emit index u) for every tile the Gaussian hits, at the Gaussian's scanned
-// offset, and records the Gaussian of each emit index; the pair list is thereby in ascending
+// Writes the tile key of every tile the Gaussian hits at emit index u (from the Gaussian's scanned
+// offset on), and records the Gaussian of each emit index; the pair list is thereby in ascending
 // Gaussian index, which the stable sort keeps within each tile, and the pairs of Gaussian i are
 // the emit indices [offsets[i], offsets[i] + counts[i]), in row-major tile order.  Nothing is
 // written past the capacity.
@@ -174,8 +174,7 @@ static_assert(kScanBlockItems % kThreads == 0, "an emit block must not straddle 
 __global__ __launch_bounds__(kThreads) void emit_kernel(
     const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
     int64_t *__restrict__ offsets, const int64_t *__restrict__ run_sums, int64_t cap,
-    int64_t *__restrict__ status, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-    uint32_t *__restrict__ pair_gid) {
+    int64_t *__restrict__ status, uint32_t *__restrict__ keys, uint32_t *__restrict__ pair_gid) {
   __shared__ int64_t s_wave[kThreads / 64];
   __shared__ int64_t s_prefix;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -216,7 +215,6 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
       for (int tx = b.tx0; tx <= b.tx1; ++tx)
         if (circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W) && k < c) {
           keys[o + k] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
-          vals[o + k] = (uint32_t)(o + k);
           pair_gid[o + k] = (uint32_t)i;
           ++k;
         }
@@ -241,7 +239,6 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
       const uint32_t rank = k + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
       if (hit && rank < sc) {
         keys[sbase + rank] = (uint32_t)(tile_off + ty * tiles_x + tx);
-        vals[sbase + rank] = (uint32_t)(sbase + rank);
         pair_gid[sbase + rank] = gid;
       }
       k += (uint32_t)__popcll(m);
@@ -369,13 +366,13 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
 
 hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
                                const uint32_t *counts, int64_t *offsets, int64_t cap,
-                               int64_t *status, uint32_t *keys, uint32_t *vals,
-                               uint32_t *pair_gid, int64_t *scan_tmp, hipStream_t s) {
+                               int64_t *status, uint32_t *keys, uint32_t *pair_gid,
+                               int64_t *scan_tmp, hipStream_t s) {
   if (N <= 0) return hipSuccess;  // the status block already holds 0 pairs, no overflow
   hipError_t e = scan_u32_to_i64_blocks(counts, offsets, N, scan_tmp, s);
   if (e != hipSuccess) return e;
   emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(
-      params, N, imgs, counts, offsets, scan_tmp, cap, status, keys, vals, pair_gid);
+      params, N, imgs, counts, offsets, scan_tmp, cap, status, keys, pair_gid);
   return hipGetLastError();
 }
 

@@ -151,13 +151,13 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
                              float2 *g32b, double4 *g64, uint32_t *counts, hipStream_t s);
 // Pair offsets and emission: offsets = exclusive scan of counts (finished inside the emit kernel,
 // which also writes the pair total and overflow flag into the status block); then every
-// Gaussian's (tile key, emit index) pairs.  vals receives emit indices (sorted along with the
-// keys), pair_gid[u] the Gaussian of emit index u; launch_resolve_ranges then maps sorted emit
-// indices to Gaussians.  scan_tmp holds scan_temp_elems(N) int64 values.
+// Gaussian's tile keys at their emit indices and pair_gid[u], the Gaussian of emit index u.  The
+// sort carries the emit indices as values (generated by its first pass); launch_resolve_ranges
+// then maps sorted emit indices to Gaussians.  scan_tmp holds scan_temp_elems(N) int64 values.
 hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
                                const uint32_t *counts, int64_t *offsets, int64_t cap,
-                               int64_t *status, uint32_t *keys, uint32_t *vals,
-                               uint32_t *pair_gid, int64_t *scan_tmp, hipStream_t s);
+                               int64_t *status, uint32_t *keys, uint32_t *pair_gid,
+                               int64_t *scan_tmp, hipStream_t s);
 hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
                                 const uint32_t *keys, const int64_t *status, int64_t cap,
                                 uint32_t *vals, int2 *ranges, hipStream_t s);
@@ -185,10 +185,12 @@ hipError_t scan_u32_blocks(const uint32_t *in, uint32_t *out, int64_t n, uint32_
 // from status on the device.  Result lands in (keys, vals); (keys_alt, vals_alt) are scratch.
 // count_word: the device word holding the number of pairs (a render's status block, whose
 // overflow flag then also empties the sort), or a plain count when status_semantics is false.
+// identity_vals: the input value of key i is i (the first pass generates it; vals is not read).
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                             uint32_t *vals_alt, const int64_t *status, int64_t cap, int key_bits,
                             int passes, int digit_bits, uint32_t *hist, uint32_t *hist_off,
-                            uint32_t *scan_tmp, hipStream_t s, bool status_semantics = true);
+                            uint32_t *scan_tmp, hipStream_t s, bool status_semantics = true,
+                            bool identity_vals = false);
 // Which buffer emit must write into so the sort's final pass ends in (keys, vals).
 inline bool sort_starts_in_alt(int passes) { return (passes & 1) != 0; }
 

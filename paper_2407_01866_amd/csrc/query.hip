@@ -21,11 +21,11 @@ namespace {
 
 constexpr int kQueryThreads = 256;
 
-// Sort keys of the points: the tile of each point (T for a point outside the image), with the
-// point's index as the value, so that a stable sort groups the points by tile in input order.
+// Sort keys of the points: the tile of each point (T for a point outside the image); the sort
+// takes the point's index as the value, so that it groups the points by tile in input order.
 __global__ __launch_bounds__(kQueryThreads) void query_keys_kernel(
     const float *__restrict__ pts, int M, int H, int W, int tiles_x, int tiles_y,
-    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t *__restrict__ count) {
+    uint32_t *__restrict__ keys, int64_t *__restrict__ count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) count[0] = M;
   if (i >= M) return;
@@ -35,7 +35,6 @@ __global__ __launch_bounds__(kQueryThreads) void query_keys_kernel(
   keys[i] = inside ? (uint32_t)(min((int)fy / kTile, tiles_y - 1) * tiles_x +
                                 min((int)fx / kTile, tiles_x - 1))
                    : (uint32_t)(tiles_x * tiles_y);
-  vals[i] = (uint32_t)i;
 }
 
 // One thread per point, in the order `order` gives (points grouped by tile, so that the lanes of
@@ -215,14 +214,13 @@ hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
     int64_t *count = reinterpret_cast<int64_t *>(b + L.count);
     const bool alt = sort_starts_in_alt(L.passes);
     query_keys_kernel<<<grid, kQueryThreads, 0, s>>>(points, M, H, W, tiles_x, tiles_y,
-                                                     alt ? keys_alt : keys, alt ? vals_alt : vs,
-                                                     count);
+                                                     alt ? keys_alt : keys, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = radix_sort_pairs(keys, vs, keys_alt, vals_alt, count, M, L.key_bits, L.passes,
                          L.digit_bits, reinterpret_cast<uint32_t *>(b + L.hist),
                          reinterpret_cast<uint32_t *>(b + L.hist_off),
-                         reinterpret_cast<uint32_t *>(b + L.scan_tmp), s, false);
+                         reinterpret_cast<uint32_t *>(b + L.scan_tmp), s, false, true);
     if (e != hipSuccess) return e;
     order = vs;
   }

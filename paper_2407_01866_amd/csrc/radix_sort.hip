@@ -40,7 +40,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
 // hist_off[d * nblocks + b] + (earlier rounds) + (earlier waves of this round) + (earlier lanes
 // of this wave with the same digit).  Lanes with equal digits are found with one ballot per bit.
 // Every thread loads its keys and values of all rounds first, so the loads are in flight together
-// instead of one round trip per round.  With block_sums, hist_off holds the digit-offset scan's
+// instead of one round trip per round.  identity: the value of key i is i itself (vals_in unread).
+// With block_sums, hist_off holds the digit-offset scan's
 // per-run prefixes only (scan_u32_blocks, at most kSortThreads runs), and the block adds the
 // exclusive prefix of the run totals itself, scanned in LDS.
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const int64_t *__restrict__ status, int64_t cap, int shift, int digit_bits,
     const uint32_t *__restrict__ hist_off, const uint32_t *__restrict__ block_sums, int nsums,
-    int64_t nblocks, bool st) {
+    int64_t nblocks, bool st, bool identity) {
   constexpr int kWaves = kSortThreads / 64;
   __shared__ uint32_t digit_run[256];
   __shared__ uint32_t wave_cnt[2][kWaves][256];
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = base + (int64_t)r * kSortThreads + tid;
     kk[r] = i < P ? keys_in[i] : 0u;
-    vv[r] = i < P ? vals_in[i] : 0u;
+    vv[r] = identity ? (uint32_t)i : (i < P ? vals_in[i] : 0u);
   }
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
@@ -133,7 +134,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                             uint32_t *vals_alt, const int64_t *status, int64_t cap, int key_bits,
                             int passes, int digit_bits, uint32_t *hist, uint32_t *hist_off,
-                            uint32_t *scan_tmp, hipStream_t s, bool status_semantics) {
+                            uint32_t *scan_tmp, hipStream_t s, bool status_semantics,
+                            bool identity_vals) {
   const int64_t nblocks = (cap + kSortTileItems - 1) / kSortTileItems;
   const int R = 1 << digit_bits;
   // pass p reads from src and writes to dst; with an odd pass count the data starts in alt
@@ -165,7 +167,7 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
     if (e != hipSuccess) return e;
     radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(
         src_k, src_v, dst_k, dst_v, status, cap, shift, bits, hist_off, run_sums, (int)runs,
-        nblocks, status_semantics);
+        nblocks, status_semantics, identity_vals && p == 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t *tk = src_k, *tv = src_v;
