@@ -85,6 +85,24 @@ __device__ __forceinline__ TileBox tile_box(float fmx, float fmy, float fs1, flo
 // whole wave (lane t tests tiles t, t + 64, ... of the box, in the box's row-major order) instead
 // of by their own lane, so one very large Gaussian does not serialize the kernel.
 constexpr int kCoopTiles = 64;
+// Smaller boxes are enumerated by a quad of consecutive lanes per Gaussian (lane q of the quad
+// tests tiles q, q + 4, ... in row-major order), which gives the kernels four times the waves.
+constexpr int kQuad = 4;
+constexpr int kQuadGauss = kThreads / kQuad;  // Gaussians per workgroup
+
+// Advances (x, y) by k positions in row-major order over rows of width w >= 1.
+__device__ __forceinline__ void rowmajor_step(int &x, int &y, int k, int w) {
+  x += k;
+  while (x >= w) {
+    x -= w;
+    ++y;
+  }
+}
+
+// The bits of a wave ballot that belong to the calling lane's quad.
+__device__ __forceinline__ uint32_t quad_bits(uint64_t m, int lane) {
+  return (uint32_t)(m >> (lane & ~(kQuad - 1))) & ((1u << kQuad) - 1u);
+}
 
 struct CoopBox {  // the candidate box of one Gaussian, broadcast from its lane
   double mx, my, r2;
@@ -121,7 +139,8 @@ __device__ __forceinline__ int box_area(const TileBox &b) {
 __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     const float *__restrict__ params, int N, Images imgs, float4 *__restrict__ g32a,
     float2 *__restrict__ g32b, double4 *__restrict__ g64, uint32_t *__restrict__ counts) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * kQuadGauss + (int)(threadIdx.x / kQuad);
+  const int q = threadIdx.x & (kQuad - 1);
   const bool valid = i < N;
   const int lane = threadIdx.x & 63;
   const int ii = valid ? i : N - 1;  // lanes past N mirror the last Gaussian and write nothing
@@ -131,12 +150,18 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
   TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
   const int area = valid ? box_area(b) : 0;
   uint32_t c = 0;
-  if (valid && area <= kCoopTiles) {
-    for (int ty = b.ty0; ty <= b.ty1; ++ty)
-      for (int tx = b.tx0; tx <= b.tx1; ++tx)
-        c += circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W);
+  if (area > 0 && area <= kCoopTiles) {  // (a non-empty box has width >= 1)
+    const int w = b.tx1 - b.tx0 + 1;
+    int x = 0, y = 0;
+    rowmajor_step(x, y, q, w);
+    for (int t = q; t < area; t += kQuad) {
+      c += circle_meets_tile(b.mx, b.my, b.r2, b.tx0 + x, b.ty0 + y, im.H, im.W);
+      rowmajor_step(x, y, kQuad, w);
+    }
   }
-  uint64_t big = __ballot(area > kCoopTiles);
+  c += __shfl_xor(c, 1, 64);  // the quad's total, in every lane of the quad
+  c += __shfl_xor(c, 2, 64);
+  uint64_t big = __ballot(area > kCoopTiles && q == 0);
   while (big) {
     const int src = __ffsll((unsigned long long)big) - 1;
     big &= big - 1;
@@ -150,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     }
     if (lane == src) c = hits;
   }
-  if (!valid) return;
+  if (!valid || q != 0) return;
   double sn, cs;
   sincos((double)th, &sn, &cs);
   double u1 = 1.0 / (double)s1, u2 = 1.0 / (double)s2;
@@ -170,17 +195,18 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
 // run_sums); a block's Gaussians lie in one run, so the block adds the sum of the earlier runs'
 // totals (integers: exact in any order), writes the finished offsets back, and the last Gaussian's
 // thread writes the pair total and the overflow flag.
-static_assert(kScanBlockItems % kThreads == 0, "an emit block must not straddle two scan runs");
+static_assert(kScanBlockItems % kQuadGauss == 0, "an emit block must not straddle two scan runs");
 __global__ __launch_bounds__(kThreads) void emit_kernel(
     const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
     int64_t *__restrict__ offsets, const int64_t *__restrict__ run_sums, int64_t cap,
     int64_t *__restrict__ status, uint32_t *__restrict__ keys, uint32_t *__restrict__ pair_gid) {
   __shared__ int64_t s_wave[kThreads / 64];
   __shared__ int64_t s_prefix;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * kQuadGauss + (int)(threadIdx.x / kQuad);
+  const int q = threadIdx.x & (kQuad - 1);
   const int lane = threadIdx.x & 63;
   {
-    const int run = (int)(((int64_t)blockIdx.x * kThreads) / kScanBlockItems);
+    const int run = (int)(((int64_t)blockIdx.x * kQuadGauss) / kScanBlockItems);
     int64_t part = 0;
     for (int r = threadIdx.x; r < run; r += kThreads) part += run_sums[r];
 #pragma unroll
@@ -196,9 +222,11 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
   }
   const int ii = i < N ? i : N - 1;
   const uint32_t c = i < N ? counts[ii] : 0u;
-  const int64_t o = i < N ? offsets[i] + s_prefix : 0;
-  if (i < N) offsets[i] = o;
-  if (i == N - 1) {
+  // the quad's first lane reads and rewrites the offset; the others take it by shuffle
+  int64_t o = (i < N && q == 0) ? offsets[i] + s_prefix : 0;
+  o = __shfl(o, lane & ~(kQuad - 1), 64);
+  if (i < N && q == 0) offsets[i] = o;
+  if (i == N - 1 && q == 0) {
     const int64_t P = o + (int64_t)c;
     status[kStatPairs] = P;
     status[kStatOverflow] = P > cap ? 1 : 0;
@@ -209,17 +237,28 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
   float s1 = params[3 * (size_t)N + ii], s2 = params[4 * (size_t)N + ii];
   TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
   const int area = active ? box_area(b) : 0;
-  if (area <= kCoopTiles) {
+  if (area > 0 && area <= kCoopTiles) {  // (a non-empty box has width >= 1)
+    // the quad walks the box in row-major order, four tiles per step; a hit's rank is the quad's
+    // hits so far plus those of its lower lanes in this step
+    const int w = b.tx1 - b.tx0 + 1;
+    int x = 0, y = 0;
+    rowmajor_step(x, y, q, w);
     uint32_t k = 0;
-    for (int ty = b.ty0; ty <= b.ty1 && active; ++ty)
-      for (int tx = b.tx0; tx <= b.tx1; ++tx)
-        if (circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W) && k < c) {
-          keys[o + k] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
-          pair_gid[o + k] = (uint32_t)i;
-          ++k;
-        }
+    for (int t0 = 0; t0 < area; t0 += kQuad) {  // uniform over the quad
+      const int t = t0 + q;
+      const int tx = b.tx0 + x, ty = b.ty0 + y;
+      rowmajor_step(x, y, kQuad, w);
+      const bool hit = t < area && circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W);
+      const uint32_t qm = quad_bits(__ballot(hit), lane);
+      const uint32_t rank = k + (uint32_t)__popc(qm & ((1u << q) - 1u));
+      if (hit && rank < c) {
+        keys[o + rank] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
+        pair_gid[o + rank] = (uint32_t)i;
+      }
+      k += (uint32_t)__popc(qm);
+    }
   }
-  uint64_t big = __ballot(area > kCoopTiles);
+  uint64_t big = __ballot(area > kCoopTiles && q == 0);
   while (big) {
     const int src = __ffsll((unsigned long long)big) - 1;
     big &= big - 1;
@@ -229,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
     const uint32_t sc = (uint32_t)__builtin_amdgcn_readlane((int)c, src);
     const int tiles_x = __builtin_amdgcn_readlane(im.tiles_x, src);
     const int tile_off = __builtin_amdgcn_readlane(im.tile_off, src);
-    const uint32_t gid = (uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63u) + src);
+    const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane(i, src);
     uint32_t k = 0;  // hits written so far (uniform)
     for (int t0 = 0; t0 < cb.area; t0 += 64) {
       const int t = t0 + lane;
@@ -359,7 +398,7 @@ hipError_t launch_binning_reset(int64_t *status, int2 *ranges, int T, hipStream_
 hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
                              float2 *g32b, double4 *g64, uint32_t *counts, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  preprocess_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(params, N, imgs, g32a,
+  preprocess_kernel<<<(N + kQuadGauss - 1) / kQuadGauss, kThreads, 0, s>>>(params, N, imgs, g32a,
                                                                         g32b, g64, counts);
   return hipGetLastError();
 }
@@ -371,7 +410,7 @@ hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
   if (N <= 0) return hipSuccess;  // the status block already holds 0 pairs, no overflow
   hipError_t e = scan_u32_to_i64_blocks(counts, offsets, N, scan_tmp, s);
   if (e != hipSuccess) return e;
-  emit_kernel<<<(N + kThreads - 1) / kThreads, kThreads, 0, s>>>(
+  emit_kernel<<<(N + kQuadGauss - 1) / kQuadGauss, kThreads, 0, s>>>(
       params, N, imgs, counts, offsets, scan_tmp, cap, status, keys, pair_gid);
   return hipGetLastError();
 }
