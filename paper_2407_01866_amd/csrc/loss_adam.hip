@@ -71,69 +71,88 @@ __device__ __forceinline__ float to_render(int r, float p, float W, float H) {
   return p;
 }
 
-// The image of Gaussian i for a block whose Gaussians start at i0: the image of i0 is found once
-// per block by binary search; the block's other Gaussians lie in it or in the next few images.
-__device__ __forceinline__ ImageDesc block_image_of(const Images &imgs, int i, int i0, int *s_b0) {
-  if (!imgs.arr) return imgs.one;
-  if (threadIdx.x == 0) {
-    int lo = 0, hi = imgs.B - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (imgs.arr[mid].gauss_off <= i0) lo = mid;
-      else hi = mid - 1;
-    }
-    *s_b0 = lo;
-  }
-  __syncthreads();
-  int b = *s_b0;
-  while (b + 1 < imgs.B && imgs.arr[b + 1].gauss_off <= i) ++b;
-  return imgs.arr[b];
-}
+// Four elements of one row per thread (Gaussians i0 + tid + 256 u of row blockIdx.y of the
+// [5+n][N] arrays, so every load and store of a block is contiguous), their loads issued
+// together and the bias corrections computed once.  u_lo > 0: lower clip of the inverse scales;
+// u_lo <= 0: 1/max(H, W) of each Gaussian's image.
+constexpr int kAdamThreads = 256;
+constexpr int kAdamItems = 4;
 
-// One thread per (row, Gaussian): blockIdx.y is the row of the [5+n][N] arrays, so loads and
-// stores of a block are contiguous.  u_lo > 0: lower clip of the inverse scales; u_lo <= 0:
-// 1/max(H, W) of each Gaussian's image.
-__global__ __launch_bounds__(256) void adam_kernel(
+__global__ __launch_bounds__(kAdamThreads) void adam_kernel(
     float *__restrict__ fit, float *__restrict__ rend, const float *__restrict__ grad,
     float *__restrict__ m, float *__restrict__ v, const int32_t *__restrict__ step,
     const int64_t *__restrict__ skip, int N, int n, Images imgs, float lr_mu, float lr_theta,
     float lr_u, float lr_c, float b1, float b2, float eps, float u_lo_arg, float u_hi) {
   __shared__ int s_b0;
   if (skip != nullptr && skip[0] != 0) return;  // uniform: the whole grid skips
-  const int i0 = blockIdx.x * blockDim.x;
-  const int i = i0 + threadIdx.x;
+  const int i0 = blockIdx.x * (kAdamThreads * kAdamItems);
   const int r = blockIdx.y;
-  const ImageDesc im = block_image_of(imgs, min(i, N - 1), i0, &s_b0);
-  if (i >= N) return;
-  const size_t e = (size_t)r * N + i;
-  const float W = (float)im.W, H = (float)im.H;
-  const float u_lo = u_lo_arg > 0.f ? u_lo_arg : 1.0f / fmaxf(W, H);
+  // the image of the block's first Gaussian, once per block; later ones walk forward from it
+  int b = 0;
+  if (imgs.arr) {
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = imgs.B - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (imgs.arr[mid].gauss_off <= i0) lo = mid;
+        else hi = mid - 1;
+      }
+      s_b0 = lo;
+    }
+    __syncthreads();
+    b = s_b0;
+  }
   const float t = (float)(step[0] + 1);
   const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
-  const float p = fit[e];
-  float g = grad[e];
-  float lr = lr_c;
-  if (r == 0) {
-    g *= W;
-    lr = lr_mu;
-  } else if (r == 1) {
-    g *= H;
-    lr = lr_mu;
-  } else if (r == 2) {
-    lr = lr_theta;
-  } else if (r == 3 || r == 4) {
-    g = -g / (p * p);  // dL/du = -s^2 dL/ds with u = 1/s
-    lr = lr_u;
+  float pv[kAdamItems], gv[kAdamItems], mv[kAdamItems], vv[kAdamItems];
+#pragma unroll
+  for (int u = 0; u < kAdamItems; ++u) {
+    const int i = i0 + u * kAdamThreads + (int)threadIdx.x;
+    const size_t e = (size_t)r * N + (i < N ? i : 0);
+    pv[u] = fit[e];
+    gv[u] = grad[e];
+    mv[u] = m[e];
+    vv[u] = v[e];
   }
-  const float mm = b1 * m[e] + (1.0f - b1) * g;
-  const float vv = b2 * v[e] + (1.0f - b2) * g * g;
-  m[e] = mm;
-  v[e] = vv;
-  float np = p - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
-  if (r == 2) np = fminf(fmaxf(np, 0.0f), 3.14159265358979323846f);
-  if (r == 3 || r == 4) np = fminf(fmaxf(np, u_lo), u_hi);
-  fit[e] = np;
-  rend[e] = to_render(r, np, W, H);
+#pragma unroll
+  for (int u = 0; u < kAdamItems; ++u) {
+    const int i = i0 + u * kAdamThreads + (int)threadIdx.x;
+    if (i >= N) break;
+    const size_t e = (size_t)r * N + i;
+    ImageDesc im;
+    if (imgs.arr) {
+      while (b + 1 < imgs.B && imgs.arr[b + 1].gauss_off <= i) ++b;
+      im = imgs.arr[b];
+    } else {
+      im = imgs.one;
+    }
+    const float W = (float)im.W, H = (float)im.H;
+    const float u_lo = u_lo_arg > 0.f ? u_lo_arg : 1.0f / fmaxf(W, H);
+    const float p = pv[u];
+    float g = gv[u];
+    float lr = lr_c;
+    if (r == 0) {
+      g *= W;
+      lr = lr_mu;
+    } else if (r == 1) {
+      g *= H;
+      lr = lr_mu;
+    } else if (r == 2) {
+      lr = lr_theta;
+    } else if (r == 3 || r == 4) {
+      g = -g / (p * p);  // dL/du = -s^2 dL/ds with u = 1/s
+      lr = lr_u;
+    }
+    const float mm = b1 * mv[u] + (1.0f - b1) * g;
+    const float vn = b2 * vv[u] + (1.0f - b2) * g * g;
+    m[e] = mm;
+    v[e] = vn;
+    float np = p - lr * (mm / bc1) / (sqrtf(vn / bc2) + eps);
+    if (r == 2) np = fminf(fmaxf(np, 0.0f), 3.14159265358979323846f);
+    if (r == 3 || r == 4) np = fminf(fmaxf(np, u_lo), u_hi);
+    fit[e] = np;
+    rend[e] = to_render(r, np, W, H);
+  }
 }
 
 __global__ void step_increment_kernel(int32_t *step, const int64_t *skip) {
@@ -249,7 +268,9 @@ hipError_t launch_adam_lo(float *fit, float *rend, const float *grad, float *m, 
                           float lr_mu, float lr_theta, float lr_u, float lr_c, float b1, float b2,
                           float eps, float u_lo, float u_hi, hipStream_t s) {
   if (N > 0) {
-    adam_kernel<<<dim3((unsigned)((N + 255) / 256), (unsigned)(5 + n)), 256, 0, s>>>(
+    constexpr int per_block = kAdamThreads * kAdamItems;
+    adam_kernel<<<dim3((unsigned)((N + per_block - 1) / per_block), (unsigned)(5 + n)),
+                  kAdamThreads, 0, s>>>(
         fit, rend, grad, m, v, step, skip, N, n, imgs, lr_mu, lr_theta, lr_u, lr_c, b1, b2, eps,
         u_lo, u_hi);
     hipError_t e = hipGetLastError();
