@@ -248,11 +248,11 @@ KERNEL_SOURCES = {"raster_fwd": "raster_fwd.hip", "raster_bwd": "raster_bwd.hip"
 KERNEL_HEADERS = ("raster_tile.hpp", "raster_common.hpp")
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- "
-             "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0 --no-ssim --no-decode "
+             "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0 --large-iters 0 --no-ssim --no-decode "
              "--launch-config 0,0,1",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'raster|elementwise' -f csv "
              "-d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --steps 3 --warmup 1 "
-             "--no-cpu-baseline --no-context --batch-iters 0 --no-ssim --no-decode --launch-config 0,0,1",
+             "--no-cpu-baseline --no-context --batch-iters 0 --large-iters 0 --no-ssim --no-decode --launch-config 0,0,1",
     "write": "rocprofv3 --pmc WRITE_SIZE (otherwise as fetch) -d gpurun_out/pmc_write -o write",
     "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_copy_fetch -o cf -- "
                   "python3 bench.py --copy-calibration",
@@ -267,7 +267,7 @@ PROFILE_CMDS = {
     "valu": "rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_INSTS_VALU SQ_INSTS_LDS "
             "SQ_WAVES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE GRBM_COUNT --kernel-include-regex raster "
             "-f csv -d gpurun_out/pmc_valu -o valu -- python3 bench.py --steps 3 --warmup 1 "
-            "--no-cpu-baseline --no-context --batch-iters 0 --no-ssim --no-decode "
+            "--no-cpu-baseline --no-context --batch-iters 0 --large-iters 0 --no-ssim --no-decode "
             "--launch-config 0,0,1",
 }
 VALU_FILE = os.path.join(PROFILES, "valu_counters_raster_texture-2048x2048-n9-N100000.txt")
@@ -503,13 +503,15 @@ def single_pass_step(torch, nat, w, target, params, cap, steps, warmup, ref_fit,
     return dt / steps * 1e3, avg, roofline, same
 
 
-def batched_vs_plain(torch, dev, iters, count=64, single_pass=True):
-    """Uneven batch (H, W in {256, 512, 1024, 2048}, 5k-80k Gaussians): one BatchFitter vs the
-    same images fitted one after another by graph-captured PlainFitters, both with the same
-    iteration (single-pass L1 kernel, or the two-pass fused pair)."""
+def batched_vs_plain(torch, dev, iters, count=64, single_pass=True, wl=None):
+    """Uneven batch (H, W in {256, 512, 1024, 2048}, 5k-80k Gaussians), or the workloads wl: one
+    BatchFitter vs the same images fitted one after another by graph-captured PlainFitters, both
+    with the same iteration (single-pass L1 kernel, or the two-pass fused pair)."""
     from paper_2407_01866_amd import synth
     from paper_2407_01866_amd.fit import BatchFitter, PlainFitter
-    wl = synth.batch_workloads(count)
+    if wl is None:
+        wl = synth.batch_workloads(count)
+    count = len(wl)
     log(f"[bench] batch of {count} images: generating inputs")
     targets = [torch.from_numpy(w.target()).to(dev) for w in wl]
     params = [torch.from_numpy(w.gaussians()).to(dev) for w in wl]
@@ -546,6 +548,36 @@ def batched_vs_plain(torch, dev, iters, count=64, single_pass=True):
             "psnr_match": max(dps) <= 0.1 and sum(dps) / count <= 0.02}
 
 
+def large_config(torch, dev, iters, batch_iters, single_pass=True):
+    """The large configuration: fit iterations at 4096^2 with 500k Gaussians (sigma 0.5-8 px),
+    timed as graph replays after a dry run of the same trajectory, with their Gaussian-pixel
+    evaluation rate; and 16 images of 1024^2 with 30k Gaussians each fitted batched against one
+    after another."""
+    from paper_2407_01866_amd import _native as nat
+    from paper_2407_01866_amd import synth
+    from paper_2407_01866_amd.fit import PlainFitter
+    w = synth.workload(4)
+    log(f"[bench] {w.name}: generating inputs")
+    f = PlainFitter(torch.from_numpy(w.target()).to(dev), torch.from_numpy(w.gaussians()).to(dev),
+                    w.K, single_pass=single_pass)
+    init = f.snapshot()
+    e_fwd = []
+    for it in range(1, iters + 1):                 # dry run: sizes the pair buffer, counts work
+        f.advance_to(it, use_graph=False)
+        e_fwd.append(int(f.status()[nat.STAT_EVALS_FWD]))
+    f.restore(init)
+    dt = timed_fit(f, iters, torch)
+    ms = dt / iters * 1e3
+    plain = {"workload": w.name, "iterations": iters, "ms_per_iter": round(ms, 4),
+             "fit_iters_per_s": round(1e3 / ms, 2), "E_fwd": float(np.mean(e_fwd)),
+             "evals_per_s": float(np.mean(e_fwd)) / (ms * 1e-3), "psnr": round(f.psnr(), 3)}
+    log(f"[bench] {w.name}: {ms:.3f} ms per iteration")
+    del f
+    batch = batched_vs_plain(torch, dev, batch_iters, single_pass=single_pass,
+                             wl=synth.small_batch_workloads())
+    return {"plain_4096": plain, "batched_16x1024": batch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -557,6 +589,8 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=100,
                     help="iterations of the batched-vs-plain comparison (0 skips it)")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--large-iters", type=int, default=20,
+                    help="iterations of the large configuration's legs (0 skips them)")
     ap.add_argument("--no-ssim", action="store_true",
                     help="skip the L1 + SSIM loss measurement")
     ap.add_argument("--no-single-pass", action="store_true",
@@ -716,6 +750,10 @@ def main():
     if args.batch_iters > 0:
         batch = batched_vs_plain(torch, dev, args.batch_iters, args.batch_count,
                                  single_pass=not args.no_single_pass)
+    large = None
+    if args.large_iters > 0:
+        large = large_config(torch, dev, args.large_iters, 2 * args.large_iters,
+                             single_pass=not args.no_single_pass)
 
     two_pass_step = ("binning + render fused with the L1 loss + adjoint + gradient reduction + "
                      "Adam (HIP graph)" if fitter.fused else
@@ -757,7 +795,7 @@ def main():
                           "autotune_ms": {str(c): round(t * 1e3, 4) for c, t in tune_times.items()}},
         "roofline": head["roofline"],
         "two_pass": two_pass, "cpu_baseline": cpu, "ssim_step": ssim, "decode": decode,
-        "paper_context": ctx, "batched_vs_plain": batch,
+        "paper_context": ctx, "batched_vs_plain": batch, "large_config": large,
     }
     print(json.dumps(out), flush=True)
 
