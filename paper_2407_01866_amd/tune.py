@@ -4,7 +4,8 @@ Every candidate gives bit-identical results; only the time differs.  The tuner t
 graph-replayed iterations of the caller's own fitter under each candidate, restores the fitter's
 state after each trial, and leaves the fastest candidate set (the fitter's graph is re-captured
 under it).  Candidates: one workgroup per tile or a persistent grid of 4, 5, 6 or 8 workgroups
-per CU, each with and without the forward's candidate culling.
+per CU, each with and without the forward's candidate culling.  The single-pass fitting kernel
+always runs one workgroup per tile, so for a single-pass fitter only the culling switch is timed.
 """
 from __future__ import annotations
 
@@ -20,6 +21,7 @@ Config = Tuple[int, int, int]   # (persistent, wgs_per_cu, fwd_cull)
 DEFAULT_CANDIDATES: Tuple[Config, ...] = (
     (0, 0, 1), (0, 0, 0), (1, 4, 1), (1, 5, 1), (1, 6, 1), (1, 8, 1), (1, 0, 1),
 )
+SINGLE_PASS_CANDIDATES: Tuple[Config, ...] = ((0, 0, 1), (0, 0, 0))
 
 
 def set_config(cfg: Config) -> None:
@@ -49,7 +51,10 @@ def autotune(fitter, candidates: Optional[Sequence[Config]] = None, iters: int =
     """Times `fitter` (a PlainFitter or BatchFitter whose pair buffer is already sized) under each
     candidate; sets and returns the fastest, with every candidate's seconds per iteration.  The
     fitter's parameters, moments and step count are restored after every trial."""
-    cands: List[Config] = list(candidates or DEFAULT_CANDIDATES)
+    if candidates is None:
+        candidates = (SINGLE_PASS_CANDIDATES if getattr(fitter, "single_pass", False)
+                      else DEFAULT_CANDIDATES)
+    cands: List[Config] = list(candidates)
     state = fitter.snapshot()
     times: Dict[Config, float] = {}
     for c in cands:

@@ -100,3 +100,18 @@ def test_autotune_restores_fitter_state():
     assert best in times and len(times) == 2 and all(t > 0 for t in times.values())
     assert f.steps_done() == step0 and torch.equal(f.fit, fit0)
     assert nat.igs_get_launch_config().as_tuple() == best
+
+
+def test_autotune_of_a_single_pass_fitter_times_only_the_culling_switch():
+    from paper_2407_01866_amd.fit import PlainFitter
+    from paper_2407_01866_amd.tune import SINGLE_PASS_CANDIDATES, autotune
+    d = dev()
+    w = synth.workload(0)
+    f = PlainFitter(torch.from_numpy(w.target()).to(d), torch.from_numpy(w.gaussians()).to(d),
+                    w.K, headroom=3.0, single_pass=True)
+    f.advance_to(3, use_graph=False)
+    fit0, step0 = f.fit.clone(), f.steps_done()
+    best, times = autotune(f, iters=2, warmup=1)
+    assert set(times) == set(SINGLE_PASS_CANDIDATES) and best in times
+    assert f.steps_done() == step0 and torch.equal(f.fit, fit0)
+    nat.igs_set_launch_config(0, 0, 1)
