@@ -42,9 +42,12 @@ def _plain_outputs(p, tgt, H, W, K):
     gp2 = torch.empty_like(gp)
     r.render_l1_into(pt, torch.from_numpy(tgt).to(d), img2, loss, sv2)
     r.backward_l1_into(pt, sv2, gp2)
+    loss3 = torch.zeros(2, dtype=torch.float64, device=d)
+    gp3 = torch.empty_like(gp)
+    r.l1_grad_into(pt, torch.from_numpy(tgt).to(d), loss3, gp3, r.new_saved())
     torch.cuda.synchronize()
     assert int(r.status_of(sv)[nat.STAT_OVERFLOW]) == 0
-    return img, r.slots(sv), gp, img2, loss, gp2
+    return img, r.slots(sv), gp, img2, loss, gp2, loss3, gp3
 
 
 @pytest.mark.parametrize("H,W,n,N,K", [(512, 384, 3, 3000, 10), (200, 136, 9, 900, 16),
@@ -81,10 +84,16 @@ def test_launch_configs_batched_identical():
         g = torch.from_numpy(synth.gen_grad_image(5, 1, 1, n * br.P).reshape(-1)).to(d)
         gp = torch.empty_like(bp)
         br.backward_into(bp, imgs, g, sv, gp)
+        tg = br.pack_images([torch.from_numpy(synth.gen_image(70 + b, H, W, n, 10))
+                             for b, (H, W, _) in enumerate(sizes)])
+        loss = torch.zeros((len(sizes), 2), dtype=torch.float64, device=d)
+        gp1 = torch.empty_like(bp)
+        br.l1_grad_into(bp, tg, loss, gp1, br.new_saved())
         torch.cuda.synchronize()
-        outs.append((imgs, gp))
-    for cfg, (a, b) in zip(CONFIGS[1:], outs[1:]):
-        assert torch.equal(a, outs[0][0]) and torch.equal(b, outs[0][1]), cfg
+        outs.append((imgs, gp, loss, gp1))
+    for cfg, got in zip(CONFIGS[1:], outs[1:]):
+        for a, b in zip(got, outs[0]):
+            assert torch.equal(a, b), cfg
 
 
 def test_autotune_restores_fitter_state():
@@ -100,6 +109,8 @@ def test_autotune_restores_fitter_state():
     assert best in times and len(times) == 2 and all(t > 0 for t in times.values())
     assert f.steps_done() == step0 and torch.equal(f.fit, fit0)
     assert nat.igs_get_launch_config().as_tuple() == best
+
+
 
 
 def test_autotune_of_a_single_pass_fitter_times_only_the_culling_switch():
