@@ -31,8 +31,13 @@ def lib():
         L.orc_num_tiles.restype = ci
         L.orc_tile_lists.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, _i32p, ci, _i64p, vp, ctypes.c_int64]
         L.orc_tile_lists.restype = ci
-        L.orc_render_tiles.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, ci, _i32p, ci, vp, vp, vp, vp, vp, vp, ci]
+        L.orc_render_tiles.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, ci, _i32p, ci, vp, vp, vp, vp,
+                                       vp, vp, ci, ctypes.c_double, vp]
         L.orc_render_tiles.restype = ci
+        L.orc_rank_pixel.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, ci, ci, vp, vp, vp, ci]
+        L.orc_rank_pixel.restype = ci
+        L.orc_blend_set.argtypes = [_f64p, ci, ci, ci, ci, _i32p, ci, _f64p]
+        L.orc_blend_set.restype = ci
         L.orc_render_dense.argtypes = [_f64p, ci, ci, ci, ci, ci, ci, ci, vp, ci]
         L.orc_render_dense.restype = ci
         L.orc_max_threads.argtypes = []
@@ -76,11 +81,22 @@ def tile_lists(params, H, W, tile=16, tiles: Optional[Sequence[int]] = None):
     return counts, lists[: int(counts.sum())]
 
 
+# Unit roundoff of float32, and the multiple of it times M (orc's rank_scale) that bounds the error
+# of q = |e|^2 evaluated in float32 from float32 rotation-scale rows and offsets: each component
+# e_a carries at most ~4 roundings of its two products' magnitudes (the two inputs, the product,
+# the sum), squaring doubles that to ~8 of M, and the final square and sum add 2 more; 16 leaves
+# room for second-order terms.
+U32 = 2.0 ** -24
+TIE_GAMMA = 16.0 * U32
+
+
 def render_tiles(params, H, W, K, tile=16, tiles=None, grad_img=None, want=("img", "topk", "qsel"),
-                 nthreads=0):
+                 nthreads=0, gamma=TIE_GAMMA):
     """Render the listed tiles; returns dict with compact per-tile arrays and, when ``grad_img``
     ([n][H][W]) is given, ``grad`` [5+n][N] holding the listed tiles' contributions and
-    ``grad_abs`` [5+n][N], the sums of the terms' magnitudes before cancellation."""
+    ``grad_abs`` [5+n][N], the sums of the terms' magnitudes before cancellation.  With "margin"
+    in ``want``: per pixel, how far the retained set is from changing when every q is perturbed
+    by up to gamma M (non-positive: a near tie, where several selections are correct)."""
     p, N, n = _prep(params)
     T = num_tiles(H, W, tile)
     t = np.arange(T, dtype=np.int32) if tiles is None else np.ascontiguousarray(tiles, dtype=np.int32)
@@ -89,6 +105,7 @@ def render_tiles(params, H, W, K, tile=16, tiles=None, grad_img=None, want=("img
     img = np.zeros((len(t), n, tp)) if "img" in want else None
     topk = np.zeros((len(t), tp, K), dtype=np.int32) if "topk" in want else None
     qsel = np.zeros((len(t), tp, K + 1)) if "qsel" in want else None
+    margin = np.zeros((len(t), tp)) if "margin" in want else None
     g = None
     grad = gabs = None
     if grad_img is not None:
@@ -98,7 +115,8 @@ def render_tiles(params, H, W, K, tile=16, tiles=None, grad_img=None, want=("img
         grad = np.zeros((5 + n, N))
         gabs = np.zeros((5 + n, N))
     rc = lib().orc_render_tiles(p, N, n, H, W, K, tile, tile, t, len(t), _ptr(img), _ptr(topk),
-                                _ptr(qsel), _ptr(g), _ptr(grad), _ptr(gabs), nthreads)
+                                _ptr(qsel), _ptr(g), _ptr(grad), _ptr(gabs), nthreads, gamma,
+                                _ptr(margin))
     if rc != 0:
         raise RuntimeError(f"orc_render_tiles failed: {rc}")
     out["tiles"] = t
@@ -108,6 +126,8 @@ def render_tiles(params, H, W, K, tile=16, tiles=None, grad_img=None, want=("img
         out["topk"] = topk
     if qsel is not None:
         out["qsel"] = qsel
+    if margin is not None:
+        out["margin"] = margin
     if grad is not None:
         out["grad"] = grad
         out["grad_abs"] = gabs
@@ -128,19 +148,47 @@ def _tiles_to_planar(arr: np.ndarray, tiles: np.ndarray, H: int, W: int, tile: i
     return out
 
 
-def render(params, H, W, K, tile=16, grad_img=None, nthreads=0):
+def render(params, H, W, K, tile=16, grad_img=None, nthreads=0, gamma=TIE_GAMMA):
     """Full-image oracle: image [n][H][W], topk [H][W][K] (Gaussian ids, -1 unused),
-    qsel [H][W][K+1] and, with ``grad_img``, the full gradient [5+n][N]."""
-    r = render_tiles(params, H, W, K, tile, None, grad_img, nthreads=nthreads)
+    qsel [H][W][K+1], margin [H][W] (see render_tiles) and, with ``grad_img``, the full gradient
+    [5+n][N]."""
+    r = render_tiles(params, H, W, K, tile, None, grad_img, want=("img", "topk", "qsel", "margin"),
+                     nthreads=nthreads, gamma=gamma)
     t = r["tiles"]
     out = {
         "img": _tiles_to_planar(r["img"], t, H, W, tile),
         "topk": np.moveaxis(_tiles_to_planar(np.moveaxis(r["topk"], 2, 1), t, H, W, tile, -1), 0, 2),
         "qsel": np.moveaxis(_tiles_to_planar(np.moveaxis(r["qsel"], 2, 1), t, H, W, tile, np.inf), 0, 2),
+        "margin": _tiles_to_planar(r["margin"][:, None, :], t, H, W, tile, np.inf)[0],
     }
     if "grad" in r:
         out["grad"] = r["grad"]
         out["grad_abs"] = r["grad_abs"]
+    return out
+
+
+def rank_pixel(params, H, W, h, w, tile=16):
+    """Every member of the hit set of pixel (h, w)'s tile ranked there by (q, index):
+    (idx int32, q, M) in rank order (M: the rounding scale of q, see render_tiles)."""
+    p, N, n = _prep(params)
+    m = lib().orc_rank_pixel(p, N, n, H, W, tile, tile, h, w, None, None, None, 0)
+    if m < 0:
+        raise RuntimeError(f"orc_rank_pixel failed: {m}")
+    idx = np.zeros(max(m, 1), dtype=np.int32)
+    q = np.zeros(max(m, 1))
+    mb = np.zeros(max(m, 1))
+    lib().orc_rank_pixel(p, N, n, H, W, tile, tile, h, w, _ptr(idx), _ptr(q), _ptr(mb), m)
+    return idx[:m], q[:m], mb[:m]
+
+
+def blend_set(params, h, w, ids) -> np.ndarray:
+    """Eq. 5 over the given Gaussians at the centre of pixel (h, w): colour [n]."""
+    p, N, n = _prep(params)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    out = np.zeros(n)
+    rc = lib().orc_blend_set(p, N, n, h, w, ids, len(ids), out)
+    if rc != 0:
+        raise RuntimeError(f"orc_blend_set failed: {rc}")
     return out
 
 

@@ -47,6 +47,7 @@
 
 typedef struct {
     double q;
+    double mb; /* rounding scale of q, see rank_scale */
     int32_t idx;
 } cand_t;
 
@@ -90,6 +91,25 @@ static double quad_form(double mx, double my, double th, double s1, double s2, d
     if (e1_out) *e1_out = e1;
     if (e2_out) *e2_out = e2;
     return e1 * e1 / (s1 * s1) + e2 * e2 / (s2 * s2);
+}
+
+/*
+ * Scale of the rounding error of q when it is evaluated in a narrower format as |e|^2 with
+ * e = (cos dx + sin dy, -sin dx + cos dy) / s: the same squares taken over the magnitudes of the
+ * products before they cancel, M = (|cos dx| + |sin dy|)^2 / s1^2 + (|sin dx| + |cos dy|)^2 / s2^2
+ * (M >= q).  Each product, sum and input rounding perturbs e_a by a few units of the last place of
+ * |cos dx| + |sin dy| (resp. |sin dx| + |cos dy|), so such an evaluation of q is accurate to a small
+ * multiple of the unit roundoff times M; the tests use it to tell a selection that a float32
+ * ranking decides for certain from a near tie, where either answer is correct (Sec. 3.2 ranks by
+ * value; which of two nearly equal values is larger is then a rounding matter).
+ */
+static double rank_scale(double th, double s1, double s2, double px, double py, double mx,
+                         double my) {
+    double c = cos(th), s = sin(th);
+    double dx = px - mx, dy = py - my;
+    double a = fabs(c * dx) + fabs(s * dy);
+    double b = fabs(s * dx) + fabs(c * dy);
+    return a * a / (s1 * s1) + b * b / (s2 * s2);
 }
 
 int orc_num_tiles(int H, int W, int th, int tw) {
@@ -149,6 +169,11 @@ int orc_tile_lists(const double *params, int N, int n, int H, int W, int th, int
  *   topk  [ntiles][th*tw][K]   Gaussian indices of S_j^K(x) in rank order, -1 where unused
  *   qsel  [ntiles][th*tw][K+1] q of the ranked candidates 1..K+1 (+inf where absent); the gap
  *                              q_(K+1) - q_(K) measures how close the selection is to a tie
+ *   margin [ntiles][th*tw]     with gamma: min over the members j left out of
+ *                              (q_j - gamma M_j) minus max over the retained i of
+ *                              (q_i + gamma M_i) (M: rank_scale); +inf when every member is kept.
+ *                              If each member's q is known only to within gamma M, a positive
+ *                              margin means the retained set is still determined
  * Adjoint (Sec. 3.3): with g = grad_img[:, h, w] (full-size planar [n][H][W]) the contributions of
  * the listed tiles' pixels are added into grad_params [5+n][N] (caller zeroes it).  Gradients are
  * taken with S_j and S_j^K(x) held fixed.
@@ -160,7 +185,8 @@ int orc_tile_lists(const double *params, int N, int n, int H, int W, int th, int
  */
 int orc_render_tiles(const double *params, int N, int n, int H, int W, int K, int th, int tw,
                      const int32_t *tiles, int ntiles, double *img, int32_t *topk, double *qsel,
-                     const double *grad_img, double *grad_params, double *grad_abs, int nthreads) {
+                     const double *grad_img, double *grad_params, double *grad_abs, int nthreads,
+                     double gamma, double *margin) {
     if (N < 0 || n < 1 || H < 1 || W < 1 || K < 1 || th < 1 || tw < 1 || ntiles < 0) return ORC_EINVAL;
     int T = orc_num_tiles(H, W, th, tw);
     for (int t = 0; t < ntiles; ++t)
@@ -211,6 +237,7 @@ int orc_render_tiles(const double *params, int N, int n, int H, int W, int K, in
                     for (int k = 0; k < K; ++k) topk[((size_t)t * tp + p) * K + k] = -1;
                 if (qsel)
                     for (int k = 0; k <= K; ++k) qsel[((size_t)t * tp + p) * (K + 1) + k] = INFINITY;
+                if (margin) margin[(size_t)t * tp + p] = INFINITY;
                 if (!inside || m == 0) continue;
                 double px = w + 0.5, py = h + 0.5;
                 /* rank every member of S_j at this pixel by (q, index) and keep the first K */
@@ -219,9 +246,26 @@ int orc_render_tiles(const double *params, int N, int n, int H, int W, int K, in
                     cand[a].q = quad_form(P(params, N, 0, i), P(params, N, 1, i), P(params, N, 2, i),
                                           P(params, N, 3, i), P(params, N, 4, i), px, py, NULL, NULL);
                     cand[a].idx = i;
+                    cand[a].mb = margin ? rank_scale(P(params, N, 2, i), P(params, N, 3, i),
+                                                     P(params, N, 4, i), px, py, P(params, N, 0, i),
+                                                     P(params, N, 1, i))
+                                        : 0.0;
                 }
                 qsort(cand, (size_t)m, sizeof(cand_t), cand_cmp);
                 int keff = m < K ? m : K;
+                if (margin && m > K) {
+                    double hi_in = -INFINITY, lo_out = INFINITY;
+                    for (int a = 0; a < m; ++a) {
+                        if (a < keff) {
+                            double v = cand[a].q + gamma * cand[a].mb;
+                            if (v > hi_in) hi_in = v;
+                        } else {
+                            double v = cand[a].q - gamma * cand[a].mb;
+                            if (v < lo_out) lo_out = v;
+                        }
+                    }
+                    margin[(size_t)t * tp + p] = lo_out - hi_in;
+                }
                 if (topk)
                     for (int k = 0; k < keff; ++k) topk[((size_t)t * tp + p) * K + k] = cand[k].idx;
                 if (qsel)
@@ -355,6 +399,74 @@ int orc_render_dense(const double *params, int N, int n, int H, int W, int K, in
         free(cand);
     }
     return status;
+}
+
+/*
+ * Every member of the hit set S_j of the tile holding pixel (h, w), ranked at the pixel centre by
+ * (q, index) as in orc_render_tiles: idx, q and M (rank_scale) of each, in rank order.  Returns
+ * |S_j| (only the first cap entries are written) or a negative error.
+ */
+int orc_rank_pixel(const double *params, int N, int n, int H, int W, int th, int tw, int h, int w,
+                   int32_t *idx, double *q, double *mb, int cap) {
+    (void)n;
+    if (N < 0 || H < 1 || W < 1 || th < 1 || tw < 1 || h < 0 || h >= H || w < 0 || w >= W ||
+        cap < 0)
+        return ORC_EINVAL;
+    int tiles_x = (W + tw - 1) / tw;
+    int x0, x1, y0, y1;
+    tile_rect((h / th) * tiles_x + w / tw, H, W, th, tw, &x0, &x1, &y0, &y1);
+    cand_t *cand = (cand_t *)malloc(sizeof(cand_t) * (size_t)(N > 0 ? N : 1));
+    if (!cand) return ORC_ENOMEM;
+    double px = w + 0.5, py = h + 0.5;
+    int m = 0;
+    for (int i = 0; i < N; ++i) {
+        double mx = P(params, N, 0, i), my = P(params, N, 1, i), thv = P(params, N, 2, i);
+        double s1 = P(params, N, 3, i), s2 = P(params, N, 4, i);
+        if (!circle_meets_rect(mx, my, s1, s2, x0, x1, y0, y1)) continue;
+        cand[m].q = quad_form(mx, my, thv, s1, s2, px, py, NULL, NULL);
+        cand[m].mb = rank_scale(thv, s1, s2, px, py, mx, my);
+        cand[m].idx = i;
+        ++m;
+    }
+    qsort(cand, (size_t)m, sizeof(cand_t), cand_cmp);
+    for (int a = 0; a < m && a < cap; ++a) {
+        idx[a] = cand[a].idx;
+        q[a] = cand[a].q;
+        mb[a] = cand[a].mb;
+    }
+    free(cand);
+    return m;
+}
+
+/*
+ * Eq. 5 over a given set of Gaussians at the pixel centre (w + 1/2, h + 1/2): the normalized blend
+ * sum_k exp(-(q_k - q_min)/2) c_k / sum_k exp(-(q_k - q_min)/2) into out[n] (0 for an empty set).
+ */
+int orc_blend_set(const double *params, int N, int n, int h, int w, const int32_t *ids, int k,
+                  double *out) {
+    if (N < 0 || n < 1 || k < 0) return ORC_EINVAL;
+    for (int a = 0; a < k; ++a)
+        if (ids[a] < 0 || ids[a] >= N) return ORC_EINVAL;
+    for (int ch = 0; ch < n; ++ch) out[ch] = 0.0;
+    if (k == 0) return ORC_OK;
+    double px = w + 0.5, py = h + 0.5, qmin = INFINITY;
+    double *qs = (double *)malloc(sizeof(double) * (size_t)k);
+    if (!qs) return ORC_ENOMEM;
+    for (int a = 0; a < k; ++a) {
+        int i = ids[a];
+        qs[a] = quad_form(P(params, N, 0, i), P(params, N, 1, i), P(params, N, 2, i),
+                          P(params, N, 3, i), P(params, N, 4, i), px, py, NULL, NULL);
+        if (qs[a] < qmin) qmin = qs[a];
+    }
+    double Z = 0.0;
+    for (int a = 0; a < k; ++a) {
+        double wt = exp(-0.5 * (qs[a] - qmin));
+        Z += wt;
+        for (int ch = 0; ch < n; ++ch) out[ch] += wt * P(params, N, 5 + ch, ids[a]);
+    }
+    for (int ch = 0; ch < n; ++ch) out[ch] /= Z;
+    free(qs);
+    return ORC_OK;
 }
 
 int orc_max_threads(void) {

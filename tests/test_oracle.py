@@ -361,6 +361,69 @@ def test_adam_first_step_moves_by_learning_rate():
     np.testing.assert_allclose(newp, fp - lrs[:, None] * np.sign(g), rtol=1e-6)
 
 
+def _adam_vs_torch(step_fn, steps=6, seed=3):
+    """Largest difference between ``step_fn`` (the oracle's Adam signature) and torch.optim.Adam
+    followed by the fitter's clamps (theta to [0, pi], Sec. 3.1; 1/s to [1/max(H, W), 4]) over
+    ``steps`` steps with per-row learning rates (Sec. 4.1) and gradients that change sign and
+    size every step.  Parameters start next to every bound with gradients that push across it."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(seed)
+    n, N, H, W = 3, 12, 40, 64
+    p = rng.uniform(0.2, 0.8, (5 + n, N))
+    p[2] = rng.uniform(0.5, 2.5, N)
+    p[3:5] = rng.uniform(0.1, 3.0, (2, N))
+    # theta at 0 and pi, 1/s at 4 and at 1/max(H, W), each pushed outward by the first gradients
+    p[2, 0], p[2, 1] = 1e-4, math.pi - 1e-4
+    p[3, 2], p[4, 3] = 4.0 - 1e-4, 1.0 / W + 1e-5
+    lrs = fitref.row_lrs(n)
+    grads = rng.standard_normal((steps, 5 + n, N)) * rng.uniform(0.1, 10.0, (steps, 5 + n, 1))
+    grads[:, 2, 0], grads[:, 2, 1] = 1.0, -1.0
+    grads[:, 3, 2], grads[:, 4, 3] = -1.0, 1.0
+    rows = [torch.tensor(p[r], dtype=torch.float64, requires_grad=True) for r in range(5 + n)]
+    opt = torch.optim.Adam([{"params": [rows[r]], "lr": float(lrs[r])} for r in range(5 + n)])
+    q, m, v = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    worst = 0.0
+    for t in range(steps):
+        for r in range(5 + n):
+            rows[r].grad = torch.tensor(grads[t, r], dtype=torch.float64)
+        opt.step()
+        with torch.no_grad():
+            rows[2].clamp_(0.0, math.pi)
+            rows[3].clamp_(1.0 / max(H, W), 4.0)
+            rows[4].clamp_(1.0 / max(H, W), 4.0)
+        q, m, v = step_fn(q, grads[t], m, v, t + 1, lrs, H=H, W=W)
+        ref = np.stack([x.detach().numpy() for x in rows])
+        worst = max(worst, float(np.abs(q - ref).max()))
+    return worst, q
+
+
+def test_adam_matches_torch_adam_with_clamps_over_several_steps():
+    """The Adam reference (Sec. 4.1; beta1, beta2, eps as PyTorch's defaults) against PyTorch's own
+    optimizer over six steps, with the clamps of Sec. 3.1 reached in both directions."""
+    worst, q = _adam_vs_torch(fitref.adam_step)
+    assert worst < 1e-13, worst
+    assert q[2, 0] == 0.0 and q[2, 1] == math.pi
+    assert q[3, 2] == 4.0 and q[4, 3] == 1.0 / 64
+
+
+def test_adam_pin_catches_planted_mistakes():
+    """The torch comparison above fails for swapped betas, a missing clamp, a missing bias
+    correction and a wrong eps, each planted in the oracle's Adam."""
+    import functools
+    from unittest import mock
+
+    swapped = functools.partial(fitref.adam_step, b1=0.999, b2=0.9)
+    assert _adam_vs_torch(swapped)[0] > 1e-6
+    with mock.patch.object(fitref.np, "clip", lambda x, lo, hi: x):
+        assert _adam_vs_torch(fitref.adam_step)[0] > 1e-6
+
+    def no_bias_correction(p, g, m, v, step, lrs, **kw):
+        return fitref.adam_step(p, g, m, v, 10 ** 6, lrs, **kw)
+    assert _adam_vs_torch(no_bias_correction)[0] > 1e-6
+
+    assert _adam_vs_torch(functools.partial(fitref.adam_step, eps=1e-4))[0] > 1e-6
+
+
 def test_paper_constants_fix_parameter_count():
     c = json.load(open(os.path.join(GOLD, "paper_constants.json")))
     H, W, n = c["restoration_budget"]["image"]
