@@ -497,3 +497,92 @@ def test_gradient_conditioning_bounds_the_gradient():
     assert np.all(o["grad_abs"] >= np.abs(o["grad"]) * (1 - 1e-12))
     o = cref.render(p, H, W, 6, grad_img=np.abs(g))
     np.testing.assert_allclose(o["grad_abs"][5:], o["grad"][5:], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------- near-tie margin
+
+
+def test_margin_without_rounding_is_the_selection_gap():
+    """gamma = 0: the margin is q_(K+1) - q_(K), the gap the ranking has to decide (Sec. 3.2)."""
+    rng = np.random.default_rng(41)
+    H, W, n, K = 48, 40, 3, 6
+    p = make_params(rng, 150, n, H, W)
+    o = cref.render(p, H, W, K, gamma=0.0)
+    gap = o["qsel"][..., K] - o["qsel"][..., K - 1]
+    full = np.isfinite(o["qsel"][..., K])
+    np.testing.assert_array_equal(o["margin"][full], gap[full])
+    assert np.all(np.isinf(o["margin"][~full]))
+
+
+def test_rank_scale_is_q_for_axis_aligned_gaussians():
+    """For theta = 0 nothing cancels in e = R^T d / s, so the rounding scale M equals q; at
+    theta = pi/4 on the diagonal through the mean, e1 = sqrt(2)|d| and e2 = 0 while
+    M = 2 dx^2 (1/s1^2 + 1/s2^2)."""
+    H, W = 32, 32
+    p = np.array([[15.3], [16.8], [0.0], [3.0], [5.0], [0.2], [0.4], [0.6]])
+    idx, q, mb = cref.rank_pixel(p, H, W, 20, 9)
+    assert idx.tolist() == [0]
+    assert mb[0] == pytest.approx(q[0], rel=1e-15)
+    p2 = np.array([[16.5], [16.5], [math.pi / 4], [3.0], [5.0], [0.2], [0.4], [0.6]])
+    idx, q, mb = cref.rank_pixel(p2, H, W, 20, 20)
+    dx = 20.5 - 16.5
+    assert q[0] == pytest.approx(2 * dx * dx / 9.0, rel=1e-14)
+    assert mb[0] == pytest.approx(2 * dx * dx * (1 / 9.0 + 1 / 25.0), rel=1e-14)
+
+
+def test_rank_pixel_and_blend_set_reproduce_the_render():
+    """The pixel ranking lists S_j in the render's order (its first K are the render's top-K with
+    the same q) and the blend over that set is the rendered colour; one Gaussian blends to its
+    colour, two to the logistic form of Eq. 5."""
+    rng = np.random.default_rng(42)
+    H, W, n, K = 40, 56, 3, 5
+    p = make_params(rng, 120, n, H, W)
+    o = cref.render(p, H, W, K)
+    counts, lists = cref.tile_lists(p, H, W)
+    for h, w in [(0, 0), (17, 33), (39, 55), (25, 4)]:
+        idx, q, mb = cref.rank_pixel(p, H, W, h, w)
+        t = (h // 16) * ((W + 15) // 16) + w // 16
+        assert sorted(idx.tolist()) == lists[counts[:t].sum():counts[:t + 1].sum()].tolist()
+        k = min(K, len(idx))
+        assert idx[:k].tolist() == o["topk"][h, w, :k].tolist()
+        np.testing.assert_allclose(q[: k + 1], o["qsel"][h, w, : k + 1][np.isfinite(o["qsel"][h, w, : k + 1])], rtol=1e-15)
+        assert np.all(mb >= q * (1 - 1e-15))
+        np.testing.assert_allclose(cref.blend_set(p, h, w, idx[:k]), o["img"][:, h, w], rtol=1e-13)
+        assert np.array_equal(cref.blend_set(p, h, w, idx[:1]), p[5:, idx[0]])
+        a, b = idx[0], idx[1]
+        sig = 1.0 / (1.0 + math.exp(-(q[1] - q[0]) / 2))
+        np.testing.assert_allclose(cref.blend_set(p, h, w, [a, b]),
+                                   p[5:, b] + (p[5:, a] - p[5:, b]) * sig, rtol=1e-13)
+
+
+def test_positive_margin_means_perturbations_keep_the_set():
+    """Brute force: moving every candidate's q by up to gamma M (random signs and sizes, and the
+    worst case) never changes the retained set where the margin is positive, and the worst case
+    does change it where the margin is negative."""
+    rng = np.random.default_rng(43)
+    H, W, n, K = 32, 32, 3, 4
+    p = make_params(rng, 90, n, H, W)
+    gam = 1e-2                                  # large, so that both cases occur
+    o = cref.render(p, H, W, K, gamma=gam)
+    seen_pos = seen_neg = 0
+    for h in range(0, H, 3):
+        for w in range(0, W, 3):
+            idx, q, mb = cref.rank_pixel(p, H, W, h, w)
+            if len(idx) <= K:
+                assert np.isinf(o["margin"][h, w])
+                continue
+            base = set(idx[:K].tolist())
+            worst = q.copy()
+            worst[:K] += gam * mb[:K]
+            worst[K:] -= gam * mb[K:]
+            worst_set = set(idx[np.lexsort((idx, worst))[:K]].tolist())
+            if o["margin"][h, w] > 0:
+                seen_pos += 1
+                for _ in range(5):
+                    pert = q + gam * mb * rng.uniform(-1, 1, len(q))
+                    assert set(idx[np.lexsort((idx, pert))[:K]].tolist()) == base
+                assert worst_set == base
+            elif o["margin"][h, w] < 0:
+                seen_neg += 1
+                assert worst_set != base
+    assert seen_pos > 10 and seen_neg > 3, (seen_pos, seen_neg)
