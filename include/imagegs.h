@@ -24,6 +24,11 @@
  *        status[4]  E_fwd = sum over tiles of |S_j| times the tile's pixel count: the (pixel,
  *                   candidate) evaluations the render performed
  *        status[5]  E_bwd = sum over pixels of the number of retained Gaussians, min(K, |S_j|)
+ *        status[6]  1 if a gradient derived from this render must not be applied: status[1] is
+ *                   set, or the call saved 16-bit top-K slots for a separate adjoint (igs_render
+ *                   with `saved`, igs_render_l1 and their batched forms) and status[3] is set.
+ *                   igs_render_l1_grad keeps its slots on chip at full width, so a long hit set
+ *                   does not set it there.  Meant as the skip_flag of igs_adam_step.
  *    The caller reads it asynchronously (e.g. a copy to pinned memory) before trusting outputs.
  *  - Parameters are float32 structure-of-arrays [5+n][N] (Eq. 3: p_i = (mu, theta, s, c)),
  *    rows in this order:

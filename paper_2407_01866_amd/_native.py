@@ -24,7 +24,8 @@ IGS_TILE = 16
 IGS_STATUS_WORDS = 8
 
 # status block words (int64 at byte 0 of the saved state)
-STAT_PAIRS, STAT_OVERFLOW, STAT_MAX_LIST, STAT_SLOT_OVERFLOW, STAT_EVALS_FWD, STAT_EVALS_BWD = range(6)
+(STAT_PAIRS, STAT_OVERFLOW, STAT_MAX_LIST, STAT_SLOT_OVERFLOW, STAT_EVALS_FWD, STAT_EVALS_BWD,
+ STAT_SKIP) = range(7)
 
 EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "igs_saved_offsets",
             "igs_render",

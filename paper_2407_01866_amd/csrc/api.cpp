@@ -280,7 +280,7 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
                              d.digit_bits, hist, hist_off, static_cast<uint32_t *>(scan_tmp), s,
                              true, true));
     IGS_HIP(launch_resolve_ranges(src, pair_gid, keys, status, d.cap, vals, ranges, s));
-    IGS_HIP(launch_tile_stats(ranges, d.T, imgs, d.K, status, s));
+    IGS_HIP(launch_tile_stats(ranges, d.T, imgs, d.K, raster, status, s));
     if (batched) {
       // largest-first queue: tiles by descending |S_j| (16-bit keys, stable, so ties keep the
       // tile order)

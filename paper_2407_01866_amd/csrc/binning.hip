@@ -230,6 +230,7 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
     const int64_t P = o + (int64_t)c;
     status[kStatPairs] = P;
     status[kStatOverflow] = P > cap ? 1 : 0;
+    status[kStatSkip] = P > cap ? 1 : 0;
   }
   const bool active = c != 0 && o + (int64_t)c <= cap;
   const ImageDesc im = imgs.by_gauss(ii);
@@ -303,12 +304,14 @@ __global__ __launch_bounds__(kThreads) void resolve_ranges_kernel(
 }
 
 // Per-render statistics from the tile ranges: the largest |S_j|, whether any exceeds the 16-bit
-// slot range, E_fwd = sum_j |S_j| times the tile's pixel count and E_bwd = sum_j min(K, |S_j|)
+// slot range (which also marks the gradient as unusable when the render saves 16-bit slots for a
+// separate adjoint: slots16), E_fwd = sum_j |S_j| times the tile's pixel count and E_bwd = sum_j min(K, |S_j|)
 // times the tile's pixel count.  Every block reduces its tiles and adds them with 64-bit integer
 // atomics (exact and order independent) into the status block, zeroed beforehand.
 constexpr int kStatThreads = 256;
 __global__ __launch_bounds__(kStatThreads) void tile_stats_kernel(const int2 *__restrict__ ranges,
                                                                   int T, Images imgs, int K,
+                                                                  int slots16,
                                                                   int64_t *__restrict__ status) {
   __shared__ unsigned long long s_max[kStatThreads / 64], s_ef[kStatThreads / 64],
       s_eb[kStatThreads / 64];
@@ -348,7 +351,10 @@ __global__ __launch_bounds__(kStatThreads) void tile_stats_kernel(const int2 *__
     }
     unsigned long long *st = reinterpret_cast<unsigned long long *>(status);
     atomicMax(&st[kStatMaxList], mx);
-    if (mx > 0xFFFF) atomicMax(&st[kStatSlotOverflow], 1ull);
+    if (mx > 0xFFFF) {
+      atomicMax(&st[kStatSlotOverflow], 1ull);
+      if (slots16) atomicMax(&st[kStatSkip], 1ull);
+    }
     atomicAdd(&st[kStatEvalsFwd], ef);
     atomicAdd(&st[kStatEvalsBwd], eb);
   }
@@ -431,11 +437,11 @@ hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uin
   return hipGetLastError();
 }
 
-hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K,
+hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K, bool slots16,
                              int64_t *status, hipStream_t s) {
   if (T <= 0) return hipSuccess;
-  tile_stats_kernel<<<(T + kStatThreads - 1) / kStatThreads, kStatThreads, 0, s>>>(ranges, T, imgs,
-                                                                                 K, status);
+  tile_stats_kernel<<<(T + kStatThreads - 1) / kStatThreads, kStatThreads, 0, s>>>(
+      ranges, T, imgs, K, slots16 ? 1 : 0, status);
   return hipGetLastError();
 }
 

@@ -23,7 +23,9 @@ enum StatusWord {
   kStatMaxList = 2,
   kStatSlotOverflow = 3,
   kStatEvalsFwd = 4,
-  kStatEvalsBwd = 5
+  kStatEvalsBwd = 5,
+  kStatSkip = 6  // the render's gradient must not be applied (pair overflow, or 16-bit slots
+                 // that cannot address a hit set)
 };
 
 // Radix sort geometry.
@@ -161,7 +163,9 @@ hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
 hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
                                 const uint32_t *keys, const int64_t *status, int64_t cap,
                                 uint32_t *vals, int2 *ranges, hipStream_t s);
-hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K,
+// slots16: the render saves 16-bit top-K slots for a separate adjoint, so a hit set longer than
+// 65535 also sets the status block's skip word.
+hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K, bool slots16,
                              int64_t *status, hipStream_t s);
 // Sort keys for the largest-first tile queue: key = 0xFFFF - min(|S_j|, 0xFFFF), value = tile;
 // also writes T to *count.

@@ -71,7 +71,10 @@ __attribute__((amdgpu_waves_per_eu(bwd_min_waves(NC, KT)))) void raster_bwd_kern
   {
     const uint16_t *__restrict__ slots = slots_all + (int64_t)K * im.pix_off + pix;
 #pragma unroll
-    for (int k = 0; k < KT; ++k) sl[k] = (inside && k < K) ? (int)slots[(int64_t)k * HW] : 0xFFFF;
+    for (int k = 0; k < KT; ++k) {
+      const int v = (inside && k < K) ? (int)slots[(int64_t)k * HW] : (int)kEmptySlot;
+      sl[k] = v == (int)kEmptySlot ? -1 : v;
+    }
     const float2 ax = inside ? aux_all[im.pix_off + pix] : make_float2(0.f, 0.f);
     float gv[NC];
     float gc = 0.f;

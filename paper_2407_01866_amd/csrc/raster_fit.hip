@@ -69,7 +69,7 @@ __attribute__((amdgpu_waves_per_eu(fit_min_waves(NC, KT)))) void raster_fit_kern
 #pragma unroll
   for (int r = 0; r < ROW; ++r) row[r] = 0.f;
 #pragma unroll
-  for (int k = 0; k < KT; ++k) sl[k] = kEmptySlot;
+  for (int k = 0; k < KT; ++k) sl[k] = -1;  // the slots never leave the workgroup: full width
   if (inside) {
     const int64_t pix = (int64_t)py * W + px;
     const float *__restrict__ target = target_all + (int64_t)n * im.pix_off + pix;
@@ -122,7 +122,7 @@ __attribute__((amdgpu_waves_per_eu(fit_min_waves(NC, KT)))) void raster_fit_kern
     row[NC + 2] = invZ;
 #pragma unroll
     for (int k = 0; k < KT; ++k)
-      if (k < K && k < keff && ts[k] >= 0) sl[k] = min(ts[k], 0xFFFF);
+      if (k < K && k < keff && ts[k] >= 0) sl[k] = ts[k];
   }
   __syncthreads();  // the forward's LDS is dead
   store_px_row<NC>(smem, row);

@@ -381,7 +381,7 @@ __device__ __forceinline__ void store_px_row(unsigned char *smem, const float (&
         make_float4(row[r], row[r + 1], row[r + 2], row[r + 3]);
 }
 
-// The tile's records: sl[k] are the calling lane's retained slots (0xFFFF = none), the pixel
+// The tile's records: sl[k] are the calling lane's retained slots (-1 = none), the pixel
 // rows are in LDS (store_px_row; visible after the first barrier here), S_j = vals[start,
 // start + cnt) with emit indices src[start, start + cnt), and the tile's top-left pixel is
 // (x0, y0).  Every thread of the workgroup calls it; LDS is free again when it returns.

@@ -93,8 +93,13 @@ class _FitLoop:
 
     def grow(self, factor: float = 1.5) -> None:
         """Enlarge the pair buffer to ``factor`` times the larger of the current capacity and the
-        last render's requirement; drops the captured graph (it is re-captured on demand)."""
+        last render's requirement; drops the captured graph (it is re-captured on demand).  Raises
+        if the last iteration was skipped for a hit set too long for the two-pass adjoint's 16-bit
+        slots (the single-pass path has no such limit)."""
         st = self.status()
+        if int(st[nat.STAT_SKIP]) != 0 and int(st[nat.STAT_OVERFLOW]) == 0:
+            raise RuntimeError("a tile hit set exceeds 65535 Gaussians, more than the two-pass "
+                               "adjoint's 16-bit slots address; fit with single_pass=True")
         need = max(self.r.cap, int(st[nat.STAT_PAIRS]))
         self.r.set_capacity(int(need * factor) + 1024)
         self.saved = self.r.new_saved()
@@ -126,8 +131,9 @@ class _FitLoop:
             out.append((it, self.psnr()))
         return out
 
-    def _overflow_word(self) -> torch.Tensor:
-        return self.r.status_of(self.saved)[nat.STAT_OVERFLOW:nat.STAT_OVERFLOW + 1]
+    def _skip_word(self) -> torch.Tensor:
+        """The status word that makes Adam skip an iteration whose gradient is unusable."""
+        return self.r.status_of(self.saved)[nat.STAT_SKIP:nat.STAT_SKIP + 1]
 
     def snapshot(self) -> dict:
         return self.state_dict()
@@ -193,9 +199,8 @@ class PlainFitter(_FitLoop):
         else:
             self.l1_ws = _aligned_bytes(nat.igs_l1_workspace_size(self.target.numel()), self.dev)
         if pair_capacity is None:
-            # size the pair buffer from one render of the initial state, with headroom for growth
-            _, saved = self.r.render(self.rend, keep_state=True)
-            P = int(self.r.status_of(saved)[nat.STAT_PAIRS])
+            # size the pair buffer from a binning of the initial state, with headroom for growth
+            P = int(self.r.status_of(self.r.bin(self.rend))[nat.STAT_PAIRS])
             self.r.set_capacity(max(1024, int(P * headroom)))
         self.saved = self.r.new_saved()
         self.graph: Optional[torch.cuda.CUDAGraph] = None
@@ -248,13 +253,13 @@ class PlainFitter(_FitLoop):
         self.graph = None
 
     def _size_pairs(self) -> None:
-        _, saved = self.r.render(self.rend, keep_state=True)
-        P = int(self.r.status_of(saved)[nat.STAT_PAIRS])
+        P = int(self.r.status_of(self.r.bin(self.rend))[nat.STAT_PAIRS])
         self.r.set_capacity(max(1024, int(P * self.headroom)))
         self.saved = self.r.new_saved()
 
     def densify(self, count: int) -> None:
-        """Error-guided addition of ``count`` Gaussians (Eq. 7) from the last iteration's render,
+        """Error-guided addition of ``count`` Gaussians (Eq. 7) from a render of the current
+        parameters (every loss path renders them the same way, growing the pair buffer if needed),
         initialized like the content-adaptive ones (Sec. 4.1); drops the captured graph."""
         if count <= 0:
             return
@@ -264,8 +269,8 @@ class PlainFitter(_FitLoop):
         if self.place_ws is None:
             self.place_ws = _aligned_bytes(nat.igs_place_workspace_size(self.H, self.W),
                                            self.dev)
-        if self.single_pass:
-            self.r.render_into(self.rend, self.image, self.saved)
+        img, _ = self.r.render(self.rend, keep_state=False)
+        self.image.copy_(img)
         N_old = self.N
         self._resize(N_old + count)
         u = torch.rand(count, generator=self.gen, device=self.dev)
@@ -305,12 +310,13 @@ class PlainFitter(_FitLoop):
                                      self.grad_image, self.loss, self.l1_ws, self.l1_ws.numel())
             self.r.backward_into(self.rend, self.image, self.grad_image, self.saved,
                                  self.grad_params)
-        # an iteration whose render overflowed the pair buffer changes nothing (and does not
-        # count); the host notices from the step counter, grows the buffer and repeats it
+        # an iteration whose render overflowed the pair buffer (or, two-pass, whose hit sets are
+        # too long for 16-bit slots) changes nothing and does not count; the host notices from the
+        # step counter, grows the buffer and repeats it (or raises)
         nat.igs_adam_step(self.fit, self.rend, self.grad_params, self.m, self.v, self.step_count,
                           self.N, self.n, self.H, self.W, a.lr_mu, a.lr_theta, a.lr_inv_scale,
                           a.lr_color, a.beta1, a.beta2, a.eps, 1.0 / max(self.H, self.W),
-                          a.inv_scale_hi, skip_flag=self._overflow_word())
+                          a.inv_scale_hi, skip_flag=self._skip_word())
 
     # --------------------------------------------------------------------------- bookkeeping
 
@@ -433,7 +439,7 @@ class BatchFitter(_FitLoop):
         nat.igs_adam_step_batched(self.fit, self.rend, self.grad_params, self.m, self.v,
                                   self.step_count, r.descs, r.d_descs, self.n, a.lr_mu, a.lr_theta,
                                   a.lr_inv_scale, a.lr_color, a.beta1, a.beta2, a.eps,
-                                  a.inv_scale_hi, skip_flag=self._overflow_word())
+                                  a.inv_scale_hi, skip_flag=self._skip_word())
 
     def psnrs(self) -> List[float]:
         mse = self.loss[:, 2 if self.ssim_weight > 0 else 1].cpu().tolist()
