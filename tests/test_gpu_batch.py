@@ -63,9 +63,7 @@ def test_batched_render_matches_oracle_per_image():
     torch.cuda.synchronize()
     for b, ((H, W, N), p) in enumerate(zip(SIZES, params)):
         ref = cref.render(p.astype(np.float64), H, W, K)
-        qk, qk1 = ref["qsel"][..., K - 1], ref["qsel"][..., K]
-        with np.errstate(invalid="ignore"):
-            ok = ~(np.isfinite(qk1) & (qk1 - qk <= 1e-5 * (1 + qk1)))
+        ok = ref["margin"] > 0                        # near ties: see test_gpu_render
         got = br.image_views(imgs)[b].cpu().numpy().astype(np.float64)
         err = np.abs(got - ref["img"])[:, ok]
         assert np.all(err <= 1e-5 * np.abs(ref["img"][:, ok]) + 1e-7), (b, err.max())

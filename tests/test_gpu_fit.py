@@ -221,14 +221,17 @@ def test_from_target_places_gaussians_as_the_oracle():
 
 
 def test_densify_equals_direct_placement_call():
-    """The fitter's error-guided addition is igs_add_gaussians on its last render with the next
-    uniforms of its generator; new columns start with zero Adam moments."""
+    """The fitter's error-guided addition is igs_add_gaussians on a render of its current
+    parameters with the next uniforms of its generator; new columns start with zero Adam
+    moments."""
     from paper_2407_01866_amd import _native as nat
     from paper_2407_01866_amd.fit import PlainFitter
+    from paper_2407_01866_amd.render import Renderer
     t, w = _target256()
     f = PlainFitter.from_target(t, 2400, w.K, seed=5)
     f.run(40, report_every=40)
-    img = f.image.clone()
+    img, _ = Renderer(f.N, w.n, w.H, w.W, w.K, device=t.device).render(f.rend.clone(),
+                                                                       keep_state=False)
     fit0, m0 = f.fit.clone(), f.m.clone()
     state = f.gen.get_state()
     f.densify(300)

@@ -1,12 +1,22 @@
 """GPU parity of the HIP renderer against the FP64 oracle, through the C ABI.
 
-Bars: tile hit sets bit-exact; top-K index sets bit-exact wherever the oracle's gap between the
-K-th and (K+1)-th ranked q exceeds 1e-5 (1 + q_(K+1)) (several answers are correct inside that
-band); pixels |d| <= 1e-5 |ref| + 1e-7 at those pixels; gradients per parameter row
-|d| <= 1e-4 max(|ref|, 1e-2 max|ref_row|) with the upstream gradient zeroed at near-tie pixels
-(so both sides differentiate the same selection), plus 1e-5 times the oracle's sum of the terms'
-magnitudes before cancellation, the size of float32 evaluation error in a sum whose exact value
-is zero or nearly so (e.g. the geometry gradient of a Gaussian that is alone in its pixels).
+Bars:
+* tile hit sets bit-exact;
+* top-K index sets bit-exact at every pixel whose selection a float32 ranking decides for certain:
+  the oracle's margin (the best left-out q minus the worst retained q, each moved towards the
+  other by the float32 rounding bound of q, 16 u M with M the magnitude q is summed from) is
+  positive.  Elsewhere (a near tie: several selections are correct) the GPU's set must be one of
+  them (its members' q, lowered by the bound, may not exceed any left-out member's q raised by it)
+  and the pixel must equal the oracle's Eq. 5 blend over the GPU's own set; such pixels must be
+  fewer than 1e-4 of a workload's pixels;
+* pixels |d| <= 1e-5 |ref| + 1e-7;
+* gradients per parameter row |d| <= 1e-4 max(|ref|, 1e-2 max|ref_row|) with the upstream
+  gradient zeroed at near-tie pixels (so both sides differentiate the same selection), widened
+  only where the sum is ill-conditioned: the bar is the larger of that and 1e-5 times the oracle's
+  sum of the terms' magnitudes before cancellation (a float32 sum of such terms is accurate to a
+  small multiple of the unit roundoff times that magnitude), so the widening can apply only where
+  the magnitudes exceed 10 times the bar's own scale.  The entries that pass only through it are
+  counted and bounded.
 """
 import math
 
@@ -19,10 +29,12 @@ from paper_2407_01866_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-GAP_REL = 1e-5
 PIX_REL, PIX_ABS = 1e-5, 1e-7
 GRAD_REL, GRAD_FLOOR = 1e-4, 1e-2
 GRAD_COND = 1e-5      # times the oracle's sum of term magnitudes (float32 evaluation error bound)
+TIE_FRAC = 1e-4       # largest share of a workload's pixels that may lie in a near tie
+# largest share of a case's gradient entries that may pass only through the conditioning term
+COND_FRAC = 0.05
 
 
 def dev():
@@ -36,11 +48,10 @@ def renderer(N, n, H, W, K, cap=None):
     return Renderer(N, n, H, W, K, pair_capacity=cap, device=dev())
 
 
-def near_tie_mask(qsel, K):
-    """True where the oracle's selection is within the near-tie band."""
-    qk, qk1 = qsel[..., K - 1], qsel[..., K]
-    with np.errstate(invalid="ignore"):
-        return np.isfinite(qk1) & (qk1 - qk <= GAP_REL * (1.0 + qk1))
+def near_tie_mask(ref):
+    """True where a float32 ranking may correctly pick another set than the oracle's (the oracle's
+    margin is not positive)."""
+    return ref["margin"] <= 0
 
 
 def gpu_ids(r, saved, H, W, K):
@@ -61,9 +72,30 @@ def check_tile_lists(p64, H, W, ranges, vals):
     assert np.array_equal(vals[: counts.sum()], lists)
 
 
-def check_forward(img_gpu, ids_gpu, ref, K, tie=None):
+def check_tie_pixel(img_px, ids_px, p64, H, W, h, w, K):
+    """A near-tie pixel (h, w): the GPU's set (ids_px, -1 = unused) must be a correct selection
+    under the float32 rounding bound of q, and its colour the oracle's blend over that set."""
+    idx, q, mb = cref.rank_pixel(p64, H, W, h, w)
+    got = np.sort(ids_px[ids_px >= 0])
+    assert len(got) == min(K, len(idx)), (h, w, got)
+    inside = np.isin(idx, got)
+    assert inside.sum() == len(got), (h, w, "GPU set holds a non-member")
+    gam = cref.TIE_GAMMA
+    if (~inside).any():
+        lo_in = (q[inside] - gam * mb[inside]).max()
+        hi_out = (q[~inside] + gam * mb[~inside]).min()
+        assert lo_in <= hi_out, (h, w, lo_in, hi_out)
+    ref = cref.blend_set(p64, h, w, got)
+    assert np.all(np.abs(img_px - ref) <= PIX_REL * np.abs(ref) + PIX_ABS), (h, w, img_px, ref)
+
+
+def check_forward(img_gpu, ids_gpu, ref, K, tie=None, p64=None, HW=None, origin=(0, 0),
+                  workload=False):
+    """Top-K sets and pixels of a (sub)image against the oracle; at near-tie pixels the GPU's set
+    is validated instead (needs p64 and HW = (H, W) of the whole image; origin = (y0, x0) of the
+    sub-image).  workload: the near-tie share must stay below TIE_FRAC.  Returns the tie count."""
     if tie is None:
-        tie = near_tie_mask(ref["qsel"], K)
+        tie = near_tie_mask(ref)
     ok = ~tie
     a = np.sort(np.where(ids_gpu < 0, np.iinfo(np.int64).max, ids_gpu), axis=-1)
     b = np.sort(np.where(ref["topk"] < 0, np.iinfo(np.int64).max, ref["topk"]), axis=-1)
@@ -73,19 +105,42 @@ def check_forward(img_gpu, ids_gpu, ref, K, tie=None):
     lim = PIX_REL * np.abs(ref["img"]) + PIX_ABS
     bad = (d > lim) & ok[None]
     assert bad.sum() == 0, f"{bad.sum()} pixel values out of tolerance, worst {d[ok[None].repeat(d.shape[0], 0)].max():.3e}"
-    return int(tie.sum())
+    nt = int(tie.sum())
+    if nt:
+        assert p64 is not None, "near-tie pixels need the parameters to be validated"
+        H, W = HW
+        for y, x in zip(*np.nonzero(tie)):
+            check_tie_pixel(img_gpu[:, y, x], ids_gpu[y, x], p64, H, W, origin[0] + y,
+                            origin[1] + x, K)
+    print(f"[forward] near-tie pixels {nt} of {tie.size} ({nt / tie.size:.2e}), each validated",
+          flush=True)
+    if workload:
+        assert nt < TIE_FRAC * tie.size, (nt, tie.size)
+    return nt
 
 
 def check_grad(g_gpu, g_ref, g_abs):
+    """Gradient bar (see the module notes).  Returns the number of entries that pass only through
+    the conditioning term."""
     rowmax = np.abs(g_ref).max(axis=1, keepdims=True)
-    lim = GRAD_REL * np.maximum(np.abs(g_ref), GRAD_FLOOR * rowmax) + GRAD_COND * g_abs + 1e-30
-    bad = np.abs(g_gpu - g_ref) > lim
+    plain = GRAD_REL * np.maximum(np.abs(g_ref), GRAD_FLOOR * rowmax) + 1e-30
+    lim = np.maximum(plain, GRAD_COND * g_abs)
+    err = np.abs(g_gpu - g_ref)
+    bad = err > lim
     assert bad.sum() == 0, (f"{bad.sum()} gradient entries out of tolerance; rows "
                             f"{sorted(set(np.nonzero(bad)[0].tolist()))}, worst rel "
-                            f"{(np.abs(g_gpu - g_ref) / lim).max():.3f}")
+                            f"{(err / lim).max():.3f}")
+    widened = err > plain
+    nw = int(widened.sum())
+    worst = float((err / plain).max()) if err.size else 0.0
+    print(f"[grad] entries {err.size}, beyond the plain 1e-4 bar {nw} ({nw / max(err.size, 1):.2e}; "
+          f"all with term magnitudes > 10x the bar's scale), worst err/plain-bar {worst:.2f}",
+          flush=True)
+    assert nw <= COND_FRAC * err.size, (nw, err.size)
+    return nw
 
 
-def run_full(p, H, W, K, seed=0, cap=None, check_bwd=True):
+def run_full(p, H, W, K, seed=0, cap=None, check_bwd=True, workload=False):
     """Full-image parity of forward and adjoint against the oracle."""
     n, N = p.shape[0] - 5, p.shape[1]
     print(f"[parity] H={H} W={W} n={n} N={N} K={K} seed={seed}", flush=True)
@@ -98,8 +153,9 @@ def run_full(p, H, W, K, seed=0, cap=None, check_bwd=True):
     ids, ranges, vals = gpu_ids(r, saved, H, W, K)
     check_tile_lists(p64, H, W, ranges, vals)
     ref = cref.render(p64, H, W, K)
-    tie = near_tie_mask(ref["qsel"], K)
-    check_forward(img.cpu().numpy().astype(np.float64), ids, ref, K, tie)
+    tie = near_tie_mask(ref)
+    check_forward(img.cpu().numpy().astype(np.float64), ids, ref, K, tie, p64, (H, W),
+                  workload=workload)
     if not check_bwd:
         return r
     g = synth.gen_grad_image(seed + 17, n, H, W)
@@ -117,7 +173,7 @@ def run_full(p, H, W, K, seed=0, cap=None, check_bwd=True):
 
 def test_plain_256_n3_N2000():
     w = synth.workload(0)
-    run_full(w.gaussians(), w.H, w.W, w.K, seed=1)
+    run_full(w.gaussians(), w.H, w.W, w.K, seed=1, workload=True)
 
 
 @pytest.mark.parametrize("H,W,N,n,K", [(200, 136, 800, 3, 10), (17, 33, 40, 1, 4),
@@ -129,7 +185,7 @@ def test_ragged_shapes(H, W, N, n, K):
 
 def test_fit_workload_1024_N20000_full():
     w = synth.workload(1)
-    run_full(w.gaussians(), w.H, w.W, w.K, seed=2)
+    run_full(w.gaussians(), w.H, w.W, w.K, seed=2, workload=True)
 
 
 def big_footprint_params():
@@ -296,8 +352,9 @@ def sampled_parity(w, n_tiles=48, n_gauss=24, seed=0):
     for a, t in enumerate(tiles):
         assert ranges[t, 1] - ranges[t, 0] == counts[a]
         assert np.array_equal(vals[ranges[t, 0]:ranges[t, 1]], lists[off[a]:off[a + 1]])
-    ref = cref.render_tiles(p64, H, W, K, tiles=tiles)
+    ref = cref.render_tiles(p64, H, W, K, tiles=tiles, want=("img", "topk", "margin"))
     img_np = img.cpu().numpy()
+    ntie = npx = 0
     for a, t in enumerate(tiles):
         tx, ty = t % tx_n, t // tx_n
         x0, y0 = tx * 16, ty * 16
@@ -307,19 +364,23 @@ def sampled_parity(w, n_tiles=48, n_gauss=24, seed=0):
         sl = slots[:, y0:y1, x0:x1]
         ids = np.where(sl >= 0, vals[np.clip(ranges[t, 0] + sl, 0, len(vals) - 1)], -1)
         rt = ref["topk"][a].reshape(16, 16, K)[: y1 - y0, : x1 - x0]
-        rq = ref["qsel"][a].reshape(16, 16, K + 1)[: y1 - y0, : x1 - x0]
-        check_forward(gi, np.moveaxis(ids, 0, 2), {"img": ri, "topk": rt, "qsel": rq}, K)
+        rm = ref["margin"][a].reshape(16, 16)[: y1 - y0, : x1 - x0]
+        ntie += check_forward(gi, np.moveaxis(ids, 0, 2), {"img": ri, "topk": rt, "margin": rm}, K,
+                              None, p64, (H, W), (y0, x0))
+        npx += (y1 - y0) * (x1 - x0)
+    print(f"[sampled] near-tie pixels {ntie} of {npx} sampled", flush=True)
+    assert ntie < TIE_FRAC * npx
     # gradients of sampled Gaussians, upstream gradient zeroed at near-tie pixels of their tiles
     gids = rng.choice(w.N, n_gauss, replace=False)
     g = synth.gen_grad_image(seed + 99, n, H, W)
     sub_counts, _ = cref.tile_lists(p64[:, gids], H, W)
     gtiles = np.nonzero(sub_counts > 0)[0].astype(np.int32)
-    qs = cref.render_tiles(p64, H, W, K, tiles=gtiles, want=("qsel",))["qsel"]
+    qs = cref.render_tiles(p64, H, W, K, tiles=gtiles, want=("margin",))["margin"]
     for a, t in enumerate(gtiles):
         tx, ty = t % tx_n, t // tx_n
         x0, y0 = tx * 16, ty * 16
         x1, y1 = min(x0 + 16, W), min(y0 + 16, H)
-        tie = near_tie_mask(qs[a].reshape(16, 16, K + 1)[: y1 - y0, : x1 - x0], K)
+        tie = qs[a].reshape(16, 16)[: y1 - y0, : x1 - x0] <= 0
         g[:, y0:y1, x0:x1][:, tie] = 0.0
     gt = torch.from_numpy(g).to(d)
     gp = r.backward(pt, img, gt, saved).cpu().numpy().astype(np.float64)[:, gids]
@@ -402,7 +463,7 @@ def test_autograd_function_matches_oracle_chain_rule():
     img = RenderFn.apply(means, theta, inv, col, H, W, K)
     rp32 = fitref.to_render_space(fp, H, W)
     ref = cref.render(rp32.astype(np.float32).astype(np.float64), H, W, K)
-    tie = near_tie_mask(ref["qsel"], K)
+    tie = near_tie_mask(ref)
     g = synth.gen_grad_image(5, n, H, W)
     g[:, tie] = 0
     (img * torch.from_numpy(g).to(d)).sum().backward()
@@ -436,7 +497,7 @@ def test_autograd_function_vs_finite_differences_on_texture_crop():
     fp32 = fp.astype(np.float32)
     rp = fitref.to_render_space(fp32.astype(np.float64), C, C).astype(np.float32).astype(np.float64)
     ref = cref.render(rp, C, C, K)
-    tie = near_tie_mask(ref["qsel"], K)
+    tie = near_tie_mask(ref)
     g = synth.gen_grad_image(78, n, C, C)
     g[:, tie] = 0
     args = [torch.tensor(a, dtype=torch.float32, device=d, requires_grad=True)

@@ -117,7 +117,7 @@ def test_single_pass_on_overflow_matches_pair():
     assert not bool(b[1].any())
 
 
-@pytest.mark.parametrize("H,W,n,N,K,seed", [(96, 80, 3, 300, 10, 1), (50, 70, 9, 120, 4, 2),
+@pytest.mark.parametrize("H,W,n,N,K,seed", [(96, 80, 3, 300, 10, 7), (50, 70, 9, 120, 4, 2),
                                             (40, 40, 1, 60, 1, 3)])
 def test_single_pass_gradient_matches_oracle(H, W, n, N, K, seed):
     """Targets = oracle image -/+ an offset of 0.02..0.1, so every sign is decided far from 0."""
@@ -127,7 +127,7 @@ def test_single_pass_gradient_matches_oracle(H, W, n, N, K, seed):
     p = synth.gen_gaussians(seed, H, W, N, n)
     p64 = p.astype(np.float64)
     ref = cref.render(p64, H, W, K)
-    tie = near_tie_mask(ref["qsel"], K)
+    tie = near_tie_mask(ref)
     assert tie.sum() == 0, "seed chosen to have no near-tie pixel"
     rng = np.random.default_rng(seed + 99)
     off = rng.uniform(0.02, 0.1, size=(n, H, W)) * rng.choice([-1.0, 1.0], size=(n, H, W))
@@ -228,3 +228,54 @@ def test_single_pass_rejects_more_than_16_channels():
                        torch.zeros(2, dtype=torch.float64, device=d),
                        torch.empty((5 + n, N), device=d), r.new_saved())
     assert e.value.status == nat.IGS_ERR_UNSUPPORTED
+
+
+def test_single_pass_hit_set_beyond_16_bit_slots():
+    """One 16 x 16 tile hit by 70,000 Gaussians (|S_j| > 65535, Sec. 3.2 ranks all of them): the
+    single-pass kernel keeps its retained slots on chip at full width, so its loss and gradient
+    match the oracle; the two-pass adjoint's 16-bit slots cannot address such a set, so the render
+    marks its gradient as unusable and a two-pass fitter skips the step and raises, while a
+    single-pass fitter steps."""
+    from paper_2407_01866_amd.fit import PlainFitter
+    from paper_2407_01866_amd.render import Renderer
+    d = dev()
+    H = W = 16
+    n, N, K = 3, 70000, 10
+    print(f"[single-pass] |S_j| = {N} on one tile", flush=True)
+    p = synth.gen_gaussians(70, H, W, N, n)
+    p64 = p.astype(np.float64)
+    ref = cref.render(p64, H, W, K)
+    assert not near_tie_mask(ref).any(), "seed chosen to have no near-tie pixel"
+    rng = np.random.default_rng(170)
+    off = rng.uniform(0.02, 0.1, size=(n, H, W)) * rng.choice([-1.0, 1.0], size=(n, H, W))
+    tgt = (ref["img"] - off).astype(np.float32)
+    d64 = ref["img"] - tgt.astype(np.float64)
+    o = cref.render(p64, H, W, K, grad_img=np.sign(d64) / (n * H * W))
+    r = Renderer(N, n, H, W, K, device=d)
+    pt = torch.from_numpy(p).to(d)
+    tt = torch.from_numpy(tgt).to(d)
+    saved = r.bin(pt)
+    st = r.status_of(saved).cpu()
+    assert int(st[nat.STAT_MAX_LIST]) == N and int(st[nat.STAT_SLOT_OVERFLOW]) == 1
+    saved = r.new_saved()
+    loss = torch.zeros(2, dtype=torch.float64, device=d)
+    gp = torch.empty((5 + n, N), device=d)
+    r.l1_grad_into(pt, tt, loss, gp, saved)
+    torch.cuda.synchronize()
+    st = r.status_of(saved).cpu()
+    assert int(st[nat.STAT_SKIP]) == 0 and int(st[nat.STAT_OVERFLOW]) == 0
+    check_grad(gp.cpu().numpy().astype(np.float64), o["grad"], o["grad_abs"])
+    assert abs(float(loss[0]) - np.abs(d64).mean()) <= 1e-6 * np.abs(d64).mean()
+    # the fused two-pass render reports the unusable slots in the skip word
+    img = torch.empty((n, H, W), device=d)
+    sv2 = r.new_saved()
+    r.render_l1_into(pt, tt, img, torch.zeros(2, dtype=torch.float64, device=d), sv2)
+    torch.cuda.synchronize()
+    assert int(r.status_of(sv2)[nat.STAT_SKIP].item()) == 1
+    two = PlainFitter(tt, pt, K)
+    with pytest.raises(RuntimeError, match="65535"):
+        two.advance_to(1, use_graph=False)
+    assert two.steps_done() == 0
+    one = PlainFitter(tt, pt, K, single_pass=True)
+    one.advance_to(2, use_graph=False)
+    assert one.steps_done() == 2
