@@ -63,26 +63,51 @@ def bwd_valu_ops(e_bwd, n):
     return (35.0 + 3.0 * n) * e_bwd
 
 
-def cpu_baseline(params, H, W, K, grad_img, budget_s=10.0):
-    """The FP64 oracle (forward + adjoint) on the host's cores over whole frames of the workload:
-    one frame, repeated while the total stays within about ``budget_s`` seconds."""
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it), from /proc/cpuinfo."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(params, H, W, K, grad_img, budget_s=15.0):
+    """The FP64 oracle (forward + adjoint) on the host's cores: three timed runs over one whole
+    frame of the workload on all threads (the median is reported), then one thread over an evenly
+    strided sample of the frame's tiles sized to about a quarter of ``budget_s``."""
     from oracle import cref
     p64 = params.astype(np.float64)
     T = cref.num_tiles(H, W)
     tiles = np.arange(T, dtype=np.int32)
     counts, _ = cref.tile_lists(p64, H, W, tiles=tiles)
-    e_frame = float((counts * tile_pixels(H, W)).sum())
-    t0 = time.perf_counter()
-    cref.render_tiles(p64, H, W, K, tiles=tiles, grad_img=grad_img, want=("img",))
-    frames, dt = 1, time.perf_counter() - t0
-    while dt + dt / frames <= budget_s:
-        cref.render_tiles(p64, H, W, K, tiles=tiles, grad_img=grad_img, want=("img",))
-        frames += 1
+    e_tile = counts.astype(np.float64) * tile_pixels(H, W)
+    cores = cref.max_threads()
+
+    def timed(tl, nthreads):
+        t0 = time.perf_counter()
+        cref.render_tiles(p64, H, W, K, tiles=tl, grad_img=grad_img, want=("img",),
+                          nthreads=nthreads)
         dt = time.perf_counter() - t0
-    return {"value": e_frame * frames / dt, "unit": "Gaussian-pixel evals/s",
-            "cores": cref.max_threads(), "kind": "oracle",
-            "sample": f"{frames} whole frame(s) of the workload ({T} tiles, all pixels), forward "
-                      f"+ adjoint in FP64 with a seeded upstream gradient, {dt:.1f} s"}
+        return float(e_tile[tl].sum()) / dt, dt
+
+    runs = [timed(tiles, cores) for _ in range(3)]
+    rates = sorted(r for r, _ in runs)
+    frame_s = sorted(dt for _, dt in runs)[1]
+    # one thread: a strided sample of tiles (every stride-th tile of the frame)
+    stride = max(1, int(math.ceil(frame_s * cores / max(budget_s / 4.0, 0.5))))
+    one_rate, one_dt = timed(tiles[::stride], 1)
+    return {"value": rates[1], "unit": "Gaussian-pixel evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "runs": [round(r, 1) for r in rates],
+            "sample": f"median of 3 runs over one whole frame of the workload ({T} tiles, all "
+                      f"pixels, {frame_s:.2f} s each) on {cores} threads, forward + adjoint in "
+                      f"FP64 with a seeded upstream gradient",
+            "one_core": {"value": one_rate, "unit": "Gaussian-pixel evals/s", "cores": 1,
+                         "sample": f"every {stride}th tile of the frame ({len(tiles[::stride])} "
+                                   f"tiles), one thread, {one_dt:.1f} s"}}
 
 
 def paper_context(torch, dev, K=10):

@@ -57,3 +57,16 @@ def test_single_pass_work_is_the_sum_of_both_passes():
     # per (pixel, candidate) 9 lane-ops, per pixel 60 + 18 n; per retained pair 35 + 3 n
     assert bench.fwd_valu_ops(e_fwd, hw, n) == pytest.approx(9 * e_fwd + (60 + 18 * n) * hw)
     assert bench.bwd_valu_ops(e_bwd, n) == pytest.approx((35 + 3 * n) * e_bwd)
+
+
+def test_cpu_baseline_reports_model_median_of_three_and_one_thread():
+    import numpy as np
+    from paper_2407_01866_amd import synth
+    H, W, n = 64, 48, 3
+    p = synth.gen_gaussians(3, H, W, 100, n)
+    g = synth.gen_grad_image(4, n, H, W).astype(np.float64)
+    r = bench.cpu_baseline(p, H, W, 10, g, budget_s=1.0)
+    assert r["kind"] == "oracle" and r["cores"] >= 1 and r["cpu_model"]
+    assert len(r["runs"]) == 3 and r["runs"][0] <= r["value"] <= r["runs"][2]
+    assert r["one_core"]["cores"] == 1 and r["one_core"]["value"] > 0
+    assert "tiles" in r["one_core"]["sample"]
