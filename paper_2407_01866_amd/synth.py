@@ -90,6 +90,63 @@ def gen_gaussians(seed: int, H: int, W: int, N: int, n: int,
     return out
 
 
+def gen_fitted_like(seed: int, H: int, W: int, N: int, n: int) -> np.ndarray:
+    """A parameter set with the spread of a texture fit a few dozen Adam iterations in, float32
+    [5+n][N] in pixel units.  Fitting stretches some Gaussians across large parts of the image,
+    makes many strongly anisotropic, pushes colours outside [0, 1], means a little past the border
+    and angles onto the clamp values 0 and pi; this draws such a set directly:
+
+    * the base set as ``gen_gaussians`` (scales 1-12 px);
+    * 2.5% elongated: the long scale log-uniform in [20, 80] px, the short one in [1, 20] px;
+    * 30 large: the long scale log-uniform in [100, 600] px, the short one in [10, 80] px,
+      and one of them isotropic at max(H, W) px with its mean inside the image (it covers every
+      tile);
+    * a cluster of 600 Gaussians of 1-6 px with means in a 48 x 48 px square, so that a few tiles
+      hold several hundred candidates;
+    * 5% of the colours redrawn from U[-0.35, 1.35]; 5% of the angles set to exactly 0 or pi;
+      1% of the means redrawn from U[-25, W + 25] x U[-25, H + 25].
+    """
+    rng = np.random.default_rng(seed)
+    p = gen_gaussians(seed + 1, H, W, N, n).astype(np.float64)
+    big = float(max(H, W))
+    idx = rng.permutation(N)
+    n_el = int(round(0.025 * N))
+    n_lg = min(30, max(0, N - n_el))
+    n_cl = min(600, max(0, N - n_el - n_lg))
+    el, lg, cl = idx[:n_el], idx[n_el:n_el + n_lg], idx[n_el + n_lg:n_el + n_lg + n_cl]
+
+    def logu(a, b, size):
+        return np.exp(rng.uniform(math.log(a), math.log(b), size=size))
+
+    for sel, (la, lb), (sa, sb) in ((el, (20.0, 80.0), (1.0, 20.0)),
+                                    (lg, (100.0, 600.0), (10.0, 80.0))):
+        long_ = logu(la, max(lb, la), len(sel))
+        short = logu(sa, sb, len(sel))
+        first = rng.random(len(sel)) < 0.5
+        p[3, sel] = np.where(first, long_, short)
+        p[4, sel] = np.where(first, short, long_)
+    if n_lg >= 1:
+        p[3, lg[0]] = big
+        p[4, lg[0]] = big
+        p[0, lg[0]] = rng.uniform(0.25 * W, 0.75 * W)
+        p[1, lg[0]] = rng.uniform(0.25 * H, 0.75 * H)
+    if n_cl:
+        cx = rng.uniform(0.0, max(W - 48.0, 0.0))
+        cy = rng.uniform(0.0, max(H - 48.0, 0.0))
+        p[0, cl] = cx + rng.uniform(0.0, min(48.0, W), size=n_cl)
+        p[1, cl] = cy + rng.uniform(0.0, min(48.0, H), size=n_cl)
+        p[3, cl] = logu(1.0, 6.0, n_cl)
+        p[4, cl] = logu(1.0, 6.0, n_cl)
+    col = rng.random((n, N)) < 0.05
+    p[5:][col] = rng.uniform(-0.35, 1.35, size=int(col.sum()))
+    ang = rng.random(N) < 0.05
+    p[2, ang] = np.where(rng.random(int(ang.sum())) < 0.5, 0.0, math.pi)
+    mu = rng.random(N) < 0.01
+    p[0, mu] = rng.uniform(-25.0, W + 25.0, size=int(mu.sum()))
+    p[1, mu] = rng.uniform(-25.0, H + 25.0, size=int(mu.sum()))
+    return p.astype(np.float32)
+
+
 def gen_grad_image(seed: int, n: int, H: int, W: int) -> np.ndarray:
     """A seeded upstream gradient / linear functional r ~ N(0,1), float32 [n][H][W]."""
     rng = np.random.default_rng(seed)

@@ -11,12 +11,12 @@ Bars:
   fewer than 1e-4 of a workload's pixels;
 * pixels |d| <= 1e-5 |ref| + 1e-7;
 * gradients per parameter row |d| <= 1e-4 max(|ref|, 1e-2 max|ref_row|) with the upstream
-  gradient zeroed at near-tie pixels (so both sides differentiate the same selection), widened
-  only where the sum is ill-conditioned: the bar is the larger of that and 1e-5 times the oracle's
-  sum of the terms' magnitudes before cancellation (a float32 sum of such terms is accurate to a
-  small multiple of the unit roundoff times that magnitude), so the widening can apply only where
-  the magnitudes exceed 10 times the bar's own scale.  The entries that pass only through it are
-  counted and bounded.
+  gradient zeroed at near-tie pixels (so both sides differentiate the same selection).  That bar
+  is 0 for a row whose exact gradient is identically 0 (the geometry rows of K = 1, where every
+  retained weight is 1 and each pixel's colour is its one Gaussian's); a float32 kernel leaves
+  rounding residue there, so such a row is held instead to 1e-5 times the oracle's sum of the
+  terms' magnitudes before cancellation (grad_abs; a float32 evaluation of the sum is accurate to
+  a small multiple of the unit roundoff times it).  Every other entry meets the plain bar.
 """
 import math
 
@@ -31,10 +31,8 @@ pytestmark = pytest.mark.gpu
 
 PIX_REL, PIX_ABS = 1e-5, 1e-7
 GRAD_REL, GRAD_FLOOR = 1e-4, 1e-2
-GRAD_COND = 1e-5      # times the oracle's sum of term magnitudes (float32 evaluation error bound)
+GRAD_COND = 1e-5      # times the oracle's sum of term magnitudes, in identically zero rows
 TIE_FRAC = 1e-4       # largest share of a workload's pixels that may lie in a near tie
-# largest share of a case's gradient entries that may pass only through the conditioning term
-COND_FRAC = 0.05
 
 
 def dev():
@@ -119,25 +117,32 @@ def check_forward(img_gpu, ids_gpu, ref, K, tie=None, p64=None, HW=None, origin=
     return nt
 
 
-def check_grad(g_gpu, g_ref, g_abs):
-    """Gradient bar (see the module notes).  Returns the number of entries that pass only through
-    the conditioning term."""
+def grad_bars(g_ref, g_abs):
+    """(plain bar, identically-zero-row mask, bar) per entry: the plain bar, except in rows whose
+    exact gradient is 0 everywhere, which get GRAD_COND * g_abs."""
     rowmax = np.abs(g_ref).max(axis=1, keepdims=True)
-    plain = GRAD_REL * np.maximum(np.abs(g_ref), GRAD_FLOOR * rowmax) + 1e-30
-    lim = np.maximum(plain, GRAD_COND * g_abs)
+    plain = GRAD_REL * np.maximum(np.abs(g_ref), GRAD_FLOOR * rowmax)
+    zero = np.broadcast_to(rowmax == 0, g_ref.shape)
+    return plain, zero, np.where(zero, GRAD_COND * g_abs, plain)
+
+
+def check_grad(g_gpu, g_ref, g_abs):
+    """Gradient bar (see the module notes).  Returns the number of entries of identically zero
+    rows that the GPU leaves nonzero (rounding residue)."""
+    plain, zero, lim = grad_bars(g_ref, g_abs)
     err = np.abs(g_gpu - g_ref)
     bad = err > lim
     assert bad.sum() == 0, (f"{bad.sum()} gradient entries out of tolerance; rows "
                             f"{sorted(set(np.nonzero(bad)[0].tolist()))}, worst rel "
-                            f"{(err / lim).max():.3f}")
-    widened = err > plain
-    nw = int(widened.sum())
-    worst = float((err / plain).max()) if err.size else 0.0
-    print(f"[grad] entries {err.size}, beyond the plain 1e-4 bar {nw} ({nw / max(err.size, 1):.2e}; "
-          f"all with term magnitudes > 10x the bar's scale), worst err/plain-bar {worst:.2f}",
-          flush=True)
-    assert nw <= COND_FRAC * err.size, (nw, err.size)
-    return nw
+                            f"{(err / np.maximum(lim, 1e-300)).max():.3f}")
+    nz = int(zero.sum())
+    resid = zero & (err > 0)
+    nr = int(resid.sum())
+    worst = float((err[resid] / (GRAD_COND * g_abs[resid])).max()) if nr else 0.0
+    print(f"[grad] entries {err.size}: {err.size - nz} within the plain 1e-4 bar, {nz} in "
+          f"identically zero rows ({nr} with rounding residue, worst at {worst:.2f} of their "
+          f"bar)", flush=True)
+    return nr
 
 
 def run_full(p, H, W, K, seed=0, cap=None, check_bwd=True, workload=False):
