@@ -195,6 +195,29 @@ igs_status igs_render_l1_grad(const float *params, int32_t N, int32_t n, int32_t
                               void *stream);
 
 /*
+ * igs_render_l1_grad for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or fitting loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, bit for bit, with the workspace taken from a static device array of
+ * IGS_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on until the process
+ * ends.  The caller still provides every input and output, `saved` included.  No device memory
+ * is allocated or freed by the call.
+ *   arguments: as igs_render_l1_grad without workspace / ws_bytes
+ * The workspace igs_render_buffer_sizes reports for these arguments must fit the array (64 MiB:
+ * e.g. a 1024 x 1024 x 3 fit with 20,000 Gaussians and a few hundred thousand pairs); otherwise
+ * IGS_ERR_WORKSPACE and nothing is launched.  All calls on one device share its array: calls that
+ * overlap on a device (other streams, threads) race and give undefined results; calls in one
+ * stream order are safe.  The array keeps the last call's contents; the kernels read nothing from
+ * it that the same call did not write.
+ * Errors: as igs_render_l1_grad; IGS_ERR_WORKSPACE when the workspace would exceed the array.
+ */
+#define IGS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+igs_status igs_render_l1_grad_noalloc(const float *params, int32_t N, int32_t n, int32_t H,
+                                      int32_t W, int32_t K, int32_t tile_h, int32_t tile_w,
+                                      int64_t pair_capacity, const float *target, double *loss_out,
+                                      float *grad_params, void *saved, size_t saved_bytes,
+                                      void *stream);
+
+/*
  * Binning alone (Sec. 3.2): the footprint bound, pair emission, sort and tile ranges of
  * igs_render, written into `saved` without rasterizing, for decoders that answer point queries
  * (igs_query).  Arguments, sizes, status block and errors as igs_render (image not needed).

@@ -22,6 +22,7 @@ IGS_MAX_K = 32
 IGS_MAX_CHANNELS = 32
 IGS_TILE = 16
 IGS_STATUS_WORDS = 8
+IGS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # status block words (int64 at byte 0 of the saved state)
 (STAT_PAIRS, STAT_OVERFLOW, STAT_MAX_LIST, STAT_SLOT_OVERFLOW, STAT_EVALS_FWD, STAT_EVALS_BWD,
@@ -41,6 +42,7 @@ EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "
             "igs_query_workspace_size", "igs_l1_ssim_batched_workspace_size",
             "igs_l1_ssim_loss_grad_batched",
             "igs_params_to_fp16", "igs_decode_fp16", "igs_render_l1_grad",
+            "igs_render_l1_grad_noalloc",
             "igs_render_l1_grad_batched")
 
 PHASES = ("binning", "raster_fwd", "raster_bwd", "loss", "adam", "grad_reduce", "raster_fit")
@@ -176,6 +178,9 @@ def lib() -> ctypes.CDLL:
     L.igs_render_l1_grad.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, vp, vp, vp,
                                      sz, vp, sz, vp]
     L.igs_render_l1_grad.restype = i32
+    L.igs_render_l1_grad_noalloc.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, vp,
+                                             vp, vp, sz, vp]
+    L.igs_render_l1_grad_noalloc.restype = i32
     L.igs_render_l1_grad_batched.argtypes = [vp, dp, vp, i32, i32, i32, i64, vp, vp, vp, vp, sz,
                                              vp, sz, vp]
     L.igs_render_l1_grad_batched.restype = i32
@@ -296,6 +301,16 @@ def igs_render_l1_grad(params, N, n, H, W, K, tile_h, tile_w, pair_capacity, tar
         _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, pair_capacity,
         _f32(target, "target"), _ptr(loss_out), _f32(grad_params, "grad_params") if N > 0 else None,
         _ptr(saved), saved_bytes, _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def igs_render_l1_grad_noalloc(params, N, n, H, W, K, tile_h, tile_w, pair_capacity, target,
+                               loss_out, grad_params, saved, saved_bytes, stream=None) -> None:
+    if loss_out.dtype != torch.float64:
+        raise TypeError("loss_out must be float64[2]")
+    _check("igs_render_l1_grad_noalloc", lib().igs_render_l1_grad_noalloc(
+        _f32(params, "params") if N > 0 else None, N, n, H, W, K, tile_h, tile_w, pair_capacity,
+        _f32(target, "target"), _ptr(loss_out), _f32(grad_params, "grad_params") if N > 0 else None,
+        _ptr(saved), saved_bytes, _stream(stream)))
 
 
 def igs_l1_workspace_size(count: int) -> int:

@@ -4,6 +4,7 @@
 #include "../../include/imagegs.h"
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 #include "timing.hpp"
@@ -558,6 +559,57 @@ IGS_API igs_status igs_render_l1_grad(const float *params, int32_t N, int32_t n,
     return IGS_ERR_INVALID_ARG;
   return fit_l1_impl(params, make_dims(N, n, H, W, K, pair_capacity), single_view(H, W, N), false,
                      target, loss_out, grad_params, saved, saved_bytes, workspace, ws_bytes,
+                     static_cast<hipStream_t>(stream));
+}
+
+// --------------------------------------------------------------- no-allocation variant
+
+namespace {
+
+// Workspace of igs_render_l1_grad_noalloc.  Every device the library runs on holds its own copy
+// until the process ends; host code only ever uses its per-device address (scratch_address),
+// never this name.
+static __device__ __align__(256) unsigned char scratch[IGS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 256;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The address of the current device's copy of `scratch`, looked up once per device.
+igs_status scratch_address(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return IGS_ERR_HIP;
+  if (dev < 0 || dev >= kMaxScratchDevices) return IGS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return IGS_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return IGS_OK;
+}
+
+}  // namespace
+
+IGS_API igs_status igs_render_l1_grad_noalloc(const float *params, int32_t N, int32_t n,
+                                              int32_t H, int32_t W, int32_t K, int32_t tile_h,
+                                              int32_t tile_w, int64_t pair_capacity,
+                                              const float *target, double *loss_out,
+                                              float *grad_params, void *saved, size_t saved_bytes,
+                                              void *stream) {
+  igs_status st = check_dims(N, n, H, W, K, tile_h, tile_w, pair_capacity);
+  if (st != IGS_OK) return st;
+  if (n > kMaxFusedChannels) return IGS_ERR_UNSUPPORTED;
+  if ((N > 0 && (!params || !grad_params)) || !target || !loss_out || !saved)
+    return IGS_ERR_INVALID_ARG;
+  const Dims d = make_dims(N, n, H, W, K, pair_capacity);
+  if (ws_layout(d).total > (size_t)IGS_NOALLOC_SCRATCH_BYTES) return IGS_ERR_WORKSPACE;
+  void *ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != IGS_OK) return st;
+  return fit_l1_impl(params, d, single_view(H, W, N), false, target, loss_out, grad_params, saved,
+                     saved_bytes, ws, (size_t)IGS_NOALLOC_SCRATCH_BYTES,
                      static_cast<hipStream_t>(stream));
 }
 

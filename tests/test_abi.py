@@ -120,6 +120,26 @@ def test_render_validates_before_device_work(nat):
     assert L.igs_l1_workspace_size(1000, ctypes.byref(sz)) == 0 and sz.value >= 16
 
 
+def test_noalloc_single_pass_validates_before_device_work(nat):
+    """The no-allocation single-pass call rejects bad arguments, and a problem whose workspace
+    would not fit its static array, before any HIP call (the fake pointers are never
+    dereferenced)."""
+    L = nat.lib()
+    fake = ctypes.c_void_p(0x1000)
+    args = lambda n=3, tile=16, cap=100, tgt=fake, saved=fake: (
+        fake, 10, n, 64, 64, 10, tile, tile, cap, tgt, fake, fake, saved, 1 << 20, None)
+    assert L.igs_render_l1_grad_noalloc(*args(tgt=None)) == -1
+    assert L.igs_render_l1_grad_noalloc(*args(saved=None)) == -1
+    assert L.igs_render_l1_grad_noalloc(*args(tile=8)) == -4
+    assert L.igs_render_l1_grad_noalloc(*args(n=17)) == -4
+    ws_fit, _ = nat.igs_render_buffer_sizes(10, 3, 64, 64, 10, 16, 16, 100)
+    assert ws_fit <= nat.IGS_NOALLOC_SCRATCH_BYTES
+    big = 1 << 24
+    ws_big, _ = nat.igs_render_buffer_sizes(10, 3, 64, 64, 10, 16, 16, big)
+    assert ws_big > nat.IGS_NOALLOC_SCRATCH_BYTES
+    assert L.igs_render_l1_grad_noalloc(*args(cap=big)) == -2
+
+
 def test_l1_ssim_validates_before_device_work(nat):
     L = nat.lib()
     sz = ctypes.c_size_t(0)
