@@ -40,15 +40,13 @@ __device__ __forceinline__ float quad_q32(float A, float B, float C, float D, fl
   return fmaf(e1, e1, e2 * e2);
 }
 
-// Sorted insertion into a register-resident top-KT list of keys: one max and one min per entry.
+// Sorted insertion into a register-resident ascending top-KT list of keys: entry k becomes
+// min(old k, max(key, old k-1)), one max and one min per entry with no chain between entries.
 template <int KT>
 __device__ __forceinline__ void topk_insert(double (&tk)[KT], double key) {
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    const double hi = __builtin_fmax(key, tk[k]);
-    tk[k] = __builtin_fmin(key, tk[k]);
-    key = hi;
-  }
+  for (int k = KT - 1; k > 0; --k) tk[k] = __builtin_fmin(tk[k], __builtin_fmax(key, tk[k - 1]));
+  tk[0] = __builtin_fmin(tk[0], key);
 }
 
 // Blend weight exp(-(q - shift)/2) (Eq. 5 scaled by exp(shift/2), which cancels in the ratio).

@@ -24,9 +24,11 @@ __host__ __device__ constexpr size_t fit_lds_bytes() {
                                                      : (size_t)bwd_lds<NC, KT>().total;
 }
 
-// Register budget: four waves per SIMD (<= 128 VGPRs) where that fits without spilling.
+// Register budget: five waves per SIMD (<= 96 VGPRs; the LDS of up to n = 9 also lets five
+// workgroups share a CU) where that costs at most a few spills outside the per-candidate and
+// per-item loops, else four (<= 128) or two.
 __host__ __device__ constexpr int fit_min_waves(int nc, int kt) {
-  return (nc + kt <= 25 && !(nc >= 16 && kt >= 4)) ? 4 : 2;
+  return (nc <= 9 && kt <= 10) ? 5 : ((nc + kt <= 25 && !(nc >= 16 && kt >= 4)) ? 4 : 2);
 }
 
 template <int NC, int KT>
@@ -124,12 +126,13 @@ __attribute__((amdgpu_waves_per_eu(fit_min_waves(NC, KT)))) void raster_fit_kern
     for (int k = 0; k < KT; ++k)
       if (k < K && k < keff && ts[k] >= 0) sl[k] = ts[k];
   }
+  // the tile's loss sums first, so that they hold no registers through the adjoint
+  const double2 t = tile_loss_sums(l1_abs, l1_sq, s_red);
+  if (tid == 0) loss_part[tile] = t;
   __syncthreads();  // the forward's LDS is dead
   store_px_row<NC>(smem, row);
   adjoint_batches<NC, KT>(smem, start, cnt, x0, y0, sl, vals, src, g32a, g64, params, N, n,
                           part);
-  const double2 t = tile_loss_sums(l1_abs, l1_sq, s_red);
-  if (tid == 0) loss_part[tile] = t;
 }
 
 template <int NC, int KT>

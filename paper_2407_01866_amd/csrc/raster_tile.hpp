@@ -89,6 +89,37 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Inclusive sum over the 64 lanes of a wave by DPP: row shifts give each lane the sum of its row
+// up to itself, then the last lane of each row is broadcast into the following rows.  Lanes a
+// shift or a row mask leaves without a source add 0.
+__device__ __forceinline__ int wave_inclusive_sum(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+
+// The same for a double (each step moves both words): lane 63 ends with the wave's sum, added in
+// a fixed order.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_inclusive_sum_f64(double v) {
+  v += dpp_f64<0x111, 0xF>(v);
+  v += dpp_f64<0x112, 0xF>(v);
+  v += dpp_f64<0x114, 0xF>(v);
+  v += dpp_f64<0x118, 0xF>(v);
+  v += dpp_f64<0x142, 0xA>(v);
+  v += dpp_f64<0x143, 0xC>(v);
+  return v;
+}
+
 // The forward's LDS: ranking data in visiting order (position m of the batch's candidate order),
 // blend data in slot order (position j in S_j minus the batch base), bucket counters, colours.
 struct FwdLds {
@@ -184,12 +215,7 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
     __syncthreads();
     if (tid < 64) {  // bucket starts: exclusive scan of the counters (one wave)
       const int c = tid < kBuckets ? S.bcnt[tid] : 0;
-      int inc = c;
-#pragma unroll
-      for (int d = 1; d < kBuckets; d <<= 1) {
-        const int o = __shfl_up(inc, d, 64);
-        if (tid >= d) inc += o;
-      }
+      const int inc = wave_inclusive_sum(c);
       if (tid < kBuckets) S.bstart[tid] = inc - c;
     }
     __syncthreads();
@@ -202,21 +228,22 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
     }
     if (tid < kBuckets) S.bcnt[tid] = 0;  // ready for the next batch
     __syncthreads();
-    // four positions per step; the skip decisions are wave-uniform (scalar branches)
-    for (int m = 0; m < nb; m += 4) {
+    // eight positions per step.  Every lane of a wave reads the same bound, so a skip decision is
+    // uniform over the wave and a skipped candidate costs one vector compare.
+    for (int m = 0; m < nb; m += 8) {
       // the largest K-th key of the wave (the lists only shrink, so a stale value is safe)
       const uint32_t th = wave_max_u32((uint32_t)__double2hiint(tk[KT - 1]));
       const float q_tau = __uint_as_float(th - kKeyBias);
       // every later candidate's bound is at least the floor of this position's bucket
       if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(S.pcd[m].w))) > q_tau)
         break;
-      const float4 lb4 = *reinterpret_cast<const float4 *>(&S.plbw[wave * kFwdBatch + m]);
-      const float lbu[4] = {lb4.x, lb4.y, lb4.z, lb4.w};
+      const float4 lba = *reinterpret_cast<const float4 *>(&S.plbw[wave * kFwdBatch + m]);
+      const float4 lbb = *reinterpret_cast<const float4 *>(&S.plbw[wave * kFwdBatch + m + 4]);
+      const float lbu[8] = {lba.x, lba.y, lba.z, lba.w, lbb.x, lbb.y, lbb.z, lbb.w};
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         if (m + u >= nb) break;
-        if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lbu[u]))) > q_tau)
-          continue;
+        if (lbu[u] > q_tau) continue;
         const float4 g = S.pgeo[m + u];
         const float4 cd = S.pcd[m + u];
         const float dx = fx - g.x, dy = fy - g.y;
@@ -303,22 +330,17 @@ __device__ __forceinline__ void winners(const FwdLds &S, bool single, int start,
 // j (in chunk order) and writes them as one record at the pair's emit index.  No atomics touch
 // floating point, in LDS or in memory, so the records are reproducible bit for bit.
 
-// Per-Gaussian item counters are split into kSub sub-counters, (wave, lane & 3): each is touched
+// Per-Gaussian item counters are split into kSub sub-counters, (wave, lane & 1): each is touched
 // by one wave only, so the ranks it hands out follow the program and lane order (no dependence on
 // how waves interleave) and the order of items in a run, hence every float sum, is reproducible;
-// the lane split spreads same-address LDS atomics.
-constexpr int kSub = 16;
-__device__ __forceinline__ int item_sub(int tid) { return ((tid >> 6) << 2) | (tid & 3); }
+// the lane split halves same-address LDS atomics.
+constexpr int kSub = 8;
+__device__ __forceinline__ int item_sub(int tid) { return ((tid >> 6) << 1) | (tid & 1); }
 
 // Exclusive scan of v over the 256 threads of the block; returns the block total in *total.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int o = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += o;
-  }
+  const int inc = wave_inclusive_sum(v);
   if (lane == 63) s_wave[w] = inc;
   __syncthreads();
   int off = 0, tot = 0;
@@ -332,10 +354,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave, int *tot
   return off + inc - v;
 }
 
-// The adjoint's LDS layout (byte offsets).  The per-chunk sums (written after the items are
-// placed) reuse the space of the per-Gaussian counters (dead by then).
+// The adjoint's LDS layout (byte offsets).  The per-Gaussian counters and the placed items share
+// one region, which the per-chunk sums reuse once every chunk has read its items.
 struct BwdLds {
-  unsigned px, part, off, cho, owner, gid, wave, item, total;
+  unsigned px, part, off, cho, owner, gid, src, wave, item, total;
 };
 
 // Per-pixel row in LDS: g[0..NC), g.c_r, shift, 1/Z, padding to a multiple of 4 floats.
@@ -347,13 +369,15 @@ __host__ __device__ constexpr BwdLds bwd_lds() {
   constexpr unsigned ROW = px_row<NC>();
   constexpr unsigned NACC = 5 + NC;
   constexpr unsigned cnt_bytes = 4 * (kBatch * kSub + kRasterThreads);  // + one dummy per lane
+  constexpr unsigned item_bytes = 2 * kRasterThreads * KT;
   constexpr unsigned part_bytes = 4 * kRasterThreads * NACC;
   BwdLds L{};
   unsigned o = 0;
   L.px = o;
   o += 4 * kRasterThreads * ROW;
   L.part = o;
-  o += part_bytes > cnt_bytes ? part_bytes : cnt_bytes;
+  L.item = o + cnt_bytes;
+  o += part_bytes > cnt_bytes + item_bytes ? part_bytes : cnt_bytes + item_bytes;
   L.off = o;
   o += 4 * (kBatch + 4);
   L.cho = o;
@@ -362,10 +386,10 @@ __host__ __device__ constexpr BwdLds bwd_lds() {
   o += 2 * kRasterThreads;
   L.gid = o;
   o += 4 * kBatch;
+  L.src = o;
+  o += 4 * kBatch;
   L.wave = o;
   o += 32;
-  L.item = o;
-  o += 2 * kRasterThreads * KT;
   L.total = (o + 15) & ~15u;
   return L;
 }
@@ -404,6 +428,7 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
   int *s_cho = reinterpret_cast<int *>(smem + L.cho);              // [kBatch + 1] chunk starts
   uint16_t *s_owner = reinterpret_cast<uint16_t *>(smem + L.owner);  // [256] chunk -> j
   uint32_t *s_gid = reinterpret_cast<uint32_t *>(smem + L.gid);    // [kBatch] j -> Gaussian
+  uint32_t *s_src = reinterpret_cast<uint32_t *>(smem + L.src);    // [kBatch] j -> emit index
   int *s_wave = reinterpret_cast<int *>(smem + L.wave);
   uint16_t *s_item = reinterpret_cast<uint16_t *>(smem + L.item);  // [256 * KT] px | j << 8
 
@@ -412,10 +437,9 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
   for (int base = 0; base < cnt; base += kBatch) {
     const int nb = min(kBatch, cnt - base);
     if (base > 0) __syncthreads();  // previous batch fully consumed
-    uint32_t my_src = 0;  // emit index of the batch's Gaussian tid
     if (tid < nb) {
       s_gid[tid] = vals[start + base + tid];
-      my_src = src[start + base + tid];
+      s_src[tid] = src[start + base + tid];
     }
 #pragma unroll
     for (int c = 0; c < kSub; ++c) s_cnt8[tid * kSub + c] = 0;
@@ -503,13 +527,13 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
     __syncthreads();
 
     // 2: chunk tid, one Gaussian, accumulated in registers
+    float G1 = 0.f, G2 = 0.f, G11 = 0.f, G22 = 0.f, G12 = 0.f;
+    float gcol[NC];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) gcol[ch] = 0.f;
     if (has) {
       const int first = s_off[j] + (tid - s_cho[j]) * R;
       const int end = min(first + R, s_off[j + 1]);
-      float G1 = 0.f, G2 = 0.f, G11 = 0.f, G22 = 0.f, G12 = 0.f;
-      float gcol[NC];
-#pragma unroll
-      for (int ch = 0; ch < NC; ++ch) gcol[ch] = 0.f;
       for (int it = first; it < end; ++it) {
         const int p = s_item[it] & 0xFF;
         float rw[ROW];
@@ -540,6 +564,9 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
 #pragma unroll
         for (int ch = 0; ch < NC; ++ch) gcol[ch] = fmaf(alpha, rw[ch], gcol[ch]);
       }
+    }
+    __syncthreads();  // every chunk has read its items: the sums may overwrite them
+    if (has) {
       float *prow = &s_part[tid * NACC];
       prow[0] = G1;
       prow[1] = G2;
@@ -551,26 +578,21 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
     }
     __syncthreads();
 
-    // 3: Gaussian tid adds up its chunks and writes the pair's record (zeros when no pixel of
-    // the tile retained it)
-    if (tid < nb) {
+    // 3: the pair records, LP lanes per Gaussian: lane r adds up entry r of the Gaussian's chunks
+    // in chunk order (zeros when no pixel of the tile retained it, and in the padding)
+    {
       constexpr int NR = (NACC + 3) & ~3;
-      float acc[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] = 0.f;
-      for (int c = 0; c < my_ch; ++c) {
-#pragma unroll
-        for (int r = 0; r < NACC; ++r) acc[r] += s_part[(my_cho + c) * NACC + r];
-      }
+      constexpr int LP = NR <= 16 ? 16 : (NR <= 32 ? 32 : 64);
       const int stride = part_stride(n);
-      float4 *rec = reinterpret_cast<float4 *>(part + (size_t)my_src * stride);
-#pragma unroll
-      for (int q = 0; q < NR / 4; ++q) {
-        if (4 * q < stride) {
-          float v[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (4 * q + e < 5 + n) ? acc[4 * q + e] : 0.f;
-          rec[q] = make_float4(v[0], v[1], v[2], v[3]);
+      const int r = tid & (LP - 1);
+      for (int jj = tid / LP; jj < nb; jj += kRasterThreads / LP) {
+        if (r < stride) {
+          float acc = 0.f;
+          if (r < 5 + n) {
+            const int c1 = s_cho[jj + 1];
+            for (int c = s_cho[jj]; c < c1; ++c) acc += s_part[c * NACC + r];
+          }
+          part[(size_t)s_src[jj] * stride + r] = acc;
         }
       }
     }
@@ -578,16 +600,13 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
   __syncthreads();  // LDS is reused by the next phase or tile
 }
 
-// Tile loss sums (sum |d|, sum d^2) over the workgroup: wave sums by shuffles, then a fixed order
+// Tile loss sums (sum |d|, sum d^2) over the workgroup: wave sums by DPP, then a fixed order
 // over the four waves; the result is valid in thread 0.
 __device__ __forceinline__ double2 tile_loss_sums(double a, double b, double *s_red) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    a += __shfl_down(a, d, 64);
-    b += __shfl_down(b, d, 64);
-  }
+  a = wave_inclusive_sum_f64(a);
+  b = wave_inclusive_sum_f64(b);
   const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
+  if ((threadIdx.x & 63) == 63) {
     s_red[2 * wave] = a;
     s_red[2 * wave + 1] = b;
   }
