@@ -49,9 +49,10 @@ __device__ __forceinline__ void topk_insert(double (&tk)[KT], double key) {
   tk[0] = __builtin_fmin(tk[0], key);
 }
 
-// Blend weight exp(-(q - shift)/2) (Eq. 5 scaled by exp(shift/2), which cancels in the ratio).
+// Blend weight exp(-(q - shift)/2) (Eq. 5 scaled by exp(shift/2), which cancels in the ratio),
+// as 2^((q - shift) * (-log2(e) / 2)): one multiply and the hardware base-2 exponential.
 __device__ __forceinline__ float blend_weight(double q, float shift) {
-  return __expf(-0.5f * (float)(q - (double)shift));
+  return __builtin_amdgcn_exp2f((float)(q - (double)shift) * -0.72134752044448170f);
 }
 
 // Kernel variants by top-K capacity: the smallest KT >= K is used (the first K entries of a

@@ -259,7 +259,10 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
 // The retained members of a pixel (its first keff = min(K, |S_j|) keys), re-evaluated in double:
 // ts[k] their slots (-1 when absent), src[k] where their colour is (LDS row when single, else the
 // Gaussian index), w[k] their weights exp(-(q_k - shift)/2) with shift = q of the first, and Z the
-// weights' sum.
+// weights' sum.  No member of S_j is ever cut off (every candidate's key is finite and the
+// forward skips a candidate only once the lane's list is full), so every lane's list holds
+// min(|S_j|, KT) keys and the retained entries are exactly k < keff, the same for the whole
+// workgroup: the loop over them is a uniform branch.
 template <int KT>
 __device__ __forceinline__ void winners(const FwdLds &S, bool single, int start, int keff,
                                         const double (&tk)[KT], float fx, float fy,
@@ -267,47 +270,49 @@ __device__ __forceinline__ void winners(const FwdLds &S, bool single, int start,
                                         const float4 *__restrict__ g32a,
                                         const double4 *__restrict__ g64, int (&ts)[KT],
                                         float (&w)[KT], int (&src)[KT], float &Z, float &shift) {
-#pragma unroll
-  for (int k = 0; k < KT; ++k) ts[k] = key_valid(tk[k]) ? key_slot(tk[k]) : -1;
   Z = 0.f;
   shift = 0.f;
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
+  for (int k = 0; k < KT; ++k) {  // the slots first, so that the keys' registers are free
+    ts[k] = k < keff ? key_slot(tk[k]) : -1;
     w[k] = 0.f;
     src[k] = 0;
-    if (k < keff && ts[k] >= 0) {  // a non-finite q never enters the list
-      const int slot = ts[k];
-      double A, B, C, D;
-      float mx, my;
-      if (single) {
-        A = S.s64[4 * slot + 0];
-        B = S.s64[4 * slot + 1];
-        C = S.s64[4 * slot + 2];
-        D = S.s64[4 * slot + 3];
-        mx = S.mu[slot].x;
-        my = S.mu[slot].y;
+  }
+  if (single) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < keff) {
+        const int slot = ts[k];
+        const double4 c = *reinterpret_cast<const double4 *>(&S.s64[4 * slot]);
+        const float2 mu = S.mu[slot];
+        double e1, e2;
+        const double q = quad_form64(fx, fy, mu.x, mu.y, c.x, c.y, c.z, c.w, e1, e2);
+        if (k == 0) shift = (float)q;
+        w[k] = blend_weight(q, shift);
+        Z += w[k];
         src[k] = slot;
-        // keeps these LDS loads and the global loads below in their own branches (merging them
-        // into loads through a pointer that is LDS or global miscompiles for gfx950)
+        // one winner's loads at a time: hoisting all of them would cost registers
         asm volatile("" ::: "memory");
-      } else {
+      }
+    }
+  } else {
+    // LDS and global reads stay in separate loops (a read through a pointer that may address
+    // either miscompiles for gfx950)
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < keff) {
+        const int slot = ts[k];
         const uint32_t gid = vals[start + slot];
         const double4 c = g64[gid];
         const float4 a = g32a[gid];
-        A = c.x;
-        B = c.y;
-        C = c.z;
-        D = c.w;
-        mx = a.x;
-        my = a.y;
+        double e1, e2;
+        const double q = quad_form64(fx, fy, a.x, a.y, c.x, c.y, c.z, c.w, e1, e2);
+        if (k == 0) shift = (float)q;
+        w[k] = blend_weight(q, shift);
+        Z += w[k];
         src[k] = (int)gid;
         asm volatile("" ::: "memory");
       }
-      double e1, e2;
-      const double q = quad_form64(fx, fy, mx, my, A, B, C, D, e1, e2);
-      if (k == 0) shift = (float)q;
-      w[k] = blend_weight(q, shift);
-      Z += w[k];
     }
   }
 }
@@ -473,14 +478,36 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
     const int my_off = packed_off & 0xFFFF;
     const int total_items = packed_total & 0xFFFF;
     const int busy = packed_total >> 16;
-    // chunk length: sum_j ceil(cnt_j / R) <= total / R + busy <= 256
-    const int R = busy < kRasterThreads
-                      ? max(1, (total_items + (kRasterThreads - busy) - 1) / (kRasterThreads - busy))
-                      : kRasterThreads;
-    const int my_ch = (my_cnt + R - 1) / R;
-    int total_chunks;
+    // chunk length R: the batch may have at most 256 chunks, sum_j ceil(cnt_j / R).  Three
+    // candidates, shortest first: the ideal ceil(total / 256), an estimate that allows half a
+    // partial chunk per Gaussian, and the guaranteed ceil(total / (256 - busy)), for which the
+    // sum is at most total / R + busy <= 256.  One scan counts the chunks of all three (a
+    // Gaussian's run is at most 256 items, so each count fits 10 bits), and the shortest that
+    // fits is used.
+    const int r_safe = busy < kRasterThreads
+                           ? max(1, (total_items + (kRasterThreads - busy) - 1) / (kRasterThreads - busy))
+                           : kRasterThreads;
+    const int r_mid = min(r_safe, max(1, (2 * total_items + (2 * kRasterThreads - busy) - 1) /
+                                             (2 * kRasterThreads - busy)));
+    const int r_min = min(r_mid, max(1, (total_items + kRasterThreads - 1) / kRasterThreads));
+    // ceil(c / R) as floor((c + R - 1/2) / R) in float with the hardware reciprocal: exact, the
+    // quotient is at least 1 / (2 R) from an integer and c, R <= 256 keep its error (a few ulps
+    // of a value below 512) far below that
+    auto chunks_of = [&](int c, int R) {
+      return (int)(((float)c + ((float)R - 0.5f)) * __builtin_amdgcn_rcpf((float)R));
+    };
+    const int packed_ch = chunks_of(my_cnt, r_min) | (chunks_of(my_cnt, r_mid) << 10) |
+                          (chunks_of(my_cnt, r_safe) << 20);
+    int packed_chunks;
     __syncthreads();  // s_wave reused
-    const int my_cho = block_exclusive_scan(my_ch, s_wave, &total_chunks);
+    const int packed_cho = block_exclusive_scan(packed_ch, s_wave, &packed_chunks);
+    const int sel = (packed_chunks & 0x3FF) <= kRasterThreads
+                        ? 0
+                        : (((packed_chunks >> 10) & 0x3FF) <= kRasterThreads ? 10 : 20);
+    const int R = sel == 0 ? r_min : (sel == 10 ? r_mid : r_safe);
+    const int my_ch = (packed_ch >> sel) & 0x3FF;
+    const int my_cho = (packed_cho >> sel) & 0x3FF;
+    const int total_chunks = (packed_chunks >> sel) & 0x3FF;
     {
       int o = my_off;
 #pragma unroll
