@@ -481,15 +481,25 @@ def timed_fit(fitter, iters, torch):
     return dt
 
 
-def single_pass_step(torch, nat, w, target, params, cap, steps, warmup, ref_fit, e_fwd, e_bwd):
+def single_pass_step(torch, nat, w, target, params, cap, steps, warmup, ref_fit, e_fwd, e_bwd,
+                     fixed_config=None):
     """The same fit (same initial state, trajectory and pair capacity) with the single-pass L1
-    kernel in place of the fused forward + adjoint pair: graph-replayed iterations, then the
-    kernels timed with HIP events on eager launches; the parameters after warmup + steps
-    iterations must equal the two-pass fitter's."""
+    kernel in place of the fused forward + adjoint pair, under launch settings tuned on this
+    fitter (or the fixed ones given): graph-replayed iterations, then the kernels timed with HIP
+    events on eager launches; the parameters after warmup + steps iterations must equal the
+    two-pass fitter's."""
     from paper_2407_01866_amd.fit import PlainFitter
+    from paper_2407_01866_amd.tune import autotune
     f = PlainFitter(target, params, w.K, pair_capacity=cap, single_pass=True)
     init = f.snapshot()
     total = warmup + steps
+    if fixed_config is not None:
+        f.launch_config, tune_times = fixed_config, {}
+    else:
+        _, tune_times = autotune(f, iters=10, warmup=3)
+    log(f"[bench] single-pass launch config {f.launch_config}: " +
+        ", ".join(f"{c}={t * 1e3:.3f} ms" for c, t in tune_times.items()))
+    f.restore(init)
     f.capture()
     for _ in range(warmup):
         f.step()
@@ -525,7 +535,7 @@ def single_pass_step(torch, nat, w, target, params, cap, steps, warmup, ref_fit,
                 "frac": round(ach / PEAK_LANE_OPS, 4), "traffic": measured_traffic("raster_fit"),
                 "valu_counters": measured_valu("raster_fit"), "avg_ms": round(avg["raster_fit"], 4),
                 "work_per_launch": f"{ops:.4g} VALU lane-ops"}
-    return dt / steps * 1e3, avg, roofline, same
+    return dt / steps * 1e3, avg, roofline, same, f.launch_config, tune_times
 
 
 def batched_vs_plain(torch, dev, iters, count=64, single_pass=True, wl=None):
@@ -624,9 +634,10 @@ def main():
                     help="skip the random-access decoding measurement")
     ap.add_argument("--ssim-profile", action="store_true",
                     help="only run 20 L1 + SSIM loss calls at the workload (for kernel traces)")
-    ap.add_argument("--launch-config", metavar="P,W,C",
-                    help="fixed launch settings (persistent, wgs_per_cu, fwd_cull) instead of "
-                         "autotuning (profiling runs use the autotuner's choice)")
+    ap.add_argument("--launch-config", metavar="P,W,C[,B,K]",
+                    help="fixed launch settings (persistent, wgs_per_cu, fwd_cull[, fwd_batch, "
+                         "k_unroll]) instead of autotuning (profiling runs use the autotuner's "
+                         "choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -683,8 +694,9 @@ def main():
     # result-invariant launch settings, chosen by timing this fitter (state restored afterwards)
     from paper_2407_01866_amd.tune import autotune, set_config
     if args.launch_config:
-        tuned = tuple(int(v) for v in args.launch_config.split(","))
-        set_config(tuned)
+        set_config(tuple(int(v) for v in args.launch_config.split(",")))
+        tuned = nat.igs_get_launch_config().as_tuple()
+        fitter.launch_config = tuned
         tune_times = {}
     else:
         tuned, tune_times = autotune(fitter, iters=10, warmup=3)
@@ -756,7 +768,8 @@ def main():
     if not args.no_single_pass:
         log("[bench] single-pass L1 fitting kernel (same trajectory)")
         single = single_pass_step(torch, nat, w, target, params, fitter.r.cap, args.steps,
-                                  args.warmup, fitter.fit, e_fwd, e_bwd)
+                                  args.warmup, fitter.fit, e_fwd, e_bwd,
+                                  tuned if args.launch_config else None)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -784,14 +797,20 @@ def main():
                      "Adam (HIP graph)" if fitter.fused else
                      "binning + render + L1 gradient + adjoint + gradient reduction + Adam "
                      "(HIP graph)")
+    def config_record(cfg, times):
+        return {"persistent": cfg[0], "wgs_per_cu": cfg[1], "fwd_cull": cfg[2],
+                "fwd_batch": cfg[3] or 192, "k_unroll": cfg[4],
+                "autotune_ms": {str(c): round(t * 1e3, 4) for c, t in times.items()}}
+
     two_pass = {"step": two_pass_step, "ms_per_step": ms_per_step,
+                "launch_config": config_record(tuned, tune_times),
                 "fit_iters_per_s": 1e3 / ms_per_step,
                 "fwd_bwd_evals_per_s": e_fwd / (fwdbwd_ms * 1e-3),
                 "phase_ms": {k: round(v, 4) for k, v in avg.items() if v > 0},
                 "roofline": roofline, "roofline_adjoint": roofline_bwd}
     if single is not None:
         # the headline step: the single-pass kernel (same loss, gradient and trajectory)
-        sp_ms, sp_avg, sp_roof, same = single
+        sp_ms, sp_avg, sp_roof, same, sp_cfg, sp_times = single
         if not same:
             raise RuntimeError("the single-pass fit diverged from the two-pass fit")
         head = {"step": "binning + single-pass render, L1 loss and adjoint + gradient reduction "
@@ -799,7 +818,7 @@ def main():
                 "fwd_bwd_evals_per_s": e_fwd / ((sp_avg["binning"] + sp_avg["raster_fit"] +
                                                  sp_avg["loss"] + sp_avg["grad_reduce"]) * 1e-3),
                 "phase_ms": {k: round(v, 4) for k, v in sp_avg.items() if v > 0},
-                "roofline": sp_roof}
+                "launch_config": config_record(sp_cfg, sp_times), "roofline": sp_roof}
     else:
         head, two_pass = two_pass, None
     ms_per_step = head["ms_per_step"]
@@ -816,8 +835,7 @@ def main():
         "phase_ms": head["phase_ms"],
         "E_fwd": e_fwd, "E_bwd": e_bwd, "pairs": pairs,
         "E_fwd_first_last": [evals[args.warmup][0], evals[-1][0]],
-        "launch_config": {"persistent": tuned[0], "wgs_per_cu": tuned[1], "fwd_cull": tuned[2],
-                          "autotune_ms": {str(c): round(t * 1e3, 4) for c, t in tune_times.items()}},
+        "launch_config": head["launch_config"],
         "roofline": head["roofline"],
         "two_pass": two_pass, "cpu_baseline": cpu, "ssim_step": ssim, "decode": decode,
         "paper_context": ctx, "batched_vs_plain": batch, "large_config": large,

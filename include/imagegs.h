@@ -507,22 +507,33 @@ igs_status igs_fit_to_render_batched(const float *fit_params, float *render_para
                                      void *stream);
 
 /*
- * Launch settings of the raster kernels, process-wide; they apply to calls issued afterwards
- * (a captured graph keeps the settings it was captured with).  No setting changes any output
- * bit; they only trade scheduling strategies, which is what an autotuner may choose among:
+ * Launch settings of the raster kernels, per host thread (every thread starts from the
+ * defaults); they apply to calls the thread issues afterwards (a captured graph keeps the
+ * settings it was captured with), so callers that interleave work tuned differently set theirs
+ * before enqueueing it.  No setting changes any output bit; they only trade scheduling and
+ * blocking strategies, which is what an autotuner may choose among:
  *   persistent  0: one workgroup per tile (default); 1: a resident grid of wgs_per_cu workgroups
  *               per CU pulls tiles from per-XCD queues in the same order (the queues live in the
- *               workspace and are cleared by a kernel before each launch, so capture is safe)
+ *               workspace and are cleared by a kernel before each launch, so capture is safe);
+ *               applies to the forward, adjoint and single-pass raster kernels
  *   wgs_per_cu  persistent grid size per CU, 0..64 (0 = as many as the kernel's resources allow)
  *   fwd_cull    1 (default): the forward visits candidates in ascending order of a lower bound of
  *               the Mahalanobis form over the tile and skips, per wave, candidates that cannot
  *               enter any of the wave's lists; 0: every candidate is ranked at every pixel
+ *   fwd_batch   members of S_j the forward stages in LDS at a time, a multiple of 32 in
+ *               [64, 256] (0 = 192); a tile whose S_j fits one batch also keeps its members'
+ *               blend data there
+ *   k_unroll    length of the forward's register-resident sorted list: the smallest compiled
+ *               length (1, 2, 4, 8, 10, 16, 32) >= max(K, k_unroll), 0 = the smallest >= K; its
+ *               first K entries are the top-K whatever its length (keys are unique)
  * Errors: IGS_ERR_INVALID_ARG (NULL or out-of-range fields).
  */
 typedef struct {
   int32_t persistent;
   int32_t wgs_per_cu;
   int32_t fwd_cull;
+  int32_t fwd_batch;
+  int32_t k_unroll;
 } igs_launch_config;
 igs_status igs_set_launch_config(const igs_launch_config *cfg);
 igs_status igs_get_launch_config(igs_launch_config *cfg);

@@ -60,14 +60,16 @@ class ImageDesc(ctypes.Structure):
 class LaunchConfig(ctypes.Structure):
     """Mirror of igs_launch_config (include/imagegs.h)."""
     _fields_ = [("persistent", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
-                ("fwd_cull", ctypes.c_int32)]
+                ("fwd_cull", ctypes.c_int32), ("fwd_batch", ctypes.c_int32),
+                ("k_unroll", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.persistent, self.wgs_per_cu, self.fwd_cull)
+        return (self.persistent, self.wgs_per_cu, self.fwd_cull, self.fwd_batch, self.k_unroll)
 
     def __repr__(self):
         return (f"LaunchConfig(persistent={self.persistent}, wgs_per_cu={self.wgs_per_cu}, "
-                f"fwd_cull={self.fwd_cull})")
+                f"fwd_cull={self.fwd_cull}, fwd_batch={self.fwd_batch}, "
+                f"k_unroll={self.k_unroll})")
 
 
 class IGSError(RuntimeError):
@@ -429,8 +431,9 @@ def igs_fit_to_render(fit_params, render_params, N, n, H, W, stream=None) -> Non
         _stream(stream)))
 
 
-def igs_set_launch_config(persistent: int = 0, wgs_per_cu: int = 0, fwd_cull: int = 1) -> None:
-    cfg = LaunchConfig(persistent, wgs_per_cu, fwd_cull)
+def igs_set_launch_config(persistent: int = 0, wgs_per_cu: int = 0, fwd_cull: int = 1,
+                          fwd_batch: int = 0, k_unroll: int = 0) -> None:
+    cfg = LaunchConfig(persistent, wgs_per_cu, fwd_cull, fwd_batch, k_unroll)
     _check("igs_set_launch_config", lib().igs_set_launch_config(ctypes.byref(cfg)))
 
 

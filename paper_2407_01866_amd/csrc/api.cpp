@@ -156,7 +156,9 @@ static T *at(void *base, size_t off) {
 
 namespace igs {
 
-static LaunchConfig g_launch_config{0, 0, 1};
+// per host thread: each thread starts from the defaults, and a fitter applies its own settings
+// on the thread that enqueues its work
+static thread_local LaunchConfig g_launch_config{0, 0, 1, 0, 0};
 
 LaunchConfig launch_config() { return g_launch_config; }
 void set_launch_config(const LaunchConfig &c) { g_launch_config = c; }
@@ -183,7 +185,7 @@ using namespace igs;
     if ((call) != hipSuccess) return IGS_ERR_HIP; \
   } while (0)
 
-IGS_API int32_t igs_abi_version(void) { return 1; }
+IGS_API int32_t igs_abi_version(void) { return 2; }
 
 IGS_API const char *igs_status_string(igs_status s) {
   switch (s) {
@@ -372,7 +374,8 @@ igs_status fit_l1_impl(const float *params, const Dims &d, const Images &imgs, b
   {
     PhaseTimer timer(kPhaseRasterFit, s);
     IGS_HIP(launch_raster_fit(ranges, vals, src, g32a, g32b, g64, params, d, imgs,
-                              batched ? order : nullptr, target, l1_part, part, s));
+                              batched ? order : nullptr, target, l1_part, part,
+                              at<int>(workspace, WL.queue_fwd), s));
   }
   {
     PhaseTimer timer(kPhaseLoss, s);
@@ -1009,18 +1012,23 @@ IGS_API igs_status igs_fit_to_render_batched(const float *fit_params, float *ren
 
 IGS_API igs_status igs_set_launch_config(const igs_launch_config *cfg) {
   if (!cfg || (cfg->persistent != 0 && cfg->persistent != 1) || cfg->wgs_per_cu < 0 ||
-      cfg->wgs_per_cu > 64 || (cfg->fwd_cull != 0 && cfg->fwd_cull != 1))
+      cfg->wgs_per_cu > 64 || (cfg->fwd_cull != 0 && cfg->fwd_cull != 1) ||
+      (cfg->fwd_batch != 0 && (cfg->fwd_batch < 64 || cfg->fwd_batch > kFwdBatchMax ||
+                               cfg->fwd_batch % 32 != 0)) ||
+      cfg->k_unroll < 0 || cfg->k_unroll > IGS_MAX_K)
     return IGS_ERR_INVALID_ARG;
-  set_launch_config(LaunchConfig{cfg->persistent, cfg->wgs_per_cu, cfg->fwd_cull});
+  set_launch_config(LaunchConfig{cfg->persistent, cfg->wgs_per_cu, cfg->fwd_cull, cfg->fwd_batch,
+                                 cfg->k_unroll});
   return IGS_OK;
 }
-
 IGS_API igs_status igs_get_launch_config(igs_launch_config *cfg) {
   if (!cfg) return IGS_ERR_INVALID_ARG;
   const LaunchConfig c = launch_config();
   cfg->persistent = c.persistent;
   cfg->wgs_per_cu = c.wgs_per_cu;
   cfg->fwd_cull = c.fwd_cull;
+  cfg->fwd_batch = c.fwd_batch;
+  cfg->k_unroll = c.k_unroll;
   return IGS_OK;
 }
 

@@ -30,7 +30,7 @@ enum StatusWord {
 
 // Radix sort geometry.
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortTileItems = kSortThreads * kSortItems;  // keys per sort block
 
 // Scan geometry.
@@ -40,16 +40,23 @@ constexpr int kScanBlockItems = kScanThreads * kScanItems;
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
-// Process-wide launch settings of the raster kernels (igs_set_launch_config).  None of them
-// changes a result bit: they choose how tiles are scheduled and whether the forward may skip
-// candidates that provably cannot enter a list.
+// Launch settings of the raster kernels, per host thread (igs_set_launch_config).  None of them
+// changes a result bit: they choose how tiles are scheduled, whether the forward may skip
+// candidates that provably cannot enter a list, how many candidates the forward stages in LDS at
+// a time and how long its register-resident list is (its first K entries are the top-K whatever
+// its length, because keys are unique).
 struct LaunchConfig {
   int persistent;  // 0: one workgroup per tile; 1: resident workgroups pulling tiles
   int wgs_per_cu;  // persistent grid size per CU; <= 0: as many as fit
   int fwd_cull;    // forward candidate ordering and wave-level culling
+  int fwd_batch;   // candidates per forward LDS batch, a multiple of 32 in [64, 256]; 0: 192
+  int k_unroll;    // list length: the smallest compiled one >= max(K, k_unroll); 0: >= K
 };
 LaunchConfig launch_config();
 void set_launch_config(const LaunchConfig &c);
+constexpr int kFwdBatchDefault = 192;
+constexpr int kFwdBatchMax = 256;
+inline int fwd_batch_of(const LaunchConfig &c) { return c.fwd_batch > 0 ? c.fwd_batch : kFwdBatchDefault; }
 // Persistent grid: per_cu workgroups on every CU of the current device, a multiple of 8 (one
 // share per XCD), at least 8, and no more than needed for T tiles (rounded up to 8).
 int persistent_grid(int per_cu, int T);
@@ -233,7 +240,7 @@ hipError_t launch_raster_fit(const int2 *ranges, const uint32_t *vals, const uin
                              const float4 *g32a, const float2 *g32b, const double4 *g64,
                              const float *params, const Dims &d, const Images &imgs,
                              const int *tile_order, const float *target, double2 *loss_part,
-                             float *part, hipStream_t s);
+                             float *part, int *queue, hipStream_t s);
 
 // loss_adam.hip
 // SSIM strips of one channel plane of an H x W image in the batched stencils (32 x 128 each).

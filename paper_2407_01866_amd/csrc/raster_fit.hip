@@ -13,15 +13,17 @@
 //   3. adjoint_batches: the per-pair gradient records.
 // Loss, records and hence the gradient are therefore bit for bit those of the fused forward +
 // adjoint pair.  LDS is the larger of the two phases' and the register budget the adjoint's.
+#include <algorithm>
+
 #include "raster_tile.hpp"
 
 namespace igs {
 namespace {
 
 template <int NC, int KT>
-__host__ __device__ constexpr size_t fit_lds_bytes() {
-  return fwd_lds_bytes(NC) > bwd_lds<NC, KT>().total ? fwd_lds_bytes(NC)
-                                                     : (size_t)bwd_lds<NC, KT>().total;
+__host__ __device__ constexpr size_t fit_lds_bytes(int fb) {
+  return fwd_lds_bytes(NC, fb) > bwd_lds<NC, KT>().total ? fwd_lds_bytes(NC, fb)
+                                                         : (size_t)bwd_lds<NC, KT>().total;
 }
 
 // Register budget: five waves per SIMD (<= 96 VGPRs; the LDS of up to n = 9 also lets five
@@ -31,7 +33,10 @@ __host__ __device__ constexpr int fit_min_waves(int nc, int kt) {
   return (nc <= 9 && kt <= 10) ? 5 : ((nc + kt <= 25 && !(nc >= 16 && kt >= 4)) ? 4 : 2);
 }
 
-template <int NC, int KT>
+// P: persistent scheduling, resident workgroups taking tiles from the shared queue (a
+// compile-time choice so that the one-workgroup-per-tile kernel keeps the register budget of
+// straight-line code).
+template <int NC, int KT, bool P>
 __global__ __launch_bounds__(kRasterThreads)
 __attribute__((amdgpu_waves_per_eu(fit_min_waves(NC, KT)))) void raster_fit_kernel(
     const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
@@ -39,13 +44,16 @@ __attribute__((amdgpu_waves_per_eu(fit_min_waves(NC, KT)))) void raster_fit_kern
     const float2 *__restrict__ g32b, const double4 *__restrict__ g64,
     const float *__restrict__ params, int N, int n, int K, int T, Images imgs,
     const int *__restrict__ tile_order, const float *__restrict__ target_all,
-    double2 *__restrict__ loss_part, float *__restrict__ part, int cull) {
+    double2 *__restrict__ loss_part, float *__restrict__ part, TileQueue queue, int cull,
+    int fb) {
   constexpr int ROW = px_row<NC>();
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[2 * kWaves];
-  const FwdLds S = fwd_lds(smem);
+  const FwdLds S = fwd_lds(smem, fb);
   const int tid = threadIdx.x;
-  const int idx = blockIdx.x;  // the grid is exactly T workgroups
+  int idx = 0;
+  if (!P) queue.persistent = 0;
+  for (bool first = true; next_tile_index(queue, T, first, idx); first = false) {
   const int tile = __builtin_amdgcn_readfirstlane(tile_order ? tile_order[idx] : xcd_tile(idx, T));
   const ImageDesc im = imgs.by_tile(tile);
   const int W = im.W, H = im.H;
@@ -59,7 +67,7 @@ __attribute__((amdgpu_waves_per_eu(fit_min_waves(NC, KT)))) void raster_fit_kern
   const int2 rg = ranges[tile];
   const int start = __builtin_amdgcn_readfirstlane(rg.x);
   const int cnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
-  const bool single = cnt <= kFwdBatch;
+  const bool single = cnt <= fb;
 
   double tk[KT];
   rank_tile<KT>(S, start, cnt, single, tx, ty, fx, fy, vals, g32a, g32b, g64, params, N, n, cull,
@@ -133,24 +141,41 @@ __attribute__((amdgpu_waves_per_eu(fit_min_waves(NC, KT)))) void raster_fit_kern
   store_px_row<NC>(smem, row);
   adjoint_batches<NC, KT>(smem, start, cnt, x0, y0, sl, vals, src, g32a, g64, params, N, n,
                           part);
+  }
 }
 
-template <int NC, int KT>
+template <int NC, int KT, bool P>
 hipError_t launch_fit_t(const int2 *ranges, const uint32_t *vals, const uint32_t *src,
                         const float4 *g32a, const float2 *g32b, const double4 *g64,
                         const float *params, const Dims &d, const Images &imgs,
                         const int *tile_order, const float *target, double2 *loss_part,
-                        float *part, hipStream_t s) {
-  constexpr size_t lds = fit_lds_bytes<NC, KT>();
+                        float *part, int *queue, hipStream_t s) {
+  const LaunchConfig cfg = launch_config();
+  const int fb = fwd_batch_of(cfg);
+  const size_t lds = fit_lds_bytes<NC, KT>(fb);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)raster_fit_kernel<NC, KT>,
+    hipError_t e = hipFuncSetAttribute((const void *)raster_fit_kernel<NC, KT, P>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   if (d.T <= 0) return hipSuccess;
-  raster_fit_kernel<NC, KT><<<d.T, kRasterThreads, lds, s>>>(
+  TileQueue q{queue, 0};
+  int grid = d.T;
+  if (P) {
+    int per_cu = cfg.wgs_per_cu;
+    if (per_cu <= 0) {
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, (const void *)raster_fit_kernel<NC, KT, P>, kRasterThreads, lds);
+      if (e != hipSuccess) return e;
+    }
+    grid = persistent_grid(per_cu, d.T);
+    q.persistent = 1;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(queue), 8, 0u, s);
+    if (e != hipSuccess) return e;
+  }
+  raster_fit_kernel<NC, KT, P><<<grid, kRasterThreads, lds, s>>>(
       ranges, vals, src, g32a, g32b, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, target,
-      loss_part, part, launch_config().fwd_cull);
+      loss_part, part, q, cfg.fwd_cull, fb);
   return hipGetLastError();
 }
 
@@ -159,12 +184,18 @@ hipError_t launch_fit_nc(const int2 *ranges, const uint32_t *vals, const uint32_
                          const float4 *g32a, const float2 *g32b, const double4 *g64,
                          const float *params, const Dims &d, const Images &imgs,
                          const int *tile_order, const float *target, double2 *loss_part,
-                         float *part, hipStream_t s) {
-  const int kt = pick_kt(d.K);
+                         float *part, int *queue, hipStream_t s) {
+  const LaunchConfig cfg = launch_config();
+  const int kt = pick_kt(std::max(d.K, cfg.k_unroll));
+  const bool pers = cfg.persistent != 0;
 #define IGS_FIT_KT(KTV)                                                                         \
-  if (kt == KTV)                                                                                \
-    return launch_fit_t<NC, KTV>(ranges, vals, src, g32a, g32b, g64, params, d, imgs, tile_order, \
-                                 target, loss_part, part, s);
+  if (kt == KTV) {                                                                              \
+    if (pers)                                                                                   \
+      return launch_fit_t<NC, KTV, true>(ranges, vals, src, g32a, g32b, g64, params, d, imgs,   \
+                                         tile_order, target, loss_part, part, queue, s);        \
+    return launch_fit_t<NC, KTV, false>(ranges, vals, src, g32a, g32b, g64, params, d, imgs,    \
+                                        tile_order, target, loss_part, part, queue, s);         \
+  }
   IGS_FOR_EACH_KT(IGS_FIT_KT)
 #undef IGS_FIT_KT
   return hipErrorInvalidValue;
@@ -176,11 +207,11 @@ hipError_t launch_raster_fit(const int2 *ranges, const uint32_t *vals, const uin
                              const float4 *g32a, const float2 *g32b, const double4 *g64,
                              const float *params, const Dims &d, const Images &imgs,
                              const int *tile_order, const float *target, double2 *loss_part,
-                             float *part, hipStream_t s) {
+                             float *part, int *queue, hipStream_t s) {
 #define IGS_FIT_NC(NCV)                                                                     \
   if (d.n <= NCV)                                                                           \
     return launch_fit_nc<NCV>(ranges, vals, src, g32a, g32b, g64, params, d, imgs, tile_order, \
-                              target, loss_part, part, s);
+                              target, loss_part, part, queue, s);
   IGS_FIT_NC(1)
   IGS_FIT_NC(3)
   IGS_FIT_NC(4)

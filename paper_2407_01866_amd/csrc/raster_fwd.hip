@@ -14,6 +14,8 @@
 // min/max are not wrapped in NaN-quieting instructions; q is clamped below 1e38 before packing so a
 // non-finite value can only rank last.
 // Candidate order and wave-level culling are described with rank_tile.
+#include <algorithm>
+
 #include "raster_tile.hpp"
 
 namespace igs {
@@ -68,9 +70,9 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
     const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n, int K, int T,
     Images imgs, const int *__restrict__ tile_order, float *__restrict__ image_all,
     uint16_t *__restrict__ slots_all, float2 *__restrict__ aux_all, L1Out l1, TileQueue queue,
-    int cull) {
+    int cull, int fb) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const FwdLds S = fwd_lds(smem);
+  const FwdLds S = fwd_lds(smem, fb);
   const int ncp = n;
 
   const int tid = threadIdx.x;
@@ -93,7 +95,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
   // uniform over the workgroup; readfirstlane keeps the loop bounds in scalar registers
   const int start = __builtin_amdgcn_readfirstlane(rg.x);
   const int cnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
-  const bool single = cnt <= kFwdBatch;  // whole S_j stays resident for the blend
+  const bool single = cnt <= fb;  // whole S_j stays resident for the blend
 
   double tk[KT];
   rank_tile<KT>(S, start, cnt, single, tx, ty, fx, fy, vals, g32a, g32b, g64, params, N, n, cull,
@@ -255,8 +257,9 @@ hipError_t launch_fwd_t(const int2 *ranges, const uint32_t *vals, const float4 *
                         const Dims &d, const Images &imgs, const int *tile_order, float *image,
                         uint16_t *slots, float2 *aux, const L1Out &l1, int *queue,
                         hipStream_t s) {
-  const size_t lds = kFwdLdsFixed + (size_t)d.n * kFwdBatch * sizeof(float);
   const LaunchConfig cfg = launch_config();
+  const int fb = fwd_batch_of(cfg);
+  const size_t lds = fwd_lds_bytes(d.n, fb);
   TileQueue q{queue, 0};
   int grid = d.T;
   if (P) {
@@ -273,7 +276,7 @@ hipError_t launch_fwd_t(const int2 *ranges, const uint32_t *vals, const float4 *
   }
   raster_fwd_kernel<KT, L1, P><<<grid, kRasterThreads, lds, s>>>(
       ranges, vals, g32a, g32b, g64, params, d.N, d.n, d.K, d.T, imgs, tile_order, image, slots,
-      aux, l1, q, cfg.fwd_cull);
+      aux, l1, q, cfg.fwd_cull, fb);
   return hipGetLastError();
 }
 
@@ -284,7 +287,7 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
                              const Dims &d, const Images &imgs, const int *tile_order,
                              float *image, uint16_t *slots, float2 *aux, const float *target,
                              float2 *l1_rec, double2 *l1_part, int *queue, hipStream_t s) {
-  const int kt = pick_kt(d.K);
+  const int kt = pick_kt(std::max(d.K, launch_config().k_unroll));
   const L1Out l1{target, l1_rec, l1_part};
   const bool fused = target != nullptr;
   const bool pers = launch_config().persistent != 0;

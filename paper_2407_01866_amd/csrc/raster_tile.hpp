@@ -23,17 +23,16 @@ namespace igs {
 // enter any of their lists and is skipped by the whole wave, and once the bucket floor exceeds it
 // the wave stops.  Winners come early in this order, so most of the tail is skipped.
 
-// Candidates staged in LDS per batch: 192 keeps the forward's LDS (124 B per candidate for n = 9)
-// small enough for six workgroups per CU, the occupancy its registers allow.
-constexpr int kFwdBatch = 192;
-// LDS bytes before the colour rows: per candidate 48 B of ranking data in visiting order and 40 B
-// of blend geometry in slot order, then the bucket counters.
-constexpr unsigned kFwdLdsFixed = 88 * kFwdBatch + 2 * 16 * 4;
+// Candidates staged in LDS per batch: fb, a launch setting (default 192, which keeps the
+// forward's LDS, 124 B per candidate at n = 9, small enough for six workgroups per CU).  Per
+// candidate 48 B of ranking data in visiting order and 40 B of blend geometry in slot order, then
+// the bucket counters, then the colour rows.
 constexpr int kBuckets = 16;
 constexpr int kWaves = kRasterThreads / 64;  // each wave covers 4 rows of the tile
 
-__host__ __device__ constexpr size_t fwd_lds_bytes(int n) {
-  return kFwdLdsFixed + (size_t)n * kFwdBatch * sizeof(float);
+__host__ __device__ constexpr size_t fwd_lds_fixed(int fb) { return 88 * (size_t)fb + 2 * 16 * 4; }
+__host__ __device__ constexpr size_t fwd_lds_bytes(int n, int fb) {
+  return fwd_lds_fixed(fb) + (size_t)n * fb * sizeof(float);
 }
 
 // Minimum of q over the rectangle [dxa, dxb] x [dya, dyb] of offsets from the mean: 0 if the
@@ -125,30 +124,32 @@ __device__ __forceinline__ double wave_inclusive_sum_f64(double v) {
 struct FwdLds {
   float4 *pgeo;   // mu_x, mu_y, A, B
   float4 *pcd;    // C, D, slot, bucket floor
-  float *plbw;    // [kWaves][kFwdBatch] bounds
+  float *plbw;    // [kWaves][fb] bounds
   float2 *mu;     // mu_x, mu_y
-  double *s64;    // [kFwdBatch][4] A, B, C, D
+  double *s64;    // [fb][4] A, B, C, D
   int *bcnt;      // [kBuckets] counters
   int *bstart;    // [kBuckets] starts
-  float *col;     // [kFwdBatch][n]
+  float *col;     // [fb][n]
+  int fb;         // candidates per batch
 };
 
-__device__ __forceinline__ FwdLds fwd_lds(unsigned char *smem) {
+__device__ __forceinline__ FwdLds fwd_lds(unsigned char *smem, int fb) {
   FwdLds S;
   S.pgeo = reinterpret_cast<float4 *>(smem);
-  S.pcd = reinterpret_cast<float4 *>(smem + 16 * kFwdBatch);
-  S.plbw = reinterpret_cast<float *>(smem + 32 * kFwdBatch);
-  S.mu = reinterpret_cast<float2 *>(smem + 48 * kFwdBatch);
-  S.s64 = reinterpret_cast<double *>(smem + 56 * kFwdBatch);
-  S.bcnt = reinterpret_cast<int *>(smem + 88 * kFwdBatch);
+  S.pcd = reinterpret_cast<float4 *>(smem + 16 * fb);
+  S.plbw = reinterpret_cast<float *>(smem + 32 * fb);
+  S.mu = reinterpret_cast<float2 *>(smem + 48 * fb);
+  S.s64 = reinterpret_cast<double *>(smem + 56 * fb);
+  S.bcnt = reinterpret_cast<int *>(smem + 88 * fb);
   S.bstart = S.bcnt + kBuckets;
-  S.col = reinterpret_cast<float *>(smem + kFwdLdsFixed);
+  S.col = reinterpret_cast<float *>(smem + fwd_lds_fixed(fb));
+  S.fb = fb;
   return S;
 }
 
 // Ranks the tile's hit set S_j = vals[start, start + cnt) at the pixel centre (fx, fy) of the
 // calling lane: tk receives the lane's KT smallest keys in ascending order (kKeyEmpty past the
-// last member).  single (cnt <= kFwdBatch): the blend geometry and colours of every member are
+// last member).  single (cnt <= S.fb): the blend geometry and colours of every member are
 // left in LDS, in slot order, for the blend.  Every thread of the workgroup calls it.
 template <int KT>
 __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, bool single, int tx,
@@ -166,8 +167,9 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
 
   const int wave = tid >> 6;
   if (tid < kBuckets) S.bcnt[tid] = 0;
-  for (int base = 0; base < cnt; base += kFwdBatch) {
-    const int nb = min(kFwdBatch, cnt - base);
+  const int fb = S.fb;
+  for (int base = 0; base < cnt; base += fb) {
+    const int nb = min(fb, cnt - base);
     __syncthreads();
     int bucket = 0, brank = 0;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -224,7 +226,7 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
       S.pgeo[pos] = a;
       S.pcd[pos] = make_float4(b.x, b.y, __int_as_float(base + tid), bucket_floor(bucket));
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) S.plbw[w * kFwdBatch + pos] = lbw[w];
+      for (int w = 0; w < kWaves; ++w) S.plbw[w * fb + pos] = lbw[w];
     }
     if (tid < kBuckets) S.bcnt[tid] = 0;  // ready for the next batch
     __syncthreads();
@@ -237,8 +239,8 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
       // every later candidate's bound is at least the floor of this position's bucket
       if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(S.pcd[m].w))) > q_tau)
         break;
-      const float4 lba = *reinterpret_cast<const float4 *>(&S.plbw[wave * kFwdBatch + m]);
-      const float4 lbb = *reinterpret_cast<const float4 *>(&S.plbw[wave * kFwdBatch + m + 4]);
+      const float4 lba = *reinterpret_cast<const float4 *>(&S.plbw[wave * fb + m]);
+      const float4 lbb = *reinterpret_cast<const float4 *>(&S.plbw[wave * fb + m + 4]);
       const float lbu[8] = {lba.x, lba.y, lba.z, lba.w, lbb.x, lbb.y, lbb.z, lbb.w};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {

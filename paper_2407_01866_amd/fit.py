@@ -65,9 +65,17 @@ class AdamConfig:
 
 class _FitLoop:
     """Iteration bookkeeping shared by the plain and batched fitters: graph capture, the device
-    step counter, and repetition of iterations whose render overflowed the pair buffer."""
+    step counter, repetition of iterations whose render overflowed the pair buffer, and the
+    fitter's own raster launch settings (``launch_config``: a (persistent, wgs_per_cu, fwd_cull,
+    fwd_batch, k_unroll) tuple applied on the enqueueing thread before every eager step and
+    capture; None keeps the thread's current settings)."""
 
     graph = None
+    launch_config = None
+
+    def _apply_launch_config(self) -> None:
+        if self.launch_config is not None:
+            nat.igs_set_launch_config(*self.launch_config)
 
     def capture(self) -> None:
         """Capture one iteration as a HIP graph (the library allocates nothing, so buffers and
@@ -293,6 +301,7 @@ class PlainFitter(_FitLoop):
 
     def step_async(self) -> None:
         """Enqueue one iteration on the current stream (no synchronization)."""
+        self._apply_launch_config()
         a = self.adam
         if self.single_pass:
             self.r.l1_grad_into(self.rend, self.target, self.loss, self.grad_params, self.saved)
@@ -418,6 +427,7 @@ class BatchFitter(_FitLoop):
         self.status_host = torch.zeros(8, dtype=torch.int64).pin_memory()
 
     def step_async(self) -> None:
+        self._apply_launch_config()
         a = self.adam
         r = self.r
         if self.single_pass:

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(nat):
 
 
 def test_abi_version_and_status_strings(nat):
-    assert nat.igs_abi_version() == 1
+    assert nat.igs_abi_version() == 2
     assert nat.igs_status_string(0) == "ok"
     for s in (-1, -2, -3, -4):
         assert nat.igs_status_string(s) not in ("ok", "unknown status")
@@ -206,17 +206,40 @@ def test_decoding_validates_before_device_work(nat):
 def test_launch_config_roundtrip_and_validation(nat):
     L = nat.lib()
     try:
-        nat.igs_set_launch_config(1, 6, 0)
-        assert nat.igs_get_launch_config().as_tuple() == (1, 6, 0)
-        for bad in ((2, 0, 1), (0, -1, 1), (0, 65, 1), (0, 0, 2)):
+        nat.igs_set_launch_config(1, 6, 0, 128, 16)
+        assert nat.igs_get_launch_config().as_tuple() == (1, 6, 0, 128, 16)
+        for bad in ((2, 0, 1), (0, -1, 1), (0, 65, 1), (0, 0, 2), (0, 0, 1, 32), (0, 0, 1, 288),
+                    (0, 0, 1, 100), (0, 0, 1, 0, -1), (0, 0, 1, 0, 33)):
             with pytest.raises(nat.IGSError) as e:
                 nat.igs_set_launch_config(*bad)
             assert e.value.status == -1
-        assert nat.igs_get_launch_config().as_tuple() == (1, 6, 0)
+        assert nat.igs_get_launch_config().as_tuple() == (1, 6, 0, 128, 16)
         assert L.igs_set_launch_config(None) == -1 and L.igs_get_launch_config(None) == -1
     finally:
         nat.igs_set_launch_config(0, 0, 1)
-    assert nat.igs_get_launch_config().as_tuple() == (0, 0, 1)
+    assert nat.igs_get_launch_config().as_tuple() == (0, 0, 1, 0, 0)
+
+
+def test_launch_config_is_per_host_thread(nat):
+    """A setting made on one thread leaves every other thread's settings alone, and a new thread
+    starts from the defaults."""
+    import threading
+    seen = {}
+
+    def worker():
+        seen["start"] = nat.igs_get_launch_config().as_tuple()
+        nat.igs_set_launch_config(1, 5, 0)
+        seen["set"] = nat.igs_get_launch_config().as_tuple()
+
+    try:
+        nat.igs_set_launch_config(1, 8, 1)
+        t = threading.Thread(target=worker)
+        t.start()
+        t.join()
+        assert seen == {"start": (0, 0, 1, 0, 0), "set": (1, 5, 0, 0, 0)}
+        assert nat.igs_get_launch_config().as_tuple() == (1, 8, 1, 0, 0)
+    finally:
+        nat.igs_set_launch_config(0, 0, 1)
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

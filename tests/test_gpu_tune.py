@@ -1,5 +1,6 @@
-"""Launch settings (one workgroup per tile or persistent tile queues, forward culling on or off)
-must not change a single output bit, and the autotuner must leave the fitter's state as it was."""
+"""Launch settings (one workgroup per tile or persistent tile queues, forward culling on or off,
+the forward's LDS batch size, the length of its register-resident list) must not change a single
+output bit, and the autotuner must leave the fitter's state as it was."""
 import numpy as np
 import pytest
 import torch
@@ -9,7 +10,9 @@ import paper_2407_01866_amd._native as nat
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = [(0, 0, 1), (0, 0, 0), (1, 0, 1), (1, 4, 0), (1, 1, 1), (1, 8, 1)]
+CONFIGS = [(0, 0, 1, 0, 0), (0, 0, 0, 0, 0), (1, 0, 1, 0, 0), (1, 4, 0, 0, 0), (1, 1, 1, 0, 0),
+           (1, 8, 1, 0, 0), (0, 0, 1, 64, 0), (0, 0, 1, 128, 16), (1, 0, 1, 256, 32),
+           (0, 0, 0, 96, 32)]
 
 
 def dev():
@@ -105,7 +108,8 @@ def test_autotune_restores_fitter_state():
                     w.K, headroom=3.0)
     f.advance_to(3, use_graph=False)
     fit0, step0 = f.fit.clone(), f.steps_done()
-    best, times = autotune(f, candidates=[(0, 0, 1), (1, 0, 1)], iters=2, warmup=1)
+    best, times = autotune(f, candidates=[(0, 0, 1, 0, 0), (1, 0, 1, 128, 16)], iters=2,
+                           warmup=1)
     assert best in times and len(times) == 2 and all(t > 0 for t in times.values())
     assert f.steps_done() == step0 and torch.equal(f.fit, fit0)
     assert nat.igs_get_launch_config().as_tuple() == best
@@ -113,9 +117,11 @@ def test_autotune_restores_fitter_state():
 
 
 
-def test_autotune_of_a_single_pass_fitter_times_only_the_culling_switch():
+def test_autotune_coordinate_descent_of_a_single_pass_fitter():
+    """Scheduling and culling first, then the LDS batch, then the list length; every trial
+    restores the fitter, and the fitter keeps the winner."""
     from paper_2407_01866_amd.fit import PlainFitter
-    from paper_2407_01866_amd.tune import SINGLE_PASS_CANDIDATES, autotune
+    from paper_2407_01866_amd.tune import FWD_BATCHES, SINGLE_PASS_SCHEDULES, autotune
     d = dev()
     w = synth.workload(0)
     f = PlainFitter(torch.from_numpy(w.target()).to(d), torch.from_numpy(w.gaussians()).to(d),
@@ -123,6 +129,35 @@ def test_autotune_of_a_single_pass_fitter_times_only_the_culling_switch():
     f.advance_to(3, use_graph=False)
     fit0, step0 = f.fit.clone(), f.steps_done()
     best, times = autotune(f, iters=2, warmup=1)
-    assert set(times) == set(SINGLE_PASS_CANDIDATES) and best in times
+    assert {c[:3] for c in times} == set(SINGLE_PASS_SCHEDULES)
+    assert {c[3] for c in times} == set(FWD_BATCHES) and {c[4] for c in times} == {0, 16}
+    assert len(times) == len(SINGLE_PASS_SCHEDULES) + len(FWD_BATCHES) - 1 + 1
+    assert best in times and f.launch_config == best
     assert f.steps_done() == step0 and torch.equal(f.fit, fit0)
     nat.igs_set_launch_config(0, 0, 1)
+
+
+def test_fitters_apply_their_own_launch_settings():
+    """Two fitters tuned differently, stepped alternately on one thread: each step runs under its
+    own fitter's settings (and, every setting being result-invariant, both match an untuned
+    fitter bit for bit)."""
+    from paper_2407_01866_amd.fit import PlainFitter
+    w = synth.workload(0)
+    d = dev()
+    t = torch.from_numpy(w.target()).to(d)
+    p = torch.from_numpy(w.gaussians()).to(d)
+    fa = PlainFitter(t, p, w.K)
+    fb = PlainFitter(t, p, w.K)
+    fc = PlainFitter(t, p, w.K)
+    fa.launch_config = (1, 4, 0, 128, 16)
+    fb.launch_config = (0, 0, 1, 0, 0)
+    nat.igs_set_launch_config(1, 6, 1)
+    for _ in range(3):
+        fa.step_async()
+        assert nat.igs_get_launch_config().as_tuple() == (1, 4, 0, 128, 16)
+        fb.step_async()
+        assert nat.igs_get_launch_config().as_tuple() == (0, 0, 1, 0, 0)
+        fc.step_async()                      # no own settings: the thread's current ones
+        assert nat.igs_get_launch_config().as_tuple() == (0, 0, 1, 0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(fa.fit, fc.fit) and torch.equal(fb.fit, fc.fit)
