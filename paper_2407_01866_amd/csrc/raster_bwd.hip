@@ -128,8 +128,10 @@ __device__ __forceinline__ float row_sum16(float v) {
 }
 
 // Per Gaussian, the sum of its pair records (contiguous in emit order, one per tile it hits, in
-// tile order).  Up to kRowRecords records: one row of 16 lanes, lane l adding records l, l + 16,
-// ... in that order, then the row's lanes summed with a fixed tree.  More records (a footprint of
+// tile order).  Up to kRowRecords records: one row of 16 lanes; for records of at most four
+// float4 columns (n <= 11) lane l adds column l & 3 of records l >> 2, (l >> 2) + 4, ... and the
+// four lanes of a column are added with a fixed tree, for wider ones lane l adds whole records
+// l, l + 16, ... in that order and the row's lanes are summed with a fixed tree.  More records (a footprint of
 // hundreds of tiles, which a fit can grow): the whole workgroup that holds the Gaussian's row,
 // thread t adding records t, t + 256, ... in that order, then a fixed shuffle tree per wave and
 // the four waves in order.  Every order depends only on the record count, so the result is
@@ -209,6 +211,35 @@ __device__ __forceinline__ void write_gradient(int i, const float (&acc)[NR],
     if (ch < n) grad[(size_t)(5 + ch) * N + i] = acc[5 + ch];
 }
 
+// The gradient entries that come from float4 column q of a Gaussian's record sum: column 0 holds
+// (G1, G2, G11, G22), the mean and scale entries; column 1 starts with G12, the angle entry;
+// entries 5 + ch are the colour sums.
+template <int NC>
+__device__ __forceinline__ void write_gradient_column(int i, int q, float4 a,
+                                                      const float *__restrict__ params,
+                                                      const float4 *__restrict__ g32a,
+                                                      const float2 *__restrict__ g32b, int N,
+                                                      int n, float *__restrict__ grad) {
+  const float v[4] = {a.x, a.y, a.z, a.w};
+  if (q == 0) {
+    const float4 g = g32a[i];
+    const float2 cd = g32b[i];
+    const float u1 = 1.0f / params[3 * (size_t)N + i], u2 = 1.0f / params[4 * (size_t)N + i];
+    grad[i] = -2.0f * (g.z * a.x + cd.x * a.y);
+    grad[(size_t)N + i] = -2.0f * (g.w * a.x + cd.y * a.y);
+    grad[3 * (size_t)N + i] = -2.0f * u1 * a.z;
+    grad[4 * (size_t)N + i] = -2.0f * u2 * a.w;
+  } else if (q == 1) {
+    const float u1 = 1.0f / params[3 * (size_t)N + i], u2 = 1.0f / params[4 * (size_t)N + i];
+    grad[2 * (size_t)N + i] = 2.0f * (u1 / u2 - u2 / u1) * a.x;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ch = 4 * q + e - 5;
+    if (ch >= 0 && ch < n && ch < NC) grad[(size_t)(5 + ch) * N + i] = v[e];
+  }
+}
+
 template <int NC>
 __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(
     const float *__restrict__ params, const float4 *__restrict__ g32a,
@@ -227,7 +258,46 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(
   const uint32_t c = (valid && status[kStatOverflow] == 0) ? counts[ii] : 0u;
   const bool big = c > kRowRecords;
   if (l == 0) s_big[row] = big ? c : 0u;
-  if (!big) {
+  if (!big && NR <= 16) {
+    // records of at most four float4 columns (n <= 11): lane l adds column l & 3 of records
+    // l >> 2, (l >> 2) + 4, ... in that order (the row reads four whole records per step), then
+    // the four lanes of each column are added with a fixed tree (xor 4, then xor 8), and lane q
+    // of the row writes the gradient entries of column q
+    const float4 *__restrict__ rec =
+        reinterpret_cast<const float4 *>(part + (size_t)offsets[ii] * (4 * stride4));
+    const int q = l & 3;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (q < stride4) {
+      uint32_t t = (uint32_t)(l >> 2);
+      for (; t + 12 < c; t += 16) {  // four records' loads in flight, added in record order
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = rec[(size_t)(t + 4 * u) * stride4 + q];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a.x += v[u].x;
+          a.y += v[u].y;
+          a.z += v[u].z;
+          a.w += v[u].w;
+        }
+      }
+      for (; t < c; t += 4) {
+        const float4 v = rec[(size_t)t * stride4 + q];
+        a.x += v.x;
+        a.y += v.y;
+        a.z += v.z;
+        a.w += v.w;
+      }
+    }
+#pragma unroll
+    for (int d = 4; d <= 8; d <<= 1) {
+      a.x += __shfl_xor(a.x, d, 64);
+      a.y += __shfl_xor(a.y, d, 64);
+      a.z += __shfl_xor(a.z, d, 64);
+      a.w += __shfl_xor(a.w, d, 64);
+    }
+    if (valid && l < 4) write_gradient_column<NC>(i, q, a, params, g32a, g32b, N, n, grad);
+  } else if (!big) {
     const float4 *__restrict__ rec =
         reinterpret_cast<const float4 *>(part + (size_t)offsets[ii] * (4 * stride4));
     float acc[NR];

@@ -197,8 +197,11 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
       const float A = a.z, B = a.w, C = b.x, D = b.y;
       const float p11 = fmaf(A, A, C * C), p12 = fmaf(A, B, C * D), p22 = fmaf(B, B, D * D);
       const float r1 = fmaf(A, A, B * B), r2 = fmaf(C, C, D * D);  // 1/s_1^2, 1/s_2^2
-      const float kappa = sqrtf(fmaxf(r1, r2) / fminf(r1, r2)) * 1.001f;
-      const float i11 = 1.0f / p11, i22 = 1.0f / p22;
+      // hardware reciprocals: the 0.1% widening of kappa covers their few ulps, and an inexact
+      // edge minimizer moves an edge minimum only in second order
+      const float kappa =
+          sqrtf(fmaxf(r1, r2) * __builtin_amdgcn_rcpf(fminf(r1, r2))) * 1.001f;
+      const float i11 = __builtin_amdgcn_rcpf(p11), i22 = __builtin_amdgcn_rcpf(p22);
       const float dxa = ((float)(tx * kTile) + 0.5f) - a.x;
       const float dxb = ((float)(tx * kTile + kTile - 1) + 0.5f) - a.x;
       const float tya = -p12 * dxa * i22, tyb = -p12 * dxb * i22;
