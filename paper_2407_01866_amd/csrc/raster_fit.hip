@@ -89,7 +89,8 @@ __attribute__((amdgpu_waves_per_eu(fit_min_waves(NC, KT)))) void raster_fit_kern
     const int keff = min(K, cnt);
     int ts[KT], srcg[KT];
     float w[KT], Z, shift;
-    winners<KT>(S, single, start, keff, tk, fx, fy, vals, g32a, g64, ts, w, srcg, Z, shift);
+    winners<KT, true>(S, single, start, keff, tk, fx, fy, vals, g32a, g64, ts, w, srcg, Z,
+                      shift);
     const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
     const float inv_count = (float)(1.0 / ((double)n * (double)HW));
     // channel sums in rank order; entries past the retained ones have weight 0 and index 0 (a

@@ -111,7 +111,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
   const int keff = min(K, cnt);
   int ts[KT], src[KT];
   float w[KT], Z, shift;
-  winners<KT>(S, single, start, keff, tk, fx, fy, vals, g32a, g64, ts, w, src, Z, shift);
+  winners<KT, false>(S, single, start, keff, tk, fx, fy, vals, g32a, g64, ts, w, src, Z, shift);
   if constexpr (!P) {
   const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
   const float inv_count = L1 ? (float)(1.0 / ((double)n * (double)HW)) : 0.f;

@@ -268,7 +268,9 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
 // forward skips a candidate only once the lane's list is full), so every lane's list holds
 // min(|S_j|, KT) keys and the retained entries are exactly k < keff, the same for the whole
 // workgroup: the loop over them is a uniform branch.
-template <int KT>
+// AHEAD: in the single-batch case, issue the next winner's LDS reads before this winner's
+// arithmetic (worth its ten registers in the single-pass kernel, not in the forward kernel).
+template <int KT, bool AHEAD>
 __device__ __forceinline__ void winners(const FwdLds &S, bool single, int start, int keff,
                                         const double (&tk)[KT], float fx, float fy,
                                         const uint32_t *__restrict__ vals,
@@ -283,7 +285,33 @@ __device__ __forceinline__ void winners(const FwdLds &S, bool single, int start,
     w[k] = 0.f;
     src[k] = 0;
   }
-  if (single) {
+  if (single && AHEAD) {
+    // one winner ahead: hoisting all of them would cost registers
+    double4 cn = make_double4(0.0, 0.0, 0.0, 0.0);
+    float2 mn = make_float2(0.f, 0.f);
+    if (keff > 0) {
+      cn = *reinterpret_cast<const double4 *>(&S.s64[4 * ts[0]]);
+      mn = S.mu[ts[0]];
+    }
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < keff) {
+        const double4 c = cn;
+        const float2 mu = mn;
+        if (k + 1 < keff) {
+          cn = *reinterpret_cast<const double4 *>(&S.s64[4 * ts[k + 1]]);
+          mn = S.mu[ts[k + 1]];
+        }
+        asm volatile("" ::: "memory");
+        double e1, e2;
+        const double q = quad_form64(fx, fy, mu.x, mu.y, c.x, c.y, c.z, c.w, e1, e2);
+        if (k == 0) shift = (float)q;
+        w[k] = blend_weight(q, shift);
+        Z += w[k];
+        src[k] = ts[k];
+      }
+    }
+  } else if (single) {
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
       if (k < keff) {
@@ -617,14 +645,25 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
       constexpr int LP = NR <= 16 ? 16 : (NR <= 32 ? 32 : 64);
       const int stride = part_stride(n);
       const int r = tid & (LP - 1);
-      for (int jj = tid / LP; jj < nb; jj += kRasterThreads / LP) {
-        if (r < stride) {
+      if (r < stride) {
+        for (int jj = tid / LP; jj < nb; jj += kRasterThreads / LP) {
+          const int c1 = s_cho[jj + 1];
+          const uint32_t dst = s_src[jj];
           float acc = 0.f;
           if (r < 5 + n) {
-            const int c1 = s_cho[jj + 1];
-            for (int c = s_cho[jj]; c < c1; ++c) acc += s_part[c * NACC + r];
+            int c = s_cho[jj];
+            // four chunks' loads in flight, added one at a time in chunk order
+            for (; c + 4 <= c1; c += 4) {
+              const float v0 = s_part[c * NACC + r], v1 = s_part[(c + 1) * NACC + r];
+              const float v2 = s_part[(c + 2) * NACC + r], v3 = s_part[(c + 3) * NACC + r];
+              acc += v0;
+              acc += v1;
+              acc += v2;
+              acc += v3;
+            }
+            for (; c < c1; ++c) acc += s_part[c * NACC + r];
           }
-          part[(size_t)s_src[jj] * stride + r] = acc;
+          part[(size_t)dst * stride + r] = acc;
         }
       }
     }
