@@ -387,6 +387,17 @@ igs_status igs_adam_step(float *fit_params, float *render_params, const float *g
 igs_status igs_fit_to_render(const float *fit_params, float *render_params, int32_t N, int32_t n,
                              int32_t H, int32_t W, void *stream);
 
+/*
+ * Chain rule from the renderer's units to the fitter's (the same rule igs_adam_step applies
+ * before its update): for the [5+n][N] gradient grad_render with respect to render parameters,
+ * writes grad_fit [5+n][N], the gradient with respect to fit_params (layout of igs_adam_step):
+ * rows mu_x/W and mu_y/H get W and H times the mean rows, theta and colour rows are copied, and
+ * the inverse-scale rows u = 1/s get -dL/ds / u^2.  grad_fit may not alias the inputs.
+ * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_HIP.
+ */
+igs_status igs_grad_to_fit(const float *fit_params, const float *grad_render, float *grad_fit,
+                           int32_t N, int32_t n, int32_t H, int32_t W, void *stream);
+
 /* ------------------------------------------------------------------------------------------
  * Batches: many images of uneven size and Gaussian count rendered, differentiated and optimized
  * by one launch per phase.  The images are concatenated: the parameter array is [5+n][Ntot]

@@ -31,7 +31,7 @@ IGS_NOALLOC_SCRATCH_BYTES = 64 << 20
 EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "igs_saved_offsets",
             "igs_render",
             "igs_render_backward", "igs_l1_workspace_size", "igs_l1_loss_grad", "igs_adam_step",
-            "igs_fit_to_render", "igs_timing_enable", "igs_timing_read", "igs_batch_describe",
+            "igs_fit_to_render", "igs_grad_to_fit", "igs_timing_enable", "igs_timing_read", "igs_batch_describe",
             "igs_batch_buffer_sizes", "igs_batch_saved_offsets", "igs_render_batched",
             "igs_render_backward_batched", "igs_l1_batched_workspace_size",
             "igs_l1_loss_grad_batched", "igs_adam_step_batched", "igs_fit_to_render_batched",
@@ -138,6 +138,8 @@ def lib() -> ctypes.CDLL:
     L.igs_adam_step.restype = i32
     L.igs_fit_to_render.argtypes = [vp, vp, i32, i32, i32, i32, vp]
     L.igs_fit_to_render.restype = i32
+    L.igs_grad_to_fit.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
+    L.igs_grad_to_fit.restype = i32
     dp = ctypes.POINTER(ImageDesc)
     i32p = ctypes.POINTER(i32)
     L.igs_l1_ssim_batched_workspace_size.argtypes = [dp, i32, i32, ctypes.POINTER(sz)]
@@ -429,6 +431,12 @@ def igs_fit_to_render(fit_params, render_params, N, n, H, W, stream=None) -> Non
     _check("igs_fit_to_render", lib().igs_fit_to_render(
         _f32(fit_params, "fit_params"), _f32(render_params, "render_params"), N, n, H, W,
         _stream(stream)))
+
+
+def igs_grad_to_fit(fit_params, grad_render, grad_fit, N, n, H, W, stream=None) -> None:
+    _check("igs_grad_to_fit", lib().igs_grad_to_fit(
+        _f32(fit_params, "fit_params"), _f32(grad_render, "grad_render"),
+        _f32(grad_fit, "grad_fit"), N, n, H, W, _stream(stream)))
 
 
 def igs_set_launch_config(persistent: int = 0, wgs_per_cu: int = 0, fwd_cull: int = 1,

@@ -896,6 +896,16 @@ IGS_API igs_status igs_fit_to_render(const float *fit_params, float *render_para
   return IGS_OK;
 }
 
+IGS_API igs_status igs_grad_to_fit(const float *fit_params, const float *grad_render,
+                                   float *grad_fit, int32_t N, int32_t n, int32_t H, int32_t W,
+                                   void *stream) {
+  if (N < 0 || n < 1 || n > IGS_MAX_CHANNELS || H < 1 || W < 1) return IGS_ERR_INVALID_ARG;
+  if (N > 0 && (!fit_params || !grad_render || !grad_fit)) return IGS_ERR_INVALID_ARG;
+  IGS_HIP(launch_grad_to_fit(fit_params, grad_render, grad_fit, N, n, single_view(H, W, N),
+                             static_cast<hipStream_t>(stream)));
+  return IGS_OK;
+}
+
 IGS_API igs_status igs_l1_batched_workspace_size(const igs_image_desc *descs, int32_t B, int32_t n,
                                                  size_t *ws_bytes) {
   int64_t blocks = 0;

@@ -290,6 +290,9 @@ hipError_t launch_adam_lo(float *fit, float *rend, const float *grad, float *m, 
                           float eps, float u_lo, float u_hi, hipStream_t s);
 hipError_t launch_fit_to_render(const float *fit, float *rend, int N, int n, const Images &imgs,
                                 hipStream_t s);
+// Gradient with respect to render parameters -> gradient with respect to fitter parameters.
+hipError_t launch_grad_to_fit(const float *fit, const float *grad_rend, float *grad_fit, int N,
+                              int n, const Images &imgs, hipStream_t s);
 // Batched L1: per-image mean normalization; loss_out is double[B][2].
 int l1_batch_block_items();
 hipError_t launch_l1_batched(const float *images, const float *targets, const Images &imgs,

@@ -71,6 +71,15 @@ __device__ __forceinline__ float to_render(int r, float p, float W, float H) {
   return p;
 }
 
+// Chain rule from a gradient with respect to render parameter row r to the fitter parameter p of
+// that row: mu = W (mu/W) and H (mu/H), s = 1/u so dL/du = -s^2 dL/ds = -dL/ds / u^2.
+__device__ __forceinline__ float grad_to_fit(int r, float g, float p, float W, float H) {
+  if (r == 0) return g * W;
+  if (r == 1) return g * H;
+  if (r == 3 || r == 4) return -g / (p * p);
+  return g;
+}
+
 // Four elements of one row per thread (Gaussians i0 + tid + 256 u of row blockIdx.y of the
 // [5+n][N] arrays, so every load and store of a block is contiguous), their loads issued
 // together and the bias corrections computed once.  u_lo > 0: lower clip of the inverse scales;
@@ -129,20 +138,8 @@ __global__ __launch_bounds__(kAdamThreads) void adam_kernel(
     const float W = (float)im.W, H = (float)im.H;
     const float u_lo = u_lo_arg > 0.f ? u_lo_arg : 1.0f / fmaxf(W, H);
     const float p = pv[u];
-    float g = gv[u];
-    float lr = lr_c;
-    if (r == 0) {
-      g *= W;
-      lr = lr_mu;
-    } else if (r == 1) {
-      g *= H;
-      lr = lr_mu;
-    } else if (r == 2) {
-      lr = lr_theta;
-    } else if (r == 3 || r == 4) {
-      g = -g / (p * p);  // dL/du = -s^2 dL/ds with u = 1/s
-      lr = lr_u;
-    }
+    const float g = grad_to_fit(r, gv[u], p, W, H);
+    const float lr = r <= 1 ? lr_mu : (r == 2 ? lr_theta : (r <= 4 ? lr_u : lr_c));
     const float mm = b1 * mv[u] + (1.0f - b1) * g;
     const float vn = b2 * vv[u] + (1.0f - b2) * g * g;
     m[e] = mm;
@@ -168,6 +165,18 @@ __global__ __launch_bounds__(256) void fit_to_render_kernel(const float *__restr
   const int r = (int)(e / N);
   const ImageDesc im = imgs.by_gauss((int)(e - (int64_t)r * N));
   rend[e] = to_render(r, fit[e], (float)im.W, (float)im.H);
+}
+
+__global__ __launch_bounds__(256) void grad_to_fit_kernel(const float *__restrict__ fit,
+                                                          const float *__restrict__ grad_rend,
+                                                          float *__restrict__ grad_fit, int N,
+                                                          int n, Images imgs) {
+  const int64_t total = (int64_t)(5 + n) * N;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int r = (int)(e / N);
+  const ImageDesc im = imgs.by_gauss((int)(e - (int64_t)r * N));
+  grad_fit[e] = grad_to_fit(r, grad_rend[e], fit[e], (float)im.W, (float)im.H);
 }
 
 // Batched L1: block k belongs to the image b with l1_block_off[b] <= k < l1_block_off[b+1] and
@@ -285,6 +294,15 @@ hipError_t launch_fit_to_render(const float *fit, float *rend, int N, int n, con
   const int64_t total = (int64_t)(5 + n) * N;
   if (total <= 0) return hipSuccess;
   fit_to_render_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(fit, rend, N, n, imgs);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_to_fit(const float *fit, const float *grad_rend, float *grad_fit, int N,
+                              int n, const Images &imgs, hipStream_t s) {
+  const int64_t total = (int64_t)(5 + n) * N;
+  if (total <= 0) return hipSuccess;
+  grad_to_fit_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(fit, grad_rend, grad_fit, N,
+                                                                      n, imgs);
   return hipGetLastError();
 }
 

@@ -204,31 +204,35 @@ class RenderFn(torch.autograd.Function):
     """Differentiable Image-GS render in the fitter's parameterization.
 
     Inputs: means [N,2] normalized to [0,1]^2 (x by W, y by H), theta [N], inverse scales [N,2]
-    (1/s in 1/pixels), colors [N,n]; H, W, K.  Output: [n,H,W].  The backward returns gradients
-    for the four tensors, computed by the HIP adjoint through the K retained Gaussians."""
+    (1/s in 1/pixels), colors [N,n]; H, W, K.  Output: [n,H,W].  The parameters are gathered into
+    the [5+n][N] fitter layout of igs_adam_step (a copy), converted to render units by
+    igs_fit_to_render, rendered, and the backward runs the HIP adjoint through the K retained
+    Gaussians and igs_grad_to_fit for the chain rule back to the fitter's units."""
 
     @staticmethod
     def forward(ctx, means, theta, inv_scales, colors, H: int, W: int, K: int = 10):
         N, n = means.shape[0], colors.shape[1]
-        wh = torch.tensor([W, H], dtype=means.dtype, device=means.device)
-        params = pack_params(means * wh, theta, 1.0 / inv_scales, colors)
+        fit = torch.cat([means.T, theta.reshape(1, N), inv_scales.T, colors.T], dim=0)
+        fit = fit.float().contiguous()
+        params = torch.empty_like(fit)
+        if N > 0:
+            nat.igs_fit_to_render(fit, params, N, n, H, W)
         r = renderer_for(N, n, H, W, K, means.device)
         image, saved = r.render(params, keep_state=True)
         ctx.r, ctx.saved_state = r, saved
-        ctx.H, ctx.W = H, W
-        ctx.save_for_backward(params, image, inv_scales)
+        ctx.H, ctx.W, ctx.N, ctx.n = H, W, N, n
+        ctx.save_for_backward(fit, params, image)
         return image
 
     @staticmethod
     def backward(ctx, grad_image):
-        params, image, inv_scales = ctx.saved_tensors
+        fit, params, image = ctx.saved_tensors
         gp = ctx.r.backward(params, image, grad_image.float().contiguous(), ctx.saved_state)
-        W, H = ctx.W, ctx.H
-        d_means = torch.stack([gp[0] * W, gp[1] * H], dim=1)
-        d_theta = gp[2].clone()
-        d_inv = (-gp[3:5] / (inv_scales.T * inv_scales.T)).T      # dL/du = -s^2 dL/ds
-        d_colors = gp[5:].T.contiguous()
-        return d_means, d_theta, d_inv.contiguous(), d_colors, None, None, None
+        g = torch.empty_like(gp)
+        if ctx.N > 0:
+            nat.igs_grad_to_fit(fit, gp, g, ctx.N, ctx.n, ctx.H, ctx.W)
+        return (g[0:2].T.contiguous(), g[2].clone(), g[3:5].T.contiguous(), g[5:].T.contiguous(),
+                None, None, None)
 
 
 class BatchRenderer:

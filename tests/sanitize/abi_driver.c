@@ -67,6 +67,7 @@ int main(void) {
     CHECK(igs_adam_step(NULL, NULL, NULL, NULL, NULL, NULL, NULL, 4, 3, 8, 8, 1e-3f, 1e-3f, 1e-3f,
                         1e-3f, 0.9f, 0.999f, 1e-8f, 0.1f, 4.0f, NULL) == IGS_ERR_INVALID_ARG);
     CHECK(igs_fit_to_render(NULL, NULL, 4, 0, 8, 8, NULL) == IGS_ERR_INVALID_ARG);
+    CHECK(igs_grad_to_fit(NULL, NULL, NULL, 4, 3, 8, 8, NULL) == IGS_ERR_INVALID_ARG);
     /* batches: descriptors written on the host, then checked */
     int32_t Hs[3] = {256, 17, 512}, Ws[3] = {64, 33, 512}, Ns[3] = {100, 0, 5000};
     igs_image_desc d[3];

@@ -85,6 +85,8 @@ def test_render_validates_before_device_work(nat):
     assert L.igs_adam_step(None, None, None, None, None, None, None, 4, 3, 8, 8, 1e-3, 1e-3, 1e-3,
                            1e-3, 0.9, 0.999, 1e-8, 0.1, 4.0, None) == -1
     assert L.igs_fit_to_render(None, None, 4, 0, 8, 8, None) == -1
+    assert L.igs_grad_to_fit(None, None, None, 4, 3, 8, 8, None) == -1
+    assert L.igs_grad_to_fit(None, None, None, 4, 0, 8, 8, None) == -1
     # fused render + L1: saved state and target are required, n is limited to 16 channels
     assert L.igs_render_l1(None, 0, 3, 16, 16, 10, 16, 16, 100, None, None, None, None, 0, None, 0,
                            None) == -1

@@ -452,6 +452,22 @@ def test_adam_step_matches_reference():
     np.testing.assert_allclose(r_t.cpu().numpy(), fitref.to_render_space(f_ref, H, W), rtol=2e-5, atol=2e-5)
 
 
+def test_grad_to_fit_matches_reference_chain_rule():
+    """igs_grad_to_fit: the chain rule from render to fitter units (Sec. 4.1 normalized means,
+    Sec. 3.3 inverse scales) against the oracle's, on random gradients of a fitted-space set."""
+    from paper_2407_01866_amd import _native as nat
+    d = dev()
+    H, W, n, N = 72, 136, 4, 700
+    rp = synth.gen_gaussians(31, H, W, N, n)
+    fp = fitref.to_fit_space(rp.astype(np.float64), H, W).astype(np.float32)
+    g = (np.random.default_rng(32).standard_normal((5 + n, N)) * 1e-2).astype(np.float32)
+    out = torch.empty((5 + n, N), device=d)
+    nat.igs_grad_to_fit(torch.from_numpy(fp).to(d), torch.from_numpy(g).to(d), out, N, n, H, W)
+    torch.cuda.synchronize()
+    ref = fitref.grad_to_fit_space(g.astype(np.float64), fp.astype(np.float64), H, W)
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=2e-6, atol=0)
+
+
 # ------------------------------------------------------------------------- autograd.Function
 
 
