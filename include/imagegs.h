@@ -71,6 +71,16 @@ int32_t igs_abi_version(void);
 /* Human-readable name of a status code (static storage). */
 const char *igs_status_string(igs_status s);
 
+/* Bounds-checked build only (libimagegs_debug.so, the same sources compiled with
+ * IGS_BOUNDS_CHECK): in that build the kernels validate their indices into the LDS batches
+ * (forward staging, retained slots, the adjoint's counters, items and chunks) and into the pair
+ * arrays (emission, sort scatter, sorted emit indices) against the buffer sizes; an index out of
+ * range sets the bit of its site and is replaced by 0, so no access leaves its buffer.  Writes
+ * to *out the OR of the sites met since the previous call and clears them (synchronizes the
+ * device); 0 means no violation.  The normal build has no checks: *out = 0 and the call returns
+ * IGS_ERR_UNSUPPORTED.  Errors: IGS_ERR_INVALID_ARG (out NULL), IGS_ERR_HIP. */
+igs_status igs_bounds_violations(uint32_t *out);
+
 /*
  * Buffer sizes for igs_render / igs_render_backward with these dimensions.
  *   pair_capacity: how many (tile, Gaussian) pairs the binning may hold (>= 1, < 2^31).  P, the

@@ -12,6 +12,8 @@ from typing import Optional, Tuple
 import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libimagegs.so")
+# the bounds-checked build of the same sources (build.py --debug); see igs_bounds_violations
+LIB_DEBUG_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libimagegs_debug.so")
 
 IGS_OK = 0
 IGS_ERR_INVALID_ARG = -1
@@ -31,7 +33,8 @@ IGS_NOALLOC_SCRATCH_BYTES = 64 << 20
 EXPORTED = ("igs_abi_version", "igs_status_string", "igs_render_buffer_sizes", "igs_saved_offsets",
             "igs_render",
             "igs_render_backward", "igs_l1_workspace_size", "igs_l1_loss_grad", "igs_adam_step",
-            "igs_fit_to_render", "igs_grad_to_fit", "igs_timing_enable", "igs_timing_read", "igs_batch_describe",
+            "igs_fit_to_render", "igs_grad_to_fit", "igs_bounds_violations",
+            "igs_timing_enable", "igs_timing_read", "igs_batch_describe",
             "igs_batch_buffer_sizes", "igs_batch_saved_offsets", "igs_render_batched",
             "igs_render_backward_batched", "igs_l1_batched_workspace_size",
             "igs_l1_loss_grad_batched", "igs_adam_step_batched", "igs_fit_to_render_batched",
@@ -82,13 +85,38 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
+    """The library every wrapper below calls (libimagegs.so unless `using` selected another)."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built: run `python paper_2407_01866_amd/build.py` "
+    _lib = load(LIB_PATH)
+    return _lib
+
+
+class using:
+    """Context manager: the wrappers call the given loaded library (e.g. load(LIB_DEBUG_PATH))
+    inside the block, and the previous one afterwards."""
+
+    def __init__(self, L: ctypes.CDLL):
+        self.L, self.prev = L, None
+
+    def __enter__(self):
+        global _lib
+        self.prev, _lib = _lib, self.L
+        return self.L
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.prev
+        return False
+
+
+def load(path: str) -> ctypes.CDLL:
+    """Loads a build of libimagegs and declares its entry points (argument marshalling only)."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python paper_2407_01866_amd/build.py` "
                           "(or __graft_entry__.build()) first")
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     i32, i64, sz, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
     f32 = ctypes.c_float
     L.igs_abi_version.argtypes = []
@@ -196,7 +224,8 @@ def lib() -> ctypes.CDLL:
     L.igs_timing_enable.restype = i32
     L.igs_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
     L.igs_timing_read.restype = i32
-    _lib = L
+    L.igs_bounds_violations.argtypes = [ctypes.POINTER(ctypes.c_uint32)]
+    L.igs_bounds_violations.restype = i32
     return L
 
 
@@ -449,6 +478,17 @@ def igs_get_launch_config() -> LaunchConfig:
     cfg = LaunchConfig()
     _check("igs_get_launch_config", lib().igs_get_launch_config(ctypes.byref(cfg)))
     return cfg
+
+
+def igs_bounds_violations() -> Optional[int]:
+    """The sites (bit mask) where the bounds-checked build met an out-of-range index since the
+    last call, or None for a normal build (which has no checks).  Synchronizes the device."""
+    out = ctypes.c_uint32(0)
+    st = lib().igs_bounds_violations(ctypes.byref(out))
+    if st == IGS_ERR_UNSUPPORTED:
+        return None
+    _check("igs_bounds_violations", st)
+    return int(out.value)
 
 
 def igs_timing_enable(on: bool) -> None:

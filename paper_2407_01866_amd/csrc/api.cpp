@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 #include "timing.hpp"
@@ -186,6 +187,28 @@ using namespace igs;
   } while (0)
 
 IGS_API int32_t igs_abi_version(void) { return 2; }
+
+#ifdef IGS_BOUNDS_CHECK
+namespace igs {
+static std::vector<BoundsReader> &bounds_readers() {
+  static std::vector<BoundsReader> r;
+  return r;
+}
+void register_bounds_reader(BoundsReader r) { bounds_readers().push_back(r); }
+}  // namespace igs
+#endif
+
+IGS_API igs_status igs_bounds_violations(uint32_t *out) {
+  if (!out) return IGS_ERR_INVALID_ARG;
+  *out = 0;
+#ifdef IGS_BOUNDS_CHECK
+  if (hipDeviceSynchronize() != hipSuccess) return IGS_ERR_HIP;
+  for (BoundsReader r : bounds_readers()) *out |= r();
+  return IGS_OK;
+#else
+  return IGS_ERR_UNSUPPORTED;
+#endif
+}
 
 IGS_API const char *igs_status_string(igs_status s) {
   switch (s) {

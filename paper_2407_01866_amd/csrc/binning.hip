@@ -253,8 +253,9 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
       const uint32_t qm = quad_bits(__ballot(hit), lane);
       const uint32_t rank = k + (uint32_t)__popc(qm & ((1u << q) - 1u));
       if (hit && rank < c) {
-        keys[o + rank] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
-        pair_gid[o + rank] = (uint32_t)i;
+        const int64_t u = IGS_IDX(o + rank, cap, kSiteEmit);
+        keys[u] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
+        pair_gid[u] = (uint32_t)i;
       }
       k += (uint32_t)__popc(qm);
     }
@@ -278,8 +279,9 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
       const uint64_t m = __ballot(hit);
       const uint32_t rank = k + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
       if (hit && rank < sc) {
-        keys[sbase + rank] = (uint32_t)(tile_off + ty * tiles_x + tx);
-        pair_gid[sbase + rank] = gid;
+        const int64_t u = IGS_IDX(sbase + rank, cap, kSiteEmit);
+        keys[u] = (uint32_t)(tile_off + ty * tiles_x + tx);
+        pair_gid[u] = gid;
       }
       k += (uint32_t)__popcll(m);
     }
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void resolve_ranges_kernel(
   if (P > cap) P = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += stride) {
-    vals[p] = pair_gid[src[p]];
+    vals[p] = pair_gid[IGS_IDX(src[p], cap, kSiteResolve)];
     const uint32_t k = keys[p];
     if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
     if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);

@@ -16,6 +16,52 @@ constexpr int kMaxK = 32;
 constexpr int kMaxChannels = 32;
 constexpr uint16_t kEmptySlot = 0xFFFF;
 
+// Bounds-checked build (compiled with IGS_BOUNDS_CHECK, libimagegs_debug.so): an index checked
+// with IGS_IDX that falls outside its buffer sets the bit of its site in this translation unit's
+// violation word and is replaced by 0, so the access stays inside the buffer;
+// igs_bounds_violations collects and clears the words.  In the normal build IGS_IDX is the index
+// itself and nothing is compiled.
+enum BoundsSite : unsigned {
+  kSiteEmit = 0,         // pair emission: emit index < pair capacity
+  kSiteSortScatter = 1,  // radix scatter: destination < pair capacity
+  kSiteResolve = 2,      // sorted emit index < pair capacity
+  kSiteStage = 3,        // forward LDS batch: visiting position < batch size
+  kSiteSlot = 4,         // a retained slot of a single-batch tile < batch size
+  kSiteAdjCounter = 5,   // adjoint LDS: per-Gaussian sub-counters
+  kSiteAdjItem = 6,      // adjoint LDS: placed items
+  kSiteAdjChunk = 7,     // adjoint LDS: chunk owners and chunk rows
+};
+#ifdef IGS_BOUNDS_CHECK
+namespace {
+__device__ unsigned int g_bounds_word;
+}
+__device__ __forceinline__ int64_t check_index(int64_t i, int64_t n, unsigned site) {
+  if (i < 0 || i >= n) {
+    atomicOr(&g_bounds_word, 1u << site);
+    return 0;
+  }
+  return i;
+}
+#define IGS_IDX(i, n, site) ::igs::check_index((int64_t)(i), (int64_t)(n), (site))
+using BoundsReader = unsigned (*)();
+void register_bounds_reader(BoundsReader r);  // api.cpp
+namespace {
+// reads and clears this translation unit's word (synchronous)
+inline unsigned take_bounds_word() {
+  unsigned v = 0, z = 0;
+  if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_bounds_word), sizeof(v)) != hipSuccess) return ~0u;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_bounds_word), &z, sizeof(z)) != hipSuccess) return ~0u;
+  return v;
+}
+struct BoundsRegistrar {
+  BoundsRegistrar() { register_bounds_reader(&take_bounds_word); }
+};
+const BoundsRegistrar g_bounds_registrar;
+}  // namespace
+#else
+#define IGS_IDX(i, n, site) (i)
+#endif
+
 // Device status block (int64 words), see include/imagegs.h.
 enum StatusWord {
   kStatPairs = 0,

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     }
     __syncthreads();
     if (valid) {
-      uint32_t pos = wave_cnt[buf][w][d] + (uint32_t)rank;
+      const int64_t pos = IGS_IDX(wave_cnt[buf][w][d] + (uint32_t)rank, cap, kSiteSortScatter);
       keys_out[pos] = key;
       vals_out[pos] = val;
     }

@@ -225,7 +225,7 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
     }
     __syncthreads();
     if (tid < nb) {  // scatter the ranking data into visiting order
-      const int pos = S.bstart[bucket] + brank;
+      const int pos = (int)IGS_IDX(S.bstart[bucket] + brank, fb, kSiteStage);
       S.pgeo[pos] = a;
       S.pcd[pos] = make_float4(b.x, b.y, __int_as_float(base + tid), bucket_floor(bucket));
 #pragma unroll
@@ -290,8 +290,9 @@ __device__ __forceinline__ void winners(const FwdLds &S, bool single, int start,
     double4 cn = make_double4(0.0, 0.0, 0.0, 0.0);
     float2 mn = make_float2(0.f, 0.f);
     if (keff > 0) {
-      cn = *reinterpret_cast<const double4 *>(&S.s64[4 * ts[0]]);
-      mn = S.mu[ts[0]];
+      const int sb = (int)IGS_IDX(ts[0], S.fb, kSiteSlot);
+      cn = *reinterpret_cast<const double4 *>(&S.s64[4 * sb]);
+      mn = S.mu[sb];
     }
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
@@ -299,8 +300,9 @@ __device__ __forceinline__ void winners(const FwdLds &S, bool single, int start,
         const double4 c = cn;
         const float2 mu = mn;
         if (k + 1 < keff) {
-          cn = *reinterpret_cast<const double4 *>(&S.s64[4 * ts[k + 1]]);
-          mn = S.mu[ts[k + 1]];
+          const int sb = (int)IGS_IDX(ts[k + 1], S.fb, kSiteSlot);
+          cn = *reinterpret_cast<const double4 *>(&S.s64[4 * sb]);
+          mn = S.mu[sb];
         }
         asm volatile("" ::: "memory");
         double e1, e2;
@@ -316,8 +318,9 @@ __device__ __forceinline__ void winners(const FwdLds &S, bool single, int start,
     for (int k = 0; k < KT; ++k) {
       if (k < keff) {
         const int slot = ts[k];
-        const double4 c = *reinterpret_cast<const double4 *>(&S.s64[4 * slot]);
-        const float2 mu = S.mu[slot];
+        const int sb = (int)IGS_IDX(slot, S.fb, kSiteSlot);
+        const double4 c = *reinterpret_cast<const double4 *>(&S.s64[4 * sb]);
+        const float2 mu = S.mu[sb];
         double e1, e2;
         const double q = quad_form64(fx, fy, mu.x, mu.y, c.x, c.y, c.z, c.w, e1, e2);
         if (k == 0) shift = (float)q;
@@ -491,7 +494,8 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
       const int j = sl[k] - base;
       const bool ok = (unsigned)j < (unsigned)nb;
       const int a = ok ? j * kSub + sub : kBatch * kSub + tid;
-      const int r = atomicAdd(&s_cnt8[a], 1);
+      const int r =
+          atomicAdd(&s_cnt8[IGS_IDX(a, kBatch * kSub + kRasterThreads, kSiteAdjCounter)], 1);
       e[k] = ok ? (uint32_t)(j | (r << 8)) : 0xFFFFFFFFu;
     }
     __syncthreads();
@@ -551,7 +555,8 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
     }
     s_off[tid] = my_off;
     s_cho[tid] = my_cho;
-    for (int c = 0; c < my_ch; ++c) s_owner[my_cho + c] = (uint16_t)tid;
+    for (int c = 0; c < my_ch; ++c)
+      s_owner[IGS_IDX(my_cho + c, kRasterThreads, kSiteAdjChunk)] = (uint16_t)tid;
     if (tid == 0) {
       s_off[kBatch] = total_items;
       s_cho[kBatch] = total_chunks;
@@ -581,7 +586,9 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
     for (int k = 0; k < KT; ++k) {
       if (e[k] != 0xFFFFFFFFu) {
         const int jj = e[k] & 0xFF;
-        s_item[s_cnt8[jj * kSub + sub] + (e[k] >> 8)] = (uint16_t)(tid | (jj << 8));
+        const int64_t at = IGS_IDX(s_cnt8[jj * kSub + sub] + (e[k] >> 8), kRasterThreads * KT,
+                                   kSiteAdjItem);
+        s_item[at] = (uint16_t)(tid | (jj << 8));
       }
     }
     __syncthreads();
@@ -595,7 +602,7 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
       const int first = s_off[j] + (tid - s_cho[j]) * R;
       const int end = min(first + R, s_off[j + 1]);
       for (int it = first; it < end; ++it) {
-        const int p = s_item[it] & 0xFF;
+        const int p = s_item[IGS_IDX(it, kRasterThreads * KT, kSiteAdjItem)] & 0xFF;
         float rw[ROW];
 #pragma unroll
         for (int r = 0; r < ROW; r += 4) {
@@ -652,6 +659,9 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
           float acc = 0.f;
           if (r < 5 + n) {
             int c = s_cho[jj];
+#ifdef IGS_BOUNDS_CHECK
+            if (c1 > kRasterThreads) IGS_IDX(c1, kRasterThreads + 1, kSiteAdjChunk);
+#endif
             // four chunks' loads in flight, added one at a time in chunk order
             for (; c + 4 <= c1; c += 4) {
               const float v0 = s_part[c * NACC + r], v1 = s_part[(c + 1) * NACC + r];

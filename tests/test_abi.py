@@ -35,6 +35,22 @@ def test_every_declared_symbol_is_exported(nat):
     assert set(names) == set(nat.EXPORTED)
 
 
+def test_bounds_checked_build_exports_the_same_symbols(nat):
+    """The bounds-checked build (libimagegs_debug.so) has the same C ABI; the normal build
+    reports that it has no checks."""
+    if not os.path.exists(nat.LIB_DEBUG_PATH):
+        from paper_2407_01866_amd import build
+        build.build(debug=True)
+    D = nat.load(nat.LIB_DEBUG_PATH)
+    for name in declared_functions():
+        assert hasattr(D, name), name
+    out = ctypes.c_uint32(7)
+    assert nat.lib().igs_bounds_violations(ctypes.byref(out)) == nat.IGS_ERR_UNSUPPORTED
+    assert out.value == 0
+    assert nat.lib().igs_bounds_violations(None) == nat.IGS_ERR_INVALID_ARG
+    assert D.igs_abi_version() == nat.igs_abi_version()
+
+
 def test_abi_version_and_status_strings(nat):
     assert nat.igs_abi_version() == 2
     assert nat.igs_status_string(0) == "ok"
