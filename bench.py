@@ -634,6 +634,9 @@ def main():
                     help="skip the random-access decoding measurement")
     ap.add_argument("--ssim-profile", action="store_true",
                     help="only run 20 L1 + SSIM loss calls at the workload (for kernel traces)")
+    ap.add_argument("--decode-profile", action="store_true",
+                    help="only run 5 random-access decoding calls (4M points) on the workload's "
+                         "initial Gaussians (for kernel traces)")
     ap.add_argument("--launch-config", metavar="P,W,C[,B,K]",
                     help="fixed launch settings (persistent, wgs_per_cu, fwd_cull[, fwd_batch, "
                          "k_unroll]) instead of autotuning (profiling runs use the autotuner's "
@@ -674,6 +677,9 @@ def main():
     if args.ssim_profile:
         fitter.step_async()                     # a rendered image of the workload
         _ssim_calls(torch, dev, w, fitter.image, target, 20)
+        return
+    if args.decode_profile:
+        log(json.dumps(decode_step(torch, dev, w, params, calls=5)))
         return
     init = fitter.snapshot()
     # dry run of the same trajectory, one iteration at a time: sizes the pair buffer for every
