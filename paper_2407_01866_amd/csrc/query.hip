@@ -39,15 +39,20 @@ __global__ __launch_bounds__(kQueryThreads) void query_keys_kernel(
 
 // One thread per point, in the order `order` gives (points grouped by tile, so that the lanes of
 // a wave walk the same hit set and load the same candidates), or in input order when order is
-// null.  Points outside [0, W) x [0, H) (or not finite) decode to 0.
-template <int KT>
+// null.  With an order, each XCD takes a contiguous run of the sorted points (the workgroup ids
+// it receives are mapped as the raster kernels map tiles), so the Gaussians of neighbouring
+// tiles stay in that XCD's L2.  Points outside [0, W) x [0, H) (or not finite) decode to 0.
+// NC >= n: the colours are accumulated in registers and each point's n results are written
+// together.
+template <int NC, int KT>
 __global__ __launch_bounds__(kQueryThreads) void query_kernel(
     const float *__restrict__ params, int N, int n, int H, int W, int K, int tiles_x,
     int tiles_y, const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
     const double4 *__restrict__ g64, const float *__restrict__ pts, int M,
     const uint32_t *__restrict__ order, float *__restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int t = blk * blockDim.x + threadIdx.x;
   const bool valid = t < M;  // lanes past the end stay for the wave-wide broadcasts
   const int i = valid ? (order ? (int)order[t] : t) : 0;
   const float2 pt = valid ? reinterpret_cast<const float2 *>(pts)[i] : make_float2(-1.f, -1.f);
@@ -119,14 +124,21 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
   }
   const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
   if (!valid) return;
-  for (int ch = 0; ch < n; ++ch) {
-    float acc = 0.f;
+  float acc[NC];
 #pragma unroll
-    for (int k = 0; k < KT; ++k)
-      if (k < keff && key_valid(tk[k]))
-        acc = fmaf(w[k], params[(size_t)(5 + ch) * N + src[k]], acc);
-    out[(size_t)i * n + ch] = acc * invZ;
+  for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.f;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    if (k < keff && key_valid(tk[k])) {
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch)
+        if (ch < n) acc[ch] = fmaf(w[k], params[(size_t)(5 + ch) * N + src[k]], acc[ch]);
+    }
   }
+  float *__restrict__ o = out + (size_t)i * n;
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch)
+    if (ch < n) o[ch] = acc[ch] * invZ;
 }
 
 __global__ __launch_bounds__(256) void to_fp16_kernel(const float *__restrict__ src, int64_t count,
@@ -156,6 +168,27 @@ __global__ __launch_bounds__(256) void decode_fp16_kernel(const uint16_t *__rest
 }  // namespace
 
 namespace {
+template <int NC>
+hipError_t launch_query_nc(const float *params, int N, int n, int H, int W, int K, int tiles_x,
+                           int tiles_y, const int2 *ranges, const uint32_t *vals,
+                           const float4 *g32a, const float2 *g32b, const double4 *g64,
+                           const float *points, int M, const uint32_t *order, float *out,
+                           int grid, hipStream_t s) {
+  switch (pick_kt(K)) {
+#define IGS_QUERY_CASE(KT)                                                                     \
+  case KT:                                                                                     \
+    query_kernel<NC, KT><<<grid, kQueryThreads, 0, s>>>(params, N, n, H, W, K, tiles_x,      \
+                                                        tiles_y, ranges, vals, g32a, g32b,   \
+                                                        g64, points, M, order, out);         \
+    break;
+    IGS_FOR_EACH_KT(IGS_QUERY_CASE)
+#undef IGS_QUERY_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 struct QueryWs {
   size_t keys, vals, keys_alt, vals_alt, hist, hist_off, scan_tmp, count, total;
   int key_bits, passes, digit_bits;
@@ -224,19 +257,14 @@ hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
     if (e != hipSuccess) return e;
     order = vs;
   }
-  switch (pick_kt(K)) {
-#define IGS_QUERY_CASE(KT)                                                                    \
-  case KT:                                                                                    \
-    query_kernel<KT><<<grid, kQueryThreads, 0, s>>>(params, N, n, H, W, K, tiles_x, tiles_y, \
-                                                    ranges, vals, g32a, g32b, g64, points, M, \
-                                                    order, out);                              \
-    break;
-    IGS_FOR_EACH_KT(IGS_QUERY_CASE)
-#undef IGS_QUERY_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (n <= 4) return launch_query_nc<4>(params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals,
+                                         g32a, g32b, g64, points, M, order, out, grid, s);
+  if (n <= 9) return launch_query_nc<9>(params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals,
+                                         g32a, g32b, g64, points, M, order, out, grid, s);
+  if (n <= 16) return launch_query_nc<16>(params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals,
+                                           g32a, g32b, g64, points, M, order, out, grid, s);
+  return launch_query_nc<32>(params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals, g32a, g32b,
+                             g64, points, M, order, out, grid, s);
 }
 
 hipError_t launch_to_fp16(const float *src, int64_t count, uint16_t *dst, hipStream_t s) {
