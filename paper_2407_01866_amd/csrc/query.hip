@@ -43,7 +43,15 @@ __global__ __launch_bounds__(kQueryThreads) void query_keys_kernel(
 // it receives are mapped as the raster kernels map tiles), so the Gaussians of neighbouring
 // tiles stay in that XCD's L2.  Points outside [0, W) x [0, H) (or not finite) decode to 0.
 // NC >= n: the colours are accumulated in registers and each point's n results are written
-// together.
+// together.  A tile of at most qstage(NC) members has its members' colours staged in the wave's
+// LDS rows while its candidates are loaded, so the blend reads them there instead of gathering
+// n scattered parameters per winner.
+__host__ __device__ constexpr int qstage(int nc) { return nc <= 16 ? 128 : 64; }
+template <int NC>
+__host__ __device__ constexpr size_t query_lds_bytes() {
+  return (size_t)(kQueryThreads / 64) * qstage(NC) * NC * sizeof(float);
+}
+
 template <int NC, int KT>
 __global__ __launch_bounds__(kQueryThreads) void query_kernel(
     const float *__restrict__ params, int N, int n, int H, int W, int K, int tiles_x,
@@ -51,6 +59,9 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
     const double4 *__restrict__ g64, const float *__restrict__ pts, int M,
     const uint32_t *__restrict__ order, float *__restrict__ out) {
+  constexpr int QS = qstage(NC);
+  extern __shared__ __align__(16) unsigned char qsm[];
+  float *__restrict__ scol = reinterpret_cast<float *>(qsm) + (threadIdx.x >> 6) * QS * NC;
   const int blk = order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
   const int t = blk * blockDim.x + threadIdx.x;
   const bool valid = t < M;  // lanes past the end stay for the wave-wide broadcasts
@@ -70,8 +81,15 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
   for (int k = 0; k < KT; ++k) tk[k] = kKeyEmpty;
   // one pass per distinct tile among the wave's lanes (one or two once the points are grouped):
   // the wave loads that tile's candidates 64 at a time, one per lane, and broadcasts each to
-  // every lane with readlane; the lanes of that tile rank it
+  // every lane with readlane; the lanes of that tile rank it.  Each lane also bounds its
+  // candidate's q from below over the whole tile (every point of the tile lies in it), and the
+  // wave visits the 64 in ascending buckets of that bound, skipping a candidate whose bound
+  // exceeds the largest K-th key of the tile's lanes (it cannot enter any of their lists) and
+  // stopping once a bucket's floor does; the lists are those of ranking every candidate.
   const int lane = threadIdx.x & 63;
+  float res[NC];  // the point's colour (0 outside the image)
+#pragma unroll
+  for (int ch = 0; ch < NC; ++ch) res[ch] = 0.f;
   uint64_t todo = __ballot(tile >= 0);
   while (todo) {
     const int tc = __builtin_amdgcn_readlane(tile, __ffsll((unsigned long long)todo) - 1);
@@ -79,68 +97,130 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
     const int ustart = __builtin_amdgcn_readfirstlane(rg.x);
     const int ucnt = __builtin_amdgcn_readfirstlane(rg.y - rg.x);
     const bool mine = tile == tc;
+    const float rx0 = (float)((tc % tiles_x) * kTile), ry0 = (float)((tc / tiles_x) * kTile);
     for (int b0 = 0; b0 < ucnt; b0 += 64) {
       const int nb = min(64, ucnt - b0);
       float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
       float2 b = make_float2(0.f, 0.f);
+      float lb = 0.f;
       if (lane < nb) {
         const uint32_t gid = vals[ustart + b0 + lane];
         a = g32a[gid];
         b = g32b[gid];
+        if (ucnt <= QS) {
+#pragma unroll
+          for (int ch = 0; ch < NC; ++ch)
+            if (ch < n) scol[(b0 + lane) * NC + ch] = params[(size_t)(5 + ch) * N + gid];
+        }
+        const float A = a.z, B = a.w, C = b.x, D = b.y;
+        const float p11 = fmaf(A, A, C * C), p12 = fmaf(A, B, C * D), p22 = fmaf(B, B, D * D);
+        const float r1 = fmaf(A, A, B * B), r2 = fmaf(C, C, D * D);  // 1/s_1^2, 1/s_2^2
+        const float kappa =
+            sqrtf(fmaxf(r1, r2) * __builtin_amdgcn_rcpf(fminf(r1, r2))) * 1.001f;
+        const float i11 = __builtin_amdgcn_rcpf(p11), i22 = __builtin_amdgcn_rcpf(p22);
+        const float dxa = rx0 - a.x, dxb = (rx0 + (float)kTile) - a.x;
+        const float dya = ry0 - a.y, dyb = (ry0 + (float)kTile) - a.y;
+        lb = safe_lb(rect_min_q(A, B, C, D, i11, p12, -p12 * dxa * i22, -p12 * dxb * i22, dxa,
+                                dxb, dya, dyb),
+                     kappa);
       }
-      for (int k = 0; k < nb; ++k) {
-        const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.x), k));
-        const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.y), k));
-        const float A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.z), k));
-        const float B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.w), k));
-        const float C = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.x), k));
-        const float D = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.y), k));
-        const double key = rank_key(quad_q32(A, B, C, D, fx - mx, fy - my), b0 + k);
-        if (mine && key < tk[KT - 1]) topk_insert<KT>(tk, key);
+      const int bk = lb_bucket(lb);
+      const uint64_t live = nb == 64 ? ~0ull : ((1ull << nb) - 1ull);
+      for (int bb = 0; bb < kBuckets; ++bb) {
+        uint64_t set = __ballot(bk == bb) & live;
+        if (!set) continue;
+        // the largest K-th key among the tile's lanes (the lists only shrink: a stale value is
+        // safe); every bound in this bucket and the later ones is at least its floor
+        float q_tau = __uint_as_float(
+            wave_max_u32(mine ? (uint32_t)__double2hiint(tk[KT - 1]) : 0u) - kKeyBias);
+        if (bucket_floor(bb) > q_tau) break;
+        for (int v = 0; set; ++v) {
+          const int k = __ffsll((unsigned long long)set) - 1;
+          set &= set - 1;
+          if ((v & 7) == 7)
+            q_tau = __uint_as_float(
+                wave_max_u32(mine ? (uint32_t)__double2hiint(tk[KT - 1]) : 0u) - kKeyBias);
+          if (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(lb), k)) > q_tau) continue;
+          const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.x), k));
+          const float my = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.y), k));
+          const float A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.z), k));
+          const float B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a.w), k));
+          const float C = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.x), k));
+          const float D = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.y), k));
+          const double key = rank_key(quad_q32(A, B, C, D, fx - mx, fy - my), b0 + k);
+          if (mine && key < tk[KT - 1]) topk_insert<KT>(tk, key);
+        }
       }
     }
+    // the blend of the tile's lanes: the winners re-evaluated in double, weights relative to the
+    // best, colours summed in rank order (from the staged rows when the tile has them)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (mine) {
+      const int keff = min(K, cnt);
+      float w[KT];
+      uint32_t src[KT];
+      int slot[KT];
+      float Z = 0.f, shift = 0.f;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        w[k] = 0.f;
+        src[k] = 0;
+        slot[k] = 0;
+        if (k < keff && key_valid(tk[k])) {
+          slot[k] = key_slot(tk[k]);
+          const uint32_t gid = vals[start + slot[k]];
+          const double4 c = g64[gid];
+          const float4 ga = g32a[gid];
+          double e1, e2;
+          const double q = quad_form64(fx, fy, ga.x, ga.y, c.x, c.y, c.z, c.w, e1, e2);
+          if (k == 0) shift = (float)q;
+          w[k] = blend_weight(q, shift);
+          Z += w[k];
+          src[k] = gid;
+        }
+      }
+      const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
+      float acc[NC];
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.f;
+      // LDS and global colour reads stay in separate loops (a read through a pointer that may
+      // address either miscompiles for gfx950)
+      if (ucnt <= QS) {
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+          if (k < keff && key_valid(tk[k])) {
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch)
+              if (ch < n) acc[ch] = fmaf(w[k], scol[slot[k] * NC + ch], acc[ch]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+          if (k < keff && key_valid(tk[k])) {
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch)
+              if (ch < n) acc[ch] = fmaf(w[k], params[(size_t)(5 + ch) * N + src[k]], acc[ch]);
+          }
+        }
+      }
+#pragma unroll
+      for (int ch = 0; ch < NC; ++ch) res[ch] = acc[ch] * invZ;
+    }
+    // the staged rows are read before the next tile's are written
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     todo &= ~__ballot(mine);
   }
-  // blend: the winners re-evaluated in double, weights relative to the best, in rank order
-  const int keff = min(K, cnt);
-  float w[KT];
-  uint32_t src[KT];
-  float Z = 0.f, shift = 0.f;
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    w[k] = 0.f;
-    src[k] = 0;
-    if (k < keff && key_valid(tk[k])) {
-      const uint32_t gid = vals[start + key_slot(tk[k])];
-      const double4 c = g64[gid];
-      const float4 a = g32a[gid];
-      double e1, e2;
-      const double q = quad_form64(fx, fy, a.x, a.y, c.x, c.y, c.z, c.w, e1, e2);
-      if (k == 0) shift = (float)q;
-      w[k] = blend_weight(q, shift);
-      Z += w[k];
-      src[k] = gid;
-    }
-  }
-  const float invZ = Z > 0.f ? 1.0f / Z : 0.0f;
   if (!valid) return;
-  float acc[NC];
-#pragma unroll
-  for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.f;
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    if (k < keff && key_valid(tk[k])) {
-#pragma unroll
-      for (int ch = 0; ch < NC; ++ch)
-        if (ch < n) acc[ch] = fmaf(w[k], params[(size_t)(5 + ch) * N + src[k]], acc[ch]);
-    }
-  }
   float *__restrict__ o = out + (size_t)i * n;
 #pragma unroll
   for (int ch = 0; ch < NC; ++ch)
-    if (ch < n) o[ch] = acc[ch] * invZ;
+    if (ch < n) o[ch] = res[ch];
 }
-
 __global__ __launch_bounds__(256) void to_fp16_kernel(const float *__restrict__ src, int64_t count,
                                                       uint16_t *__restrict__ dst) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -177,9 +257,9 @@ hipError_t launch_query_nc(const float *params, int N, int n, int H, int W, int 
   switch (pick_kt(K)) {
 #define IGS_QUERY_CASE(KT)                                                                     \
   case KT:                                                                                     \
-    query_kernel<NC, KT><<<grid, kQueryThreads, 0, s>>>(params, N, n, H, W, K, tiles_x,      \
-                                                        tiles_y, ranges, vals, g32a, g32b,   \
-                                                        g64, points, M, order, out);         \
+    query_kernel<NC, KT><<<grid, kQueryThreads, query_lds_bytes<NC>(), s>>>(                  \
+        params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals, g32a, g32b, g64, points, M,   \
+        order, out);                                                                           \
     break;
     IGS_FOR_EACH_KT(IGS_QUERY_CASE)
 #undef IGS_QUERY_CASE

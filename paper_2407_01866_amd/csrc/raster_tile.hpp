@@ -27,65 +27,11 @@ namespace igs {
 // forward's LDS, 124 B per candidate at n = 9, small enough for six workgroups per CU).  Per
 // candidate 48 B of ranking data in visiting order and 40 B of blend geometry in slot order, then
 // the bucket counters, then the colour rows.
-constexpr int kBuckets = 16;
 constexpr int kWaves = kRasterThreads / 64;  // each wave covers 4 rows of the tile
 
 __host__ __device__ constexpr size_t fwd_lds_fixed(int fb) { return 88 * (size_t)fb + 2 * 16 * 4; }
 __host__ __device__ constexpr size_t fwd_lds_bytes(int n, int fb) {
   return fwd_lds_fixed(fb) + (size_t)n * fb * sizeof(float);
-}
-
-// Minimum of q over the rectangle [dxa, dxb] x [dya, dyb] of offsets from the mean: 0 if the
-// rectangle holds the mean, else the least of the four edge minima, each the 1-D minimum of the
-// quadratic along the edge (at -p12 dx / p22, resp. -p12 dy / p11) clamped to the edge.  tya, tyb
-// are the unclamped minimizers along the edges x = dxa and x = dxb.  In float32 with the same
-// factored expression as the ranking, so its error is that of the ranking's q; an inexact
-// minimizer changes an edge minimum only in second order.
-__device__ __forceinline__ float rect_min_q(float A, float B, float C, float D, float i11,
-                                            float p12, float tya, float tyb, float dxa, float dxb,
-                                            float dya, float dyb) {
-  if (dxa <= 0.f && dxb >= 0.f && dya <= 0.f && dyb >= 0.f) return 0.f;
-  float best = quad_q32(A, B, C, D, dxa, fminf(fmaxf(tya, dya), dyb));
-  best = fminf(best, quad_q32(A, B, C, D, dxb, fminf(fmaxf(tyb, dya), dyb)));
-  best = fminf(best, quad_q32(A, B, C, D, fminf(fmaxf(-p12 * dya * i11, dxa), dxb), dya));
-  best = fminf(best, quad_q32(A, B, C, D, fminf(fmaxf(-p12 * dyb * i11, dxa), dxb), dyb));
-  return best;
-}
-
-// A lower bound of the float32 q that the ranking evaluates at any pixel centre of the
-// rectangle: the minimum over the rectangle, itself evaluated in float32 (relative error below
-// 16 ulp(1) times the condition number kappa = s_max/s_min, like the ranking's q), shrunk by
-// 64 ulp(1) times kappa.  0 (never skip) when the margin reaches 1 or the input is not finite;
-// capped at 1e37 so that a lane with fewer than K keys (sentinel threshold) never skips.
-__device__ __forceinline__ float safe_lb(float m, float kappa) {
-  const float f = 1.0f - 64.0f * 5.9604644775390625e-8f * kappa;
-  const float v = m * f;
-  if (!(f > 0.f) || !(v >= 0.f)) return 0.f;
-  return fminf(v, 1e37f);
-}
-
-// Bucket of a lower bound: 0 for 0, 1 for (0, 1/4), then one per octave from 1/4 up to >= 2048.
-__device__ __forceinline__ int lb_bucket(float lb) {
-  if (!(lb > 0.f)) return 0;
-  const int e = (int)((__float_as_uint(lb) >> 23) & 0xFF) - 127;  // floor(log2 lb) for normals
-  return 1 + min(max(e + 3, 0), kBuckets - 2);
-}
-// Smallest value any bound in bucket b can have.
-__device__ __forceinline__ float bucket_floor(int b) {
-  return b <= 1 ? 0.f : __uint_as_float((uint32_t)(127 + b - 4) << 23);  // 2^(b-4)
-}
-
-// Maximum over the 64 lanes of a wave, with DPP row shifts and row broadcasts (no LDS); every
-// lane of a row sees the partial maxima of lower lanes, lane 63 the total, which is returned to
-// all lanes as a scalar.
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false));  // shr 1
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false));  // shr 2
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));  // shr 4
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));  // shr 8
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // bcast 15
-  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // bcast 31
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Inclusive sum over the 64 lanes of a wave by DPP: row shifts give each lane the sum of its row
