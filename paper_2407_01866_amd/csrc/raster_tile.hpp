@@ -68,8 +68,9 @@ __device__ __forceinline__ double wave_inclusive_sum_f64(double v) {
 // The forward's LDS: ranking data in visiting order (position m of the batch's candidate order),
 // blend data in slot order (position j in S_j minus the batch base), bucket counters, colours.
 struct FwdLds {
-  float4 *pgeo;   // mu_x, mu_y, A, B
-  float4 *pcd;    // C, D, slot, bucket floor
+  float4 *pcand;  // [fb][2]: (mu_x, mu_y, A, B), (slot, C, D, bucket floor); interleaved so that
+                  // one address serves both reads, the slot first so that it becomes the key's
+                  // low word in place
   float *plbw;    // [kWaves][fb] bounds
   float2 *mu;     // mu_x, mu_y
   double *s64;    // [fb][4] A, B, C, D
@@ -81,8 +82,7 @@ struct FwdLds {
 
 __device__ __forceinline__ FwdLds fwd_lds(unsigned char *smem, int fb) {
   FwdLds S;
-  S.pgeo = reinterpret_cast<float4 *>(smem);
-  S.pcd = reinterpret_cast<float4 *>(smem + 16 * fb);
+  S.pcand = reinterpret_cast<float4 *>(smem);
   S.plbw = reinterpret_cast<float *>(smem + 32 * fb);
   S.mu = reinterpret_cast<float2 *>(smem + 48 * fb);
   S.s64 = reinterpret_cast<double *>(smem + 56 * fb);
@@ -172,8 +172,8 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
     __syncthreads();
     if (tid < nb) {  // scatter the ranking data into visiting order
       const int pos = (int)IGS_IDX(S.bstart[bucket] + brank, fb, kSiteStage);
-      S.pgeo[pos] = a;
-      S.pcd[pos] = make_float4(b.x, b.y, __int_as_float(base + tid), bucket_floor(bucket));
+      S.pcand[2 * pos] = a;
+      S.pcand[2 * pos + 1] = make_float4(__int_as_float(base + tid), b.x, b.y, bucket_floor(bucket));
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) S.plbw[w * fb + pos] = lbw[w];
     }
@@ -186,7 +186,8 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
       const uint32_t th = wave_max_u32((uint32_t)__double2hiint(tk[KT - 1]));
       const float q_tau = __uint_as_float(th - kKeyBias);
       // every later candidate's bound is at least the floor of this position's bucket
-      if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(S.pcd[m].w))) > q_tau)
+      if (__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(S.pcand[2 * m + 1].w))) >
+          q_tau)
         break;
       const float4 lba = *reinterpret_cast<const float4 *>(&S.plbw[wave * fb + m]);
       const float4 lbb = *reinterpret_cast<const float4 *>(&S.plbw[wave * fb + m + 4]);
@@ -195,12 +196,12 @@ __device__ __forceinline__ void rank_tile(const FwdLds &S, int start, int cnt, b
       for (int u = 0; u < 8; ++u) {
         if (m + u >= nb) break;
         if (lbu[u] > q_tau) continue;
-        const float4 g = S.pgeo[m + u];
-        const float4 cd = S.pcd[m + u];
+        const float4 g = S.pcand[2 * (m + u)];
+        const float4 cd = S.pcand[2 * (m + u) + 1];
         const float dx = fx - g.x, dy = fy - g.y;
         const float e1 = fmaf(g.z, dx, g.w * dy);
-        const float e2 = fmaf(cd.x, dx, cd.y * dy);
-        const double key = rank_key(fmaf(e1, e1, e2 * e2), __float_as_int(cd.z));
+        const float e2 = fmaf(cd.y, dx, cd.z * dy);
+        const double key = rank_key(fmaf(e1, e1, e2 * e2), __float_as_int(cd.x));
         if (key < tk[KT - 1]) topk_insert<KT>(tk, key);
       }
     }
