@@ -296,8 +296,8 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
 
   {
     PhaseTimer timer(kPhaseBinning, s);
-    IGS_HIP(launch_binning_reset(status, ranges, d.T, s));
-    IGS_HIP(launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, s));
+    IGS_HIP(
+        launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, status, ranges, d.T, s));
     const bool alt = sort_starts_in_alt(d.passes);
     IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status,
                                 alt ? keys_alt : keys, pair_gid, static_cast<int64_t *>(scan_tmp),
@@ -400,14 +400,11 @@ igs_status fit_l1_impl(const float *params, const Dims &d, const Images &imgs, b
                               batched ? order : nullptr, target, l1_part, part,
                               at<int>(workspace, WL.queue_fwd), s));
   }
-  {
-    PhaseTimer timer(kPhaseLoss, s);
-    IGS_HIP(launch_l1_tiles_final(l1_part, imgs, d.n, loss_out, s));
-  }
+  // the gradient reduction also finishes the loss (one launch less)
   PhaseTimer timer(kPhaseGradReduce, s);
   IGS_HIP(launch_grad_reduce(params, g32a, g32b, at<uint32_t>(saved, SL.counts),
                              at<int64_t>(saved, SL.offsets), at<int64_t>(saved, SL.status), part,
-                             d.N, d.n, grad_params, s));
+                             d.N, d.n, grad_params, s, l1_part, &imgs, loss_out));
   return IGS_OK;
 }
 

@@ -2,6 +2,8 @@
 // circle/tile hit counting, pair emission and per-tile ranges over the sorted pair list.
 #include "common.hpp"
 
+#include <algorithm>
+
 namespace igs {
 namespace {
 
@@ -17,14 +19,6 @@ __global__ void fill_f32_kernel(float *__restrict__ p, int64_t count, float valu
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < count; i += stride) p[i] = value;
-}
-
-__global__ void binning_reset_kernel(int64_t *__restrict__ status, uint32_t *__restrict__ words,
-                                     int64_t count) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 8) status[i] = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < count; i += stride) words[i] = 0u;
 }
 
 // Closed tile rectangle [x0, x1] x [y0, y1] (clipped to the image) against the circle of radius
@@ -135,10 +129,19 @@ __device__ __forceinline__ int box_area(const TileBox &b) {
 
 // Per Gaussian: rotation/inverse-scale coefficients (A, B; C, D) with e = (A dx + B dy,
 // C dx + D dy) = diag(1/s1, 1/s2) R(theta)^T (x - mu), so that q = |e|^2 (Eq. 1-2); kept in
-// float for ranking and in double for the blend weights; plus the exact tile-hit count.
+// float for ranking and in double for the blend weights; plus the exact tile-hit count.  The
+// kernel also zeroes the render's status block and the tile ranges (zero_words words), which
+// the later binning kernels fill in; it is launched with at least one workgroup even for N = 0.
 __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     const float *__restrict__ params, int N, Images imgs, float4 *__restrict__ g32a,
-    float2 *__restrict__ g32b, double4 *__restrict__ g64, uint32_t *__restrict__ counts) {
+    float2 *__restrict__ g32b, double4 *__restrict__ g64, uint32_t *__restrict__ counts,
+    int64_t *__restrict__ status, uint32_t *__restrict__ zero_words, int64_t nzero) {
+  {
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g < 8) status[g] = 0;
+    for (int64_t k = g; k < nzero; k += (int64_t)gridDim.x * kThreads) zero_words[k] = 0u;
+  }
+  if (N <= 0) return;
   const int i = blockIdx.x * kQuadGauss + (int)(threadIdx.x / kQuad);
   const int q = threadIdx.x & (kQuad - 1);
   const bool valid = i < N;
@@ -396,18 +399,13 @@ hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_binning_reset(int64_t *status, int2 *ranges, int T, hipStream_t s) {
-  const int64_t count = 2 * (int64_t)T;
-  binning_reset_kernel<<<grid_for(count > 8 ? count : 8, kThreads, 4096), kThreads, 0, s>>>(
-      status, reinterpret_cast<uint32_t *>(ranges), count);
-  return hipGetLastError();
-}
-
 hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
-                             float2 *g32b, double4 *g64, uint32_t *counts, hipStream_t s) {
-  if (N <= 0) return hipSuccess;
-  preprocess_kernel<<<(N + kQuadGauss - 1) / kQuadGauss, kThreads, 0, s>>>(params, N, imgs, g32a,
-                                                                        g32b, g64, counts);
+                             float2 *g32b, double4 *g64, uint32_t *counts, int64_t *status,
+                             int2 *ranges, int T, hipStream_t s) {
+  const int grid = std::max((N + kQuadGauss - 1) / kQuadGauss, 1);
+  preprocess_kernel<<<grid, kThreads, 0, s>>>(params, N, imgs, g32a, g32b, g64, counts, status,
+                                              reinterpret_cast<uint32_t *>(ranges),
+                                              2 * (int64_t)T);
   return hipGetLastError();
 }
 

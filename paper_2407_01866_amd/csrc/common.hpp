@@ -200,10 +200,10 @@ size_t scan_temp_elems(int64_t n);
 // binning.hip
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s);
-// Zeroes the status block and the T tile ranges in one launch.
-hipError_t launch_binning_reset(int64_t *status, int2 *ranges, int T, hipStream_t s);
+// Also zeroes the status block and the T tile ranges (launched even for N = 0).
 hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
-                             float2 *g32b, double4 *g64, uint32_t *counts, hipStream_t s);
+                             float2 *g32b, double4 *g64, uint32_t *counts, int64_t *status,
+                             int2 *ranges, int T, hipStream_t s);
 // Pair offsets and emission: offsets = exclusive scan of counts (finished inside the emit kernel,
 // which also writes the pair total and overflow flag into the status block); then every
 // Gaussian's tile keys at their emit indices and pair_gid[u], the Gaussian of emit index u.  The
@@ -274,10 +274,14 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uin
                              const float *image, const float *grad_image, const float2 *l1_rec,
                              const uint16_t *slots, const float2 *aux, float *part, int *queue,
                              hipStream_t s);
+// With l1_part, its first workgroups also finish the tile loss sums of the images into
+// loss_out (as launch_l1_tiles_final, bit for bit), saving that launch.
 hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const float2 *g32b,
                               const uint32_t *counts, const int64_t *offsets,
                               const int64_t *status, const float *part, int N, int n,
-                              float *grad_params, hipStream_t s);
+                              float *grad_params, hipStream_t s,
+                              const double2 *l1_part = nullptr, const Images *imgs = nullptr,
+                              double *loss_out = nullptr);
 
 // raster_fit.hip: render, L1 comparison and adjoint of every tile in one pass; writes the tile loss
 // sums (as the fused forward) and the adjoint's per-pair records (as launch_raster_bwd), nothing

@@ -26,6 +26,8 @@
 // exact double-precision expression.
 #include "raster_tile.hpp"
 
+#include <algorithm>
+
 namespace igs {
 namespace {
 
@@ -245,8 +247,15 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(
     const float *__restrict__ params, const float4 *__restrict__ g32a,
     const float2 *__restrict__ g32b, const uint32_t *__restrict__ counts,
     const int64_t *__restrict__ offsets, const int64_t *__restrict__ status,
-    const float *__restrict__ part, int N, int n, float *__restrict__ grad) {
+    const float *__restrict__ part, int N, int n, float *__restrict__ grad,
+    const double2 *__restrict__ l1_part, Images imgs, double *__restrict__ loss_out) {
   constexpr int NR = (5 + NC + 3) & ~3;
+  if (l1_part && (int)blockIdx.x < imgs.B) {  // the loss of image blockIdx.x, first
+    __shared__ double s_loss[2 * kLossThreads / 64];
+    static_assert(kReduceThreads == kLossThreads, "one thread layout for the loss");
+    tile_loss_final(l1_part, imgs.at(blockIdx.x), n, loss_out + 2 * blockIdx.x, s_loss);
+  }
+  if (N <= 0) return;  // (uniform) a launch for the losses alone
   __shared__ uint32_t s_big[kReduceRows];  // per row: record count if the workgroup reduces it
   __shared__ float s_wave[kReduceThreads / 64][NR];
   const int l = threadIdx.x & (kReduceLanes - 1);
@@ -442,13 +451,18 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uin
 hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const float2 *g32b,
                               const uint32_t *counts, const int64_t *offsets,
                               const int64_t *status, const float *part, int N, int n,
-                              float *grad_params, hipStream_t s) {
-  if (N <= 0) return hipSuccess;
-  const int blocks = (int)(((int64_t)N + kReduceRows - 1) / kReduceRows);
+                              float *grad_params, hipStream_t s, const double2 *l1_part,
+                              const Images *imgs, double *loss_out) {
+  const int loss_blocks = l1_part ? imgs->B : 0;
+  const int blocks = std::max((int)(((int64_t)std::max(N, 0) + kReduceRows - 1) / kReduceRows),
+                              loss_blocks);
+  if (blocks <= 0) return hipSuccess;
+  const Images none{};
 #define IGS_RED_NC(NCV)                                                                        \
   if (n <= NCV) {                                                                              \
     grad_reduce_kernel<NCV><<<blocks, kReduceThreads, 0, s>>>(                                 \
-        params, g32a, g32b, counts, offsets, status, part, N, n, grad_params);                  \
+        params, g32a, g32b, counts, offsets, status, part, N, n, grad_params, l1_part,         \
+        l1_part ? *imgs : none, loss_out);                                                     \
     return hipGetLastError();                                                                  \
   }
   IGS_RED_NC(1)

@@ -111,6 +111,57 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// The mean absolute and mean squared differences of one image from its per-tile loss sums
+// (sum |d|, sum d^2), in a fixed order: thread t of a kLossThreads block adds tiles t, t + 256,
+// ... (four loads in flight, added in tile order), then a shuffle tree per wave and the waves in
+// order.  Every thread of the block calls it (it synchronizes the block); thread 0 writes
+// out[0..1].  Shared by the forward's loss pass and the single-pass fit's gradient reduction, so
+// both give the same loss bit for bit.
+constexpr int kLossThreads = 256;
+__device__ __forceinline__ void tile_loss_final(const double2 *__restrict__ part,
+                                                const ImageDesc &im, int n, double *out,
+                                                double *sh) {
+  const int T = im.tiles_x * im.tiles_y;
+  double a = 0.0, b = 0.0;
+  int t = threadIdx.x;
+  for (; t + 3 * kLossThreads < T; t += 4 * kLossThreads) {
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[im.tile_off + t + u * kLossThreads];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a += v[u].x;
+      b += v[u].y;
+    }
+  }
+  for (; t < T; t += kLossThreads) {
+    const double2 v = part[im.tile_off + t];
+    a += v.x;
+    b += v.y;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += __shfl_down(a, d, 64);
+    b += __shfl_down(b, d, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[2 * w] = a;
+    sh[2 * w + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int k = 0; k < kLossThreads / 64; ++k) {
+      sa += sh[2 * k];
+      sb += sh[2 * k + 1];
+    }
+    const double inv = 1.0 / ((double)n * (double)im.H * (double)im.W);
+    out[0] = sa * inv;
+    out[1] = sb * inv;
+  }
+}
+
 // Kernel variants by top-K capacity: the smallest KT >= K is used (the first K entries of a
 // sorted top-KT list are the top-K).
 #define IGS_FOR_EACH_KT(X) X(1) X(2) X(4) X(8) X(10) X(16) X(32)

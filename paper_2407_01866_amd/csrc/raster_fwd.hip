@@ -32,28 +32,6 @@ struct L1Out {
   double2 *part;        // per tile: (sum |d|, sum d^2)
 };
 
-__device__ __forceinline__ double2 block_sum2(double a, double b, double *sh,
-                                              int nwaves = kRasterThreads / 64) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    a += __shfl_down(a, d, 64);
-    b += __shfl_down(b, d, 64);
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) {
-    sh[2 * w] = a;
-    sh[2 * w + 1] = b;
-  }
-  __syncthreads();
-  double2 t = make_double2(0.0, 0.0);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < nwaves; ++k) {
-      t.x += sh[2 * k];
-      t.y += sh[2 * k + 1];
-    }
-  return t;  // valid in thread 0
-}
-
 // Register budget: six waves per SIMD (<= 80 VGPRs) for lists of up to 10 keys; five with the
 // fused L1 epilogue at 8 and 10 keys, where 80 registers would spill.
 __host__ __device__ constexpr int fwd_min_waves(int kt, bool l1, bool p) {
@@ -219,36 +197,10 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves(KT, L1, P)))) void raster_fwd_k
 
 // Per image: mean |d| and mean d^2 from the per-tile sums of its tiles (fixed order: thread t
 // adds tiles t, t + 1024, ... in sequence, then a fixed tree over the threads).
-constexpr int kFinalThreads = 1024;
-
-__global__ __launch_bounds__(kFinalThreads) void l1_tiles_final_kernel(
+__global__ __launch_bounds__(kLossThreads) void l1_tiles_final_kernel(
     const double2 *__restrict__ part, Images imgs, int n, double *__restrict__ out) {
-  __shared__ double sh[2 * kFinalThreads / 64];
-  const ImageDesc im = imgs.at(blockIdx.x);
-  const int T = im.tiles_x * im.tiles_y;
-  double a = 0.0, b = 0.0;
-  int t = threadIdx.x;
-  for (; t + 3 * kFinalThreads < T; t += 4 * kFinalThreads) {  // four loads in flight
-    double2 v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = part[im.tile_off + t + u * kFinalThreads];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a += v[u].x;
-      b += v[u].y;
-    }
-  }
-  for (; t < T; t += kFinalThreads) {
-    const double2 v = part[im.tile_off + t];
-    a += v.x;
-    b += v.y;
-  }
-  const double2 s = block_sum2(a, b, sh, kFinalThreads / 64);
-  if (threadIdx.x == 0) {
-    const double inv = 1.0 / ((double)n * (double)im.H * (double)im.W);
-    out[2 * blockIdx.x] = s.x * inv;
-    out[2 * blockIdx.x + 1] = s.y * inv;
-  }
+  __shared__ double sh[2 * kLossThreads / 64];
+  tile_loss_final(part, imgs.at(blockIdx.x), n, out + 2 * blockIdx.x, sh);
 }
 
 template <int KT, bool L1, bool P>
@@ -311,7 +263,7 @@ hipError_t launch_raster_fwd(const int2 *ranges, const uint32_t *vals, const flo
 
 hipError_t launch_l1_tiles_final(const double2 *l1_part, const Images &imgs, int n,
                                  double *loss_out, hipStream_t s) {
-  l1_tiles_final_kernel<<<imgs.B, kFinalThreads, 0, s>>>(l1_part, imgs, n, loss_out);
+  l1_tiles_final_kernel<<<imgs.B, kLossThreads, 0, s>>>(l1_part, imgs, n, loss_out);
   return hipGetLastError();
 }
 
