@@ -272,6 +272,16 @@ KERNEL_SOURCES = {"raster_fwd": "raster_fwd.hip", "raster_bwd": "raster_bwd.hip"
 # headers whose device code the raster kernels inline
 KERNEL_HEADERS = ("raster_tile.hpp", "raster_common.hpp")
 PROFILE_CMDS = {
+    "decode_trace": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/qprof/trace -o t -- "
+                    "python3 bench.py --decode-profile",
+    "decode_sq": "rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_INSTS_LDS SQ_THREAD_CYCLES_VALU "
+                 "SQ_INSTS_VMEM_RD SQ_WAIT_INST_ANY SQ_BUSY_CYCLES GRBM_GUI_ACTIVE "
+                 "--kernel-include-regex query -f csv -d gpurun_out/qprof/sq -o p -- python3 "
+                 "bench.py --decode-profile",
+    "decode_fetch": "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex query -f csv -d "
+                    "gpurun_out/qprof/fetch -o p -- python3 bench.py --decode-profile",
+    "decode_write": "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex query -f csv -d "
+                    "gpurun_out/qprof/write -o p -- python3 bench.py --decode-profile",
     "trace": "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o trace -- "
              "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-context --batch-iters 0 --large-iters 0 --no-ssim --no-decode "
              "--launch-config 0,0,1",
@@ -424,6 +434,61 @@ def summarize_profiles(out_dir):
                    f"write_kib {wk[0]:.1f} read_bytes {rb:.4g} write_bytes {wb:.4g} "
                    f"traffic_bytes {rb + wb:.4g}")
     open(TRAFFIC_FILE, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+    qdir = os.path.join(out_dir, "qprof")
+    if os.path.isdir(qdir):
+        summarize_decode_profile(qdir, f_factor * 1024, w_factor * 1024)
+
+
+def summarize_decode_profile(qdir, fetch_per_kib, write_per_kib):
+    """The decode path's summary: kernel trace and SQ/traffic counters of `query_kernel` from the
+    four rocprofv3 runs of bench.py --decode-profile under qdir."""
+    import csv
+    import collections
+    import glob
+    import hashlib
+    import re
+
+    def pmc(sub):
+        f = glob.glob(os.path.join(qdir, sub, "**", "*counter_collection.csv"), recursive=True)[0]
+        per = collections.defaultdict(list)
+        for r in csv.DictReader(open(f)):
+            if "query_kernel" in r["Kernel_Name"]:
+                per[r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in per.items()}
+
+    stats = glob.glob(os.path.join(qdir, "trace", "**", "*kernel_stats.csv"), recursive=True)[0]
+    rows = [r for r in csv.DictReader(open(stats))
+            if any(k in r["Name"] for k in ("query", "radix", "scan_block_kernel<unsigned int, unsigned int>"))]
+    sq, fe, wr = pmc("sq"), pmc("fetch"), pmc("write")
+    h = hashlib.sha256()
+    for name in ("query.hip", "raster_common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2407_01866_amd", "csrc", name), "rb").read())
+    cyc = sq["GRBM_GUI_ACTIVE"] / 8
+    out = ["# Random-access decoding, texture-2048x2048-n9-N100000 (initial Gaussians): 4,194,304 "
+           "uniform points per call",
+           "# commands (from the repository root on the GPU box, TMPDIR=/tmp):"]
+    out += ["#   " + PROFILE_CMDS[k] for k in ("decode_trace", "decode_sq", "decode_fetch",
+                                             "decode_write")]
+    out += [f"# bytes: FETCH_SIZE x {fetch_per_kib:.1f} and WRITE_SIZE x {write_per_kib:.1f} per "
+            "counted KiB (the copy calibration of the raster traffic summary); issue_busy = "
+            "SQ_INSTS_VALU x 4 cycles / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8); active_lanes = "
+            "SQ_THREAD_CYCLES_VALU / (64 SQ_INSTS_VALU)",
+            f"source_sha256(query.hip+raster_common.hpp) {h.hexdigest()[:16]}"]
+    for r in rows:
+        name = re.sub(r"\(.*", "", r["Name"].replace("void ", "").replace(
+            "igs::(anonymous namespace)::", ""))
+        out.append(f"kernel {name} calls {r['Calls']} avg_us {float(r['AverageNs']) / 1e3:.2f}")
+    out.append(f"query_kernel valu_insts {sq['SQ_INSTS_VALU']:.4g} waves {sq['SQ_WAVES']:.0f} "
+               f"valu_per_wave {sq['SQ_INSTS_VALU'] / sq['SQ_WAVES']:.0f} vmem_rd_per_wave "
+               f"{sq['SQ_INSTS_VMEM_RD'] / sq['SQ_WAVES']:.0f} issue_busy "
+               f"{sq['SQ_INSTS_VALU'] * 4 / 1024 / cyc:.3f} active_lanes "
+               f"{sq['SQ_THREAD_CYCLES_VALU'] / (64 * sq['SQ_INSTS_VALU']):.3f}")
+    out.append(f"query_kernel fetch_kib {fe['FETCH_SIZE']:.4g} write_kib {wr['WRITE_SIZE']:.4g} "
+               f"read_bytes {fe['FETCH_SIZE'] * fetch_per_kib:.4g} write_bytes "
+               f"{wr['WRITE_SIZE'] * write_per_kib:.4g}")
+    open(os.path.join(PROFILES, "query_decode_texture-2048x2048-n9-N100000.txt"), "w").write(
+        "\n".join(out) + "\n")
     print("\n".join(out))
 
 
