@@ -499,7 +499,7 @@ def measured_valu(kernel, fused=True):
         return None
     want = {"raster_fwd": "raster_fwd_kernel<10,true,false>",
             "raster_bwd": "raster_bwd_kernel<9,10,true>",
-            "raster_fit": "raster_fit_kernel<9,10>"}[kernel]
+            "raster_fit": "raster_fit_kernel<9,10,false>"}[kernel]
     for line in open(VALU_FILE):
         f = line.split()
         if len(f) > 2 and f[0] == "kernel" and f[1] == want:
