@@ -113,7 +113,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 
 // The mean absolute and mean squared differences of one image from its per-tile loss sums
 // (sum |d|, sum d^2), in a fixed order: thread t of a kLossThreads block adds tiles t, t + 256,
-// ... (four loads in flight, added in tile order), then a shuffle tree per wave and the waves in
+// ... (eight loads in flight, added in tile order), then a shuffle tree per wave and the waves in
 // order.  Every thread of the block calls it (it synchronizes the block); thread 0 writes
 // out[0..1].  Shared by the forward's loss pass and the single-pass fit's gradient reduction, so
 // both give the same loss bit for bit.
@@ -124,12 +124,12 @@ __device__ __forceinline__ void tile_loss_final(const double2 *__restrict__ part
   const int T = im.tiles_x * im.tiles_y;
   double a = 0.0, b = 0.0;
   int t = threadIdx.x;
-  for (; t + 3 * kLossThreads < T; t += 4 * kLossThreads) {
-    double2 v[4];
+  for (; t + 7 * kLossThreads < T; t += 8 * kLossThreads) {
+    double2 v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = part[im.tile_off + t + u * kLossThreads];
+    for (int u = 0; u < 8; ++u) v[u] = part[im.tile_off + t + u * kLossThreads];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       a += v[u].x;
       b += v[u].y;
     }
