@@ -290,12 +290,20 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(
           a.w += v[u].w;
         }
       }
-      for (; t < c; t += 4) {
-        const float4 v = rec[(size_t)t * stride4 + q];
-        a.x += v.x;
-        a.y += v.y;
-        a.z += v.z;
-        a.w += v.w;
+      // the last (at most three) records of this lane: loads issued together, added in order
+      float4 v[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u)
+        v[u] = t + 4 * u < c ? rec[(size_t)(t + 4 * u) * stride4 + q]
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        if (t + 4 * u < c) {
+          a.x += v[u].x;
+          a.y += v[u].y;
+          a.z += v[u].z;
+          a.w += v[u].w;
+        }
       }
     }
 #pragma unroll

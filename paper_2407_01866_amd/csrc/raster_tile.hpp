@@ -376,7 +376,7 @@ __host__ __device__ constexpr BwdLds bwd_lds() {
   o += 4 * kBatch;
   L.src = o;
   o += 4 * kBatch;
-  L.wave = o;
+  L.wave = o;  // two scans' wave totals
   o += 32;
   L.total = (o + 15) & ~15u;
   return L;
@@ -483,8 +483,8 @@ __device__ __forceinline__ void adjoint_batches(unsigned char *smem, int start, 
     const int packed_ch = chunks_of(my_cnt, r_min) | (chunks_of(my_cnt, r_mid) << 10) |
                           (chunks_of(my_cnt, r_safe) << 20);
     int packed_chunks;
-    __syncthreads();  // s_wave reused
-    const int packed_cho = block_exclusive_scan(packed_ch, s_wave, &packed_chunks);
+    // (a second LDS slot, so the first scan's readers need no barrier before it is written)
+    const int packed_cho = block_exclusive_scan(packed_ch, s_wave + 4, &packed_chunks);
     const int sel = (packed_chunks & 0x3FF) <= kRasterThreads
                         ? 0
                         : (((packed_chunks >> 10) & 0x3FF) <= kRasterThreads ? 10 : 20);
