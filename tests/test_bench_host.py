@@ -38,7 +38,7 @@ def test_counters_are_used_only_for_the_source_they_were_taken_from(tmp_path, mo
                        f"kernel raster_fit source_sha256 {sha} fetch_kib 1 write_kib 1 "
                        "read_bytes 4e8 write_bytes 7e7 traffic_bytes 4.7e+08\n")
     valu = tmp_path / "valu.txt"
-    valu.write_text(f"kernel raster_fit_kernel<9,10> family raster_fit source_sha256 {sha} "
+    valu.write_text(f"kernel raster_fit_kernel<9,10,false> family raster_fit source_sha256 {sha} "
                     "dispatches 8 valu_insts 2.2e+08 lds_insts 2.6e+07 cycles_per_xcd 1.2e+06 "
                     "issue_busy 0.703 active_lanes 0.823 executed_lane_slots 1.412e+10\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(traffic))
