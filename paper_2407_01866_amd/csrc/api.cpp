@@ -20,6 +20,17 @@ static int ceil_log2(int64_t x) {
   return b;
 }
 
+// Pair sort plan: up to 16 key bits, a partition by the top min(8, key_bits) bits and one
+// workgroup per group for the rest (at most 8 bits); the Gaussian index rides in the key when
+// tile and Gaussian bits fit 32 bits together.
+static void set_group_sort(Dims &d) {
+  d.group_sort = d.key_bits <= 16;
+  d.hb = std::min(8, d.key_bits);
+  d.lb = d.key_bits - d.hb;
+  d.gid_shift =
+      d.group_sort && ceil_log2(std::max(d.N, 1)) + d.key_bits <= 32 ? d.key_bits : 0;
+}
+
 Dims make_dims(int N, int n, int H, int W, int K, int64_t cap) {
   Dims d{};
   d.N = N;
@@ -36,6 +47,7 @@ Dims make_dims(int N, int n, int H, int W, int K, int64_t cap) {
   d.passes = (d.key_bits + 7) / 8;
   d.digit_bits = (d.key_bits + d.passes - 1) / d.passes;
   d.sort_blocks = (cap + kSortTileItems - 1) / kSortTileItems;
+  set_group_sort(d);
   return d;
 }
 
@@ -58,6 +70,7 @@ Dims make_batch_dims(const ImageDesc *descs, int B, int n, int K, int64_t cap) {
   d.passes = (d.key_bits + 7) / 8;
   d.digit_bits = (d.key_bits + d.passes - 1) / d.passes;
   d.sort_blocks = (std::max<int64_t>(cap, d.T) + kSortTileItems - 1) / kSortTileItems;
+  set_group_sort(d);
   return d;
 }
 
@@ -130,6 +143,8 @@ WsLayout ws_layout(const Dims &d) {
   o = align_up(o + 8 * sizeof(int));
   L.queue_bwd = o;
   o = align_up(o + 8 * sizeof(int));
+  L.group_part = o;
+  o = align_up(o + 3 * kMaxGroups * sizeof(uint64_t));
   L.l1_tmp = o;
   L.total = o;
   return L;
@@ -296,17 +311,29 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
 
   {
     PhaseTimer timer(kPhaseBinning, s);
-    IGS_HIP(
-        launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, status, ranges, d.T, s));
-    const bool alt = sort_starts_in_alt(d.passes);
-    IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status,
-                                alt ? keys_alt : keys, pair_gid, static_cast<int64_t *>(scan_tmp),
-                                s));
-    IGS_HIP(radix_sort_pairs(keys, src, keys_alt, vals_alt, status, d.cap, d.key_bits, d.passes,
-                             d.digit_bits, hist, hist_off, static_cast<uint32_t *>(scan_tmp), s,
-                             true, true));
-    IGS_HIP(launch_resolve_ranges(src, pair_gid, keys, status, d.cap, vals, ranges, s));
-    IGS_HIP(launch_tile_stats(ranges, d.T, imgs, d.K, raster, status, s));
+    // the group sort writes every tile's range itself; the LSD path needs them zeroed
+    IGS_HIP(launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, status, ranges,
+                              d.group_sort ? 0 : d.T, s));
+    if (d.group_sort) {
+      IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status, keys,
+                                  pair_gid, d.gid_shift, static_cast<int64_t *>(scan_tmp), s));
+      PartitionOffsets po;
+      IGS_HIP(radix_partition_pairs(keys, keys_alt, vals_alt, status, d.cap, d.lb, d.hb, hist,
+                                    hist_off, static_cast<uint32_t *>(scan_tmp), s, &po));
+      IGS_HIP(launch_group_sort(keys_alt, vals_alt, po, d.cap, d.hb, d.lb, d.gid_shift, pair_gid,
+                                imgs, d.T, d.K, raster, status,
+                                at<uint64_t>(workspace, WL.group_part), src, vals, ranges, s));
+    } else {
+      const bool alt = sort_starts_in_alt(d.passes);
+      IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status,
+                                  alt ? keys_alt : keys, pair_gid, 0,
+                                  static_cast<int64_t *>(scan_tmp), s));
+      IGS_HIP(radix_sort_pairs(keys, src, keys_alt, vals_alt, status, d.cap, d.key_bits,
+                               d.passes, d.digit_bits, hist, hist_off,
+                               static_cast<uint32_t *>(scan_tmp), s, true, true));
+      IGS_HIP(launch_resolve_ranges(src, pair_gid, keys, status, d.cap, vals, ranges, s));
+      IGS_HIP(launch_tile_stats(ranges, d.T, imgs, d.K, raster, status, s));
+    }
     if (batched) {
       // largest-first queue: tiles by descending |S_j| (16-bit keys, stable, so ties keep the
       // tile order)

@@ -190,7 +190,8 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
 }
 
 // Writes the tile key of every tile the Gaussian hits at emit index u (from the Gaussian's scanned
-// offset on), and records the Gaussian of each emit index; the pair list is thereby in ascending
+// offset on), and records the Gaussian of each emit index (in the key's bits from gid_shift on
+// when gid_shift > 0, else in pair_gid[u]); the pair list is thereby in ascending
 // Gaussian index, which the stable sort keeps within each tile, and the pairs of Gaussian i are
 // the emit indices [offsets[i], offsets[i] + counts[i]), in row-major tile order.  Nothing is
 // written past the capacity.
@@ -202,7 +203,8 @@ static_assert(kScanBlockItems % kQuadGauss == 0, "an emit block must not straddl
 __global__ __launch_bounds__(kThreads) void emit_kernel(
     const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
     int64_t *__restrict__ offsets, const int64_t *__restrict__ run_sums, int64_t cap,
-    int64_t *__restrict__ status, uint32_t *__restrict__ keys, uint32_t *__restrict__ pair_gid) {
+    int64_t *__restrict__ status, uint32_t *__restrict__ keys, uint32_t *__restrict__ pair_gid,
+    int gid_shift) {
   __shared__ int64_t s_wave[kThreads / 64];
   __shared__ int64_t s_prefix;
   const int i = blockIdx.x * kQuadGauss + (int)(threadIdx.x / kQuad);
@@ -257,8 +259,13 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
       const uint32_t rank = k + (uint32_t)__popc(qm & ((1u << q) - 1u));
       if (hit && rank < c) {
         const int64_t u = IGS_IDX(o + rank, cap, kSiteEmit);
-        keys[u] = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
-        pair_gid[u] = (uint32_t)i;
+        const uint32_t tile = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
+        if (gid_shift) {
+          keys[u] = tile | ((uint32_t)i << gid_shift);
+        } else {
+          keys[u] = tile;
+          pair_gid[u] = (uint32_t)i;
+        }
       }
       k += (uint32_t)__popc(qm);
     }
@@ -283,8 +290,13 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
       const uint32_t rank = k + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
       if (hit && rank < sc) {
         const int64_t u = IGS_IDX(sbase + rank, cap, kSiteEmit);
-        keys[u] = (uint32_t)(tile_off + ty * tiles_x + tx);
-        pair_gid[u] = gid;
+        const uint32_t tile = (uint32_t)(tile_off + ty * tiles_x + tx);
+        if (gid_shift) {
+          keys[u] = tile | (gid << gid_shift);
+        } else {
+          keys[u] = tile;
+          pair_gid[u] = gid;
+        }
       }
       k += (uint32_t)__popcll(m);
     }
@@ -365,6 +377,299 @@ __global__ __launch_bounds__(kStatThreads) void tile_stats_kernel(const int2 *__
   }
 }
 
+// Lanes of the wave whose digit d (its low `bits` bits) equals the calling lane's, among the valid
+// lanes: one ballot per bit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int bits, bool valid) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// Second stage of the pair sort.  The pairs arrive partitioned stably by the top hb bits of the
+// tile key (from emit order, so each group's pairs are in ascending emit index); workgroup g owns
+// group g, the tiles [g 2^lb, (g + 1) 2^lb), and its segment [s0, s1) of the partitioned list.
+// Each wave takes a contiguous share of the segment, in whole rounds of 64 pairs, and counts it
+// per tile (lanes with equal tiles found by match_digit; the lowest of them adds their number to
+// the wave's own counter).  The counts give every tile's range and statistics and, scanned
+// tile-major over the waves, where each wave's pairs of each tile start.  Each wave then scatters
+// its share in order with no further synchronization, since only it touches its own positions.
+// Result: tile-major order with each tile's pairs in ascending emit index, the same as a stable
+// sort of the whole list by tile.  The first IT rounds of a share stay in registers between the
+// two passes, with their ranks; longer shares are read again.  A segment of at most kGroupStage
+// pairs is scattered into LDS and written out contiguously (coalesced stores rather than one
+// memory request per pair); a longer one is scattered to memory directly.
+constexpr int kGroupStage = 12288;
+template <int NT, int IT>
+__global__ __launch_bounds__(NT) void group_sort_kernel(
+    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ emit_idx,
+    const uint32_t *__restrict__ hist_off, const uint32_t *__restrict__ run_sums, int nruns,
+    int64_t nblocks, int64_t cap, int lb, int gid_shift, const uint32_t *__restrict__ pair_gid,
+    Images imgs, int T, int K, const int64_t *__restrict__ status,
+    unsigned long long *__restrict__ part, uint32_t *__restrict__ src, uint32_t *__restrict__ vals,
+    int2 *__restrict__ ranges) {
+  constexpr int kW = NT / 64;
+  static_assert(NT >= 256, "one thread per tile of a group");
+  __shared__ uint32_t wcnt[kW][256];  // per-wave counts, then the wave's next position per tile
+  __shared__ uint32_t tcnt[256], tstart[256];
+  __shared__ int64_t s_pre[kW][2];
+  __shared__ unsigned long long s_st[kW][3];
+  __shared__ uint32_t stage[2][kGroupStage];  // sorted emit indices and Gaussians of the segment
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = blockIdx.x;
+  const int R = 1 << lb;
+  const uint32_t mask = (uint32_t)R - 1;
+  int64_t P = status[kStatOverflow] ? 0 : status[kStatPairs];
+  if (P > cap) P = 0;
+  // the segment: the partition's digit offsets at (g, block 0) and (g + 1, block 0)
+  const int64_t h0 = (int64_t)g * nblocks, h1 = h0 + nblocks;
+  const bool last = g + 1 == (int)gridDim.x;
+  const uint32_t o0 = hist_off[h0];
+  const uint32_t o1 = last ? 0u : hist_off[h1];
+  for (int i = tid; i < kW * 256; i += NT) (&wcnt[0][0])[i] = 0u;
+  int64_t a0 = 0, a1 = 0;
+  if (run_sums) {
+    const int64_t r0 = h0 / kScanBlockItems, r1 = h1 / kScanBlockItems;
+    for (int r = tid; r < nruns; r += NT) {
+      const int64_t v = run_sums[r];
+      a0 += r < r0 ? v : 0;
+      a1 += r < r1 ? v : 0;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      a0 += __shfl_down(a0, d, 64);
+      a1 += __shfl_down(a1, d, 64);
+    }
+    if (lane == 0) {
+      s_pre[w][0] = a0;
+      s_pre[w][1] = a1;
+    }
+  }
+  __syncthreads();
+  if (run_sums) {
+    a0 = a1 = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+      a0 += s_pre[k][0];
+      a1 += s_pre[k][1];
+    }
+  }
+  const int64_t s0 = (int64_t)o0 + a0;
+  const int64_t s1 = last ? P : (int64_t)o1 + a1;
+  // this wave's share [b0, b1)
+  const int64_t share = ((s1 - s0 + kW - 1) / kW + 63) & ~(int64_t)63;
+  const int64_t b0 = min(s0 + (int64_t)w * share, s1), b1 = min(b0 + share, s1);
+  const int rounds = (int)((b1 - b0 + 63) >> 6);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // pass 1: per-wave counts per tile
+  uint32_t kk[IT], vv[IT], rk[IT];
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    const int64_t i = b0 + (int64_t)r * 64 + lane;
+    kk[r] = i < b1 ? keys[i] : 0u;
+    vv[r] = i < b1 ? emit_idx[i] : 0u;
+    rk[r] = 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    if (r >= rounds) break;  // uniform over the wave
+    const bool valid = b0 + (int64_t)r * 64 + lane < b1;
+    const uint32_t d = kk[r] & mask;
+    const uint64_t peers = match_digit(d, lb, valid);
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask), c = (uint32_t)__popcll(peers);
+    rk[r] = rank | (c << 8);
+    if (valid && rank == 0) wcnt[w][d] += c;
+  }
+  for (int r = IT; r < rounds; ++r) {
+    const int64_t i = b0 + (int64_t)r * 64 + lane;
+    const bool valid = i < b1;
+    const uint32_t d = (valid ? keys[i] : 0u) & mask;
+    const uint64_t peers = match_digit(d, lb, valid);
+    if (valid && __popcll(peers & lt_mask) == 0) wcnt[w][d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // tile totals; tile starts (exclusive scan, four tiles per lane of the first wave)
+  if (tid < R) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) t += wcnt[k][tid];
+    tcnt[tid] = t;
+  }
+  __syncthreads();
+  if (w == 0) {
+    uint32_t c[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = lane * 4 + j;
+      c[j] = d < R ? tcnt[d] : 0u;
+      sum += c[j];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    uint32_t run = (uint32_t)s0 + inc - sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = lane * 4 + j;
+      if (d < R) tstart[d] = run;
+      run += c[j];
+    }
+  }
+  __syncthreads();
+  // every wave's first position per tile; ranges and statistics of the group's tiles
+  {
+    unsigned long long mx = 0, ef = 0, eb = 0;
+    if (tid < R) {
+      const uint32_t st = tstart[tid];
+      uint32_t run = st;
+#pragma unroll
+      for (int k = 0; k < kW; ++k) {
+        const uint32_t c = wcnt[k][tid];
+        wcnt[k][tid] = run;
+        run += c;
+      }
+      const int t = g * R + tid;
+      const uint32_t c = tcnt[tid];
+      if (t < T) {
+        ranges[t] = c ? make_int2((int)st, (int)(st + c)) : make_int2(0, 0);
+        if (c) {
+          const ImageDesc im = imgs.by_tile(t);
+          const int lt = t - im.tile_off;
+          const int tx = lt % im.tiles_x, ty = lt / im.tiles_x;
+          const unsigned long long npx =
+              (unsigned long long)min(im.W - tx * kTile, kTile) * min(im.H - ty * kTile, kTile);
+          mx = c;
+          ef = c * npx;
+          eb = (c < (uint32_t)K ? c : (uint32_t)K) * npx;
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const unsigned long long omx = __shfl_down(mx, d, 64);
+      mx = omx > mx ? omx : mx;
+      ef += __shfl_down(ef, d, 64);
+      eb += __shfl_down(eb, d, 64);
+    }
+    if (lane == 0) {
+      s_st[w][0] = mx;
+      s_st[w][1] = ef;
+      s_st[w][2] = eb;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {  // the group's share of the statistics, summed by group_stats_kernel
+    unsigned long long mx = 0, ef = 0, eb = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+      mx = s_st[k][0] > mx ? s_st[k][0] : mx;
+      ef += s_st[k][1];
+      eb += s_st[k][2];
+    }
+    part[3 * g] = mx;
+    part[3 * g + 1] = ef;
+    part[3 * g + 2] = eb;
+  }
+  // pass 2: each wave scatters its share in order (a lane reads its tile's next position, the
+  // lowest lane of the tile then advances it past the round's pairs of that tile)
+  const int64_t n = s1 - s0;
+  const bool staged = n <= kGroupStage;  // uniform over the workgroup
+  auto place = [&](uint32_t base, uint32_t rank, uint32_t e, uint32_t gid) {
+    if (staged) {
+      const int64_t j = IGS_IDX((int64_t)base + rank - s0, n, kSiteSortScatter);
+      stage[0][j] = e;
+      stage[1][j] = gid;
+    } else {
+      const int64_t pos = IGS_IDX((int64_t)base + rank, cap, kSiteSortScatter);
+      src[pos] = e;
+      vals[pos] = gid;
+    }
+  };
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    if (r >= rounds) break;  // uniform over the wave
+    const bool valid = b0 + (int64_t)r * 64 + lane < b1;
+    if (valid) {
+      const uint32_t d = kk[r] & mask, rank = rk[r] & 0xFFu;
+      const uint32_t base = wcnt[w][d];
+      place(base, rank, vv[r],
+            gid_shift ? kk[r] >> gid_shift : pair_gid[IGS_IDX((int64_t)vv[r], cap, kSiteResolve)]);
+      if (rank == 0) wcnt[w][d] = base + (rk[r] >> 8);
+    }
+  }
+  for (int r = IT; r < rounds; ++r) {
+    const int64_t i = b0 + (int64_t)r * 64 + lane;
+    const bool valid = i < b1;
+    const uint32_t key = valid ? keys[i] : 0u;
+    const uint32_t d = key & mask;
+    const uint64_t peers = match_digit(d, lb, valid);
+    if (valid) {
+      const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+      const uint32_t base = wcnt[w][d];
+      const uint32_t e = emit_idx[i];
+      place(base, rank, e,
+            gid_shift ? key >> gid_shift : pair_gid[IGS_IDX((int64_t)e, cap, kSiteResolve)]);
+      if (rank == 0) wcnt[w][d] = base + (uint32_t)__popcll(peers);
+    }
+  }
+  if (staged) {
+    __syncthreads();
+    for (int j = tid; j < (int)n; j += NT) {
+      src[s0 + j] = stage[0][j];
+      vals[s0 + j] = stage[1][j];
+    }
+  }
+}
+
+// The tile statistics of the status block from the groups' shares (integers: exact in any
+// order).  One workgroup; a plain store per word, so no atomics contend for the block's one cache
+// line.  The preprocess kernel zeroed the words and the emit kernel set the skip word on a pair
+// overflow, which this kernel only ever raises.
+constexpr int kStatsThreads = 256;
+__global__ __launch_bounds__(kStatsThreads) void group_stats_kernel(
+    const unsigned long long *__restrict__ part, int G, int slots16, int64_t *__restrict__ status) {
+  __shared__ unsigned long long s_st[kStatsThreads / 64][3];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  unsigned long long mx = 0, ef = 0, eb = 0;
+  for (int g = tid; g < G; g += kStatsThreads) {
+    const unsigned long long m = part[3 * g];
+    mx = m > mx ? m : mx;
+    ef += part[3 * g + 1];
+    eb += part[3 * g + 2];
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long omx = __shfl_down(mx, d, 64);
+    mx = omx > mx ? omx : mx;
+    ef += __shfl_down(ef, d, 64);
+    eb += __shfl_down(eb, d, 64);
+  }
+  if (lane == 0) {
+    s_st[w][0] = mx;
+    s_st[w][1] = ef;
+    s_st[w][2] = eb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = 1; k < kStatsThreads / 64; ++k) {
+      mx = s_st[k][0] > mx ? s_st[k][0] : mx;
+      ef += s_st[k][1];
+      eb += s_st[k][2];
+    }
+    status[kStatMaxList] = (int64_t)mx;
+    status[kStatSlotOverflow] = mx > 0xFFFF ? 1 : 0;
+    if (slots16 && mx > 0xFFFF) status[kStatSkip] = 1;
+    status[kStatEvalsFwd] = (int64_t)ef;
+    status[kStatEvalsBwd] = (int64_t)eb;
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void tile_order_keys_kernel(const int2 *__restrict__ ranges,
                                                                    int T, uint32_t *__restrict__ keys,
                                                                    uint32_t *__restrict__ vals,
@@ -412,12 +717,31 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
 hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
                                const uint32_t *counts, int64_t *offsets, int64_t cap,
                                int64_t *status, uint32_t *keys, uint32_t *pair_gid,
-                               int64_t *scan_tmp, hipStream_t s) {
+                               int gid_shift, int64_t *scan_tmp, hipStream_t s) {
   if (N <= 0) return hipSuccess;  // the status block already holds 0 pairs, no overflow
   hipError_t e = scan_u32_to_i64_blocks(counts, offsets, N, scan_tmp, s);
   if (e != hipSuccess) return e;
   emit_kernel<<<(N + kQuadGauss - 1) / kQuadGauss, kThreads, 0, s>>>(
-      params, N, imgs, counts, offsets, scan_tmp, cap, status, keys, pair_gid);
+      params, N, imgs, counts, offsets, scan_tmp, cap, status, keys, pair_gid, gid_shift);
+  return hipGetLastError();
+}
+
+constexpr int kGroupThreads = 1024;
+constexpr int kGroupItems = 8;
+
+hipError_t launch_group_sort(const uint32_t *keys, const uint32_t *emit_idx,
+                             const PartitionOffsets &po, int64_t cap, int hb, int lb,
+                             int gid_shift, const uint32_t *pair_gid, const Images &imgs, int T,
+                             int K, bool slots16, int64_t *status, uint64_t *group_part,
+                             uint32_t *src, uint32_t *vals, int2 *ranges, hipStream_t s) {
+  if (lb < 0 || lb > 8 || hb < 1 || hb > 8) return hipErrorInvalidValue;
+  unsigned long long *part = reinterpret_cast<unsigned long long *>(group_part);
+  group_sort_kernel<kGroupThreads, kGroupItems><<<1u << hb, kGroupThreads, 0, s>>>(
+      keys, emit_idx, po.hist_off, po.run_sums, po.nruns, po.nblocks, cap, lb, gid_shift,
+      pair_gid, imgs, T, K, status, part, src, vals, ranges);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  group_stats_kernel<<<1, kStatsThreads, 0, s>>>(part, 1 << hb, slots16 ? 1 : 0, status);
   return hipGetLastError();
 }
 

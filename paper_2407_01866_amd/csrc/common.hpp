@@ -172,6 +172,12 @@ struct Dims {
   int64_t HW;
   int key_bits, passes, digit_bits;
   int64_t sort_blocks;
+  // Pair sort by tile.  group_sort (key_bits <= 16): a stable partition by the key's top hb bits,
+  // then one workgroup per group sorting by the low lb bits (launch_group_sort); otherwise LSD
+  // passes of digit_bits.  gid_shift > 0: the emitted keys carry the Gaussian index above the
+  // tile bits (key = tile | gid << gid_shift), so the sorted keys give it without a lookup.
+  bool group_sort;
+  int hb, lb, gid_shift;
 };
 
 Dims make_dims(int N, int n, int H, int W, int K, int64_t cap);
@@ -185,7 +191,8 @@ struct SavedLayout {
 // Byte offsets inside the caller's workspace.
 struct WsLayout {
   size_t keys, keys_alt, vals_alt, pair_gid, hist, hist_off, scan_tmp, part, order_keys,
-      order_keys_alt, order_vals_alt, order_count, l1_part, queue_fwd, queue_bwd, l1_tmp, total;
+      order_keys_alt, order_vals_alt, order_count, l1_part, queue_fwd, queue_bwd, group_part,
+      l1_tmp, total;
 };
 // Floats per (tile, Gaussian) partial-gradient record of the adjoint: 5 geometry sums and n
 // colour sums, padded to a multiple of four (16-byte aligned records).
@@ -209,9 +216,10 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
 // Gaussian's tile keys at their emit indices and pair_gid[u], the Gaussian of emit index u.  The
 // sort carries the emit indices as values (generated by its first pass); launch_resolve_ranges
 // then maps sorted emit indices to Gaussians.  scan_tmp holds scan_temp_elems(N) int64 values.
+// gid_shift > 0: keys carry the Gaussian above the tile bits and pair_gid is not written.
 hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
                                const uint32_t *counts, int64_t *offsets, int64_t cap,
-                               int64_t *status, uint32_t *keys, uint32_t *pair_gid,
+                               int64_t *status, uint32_t *keys, uint32_t *pair_gid, int gid_shift,
                                int64_t *scan_tmp, hipStream_t s);
 hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
                                 const uint32_t *keys, const int64_t *status, int64_t cap,
@@ -220,6 +228,27 @@ hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
 // 65535 also sets the status block's skip word.
 hipError_t launch_tile_stats(const int2 *ranges, int T, const Images &imgs, int K, bool slots16,
                              int64_t *status, hipStream_t s);
+// Where the segments of a stable partition's digits start (radix_partition_pairs): digit g's
+// first pair is hist_off[g * nblocks] plus, when run_sums is set, the sum of run_sums over the
+// runs before run (g * nblocks) / kScanBlockItems.
+struct PartitionOffsets {
+  const uint32_t *hist_off;
+  const uint32_t *run_sums;  // nullptr: hist_off holds full prefixes
+  int nruns;
+  int64_t nblocks;
+};
+// Second stage of the pair sort: one workgroup per group g < 2^hb of the partitioned pairs
+// (keys, emit indices) sorts its segment stably by the low lb key bits and writes the sorted emit
+// indices (src), the Gaussian of each sorted pair (vals: the key's bits from gid_shift on, or
+// pair_gid[emit index] when gid_shift is 0), every tile's range (empty tiles [0, 0)) and the
+// tile statistics of the status block (largest |S_j|, slot overflow, E_fwd, E_bwd; slots16 as
+// in launch_tile_stats), summed from per-group shares in group_part (kMaxGroups x 3 words).
+constexpr int kMaxGroups = 256;
+hipError_t launch_group_sort(const uint32_t *keys, const uint32_t *emit_idx,
+                             const PartitionOffsets &po, int64_t cap, int hb, int lb,
+                             int gid_shift, const uint32_t *pair_gid, const Images &imgs, int T,
+                             int K, bool slots16, int64_t *status, uint64_t *group_part,
+                             uint32_t *src, uint32_t *vals, int2 *ranges, hipStream_t s);
 // Sort keys for the largest-first tile queue: key = 0xFFFF - min(|S_j|, 0xFFFF), value = tile;
 // also writes T to *count.
 hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uint32_t *vals,
@@ -248,6 +277,13 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                             int passes, int digit_bits, uint32_t *hist, uint32_t *hist_off,
                             uint32_t *scan_tmp, hipStream_t s, bool status_semantics = true,
                             bool identity_vals = false);
+// One stable pass of the pair sort by bits [shift, shift + bits) of keys, from emit order (the
+// values are the emit indices); the pair count comes from the render status block.  Result in
+// (keys_out, emit_out); po receives where each digit's segment starts.
+hipError_t radix_partition_pairs(const uint32_t *keys, uint32_t *keys_out, uint32_t *emit_out,
+                                 const int64_t *status, int64_t cap, int shift, int bits,
+                                 uint32_t *hist, uint32_t *hist_off, uint32_t *scan_tmp,
+                                 hipStream_t s, PartitionOffsets *po);
 // Which buffer emit must write into so the sort's final pass ends in (keys, vals).
 inline bool sort_starts_in_alt(int passes) { return (passes & 1) != 0; }
 

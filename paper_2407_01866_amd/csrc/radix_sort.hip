@@ -131,13 +131,42 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
 
 }  // namespace
 
+// One stable scatter pass by the digit at bits [shift, shift + bits): per-block histograms, the
+// digit-offset scan and the scatter from (src_k, src_v) into (dst_k, dst_v).  The scan leaves
+// per-run prefixes in hist_off and the run totals in scan_tmp (*run_sums = scan_tmp, *nruns runs)
+// when there are at most kSortThreads runs, else the full prefixes (*run_sums = nullptr).
+static hipError_t sort_pass(const uint32_t *src_k, const uint32_t *src_v, uint32_t *dst_k,
+                            uint32_t *dst_v, const int64_t *status, int64_t cap, int shift,
+                            int bits, uint32_t *hist, uint32_t *hist_off, uint32_t *scan_tmp,
+                            int64_t nblocks, hipStream_t s, bool st, bool identity,
+                            const uint32_t **run_sums, int *nruns) {
+  radix_upsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(src_k, status, cap, shift, bits,
+                                                                   hist, nblocks, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t hn = (int64_t)(1 << bits) * nblocks;
+  const int64_t runs = (hn + kScanBlockItems - 1) / kScanBlockItems;
+  *run_sums = nullptr;
+  *nruns = (int)runs;
+  if (runs <= kSortThreads) {
+    e = scan_u32_blocks(hist, hist_off, hn, scan_tmp, s);
+    *run_sums = scan_tmp;
+  } else {
+    e = scan_u32_to_u32(hist, hist_off, hn, scan_tmp, s);
+  }
+  if (e != hipSuccess) return e;
+  radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+      src_k, src_v, dst_k, dst_v, status, cap, shift, bits, hist_off, *run_sums, (int)runs,
+      nblocks, st, identity);
+  return hipGetLastError();
+}
+
 hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                             uint32_t *vals_alt, const int64_t *status, int64_t cap, int key_bits,
                             int passes, int digit_bits, uint32_t *hist, uint32_t *hist_off,
                             uint32_t *scan_tmp, hipStream_t s, bool status_semantics,
                             bool identity_vals) {
   const int64_t nblocks = (cap + kSortTileItems - 1) / kSortTileItems;
-  const int R = 1 << digit_bits;
   // pass p reads from src and writes to dst; with an odd pass count the data starts in alt
   uint32_t *src_k = sort_starts_in_alt(passes) ? keys_alt : keys;
   uint32_t *src_v = sort_starts_in_alt(passes) ? vals_alt : vals;
@@ -148,27 +177,11 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
     int bits = digit_bits;
     if (shift + bits > key_bits) bits = key_bits - shift;
     if (bits < 1) bits = 1;
-    radix_upsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(src_k, status, cap, shift, bits,
-                                                                     hist, nblocks,
-                                                                     status_semantics);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // digit offsets: the per-run prefixes here and the run totals' prefix inside the scatter
-    // kernel, or the whole recursive scan when there are more runs than its threads
-    const int64_t hn = (int64_t)(1 << bits) * nblocks;
-    const int64_t runs = (hn + kScanBlockItems - 1) / kScanBlockItems;
-    const uint32_t *run_sums = nullptr;
-    if (runs <= kSortThreads) {
-      e = scan_u32_blocks(hist, hist_off, hn, scan_tmp, s);
-      run_sums = scan_tmp;
-    } else {
-      e = scan_u32_to_u32(hist, hist_off, hn, scan_tmp, s);
-    }
-    if (e != hipSuccess) return e;
-    radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-        src_k, src_v, dst_k, dst_v, status, cap, shift, bits, hist_off, run_sums, (int)runs,
-        nblocks, status_semantics, identity_vals && p == 0);
-    e = hipGetLastError();
+    const uint32_t *run_sums;
+    int nruns;
+    hipError_t e = sort_pass(src_k, src_v, dst_k, dst_v, status, cap, shift, bits, hist, hist_off,
+                             scan_tmp, nblocks, s, status_semantics, identity_vals && p == 0,
+                             &run_sums, &nruns);
     if (e != hipSuccess) return e;
     uint32_t *tk = src_k, *tv = src_v;
     src_k = dst_k;
@@ -176,8 +189,17 @@ hipError_t radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
     dst_k = tk;
     dst_v = tv;
   }
-  (void)R;
   return hipSuccess;
+}
+
+hipError_t radix_partition_pairs(const uint32_t *keys, uint32_t *keys_out, uint32_t *emit_out,
+                                 const int64_t *status, int64_t cap, int shift, int bits,
+                                 uint32_t *hist, uint32_t *hist_off, uint32_t *scan_tmp,
+                                 hipStream_t s, PartitionOffsets *po) {
+  po->nblocks = (cap + kSortTileItems - 1) / kSortTileItems;
+  po->hist_off = hist_off;
+  return sort_pass(keys, nullptr, keys_out, emit_out, status, cap, shift, bits, hist, hist_off,
+                   scan_tmp, po->nblocks, s, true, true, &po->run_sums, &po->nruns);
 }
 
 }  // namespace igs
