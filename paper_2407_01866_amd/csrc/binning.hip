@@ -42,8 +42,11 @@ struct TileBox {
   double mx, my, r2;
 };
 
-// Candidate tile range of one Gaussian: every tile whose rectangle can meet the circle, widened
-// by one tile on each side so that rounding of mu +- r never drops a tangent tile.
+// Candidate tile range of one Gaussian: every tile whose rectangle can meet the circle.  The test
+// above passes only tiles within r (1 + 2^-51) of mu along each axis (its squares and sum are
+// rounded), and mu -+ r is evaluated to within a few ulps of its magnitude, so the range is taken
+// over mu -+ (r + m) with a margin m = 1e-9 (1 + |mu| + r), far above both: a superset of the
+// hits, each of which is then tested exactly.
 __device__ __forceinline__ TileBox tile_box(float fmx, float fmy, float fs1, float fs2,
                                             int tiles_x, int tiles_y) {
 #pragma clang fp contract(off)
@@ -57,8 +60,9 @@ __device__ __forceinline__ TileBox tile_box(float fmx, float fmy, float fs1, flo
     b.tx1 = b.ty1 = 0;
     return b;
   }
-  double lo_x = floor((b.mx - r) / kTile) - 1.0, hi_x = floor((b.mx + r) / kTile) + 1.0;
-  double lo_y = floor((b.my - r) / kTile) - 1.0, hi_y = floor((b.my + r) / kTile) + 1.0;
+  const double mgx = 1e-9 * (1.0 + fabs(b.mx) + r), mgy = 1e-9 * (1.0 + fabs(b.my) + r);
+  double lo_x = floor((b.mx - r - mgx) / kTile), hi_x = floor((b.mx + r + mgx) / kTile);
+  double lo_y = floor((b.my - r - mgy) / kTile), hi_y = floor((b.my + r + mgy) / kTile);
   lo_x = fmax(lo_x, 0.0);
   lo_y = fmax(lo_y, 0.0);
   hi_x = fmin(hi_x, (double)(tiles_x - 1));
@@ -75,9 +79,44 @@ __device__ __forceinline__ TileBox tile_box(float fmx, float fmy, float fs1, flo
   return b;
 }
 
+// The hits of tile row ty among the columns [tx0, tx1].  Along a row the test above depends on the
+// column only through |dx|, the distance from mu_x to the tile's x-range, and passes for all |dx|
+// up to a threshold (the rounded square and sum are monotone), while |dx| grows with the distance
+// from the column nearest mu_x.  So the hits are one run [L, R] about that column: its ends are
+// found by the exact test at an estimate (mu_x -+ the chord's half width) and at its neighbours.
+// Returns R - L + 1, or 0 when the row has no hit.
+__device__ __forceinline__ int row_run(double mx, double my, double r2, int ty, int tx0, int tx1,
+                                       int H, int W, int &L) {
+#pragma clang fp contract(off)
+  const double y0 = (double)(ty * kTile), y1 = (double)min(ty * kTile + kTile, H);
+  const double cy = my < y0 ? y0 : (my > y1 ? y1 : my);
+  const double dy = my - cy;
+  const double dy2 = dy * dy;
+  // circle_meets_tile for the row's tiles: the same roundings, the row's dy^2 formed once
+  auto hit = [&](int tx) {
+    const double x0 = (double)(tx * kTile), x1 = (double)min(tx * kTile + kTile, W);
+    const double cx = mx < x0 ? x0 : (mx > x1 ? x1 : mx);
+    const double dx = mx - cx;
+    return dx * dx + dy2 <= r2;
+  };
+  const int c = (int)fmin(fmax(floor(mx * (1.0 / kTile)), (double)tx0), (double)tx1);
+  L = c;
+  if (!hit(c)) return 0;
+  // run ends estimated in float (the exact tests below settle them)
+  const float hw = sqrtf(fmaxf((float)(r2 - dy2), 0.f)), mxf = (float)mx;
+  int R = (int)fminf(fmaxf(floorf((mxf + hw) * (1.f / kTile)), (float)c), (float)tx1);
+  int Lx = (int)fmaxf(fminf(floorf((mxf - hw) * (1.f / kTile)), (float)c), (float)tx0);
+  while (R < tx1 && hit(R + 1)) ++R;
+  while (R > c && !hit(R)) --R;
+  while (Lx > tx0 && hit(Lx - 1)) --Lx;
+  while (Lx < c && !hit(Lx)) ++Lx;
+  L = Lx;
+  return R - Lx + 1;
+}
+
 // Gaussians whose candidate tile box has more than this many tiles are enumerated by their
-// whole wave (lane t tests tiles t, t + 64, ... of the box, in the box's row-major order) instead
-// of by their own lane, so one very large Gaussian does not serialize the kernel.
+// whole wave, one box row per lane (row_run), instead of by their own lanes, so one very large
+// Gaussian does not serialize the kernel.
 constexpr int kCoopTiles = 64;
 // Smaller boxes are enumerated by a quad of consecutive lanes per Gaussian (lane q of the quad
 // tests tiles q, q + 4, ... in row-major order), which gives the kernels four times the waves.
@@ -152,6 +191,15 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
   float s1 = params[3 * (size_t)N + ii], s2 = params[4 * (size_t)N + ii];
   TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
   const int area = valid ? box_area(b) : 0;
+  if (valid && q == 0) {  // (before the tile loops, so that little stays live across them)
+    double sn, cs;
+    sincos((double)th, &sn, &cs);
+    double u1 = 1.0 / (double)s1, u2 = 1.0 / (double)s2;
+    double A = u1 * cs, B = u1 * sn, C = -u2 * sn, D = u2 * cs;
+    g64[i] = make_double4(A, B, C, D);
+    g32a[i] = make_float4(mx, my, (float)A, (float)B);
+    g32b[i] = make_float2((float)C, (float)D);
+  }
   uint32_t c = 0;
   if (area > 0 && area <= kCoopTiles) {  // (a non-empty box has width >= 1)
     const int w = b.tx1 - b.tx0 + 1;
@@ -169,24 +217,19 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     const int src = __ffsll((unsigned long long)big) - 1;
     big &= big - 1;
     const CoopBox cb = coop_box(b, im, src);
+    const int rows = cb.area / cb.w;
     uint32_t hits = 0;
-    for (int t0 = 0; t0 < cb.area; t0 += 64) {
-      const int t = t0 + lane;
-      const bool hit = t < cb.area && circle_meets_tile(cb.mx, cb.my, cb.r2, cb.tx0 + t % cb.w,
-                                                        cb.ty0 + t / cb.w, cb.H, cb.W);
-      hits += (uint32_t)__popcll(__ballot(hit));
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+      int L;
+      if (r0 + lane < rows)
+        hits += (uint32_t)row_run(cb.mx, cb.my, cb.r2, cb.ty0 + r0 + lane, cb.tx0,
+                                  cb.tx0 + cb.w - 1, cb.H, cb.W, L);
     }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) hits += __shfl_xor(hits, d, 64);
     if (lane == src) c = hits;
   }
-  if (!valid || q != 0) return;
-  double sn, cs;
-  sincos((double)th, &sn, &cs);
-  double u1 = 1.0 / (double)s1, u2 = 1.0 / (double)s2;
-  double A = u1 * cs, B = u1 * sn, C = -u2 * sn, D = u2 * cs;
-  g64[i] = make_double4(A, B, C, D);
-  g32a[i] = make_float4(mx, my, (float)A, (float)B);
-  g32b[i] = make_float2((float)C, (float)D);
-  counts[i] = c;
+  if (valid && q == 0) counts[i] = c;
 }
 
 // Writes the tile key of every tile the Gaussian hits at emit index u (from the Gaussian's scanned
@@ -281,24 +324,46 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
     const int tiles_x = __builtin_amdgcn_readlane(im.tiles_x, src);
     const int tile_off = __builtin_amdgcn_readlane(im.tile_off, src);
     const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane(i, src);
+    // 64 box rows at a time: each lane finds its row's run, a scan over the lanes places the
+    // runs in row order, then the wave writes the runs one row after another, lanes along the run
+    const int rows = cb.area / cb.w;
     uint32_t k = 0;  // hits written so far (uniform)
-    for (int t0 = 0; t0 < cb.area; t0 += 64) {
-      const int t = t0 + lane;
-      const int tx = cb.tx0 + t % cb.w, ty = cb.ty0 + t / cb.w;
-      const bool hit = t < cb.area && circle_meets_tile(cb.mx, cb.my, cb.r2, tx, ty, cb.H, cb.W);
-      const uint64_t m = __ballot(hit);
-      const uint32_t rank = k + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      if (hit && rank < sc) {
-        const int64_t u = IGS_IDX(sbase + rank, cap, kSiteEmit);
-        const uint32_t tile = (uint32_t)(tile_off + ty * tiles_x + tx);
-        if (gid_shift) {
-          keys[u] = tile | (gid << gid_shift);
-        } else {
-          keys[u] = tile;
-          pair_gid[u] = gid;
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+      int L = 0;
+      const uint32_t cnt = r0 + lane < rows
+                               ? (uint32_t)row_run(cb.mx, cb.my, cb.r2, cb.ty0 + r0 + lane, cb.tx0,
+                                                   cb.tx0 + cb.w - 1, cb.H, cb.W, L)
+                               : 0u;
+      uint32_t inc = cnt;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+      }
+      const uint32_t start = k + inc - cnt;
+      uint64_t live = __ballot(cnt > 0);
+      while (live) {
+        const int rl = __ffsll((unsigned long long)live) - 1;
+        live &= live - 1;
+        const uint32_t rc = (uint32_t)__builtin_amdgcn_readlane((int)cnt, rl);
+        const uint32_t rs = (uint32_t)__builtin_amdgcn_readlane((int)start, rl);
+        const int rL = __builtin_amdgcn_readlane(L, rl);
+        const uint32_t row_key = (uint32_t)(tile_off + (cb.ty0 + r0 + rl) * tiles_x + rL);
+        for (uint32_t j = lane; j < rc; j += 64) {
+          const uint32_t rank = rs + j;
+          if (rank < sc) {
+            const int64_t u = IGS_IDX(sbase + rank, cap, kSiteEmit);
+            const uint32_t tile = row_key + j;
+            if (gid_shift) {
+              keys[u] = tile | (gid << gid_shift);
+            } else {
+              keys[u] = tile;
+              pair_gid[u] = gid;
+            }
+          }
         }
       }
-      k += (uint32_t)__popcll(m);
+      k += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     }
   }
 }
