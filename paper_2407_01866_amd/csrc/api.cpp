@@ -125,8 +125,7 @@ WsLayout ws_layout(const Dims &d) {
   L.hist_off = o;
   o = align_up(o + (size_t)hist_elems * sizeof(uint32_t));
   L.scan_tmp = o;
-  o = align_up(o + std::max(scan_temp_elems(std::max<int64_t>(d.N, 1)) * sizeof(int64_t),
-                            scan_temp_elems(hist_elems) * sizeof(uint32_t)));
+  o = align_up(o + scan_temp_elems(hist_elems) * sizeof(uint32_t));
   L.part = o;
   o = align_up(o + (size_t)d.cap * part_stride(d.n) * sizeof(float));
   L.order_keys = o;  // largest-first tile queue of a batch: sort scratch
@@ -145,6 +144,8 @@ WsLayout ws_layout(const Dims &d) {
   o = align_up(o + 8 * sizeof(int));
   L.group_part = o;
   o = align_up(o + 3 * kMaxGroups * sizeof(uint64_t));
+  L.block_tot = o;
+  o = align_up(o + (size_t)std::max(gauss_blocks(d.N), 1) * sizeof(uint32_t));
   L.l1_tmp = o;
   L.total = o;
   return L;
@@ -312,11 +313,12 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
   {
     PhaseTimer timer(kPhaseBinning, s);
     // the group sort writes every tile's range itself; the LSD path needs them zeroed
-    IGS_HIP(launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, status, ranges,
-                              d.group_sort ? 0 : d.T, s));
+    uint32_t *block_tot = at<uint32_t>(workspace, WL.block_tot);
+    IGS_HIP(launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, offsets, block_tot,
+                              status, ranges, d.group_sort ? 0 : d.T, s));
     if (d.group_sort) {
       IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status, keys,
-                                  pair_gid, d.gid_shift, static_cast<int64_t *>(scan_tmp), s));
+                                  pair_gid, d.gid_shift, block_tot, s));
       PartitionOffsets po;
       IGS_HIP(radix_partition_pairs(keys, keys_alt, vals_alt, status, d.cap, d.lb, d.hb, hist,
                                     hist_off, static_cast<uint32_t *>(scan_tmp), s, &po));
@@ -326,8 +328,7 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
     } else {
       const bool alt = sort_starts_in_alt(d.passes);
       IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status,
-                                  alt ? keys_alt : keys, pair_gid, 0,
-                                  static_cast<int64_t *>(scan_tmp), s));
+                                  alt ? keys_alt : keys, pair_gid, 0, block_tot, s));
       IGS_HIP(radix_sort_pairs(keys, src, keys_alt, vals_alt, status, d.cap, d.key_bits,
                                d.passes, d.digit_bits, hist, hist_off,
                                static_cast<uint32_t *>(scan_tmp), s, true, true));

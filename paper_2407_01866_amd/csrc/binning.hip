@@ -168,13 +168,17 @@ __device__ __forceinline__ int box_area(const TileBox &b) {
 
 // Per Gaussian: rotation/inverse-scale coefficients (A, B; C, D) with e = (A dx + B dy,
 // C dx + D dy) = diag(1/s1, 1/s2) R(theta)^T (x - mu), so that q = |e|^2 (Eq. 1-2); kept in
-// float for ranking and in double for the blend weights; plus the exact tile-hit count.  The
-// kernel also zeroes the render's status block and the tile ranges (zero_words words), which
-// the later binning kernels fill in; it is launched with at least one workgroup even for N = 0.
+// float for ranking and in double for the blend weights; plus the exact tile-hit count, its
+// exclusive prefix within the workgroup's Gaussians (offsets, finished by the emit kernel) and
+// the workgroup's total (block_tot).  The kernel also zeroes the render's status block and
+// zero_words words (the tile ranges, when the sort does not write them all), which the later
+// binning kernels fill in; it is launched with at least one workgroup even for N = 0.
 __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     const float *__restrict__ params, int N, Images imgs, float4 *__restrict__ g32a,
     float2 *__restrict__ g32b, double4 *__restrict__ g64, uint32_t *__restrict__ counts,
-    int64_t *__restrict__ status, uint32_t *__restrict__ zero_words, int64_t nzero) {
+    int64_t *__restrict__ offsets, uint32_t *__restrict__ block_tot, int64_t *__restrict__ status,
+    uint32_t *__restrict__ zero_words, int64_t nzero) {
+  __shared__ uint32_t s_wtot[kThreads / 64];
   {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (g < 8) status[g] = 0;
@@ -229,7 +233,27 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     for (int d = 32; d >= 1; d >>= 1) hits += __shfl_xor(hits, d, 64);
     if (lane == src) c = hits;
   }
-  if (valid && q == 0) counts[i] = c;
+  // exclusive prefix of the workgroup's counts (one per quad, from its first lane)
+  const uint32_t v = (valid && q == 0) ? c : 0u;
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) s_wtot[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  uint32_t woff = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kThreads / 64; ++k) {
+    woff += k < (int)(threadIdx.x >> 6) ? s_wtot[k] : 0u;
+    tot += s_wtot[k];
+  }
+  if (valid && q == 0) {
+    counts[i] = c;
+    offsets[i] = (int64_t)(woff + inc - v);
+  }
+  if (threadIdx.x == 0) block_tot[blockIdx.x] = tot;
 }
 
 // Writes the tile key of every tile the Gaussian hits at emit index u (from the Gaussian's scanned
@@ -238,14 +262,13 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
 // Gaussian index, which the stable sort keeps within each tile, and the pairs of Gaussian i are
 // the emit indices [offsets[i], offsets[i] + counts[i]), in row-major tile order.  Nothing is
 // written past the capacity.
-// offsets arrives as the scan's per-run prefixes (runs of kScanBlockItems counts, whose totals are
-// run_sums); a block's Gaussians lie in one run, so the block adds the sum of the earlier runs'
-// totals (integers: exact in any order), writes the finished offsets back, and the last Gaussian's
-// thread writes the pair total and the overflow flag.
-static_assert(kScanBlockItems % kQuadGauss == 0, "an emit block must not straddle two scan runs");
+// offsets arrives as prefixes within each preprocess workgroup (the emit kernel's workgroups take
+// the same Gaussians), whose totals are block_tot; the block adds the sum of the earlier blocks'
+// totals (integers: exact in any order), writes the finished offsets back, and the last
+// Gaussian's thread writes the pair total and the overflow flag.
 __global__ __launch_bounds__(kThreads) void emit_kernel(
     const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
-    int64_t *__restrict__ offsets, const int64_t *__restrict__ run_sums, int64_t cap,
+    int64_t *__restrict__ offsets, const uint32_t *__restrict__ block_tot, int64_t cap,
     int64_t *__restrict__ status, uint32_t *__restrict__ keys, uint32_t *__restrict__ pair_gid,
     int gid_shift) {
   __shared__ int64_t s_wave[kThreads / 64];
@@ -254,9 +277,8 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
   const int q = threadIdx.x & (kQuad - 1);
   const int lane = threadIdx.x & 63;
   {
-    const int run = (int)(((int64_t)blockIdx.x * kQuadGauss) / kScanBlockItems);
     int64_t part = 0;
-    for (int r = threadIdx.x; r < run; r += kThreads) part += run_sums[r];
+    for (int r = threadIdx.x; r < (int)blockIdx.x; r += kThreads) part += block_tot[r];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) part += __shfl_down(part, d, 64);
     if (lane == 0) s_wave[threadIdx.x >> 6] = part;
@@ -769,11 +791,15 @@ hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s) 
   return hipGetLastError();
 }
 
+int gauss_blocks(int N) { return (N + kQuadGauss - 1) / kQuadGauss; }
+
 hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
-                             float2 *g32b, double4 *g64, uint32_t *counts, int64_t *status,
-                             int2 *ranges, int T, hipStream_t s) {
-  const int grid = std::max((N + kQuadGauss - 1) / kQuadGauss, 1);
-  preprocess_kernel<<<grid, kThreads, 0, s>>>(params, N, imgs, g32a, g32b, g64, counts, status,
+                             float2 *g32b, double4 *g64, uint32_t *counts, int64_t *offsets,
+                             uint32_t *block_tot, int64_t *status, int2 *ranges, int T,
+                             hipStream_t s) {
+  const int grid = std::max(gauss_blocks(N), 1);
+  preprocess_kernel<<<grid, kThreads, 0, s>>>(params, N, imgs, g32a, g32b, g64, counts, offsets,
+                                              block_tot, status,
                                               reinterpret_cast<uint32_t *>(ranges),
                                               2 * (int64_t)T);
   return hipGetLastError();
@@ -782,12 +808,10 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
 hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
                                const uint32_t *counts, int64_t *offsets, int64_t cap,
                                int64_t *status, uint32_t *keys, uint32_t *pair_gid,
-                               int gid_shift, int64_t *scan_tmp, hipStream_t s) {
+                               int gid_shift, const uint32_t *block_tot, hipStream_t s) {
   if (N <= 0) return hipSuccess;  // the status block already holds 0 pairs, no overflow
-  hipError_t e = scan_u32_to_i64_blocks(counts, offsets, N, scan_tmp, s);
-  if (e != hipSuccess) return e;
-  emit_kernel<<<(N + kQuadGauss - 1) / kQuadGauss, kThreads, 0, s>>>(
-      params, N, imgs, counts, offsets, scan_tmp, cap, status, keys, pair_gid, gid_shift);
+  emit_kernel<<<gauss_blocks(N), kThreads, 0, s>>>(params, N, imgs, counts, offsets, block_tot,
+                                                   cap, status, keys, pair_gid, gid_shift);
   return hipGetLastError();
 }
 

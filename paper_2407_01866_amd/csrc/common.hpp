@@ -192,7 +192,7 @@ struct SavedLayout {
 struct WsLayout {
   size_t keys, keys_alt, vals_alt, pair_gid, hist, hist_off, scan_tmp, part, order_keys,
       order_keys_alt, order_vals_alt, order_count, l1_part, queue_fwd, queue_bwd, group_part,
-      l1_tmp, total;
+      block_tot, l1_tmp, total;
 };
 // Floats per (tile, Gaussian) partial-gradient record of the adjoint: 5 geometry sums and n
 // colour sums, padded to a multiple of four (16-byte aligned records).
@@ -207,20 +207,26 @@ size_t scan_temp_elems(int64_t n);
 // binning.hip
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s);
-// Also zeroes the status block and the T tile ranges (launched even for N = 0).
+// Workgroups of the preprocess and emit kernels for N Gaussians (one block_tot word each).
+int gauss_blocks(int N);
+// Per-Gaussian geometry and tile-hit counts, with their exclusive prefix inside each workgroup
+// (offsets) and each workgroup's total (block_tot).  Also zeroes the status block and the T tile
+// ranges (launched even for N = 0).
 hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
-                             float2 *g32b, double4 *g64, uint32_t *counts, int64_t *status,
-                             int2 *ranges, int T, hipStream_t s);
-// Pair offsets and emission: offsets = exclusive scan of counts (finished inside the emit kernel,
-// which also writes the pair total and overflow flag into the status block); then every
-// Gaussian's tile keys at their emit indices and pair_gid[u], the Gaussian of emit index u.  The
-// sort carries the emit indices as values (generated by its first pass); launch_resolve_ranges
-// then maps sorted emit indices to Gaussians.  scan_tmp holds scan_temp_elems(N) int64 values.
-// gid_shift > 0: keys carry the Gaussian above the tile bits and pair_gid is not written.
+                             float2 *g32b, double4 *g64, uint32_t *counts, int64_t *offsets,
+                             uint32_t *block_tot, int64_t *status, int2 *ranges, int T,
+                             hipStream_t s);
+// Pair offsets and emission: offsets = exclusive scan of counts (finished inside the emit kernel
+// from the preprocess kernel's per-workgroup prefixes and totals; it also writes the pair total
+// and overflow flag into the status block); then every Gaussian's tile keys at their emit
+// indices and pair_gid[u], the Gaussian of emit index u.  The sort carries the emit indices as
+// values (generated by its first pass); the Gaussian of a sorted pair then comes from its key
+// (gid_shift > 0: keys carry the Gaussian above the tile bits and pair_gid is not written) or
+// from pair_gid.
 hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
                                const uint32_t *counts, int64_t *offsets, int64_t cap,
                                int64_t *status, uint32_t *keys, uint32_t *pair_gid, int gid_shift,
-                               int64_t *scan_tmp, hipStream_t s);
+                               const uint32_t *block_tot, hipStream_t s);
 hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
                                 const uint32_t *keys, const int64_t *status, int64_t cap,
                                 uint32_t *vals, int2 *ranges, hipStream_t s);
@@ -255,10 +261,6 @@ hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uin
                                   int64_t *count, hipStream_t s);
 
 // scan.hip: exclusive scans; temp must hold scan_temp_elems(n) elements of the output type.
-// Level one of an exclusive scan of uint32 counts into int64 offsets (per-run prefixes and run
-// totals, as scan_u32_blocks).
-hipError_t scan_u32_to_i64_blocks(const uint32_t *in, int64_t *out, int64_t n,
-                                  int64_t *block_sums, hipStream_t s);
 hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *temp,
                            hipStream_t s);
 // Level one of scan_u32_to_u32 alone: exclusive prefixes within each run of kScanBlockItems

@@ -111,14 +111,6 @@ hipError_t scan_u32_blocks(const uint32_t *in, uint32_t *out, int64_t n, uint32_
   return hipGetLastError();
 }
 
-hipError_t scan_u32_to_i64_blocks(const uint32_t *in, int64_t *out, int64_t n,
-                                  int64_t *block_sums, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  scan_block_kernel<uint32_t, int64_t>
-      <<<(unsigned)blocks_for(n), kScanThreads, 0, s>>>(in, out, n, block_sums);
-  return hipGetLastError();
-}
-
 hipError_t scan_f64(const double *in, double *out, int64_t n, double *temp, hipStream_t s) {
   return scan_rec<double, double>(in, out, n, temp, s);
 }
