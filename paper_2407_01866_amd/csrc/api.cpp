@@ -146,6 +146,10 @@ WsLayout ws_layout(const Dims &d) {
   o = align_up(o + 3 * kMaxGroups * sizeof(uint64_t));
   L.block_tot = o;
   o = align_up(o + (size_t)std::max(gauss_blocks(d.N), 1) * sizeof(uint32_t));
+  L.hit_mask = o;
+  o = align_up(o + (size_t)d.N * sizeof(uint64_t));
+  L.hit_box = o;
+  o = align_up(o + (size_t)d.N * sizeof(uint32_t));
   L.l1_tmp = o;
   L.total = o;
   return L;
@@ -314,11 +318,13 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
     PhaseTimer timer(kPhaseBinning, s);
     // the group sort writes every tile's range itself; the LSD path needs them zeroed
     uint32_t *block_tot = at<uint32_t>(workspace, WL.block_tot);
+    uint64_t *hit_mask = at<uint64_t>(workspace, WL.hit_mask);
+    uint32_t *hit_box = at<uint32_t>(workspace, WL.hit_box);
     IGS_HIP(launch_preprocess(params, d.N, imgs, g32a, g32b, g64, counts, offsets, block_tot,
-                              status, ranges, d.group_sort ? 0 : d.T, s));
+                              hit_mask, hit_box, status, ranges, d.group_sort ? 0 : d.T, s));
     if (d.group_sort) {
       IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status, keys,
-                                  pair_gid, d.gid_shift, block_tot, s));
+                                  pair_gid, d.gid_shift, block_tot, hit_mask, hit_box, s));
       PartitionOffsets po;
       IGS_HIP(radix_partition_pairs(keys, keys_alt, vals_alt, status, d.cap, d.lb, d.hb, hist,
                                     hist_off, static_cast<uint32_t *>(scan_tmp), s, &po));
@@ -328,7 +334,8 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
     } else {
       const bool alt = sort_starts_in_alt(d.passes);
       IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status,
-                                  alt ? keys_alt : keys, pair_gid, 0, block_tot, s));
+                                  alt ? keys_alt : keys, pair_gid, 0, block_tot, hit_mask,
+                                  hit_box, s));
       IGS_HIP(radix_sort_pairs(keys, src, keys_alt, vals_alt, status, d.cap, d.key_bits,
                                d.passes, d.digit_bits, hist, hist_off,
                                static_cast<uint32_t *>(scan_tmp), s, true, true));

@@ -123,6 +123,15 @@ constexpr int kCoopTiles = 64;
 constexpr int kQuad = 4;
 constexpr int kQuadGauss = kThreads / kQuad;  // Gaussians per workgroup
 
+// A box of at most kCoopTiles tiles as recorded by the preprocess kernel for the emit kernel:
+// origin (12 bits each; tile coordinates are below 4096) and width - 1 (6 bits), with the hit
+// pattern in a 64-bit mask (bit t = tile t of the box in row-major order).  kBoxCoop marks a box
+// the emit kernel enumerates again itself (larger boxes, which walk rows).
+constexpr uint32_t kBoxCoop = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t pack_box(int tx0, int ty0, int w) {
+  return (uint32_t)tx0 | ((uint32_t)ty0 << 12) | ((uint32_t)(w - 1) << 24);
+}
+
 // Advances (x, y) by k positions in row-major order over rows of width w >= 1.
 __device__ __forceinline__ void rowmajor_step(int &x, int &y, int k, int w) {
   x += k;
@@ -130,11 +139,6 @@ __device__ __forceinline__ void rowmajor_step(int &x, int &y, int k, int w) {
     x -= w;
     ++y;
   }
-}
-
-// The bits of a wave ballot that belong to the calling lane's quad.
-__device__ __forceinline__ uint32_t quad_bits(uint64_t m, int lane) {
-  return (uint32_t)(m >> (lane & ~(kQuad - 1))) & ((1u << kQuad) - 1u);
 }
 
 struct CoopBox {  // the candidate box of one Gaussian, broadcast from its lane
@@ -176,7 +180,8 @@ __device__ __forceinline__ int box_area(const TileBox &b) {
 __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     const float *__restrict__ params, int N, Images imgs, float4 *__restrict__ g32a,
     float2 *__restrict__ g32b, double4 *__restrict__ g64, uint32_t *__restrict__ counts,
-    int64_t *__restrict__ offsets, uint32_t *__restrict__ block_tot, int64_t *__restrict__ status,
+    int64_t *__restrict__ offsets, uint32_t *__restrict__ block_tot,
+    uint64_t *__restrict__ hit_mask, uint32_t *__restrict__ hit_box, int64_t *__restrict__ status,
     uint32_t *__restrict__ zero_words, int64_t nzero) {
   __shared__ uint32_t s_wtot[kThreads / 64];
   {
@@ -205,17 +210,28 @@ __global__ __launch_bounds__(kThreads) void preprocess_kernel(
     g32b[i] = make_float2((float)C, (float)D);
   }
   uint32_t c = 0;
+  uint64_t hm = 0;  // hit pattern of a small box
   if (area > 0 && area <= kCoopTiles) {  // (a non-empty box has width >= 1)
     const int w = b.tx1 - b.tx0 + 1;
     int x = 0, y = 0;
     rowmajor_step(x, y, q, w);
     for (int t = q; t < area; t += kQuad) {
-      c += circle_meets_tile(b.mx, b.my, b.r2, b.tx0 + x, b.ty0 + y, im.H, im.W);
+      if (circle_meets_tile(b.mx, b.my, b.r2, b.tx0 + x, b.ty0 + y, im.H, im.W)) {
+        ++c;
+        hm |= 1ull << t;
+      }
       rowmajor_step(x, y, kQuad, w);
     }
   }
-  c += __shfl_xor(c, 1, 64);  // the quad's total, in every lane of the quad
+  c += __shfl_xor(c, 1, 64);  // the quad's total and pattern, in every lane of the quad
   c += __shfl_xor(c, 2, 64);
+  hm |= __shfl_xor(hm, 1, 64);
+  hm |= __shfl_xor(hm, 2, 64);
+  if (valid && q == 0) {
+    hit_box[i] = area > kCoopTiles ? kBoxCoop
+                                   : (area > 0 ? pack_box(b.tx0, b.ty0, b.tx1 - b.tx0 + 1) : 0u);
+    hit_mask[i] = hm;
+  }
   uint64_t big = __ballot(area > kCoopTiles && q == 0);
   while (big) {
     const int src = __ffsll((unsigned long long)big) - 1;
@@ -270,7 +286,7 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
     const float *__restrict__ params, int N, Images imgs, const uint32_t *__restrict__ counts,
     int64_t *__restrict__ offsets, const uint32_t *__restrict__ block_tot, int64_t cap,
     int64_t *__restrict__ status, uint32_t *__restrict__ keys, uint32_t *__restrict__ pair_gid,
-    int gid_shift) {
+    int gid_shift, const uint64_t *__restrict__ hit_mask, const uint32_t *__restrict__ hit_box) {
   __shared__ int64_t s_wave[kThreads / 64];
   __shared__ int64_t s_prefix;
   const int i = blockIdx.x * kQuadGauss + (int)(threadIdx.x / kQuad);
@@ -304,38 +320,37 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(
   }
   const bool active = c != 0 && o + (int64_t)c <= cap;
   const ImageDesc im = imgs.by_gauss(ii);
-  float mx = params[ii], my = params[(size_t)N + ii];
-  float s1 = params[3 * (size_t)N + ii], s2 = params[4 * (size_t)N + ii];
-  TileBox b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
-  const int area = active ? box_area(b) : 0;
-  if (area > 0 && area <= kCoopTiles) {  // (a non-empty box has width >= 1)
-    // the quad walks the box in row-major order, four tiles per step; a hit's rank is the quad's
-    // hits so far plus those of its lower lanes in this step
-    const int w = b.tx1 - b.tx0 + 1;
-    int x = 0, y = 0;
-    rowmajor_step(x, y, q, w);
-    uint32_t k = 0;
-    for (int t0 = 0; t0 < area; t0 += kQuad) {  // uniform over the quad
-      const int t = t0 + q;
-      const int tx = b.tx0 + x, ty = b.ty0 + y;
-      rowmajor_step(x, y, kQuad, w);
-      const bool hit = t < area && circle_meets_tile(b.mx, b.my, b.r2, tx, ty, im.H, im.W);
-      const uint32_t qm = quad_bits(__ballot(hit), lane);
-      const uint32_t rank = k + (uint32_t)__popc(qm & ((1u << q) - 1u));
-      if (hit && rank < c) {
-        const int64_t u = IGS_IDX(o + rank, cap, kSiteEmit);
-        const uint32_t tile = (uint32_t)(im.tile_off + ty * im.tiles_x + tx);
-        if (gid_shift) {
-          keys[u] = tile | ((uint32_t)i << gid_shift);
-        } else {
-          keys[u] = tile;
-          pair_gid[u] = (uint32_t)i;
-        }
+  const uint32_t bx = active ? hit_box[ii] : 0u;
+  const bool coop = active && bx == kBoxCoop;
+  if (active && !coop) {
+    // a small box's hits from the pattern the preprocess kernel recorded: lane q of the quad
+    // writes the hits of ranks q, q + 4, ... (the pattern's set bits, in row-major order)
+    const int tx0 = (int)(bx & 0xFFFu), ty0 = (int)((bx >> 12) & 0xFFFu), w = (int)(bx >> 24) + 1;
+    const uint32_t inv = (65536u + (uint32_t)w - 1u) / (uint32_t)w;  // (t inv) >> 16 = t / w
+    uint64_t m = hit_mask[ii];                                          // for t < 64, w <= 64
+    for (int k = 0; k < q; ++k) m &= m - 1;
+    for (uint32_t rank = (uint32_t)q; m != 0 && rank < c; rank += kQuad) {
+      const int t = __ffsll((unsigned long long)m) - 1;
+      const int ty = (int)(((uint32_t)t * inv) >> 16), tx = t - ty * w;
+      const int64_t u = IGS_IDX(o + rank, cap, kSiteEmit);
+      const uint32_t tile = (uint32_t)(im.tile_off + (ty0 + ty) * im.tiles_x + tx0 + tx);
+      if (gid_shift) {
+        keys[u] = tile | ((uint32_t)i << gid_shift);
+      } else {
+        keys[u] = tile;
+        pair_gid[u] = (uint32_t)i;
       }
-      k += (uint32_t)__popc(qm);
+#pragma unroll
+      for (int k = 0; k < kQuad; ++k) m &= m - 1;
     }
   }
-  uint64_t big = __ballot(area > kCoopTiles && q == 0);
+  TileBox b{};
+  if (coop) {
+    const float mx = params[ii], my = params[(size_t)N + ii];
+    const float s1 = params[3 * (size_t)N + ii], s2 = params[4 * (size_t)N + ii];
+    b = tile_box(mx, my, s1, s2, im.tiles_x, im.tiles_y);
+  }
+  uint64_t big = __ballot(coop && q == 0);
   while (big) {
     const int src = __ffsll((unsigned long long)big) - 1;
     big &= big - 1;
@@ -795,11 +810,11 @@ int gauss_blocks(int N) { return (N + kQuadGauss - 1) / kQuadGauss; }
 
 hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
                              float2 *g32b, double4 *g64, uint32_t *counts, int64_t *offsets,
-                             uint32_t *block_tot, int64_t *status, int2 *ranges, int T,
-                             hipStream_t s) {
+                             uint32_t *block_tot, uint64_t *hit_mask, uint32_t *hit_box,
+                             int64_t *status, int2 *ranges, int T, hipStream_t s) {
   const int grid = std::max(gauss_blocks(N), 1);
   preprocess_kernel<<<grid, kThreads, 0, s>>>(params, N, imgs, g32a, g32b, g64, counts, offsets,
-                                              block_tot, status,
+                                              block_tot, hit_mask, hit_box, status,
                                               reinterpret_cast<uint32_t *>(ranges),
                                               2 * (int64_t)T);
   return hipGetLastError();
@@ -808,10 +823,12 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
 hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
                                const uint32_t *counts, int64_t *offsets, int64_t cap,
                                int64_t *status, uint32_t *keys, uint32_t *pair_gid,
-                               int gid_shift, const uint32_t *block_tot, hipStream_t s) {
+                               int gid_shift, const uint32_t *block_tot,
+                               const uint64_t *hit_mask, const uint32_t *hit_box, hipStream_t s) {
   if (N <= 0) return hipSuccess;  // the status block already holds 0 pairs, no overflow
   emit_kernel<<<gauss_blocks(N), kThreads, 0, s>>>(params, N, imgs, counts, offsets, block_tot,
-                                                   cap, status, keys, pair_gid, gid_shift);
+                                                   cap, status, keys, pair_gid, gid_shift,
+                                                   hit_mask, hit_box);
   return hipGetLastError();
 }
 

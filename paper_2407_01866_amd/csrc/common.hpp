@@ -192,7 +192,7 @@ struct SavedLayout {
 struct WsLayout {
   size_t keys, keys_alt, vals_alt, pair_gid, hist, hist_off, scan_tmp, part, order_keys,
       order_keys_alt, order_vals_alt, order_count, l1_part, queue_fwd, queue_bwd, group_part,
-      block_tot, l1_tmp, total;
+      block_tot, hit_mask, hit_box, l1_tmp, total;
 };
 // Floats per (tile, Gaussian) partial-gradient record of the adjoint: 5 geometry sums and n
 // colour sums, padded to a multiple of four (16-byte aligned records).
@@ -210,12 +210,13 @@ hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t s);
 // Workgroups of the preprocess and emit kernels for N Gaussians (one block_tot word each).
 int gauss_blocks(int N);
 // Per-Gaussian geometry and tile-hit counts, with their exclusive prefix inside each workgroup
-// (offsets) and each workgroup's total (block_tot).  Also zeroes the status block and the T tile
-// ranges (launched even for N = 0).
+// (offsets) and each workgroup's total (block_tot), and for the emit kernel each Gaussian's
+// candidate box and hit pattern (hit_box, hit_mask; N each).  Also zeroes the status block and
+// the T tile ranges (launched even for N = 0).
 hipError_t launch_preprocess(const float *params, int N, const Images &imgs, float4 *g32a,
                              float2 *g32b, double4 *g64, uint32_t *counts, int64_t *offsets,
-                             uint32_t *block_tot, int64_t *status, int2 *ranges, int T,
-                             hipStream_t s);
+                             uint32_t *block_tot, uint64_t *hit_mask, uint32_t *hit_box,
+                             int64_t *status, int2 *ranges, int T, hipStream_t s);
 // Pair offsets and emission: offsets = exclusive scan of counts (finished inside the emit kernel
 // from the preprocess kernel's per-workgroup prefixes and totals; it also writes the pair total
 // and overflow flag into the status block); then every Gaussian's tile keys at their emit
@@ -226,7 +227,8 @@ hipError_t launch_preprocess(const float *params, int N, const Images &imgs, flo
 hipError_t launch_offsets_emit(const float *params, int N, const Images &imgs,
                                const uint32_t *counts, int64_t *offsets, int64_t cap,
                                int64_t *status, uint32_t *keys, uint32_t *pair_gid, int gid_shift,
-                               const uint32_t *block_tot, hipStream_t s);
+                               const uint32_t *block_tot, const uint64_t *hit_mask,
+                               const uint32_t *hit_box, hipStream_t s);
 hipError_t launch_resolve_ranges(const uint32_t *src, const uint32_t *pair_gid,
                                 const uint32_t *keys, const int64_t *status, int64_t cap,
                                 uint32_t *vals, int2 *ranges, hipStream_t s);
