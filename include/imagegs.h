@@ -236,8 +236,12 @@ igs_status igs_bin(const float *params, int32_t N, int32_t n, int32_t H, int32_t
                    int32_t tile_h, int32_t tile_w, int64_t pair_capacity, void *saved,
                    size_t saved_bytes, void *workspace, size_t ws_bytes, void *stream);
 
-/* Scratch bytes igs_query needs to sort M points by tile for an H x W image. */
-igs_status igs_query_workspace_size(int32_t M, int32_t H, int32_t W, size_t *ws_bytes);
+/* Scratch bytes igs_query needs for M points and N Gaussians of n channels on an H x W image:
+ * the sort of the points by tile, and one packed record per Gaussian (its ranking and blend
+ * geometry and colours, 128 bytes for n <= 16), so that a query reads one record per hit-set
+ * member instead of gathering from n + 3 arrays.  Errors: IGS_ERR_INVALID_ARG. */
+igs_status igs_query_workspace_size(int32_t M, int32_t N, int32_t n, int32_t H, int32_t W,
+                                    size_t *ws_bytes);
 
 /*
  * Random access (Sec. 1, Sec. 3.2): the colour of the representation at M arbitrary points of
@@ -251,10 +255,11 @@ igs_status igs_query_workspace_size(int32_t M, int32_t H, int32_t W, size_t *ws_
  *          or not finite give 0
  *   out    [M][n] float32 device output: the n channels of each point together
  *   workspace  NULL: the points are evaluated in input order (right when they are already
- *          grouped by tile, e.g. in scanline order); else device scratch of at least
- *          igs_query_workspace_size bytes, 256-byte aligned, used to sort the points by tile
- *          first (a stable sort, so results do not depend on it) so that neighbouring lanes
- *          share a hit set
+ *          grouped by tile, e.g. in scanline order), reading the Gaussians' data where `saved`
+ *          and `params` hold it; else device scratch of at least igs_query_workspace_size
+ *          bytes, 256-byte aligned, used to sort the points by tile first (a stable sort, so
+ *          results do not depend on it) so that neighbouring lanes share a hit set, and to pack
+ *          each Gaussian's data into one record (the results are the same either way)
  * Errors: IGS_ERR_INVALID_ARG, IGS_ERR_UNSUPPORTED (tile size), IGS_ERR_WORKSPACE (saved or
  * workspace too small or misaligned), IGS_ERR_HIP.
  */

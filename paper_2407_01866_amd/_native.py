@@ -146,7 +146,7 @@ def load(path: str) -> ctypes.CDLL:
     L.igs_bin.restype = i32
     L.igs_query.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, i64, vp, sz, vp, i32, vp, vp,
                             sz, vp]
-    L.igs_query_workspace_size.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+    L.igs_query_workspace_size.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
     L.igs_query_workspace_size.restype = i32
     L.igs_query.restype = i32
     L.igs_params_to_fp16.argtypes = [vp, i32, i32, vp, vp]
@@ -385,9 +385,10 @@ def igs_bin(params, N, n, H, W, K, tile_h, tile_w, cap, saved, saved_bytes, work
         _ptr(saved), saved_bytes, _ptr(workspace), ws_bytes, _stream(stream)))
 
 
-def igs_query_workspace_size(M: int, H: int, W: int) -> int:
+def igs_query_workspace_size(M: int, N: int, n: int, H: int, W: int) -> int:
     ws = ctypes.c_size_t(0)
-    _check("igs_query_workspace_size", lib().igs_query_workspace_size(M, H, W, ctypes.byref(ws)))
+    _check("igs_query_workspace_size",
+           lib().igs_query_workspace_size(M, N, n, H, W, ctypes.byref(ws)))
     return ws.value
 
 

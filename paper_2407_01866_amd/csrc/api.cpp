@@ -206,7 +206,7 @@ using namespace igs;
     if ((call) != hipSuccess) return IGS_ERR_HIP; \
   } while (0)
 
-IGS_API int32_t igs_abi_version(void) { return 2; }
+IGS_API int32_t igs_abi_version(void) { return 3; }
 
 #ifdef IGS_BOUNDS_CHECK
 namespace igs {
@@ -513,9 +513,11 @@ IGS_API igs_status igs_bin(const float *params, int32_t N, int32_t n, int32_t H,
                      static_cast<hipStream_t>(stream), nullptr, nullptr, false);
 }
 
-IGS_API igs_status igs_query_workspace_size(int32_t M, int32_t H, int32_t W, size_t *ws_bytes) {
-  if (M < 0 || H < 1 || W < 1 || !ws_bytes) return IGS_ERR_INVALID_ARG;
-  *ws_bytes = query_workspace_bytes(M, H, W);
+IGS_API igs_status igs_query_workspace_size(int32_t M, int32_t N, int32_t n, int32_t H,
+                                            int32_t W, size_t *ws_bytes) {
+  if (M < 0 || N < 0 || n < 1 || n > IGS_MAX_CHANNELS || H < 1 || W < 1 || !ws_bytes)
+    return IGS_ERR_INVALID_ARG;
+  *ws_bytes = query_workspace_bytes(M, N, n, H, W);
   return IGS_OK;
 }
 
@@ -532,7 +534,7 @@ IGS_API igs_status igs_query(const float *params, int32_t N, int32_t n, int32_t 
   const SavedLayout SL = saved_layout(d);
   if (saved_bytes < SL.total) return IGS_ERR_WORKSPACE;
   if (!aligned(saved)) return IGS_ERR_WORKSPACE;
-  if (workspace && (ws_bytes < query_workspace_bytes(M, H, W) || !aligned(workspace)))
+  if (workspace && (ws_bytes < query_workspace_bytes(M, N, n, H, W) || !aligned(workspace)))
     return IGS_ERR_WORKSPACE;
   void *sv = const_cast<void *>(saved);
   IGS_HIP(launch_query(params, N, n, H, W, K, at<int2>(sv, SL.ranges), at<uint32_t>(sv, SL.vals),

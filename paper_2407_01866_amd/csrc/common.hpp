@@ -342,7 +342,7 @@ hipError_t launch_l1_ssim_batched(const float *images, const float *targets, con
 
 // Decoding (query.hip): colours at arbitrary points from a binning pass's tile lists; float16
 // storage of the fitter's parameters and decoding of a prefix into renderer units.
-size_t query_workspace_bytes(int64_t M, int H, int W);
+size_t query_workspace_bytes(int64_t M, int N, int n, int H, int W);
 // ws == nullptr: points processed in input order; else they are first sorted by tile.
 hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
                         const int2 *ranges, const uint32_t *vals, const float4 *g32a,

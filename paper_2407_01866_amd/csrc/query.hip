@@ -45,21 +45,40 @@ __global__ __launch_bounds__(kQueryThreads) void query_keys_kernel(
 // NC >= n: the colours are accumulated in registers and each point's n results are written
 // together.  A tile of at most qstage(NC) members has its members' colours staged in the wave's
 // LDS rows while its candidates are loaded, so the blend reads them there instead of gathering
-// n scattered parameters per winner.
+// n scattered parameters per winner.  REC: every Gaussian's data is read from one record of
+// query_rec_stride(n) floats (query_records_kernel) instead of from the three geometry arrays and
+// n parameter rows, so a member touches one or two cache lines instead of up to n + 3.
 __host__ __device__ constexpr int qstage(int nc) { return nc <= 16 ? 128 : 64; }
+// Record of one Gaussian for the point queries: float4 (mu_x, mu_y, A, B) at 0, float2 (C, D) at
+// 4, double4 (A, B, C, D) at 8, the n colours from 16; 128 bytes for n <= 16.
+__host__ __device__ constexpr int query_rec_stride(int n) { return n <= 16 ? 32 : 48; }
+
+__global__ __launch_bounds__(256) void query_records_kernel(
+    const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
+    const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n,
+    float *__restrict__ rec) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float *__restrict__ r = rec + (size_t)i * query_rec_stride(n);
+  *reinterpret_cast<float4 *>(r) = g32a[i];
+  *reinterpret_cast<float2 *>(r + 4) = g32b[i];
+  *reinterpret_cast<double4 *>(r + 8) = g64[i];
+  for (int ch = 0; ch < n; ++ch) r[16 + ch] = params[(size_t)(5 + ch) * N + i];
+}
 template <int NC>
 __host__ __device__ constexpr size_t query_lds_bytes() {
   return (size_t)(kQueryThreads / 64) * qstage(NC) * NC * sizeof(float);
 }
 
-template <int NC, int KT>
+template <int NC, int KT, bool REC>
 __global__ __launch_bounds__(kQueryThreads) void query_kernel(
     const float *__restrict__ params, int N, int n, int H, int W, int K, int tiles_x,
     int tiles_y, const int2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
-    const double4 *__restrict__ g64, const float *__restrict__ pts, int M,
-    const uint32_t *__restrict__ order, float *__restrict__ out) {
+    const double4 *__restrict__ g64, const float *__restrict__ rec, const float *__restrict__ pts,
+    int M, const uint32_t *__restrict__ order, float *__restrict__ out) {
   constexpr int QS = qstage(NC);
+  constexpr int RS = query_rec_stride(NC);
   extern __shared__ __align__(16) unsigned char qsm[];
   float *__restrict__ scol = reinterpret_cast<float *>(qsm) + (threadIdx.x >> 6) * QS * NC;
   const int blk = order ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -105,12 +124,23 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
       float lb = 0.f;
       if (lane < nb) {
         const uint32_t gid = vals[ustart + b0 + lane];
-        a = g32a[gid];
-        b = g32b[gid];
-        if (ucnt <= QS) {
+        if (REC) {
+          const float *__restrict__ r = rec + (size_t)gid * RS;
+          a = *reinterpret_cast<const float4 *>(r);
+          b = *reinterpret_cast<const float2 *>(r + 4);
+          if (ucnt <= QS) {
 #pragma unroll
-          for (int ch = 0; ch < NC; ++ch)
-            if (ch < n) scol[(b0 + lane) * NC + ch] = params[(size_t)(5 + ch) * N + gid];
+            for (int ch = 0; ch < NC; ++ch)
+              if (ch < n) scol[(b0 + lane) * NC + ch] = r[16 + ch];
+          }
+        } else {
+          a = g32a[gid];
+          b = g32b[gid];
+          if (ucnt <= QS) {
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch)
+              if (ch < n) scol[(b0 + lane) * NC + ch] = params[(size_t)(5 + ch) * N + gid];
+          }
         }
         const float A = a.z, B = a.w, C = b.x, D = b.y;
         const float p11 = fmaf(A, A, C * C), p12 = fmaf(A, B, C * D), p22 = fmaf(B, B, D * D);
@@ -171,8 +201,10 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
         if (k < keff && key_valid(tk[k])) {
           slot[k] = key_slot(tk[k]);
           const uint32_t gid = vals[start + slot[k]];
-          const double4 c = g64[gid];
-          const float4 ga = g32a[gid];
+          const double4 c = REC ? *reinterpret_cast<const double4 *>(rec + (size_t)gid * RS + 8)
+                                : g64[gid];
+          const float4 ga = REC ? *reinterpret_cast<const float4 *>(rec + (size_t)gid * RS)
+                                : g32a[gid];
           double e1, e2;
           const double q = quad_form64(fx, fy, ga.x, ga.y, c.x, c.y, c.z, c.w, e1, e2);
           if (k == 0) shift = (float)q;
@@ -202,7 +234,11 @@ __global__ __launch_bounds__(kQueryThreads) void query_kernel(
           if (k < keff && key_valid(tk[k])) {
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch)
-              if (ch < n) acc[ch] = fmaf(w[k], params[(size_t)(5 + ch) * N + src[k]], acc[ch]);
+              if (ch < n)
+                acc[ch] = fmaf(w[k],
+                               REC ? rec[(size_t)src[k] * RS + 16 + ch]
+                                   : params[(size_t)(5 + ch) * N + src[k]],
+                               acc[ch]);
           }
         }
       }
@@ -252,14 +288,19 @@ template <int NC>
 hipError_t launch_query_nc(const float *params, int N, int n, int H, int W, int K, int tiles_x,
                            int tiles_y, const int2 *ranges, const uint32_t *vals,
                            const float4 *g32a, const float2 *g32b, const double4 *g64,
-                           const float *points, int M, const uint32_t *order, float *out,
-                           int grid, hipStream_t s) {
+                           const float *rec, const float *points, int M, const uint32_t *order,
+                           float *out, int grid, hipStream_t s) {
   switch (pick_kt(K)) {
 #define IGS_QUERY_CASE(KT)                                                                     \
   case KT:                                                                                     \
-    query_kernel<NC, KT><<<grid, kQueryThreads, query_lds_bytes<NC>(), s>>>(                  \
-        params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals, g32a, g32b, g64, points, M,   \
-        order, out);                                                                           \
+    if (rec)                                                                                   \
+      query_kernel<NC, KT, true><<<grid, kQueryThreads, query_lds_bytes<NC>(), s>>>(          \
+          params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals, g32a, g32b, g64, rec, points, \
+          M, order, out);                                                                      \
+    else                                                                                       \
+      query_kernel<NC, KT, false><<<grid, kQueryThreads, query_lds_bytes<NC>(), s>>>(         \
+          params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals, g32a, g32b, g64, rec, points, \
+          M, order, out);                                                                      \
     break;
     IGS_FOR_EACH_KT(IGS_QUERY_CASE)
 #undef IGS_QUERY_CASE
@@ -270,12 +311,12 @@ hipError_t launch_query_nc(const float *params, int N, int n, int H, int W, int 
 }
 
 struct QueryWs {
-  size_t keys, vals, keys_alt, vals_alt, hist, hist_off, scan_tmp, count, total;
+  size_t keys, vals, keys_alt, vals_alt, hist, hist_off, scan_tmp, count, rec, total;
   int key_bits, passes, digit_bits;
   int64_t nblocks;
 };
 
-QueryWs query_ws(int64_t M, int H, int W) {
+QueryWs query_ws(int64_t M, int N, int n, int H, int W) {
   const int64_t T = (int64_t)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
   QueryWs L{};
   L.key_bits = 1;
@@ -302,12 +343,16 @@ QueryWs query_ws(int64_t M, int H, int W) {
   o += align_up(scan_temp_elems(hist_elems) * sizeof(uint32_t));
   L.count = o;
   o += align_up(sizeof(int64_t));
+  L.rec = o;
+  o += align_up((size_t)std::max(N, 0) * query_rec_stride(n) * sizeof(float));
   L.total = o;
   return L;
 }
 }  // namespace
 
-size_t query_workspace_bytes(int64_t M, int H, int W) { return query_ws(M, H, W).total; }
+size_t query_workspace_bytes(int64_t M, int N, int n, int H, int W) {
+  return query_ws(M, N, n, H, W).total;
+}
 
 hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
                         const int2 *ranges, const uint32_t *vals, const float4 *g32a,
@@ -317,8 +362,9 @@ hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
   const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
   const int grid = (M + kQueryThreads - 1) / kQueryThreads;
   const uint32_t *order = nullptr;
+  const float *rec = nullptr;
   if (ws) {
-    const QueryWs L = query_ws(M, H, W);
+    const QueryWs L = query_ws(M, N, n, H, W);
     char *b = static_cast<char *>(ws);
     uint32_t *keys = reinterpret_cast<uint32_t *>(b + L.keys);
     uint32_t *vs = reinterpret_cast<uint32_t *>(b + L.vals);
@@ -336,15 +382,22 @@ hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
                          reinterpret_cast<uint32_t *>(b + L.scan_tmp), s, false, true);
     if (e != hipSuccess) return e;
     order = vs;
+    if (N > 0) {
+      float *r = reinterpret_cast<float *>(b + L.rec);
+      query_records_kernel<<<(N + 255) / 256, 256, 0, s>>>(g32a, g32b, g64, params, N, n, r);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      rec = r;
+    }
   }
   if (n <= 4) return launch_query_nc<4>(params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals,
-                                         g32a, g32b, g64, points, M, order, out, grid, s);
+                                         g32a, g32b, g64, rec, points, M, order, out, grid, s);
   if (n <= 9) return launch_query_nc<9>(params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals,
-                                         g32a, g32b, g64, points, M, order, out, grid, s);
+                                         g32a, g32b, g64, rec, points, M, order, out, grid, s);
   if (n <= 16) return launch_query_nc<16>(params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals,
-                                           g32a, g32b, g64, points, M, order, out, grid, s);
+                                           g32a, g32b, g64, rec, points, M, order, out, grid, s);
   return launch_query_nc<32>(params, N, n, H, W, K, tiles_x, tiles_y, ranges, vals, g32a, g32b,
-                             g64, points, M, order, out, grid, s);
+                             g64, rec, points, M, order, out, grid, s);
 }
 
 hipError_t launch_to_fp16(const float *src, int64_t count, uint16_t *dst, hipStream_t s) {

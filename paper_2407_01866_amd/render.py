@@ -135,7 +135,7 @@ class Renderer:
         M = int(points.shape[0])
         ws, nbytes = None, 0
         if sort and M > 0:
-            nbytes = nat.igs_query_workspace_size(M, self.H, self.W)
+            nbytes = nat.igs_query_workspace_size(M, self.N, self.n, self.H, self.W)
             if getattr(self, "_qws", None) is None or self._qws.numel() < nbytes:
                 self._qws = _aligned_bytes(nbytes, self.device)
             ws = self._qws

@@ -18,7 +18,7 @@
 
 int main(void) {
     size_t ws = 0, sv = 0;
-    CHECK(igs_abi_version() == 2);
+    CHECK(igs_abi_version() == 3);
     for (int s = -5; s <= 0; ++s) CHECK(igs_status_string(s) != NULL);
     CHECK(igs_render_buffer_sizes(1000, 3, 256, 256, 10, 16, 16, 20000, &ws, &sv) == IGS_OK);
     CHECK(ws > 0 && sv > 0);
@@ -38,8 +38,9 @@ int main(void) {
     CHECK(igs_saved_offsets(1000, 3, 256, 256, 10, 16, 16, 20000, off) == IGS_OK);
     CHECK(off[0] == 0 && off[5] == (int64_t)sv);
     size_t qws = 0, lws = 0, sws = 0, pws = 0;
-    CHECK(igs_query_workspace_size(1000, 64, 64, &qws) == IGS_OK);
-    CHECK(igs_query_workspace_size(-1, 64, 64, &qws) == IGS_ERR_INVALID_ARG);
+    CHECK(igs_query_workspace_size(1000, 500, 3, 64, 64, &qws) == IGS_OK);
+    CHECK(igs_query_workspace_size(-1, 500, 3, 64, 64, &qws) == IGS_ERR_INVALID_ARG);
+    CHECK(igs_query_workspace_size(1000, 500, 0, 64, 64, &qws) == IGS_ERR_INVALID_ARG);
     CHECK(igs_l1_workspace_size(3 * 64 * 64, &lws) == IGS_OK);
     CHECK(igs_l1_ssim_workspace_size(3, 100, 70, &sws) == IGS_OK);
     CHECK(igs_l1_ssim_workspace_size(0, 100, 70, &sws) == IGS_ERR_INVALID_ARG);

@@ -52,7 +52,7 @@ def test_bounds_checked_build_exports_the_same_symbols(nat):
 
 
 def test_abi_version_and_status_strings(nat):
-    assert nat.igs_abi_version() == 2
+    assert nat.igs_abi_version() == 3
     assert nat.igs_status_string(0) == "ok"
     for s in (-1, -2, -3, -4):
         assert nat.igs_status_string(s) not in ("ok", "unknown status")
@@ -214,8 +214,10 @@ def test_decoding_validates_before_device_work(nat):
     assert L.igs_query(fake, 10, 3, 16, 16, 10, 16, 16, 100, fake, 1 << 30, fake, 5, fake, fake,
                        8, None) == -2
     sz = ctypes.c_size_t(0)
-    assert L.igs_query_workspace_size(1000, 64, 64, ctypes.byref(sz)) == 0 and sz.value >= 16000
-    assert L.igs_query_workspace_size(-1, 64, 64, ctypes.byref(sz)) == -1
+    assert L.igs_query_workspace_size(1000, 500, 3, 64, 64, ctypes.byref(sz)) == 0
+    assert sz.value >= 16000 + 500 * 128  # the point sort and one 128-byte record per Gaussian
+    assert L.igs_query_workspace_size(-1, 500, 3, 64, 64, ctypes.byref(sz)) == -1
+    assert L.igs_query_workspace_size(1000, 500, 0, 64, 64, ctypes.byref(sz)) == -1
     assert L.igs_params_to_fp16(None, 10, 3, fake, None) == -1
     assert L.igs_decode_fp16(fake, 10, 3, 11, 16, 16, fake, None) == -1
     assert L.igs_decode_fp16(fake, 10, 3, 5, 0, 16, fake, None) == -1
