@@ -53,18 +53,36 @@ __host__ __device__ constexpr int qstage(int nc) { return nc <= 16 ? 128 : 64; }
 // 4, double4 (A, B, C, D) at 8, the n colours from 16; 128 bytes for n <= 16.
 __host__ __device__ constexpr int query_rec_stride(int n) { return n <= 16 ? 32 : 48; }
 
+// One float4 of a record per thread, so that a wave's stores are contiguous: slot 0 the ranking
+// geometry, 1 (C, D), 2-3 the blend geometry, then the colours four at a time (zero past n).
 __global__ __launch_bounds__(256) void query_records_kernel(
     const float4 *__restrict__ g32a, const float2 *__restrict__ g32b,
     const double4 *__restrict__ g64, const float *__restrict__ params, int N, int n,
     float *__restrict__ rec) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slots = query_rec_stride(n) / 4;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = j / slots;
+  const int sl = (int)(j - i * slots);
   if (i >= N) return;
-  float *__restrict__ r = rec + (size_t)i * query_rec_stride(n);
-  *reinterpret_cast<float4 *>(r) = g32a[i];
-  *reinterpret_cast<float2 *>(r + 4) = g32b[i];
-  *reinterpret_cast<double4 *>(r + 8) = g64[i];
-  for (int ch = 0; ch < n; ++ch) r[16 + ch] = params[(size_t)(5 + ch) * N + i];
+  float4 v;
+  if (sl == 0) {
+    v = g32a[i];
+  } else if (sl == 1) {
+    const float2 b = g32b[i];
+    v = make_float4(b.x, b.y, 0.f, 0.f);
+  } else if (sl < 4) {
+    const double2 d = reinterpret_cast<const double2 *>(g64 + i)[sl - 2];
+    __builtin_memcpy(&v, &d, sizeof(v));
+  } else {
+    const int c0 = 4 * (sl - 4);
+    float c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = c0 + u < n ? params[(size_t)(5 + c0 + u) * N + i] : 0.f;
+    v = make_float4(c[0], c[1], c[2], c[3]);
+  }
+  reinterpret_cast<float4 *>(rec)[j] = v;
 }
+
 template <int NC>
 __host__ __device__ constexpr size_t query_lds_bytes() {
   return (size_t)(kQueryThreads / 64) * qstage(NC) * NC * sizeof(float);
@@ -384,7 +402,9 @@ hipError_t launch_query(const float *params, int N, int n, int H, int W, int K,
     order = vs;
     if (N > 0) {
       float *r = reinterpret_cast<float *>(b + L.rec);
-      query_records_kernel<<<(N + 255) / 256, 256, 0, s>>>(g32a, g32b, g64, params, N, n, r);
+      const int64_t nv = (int64_t)N * (query_rec_stride(n) / 4);
+      query_records_kernel<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(g32a, g32b, g64, params,
+                                                                         N, n, r);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       rec = r;
