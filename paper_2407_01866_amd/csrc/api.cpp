@@ -282,7 +282,8 @@ namespace {
 igs_status render_impl(const float *params, const Dims &d, const Images &imgs, bool batched,
                        float *image, void *saved, size_t saved_bytes, void *workspace,
                        size_t ws_bytes, hipStream_t s, const float *target = nullptr,
-                       double *loss_out = nullptr, bool raster = true) {
+                       double *loss_out = nullptr, bool raster = true,
+                       bool defer_stats = false) {
   const SavedLayout SL = saved_layout(d);
   const WsLayout WL = ws_layout(d);
   void *sv = saved;
@@ -330,7 +331,8 @@ igs_status render_impl(const float *params, const Dims &d, const Images &imgs, b
                                     hist_off, static_cast<uint32_t *>(scan_tmp), s, &po));
       IGS_HIP(launch_group_sort(keys_alt, vals_alt, po, d.cap, d.hb, d.lb, d.gid_shift, pair_gid,
                                 imgs, d.T, d.K, raster, status,
-                                at<uint64_t>(workspace, WL.group_part), src, vals, ranges, s));
+                                at<uint64_t>(workspace, WL.group_part), src, vals, ranges,
+                                !defer_stats, s));
     } else {
       const bool alt = sort_starts_in_alt(d.passes);
       IGS_HIP(launch_offsets_emit(params, d.N, imgs, counts, offsets, d.cap, status,
@@ -411,12 +413,13 @@ igs_status backward_impl(const float *params, const Dims &d, const Images &imgs,
 }
 
 // Single-pass L1 evaluation: binning as render_impl, then the fitting kernel (loss sums and
-// per-pair records), the loss reduction and the adjoint's per-Gaussian reduction.
+// per-pair records), the loss reduction and the adjoint's per-Gaussian reduction, which also
+// sums the binning's per-group statistics (one launch less).
 igs_status fit_l1_impl(const float *params, const Dims &d, const Images &imgs, bool batched,
                        const float *target, double *loss_out, float *grad_params, void *saved,
                        size_t saved_bytes, void *workspace, size_t ws_bytes, hipStream_t s) {
   igs_status st = render_impl(params, d, imgs, batched, nullptr, saved, saved_bytes, workspace,
-                              ws_bytes, s, nullptr, nullptr, false);
+                              ws_bytes, s, nullptr, nullptr, false, d.group_sort);
   if (st != IGS_OK) return st;
   const SavedLayout SL = saved_layout(d);
   const WsLayout WL = ws_layout(d);
@@ -435,11 +438,13 @@ igs_status fit_l1_impl(const float *params, const Dims &d, const Images &imgs, b
                               batched ? order : nullptr, target, l1_part, part,
                               at<int>(workspace, WL.queue_fwd), s));
   }
-  // the gradient reduction also finishes the loss (one launch less)
+  // the gradient reduction also finishes the loss and the binning's statistics (two launches less)
   PhaseTimer timer(kPhaseGradReduce, s);
   IGS_HIP(launch_grad_reduce(params, g32a, g32b, at<uint32_t>(saved, SL.counts),
                              at<int64_t>(saved, SL.offsets), at<int64_t>(saved, SL.status), part,
-                             d.N, d.n, grad_params, s, l1_part, &imgs, loss_out));
+                             d.N, d.n, grad_params, s, l1_part, &imgs, loss_out,
+                             d.group_sort ? at<uint64_t>(workspace, WL.group_part) : nullptr,
+                             1 << d.hb));
   return IGS_OK;
 }
 

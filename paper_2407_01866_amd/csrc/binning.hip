@@ -729,47 +729,11 @@ __global__ __launch_bounds__(NT) void group_sort_kernel(
   }
 }
 
-// The tile statistics of the status block from the groups' shares (integers: exact in any
-// order).  One workgroup; a plain store per word, so no atomics contend for the block's one cache
-// line.  The preprocess kernel zeroed the words and the emit kernel set the skip word on a pair
-// overflow, which this kernel only ever raises.
-constexpr int kStatsThreads = 256;
-__global__ __launch_bounds__(kStatsThreads) void group_stats_kernel(
-    const unsigned long long *__restrict__ part, int G, int slots16, int64_t *__restrict__ status) {
-  __shared__ unsigned long long s_st[kStatsThreads / 64][3];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  unsigned long long mx = 0, ef = 0, eb = 0;
-  for (int g = tid; g < G; g += kStatsThreads) {
-    const unsigned long long m = part[3 * g];
-    mx = m > mx ? m : mx;
-    ef += part[3 * g + 1];
-    eb += part[3 * g + 2];
-  }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const unsigned long long omx = __shfl_down(mx, d, 64);
-    mx = omx > mx ? omx : mx;
-    ef += __shfl_down(ef, d, 64);
-    eb += __shfl_down(eb, d, 64);
-  }
-  if (lane == 0) {
-    s_st[w][0] = mx;
-    s_st[w][1] = ef;
-    s_st[w][2] = eb;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int k = 1; k < kStatsThreads / 64; ++k) {
-      mx = s_st[k][0] > mx ? s_st[k][0] : mx;
-      ef += s_st[k][1];
-      eb += s_st[k][2];
-    }
-    status[kStatMaxList] = (int64_t)mx;
-    status[kStatSlotOverflow] = mx > 0xFFFF ? 1 : 0;
-    if (slots16 && mx > 0xFFFF) status[kStatSkip] = 1;
-    status[kStatEvalsFwd] = (int64_t)ef;
-    status[kStatEvalsBwd] = (int64_t)eb;
-  }
+// The tile statistics from the groups' shares, when no later kernel of the call sums them.
+__global__ __launch_bounds__(256) void group_stats_kernel(const unsigned long long *__restrict__ part,
+                                                          int G, int slots16,
+                                                          int64_t *__restrict__ status) {
+  sum_group_stats(part, G, slots16, status);
 }
 
 __global__ __launch_bounds__(kThreads) void tile_order_keys_kernel(const int2 *__restrict__ ranges,
@@ -839,7 +803,8 @@ hipError_t launch_group_sort(const uint32_t *keys, const uint32_t *emit_idx,
                              const PartitionOffsets &po, int64_t cap, int hb, int lb,
                              int gid_shift, const uint32_t *pair_gid, const Images &imgs, int T,
                              int K, bool slots16, int64_t *status, uint64_t *group_part,
-                             uint32_t *src, uint32_t *vals, int2 *ranges, hipStream_t s) {
+                             uint32_t *src, uint32_t *vals, int2 *ranges, bool stats_kernel,
+                             hipStream_t s) {
   if (lb < 0 || lb > 8 || hb < 1 || hb > 8) return hipErrorInvalidValue;
   unsigned long long *part = reinterpret_cast<unsigned long long *>(group_part);
   group_sort_kernel<kGroupThreads, kGroupItems><<<1u << hb, kGroupThreads, 0, s>>>(
@@ -847,7 +812,8 @@ hipError_t launch_group_sort(const uint32_t *keys, const uint32_t *emit_idx,
       pair_gid, imgs, T, K, status, part, src, vals, ranges);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  group_stats_kernel<<<1, kStatsThreads, 0, s>>>(part, 1 << hb, slots16 ? 1 : 0, status);
+  if (!stats_kernel) return hipSuccess;
+  group_stats_kernel<<<1, 256, 0, s>>>(part, 1 << hb, slots16 ? 1 : 0, status);
   return hipGetLastError();
 }
 

@@ -74,6 +74,49 @@ enum StatusWord {
                  // that cannot address a hit set)
 };
 
+// The tile statistics of the status block from per-group shares (part[3 g + 0..2] = largest
+// |S_j|, E_fwd and E_bwd of group g < G; integers, exact in any order), by one workgroup of 256
+// threads: a plain store per word, so no atomics contend for the block's one cache line.  The
+// preprocess kernel zeroed the words and the emit kernel set the skip word on a pair overflow,
+// which this only ever raises (slots16: a hit set beyond 16-bit slots also sets it).
+__device__ inline void sum_group_stats(const unsigned long long *__restrict__ part, int G,
+                                       int slots16, int64_t *__restrict__ status) {
+  __shared__ unsigned long long s_st[4][3];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  unsigned long long mx = 0, ef = 0, eb = 0;
+  for (int g = tid; g < G; g += 256) {
+    const unsigned long long m = part[3 * g];
+    mx = m > mx ? m : mx;
+    ef += part[3 * g + 1];
+    eb += part[3 * g + 2];
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long omx = __shfl_down(mx, d, 64);
+    mx = omx > mx ? omx : mx;
+    ef += __shfl_down(ef, d, 64);
+    eb += __shfl_down(eb, d, 64);
+  }
+  if (lane == 0) {
+    s_st[w][0] = mx;
+    s_st[w][1] = ef;
+    s_st[w][2] = eb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = 1; k < 4; ++k) {
+      mx = s_st[k][0] > mx ? s_st[k][0] : mx;
+      ef += s_st[k][1];
+      eb += s_st[k][2];
+    }
+    status[kStatMaxList] = (int64_t)mx;
+    status[kStatSlotOverflow] = mx > 0xFFFF ? 1 : 0;
+    if (slots16 && mx > 0xFFFF) status[kStatSkip] = 1;
+    status[kStatEvalsFwd] = (int64_t)ef;
+    status[kStatEvalsBwd] = (int64_t)eb;
+  }
+}
+
 // Radix sort geometry.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
@@ -250,13 +293,16 @@ struct PartitionOffsets {
 // indices (src), the Gaussian of each sorted pair (vals: the key's bits from gid_shift on, or
 // pair_gid[emit index] when gid_shift is 0), every tile's range (empty tiles [0, 0)) and the
 // tile statistics of the status block (largest |S_j|, slot overflow, E_fwd, E_bwd; slots16 as
-// in launch_tile_stats), summed from per-group shares in group_part (kMaxGroups x 3 words).
+// in launch_tile_stats), summed from per-group shares in group_part (kMaxGroups x 3 words) by a
+// one-workgroup kernel, or, with stats_kernel false, by a later kernel of the caller's
+// (launch_grad_reduce's group_part).
 constexpr int kMaxGroups = 256;
 hipError_t launch_group_sort(const uint32_t *keys, const uint32_t *emit_idx,
                              const PartitionOffsets &po, int64_t cap, int hb, int lb,
                              int gid_shift, const uint32_t *pair_gid, const Images &imgs, int T,
                              int K, bool slots16, int64_t *status, uint64_t *group_part,
-                             uint32_t *src, uint32_t *vals, int2 *ranges, hipStream_t s);
+                             uint32_t *src, uint32_t *vals, int2 *ranges, bool stats_kernel,
+                             hipStream_t s);
 // Sort keys for the largest-first tile queue: key = 0xFFFF - min(|S_j|, 0xFFFF), value = tile;
 // also writes T to *count.
 hipError_t launch_tile_order_keys(const int2 *ranges, int T, uint32_t *keys, uint32_t *vals,
@@ -315,13 +361,15 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uin
                              const uint16_t *slots, const float2 *aux, float *part, int *queue,
                              hipStream_t s);
 // With l1_part, its first workgroups also finish the tile loss sums of the images into
-// loss_out (as launch_l1_tiles_final, bit for bit), saving that launch.
+// loss_out (as launch_l1_tiles_final, bit for bit), saving that launch.  With group_part, its
+// first workgroup also sums the binning's per-group statistics into the status block (a binning
+// launched with stats_kernel false; 16-bit slots are not involved).
 hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const float2 *g32b,
-                              const uint32_t *counts, const int64_t *offsets,
-                              const int64_t *status, const float *part, int N, int n,
-                              float *grad_params, hipStream_t s,
+                              const uint32_t *counts, const int64_t *offsets, int64_t *status,
+                              const float *part, int N, int n, float *grad_params, hipStream_t s,
                               const double2 *l1_part = nullptr, const Images *imgs = nullptr,
-                              double *loss_out = nullptr);
+                              double *loss_out = nullptr, const uint64_t *group_part = nullptr,
+                              int groups = 0);
 
 // raster_fit.hip: render, L1 comparison and adjoint of every tile in one pass; writes the tile loss
 // sums (as the fused forward) and the adjoint's per-pair records (as launch_raster_bwd), nothing

@@ -246,10 +246,13 @@ template <int NC>
 __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(
     const float *__restrict__ params, const float4 *__restrict__ g32a,
     const float2 *__restrict__ g32b, const uint32_t *__restrict__ counts,
-    const int64_t *__restrict__ offsets, const int64_t *__restrict__ status,
+    const int64_t *__restrict__ offsets, int64_t *__restrict__ status,
     const float *__restrict__ part, int N, int n, float *__restrict__ grad,
-    const double2 *__restrict__ l1_part, Images imgs, double *__restrict__ loss_out) {
+    const double2 *__restrict__ l1_part, Images imgs, double *__restrict__ loss_out,
+    const unsigned long long *__restrict__ group_part, int groups) {
   constexpr int NR = (5 + NC + 3) & ~3;
+  static_assert(kReduceThreads == 256, "sum_group_stats takes one workgroup of 256 threads");
+  if (group_part && blockIdx.x == 0) sum_group_stats(group_part, groups, 0, status);
   if (l1_part && (int)blockIdx.x < imgs.B) {  // the loss of image blockIdx.x, first
     __shared__ double s_loss[2 * kLossThreads / 64];
     static_assert(kReduceThreads == kLossThreads, "one thread layout for the loss");
@@ -457,20 +460,21 @@ hipError_t launch_raster_bwd(const int2 *ranges, const uint32_t *vals, const uin
 }
 
 hipError_t launch_grad_reduce(const float *params, const float4 *g32a, const float2 *g32b,
-                              const uint32_t *counts, const int64_t *offsets,
-                              const int64_t *status, const float *part, int N, int n,
-                              float *grad_params, hipStream_t s, const double2 *l1_part,
-                              const Images *imgs, double *loss_out) {
+                              const uint32_t *counts, const int64_t *offsets, int64_t *status,
+                              const float *part, int N, int n, float *grad_params, hipStream_t s,
+                              const double2 *l1_part, const Images *imgs, double *loss_out,
+                              const uint64_t *group_part, int groups) {
   const int loss_blocks = l1_part ? imgs->B : 0;
   const int blocks = std::max((int)(((int64_t)std::max(N, 0) + kReduceRows - 1) / kReduceRows),
-                              loss_blocks);
+                              std::max(loss_blocks, group_part ? 1 : 0));
   if (blocks <= 0) return hipSuccess;
   const Images none{};
 #define IGS_RED_NC(NCV)                                                                        \
   if (n <= NCV) {                                                                              \
     grad_reduce_kernel<NCV><<<blocks, kReduceThreads, 0, s>>>(                                 \
         params, g32a, g32b, counts, offsets, status, part, N, n, grad_params, l1_part,         \
-        l1_part ? *imgs : none, loss_out);                                                     \
+        l1_part ? *imgs : none, loss_out,                                                      \
+        reinterpret_cast<const unsigned long long *>(group_part), groups);                     \
     return hipGetLastError();                                                                  \
   }
   IGS_RED_NC(1)

@@ -73,3 +73,24 @@ def test_tile_lists_and_statistics(H, W, N, smin, smax):
     assert np.array_equal(ranges[nz, 0], start[nz])
     assert not ranges[~nz].any()
     assert np.array_equal(vals[: counts.sum()], lists)
+
+
+def test_single_pass_reports_the_same_statistics():
+    """The single-pass L1 iteration sums the binning's per-group statistics in its gradient
+    reduction instead of a kernel of its own; its status block must equal binning alone's."""
+    from paper_2407_01866_amd.render import Renderer
+    d = dev()
+    H, W, N, n, K = 600, 1000, 20000, 3, 10
+    print(f"[binning] single-pass statistics H={H} W={W} N={N}", flush=True)
+    p = torch.from_numpy(synth.gen_gaussians(11, H, W, N, n, smin=1.0, smax=30.0)).to(d)
+    t = torch.from_numpy(synth.gen_image(12, H, W, n, 10)).to(d)
+    r = Renderer(N, n, H, W, K, device=d)
+    ref = r.status_of(r.bin(p)).cpu().clone()
+    saved = r.new_saved()
+    loss = torch.zeros(2, dtype=torch.float64, device=d)
+    g = torch.empty((5 + n, N), device=d)
+    r.l1_grad_into(p, t, loss, g, saved)
+    torch.cuda.synchronize()
+    st = r.status_of(saved).cpu()
+    assert torch.equal(st[:7], ref[:7]), (st[:7].tolist(), ref[:7].tolist())
+    assert int(st[nat.STAT_EVALS_FWD]) > 0
